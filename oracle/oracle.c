@@ -1,0 +1,643 @@
+/*
+ * CPU ORACLE for point-to-plane ICP and its neighbour search.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, loads or
+ * calls this file; only the test-suite, the smoke check and the CPU-baseline
+ * leg of the benchmark do.  It shares no code, header, table or helper with
+ * the GPU library.
+ *
+ * It is written to be checked by eye against the method, not to be fast:
+ *   - k nearest neighbours: the definition (Section 3, "Core operations":
+ *     k-NN queries), i.e. every reference point is ranked by a float32
+ *     squared distance and the k smallest (distance, index) pairs are kept,
+ *     ties going to the lower index.  A textbook kd-tree (Friedman, Bentley
+ *     and Finkel 1977) is offered as an accelerator with the same result;
+ *     the tests hold it bit-equal to the brute-force definition.
+ *   - normals and curvature: principal component analysis of each point's k
+ *     nearest neighbours (Section 3, "Core operations": normal and curvature
+ *     estimation, PCA), the eigenvector of the smallest eigenvalue of the
+ *     neighbourhood covariance, oriented toward a viewpoint (Section 4, the
+ *     normal-estimation benchmark enforces viewpoint-consistent normals).
+ *     Eigen-decomposition by cyclic Jacobi rotations (textbook).
+ *   - point-to-plane ICP: the loop of Section 3 ("Iterative geometric
+ *     registration": alternate correspondence search and transform
+ *     estimation) with nearest-neighbour correspondences and a rejection
+ *     distance, as in the Section 4 ICP benchmark, and the linear
+ *     least-squares point-to-plane estimator the paper cites (Low 2004):
+ *     small-angle linearisation of the rotation, 6x6 normal equations solved
+ *     by Cholesky, exact rotation Rz(gamma) Ry(beta) Rx(alpha) applied on
+ *     the left of the running pose.
+ * Everything is float64 (the paper benchmarks in double precision,
+ * Section 4) except the kNN ranking key, which is defined in float32 so that
+ * a float32 implementation can reproduce neighbour lists bit for bit:
+ *     dx = r.x - q.x, dy = ..., dz = ...   (float32 subtractions)
+ *     key = fmaf(dz, dz, fmaf(dy, dy, dx * dx))
+ * Build with -ffp-contract=off so that no other contraction happens.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------------ */
+/* float32 ranking key of the k-NN definition                                */
+/* ------------------------------------------------------------------------ */
+
+static float knn_key(const float *r, const float *q)
+{
+    float dx = r[0] - q[0];
+    float dy = r[1] - q[1];
+    float dz = r[2] - q[2];
+    return fmaf(dz, dz, fmaf(dy, dy, dx * dx));
+}
+
+/* (key, index) lexicographic order */
+static int pair_less(float ka, int64_t ia, float kb, int64_t ib)
+{
+    return ka < kb || (ka == kb && ia < ib);
+}
+
+/* keep the k best pairs in ascending order; returns nothing */
+static void topk_insert(float *kd, int32_t *ki, int k, int *filled, float key, int32_t idx)
+{
+    int n = *filled;
+    if (n == k) {
+        if (!pair_less(key, idx, kd[k - 1], ki[k - 1])) return;
+        n = k - 1;               /* drop the current worst */
+    }
+    int pos = n;
+    while (pos > 0 && pair_less(key, idx, kd[pos - 1], ki[pos - 1])) {
+        kd[pos] = kd[pos - 1];
+        ki[pos] = ki[pos - 1];
+        pos--;
+    }
+    kd[pos] = key;
+    ki[pos] = idx;
+    if (*filled < k) (*filled)++;
+}
+
+/* ------------------------------------------------------------------------ */
+/* brute-force k-NN: the definition                                          */
+/* ------------------------------------------------------------------------ */
+
+int oracle_knn_brute(const float *ref, int64_t n_ref, const float *qry, int64_t n_qry,
+                     int k, int32_t *out_idx, float *out_d2)
+{
+    if (k < 1 || k > n_ref) return 1;
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n_qry; i++) {
+        float kd[64];
+        int32_t ki[64];
+        int filled = 0;
+        for (int64_t j = 0; j < n_ref; j++)
+            topk_insert(kd, ki, k, &filled, knn_key(ref + 3 * j, qry + 3 * i), (int32_t)j);
+        for (int s = 0; s < k; s++) {
+            out_idx[i * k + s] = ki[s];
+            if (out_d2) out_d2[i * k + s] = kd[s];
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* textbook kd-tree                                                          */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t lo, hi;       /* range of perm[] owned by the node              */
+    int32_t left, right;  /* children, -1 for a leaf                        */
+    int32_t axis;
+    float split;          /* left: coord <= split, right: coord >= split    */
+} kd_node;
+
+typedef struct {
+    const float *pts;
+    int64_t n;
+    int32_t *perm;
+    kd_node *nodes;
+    int64_t n_nodes, cap;
+} kd_tree;
+
+enum { KD_LEAF = 8 };
+
+static float kd_coord(const kd_tree *t, int32_t p, int axis)
+{
+    return t->pts[3 * (int64_t)p + axis];
+}
+
+/* Quickselect (three-way partition, median-of-three pivot): afterwards
+   perm[kth] holds the kth smallest coordinate of perm[lo, hi) on ``axis``,
+   everything before it is <= and everything after it is >=. */
+static void kd_select(kd_tree *t, int32_t lo, int32_t hi, int32_t kth, int axis)
+{
+    int32_t *pm = t->perm;
+    while (hi - lo > 1) {
+        float a = kd_coord(t, pm[lo], axis), b = kd_coord(t, pm[lo + (hi - lo) / 2], axis);
+        float c = kd_coord(t, pm[hi - 1], axis);
+        float pv = (a < b) ? ((b < c) ? b : ((a < c) ? c : a)) : ((a < c) ? a : ((b < c) ? c : b));
+        int32_t lt = lo, i = lo, gt = hi;
+        while (i < gt) {
+            float v = kd_coord(t, pm[i], axis);
+            if (v < pv) { int32_t tmp = pm[lt]; pm[lt] = pm[i]; pm[i] = tmp; lt++; i++; }
+            else if (v > pv) { gt--; int32_t tmp = pm[gt]; pm[gt] = pm[i]; pm[i] = tmp; }
+            else i++;
+        }
+        if (kth < lt) hi = lt;
+        else if (kth >= gt) lo = gt;
+        else return;
+    }
+}
+
+static int32_t kd_build_rec(kd_tree *t, int32_t lo, int32_t hi)
+{
+    int32_t id = (int32_t)t->n_nodes++;
+    kd_node *nd = &t->nodes[id];
+    nd->lo = lo; nd->hi = hi; nd->left = nd->right = -1; nd->axis = 0; nd->split = 0.f;
+    if (hi - lo <= KD_LEAF) return id;
+    /* split on the axis of widest spread, at the median */
+    float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+    for (int32_t i = lo; i < hi; i++)
+        for (int a = 0; a < 3; a++) {
+            float v = t->pts[3 * (int64_t)t->perm[i] + a];
+            if (v < mn[a]) mn[a] = v;
+            if (v > mx[a]) mx[a] = v;
+        }
+    int axis = 0;
+    for (int a = 1; a < 3; a++)
+        if (mx[a] - mn[a] > mx[axis] - mn[axis]) axis = a;
+    if (!(mx[axis] > mn[axis])) return id;       /* all points coincide: leaf */
+    int32_t mid = lo + (hi - lo) / 2;
+    kd_select(t, lo, hi, mid, axis);
+    float split = kd_coord(t, t->perm[mid], axis);
+    /* left holds perm[lo, mid) whose coords are <= split, right holds
+       perm[mid, hi) whose coords are >= split (the selection guarantees it) */
+    t->nodes[id].axis = axis;
+    t->nodes[id].split = split;
+    int32_t l = kd_build_rec(t, lo, mid);
+    int32_t r = kd_build_rec(t, mid, hi);
+    t->nodes[id].left = l;
+    t->nodes[id].right = r;
+    return id;
+}
+
+static int kd_build(kd_tree *t, const float *pts, int64_t n)
+{
+    t->pts = pts;
+    t->n = n;
+    t->perm = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1));
+    t->cap = 2 * (n / (KD_LEAF / 2) + 2);
+    t->nodes = (kd_node *)malloc(sizeof(kd_node) * (size_t)t->cap);
+    t->n_nodes = 0;
+    if (!t->perm || !t->nodes) return 1;
+    for (int64_t i = 0; i < n; i++) t->perm[i] = (int32_t)i;
+    if (n > 0) kd_build_rec(t, 0, (int32_t)n);
+    return 0;
+}
+
+static void kd_free(kd_tree *t)
+{
+    free(t->perm);
+    free(t->nodes);
+}
+
+/* k-NN under the float32 key.  A subtree beyond a splitting plane at axis
+   distance a holds only points whose float32 key is at least
+   a^2 * (1 - 6e-7) (five roundings of relative size 2^-24 at most), so it
+   is skipped only when a^2 * (1 - 1e-6) > current k-th key. */
+static void kd_knn_rec(const kd_tree *t, int32_t id, const float *q, int k,
+                       float *kd, int32_t *ki, int *filled)
+{
+    const kd_node *nd = &t->nodes[id];
+    if (nd->left < 0) {
+        for (int32_t i = nd->lo; i < nd->hi; i++) {
+            int32_t j = t->perm[i];
+            topk_insert(kd, ki, k, filled, knn_key(t->pts + 3 * (int64_t)j, q), j);
+        }
+        return;
+    }
+    double diff = (double)q[nd->axis] - (double)nd->split;
+    int32_t near = diff <= 0 ? nd->left : nd->right;
+    int32_t far = diff <= 0 ? nd->right : nd->left;
+    kd_knn_rec(t, near, q, k, kd, ki, filled);
+    if (*filled < k || diff * diff * (1.0 - 1e-6) <= (double)kd[k - 1])
+        kd_knn_rec(t, far, q, k, kd, ki, filled);
+}
+
+int oracle_knn_kdtree(const float *ref, int64_t n_ref, const float *qry, int64_t n_qry,
+                      int k, int32_t *out_idx, float *out_d2)
+{
+    if (k < 1 || k > n_ref || k > 64) return 1;
+    kd_tree t;
+    if (kd_build(&t, ref, n_ref)) { kd_free(&t); return 2; }
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n_qry; i++) {
+        float kd[64];
+        int32_t ki[64];
+        int filled = 0;
+        kd_knn_rec(&t, 0, qry + 3 * i, k, kd, ki, &filled);
+        for (int s = 0; s < k; s++) {
+            out_idx[i * k + s] = ki[s];
+            if (out_d2) out_d2[i * k + s] = kd[s];
+        }
+    }
+    kd_free(&t);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* 3x3 symmetric eigen-decomposition by cyclic Jacobi rotations              */
+/* ------------------------------------------------------------------------ */
+
+/* a: symmetric 3x3 (row-major), destroyed.  On return w[0] <= w[1] <= w[2]
+   and column c of v (v[r*3+c]) is the unit eigenvector of w[c]. */
+void oracle_jacobi3(double a[9], double w[3], double v[9])
+{
+    for (int i = 0; i < 9; i++) v[i] = (i % 4 == 0) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 64; sweep++) {
+        double off = a[1] * a[1] + a[2] * a[2] + a[5] * a[5];
+        if (off == 0.0) break;
+        for (int p = 0; p < 2; p++)
+            for (int q = p + 1; q < 3; q++) {
+                double apq = a[p * 3 + q];
+                if (apq == 0.0) continue;
+                double app = a[p * 3 + p], aqq = a[q * 3 + q];
+                double theta = (aqq - app) / (2.0 * apq);
+                double tt = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                double c = 1.0 / sqrt(tt * tt + 1.0), s = tt * c;
+                /* A <- J^T A J with J the rotation in the (p,q) plane */
+                for (int r = 0; r < 3; r++) {
+                    double arp = a[r * 3 + p], arq = a[r * 3 + q];
+                    a[r * 3 + p] = c * arp - s * arq;
+                    a[r * 3 + q] = s * arp + c * arq;
+                }
+                for (int r = 0; r < 3; r++) {
+                    double apr = a[p * 3 + r], aqr = a[q * 3 + r];
+                    a[p * 3 + r] = c * apr - s * aqr;
+                    a[q * 3 + r] = s * apr + c * aqr;
+                }
+                a[p * 3 + q] = a[q * 3 + p] = 0.0;
+                for (int r = 0; r < 3; r++) {
+                    double vrp = v[r * 3 + p], vrq = v[r * 3 + q];
+                    v[r * 3 + p] = c * vrp - s * vrq;
+                    v[r * 3 + q] = s * vrp + c * vrq;
+                }
+            }
+        /* stop once the off-diagonal part is negligible next to the diagonal */
+        double diag = fabs(a[0]) + fabs(a[4]) + fabs(a[8]);
+        double off2 = fabs(a[1]) + fabs(a[2]) + fabs(a[5]);
+        if (off2 <= 1e-300 || off2 < 1e-18 * diag) {
+            a[1] = a[2] = a[5] = a[3] = a[6] = a[7] = 0.0;
+            break;
+        }
+    }
+    double d[3] = {a[0], a[4], a[8]};
+    int ord[3] = {0, 1, 2};
+    for (int i = 0; i < 3; i++)
+        for (int j = i + 1; j < 3; j++)
+            if (d[ord[j]] < d[ord[i]]) { int tmp = ord[i]; ord[i] = ord[j]; ord[j] = tmp; }
+    double vs[9];
+    memcpy(vs, v, sizeof vs);
+    for (int c = 0; c < 3; c++) {
+        w[c] = d[ord[c]];
+        for (int r = 0; r < 3; r++) v[r * 3 + c] = vs[r * 3 + ord[c]];
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* normals and curvature                                                     */
+/* ------------------------------------------------------------------------ */
+
+/* Neighbourhoods N(i) = the k nearest points of i in its own cloud (i itself
+   included).  Covariance C = (1/k) sum (x - mu)(x - mu)^T in float64.  The
+   normal is the unit eigenvector of the smallest eigenvalue, flipped so that
+   n . (viewpoint - p) >= 0; when that product is exactly zero, the first
+   nonzero component is made positive.  Curvature (surface variation) is
+   l0 / (l0 + l1 + l2), 0 when the trace is 0.  A neighbourhood whose
+   covariance is all zeros has normal (0,0,0).
+   out_evals (nullable) receives the ascending eigenvalues. */
+int oracle_normals(const float *xyz, int64_t n, int k, const double viewpoint[3],
+                   int use_kdtree, double *out_normals, double *out_curv, double *out_evals)
+{
+    if (k < 1 || k > n || k > 64) return 1;
+    int32_t *nbr = (int32_t *)malloc(sizeof(int32_t) * (size_t)n * (size_t)k);
+    if (!nbr) return 2;
+    int rc = use_kdtree ? oracle_knn_kdtree(xyz, n, xyz, n, k, nbr, NULL)
+                        : oracle_knn_brute(xyz, n, xyz, n, k, nbr, NULL);
+    if (rc) { free(nbr); return rc; }
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; i++) {
+        double mu[3] = {0, 0, 0};
+        for (int s = 0; s < k; s++)
+            for (int a = 0; a < 3; a++) mu[a] += (double)xyz[3 * (int64_t)nbr[i * k + s] + a];
+        for (int a = 0; a < 3; a++) mu[a] /= k;
+        double c[9] = {0};
+        for (int s = 0; s < k; s++) {
+            double e[3];
+            for (int a = 0; a < 3; a++) e[a] = (double)xyz[3 * (int64_t)nbr[i * k + s] + a] - mu[a];
+            for (int r = 0; r < 3; r++)
+                for (int cc = 0; cc < 3; cc++) c[r * 3 + cc] += e[r] * e[cc];
+        }
+        for (int r = 0; r < 9; r++) c[r] /= k;
+        double w[3], v[9];
+        int zero = 1;
+        for (int r = 0; r < 9; r++) if (c[r] != 0.0) zero = 0;
+        double nn[3] = {0, 0, 0};
+        if (zero) {
+            w[0] = w[1] = w[2] = 0.0;
+        } else {
+            oracle_jacobi3(c, w, v);
+            for (int a = 0; a < 3; a++) nn[a] = v[a * 3 + 0];
+            double nrm = sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
+            for (int a = 0; a < 3; a++) nn[a] /= nrm;
+            double dot = 0;
+            for (int a = 0; a < 3; a++) dot += nn[a] * (viewpoint[a] - (double)xyz[3 * i + a]);
+            int flip = dot < 0;
+            if (dot == 0) {
+                for (int a = 0; a < 3; a++)
+                    if (nn[a] != 0) { flip = nn[a] < 0; break; }
+            }
+            if (flip) for (int a = 0; a < 3; a++) nn[a] = -nn[a];
+        }
+        for (int a = 0; a < 3; a++) out_normals[3 * i + a] = nn[a];
+        double tr = w[0] + w[1] + w[2];
+        if (out_curv) out_curv[i] = tr > 0 ? w[0] / tr : 0.0;
+        if (out_evals) for (int a = 0; a < 3; a++) out_evals[3 * i + a] = w[a];
+    }
+    free(nbr);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* point-to-plane ICP                                                        */
+/* ------------------------------------------------------------------------ */
+
+/* Nearest target point of p within the rejection ball, in float64: the j
+   with the smallest |p - q_j|^2 among those with |p - q_j|^2 <= *best on
+   entry (d_max^2), ties to the lower j; *bj stays -1 when the ball is empty.
+   This is the nearest neighbour followed by the rejection test, with the
+   search confined to where an accepted answer can lie.  The far side of a
+   splitting plane at distance a is skipped only when a^2 (1 - 1e-12) > best,
+   so no point that could tie is ever skipped. */
+static int nn64_better(double d2, int32_t j, double best, int32_t bj)
+{
+    return d2 < best || (d2 == best && (bj < 0 || j < bj));
+}
+
+static void kd_nn64_rec(const kd_tree *t, int32_t id, const double p[3], double *best, int32_t *bj)
+{
+    const kd_node *nd = &t->nodes[id];
+    if (nd->left < 0) {
+        for (int32_t i = nd->lo; i < nd->hi; i++) {
+            int32_t j = t->perm[i];
+            const float *q = t->pts + 3 * (int64_t)j;
+            double dx = p[0] - q[0], dy = p[1] - q[1], dz = p[2] - q[2];
+            double d2 = dx * dx + dy * dy + dz * dz;
+            if (nn64_better(d2, j, *best, *bj)) { *best = d2; *bj = j; }
+        }
+        return;
+    }
+    double diff = p[nd->axis] - (double)nd->split;
+    int32_t near = diff <= 0 ? nd->left : nd->right;
+    int32_t far = diff <= 0 ? nd->right : nd->left;
+    kd_nn64_rec(t, near, p, best, bj);
+    if (diff * diff * (1.0 - 1e-12) <= *best) kd_nn64_rec(t, far, p, best, bj);
+}
+
+static void nn64_brute(const float *tgt, int64_t nt, const double p[3], double *best, int32_t *bj)
+{
+    for (int64_t j = 0; j < nt; j++) {
+        const float *q = tgt + 3 * j;
+        double dx = p[0] - q[0], dy = p[1] - q[1], dz = p[2] - q[2];
+        double d2 = dx * dx + dy * dy + dz * dz;
+        if (nn64_better(d2, (int32_t)j, *best, *bj)) { *best = d2; *bj = (int32_t)j; }
+    }
+}
+
+/* The linearised point-to-plane system at pose T (row-major 4x4) for the
+   correspondences found at that pose:
+     p'_i = R p_i + t,   j(i) = nearest target point,
+     inlier iff |p'_i - q_j|^2 <= d_max^2 and n_j != 0,
+     r_i = (p'_i - q_j) . n_j,   J_i = [p'_i x n_j, n_j],
+     A = sum J_i^T J_i,  b = sum J_i^T r_i,  also sum r_i^2 and the count.
+   Sums run over source points in index order (deterministic).
+   corr (nullable) receives j(i) or -1 for rejected points. */
+static int p2plane_system(const float *src, int64_t ns, const float *tgt, const float *nrm, int64_t nt,
+                          const kd_tree *tree, const double T[16], double d_max,
+                          double A[36], double b[6], int64_t *inliers, double *sum_r2, int32_t *corr)
+{
+    double *rows = (double *)malloc(sizeof(double) * 7 * (size_t)(ns > 0 ? ns : 1));
+    int32_t *jj = (int32_t *)malloc(sizeof(int32_t) * (size_t)(ns > 0 ? ns : 1));
+    if (!rows || !jj) { free(rows); free(jj); return 2; }
+    double dmax2 = d_max * d_max;
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < ns; i++) {
+        const float *ps = src + 3 * i;
+        double p[3];
+        for (int a = 0; a < 3; a++)
+            p[a] = T[a * 4 + 0] * ps[0] + T[a * 4 + 1] * ps[1] + T[a * 4 + 2] * ps[2] + T[a * 4 + 3];
+        double best = dmax2;
+        int32_t bj = -1;
+        if (tree) kd_nn64_rec(tree, 0, p, &best, &bj);
+        else nn64_brute(tgt, nt, p, &best, &bj);
+        int ok = bj >= 0;
+        const float *q = tgt + 3 * (int64_t)(ok ? bj : 0);
+        const float *nq = nrm + 3 * (int64_t)(ok ? bj : 0);
+        ok = ok && (nq[0] != 0.f || nq[1] != 0.f || nq[2] != 0.f);
+        jj[i] = ok ? bj : -1;
+        if (ok) {
+            double n[3] = {nq[0], nq[1], nq[2]};
+            double r = (p[0] - q[0]) * n[0] + (p[1] - q[1]) * n[1] + (p[2] - q[2]) * n[2];
+            double *J = rows + 7 * i;
+            J[0] = p[1] * n[2] - p[2] * n[1];
+            J[1] = p[2] * n[0] - p[0] * n[2];
+            J[2] = p[0] * n[1] - p[1] * n[0];
+            J[3] = n[0]; J[4] = n[1]; J[5] = n[2];
+            J[6] = r;
+        }
+    }
+    for (int i = 0; i < 36; i++) A[i] = 0;
+    for (int i = 0; i < 6; i++) b[i] = 0;
+    int64_t cnt = 0;
+    double s2 = 0;
+    for (int64_t i = 0; i < ns; i++) {
+        if (corr) corr[i] = jj[i];
+        if (jj[i] < 0) continue;
+        const double *J = rows + 7 * i;
+        for (int r = 0; r < 6; r++) {
+            for (int c = 0; c < 6; c++) A[r * 6 + c] += J[r] * J[c];
+            b[r] += J[r] * J[6];
+        }
+        s2 += J[6] * J[6];
+        cnt++;
+    }
+    free(rows);
+    free(jj);
+    *inliers = cnt;
+    *sum_r2 = s2;
+    return 0;
+}
+
+int oracle_p2plane_system(const float *src, int64_t ns, const float *tgt, const float *nrm, int64_t nt,
+                          const double T[16], double d_max, int use_kdtree,
+                          double A[36], double b[6], int64_t *inliers, double *sum_r2, int32_t *corr)
+{
+    kd_tree t;
+    int rc;
+    if (use_kdtree) {
+        if (kd_build(&t, tgt, nt)) { kd_free(&t); return 2; }
+        rc = p2plane_system(src, ns, tgt, nrm, nt, &t, T, d_max, A, b, inliers, sum_r2, corr);
+        kd_free(&t);
+    } else {
+        rc = p2plane_system(src, ns, tgt, nrm, nt, NULL, T, d_max, A, b, inliers, sum_r2, corr);
+    }
+    return rc;
+}
+
+/* Cholesky A = L L^T of a 6x6 SPD matrix.  Fails (returns 1) when a pivot is
+   not above 1e-14 times the largest diagonal entry. */
+int oracle_cholesky6(const double A[36], double L[36])
+{
+    double dmax = 0;
+    for (int i = 0; i < 6; i++) if (A[i * 7] > dmax) dmax = A[i * 7];
+    for (int i = 0; i < 36; i++) L[i] = 0;
+    for (int j = 0; j < 6; j++) {
+        double s = A[j * 6 + j];
+        for (int k = 0; k < j; k++) s -= L[j * 6 + k] * L[j * 6 + k];
+        if (!(s > 1e-14 * dmax)) return 1;
+        L[j * 6 + j] = sqrt(s);
+        for (int i = j + 1; i < 6; i++) {
+            double t = A[i * 6 + j];
+            for (int k = 0; k < j; k++) t -= L[i * 6 + k] * L[j * 6 + k];
+            L[i * 6 + j] = t / L[j * 6 + j];
+        }
+    }
+    return 0;
+}
+
+/* x = -A^{-1} b via the Cholesky factor */
+static void chol_solve6(const double L[36], const double b[6], double x[6])
+{
+    double y[6];
+    for (int i = 0; i < 6; i++) {
+        double s = -b[i];
+        for (int k = 0; k < i; k++) s -= L[i * 6 + k] * y[k];
+        y[i] = s / L[i * 6 + i];
+    }
+    for (int i = 5; i >= 0; i--) {
+        double s = y[i];
+        for (int k = i + 1; k < 6; k++) s -= L[k * 6 + i] * x[k];
+        x[i] = s / L[i * 6 + i];
+    }
+}
+
+/* R = Rz(gamma) Ry(beta) Rx(alpha), row-major 3x3 */
+void oracle_euler_zyx(double alpha, double beta, double gamma, double R[9])
+{
+    double ca = cos(alpha), sa = sin(alpha), cb = cos(beta), sb = sin(beta);
+    double cg = cos(gamma), sg = sin(gamma);
+    double Rx[9] = {1, 0, 0, 0, ca, -sa, 0, sa, ca};
+    double Ry[9] = {cb, 0, sb, 0, 1, 0, -sb, 0, cb};
+    double Rz[9] = {cg, -sg, 0, sg, cg, 0, 0, 0, 1};
+    double Ryx[9];
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++) {
+            double s = 0;
+            for (int k = 0; k < 3; k++) s += Ry[r * 3 + k] * Rx[k * 3 + c];
+            Ryx[r * 3 + c] = s;
+        }
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++) {
+            double s = 0;
+            for (int k = 0; k < 3; k++) s += Rz[r * 3 + k] * Ryx[k * 3 + c];
+            R[r * 3 + c] = s;
+        }
+}
+
+enum { ICP_CONVERGED = 0, ICP_MAXITER = 1, ICP_DEGENERATE = 2, ICP_NO_INLIERS = 3 };
+
+/* Point-to-plane ICP.
+   T_init (nullable: identity) and T_out are row-major 4x4 maps source ->
+   target.  Each iteration: correspondences at the current pose, system,
+   x = -A^{-1} b = (alpha, beta, gamma, tau), dR = Rz Ry Rx,
+   R <- dR R, t <- dR t + tau.  Stops early on a degenerate system (fewer than
+   6 inliers or a failed Cholesky; the pose is kept) or, when conv_tol > 0,
+   once max |x_i| < conv_tol.  A final correspondence pass at the returned
+   pose gives the inlier count and rms = sqrt(sum r^2 / inliers).
+   stats_i: [status, iterations_run], stats_i64: [inliers], stats_d: [rms].
+   x_hist (nullable): max_iters*6 increments, as they were applied. */
+int oracle_icp(const float *src, int64_t ns, const float *tgt, const float *nrm, int64_t nt,
+               const double *T_init, double d_max, int max_iters, double conv_tol, int use_kdtree,
+               double T_out[16], int32_t stats_i[2], int64_t stats_i64[1], double stats_d[1],
+               double *x_hist)
+{
+    double T[16];
+    for (int i = 0; i < 16; i++) T[i] = T_init ? T_init[i] : ((i % 5 == 0) ? 1.0 : 0.0);
+    kd_tree tree;
+    int have_tree = 0;
+    if (use_kdtree) {
+        if (kd_build(&tree, tgt, nt)) { kd_free(&tree); return 2; }
+        have_tree = 1;
+    }
+    int status = ICP_MAXITER, it = 0;
+    double A[36], b[6], L[36], x[6];
+    int64_t inl;
+    double s2;
+    for (it = 0; it < max_iters; it++) {
+        int rc = p2plane_system(src, ns, tgt, nrm, nt, have_tree ? &tree : NULL, T, d_max, A, b, &inl, &s2, NULL);
+        if (rc) { if (have_tree) kd_free(&tree); return rc; }
+        if (inl == 0) { status = ICP_NO_INLIERS; break; }
+        if (inl < 6 || oracle_cholesky6(A, L)) { status = ICP_DEGENERATE; break; }
+        chol_solve6(L, b, x);
+        if (x_hist) for (int a = 0; a < 6; a++) x_hist[it * 6 + a] = x[a];
+        double dR[9];
+        oracle_euler_zyx(x[0], x[1], x[2], dR);
+        double R[9], t[3], Rn[9], tn[3];
+        for (int r = 0; r < 3; r++) {
+            for (int c = 0; c < 3; c++) R[r * 3 + c] = T[r * 4 + c];
+            t[r] = T[r * 4 + 3];
+        }
+        for (int r = 0; r < 3; r++) {
+            for (int c = 0; c < 3; c++) {
+                double s = 0;
+                for (int k = 0; k < 3; k++) s += dR[r * 3 + k] * R[k * 3 + c];
+                Rn[r * 3 + c] = s;
+            }
+            double s = 0;
+            for (int k = 0; k < 3; k++) s += dR[r * 3 + k] * t[k];
+            tn[r] = s + x[3 + r];
+        }
+        for (int r = 0; r < 3; r++) {
+            for (int c = 0; c < 3; c++) T[r * 4 + c] = Rn[r * 3 + c];
+            T[r * 4 + 3] = tn[r];
+        }
+        T[12] = T[13] = T[14] = 0.0;
+        T[15] = 1.0;
+        if (conv_tol > 0) {
+            double m = 0;
+            for (int a = 0; a < 6; a++) if (fabs(x[a]) > m) m = fabs(x[a]);
+            if (m < conv_tol) { status = ICP_CONVERGED; it++; break; }
+        }
+    }
+    int rc = p2plane_system(src, ns, tgt, nrm, nt, have_tree ? &tree : NULL, T, d_max, A, b, &inl, &s2, NULL);
+    if (have_tree) kd_free(&tree);
+    if (rc) return rc;
+    memcpy(T_out, T, sizeof T);
+    stats_i[0] = status;
+    stats_i[1] = it;
+    stats_i64[0] = inl;
+    stats_d[0] = inl > 0 ? sqrt(s2 / (double)inl) : 0.0;
+    return 0;
+}
+
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
