@@ -330,14 +330,19 @@ int oracle_normals(const float *xyz, int64_t n, int k, const double viewpoint[3]
     if (rc) { free(nbr); return rc; }
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; i++) {
+        /* covariance is translation invariant: use offsets from p_i, which
+           are exact in float64 (differences of float32 values), so a
+           neighbourhood of coincident points gives exactly zero */
         double mu[3] = {0, 0, 0};
         for (int s = 0; s < k; s++)
-            for (int a = 0; a < 3; a++) mu[a] += (double)xyz[3 * (int64_t)nbr[i * k + s] + a];
+            for (int a = 0; a < 3; a++)
+                mu[a] += (double)xyz[3 * (int64_t)nbr[i * k + s] + a] - (double)xyz[3 * i + a];
         for (int a = 0; a < 3; a++) mu[a] /= k;
         double c[9] = {0};
         for (int s = 0; s < k; s++) {
             double e[3];
-            for (int a = 0; a < 3; a++) e[a] = (double)xyz[3 * (int64_t)nbr[i * k + s] + a] - mu[a];
+            for (int a = 0; a < 3; a++)
+                e[a] = ((double)xyz[3 * (int64_t)nbr[i * k + s] + a] - (double)xyz[3 * i + a]) - mu[a];
             for (int r = 0; r < 3; r++)
                 for (int cc = 0; cc < 3; cc++) c[r * 3 + cc] += e[r] * e[cc];
         }

@@ -92,10 +92,13 @@ def test_orientation_tie_rule(oracle_mod):
     assert np.all(n == np.array([0.0, 0.0, 1.0]))
 
 
-def test_degenerate_coincident_points(oracle_mod):
-    pts = np.vstack([np.tile([[1.0, 2.0, 3.0]], (12, 1)), [[5.0, 5.0, 5.0]] * 3]).astype(np.float32)
+@pytest.mark.parametrize("p", [(1.0, 2.0, 3.0), (0.1, 0.2, 0.3), (-7.3, 1e3, 0.017)])
+def test_degenerate_coincident_points(oracle_mod, p):
+    # identical neighbours: zero covariance, so the normal is undefined and
+    # reported as (0,0,0) with curvature 0, whatever the coordinates
+    pts = np.vstack([np.tile([p], (12, 1)), [[5.0, 5.0, 5.0]] * 3]).astype(np.float32)
     n, curv, ev = oracle_mod.normals(pts, 10, (0, 0, 0))
-    assert np.all(n[:12] == 0) and np.all(curv[:12] == 0)
+    assert np.all(n[:12] == 0) and np.all(curv[:12] == 0) and np.all(ev[:12] == 0)
 
 
 def test_matches_numpy_cov_eigh(oracle_mod):
