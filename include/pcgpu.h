@@ -1,0 +1,169 @@
+/*
+ * pcgpu.h -- C ABI of the MI355X (gfx950) point-cloud hot path:
+ * k-nearest-neighbour search, PCA normals and point-to-plane ICP.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Point sets are contiguous float32 arrays of n points with x, y, z
+ *    consecutive: row-major (n, 3), which is byte-identical to the paper's
+ *    one-point-per-column, column-major 3 x n view of contiguous data
+ *    (Section 2, "Simple data representations").
+ *  - Every array argument is a DEVICE pointer unless marked (host).  Arrays
+ *    must be 4-byte aligned (8-byte for double), must not overlap an output
+ *    unless stated, and stay owned by the caller: the library never
+ *    allocates, frees or keeps device memory.  Scratch space comes from the
+ *    caller's `workspace`, at least *_workspace_size() bytes, 256-byte
+ *    aligned, whose contents are undefined on entry and on return.
+ *  - All device work is enqueued on `stream` and is asynchronous; the host
+ *    returns after argument validation and kernel launches.  Results are
+ *    valid once the stream has reached the point of the call.
+ *  - Errors: PC_EINVAL is returned synchronously, before any device work,
+ *    for a null required pointer, a misaligned pointer, a size or parameter
+ *    out of range; PC_EWORKSPACE when `workspace_bytes` is too small;
+ *    PC_EDEVICE when a kernel launch fails.  No exception or abort crosses
+ *    this interface.  Geometric outcomes of ICP (degenerate system, no
+ *    inliers) are not errors; they are reported in pc_icp_stats.status.
+ *  - Precondition: all coordinates and normals are finite.
+ *  - Point counts must be below 2^31.
+ */
+#ifndef PCGPU_H
+#define PCGPU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PC_OK = 0,
+    PC_EINVAL = 1,
+    PC_EWORKSPACE = 2,
+    PC_EDEVICE = 3
+} pc_status;
+
+enum {
+    PC_ICP_CONVERGED = 0,   /* max |increment| fell below conv_tol        */
+    PC_ICP_MAXITER = 1,     /* ran max_iters iterations                   */
+    PC_ICP_DEGENERATE = 2,  /* fewer than 6 inliers or a singular 6x6 system */
+    PC_ICP_NO_INLIERS = 3   /* no correspondence within max_corr_dist     */
+};
+
+enum { PCGPU_KMAX = 32 };   /* largest k for knn_search / estimate_normals */
+
+/* Human-readable name of a status code (static string). */
+const char *pc_status_string(pc_status s);
+
+/* ------------------------------------------------------------------------
+ * knn_search -- exact k nearest neighbours (Section 3, "Core operations":
+ * k-NN queries of the KDTree).
+ *
+ * For each query q_i the k reference points with the smallest float32 key
+ *     dx = r.x - q.x, dy = r.y - q.y, dz = r.z - q.z   (float32)
+ *     key = fmaf(dz, dz, fmaf(dy, dy, dx * dx))
+ * in ascending (key, reference index) order: ties go to the lower index.
+ * A query that is also a reference point finds itself (key 0).
+ *
+ *   ref_xyz  (n_ref, 3) float32, n_ref >= 1
+ *   qry_xyz  (n_qry, 3) float32, n_qry >= 0; may alias ref_xyz
+ *   k        1 <= k <= min(n_ref, PCGPU_KMAX)
+ *   out_idx  (n_qry, k) int32 reference indices, row i sorted as above
+ *   out_d2   (n_qry, k) float32 keys, or NULL
+ * ---------------------------------------------------------------------- */
+size_t knn_search_workspace_size(int64_t n_ref, int64_t n_qry, int k);
+pc_status knn_search(const float *ref_xyz, int64_t n_ref,
+                     const float *qry_xyz, int64_t n_qry,
+                     int k, int32_t *out_idx, float *out_d2,
+                     void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * estimate_normals -- PCA surface normals and curvature (Section 3, "Core
+ * operations": normal and curvature estimation, PCA; Section 4: k-NN
+ * neighbourhoods, viewpoint-consistent orientation).
+ *
+ * For each point p_i: N(i) = its k nearest points in the same cloud as
+ * defined by knn_search (p_i included); C = (1/k) sum (x - mu)(x - mu)^T over
+ * N(i); the normal is the unit eigenvector of C's smallest eigenvalue,
+ * flipped so that n . (viewpoint - p_i) >= 0 (when that product is exactly
+ * 0, the first nonzero component is made positive); curvature is the surface
+ * variation l0 / (l0 + l1 + l2), 0 when the trace is 0.  A neighbourhood of
+ * coincident points has normal (0, 0, 0) and curvature 0.
+ *
+ *   xyz            (n, 3) float32, n >= 0 (n == 0 is a no-op)
+ *   k              1 <= k <= min(n, PCGPU_KMAX)
+ *   viewpoint      (host) 3 floats
+ *   out_normals    (n, 3) float32, in input order
+ *   out_curvature  (n) float32, or NULL
+ * ---------------------------------------------------------------------- */
+size_t estimate_normals_workspace_size(int64_t n, int k);
+pc_status estimate_normals(const float *xyz, int64_t n, int k, const float viewpoint[3],
+                           float *out_normals, float *out_curvature,
+                           void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * icp_point_to_plane -- rigid point-to-plane ICP (Section 3, "Iterative
+ * geometric registration": alternate correspondence search and transform
+ * estimation; the linear least-squares point-to-plane estimator of Low 2004
+ * it cites; Section 4: nearest-neighbour correspondences with a rejection
+ * distance and a fixed iteration count).
+ *
+ * T maps source to target (target ~ R * source + t), starting at init_T.
+ * Each iteration: p'_i = R p_i + t (float32 copy of T), q_j = nearest target
+ * point of p'_i; the pair is an inlier when |p'_i - q_j| <= max_corr_dist
+ * and n_j != 0; r_i = (p'_i - q_j) . n_j, J_i = [p'_i x n_j, n_j];
+ * x = -(sum J^T J)^{-1} sum J^T r = (alpha, beta, gamma, tau) solved in
+ * float64 by Cholesky; R <- Rz(gamma) Ry(beta) Rx(alpha) R,
+ * t <- Rz Ry Rx t + tau in float64.  The loop stops after max_iters
+ * iterations, or earlier with PC_ICP_CONVERGED when conv_tol > 0 and
+ * max |x_i| < conv_tol, or with PC_ICP_DEGENERATE / PC_ICP_NO_INLIERS
+ * (fewer than 6 inliers or a Cholesky pivot <= 1e-14 * max diag; the pose
+ * is then kept).  A last correspondence pass at the returned pose gives the
+ * inlier count and rms = sqrt(sum r^2 / inliers).
+ *
+ *   src_xyz        (n_src, 3) float32, n_src >= 0
+ *   tgt_xyz        (n_tgt, 3) float32, n_tgt >= 0
+ *   tgt_normals    (n_tgt, 3) float32 target normals (e.g. estimate_normals)
+ *   init_T         16 float64 row-major, or NULL for identity
+ *   max_corr_dist  finite, > 0
+ *   max_iters      >= 0
+ *   conv_tol       finite, >= 0 (0 disables the early stop)
+ *   out_T          16 float64 row-major (may alias init_T)
+ *   out_stats      one pc_icp_stats (device), or NULL
+ * When n_src or n_tgt is 0, out_T = init_T and status = PC_ICP_NO_INLIERS.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int32_t status;          /* PC_ICP_*                          */
+    int32_t iterations_run;  /* increments applied                */
+    int64_t inliers;         /* at the returned pose              */
+    double rms;              /* sqrt(sum r^2 / inliers), 0 if none */
+} pc_icp_stats;
+
+size_t icp_point_to_plane_workspace_size(int64_t n_src, int64_t n_tgt, int max_iters);
+pc_status icp_point_to_plane(const float *src_xyz, int64_t n_src,
+                             const float *tgt_xyz, const float *tgt_normals, int64_t n_tgt,
+                             const double *init_T, float max_corr_dist, int max_iters,
+                             double conv_tol, double *out_T, pc_icp_stats *out_stats,
+                             void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * Diagnostics
+ * ---------------------------------------------------------------------- */
+/* Streams n_bytes (multiple of 16) from src to dst with one read and one
+   write per byte; used to calibrate bandwidth and hardware counters. */
+pc_status pc_copy_probe(void *dst, const void *src, size_t n_bytes, hipStream_t stream);
+
+/* Per-iteration history of the last icp_point_to_plane call that used this
+   workspace: for iteration i, 8 float64 values (alpha, beta, gamma, tau_x,
+   tau_y, tau_z, inliers, sum r^2) at the pose before the increment.  Returns
+   a device pointer into `workspace` (valid until it is reused), or NULL. */
+const double *icp_history(void *workspace, size_t workspace_bytes,
+                          int64_t n_src, int64_t n_tgt, int max_iters);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PCGPU_H */

@@ -1,0 +1,142 @@
+// C-ABI entry points: argument validation, workspace carving, launches.
+
+#include <math.h>
+
+#include "icp.h"
+
+using namespace pcg;
+
+namespace {
+
+constexpr int64_t kMaxPoints = (int64_t)1 << 31;
+
+bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+__global__ void k_copy16(const uint4 *__restrict__ src, uint4 *__restrict__ dst, size_t n)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *pc_status_string(pc_status s)
+{
+    switch (s) {
+    case PC_OK: return "PC_OK";
+    case PC_EINVAL: return "PC_EINVAL: invalid argument";
+    case PC_EWORKSPACE: return "PC_EWORKSPACE: workspace too small";
+    case PC_EDEVICE: return "PC_EDEVICE: device launch failed";
+    }
+    return "unknown pc_status";
+}
+
+size_t knn_search_workspace_size(int64_t n_ref, int64_t n_qry, int k)
+{
+    (void)n_qry;
+    (void)k;
+    if (n_ref < 0 || n_ref >= kMaxPoints) return 0;
+    return grid_bytes(n_ref);
+}
+
+pc_status knn_search(const float *ref_xyz, int64_t n_ref, const float *qry_xyz, int64_t n_qry, int k,
+                     int32_t *out_idx, float *out_d2, void *workspace, size_t workspace_bytes, hipStream_t stream)
+{
+    if (n_ref < 1 || n_ref >= kMaxPoints || n_qry < 0 || n_qry >= kMaxPoints) return PC_EINVAL;
+    if (k < 1 || k > PCGPU_KMAX || k > n_ref) return PC_EINVAL;
+    if (!ref_xyz || !workspace || (n_qry > 0 && (!qry_xyz || !out_idx))) return PC_EINVAL;
+    if (!aligned(ref_xyz, 4) || !aligned(qry_xyz, 4) || !aligned(out_idx, 4) || !aligned(out_d2, 4) ||
+        !aligned(workspace, 256))
+        return PC_EINVAL;
+    if (workspace_bytes < knn_search_workspace_size(n_ref, n_qry, k)) return PC_EWORKSPACE;
+    Carver c(workspace, workspace_bytes);
+    GridStore g;
+    grid_carve(c, n_ref, g);
+    if (!c.ok) return PC_EWORKSPACE;
+    if (grid_build(g, ref_xyz, stream) != hipSuccess) return PC_EDEVICE;
+    if (knn_run(g, qry_xyz, n_qry, k, out_idx, out_d2, stream) != hipSuccess) return PC_EDEVICE;
+    return PC_OK;
+}
+
+size_t estimate_normals_workspace_size(int64_t n, int k)
+{
+    (void)k;
+    if (n < 0 || n >= kMaxPoints) return 0;
+    return grid_bytes(n);
+}
+
+pc_status estimate_normals(const float *xyz, int64_t n, int k, const float viewpoint[3], float *out_normals,
+                           float *out_curvature, void *workspace, size_t workspace_bytes, hipStream_t stream)
+{
+    if (n < 0 || n >= kMaxPoints || !viewpoint) return PC_EINVAL;
+    if (k < 1 || k > PCGPU_KMAX) return PC_EINVAL;
+    if (n == 0) return PC_OK;
+    if (k > n) return PC_EINVAL;
+    if (!xyz || !out_normals || !workspace) return PC_EINVAL;
+    if (!isfinite(viewpoint[0]) || !isfinite(viewpoint[1]) || !isfinite(viewpoint[2])) return PC_EINVAL;
+    if (!aligned(xyz, 4) || !aligned(out_normals, 4) || !aligned(out_curvature, 4) || !aligned(workspace, 256))
+        return PC_EINVAL;
+    if (workspace_bytes < estimate_normals_workspace_size(n, k)) return PC_EWORKSPACE;
+    Carver c(workspace, workspace_bytes);
+    GridStore g;
+    grid_carve(c, n, g);
+    if (!c.ok) return PC_EWORKSPACE;
+    if (grid_build(g, xyz, stream) != hipSuccess) return PC_EDEVICE;
+    if (normals_run(g, xyz, k, viewpoint, out_normals, out_curvature, stream) != hipSuccess) return PC_EDEVICE;
+    return PC_OK;
+}
+
+size_t icp_point_to_plane_workspace_size(int64_t n_src, int64_t n_tgt, int max_iters)
+{
+    if (n_src < 0 || n_tgt < 0 || n_src >= kMaxPoints || n_tgt >= kMaxPoints || max_iters < 0) return 0;
+    Carver c(nullptr, ~(size_t)0 >> 1);
+    IcpStore s;
+    icp_carve(c, n_src, n_tgt, max_iters, s);
+    return c.used();
+}
+
+pc_status icp_point_to_plane(const float *src_xyz, int64_t n_src, const float *tgt_xyz, const float *tgt_normals,
+                             int64_t n_tgt, const double *init_T, float max_corr_dist, int max_iters,
+                             double conv_tol, double *out_T, pc_icp_stats *out_stats, void *workspace,
+                             size_t workspace_bytes, hipStream_t stream)
+{
+    if (n_src < 0 || n_tgt < 0 || n_src >= kMaxPoints || n_tgt >= kMaxPoints) return PC_EINVAL;
+    if (max_iters < 0 || !(max_corr_dist > 0.f) || !isfinite(max_corr_dist)) return PC_EINVAL;
+    if (!(conv_tol >= 0.0) || !isfinite(conv_tol)) return PC_EINVAL;
+    if (!out_T || !workspace) return PC_EINVAL;
+    if ((n_src > 0 && !src_xyz) || (n_tgt > 0 && (!tgt_xyz || !tgt_normals))) return PC_EINVAL;
+    if (!aligned(src_xyz, 4) || !aligned(tgt_xyz, 4) || !aligned(tgt_normals, 4) || !aligned(init_T, 8) ||
+        !aligned(out_T, 8) || !aligned(out_stats, 8) || !aligned(workspace, 256))
+        return PC_EINVAL;
+    if (workspace_bytes < icp_point_to_plane_workspace_size(n_src, n_tgt, max_iters)) return PC_EWORKSPACE;
+    Carver c(workspace, workspace_bytes);
+    IcpStore s;
+    icp_carve(c, n_src, n_tgt, max_iters, s);
+    if (!c.ok) return PC_EWORKSPACE;
+    hipError_t e = icp_run(s, src_xyz, n_src, tgt_xyz, tgt_normals, n_tgt, init_T, max_corr_dist, max_iters,
+                           conv_tol, out_T, out_stats, stream);
+    return e == hipSuccess ? PC_OK : PC_EDEVICE;
+}
+
+const double *icp_history(void *workspace, size_t workspace_bytes, int64_t n_src, int64_t n_tgt, int max_iters)
+{
+    if (!workspace || workspace_bytes < icp_point_to_plane_workspace_size(n_src, n_tgt, max_iters)) return nullptr;
+    Carver c(workspace, workspace_bytes);
+    IcpStore s;
+    icp_carve(c, n_src, n_tgt, max_iters, s);
+    return s.hist;
+}
+
+pc_status pc_copy_probe(void *dst, const void *src, size_t n_bytes, hipStream_t stream)
+{
+    if (!dst || !src || n_bytes % 16 || !aligned(dst, 16) || !aligned(src, 16)) return PC_EINVAL;
+    size_t n = n_bytes / 16;
+    if (n == 0) return PC_OK;
+    int blocks = (int)((n + 255) / 256 < 8192 ? (n + 255) / 256 : 8192);
+    k_copy16<<<blocks, 256, 0, stream>>>((const uint4 *)src, (uint4 *)dst, n);
+    return hipGetLastError() == hipSuccess ? PC_OK : PC_EDEVICE;
+}
+
+}  // extern "C"

@@ -1,0 +1,221 @@
+// Internal definitions shared by the gfx950 kernels of the point-cloud
+// library: the sparse voxel pyramid ("grid") layout, Morton keys, the cell
+// hash and small device helpers.  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "pcgpu.h"
+
+namespace pcg {
+
+// ---------------------------------------------------------------------------
+// Grid geometry.  The bounding cube of a cloud is split into 2^16 cells per
+// axis (level 0).  A level-L cell groups 2^L x 2^L x 2^L level-0 cells, so
+// its key is the level-0 Morton key shifted right by 3L, and level 16 is the
+// whole cube.  Points are stored sorted by level-0 Morton key, which makes
+// every cell at every level a contiguous run of the sorted array.
+// ---------------------------------------------------------------------------
+constexpr int kBits = 16;                 // bits per axis at level 0
+constexpr int kLevels = kBits + 1;        // levels 0..16
+constexpr uint32_t kMaxCoord = (1u << kBits) - 1u;
+constexpr uint64_t kEmptyKey = ~0ull;     // empty hash slot
+
+struct GridParams {        // written on the device by the grid builder
+    float ox, oy, oz;      // origin (cube corner)
+    float inv_h0;          // 1 / level-0 cell width
+    float h0;              // level-0 cell width
+    float margin;          // absolute slack for cell-range tests (a few ulps of the extent)
+    int32_t n;             // points in the grid
+    int32_t lmin;          // finest level kept in the pyramid
+    int32_t level_count[kLevels];   // nodes per level (valid for L >= lmin)
+    int32_t level_off[kLevels];     // first node of each level in the node arrays
+    int32_t n_nodes;       // total nodes
+    uint32_t hash_mask;    // hash capacity - 1 (capacity is a power of two)
+};
+
+// Node header: start/count of its run in the sorted arrays, first child
+// (global node index, level L-1) and number of children.
+struct NodeHdr {
+    uint32_t start, count, first_child, nchild;
+};
+
+// Node box: integer cell coordinates at its own level and the level.
+struct NodeBox {
+    uint16_t cx, cy, cz, level;
+};
+
+// Views of the workspace the grid lives in.
+struct GridView {
+    GridParams *params;
+    const float4 *pts;         // sorted points; .w = original index (bit pattern)
+    const uint64_t *keys;      // sorted level-0 Morton keys
+    const NodeHdr *hdr;
+    const NodeBox *box;
+    const uint64_t *hkeys;     // hash: (level << 48) | cell key
+    const uint32_t *hvals;     // hash: node index
+};
+
+// ---------------------------------------------------------------------------
+// Morton keys
+// ---------------------------------------------------------------------------
+__host__ __device__ inline uint64_t spread3(uint32_t v)
+{
+    uint64_t x = v & 0xffffu;
+    x = (x | (x << 16)) & 0x0000ff0000ffull;
+    x = (x | (x << 8)) & 0x00f00f00f00full;
+    x = (x | (x << 4)) & 0x0c30c30c30c3ull;
+    x = (x | (x << 2)) & 0x249249249249ull;
+    return x;
+}
+
+__host__ __device__ inline uint32_t compact3(uint64_t x)
+{
+    x &= 0x249249249249ull;
+    x = (x | (x >> 2)) & 0x0c30c30c30c3ull;
+    x = (x | (x >> 4)) & 0x00f00f00f00full;
+    x = (x | (x >> 8)) & 0x0000ff0000ffull;
+    x = (x | (x >> 16)) & 0xffffull;
+    return (uint32_t)x;
+}
+
+__host__ __device__ inline uint64_t morton3(uint32_t x, uint32_t y, uint32_t z)
+{
+    return spread3(x) | (spread3(y) << 1) | (spread3(z) << 2);
+}
+
+__device__ inline uint64_t hash_key(int level, uint64_t cellkey)
+{
+    return ((uint64_t)level << 48) | cellkey;
+}
+
+__device__ inline uint32_t hash_slot(uint64_t k, uint32_t mask)
+{
+    // 64-bit finaliser (splitmix64)
+    k ^= k >> 30;
+    k *= 0xbf58476d1ce4e5b9ull;
+    k ^= k >> 27;
+    k *= 0x94d049bb133111ebull;
+    k ^= k >> 31;
+    return (uint32_t)k & mask;
+}
+
+// Node index of cell (level, cx, cy, cz), or -1 when the cell is empty.
+__device__ inline int32_t find_cell(const GridView &g, uint32_t mask, int level,
+                                    uint32_t cx, uint32_t cy, uint32_t cz)
+{
+    uint64_t key = hash_key(level, morton3(cx, cy, cz));
+    uint32_t s = hash_slot(key, mask);
+    // the table is at most half full, so an empty slot ends every probe;
+    // the bound only guards against a corrupted table
+    for (uint32_t it = 0; it <= mask; it++) {
+        uint64_t k = g.hkeys[s];
+        if (k == key) return (int32_t)g.hvals[s];
+        if (k == kEmptyKey) return -1;
+        s = (s + 1) & mask;
+    }
+    return -1;
+}
+
+// float32 squared distance, the ranking key of the k-NN definition
+__device__ inline float knn_key(float rx, float ry, float rz, float qx, float qy, float qz)
+{
+    float dx = rx - qx, dy = ry - qy, dz = rz - qz;
+    return __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, __fmul_rn(dx, dx)));
+}
+
+// order-preserving float <-> uint mapping for atomic min/max
+__device__ inline uint32_t f2ord(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ inline float ord2f(uint32_t u)
+{
+    return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+
+__device__ inline uint32_t lane_id() { return __lane_id(); }
+
+// Squared distance from q to the closed box of a cell, computed in float32
+// and shrunk so that it never exceeds the true distance of any point the
+// cell holds (points are binned with the same rounding, see cell_lo).
+__device__ inline float cell_mindist2(const GridParams &P, float qx, float qy, float qz,
+                                      uint32_t cx, uint32_t cy, uint32_t cz, int level)
+{
+    float w = P.h0 * (float)(1u << level);
+    float lx = P.ox + (float)cx * w, ly = P.oy + (float)cy * w, lz = P.oz + (float)cz * w;
+    float dx = fmaxf(fmaxf(lx - qx, qx - (lx + w)), 0.f);
+    float dy = fmaxf(fmaxf(ly - qy, qy - (ly + w)), 0.f);
+    float dz = fmaxf(fmaxf(lz - qz, qz - (lz + w)), 0.f);
+    dx = fmaxf(dx - P.margin, 0.f);
+    dy = fmaxf(dy - P.margin, 0.f);
+    dz = fmaxf(dz - P.margin, 0.f);
+    return (dx * dx + dy * dy + dz * dz) * (1.0f - 1e-5f);
+}
+
+// level-0 cell coordinate of a coordinate value (clamped to the grid)
+__device__ inline uint32_t cell0(float v, float o, float inv_h0)
+{
+    float c = floorf((v - o) * inv_h0);
+    c = fminf(fmaxf(c, 0.f), (float)kMaxCoord);
+    return (uint32_t)c;
+}
+
+// ---------------------------------------------------------------------------
+// workspace carving
+// ---------------------------------------------------------------------------
+struct Carver {
+    uintptr_t base, cur, end;
+    bool ok;
+    Carver(void *p, size_t bytes)
+        : base((uintptr_t)p), cur((uintptr_t)p), end((uintptr_t)p + bytes), ok(true) {}
+    template <class T>
+    T *take(size_t count)
+    {
+        uintptr_t a = (cur + 255) & ~(uintptr_t)255;
+        uintptr_t e = a + count * sizeof(T);
+        if (e > end) ok = false;
+        cur = e;
+        return reinterpret_cast<T *>(a);
+    }
+    size_t used() const { return (size_t)(cur - base) + 256; }
+};
+
+// ---------------------------------------------------------------------------
+// Grid storage inside a caller workspace and its builder (grid.hip)
+// ---------------------------------------------------------------------------
+struct GridStore {
+    GridParams *params;
+    uint64_t *keys, *keys_alt;
+    uint32_t *idx, *idx_alt;
+    float4 *pts;
+    NodeHdr *hdr;
+    NodeBox *box;
+    uint64_t *hkeys;
+    uint32_t *hvals;
+    uint32_t *slev;           // per sorted point: top level at which it starts a cell (or 0xff)
+    uint32_t *radix_hist;     // radix histograms / scan space
+    int32_t *level_block;     // per block, per level: counts then offsets
+    uint32_t *bbox;           // 6 ordered-uint min/max
+    int64_t n;
+    int64_t max_nodes;
+    uint32_t hash_cap_max;
+    int nblk_sort, nblk_lvl;
+    GridView view() const
+    {
+        return GridView{params, pts, keys, hdr, box, hkeys, hvals};
+    }
+};
+
+size_t grid_bytes(int64_t n);
+void grid_carve(Carver &c, int64_t n, GridStore &g);
+// Builds the pyramid over xyz (n x 3 float32, device).  Asynchronous.
+hipError_t grid_build(GridStore &g, const float *xyz, hipStream_t s);
+// Gathers an (n x 3) per-point array into sorted order as float4 (w = 0).
+hipError_t grid_gather3(const GridStore &g, const float *src3, float4 *dst, hipStream_t s);
+
+int64_t max_pyramid_nodes(int64_t n);
+
+}  // namespace pcg

@@ -1,0 +1,230 @@
+// k-nearest-neighbour queries and PCA normals on the sparse voxel pyramid.
+//
+// k-NN (Section 3, "Core operations"): exact k nearest reference points of
+// each query under the float32 key, ties to the lower original index.
+// Normals (Section 3, "Core operations": normal and curvature estimation via
+// PCA; Section 4: 10-NN neighbourhoods, viewpoint-consistent orientation):
+// the k-NN of every point in its own cloud, their covariance, the unit
+// eigenvector of its smallest eigenvalue flipped toward the viewpoint, and
+// the surface variation l0/(l0+l1+l2).  The neighbour search and all loads
+// run in float32; the covariance is accumulated in float64 from the exact
+// query-relative offsets and decomposed with the closed-form trigonometric
+// eigenvalues of a symmetric 3x3 matrix (Smith 1961) and a cross product of
+// two rows of (C - l0 I) for the eigenvector (Kopp 2008).  The eigenvector
+// error of any solver scales as eps * l2 / (l1 - l0); float64 keeps it far
+// below 1e-5 rad wherever the normal is well defined.
+
+#include "icp.h"
+#include "search.h"
+
+namespace pcg {
+
+namespace {
+
+constexpr int kQThreads = 256;
+
+template <int KT>
+__global__ void __launch_bounds__(kQThreads) k_knn(GridView g, const float *__restrict__ qry, int64_t nq, int k,
+                                                 int32_t *__restrict__ out_idx, float *__restrict__ out_d2)
+{
+    __shared__ uint2 stk[kStack * kQThreads];
+    const GridParams P = *g.params;
+    int64_t i = blockIdx.x * (int64_t)kQThreads + threadIdx.x;
+    if (i >= nq) return;
+    Query q{qry[3 * i], qry[3 * i + 1], qry[3 * i + 2]};
+    TopK<KT> top;
+    top.init(k);
+    search<KT, 32>(g, P, q, top, k, INFINITY, stk + threadIdx.x, kQThreads);
+#pragma unroll
+    for (int s = 0; s < KT; s++) {
+        if (s >= KT - k) {
+            int o = s - (KT - k);
+            out_idx[i * k + o] = (int32_t)(uint32_t)top.h[s];
+            if (out_d2) out_d2[i * k + o] = __uint_as_float((uint32_t)(top.h[s] >> 32));
+        }
+    }
+}
+
+// eigen-decomposition of the symmetric C = [a b c; b d e; c e f] (float64):
+// ascending eigenvalues and the unit eigenvector of the smallest
+__device__ void sym3_min_eigvec(double a, double b, double c, double d, double e, double f, double lam[3],
+                                double v[3])
+{
+    double p1 = b * b + c * c + e * e;
+    if (p1 == 0.0) {
+        double dg[3] = {a, d, f};
+        int o[3] = {0, 1, 2};
+        for (int i = 0; i < 3; i++)
+            for (int j = i + 1; j < 3; j++)
+                if (dg[o[j]] < dg[o[i]]) { int t = o[i]; o[i] = o[j]; o[j] = t; }
+        for (int i = 0; i < 3; i++) lam[i] = dg[o[i]];
+        v[0] = v[1] = v[2] = 0.0;
+        v[o[0]] = 1.0;
+        return;
+    }
+    double q = (a + d + f) / 3.0;
+    double ba = a - q, bd = d - q, bf = f - q;
+    double p2 = ba * ba + bd * bd + bf * bf + 2.0 * p1;
+    double p = sqrt(p2 / 6.0);
+    double det = ba * (bd * bf - e * e) - b * (b * bf - e * c) + c * (b * e - bd * c);
+    double r = det / (2.0 * p * p * p);
+    r = r < -1.0 ? -1.0 : (r > 1.0 ? 1.0 : r);
+    double phi = acos(r) / 3.0;
+    double l2 = q + 2.0 * p * cos(phi);
+    double l0 = q + 2.0 * p * cos(phi + 2.0943951023931954923);   // + 2 pi / 3
+    double l1 = 3.0 * q - l0 - l2;
+    lam[0] = l0;
+    lam[1] = l1;
+    lam[2] = l2;
+    double r0[3] = {a - l0, b, c}, r1[3] = {b, d - l0, e}, r2[3] = {c, e, f - l0};
+    double x01[3] = {r0[1] * r1[2] - r0[2] * r1[1], r0[2] * r1[0] - r0[0] * r1[2], r0[0] * r1[1] - r0[1] * r1[0]};
+    double x02[3] = {r0[1] * r2[2] - r0[2] * r2[1], r0[2] * r2[0] - r0[0] * r2[2], r0[0] * r2[1] - r0[1] * r2[0]};
+    double x12[3] = {r1[1] * r2[2] - r1[2] * r2[1], r1[2] * r2[0] - r1[0] * r2[2], r1[0] * r2[1] - r1[1] * r2[0]};
+    double n01 = x01[0] * x01[0] + x01[1] * x01[1] + x01[2] * x01[2];
+    double n02 = x02[0] * x02[0] + x02[1] * x02[1] + x02[2] * x02[2];
+    double n12 = x12[0] * x12[0] + x12[1] * x12[1] + x12[2] * x12[2];
+    const double *best = x01;
+    double nb = n01;
+    if (n02 > nb) { best = x02; nb = n02; }
+    if (n12 > nb) { best = x12; nb = n12; }
+    double scale = fabs(l2) + fabs(l0);
+    if (nb > 1e-60 * scale * scale * scale * scale && nb > 0.0) {
+        double s = 1.0 / sqrt(nb);
+        v[0] = best[0] * s;
+        v[1] = best[1] * s;
+        v[2] = best[2] * s;
+        return;
+    }
+    // l0 (nearly) repeated: any unit vector orthogonal to the largest row of
+    // (C - l0 I) lies in its eigenspace
+    const double *row = r0;
+    double rn = r0[0] * r0[0] + r0[1] * r0[1] + r0[2] * r0[2];
+    double t1 = r1[0] * r1[0] + r1[1] * r1[1] + r1[2] * r1[2];
+    double t2 = r2[0] * r2[0] + r2[1] * r2[1] + r2[2] * r2[2];
+    if (t1 > rn) { row = r1; rn = t1; }
+    if (t2 > rn) { row = r2; rn = t2; }
+    if (!(rn > 0.0)) {
+        v[0] = 1.0; v[1] = 0.0; v[2] = 0.0;
+        return;
+    }
+    int ax = 0;
+    if (fabs(row[1]) < fabs(row[ax])) ax = 1;
+    if (fabs(row[2]) < fabs(row[ax])) ax = 2;
+    double ea[3] = {0.0, 0.0, 0.0};
+    ea[ax] = 1.0;
+    double w[3] = {row[1] * ea[2] - row[2] * ea[1], row[2] * ea[0] - row[0] * ea[2], row[0] * ea[1] - row[1] * ea[0]};
+    double s = 1.0 / sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
+    v[0] = w[0] * s;
+    v[1] = w[1] * s;
+    v[2] = w[2] * s;
+}
+
+template <int KT>
+__global__ void __launch_bounds__(kQThreads) k_normals(GridView g, const float *__restrict__ xyz, int k, float vx,
+                                                     float vy, float vz, float *__restrict__ out_n,
+                                                     float *__restrict__ out_c)
+{
+    __shared__ uint2 stk[kStack * kQThreads];
+    const GridParams P = *g.params;
+    int64_t s = blockIdx.x * (int64_t)kQThreads + threadIdx.x;
+    if (s >= P.n) return;
+    float4 p = g.pts[s];
+    uint32_t qi = __float_as_uint(p.w);
+    Query q{p.x, p.y, p.z};
+    TopK<KT> top;
+    top.init(k);
+    search<KT, 32>(g, P, q, top, k, INFINITY, stk + threadIdx.x, kQThreads);
+    // offsets from the query point are exact in float64 (differences of
+    // float32 values); covariance is translation invariant
+    double qx = p.x, qy = p.y, qz = p.z;
+    double mx = 0.0, my = 0.0, mz = 0.0;
+#pragma unroll
+    for (int t = 0; t < KT; t++) {
+        if (t < KT - k) continue;
+        uint32_t j = (uint32_t)top.h[t];
+        if (j >= (uint32_t)P.n) continue;   // unfilled slot (cannot happen for k <= n)
+        mx += (double)xyz[3 * (int64_t)j] - qx;
+        my += (double)xyz[3 * (int64_t)j + 1] - qy;
+        mz += (double)xyz[3 * (int64_t)j + 2] - qz;
+    }
+    mx /= k;
+    my /= k;
+    mz /= k;
+    double cxx = 0, cxy = 0, cxz = 0, cyy = 0, cyz = 0, czz = 0;
+#pragma unroll
+    for (int t = 0; t < KT; t++) {
+        if (t < KT - k) continue;
+        uint32_t j = (uint32_t)top.h[t];
+        if (j >= (uint32_t)P.n) continue;
+        double ex = ((double)xyz[3 * (int64_t)j] - qx) - mx;
+        double ey = ((double)xyz[3 * (int64_t)j + 1] - qy) - my;
+        double ez = ((double)xyz[3 * (int64_t)j + 2] - qz) - mz;
+        cxx += ex * ex;
+        cxy += ex * ey;
+        cxz += ex * ez;
+        cyy += ey * ey;
+        cyz += ey * ez;
+        czz += ez * ez;
+    }
+    cxx /= k; cxy /= k; cxz /= k; cyy /= k; cyz /= k; czz /= k;
+    double n[3] = {0.0, 0.0, 0.0}, lam[3] = {0.0, 0.0, 0.0};
+    bool zero = cxx == 0.0 && cxy == 0.0 && cxz == 0.0 && cyy == 0.0 && cyz == 0.0 && czz == 0.0;
+    if (!zero) {
+        sym3_min_eigvec(cxx, cxy, cxz, cyy, cyz, czz, lam, n);
+        double dot = n[0] * ((double)vx - qx) + n[1] * ((double)vy - qy) + n[2] * ((double)vz - qz);
+        bool flip = dot < 0.0;
+        if (dot == 0.0) {
+            for (int a = 0; a < 3; a++)
+                if (n[a] != 0.0) { flip = n[a] < 0.0; break; }
+        }
+        if (flip) { n[0] = -n[0]; n[1] = -n[1]; n[2] = -n[2]; }
+    }
+    out_n[3 * (int64_t)qi] = (float)n[0];
+    out_n[3 * (int64_t)qi + 1] = (float)n[1];
+    out_n[3 * (int64_t)qi + 2] = (float)n[2];
+    if (out_c) {
+        double tr = lam[0] + lam[1] + lam[2];
+        out_c[qi] = (float)(tr > 0.0 ? lam[0] / tr : 0.0);
+    }
+}
+
+template <int KT>
+void launch_knn(const GridStore &g, const float *qry, int64_t nq, int k, int32_t *oi, float *od, hipStream_t s)
+{
+    int blocks = (int)((nq + kQThreads - 1) / kQThreads);
+    k_knn<KT><<<blocks, kQThreads, 0, s>>>(g.view(), qry, nq, k, oi, od);
+}
+
+template <int KT>
+void launch_normals(const GridStore &g, const float *xyz, int k, const float *vp, float *on, float *oc,
+                    hipStream_t s)
+{
+    int blocks = (int)((g.n + kQThreads - 1) / kQThreads);
+    k_normals<KT><<<blocks, kQThreads, 0, s>>>(g.view(), xyz, k, vp[0], vp[1], vp[2], on, oc);
+}
+
+}  // namespace
+
+hipError_t knn_run(const GridStore &g, const float *qry, int64_t nq, int k, int32_t *oi, float *od, hipStream_t s)
+{
+    if (nq <= 0) return hipSuccess;
+    if (k <= 1) launch_knn<1>(g, qry, nq, k, oi, od, s);
+    else if (k <= 4) launch_knn<4>(g, qry, nq, k, oi, od, s);
+    else if (k <= 8) launch_knn<8>(g, qry, nq, k, oi, od, s);
+    else if (k <= 16) launch_knn<16>(g, qry, nq, k, oi, od, s);
+    else launch_knn<32>(g, qry, nq, k, oi, od, s);
+    return hipGetLastError();
+}
+
+hipError_t normals_run(const GridStore &g, const float *xyz, int k, const float *vp, float *on, float *oc,
+                       hipStream_t s)
+{
+    if (g.n <= 0) return hipSuccess;
+    if (k <= 4) launch_normals<4>(g, xyz, k, vp, on, oc, s);
+    else if (k <= 8) launch_normals<8>(g, xyz, k, vp, on, oc, s);
+    else if (k <= 16) launch_normals<16>(g, xyz, k, vp, on, oc, s);
+    else launch_normals<32>(g, xyz, k, vp, on, oc, s);
+    return hipGetLastError();
+}
+
+}  // namespace pcg

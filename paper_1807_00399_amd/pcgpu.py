@@ -1,0 +1,201 @@
+"""ctypes binding of libpcgpu.so (the C ABI declared in include/pcgpu.h).
+
+Argument marshalling only: every step runs in the library's HIP kernels.
+Tensors are torch CUDA (ROCm) tensors; PyTorch supplies device memory and
+the current stream.  If the library is not built this module raises at
+import time -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpcgpu.so")
+
+PC_OK, PC_EINVAL, PC_EWORKSPACE, PC_EDEVICE = 0, 1, 2, 3
+PC_ICP_CONVERGED, PC_ICP_MAXITER, PC_ICP_DEGENERATE, PC_ICP_NO_INLIERS = 0, 1, 2, 3
+KMAX = 32
+
+# every symbol the header declares
+EXPORTS = (
+    "pc_status_string",
+    "knn_search_workspace_size", "knn_search",
+    "estimate_normals_workspace_size", "estimate_normals",
+    "icp_point_to_plane_workspace_size", "icp_point_to_plane",
+    "pc_copy_probe", "icp_history",
+)
+
+
+class PcgpuError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        super().__init__(f"{what}: {status_string(status)}")
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run `python -m paper_1807_00399_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32, f32, f64, sz = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_int, ctypes.c_float,
+                                  ctypes.c_double, ctypes.c_size_t)
+    lib.pc_status_string.argtypes = [ctypes.c_int]
+    lib.pc_status_string.restype = ctypes.c_char_p
+    lib.knn_search_workspace_size.argtypes = [i64, i64, i32]
+    lib.knn_search_workspace_size.restype = sz
+    lib.knn_search.argtypes = [vp, i64, vp, i64, i32, vp, vp, vp, sz, vp]
+    lib.knn_search.restype = ctypes.c_int
+    lib.estimate_normals_workspace_size.argtypes = [i64, i32]
+    lib.estimate_normals_workspace_size.restype = sz
+    lib.estimate_normals.argtypes = [vp, i64, i32, ctypes.POINTER(ctypes.c_float), vp, vp, vp, sz, vp]
+    lib.estimate_normals.restype = ctypes.c_int
+    lib.icp_point_to_plane_workspace_size.argtypes = [i64, i64, i32]
+    lib.icp_point_to_plane_workspace_size.restype = sz
+    lib.icp_point_to_plane.argtypes = [vp, i64, vp, vp, i64, vp, f32, i32, f64, vp, vp, vp, sz, vp]
+    lib.icp_point_to_plane.restype = ctypes.c_int
+    lib.pc_copy_probe.argtypes = [vp, vp, sz, vp]
+    lib.pc_copy_probe.restype = ctypes.c_int
+    lib.icp_history.argtypes = [vp, sz, i64, i64, i32]
+    lib.icp_history.restype = ctypes.c_void_p
+    return lib
+
+
+lib = _load()
+
+
+def status_string(s: int) -> str:
+    return lib.pc_status_string(int(s)).decode()
+
+
+def _check(st: int, what: str):
+    if st != PC_OK:
+        raise PcgpuError(st, what)
+
+
+def _stream(stream=None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _pts(t: torch.Tensor, name: str) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float32 or t.dim() != 2 or t.shape[1] != 3:
+        raise ValueError(f"{name} must be a float32 (n, 3) tensor")
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    return t.contiguous()
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+class Workspace:
+    """Grow-only device scratch buffer (one per device)."""
+
+    def __init__(self):
+        self._buf: dict[int, torch.Tensor] = {}
+
+    def get(self, nbytes: int, device: torch.device) -> torch.Tensor:
+        idx = device.index if device.index is not None else torch.cuda.current_device()
+        b = self._buf.get(idx)
+        if b is None or b.numel() < nbytes:
+            b = torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+            self._buf[idx] = b
+        return b
+
+
+_ws = Workspace()
+
+
+def knn_search(ref: torch.Tensor, qry: torch.Tensor, k: int, return_d2: bool = True, stream=None,
+               workspace: torch.Tensor | None = None):
+    """Exact k-NN: (idx int32 (nq,k), d2 float32 (nq,k) or None)."""
+    ref = _pts(ref, "ref")
+    qry = ref if qry is ref else _pts(qry, "qry")
+    nq = qry.shape[0]
+    idx = torch.empty((nq, k), dtype=torch.int32, device=ref.device)
+    d2 = torch.empty((nq, k), dtype=torch.float32, device=ref.device) if return_d2 else None
+    need = lib.knn_search_workspace_size(ref.shape[0], nq, k)
+    ws = workspace if workspace is not None else _ws.get(need, ref.device)
+    st = lib.knn_search(ref.data_ptr(), ref.shape[0], qry.data_ptr(), nq, int(k), idx.data_ptr(), _ptr(d2),
+                        ws.data_ptr(), ws.numel(), _stream(stream))
+    _check(st, "knn_search")
+    return idx, d2
+
+
+def estimate_normals(xyz: torch.Tensor, k: int, viewpoint=(0.0, 0.0, 0.0), curvature: bool = True,
+                     stream=None, workspace: torch.Tensor | None = None):
+    """PCA normals (n,3) float32 and curvature (n,) float32 or None."""
+    xyz = _pts(xyz, "xyz")
+    n = xyz.shape[0]
+    nrm = torch.empty((n, 3), dtype=torch.float32, device=xyz.device)
+    cur = torch.empty((n,), dtype=torch.float32, device=xyz.device) if curvature else None
+    vp = (ctypes.c_float * 3)(*[float(v) for v in viewpoint])
+    need = lib.estimate_normals_workspace_size(n, k)
+    ws = workspace if workspace is not None else _ws.get(need, xyz.device)
+    st = lib.estimate_normals(xyz.data_ptr(), n, int(k), vp, nrm.data_ptr(), _ptr(cur), ws.data_ptr(),
+                              ws.numel(), _stream(stream))
+    _check(st, "estimate_normals")
+    return nrm, cur
+
+
+STATS_DTYPE = [("status", "<i4"), ("iterations_run", "<i4"), ("inliers", "<i8"), ("rms", "<f8")]
+
+
+def icp_point_to_plane(src: torch.Tensor, tgt: torch.Tensor, tgt_normals: torch.Tensor, init_T=None,
+                       max_corr_dist: float = 0.05, max_iters: int = 30, conv_tol: float = 0.0,
+                       stream=None, workspace: torch.Tensor | None = None, out_T: torch.Tensor | None = None,
+                       out_stats: torch.Tensor | None = None, read_stats: bool = True):
+    """Point-to-plane ICP.  Returns (T (4,4) float64 device tensor, stats).
+
+    stats is a dict read back from the device when read_stats is True
+    (this synchronises the stream), else the raw 24-byte device tensor."""
+    src = _pts(src, "src")
+    tgt = _pts(tgt, "tgt")
+    tgt_normals = _pts(tgt_normals, "tgt_normals")
+    if tgt_normals.shape[0] != tgt.shape[0]:
+        raise ValueError("tgt_normals must match tgt")
+    dev = src.device
+    T0 = None
+    if init_T is not None:
+        T0 = torch.as_tensor(init_T, dtype=torch.float64).reshape(4, 4).to(dev).contiguous()
+    T = out_T if out_T is not None else torch.empty((4, 4), dtype=torch.float64, device=dev)
+    stats = out_stats if out_stats is not None else torch.zeros(24, dtype=torch.uint8, device=dev)
+    need = lib.icp_point_to_plane_workspace_size(src.shape[0], tgt.shape[0], int(max_iters))
+    ws = workspace if workspace is not None else _ws.get(need, dev)
+    st = lib.icp_point_to_plane(src.data_ptr(), src.shape[0], tgt.data_ptr(), tgt_normals.data_ptr(),
+                                tgt.shape[0], _ptr(T0), float(max_corr_dist), int(max_iters), float(conv_tol),
+                                T.data_ptr(), stats.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream))
+    _check(st, "icp_point_to_plane")
+    if not read_stats:
+        return T, stats
+    return T, decode_stats(stats)
+
+
+def decode_stats(stats: torch.Tensor) -> dict:
+    import numpy as np
+    raw = stats.cpu().numpy().tobytes()
+    rec = np.frombuffer(raw, dtype=np.dtype(STATS_DTYPE))[0]
+    return {name: rec[name].item() for name, _ in STATS_DTYPE}
+
+
+def icp_history(workspace: torch.Tensor, n_src: int, n_tgt: int, max_iters: int, iterations: int):
+    """(iterations, 8) float64 host array: increment, inliers, sum r^2."""
+    p = lib.icp_history(workspace.data_ptr(), workspace.numel(), n_src, n_tgt, max_iters)
+    if not p or iterations <= 0:
+        return None
+    off = p - workspace.data_ptr()
+    h = workspace[off: off + 8 * 8 * iterations].view(torch.float64).reshape(iterations, 8)
+    return h.cpu().numpy()
+
+
+def workspace_for_icp(n_src: int, n_tgt: int, max_iters: int, device) -> torch.Tensor:
+    need = lib.icp_point_to_plane_workspace_size(n_src, n_tgt, max_iters)
+    return torch.empty(need, dtype=torch.uint8, device=device)
+
+
+def copy_probe(dst: torch.Tensor, src: torch.Tensor, stream=None):
+    _check(lib.pc_copy_probe(dst.data_ptr(), src.data_ptr(), src.numel() * src.element_size(), _stream(stream)),
+           "pc_copy_probe")

@@ -1,0 +1,109 @@
+"""C-ABI contract on the CPU: the library loads, exports every function the
+header declares, and rejects bad arguments before any device work."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pcgpu.h")
+
+
+@pytest.fixture(scope="module")
+def pc():
+    from paper_1807_00399_amd import pcgpu
+    return pcgpu
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+def test_header_functions_are_exported(pc):
+    names = declared_functions()
+    assert len(names) >= 9
+    for n in names:
+        assert hasattr(pc.lib, n), n
+    assert set(names) == set(pc.EXPORTS)
+
+
+def test_status_strings(pc):
+    assert pc.status_string(0) == "PC_OK"
+    assert "invalid" in pc.status_string(1)
+
+
+def test_workspace_sizes_monotone(pc):
+    a = pc.lib.knn_search_workspace_size(1000, 10, 4)
+    b = pc.lib.knn_search_workspace_size(100000, 10, 4)
+    assert 0 < a < b
+    assert pc.lib.icp_point_to_plane_workspace_size(-1, 10, 1) == 0
+    assert pc.lib.icp_point_to_plane_workspace_size(10, 10, 5) > pc.lib.knn_search_workspace_size(10, 10, 4)
+
+
+FAKE = 1 << 20          # an aligned non-null address; never dereferenced on these paths
+
+
+def test_knn_rejects_bad_arguments(pc):
+    L = pc.lib
+    ws = L.knn_search_workspace_size(100, 10, 4)
+    ok = dict(ref=FAKE, nr=100, q=FAKE, nq=10, k=4, oi=FAKE, od=None, w=FAKE, wb=ws)
+
+    def call(**kw):
+        a = dict(ok, **kw)
+        return L.knn_search(a["ref"], a["nr"], a["q"], a["nq"], a["k"], a["oi"], a["od"], a["w"], a["wb"], None)
+
+    assert call(ref=None) == pc.PC_EINVAL
+    assert call(nr=0) == pc.PC_EINVAL
+    assert call(k=0) == pc.PC_EINVAL
+    assert call(k=33) == pc.PC_EINVAL
+    assert call(k=101) == pc.PC_EINVAL
+    assert call(nq=-1) == pc.PC_EINVAL
+    assert call(oi=None) == pc.PC_EINVAL
+    assert call(ref=FAKE + 2) == pc.PC_EINVAL
+    assert call(w=FAKE + 16) == pc.PC_EINVAL
+    assert call(wb=ws - 1) == pc.PC_EWORKSPACE
+
+
+def test_normals_rejects_bad_arguments(pc):
+    L = pc.lib
+    vp = (ctypes.c_float * 3)(0, 0, 0)
+    ws = L.estimate_normals_workspace_size(100, 10)
+    assert L.estimate_normals(FAKE, 100, 0, vp, FAKE, None, FAKE, ws, None) == pc.PC_EINVAL
+    assert L.estimate_normals(FAKE, 100, 101, vp, FAKE, None, FAKE, ws, None) == pc.PC_EINVAL
+    assert L.estimate_normals(FAKE, 5, 6, vp, FAKE, None, FAKE, ws, None) == pc.PC_EINVAL
+    assert L.estimate_normals(None, 100, 10, vp, FAKE, None, FAKE, ws, None) == pc.PC_EINVAL
+    assert L.estimate_normals(FAKE, 100, 10, None, FAKE, None, FAKE, ws, None) == pc.PC_EINVAL
+    bad = (ctypes.c_float * 3)(float("nan"), 0, 0)
+    assert L.estimate_normals(FAKE, 100, 10, bad, FAKE, None, FAKE, ws, None) == pc.PC_EINVAL
+    assert L.estimate_normals(FAKE, 100, 10, vp, FAKE, None, FAKE, ws - 1, None) == pc.PC_EWORKSPACE
+    # empty input is a valid no-op
+    assert L.estimate_normals(None, 0, 10, vp, None, None, None, 0, None) == pc.PC_OK
+
+
+def test_icp_rejects_bad_arguments(pc):
+    L = pc.lib
+    ws = L.icp_point_to_plane_workspace_size(100, 100, 5)
+
+    def call(src=FAKE, ns=100, tgt=FAKE, nrm=FAKE, nt=100, T0=None, d=0.1, it=5, tol=0.0, out=FAKE, w=FAKE, wb=ws):
+        return L.icp_point_to_plane(src, ns, tgt, nrm, nt, T0, d, it, tol, out, None, w, wb, None)
+
+    assert call(d=0.0) == pc.PC_EINVAL
+    assert call(d=float("inf")) == pc.PC_EINVAL
+    assert call(d=float("nan")) == pc.PC_EINVAL
+    assert call(it=-1) == pc.PC_EINVAL
+    assert call(tol=-1.0) == pc.PC_EINVAL
+    assert call(out=None) == pc.PC_EINVAL
+    assert call(nrm=None) == pc.PC_EINVAL
+    assert call(T0=FAKE + 4) == pc.PC_EINVAL
+    assert call(ns=-5) == pc.PC_EINVAL
+    assert call(wb=ws - 1) == pc.PC_EWORKSPACE
+
+
+def test_copy_probe_rejects_bad_arguments(pc):
+    assert pc.lib.pc_copy_probe(FAKE, FAKE, 17, None) == pc.PC_EINVAL
+    assert pc.lib.pc_copy_probe(None, FAKE, 16, None) == pc.PC_EINVAL
+    assert pc.lib.pc_copy_probe(FAKE, FAKE, 0, None) == pc.PC_OK

@@ -1,0 +1,155 @@
+"""GPU parity: point-to-plane ICP through the C ABI against the oracle.
+
+Both sides get the same target normals (the oracle's, rounded to float32)
+so the comparison isolates the ICP loop; the end-to-end test gives each side
+its own normals.  Bar: rotation within 1e-5 rad and translation within 1e-6
+of the oracle's pose."""
+import numpy as np
+import pytest
+
+from gen import apply_rigid, make_workload, random_rigid, rng_for, sphere_plane
+from tests.helpers import pose_err
+
+pytestmark = pytest.mark.gpu
+
+ROT_TOL = 1e-5
+TRANS_TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1807_00399_amd import pcgpu
+    return pcgpu
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _oracle_normals(oracle_mod, pts, k):
+    n, _, _ = oracle_mod.normals(pts, k, (0, 0, 0))
+    return n.astype(np.float32)
+
+
+def _run_gpu(gpu, src, tgt, nrm, T0, d_max, iters, tol=0.0):
+    T, st = gpu.icp_point_to_plane(_dev(src), _dev(tgt), _dev(nrm), T0, d_max, iters, tol)
+    return T.cpu().numpy(), st
+
+
+def _parity(gpu, oracle_mod, src, tgt, nrm, T0, d_max, iters, tol=0.0, label=""):
+    _say(f"icp {label} n_src={len(src)} n_tgt={len(tgt)} d_max={d_max} iters={iters}")
+    Tg, sg = _run_gpu(gpu, src, tgt, nrm, T0, d_max, iters, tol)
+    ro = oracle_mod.icp(src, tgt, nrm, T0, d_max, iters, tol)
+    ea, et = pose_err(Tg, ro["T"])
+    assert sg["status"] == ro["status"], (sg, ro["status"])
+    assert sg["iterations_run"] == ro["iterations"]
+    assert ea <= ROT_TOL and et <= TRANS_TOL, f"pose differs: {ea:.3g} rad, {et:.3g}"
+    # inlier counts may differ only for pairs within float32 rounding of d_max
+    assert abs(sg["inliers"] - ro["inliers"]) <= max(2, 1e-4 * len(src))
+    return Tg, sg, ro
+
+
+@pytest.mark.parametrize("cfg,size", [(0, "small"), (0, "full"), (1, "small"), (2, "small")])
+def test_icp_workloads(gpu, oracle_mod, cfg, size):
+    w = make_workload(cfg, size=size)
+    nrm = _oracle_normals(oracle_mod, w.target, w.k)
+    _parity(gpu, oracle_mod, w.source, w.target, nrm, None, w.d_max, w.iters, label=w.name)
+
+
+def test_icp_recovers_ground_truth_workload0(gpu, oracle_mod):
+    w = make_workload(0)
+    nrm = _oracle_normals(oracle_mod, w.target, w.k)
+    Tg, sg = _run_gpu(gpu, w.source, w.target, nrm, None, w.d_max, w.iters)
+    ea, et = pose_err(Tg, w.T_gt)
+    assert ea < 1e-5 and et < 1e-6
+
+
+def test_icp_end_to_end_own_normals(gpu, oracle_mod):
+    # each side estimates its own normals (GPU kernels vs oracle)
+    w = make_workload(0)
+    n_gpu, _ = gpu.estimate_normals(_dev(w.target), w.k)
+    T, sg = gpu.icp_point_to_plane(_dev(w.source), _dev(w.target), n_gpu, None, w.d_max, w.iters)
+    ro = oracle_mod.icp(w.source, w.target, _oracle_normals(oracle_mod, w.target, w.k), None, w.d_max, w.iters)
+    ea, et = pose_err(T.cpu().numpy(), ro["T"])
+    assert ea <= ROT_TOL and et <= TRANS_TOL
+
+
+def test_icp_identity_pair_bit_exact(gpu, oracle_mod):
+    pts = sphere_plane(rng_for(600), 3000)
+    nrm = _oracle_normals(oracle_mod, pts, 10)
+    Tg, sg = _run_gpu(gpu, pts, pts, nrm, None, 0.1, 10)
+    assert np.array_equal(Tg, np.eye(4))
+    assert sg["rms"] == 0.0 and sg["inliers"] == 3000
+
+
+def test_icp_init_pose_and_equivariance(gpu, oracle_mod):
+    w = make_workload(0, size="small")
+    nrm = _oracle_normals(oracle_mod, w.target, w.k)
+    T0 = random_rigid(rng_for(601), 3.0, 0.02) @ w.T_gt
+    _parity(gpu, oracle_mod, w.source, w.target, nrm, T0, w.d_max, 15, label="init")
+    G = random_rigid(rng_for(602), 40.0, 2.0)
+    tgt2 = apply_rigid(G, w.target)
+    n2 = (nrm.astype(np.float64) @ G[:3, :3].T).astype(np.float32)
+    Tg, _ = _run_gpu(gpu, w.source, tgt2, n2, G, w.d_max, w.iters)
+    To = oracle_mod.icp(w.source, w.target, nrm, None, w.d_max, w.iters)["T"]
+    ea, et = pose_err(Tg, G @ To)
+    assert ea < 1e-5 and et < 1e-5
+
+
+def test_icp_degenerate_plane(gpu):
+    rng = rng_for(603)
+    xy = rng.uniform(-1, 1, size=(2000, 2))
+    pts = np.column_stack([xy, np.zeros(2000)]).astype(np.float32)
+    nrm = np.tile(np.array([[0, 0, 1]], np.float32), (2000, 1))
+    Tg, sg = _run_gpu(gpu, pts, pts, nrm, None, 0.1, 5)
+    assert sg["status"] == gpu.PC_ICP_DEGENERATE and sg["iterations_run"] == 0
+    assert np.array_equal(Tg, np.eye(4))
+
+
+def test_icp_no_inliers_and_few_inliers(gpu, oracle_mod):
+    pts = sphere_plane(rng_for(604), 500)
+    nrm = _oracle_normals(oracle_mod, pts, 10)
+    far = pts + np.float32(10.0)
+    Tg, sg = _run_gpu(gpu, far, pts, nrm, None, 0.1, 5)
+    assert sg["status"] == gpu.PC_ICP_NO_INLIERS and sg["inliers"] == 0 and sg["rms"] == 0.0
+    Tg, sg = _run_gpu(gpu, np.vstack([far, pts[:4]]), pts, nrm, None, 0.1, 5)
+    assert sg["status"] == gpu.PC_ICP_DEGENERATE and sg["iterations_run"] == 0
+
+
+def test_icp_empty_source(gpu):
+    import torch
+    tgt = _dev(sphere_plane(rng_for(605), 100))
+    src = torch.empty((0, 3), dtype=torch.float32, device="cuda")
+    T0 = random_rigid(rng_for(606), 5.0, 0.1)
+    T, st = gpu.icp_point_to_plane(src, tgt, tgt, T0, 0.1, 5)
+    assert np.array_equal(T.cpu().numpy(), T0)
+    assert st["status"] == gpu.PC_ICP_NO_INLIERS
+
+
+def test_icp_zero_iterations_reports_initial_pose(gpu, oracle_mod):
+    w = make_workload(0, size="small")
+    nrm = _oracle_normals(oracle_mod, w.target, w.k)
+    _parity(gpu, oracle_mod, w.source, w.target, nrm, None, w.d_max, 0, label="zero-iter")
+
+
+def test_icp_convergence_tolerance(gpu, oracle_mod):
+    w = make_workload(0, size="small")
+    nrm = _oracle_normals(oracle_mod, w.target, w.k)
+    Tg, sg, ro = _parity(gpu, oracle_mod, w.source, w.target, nrm, None, w.d_max, 50, tol=1e-7, label="tol")
+    assert sg["status"] == gpu.PC_ICP_CONVERGED
+
+
+def test_icp_deterministic(gpu, oracle_mod):
+    w = make_workload(1, size="small")
+    nrm = _oracle_normals(oracle_mod, w.target, w.k)
+    a, sa = _run_gpu(gpu, w.source, w.target, nrm, None, w.d_max, w.iters)
+    b, sb = _run_gpu(gpu, w.source, w.target, nrm, None, w.d_max, w.iters)
+    assert np.array_equal(a, b) and sa == sb
