@@ -29,7 +29,8 @@ constexpr int kFinThreads = 1024;
 
 struct IcpState {
     double T[16];          // current pose, float64 row-major
-    float Tf[12];          // float32 copy: rows of [R | t]
+    float Thi[12];         // float32 split of rows of [R | t]: T ~ Thi + Tlo
+    float Tlo[12];
     int32_t status;        // PC_ICP_* once stopped, PC_ICP_MAXITER while running
     int32_t iters;         // increments applied
     int32_t stop;          // set once the loop must not continue
@@ -63,13 +64,112 @@ __device__ inline CSum csum_merge(CSum a, CSum b)
     return r;
 }
 
+// Correspondence search with a float64 certificate.  The float32 search
+// keeps the best candidate and the smallest key of any other candidate; a
+// decision (which target point is nearest, whether it is within d_max) is
+// taken in float32 only when no float64 evaluation could decide otherwise:
+// keys differ from the float64 squared distances of the oracle's
+// float64-transformed point by at most err(key), which bounds the rounding
+// of the float32 pose, the float32 transform and the key itself.  Ambiguous
+// queries (close runners-up or a distance at d_max) are re-decided in
+// float64 with the same expressions as the float64 definition.
+struct NearBand {
+    uint64_t best;       // (key bits << 32) | original index
+    int32_t best_pos;    // sorted position, -1 if none within the cap
+    float second;        // smallest key of any other candidate seen
+    float delta;         // bound on |p'(float32) - p'(float64)| per axis
+
+    __device__ void init(float cap2, float dlt)
+    {
+        delta = dlt;
+        best = enc_cand(cap2 + err(cap2), __uint_as_float(0xffffffffu));
+        best_pos = -1;
+        second = INFINITY;
+    }
+    __device__ float err(float key) const
+    {
+        return 6e-7f * key + 3.5f * delta * sqrtf(key) + 6.f * delta * delta + 1e-30f;
+    }
+    __device__ float best_key() const { return __uint_as_float((uint32_t)(best >> 32)); }
+    __device__ bool have() const { return best_pos >= 0; }
+    __device__ float bound2() const
+    {
+        float b = best_key();
+        return b + 2.f * err(b);
+    }
+    __device__ void visit(float qx, float qy, float qz, uint32_t j, const float4 &p)
+    {
+        float key = knn_key(p.x, p.y, p.z, qx, qy, qz);
+        uint64_t c = enc_cand(key, p.w);
+        if (c < best) {
+            if (best_pos >= 0) second = fminf(second, best_key());
+            best = c;
+            best_pos = (int32_t)j;
+        } else if ((int32_t)j != best_pos) {
+            second = fminf(second, key);
+        }
+    }
+};
+
+// float64 re-decision: nearest point by |p' - q|^2 in float64 among those
+// with |p' - q|^2 <= d_max^2, ties to the lower original index
+struct Near64 {
+    double px, py, pz, dmax2, best;
+    uint32_t best_orig;
+    int32_t best_pos;
+    float r2;            // float32 search radius^2 that holds every candidate
+
+    __device__ bool have() const { return true; }
+    __device__ float bound2() const { return r2; }
+    __device__ void visit(float, float, float, uint32_t j, const float4 &p)
+    {
+        double dx = px - (double)p.x, dy = py - (double)p.y, dz = pz - (double)p.z;
+        double d2 = dx * dx + dy * dy + dz * dz;
+        uint32_t o = __float_as_uint(p.w);
+        if (d2 <= dmax2 && (d2 < best || (d2 == best && o < best_orig))) {
+            best = d2;
+            best_orig = o;
+            best_pos = (int32_t)j;
+        }
+    }
+};
+
+// float32 (hi, lo) split of the float64 pose used by the transform below
+__device__ inline void split_pose(IcpState *st)
+{
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 4; c++) {
+            double v = st->T[r * 4 + c];
+            float h = (float)v;
+            st->Thi[r * 4 + c] = h;
+            st->Tlo[r * 4 + c] = (float)(v - (double)h);
+        }
+}
+
+// One row of p' = R p + t in double-float arithmetic: hi + lo equals the
+// product with the float64 pose to about 2^-44 relative.  Products are split
+// exactly with fmaf (TwoProd), sums with TwoSum; the lo part of the pose only
+// needs plain float32.  This keeps residuals r = (p' - q) . n accurate when
+// |p'| is metres and |p' - q| is millimetres.
+__device__ inline void df_row(const float *h, const float *l, float px, float py, float pz, float &hi, float &lo)
+{
+    float a0 = h[0] * px, e0 = __fmaf_rn(h[0], px, -a0);
+    float a1 = h[1] * py, e1 = __fmaf_rn(h[1], py, -a1);
+    float a2 = h[2] * pz, e2 = __fmaf_rn(h[2], pz, -a2);
+    float s0 = h[3] + a0, b0 = s0 - h[3], r0 = (h[3] - (s0 - b0)) + (a0 - b0);
+    float s1 = s0 + a1, b1 = s1 - s0, r1 = (s0 - (s1 - b1)) + (a1 - b1);
+    float s2 = s1 + a2, b2 = s2 - s1, r2 = (s1 - (s2 - b2)) + (a2 - b2);
+    float tail = __fmaf_rn(l[0], px, __fmaf_rn(l[1], py, __fmaf_rn(l[2], pz, l[3])));
+    hi = s2;
+    lo = ((r0 + r1) + r2) + ((e0 + e1) + e2) + tail;
+}
+
 namespace {
 
 __global__ void k_icp_setup(const double *__restrict__ init_T, IcpState *st)
 {
     for (int i = 0; i < 16; i++) st->T[i] = init_T ? init_T[i] : ((i % 5 == 0) ? 1.0 : 0.0);
-    for (int r = 0; r < 3; r++)
-        for (int c = 0; c < 4; c++) st->Tf[r * 4 + c] = (float)st->T[r * 4 + c];
+    split_pose(st);
     st->status = PC_ICP_MAXITER;
     st->iters = 0;
     st->stop = 0;
@@ -88,7 +188,7 @@ template <int PPT>
 __global__ void __launch_bounds__(kIcpThreads) k_icp_accum(GridView g, const float *__restrict__ src, int64_t ns,
                                                          const float4 *__restrict__ nrm,
                                                          int32_t *__restrict__ prev, const IcpState *__restrict__ st,
-                                                         float dmax2, int final_pass, float2 *__restrict__ part,
+                                                         float dmax, int final_pass, float2 *__restrict__ part,
                                                          uint32_t *__restrict__ pcnt)
 {
     __shared__ uint2 stk[kStack * kIcpThreads];
@@ -96,9 +196,14 @@ __global__ void __launch_bounds__(kIcpThreads) k_icp_accum(GridView g, const flo
     __shared__ uint32_t wcnt[kIcpThreads / 64];
     if (!final_pass && st->stop) return;   // uniform across the grid
     const GridParams P = *g.params;
-    float R[12];
+    float Rh[12], Rl[12];
 #pragma unroll
-    for (int i = 0; i < 12; i++) R[i] = st->Tf[i];
+    for (int i = 0; i < 12; i++) {
+        Rh[i] = st->Thi[i];
+        Rl[i] = st->Tlo[i];
+    }
+    const double dmax64 = (double)dmax;
+    const float dmax2 = dmax * dmax;
     CSum acc[kAcc];
 #pragma unroll
     for (int a = 0; a < kAcc; a++) acc[a] = CSum{0.f, 0.f};
@@ -108,26 +213,53 @@ __global__ void __launch_bounds__(kIcpThreads) k_icp_accum(GridView g, const flo
         int64_t i = base + (int64_t)r * kIcpThreads;
         if (i >= ns) break;
         float px = src[3 * i], py = src[3 * i + 1], pz = src[3 * i + 2];
-        Query q;
-        q.x = __fmaf_rn(R[0], px, __fmaf_rn(R[1], py, __fmaf_rn(R[2], pz, R[3])));
-        q.y = __fmaf_rn(R[4], px, __fmaf_rn(R[5], py, __fmaf_rn(R[6], pz, R[7])));
-        q.z = __fmaf_rn(R[8], px, __fmaf_rn(R[9], py, __fmaf_rn(R[10], pz, R[11])));
-        TopK<1> top;
-        top.init_capped(dmax2);
+        float hx, lx, hy, ly, hz, lz;
+        df_row(Rh, Rl, px, py, pz, hx, lx);
+        df_row(Rh + 4, Rl + 4, px, py, pz, hy, ly);
+        df_row(Rh + 8, Rl + 8, px, py, pz, hz, lz);
+        Query q{hx + lx, hy + ly, hz + lz};
+        // q is p' rounded to float32 (plus ~2^-44 relative): per axis it is
+        // within half an ulp, bounded here with slack, of the float64 p'
+        float dlt = fmaxf(fmaxf(fabsf(q.x), fabsf(q.y)), fabsf(q.z)) * (1.0f / (1 << 22)) +
+                    (fabsf(px) + fabsf(py) + fabsf(pz) + fabsf(Rh[3]) + fabsf(Rh[7]) + fabsf(Rh[11])) *
+                        (1.0f / (1 << 30)) + 1e-30f;
+        NearBand v;
+        v.init(dmax2, dlt);
         int32_t j0 = prev[i];
-        if (j0 >= 0) {
-            float4 c = g.pts[j0];
-            float key = knn_key(c.x, c.y, c.z, q.x, q.y, q.z);
-            top.insert(((uint64_t)__float_as_uint(key) << 32) | __float_as_uint(c.w), j0);
+        if (j0 >= 0) v.visit(q.x, q.y, q.z, (uint32_t)j0, g.pts[j0]);
+        search<NearBand, 16>(g, P, q, v, 1, stk + threadIdx.x, kIcpThreads);
+        prev[i] = v.best_pos;
+        int32_t j = -1;
+        if (v.best_pos >= 0) {
+            float b = v.best_key();
+            float e = v.err(b);
+            bool sure_in = b + e < dmax2 * (1.0f - 1.0f / (1 << 22));
+            bool sure_out = b - e > dmax2 * (1.0f + 1.0f / (1 << 22));
+            bool sure_nn = v.second > b + 2.f * e;
+            if (sure_nn && sure_in) {
+                j = v.best_pos;
+            } else if (!sure_out) {
+                const double *T = st->T;
+                Near64 w;
+                w.px = T[0] * (double)px + T[1] * (double)py + T[2] * (double)pz + T[3];
+                w.py = T[4] * (double)px + T[5] * (double)py + T[6] * (double)pz + T[7];
+                w.pz = T[8] * (double)px + T[9] * (double)py + T[10] * (double)pz + T[11];
+                w.dmax2 = dmax64 * dmax64;
+                w.best = INFINITY;
+                w.best_orig = 0xffffffffu;
+                w.best_pos = -1;
+                w.r2 = b + 2.f * e;
+                cover<Near64, 16>(g, P, q, w, stk + threadIdx.x, kIcpThreads, 0u, 0u);
+                j = w.best_pos;
+            }
         }
-        search<1, 16>(g, P, q, top, 1, dmax2, stk + threadIdx.x, kIcpThreads);
-        int32_t j = top.best_pos;
-        prev[i] = j;
         if (j < 0) continue;
         float4 n = nrm[j];
         if (n.x == 0.f && n.y == 0.f && n.z == 0.f) continue;
         float4 t = g.pts[j];
-        float dx = q.x - t.x, dy = q.y - t.y, dz = q.z - t.z;
+        // residual vector from the double-float p': (hi - q) is exact for
+        // nearby points, so it keeps the full accuracy of hi + lo
+        float dx = (hx - t.x) + lx, dy = (hy - t.y) + ly, dz = (hz - t.z) + lz;
         float res = __fmaf_rn(dz, n.z, __fmaf_rn(dy, n.y, dx * n.x));
         float J[6];
         J[0] = __fmaf_rn(q.y, n.z, -q.z * n.y);
@@ -291,8 +423,7 @@ __global__ void __launch_bounds__(kFinThreads) k_icp_finalize(const float2 *__re
     }
     st->T[12] = st->T[13] = st->T[14] = 0.0;
     st->T[15] = 1.0;
-    for (int r = 0; r < 3; r++)
-        for (int cc = 0; cc < 4; cc++) st->Tf[r * 4 + cc] = (float)st->T[r * 4 + cc];
+    split_pose(st);
     if (hist) {
         double *h = hist + 8 * st->iters;
         for (int i = 0; i < 6; i++) h[i] = x[i];
@@ -353,20 +484,20 @@ void icp_carve(Carver &c, int64_t ns, int64_t nt, int max_iters, IcpStore &s)
 }
 
 template <int PPT>
-static void launch_accum(IcpStore &s, const float *src, int64_t ns, float dmax2, int final_pass, hipStream_t st)
+static void launch_accum(IcpStore &s, const float *src, int64_t ns, float dmax, int final_pass, hipStream_t st)
 {
-    k_icp_accum<PPT><<<s.nblk, kIcpThreads, 0, st>>>(s.grid.view(), src, ns, s.nrm, s.prev, s.st, dmax2,
+    k_icp_accum<PPT><<<s.nblk, kIcpThreads, 0, st>>>(s.grid.view(), src, ns, s.nrm, s.prev, s.st, dmax,
                                                      final_pass, s.part, s.pcnt);
 }
 
-static void accum(IcpStore &s, const float *src, int64_t ns, float dmax2, int final_pass, hipStream_t st)
+static void accum(IcpStore &s, const float *src, int64_t ns, float dmax, int final_pass, hipStream_t st)
 {
     switch (s.ppt) {
-    case 1: launch_accum<1>(s, src, ns, dmax2, final_pass, st); break;
-    case 2: launch_accum<2>(s, src, ns, dmax2, final_pass, st); break;
-    case 4: launch_accum<4>(s, src, ns, dmax2, final_pass, st); break;
-    case 8: launch_accum<8>(s, src, ns, dmax2, final_pass, st); break;
-    default: launch_accum<16>(s, src, ns, dmax2, final_pass, st); break;
+    case 1: launch_accum<1>(s, src, ns, dmax, final_pass, st); break;
+    case 2: launch_accum<2>(s, src, ns, dmax, final_pass, st); break;
+    case 4: launch_accum<4>(s, src, ns, dmax, final_pass, st); break;
+    case 8: launch_accum<8>(s, src, ns, dmax, final_pass, st); break;
+    default: launch_accum<16>(s, src, ns, dmax, final_pass, st); break;
     }
 }
 
@@ -384,13 +515,12 @@ hipError_t icp_run(IcpStore &s, const float *src, int64_t ns, const float *tgt, 
     e = grid_gather3(s.grid, tgt_n, s.nrm, st);
     if (e != hipSuccess) return e;
     k_fill_i32<<<(int)((ns + 255) / 256 < 2048 ? (ns + 255) / 256 : 2048), 256, 0, st>>>(s.prev, ns, -1);
-    float dmax2 = dmax * dmax;
     for (int it = 0; it < max_iters; it++) {
-        accum(s, src, ns, dmax2, 0, st);
+        accum(s, src, ns, dmax, 0, st);
         k_icp_finalize<<<1, kFinThreads, 0, st>>>(s.part, s.pcnt, s.nblk, s.st, 0, conv_tol, out_T, out_stats,
                                                   s.hist);
     }
-    accum(s, src, ns, dmax2, 1, st);
+    accum(s, src, ns, dmax, 1, st);
     k_icp_finalize<<<1, kFinThreads, 0, st>>>(s.part, s.pcnt, s.nblk, s.st, 1, conv_tol, out_T, out_stats, s.hist);
     return hipGetLastError();
 }

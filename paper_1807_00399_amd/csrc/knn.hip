@@ -34,7 +34,7 @@ __global__ void __launch_bounds__(kQThreads) k_knn(GridView g, const float *__re
     Query q{qry[3 * i], qry[3 * i + 1], qry[3 * i + 2]};
     TopK<KT> top;
     top.init(k);
-    search<KT, 32>(g, P, q, top, k, INFINITY, stk + threadIdx.x, kQThreads);
+    search<TopK<KT>, 32>(g, P, q, top, k, stk + threadIdx.x, kQThreads);
 #pragma unroll
     for (int s = 0; s < KT; s++) {
         if (s >= KT - k) {
@@ -133,7 +133,7 @@ __global__ void __launch_bounds__(kQThreads) k_normals(GridView g, const float *
     Query q{p.x, p.y, p.z};
     TopK<KT> top;
     top.init(k);
-    search<KT, 32>(g, P, q, top, k, INFINITY, stk + threadIdx.x, kQThreads);
+    search<TopK<KT>, 32>(g, P, q, top, k, stk + threadIdx.x, kQThreads);
     // offsets from the query point are exact in float64 (differences of
     // float32 values); covariance is translation invariant
     double qx = p.x, qy = p.y, qz = p.z;

@@ -1,53 +1,48 @@
 // Exact nearest-neighbour search over the sparse voxel pyramid.
 //
-// One lane answers one query.  Candidates are ranked by the float32 key
-// fmaf(dz,dz, fmaf(dy,dy, dx*dx)) of float32 differences and then by the
-// point's original index, the same total order as the k-NN definition, and
-// the k best are kept in a register-resident sorted list of 64-bit words
-// (key bits << 32 | original index).
+// One lane answers one query.  The traversal is generic over a candidate
+// visitor V (the ranking and the running search radius live there):
+//   bool  V::have()          a finite radius is already known (warm start)
+//   float V::bound2()        current search radius^2 (float32, inclusive)
+//   void  V::visit(j, p)     offer sorted point j with coordinates p
 //
 // The search has two phases:
-//   seed  - the smallest cell containing the query that holds enough points
-//           is searched first, which gives a finite radius R (k-th key);
+//   seed  - the smallest cell containing the query that holds `need` points
+//           is searched first, which gives a finite radius;
 //   cover - the cells of the coarsest useful level (width >= 2R) that meet
 //           the ball of radius R are searched depth-first, children nearest
 //           first, skipping every cell whose box is farther than the current
-//           k-th key and every point range the seed already contributed.
+//           radius and every point range the seed already contributed.
 // Cell boxes are shrunk by an absolute margin and a relative factor, so a
-// cell is skipped only when all of its points are strictly worse than the
-// current k-th candidate: the result is exact, ties included.
+// cell is skipped only when every point in it is strictly outside the
+// radius: no candidate inside the radius is ever missed, ties included.
 #pragma once
 
 #include "common.h"
 
 namespace pcg {
 
-constexpr int kStack = 16;          // per-lane DFS stack entries (LDS)
+constexpr int kStack = 16;              // per-lane DFS stack entries (LDS)
 constexpr int kVisitBudget = 1 << 20;   // node pops per DFS; only a corrupted tree reaches it
 
+__device__ inline uint64_t enc_cand(float key, float w) { return ((uint64_t)__float_as_uint(key) << 32) | __float_as_uint(w); }
+
+// k best candidates by (float32 key, original index): the k-NN definition.
 template <int KT>
 struct TopK {
     uint64_t h[KT];     // ascending; ~0 = empty; 0 = padding when k < KT
-    int32_t best_pos;   // sorted position of h[KT-1]'s point when KT == 1
 
     __device__ void init(int k)
     {
 #pragma unroll
         for (int s = 0; s < KT; s++) h[s] = (s < KT - k) ? 0ull : ~0ull;
-        best_pos = -1;
     }
-    // 1-NN with an inclusive acceptance radius: only keys <= cap2 enter
-    __device__ void init_capped(float cap2)
-    {
-        h[KT - 1] = ((uint64_t)__float_as_uint(cap2) << 32) | 0xffffffffull;
-        best_pos = -1;
-    }
-    __device__ bool full() const { return h[KT - 1] != ~0ull; }
+    __device__ bool have() const { return h[KT - 1] != ~0ull; }
     __device__ float bound2() const
     {
-        return full() ? __uint_as_float((uint32_t)(h[KT - 1] >> 32)) : INFINITY;
+        return have() ? __uint_as_float((uint32_t)(h[KT - 1] >> 32)) : INFINITY;
     }
-    __device__ void insert(uint64_t c, int32_t pos)
+    __device__ void insert(uint64_t c)
     {
         if (c < h[KT - 1]) {
 #pragma unroll
@@ -57,8 +52,11 @@ struct TopK {
                 h[s] = (c < prev) ? prev : ((c < cur) ? c : cur);
             }
             h[0] = (c < h[0]) ? c : h[0];
-            if (KT == 1) best_pos = pos;
         }
+    }
+    __device__ void visit(float qx, float qy, float qz, uint32_t, const float4 &p)
+    {
+        insert(enc_cand(knn_key(p.x, p.y, p.z, qx, qy, qz), p.w));
     }
 };
 
@@ -67,37 +65,29 @@ struct Query {
 };
 
 // scan sorted points [s, e) minus the excluded run [xs, xe)
-template <int KT>
+template <class V>
 __device__ inline void scan_range(const float4 *__restrict__ pts, uint32_t s, uint32_t e, uint32_t xs,
-                                  uint32_t xe, const Query &q, TopK<KT> &top)
+                                  uint32_t xe, const Query &q, V &v)
 {
     uint32_t a0 = s, a1 = e, b0 = e, b1 = e;
     if (xs < xe && xs < e && xe > s) {   // overlap with the excluded run (nested or disjoint)
         a1 = xs > s ? xs : s;
         b0 = xe < e ? xe : e;
     }
-    for (uint32_t j = a0; j < a1; j++) {
-        float4 p = pts[j];
-        float key = knn_key(p.x, p.y, p.z, q.x, q.y, q.z);
-        top.insert(((uint64_t)__float_as_uint(key) << 32) | __float_as_uint(p.w), (int32_t)j);
-    }
-    for (uint32_t j = b0; j < b1; j++) {
-        float4 p = pts[j];
-        float key = knn_key(p.x, p.y, p.z, q.x, q.y, q.z);
-        top.insert(((uint64_t)__float_as_uint(key) << 32) | __float_as_uint(p.w), (int32_t)j);
-    }
+    for (uint32_t j = a0; j < a1; j++) v.visit(q.x, q.y, q.z, j, pts[j]);
+    for (uint32_t j = b0; j < b1; j++) v.visit(q.x, q.y, q.z, j, pts[j]);
 }
 
 // Depth-first search from the entries already on the stack.
 // stk: this lane's stack column (stride `stride` entries).
-template <int KT, int LEAF>
-__device__ inline void dfs(const GridView &g, const GridParams &P, const Query &q, TopK<KT> &top,
-                           float cap2, uint2 *stk, int stride, int sp, uint32_t xs, uint32_t xe)
+template <class V, int LEAF>
+__device__ inline void dfs(const GridView &g, const GridParams &P, const Query &q, V &v, uint2 *stk, int stride,
+                           int sp, uint32_t xs, uint32_t xe)
 {
     for (int visits = 0; sp > 0 && visits < kVisitBudget; visits++) {
         --sp;
         uint2 e = stk[sp * stride];
-        float b2 = fminf(top.bound2(), cap2);
+        float b2 = v.bound2();
         if (__uint_as_float(e.y) > b2) continue;
         uint32_t m = e.x;
         NodeHdr h = g.hdr[m];
@@ -105,7 +95,7 @@ __device__ inline void dfs(const GridView &g, const GridParams &P, const Query &
         int lvl = g.box[m].level;
         bool leaf = (h.count <= (uint32_t)LEAF) || lvl == P.lmin || sp + (int)h.nchild > kStack;
         if (leaf) {
-            scan_range<KT>(g.pts, h.start, h.start + h.count, xs, xe, q, top);
+            scan_range(g.pts, h.start, h.start + h.count, xs, xe, q, v);
             continue;
         }
         // push children: those not containing q first, so the one holding
@@ -125,36 +115,13 @@ __device__ inline void dfs(const GridView &g, const GridParams &P, const Query &
     }
 }
 
-// Full search.  `need` = number of points the seed cell must hold (k, or 1
-// for the nearest neighbour).  cap2 = inclusive acceptance radius^2 (+inf
-// for plain k-NN).  When `top` already holds a candidate (a warm start) the
-// seed phase is skipped.
-template <int KT, int LEAF>
-__device__ inline void search(const GridView &g, const GridParams &P, const Query &q, TopK<KT> &top,
-                              int need, float cap2, uint2 *stk, int stride)
+// Cover phase: every cell meeting the ball of the visitor's current radius.
+template <class V, int LEAF>
+__device__ inline void cover(const GridView &g, const GridParams &P, const Query &q, V &v, uint2 *stk, int stride,
+                             uint32_t xs, uint32_t xe)
 {
     const float inv = P.inv_h0;
-    uint32_t xs = 0, xe = 0;
-    bool have = (KT == 1) ? (top.best_pos >= 0) : top.full();
-    if (!have) {
-        // seed: smallest cell around q (level lmin and up) holding >= need points
-        uint32_t c0x = cell0(q.x, P.ox, inv), c0y = cell0(q.y, P.oy, inv), c0z = cell0(q.z, P.oz, inv);
-        int32_t seed = -1;
-        for (int l = P.lmin; l < kLevels; l++) {
-            int32_t m = find_cell(g, P.hash_mask, l, c0x >> l, c0y >> l, c0z >> l);
-            if (m >= 0 && g.hdr[m].count >= (uint32_t)need) {
-                seed = m;
-                break;
-            }
-        }
-        if (seed < 0) return;   // fewer than `need` points in the cloud
-        stk[0] = make_uint2((uint32_t)seed, 0u);
-        dfs<KT, LEAF>(g, P, q, top, cap2, stk, stride, 1, 0u, 0u);
-        NodeHdr hs = g.hdr[seed];
-        xs = hs.start;
-        xe = hs.start + hs.count;
-    }
-    float b2 = fminf(top.bound2(), cap2);
+    float b2 = v.bound2();
     if (!(b2 < INFINITY)) return;
     float R = sqrtf(b2) * (1.0f + 1.0f / (1 << 20)) + P.margin;
     // coarsest needed level: cell width >= 2R (with slack) so the ball box
@@ -181,10 +148,40 @@ __device__ inline void search(const GridView &g, const GridParams &P, const Quer
                     ++sp;
                 } else {
                     NodeHdr h = g.hdr[m];
-                    scan_range<KT>(g.pts, h.start, h.start + h.count, xs, xe, q, top);
+                    scan_range(g.pts, h.start, h.start + h.count, xs, xe, q, v);
                 }
             }
-    dfs<KT, LEAF>(g, P, q, top, cap2, stk, stride, sp, xs, xe);
+    dfs<V, LEAF>(g, P, q, v, stk, stride, sp, xs, xe);
+}
+
+// Full search.  `need` = number of points the seed cell must hold (k, or 1
+// for the nearest neighbour).  When the visitor already has a finite radius
+// (a warm start) the seed phase is skipped.
+template <class V, int LEAF>
+__device__ inline void search(const GridView &g, const GridParams &P, const Query &q, V &v, int need, uint2 *stk,
+                              int stride)
+{
+    const float inv = P.inv_h0;
+    uint32_t xs = 0, xe = 0;
+    if (!v.have()) {
+        // seed: smallest cell around q (level lmin and up) holding >= need points
+        uint32_t c0x = cell0(q.x, P.ox, inv), c0y = cell0(q.y, P.oy, inv), c0z = cell0(q.z, P.oz, inv);
+        int32_t seed = -1;
+        for (int l = P.lmin; l < kLevels; l++) {
+            int32_t m = find_cell(g, P.hash_mask, l, c0x >> l, c0y >> l, c0z >> l);
+            if (m >= 0 && g.hdr[m].count >= (uint32_t)need) {
+                seed = m;
+                break;
+            }
+        }
+        if (seed < 0) return;   // fewer than `need` points in the cloud
+        stk[0] = make_uint2((uint32_t)seed, 0u);
+        dfs<V, LEAF>(g, P, q, v, stk, stride, 1, 0u, 0u);
+        NodeHdr hs = g.hdr[seed];
+        xs = hs.start;
+        xe = hs.start + hs.count;
+    }
+    cover<V, LEAF>(g, P, q, v, stk, stride, xs, xe);
 }
 
 }  // namespace pcg

@@ -47,13 +47,15 @@ def _run_gpu(gpu, src, tgt, nrm, T0, d_max, iters, tol=0.0):
 def _parity(gpu, oracle_mod, src, tgt, nrm, T0, d_max, iters, tol=0.0, label=""):
     _say(f"icp {label} n_src={len(src)} n_tgt={len(tgt)} d_max={d_max} iters={iters}")
     Tg, sg = _run_gpu(gpu, src, tgt, nrm, T0, d_max, iters, tol)
-    ro = oracle_mod.icp(src, tgt, nrm, T0, d_max, iters, tol)
+    # the ABI takes d_max as float32; the oracle gets that same value
+    ro = oracle_mod.icp(src, tgt, nrm, T0, float(np.float32(d_max)), iters, tol)
     ea, et = pose_err(Tg, ro["T"])
     assert sg["status"] == ro["status"], (sg, ro["status"])
     assert sg["iterations_run"] == ro["iterations"]
     assert ea <= ROT_TOL and et <= TRANS_TOL, f"pose differs: {ea:.3g} rad, {et:.3g}"
-    # inlier counts may differ only for pairs within float32 rounding of d_max
-    assert abs(sg["inliers"] - ro["inliers"]) <= max(2, 1e-4 * len(src))
+    # correspondence decisions are certified in float64, so counts agree
+    # unless the two poses straddle a decision (rare)
+    assert abs(sg["inliers"] - ro["inliers"]) <= max(2, 1e-5 * len(src))
     return Tg, sg, ro
 
 
@@ -77,7 +79,8 @@ def test_icp_end_to_end_own_normals(gpu, oracle_mod):
     w = make_workload(0)
     n_gpu, _ = gpu.estimate_normals(_dev(w.target), w.k)
     T, sg = gpu.icp_point_to_plane(_dev(w.source), _dev(w.target), n_gpu, None, w.d_max, w.iters)
-    ro = oracle_mod.icp(w.source, w.target, _oracle_normals(oracle_mod, w.target, w.k), None, w.d_max, w.iters)
+    ro = oracle_mod.icp(w.source, w.target, _oracle_normals(oracle_mod, w.target, w.k), None,
+                        float(np.float32(w.d_max)), w.iters)
     ea, et = pose_err(T.cpu().numpy(), ro["T"])
     assert ea <= ROT_TOL and et <= TRANS_TOL
 
