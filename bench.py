@@ -1,0 +1,201 @@
+"""Benchmark of the point-to-plane ICP hot path on one MI355X.
+
+One step = one pair through the whole path: grid + PCA normals of the
+target (estimate_normals), then point-to-plane ICP (target grid, the fixed
+iteration loop, final statistics pass).  Inputs are resident in HBM before
+the timed region; the timed region is bracketed by device synchronisation.
+
+    python bench.py [--steps K] [--warmup W] [--workload room|street|sphere]
+
+Prints one JSON line.  value = pairs/s; the loop-only Mpt*iter/s, the
+roofline of the dominant kernel (the per-iteration correspondence +
+accumulation kernel, timed with HIP events on the library's stream) and a
+CPU-oracle baseline are reported alongside.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ICP pairs/s + Mpt·iter/s at ≤1e-5 rad pose error; learned-init vs plain"
+WORKLOADS = {"sphere": 0, "room": 1, "street": 2}
+HBM_PEAK_GBS = 8000.0
+# algorithmic bytes per source point per ICP iteration: source xyz (12),
+# matched target xyz + normal (24), cell lookup (4)
+ICP_BYTES_PER_POINT = 40
+PROFILES = os.path.join(ROOT, "profiles")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="room")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+class HipEvents:
+    """Timing events from the HIP runtime, recorded by the library on the
+    stream its kernels run on."""
+
+    def __init__(self, n):
+        self.rt = ctypes.CDLL("libamdhip64.so")
+        self.rt.hipEventCreate.argtypes = [ctypes.c_void_p]
+        self.rt.hipEventElapsedTime.argtypes = [ctypes.POINTER(ctypes.c_float), ctypes.c_void_p, ctypes.c_void_p]
+        self.rt.hipEventDestroy.argtypes = [ctypes.c_void_p]
+        self.n = n
+        self.beg = (ctypes.c_void_p * n)()
+        self.end = (ctypes.c_void_p * n)()
+        for i in range(n):
+            assert self.rt.hipEventCreate(ctypes.byref(self.beg, i * ctypes.sizeof(ctypes.c_void_p))) == 0
+            assert self.rt.hipEventCreate(ctypes.byref(self.end, i * ctypes.sizeof(ctypes.c_void_p))) == 0
+
+    def elapsed_ms(self, i):
+        ms = ctypes.c_float()
+        assert self.rt.hipEventElapsedTime(ctypes.byref(ms), self.beg[i], self.end[i]) == 0
+        return ms.value
+
+    def span_ms(self, i, j):
+        ms = ctypes.c_float()
+        assert self.rt.hipEventElapsedTime(ctypes.byref(ms), self.beg[i], self.end[j]) == 0
+        return ms.value
+
+
+def traffic_from_profiles(kernel_tag, workload):
+    """HBM bytes per launch from committed rocprofv3 counter summaries, if
+    they were taken for this kernel and workload (else None)."""
+    path = os.path.join(PROFILES, f"{kernel_tag}_{workload}_counters.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+        return d.get("hbm_bytes_per_launch")
+    except Exception:
+        return None
+
+
+def cpu_baseline(w, budget_s):
+    """The CPU oracle on the same pair: kd-tree normals + ICP (OpenMP over
+    points), repeated until about budget_s seconds have passed."""
+    import oracle
+    oracle.build(force=False)
+    d32 = float(np.float32(w.d_max))
+    t0 = time.perf_counter()
+    pairs, loop_s = 0, 0.0
+    while True:
+        nrm, _, _ = oracle.normals(w.target, w.k, (0.0, 0.0, 0.0), method="kdtree")
+        t1 = time.perf_counter()
+        oracle.icp(w.source, w.target, nrm.astype(np.float32), None, d32, w.iters)
+        loop_s += time.perf_counter() - t1
+        pairs += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    el = time.perf_counter() - t0
+    return {"value": pairs / el, "unit": "pairs/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"{pairs} full pair(s) of the same workload (normals + ICP incl. kd-tree builds), "
+                      f"{el:.1f} s wall",
+            "mpt_iter_per_s": w.n * w.iters * pairs / loop_s / 1e6}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path is not sharded across GPUs",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from gen import make_workload
+    from paper_1807_00399_amd import pcgpu
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    w = make_workload(WORKLOADS[args.workload])
+    src = torch.from_numpy(w.source).to(dev)
+    tgt = torch.from_numpy(w.target).to(dev)
+    stream = torch.cuda.current_stream()
+    T = torch.empty((4, 4), dtype=torch.float64, device=dev)
+    stats = torch.zeros(24, dtype=torch.uint8, device=dev)
+    ws_n = torch.empty(pcgpu.lib.estimate_normals_workspace_size(w.n, w.k), dtype=torch.uint8, device=dev)
+    ws_i = pcgpu.workspace_for_icp(w.n, w.n, w.iters, dev)
+
+    def step():
+        nrm, _ = pcgpu.estimate_normals(tgt, w.k, curvature=False, workspace=ws_n)
+        pcgpu.icp_point_to_plane(src, tgt, nrm, None, w.d_max, w.iters, workspace=ws_i, out_T=T,
+                                 out_stats=stats, read_stats=False)
+        return nrm
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+
+    # timed region: K whole steps
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ms_per_step = 1e3 * el / args.steps
+    st = pcgpu.decode_stats(stats)
+
+    # dominant kernel: per-iteration correspondence + accumulation, events
+    # recorded by the library around each launch on its stream
+    ev = HipEvents(w.iters)
+    pcgpu.lib.pc_set_kernel_timer(ev.beg, ev.end, w.iters)
+    kern_ms, loop_ms = [], []
+    for _ in range(max(3, min(args.steps, 10))):
+        step()
+        torch.cuda.synchronize()
+        cnt = pcgpu.lib.pc_kernel_timer_count()
+        kern_ms += [ev.elapsed_ms(i) for i in range(cnt)]
+        loop_ms.append(ev.span_ms(0, cnt - 1))
+    pcgpu.lib.pc_set_kernel_timer(None, None, 0)
+    avg_kernel_s = float(np.mean(kern_ms)) * 1e-3
+    loop_s = float(np.median(loop_ms)) * 1e-3
+    algo_bytes = ICP_BYTES_PER_POINT * w.n
+    achieved = algo_bytes / avg_kernel_s / 1e9
+    traffic = traffic_from_profiles("icp_accum", args.workload)
+
+    out = {
+        "metric": METRIC,
+        "value": args.steps / el,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{w.name}: one pair, {w.n} points per cloud, k={w.k} normals, "
+                               f"d_max {w.d_max}, {w.iters} iterations",
+                   "points_per_cloud": w.n, "k": w.k, "d_max": w.d_max, "iters": w.iters},
+        "mpt_iter_per_s": w.n * w.iters / loop_s / 1e6,
+        "loop_ms": loop_s * 1e3,
+        "icp_status": st,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "kernel": "k_icp_accum", "avg_kernel_us": avg_kernel_s * 1e6,
+                     "algorithmic_bytes_per_launch": algo_bytes},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

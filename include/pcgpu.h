@@ -162,6 +162,14 @@ pc_status pc_copy_probe(void *dst, const void *src, size_t n_bytes, hipStream_t 
 const double *icp_history(void *workspace, size_t workspace_bytes,
                           int64_t n_src, int64_t n_tgt, int max_iters);
 
+/* Registers caller-owned HIP events (created with timing enabled) that
+   icp_point_to_plane records on its stream immediately before and after the
+   correspondence/accumulation kernel of iteration i, for i < capacity.  Pass
+   capacity 0 to stop.  pc_kernel_timer_count() returns how many pairs the
+   last call recorded.  For measurement only; not thread-safe. */
+pc_status pc_set_kernel_timer(hipEvent_t *begin, hipEvent_t *end, int capacity);
+int pc_kernel_timer_count(void);
+
 #ifdef __cplusplus
 }
 #endif

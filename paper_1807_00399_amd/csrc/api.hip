@@ -139,4 +139,13 @@ pc_status pc_copy_probe(void *dst, const void *src, size_t n_bytes, hipStream_t 
     return hipGetLastError() == hipSuccess ? PC_OK : PC_EDEVICE;
 }
 
+pc_status pc_set_kernel_timer(hipEvent_t *begin, hipEvent_t *end, int capacity)
+{
+    if (capacity < 0 || (capacity > 0 && (!begin || !end))) return PC_EINVAL;
+    icp_set_timer(begin, end, capacity);
+    return PC_OK;
+}
+
+int pc_kernel_timer_count(void) { return icp_timer_count(); }
+
 }  // extern "C"

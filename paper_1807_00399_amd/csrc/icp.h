@@ -23,6 +23,9 @@ hipError_t icp_run(IcpStore &s, const float *src, int64_t ns, const float *tgt, 
                    const double *init_T, float dmax, int max_iters, double conv_tol, double *out_T,
                    pc_icp_stats *out_stats, hipStream_t st);
 
+void icp_set_timer(hipEvent_t *b, hipEvent_t *e, int cap);
+int icp_timer_count();
+
 hipError_t knn_run(const GridStore &g, const float *qry, int64_t nq, int k, int32_t *oi, float *od, hipStream_t s);
 hipError_t normals_run(const GridStore &g, const float *xyz, int k, const float *vp, float *on, float *oc,
                        hipStream_t s);

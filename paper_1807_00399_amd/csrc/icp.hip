@@ -459,6 +459,20 @@ __global__ void k_icp_empty(const double *__restrict__ init_T, double *out_T, pc
 // ---------------------------------------------------------------------------
 // host side
 // ---------------------------------------------------------------------------
+// optional event timer around the iteration kernels (diagnostics)
+static hipEvent_t *g_tbeg = nullptr, *g_tend = nullptr;
+static int g_tcap = 0, g_tcount = 0;
+
+void icp_set_timer(hipEvent_t *b, hipEvent_t *e, int cap)
+{
+    g_tbeg = b;
+    g_tend = e;
+    g_tcap = (b && e && cap > 0) ? cap : 0;
+    g_tcount = 0;
+}
+
+int icp_timer_count() { return g_tcount; }
+
 static int icp_ppt(int64_t ns)
 {
     int64_t per = (ns + (int64_t)kIcpThreads * 1024 - 1) / ((int64_t)kIcpThreads * 1024);
@@ -515,8 +529,15 @@ hipError_t icp_run(IcpStore &s, const float *src, int64_t ns, const float *tgt, 
     e = grid_gather3(s.grid, tgt_n, s.nrm, st);
     if (e != hipSuccess) return e;
     k_fill_i32<<<(int)((ns + 255) / 256 < 2048 ? (ns + 255) / 256 : 2048), 256, 0, st>>>(s.prev, ns, -1);
+    g_tcount = 0;
     for (int it = 0; it < max_iters; it++) {
+        bool timed = it < g_tcap;
+        if (timed) hipEventRecord(g_tbeg[it], st);
         accum(s, src, ns, dmax, 0, st);
+        if (timed) {
+            hipEventRecord(g_tend[it], st);
+            g_tcount = it + 1;
+        }
         k_icp_finalize<<<1, kFinThreads, 0, st>>>(s.part, s.pcnt, s.nblk, s.st, 0, conv_tol, out_T, out_stats,
                                                   s.hist);
     }

@@ -25,7 +25,7 @@ EXPORTS = (
     "knn_search_workspace_size", "knn_search",
     "estimate_normals_workspace_size", "estimate_normals",
     "icp_point_to_plane_workspace_size", "icp_point_to_plane",
-    "pc_copy_probe", "icp_history",
+    "pc_copy_probe", "icp_history", "pc_set_kernel_timer", "pc_kernel_timer_count",
 )
 
 
@@ -59,6 +59,10 @@ def _load() -> ctypes.CDLL:
     lib.pc_copy_probe.restype = ctypes.c_int
     lib.icp_history.argtypes = [vp, sz, i64, i64, i32]
     lib.icp_history.restype = ctypes.c_void_p
+    lib.pc_set_kernel_timer.argtypes = [vp, vp, i32]
+    lib.pc_set_kernel_timer.restype = ctypes.c_int
+    lib.pc_kernel_timer_count.argtypes = []
+    lib.pc_kernel_timer_count.restype = ctypes.c_int
     return lib
 
 
