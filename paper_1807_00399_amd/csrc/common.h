@@ -36,14 +36,26 @@ struct GridParams {        // written on the device by the grid builder
 };
 
 // Node header: start/count of its run in the sorted arrays, first child
-// (global node index, level L-1) and number of children.
+// (global node index, level L-1) and meta = number of children | level << 8.
 struct NodeHdr {
-    uint32_t start, count, first_child, nchild;
+    uint32_t start, count, first_child, meta;
+};
+__host__ __device__ inline uint32_t node_nchild(const NodeHdr &h) { return h.meta & 0xffu; }
+__host__ __device__ inline int node_level(const NodeHdr &h) { return (int)(h.meta >> 8); }
+
+// One 32-byte node record: header plus the tight box of the node's points in
+// level-0 grid cells (inclusive), x | y << 16 packed: bx = lo.x,lo.y;
+// by = lo.z,hi.x; bz = hi.y,hi.z.  One load brings everything a traversal
+// step needs.
+struct Node {
+    NodeHdr h;
+    uint32_t bx, by, bz, pad;
 };
 
-// Node box: integer cell coordinates at its own level and the level.
-struct NodeBox {
-    uint16_t cx, cy, cz, level;
+// Hash slot: (level << 48 | cell key) and node index in one 16-byte load.
+struct HSlot {
+    uint64_t key;
+    uint32_t val, pad;
 };
 
 // Views of the workspace the grid lives in.
@@ -51,10 +63,8 @@ struct GridView {
     GridParams *params;
     const float4 *pts;         // sorted points; .w = original index (bit pattern)
     const uint64_t *keys;      // sorted level-0 Morton keys
-    const NodeHdr *hdr;
-    const NodeBox *box;
-    const uint64_t *hkeys;     // hash: (level << 48) | cell key
-    const uint32_t *hvals;     // hash: node index
+    const Node *node;
+    const HSlot *hash;
 };
 
 // ---------------------------------------------------------------------------
@@ -110,9 +120,9 @@ __device__ inline int32_t find_cell(const GridView &g, uint32_t mask, int level,
     // the table is at most half full, so an empty slot ends every probe;
     // the bound only guards against a corrupted table
     for (uint32_t it = 0; it <= mask; it++) {
-        uint64_t k = g.hkeys[s];
-        if (k == key) return (int32_t)g.hvals[s];
-        if (k == kEmptyKey) return -1;
+        HSlot e = g.hash[s];
+        if (e.key == key) return (int32_t)e.val;
+        if (e.key == kEmptyKey) return -1;
         s = (s + 1) & mask;
     }
     return -1;
@@ -138,9 +148,33 @@ __device__ inline float ord2f(uint32_t u)
 
 __device__ inline uint32_t lane_id() { return __lane_id(); }
 
-// Squared distance from q to the closed box of a cell, computed in float32
-// and shrunk so that it never exceeds the true distance of any point the
-// cell holds (points are binned with the same rounding, see cell_lo).
+// Squared distance from q to a node's box (level-0 cells lo..hi per axis),
+// computed in float32 and shrunk by the binning margin and a relative factor,
+// so it never exceeds the float32 key of any point the node holds.
+__device__ inline float node_mindist2(const GridParams &P, const Node &nd, float qx, float qy, float qz)
+{
+    float h = P.h0;
+    float lx = P.ox + (float)(nd.bx & 0xffffu) * h, hx = P.ox + (float)((nd.by >> 16) + 1u) * h;
+    float ly = P.oy + (float)(nd.bx >> 16) * h, hy = P.oy + (float)((nd.bz & 0xffffu) + 1u) * h;
+    float lz = P.oz + (float)(nd.by & 0xffffu) * h, hz = P.oz + (float)((nd.bz >> 16) + 1u) * h;
+    float dx = fmaxf(fmaxf(lx - qx, qx - hx) - P.margin, 0.f);
+    float dy = fmaxf(fmaxf(ly - qy, qy - hy) - P.margin, 0.f);
+    float dz = fmaxf(fmaxf(lz - qz, qz - hz) - P.margin, 0.f);
+    return (dx * dx + dy * dy + dz * dz) * (1.0f - 1e-5f);
+}
+
+// Blocks are dispatched round-robin over the 8 XCDs, each with its own L2:
+// map dispatch order so every XCD works on a contiguous range of queries,
+// whose neighbourhoods overlap in its cache.  A bijection on [0, nblk).
+__device__ inline int xcd_block(int b, int nblk)
+{
+    int full = (nblk / 8) * 8;
+    return b < full ? (b % 8) * (nblk / 8) + b / 8 : b;
+}
+
+// Squared distance from q to the closed box of a grid cell, computed in
+// float32 and shrunk so that it never exceeds the true distance of any point
+// the cell holds (points are binned with the same rounding, see cell0).
 __device__ inline float cell_mindist2(const GridParams &P, float qx, float qy, float qz,
                                       uint32_t cx, uint32_t cy, uint32_t cz, int level)
 {
@@ -191,10 +225,8 @@ struct GridStore {
     uint64_t *keys, *keys_alt;
     uint32_t *idx, *idx_alt;
     float4 *pts;
-    NodeHdr *hdr;
-    NodeBox *box;
-    uint64_t *hkeys;
-    uint32_t *hvals;
+    Node *node;
+    HSlot *hash;
     uint32_t *slev;           // per sorted point: top level at which it starts a cell (or 0xff)
     uint32_t *radix_hist;     // radix histograms / scan space
     int32_t *level_block;     // per block, per level: counts then offsets
@@ -205,7 +237,7 @@ struct GridStore {
     int nblk_sort, nblk_lvl;
     GridView view() const
     {
-        return GridView{params, pts, keys, hdr, box, hkeys, hvals};
+        return GridView{params, pts, keys, node, hash};
     }
 };
 

@@ -46,8 +46,9 @@ __global__ void k_bbox_init(uint32_t *bb)
     else if (t < 6) bb[t] = 0u;          // max (ordered)
 }
 
-__global__ void k_bbox(const float *__restrict__ xyz, int64_t n, uint32_t *bb)
+__global__ void __launch_bounds__(256) k_bbox(const float *__restrict__ xyz, int64_t n, uint32_t *bb)
 {
+    __shared__ float red[4][6];
     float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
          i += (int64_t)gridDim.x * blockDim.x) {
@@ -62,12 +63,22 @@ __global__ void k_bbox(const float *__restrict__ xyz, int64_t n, uint32_t *bb)
             mn[a] = fminf(mn[a], __shfl_xor(mn[a], off));
             mx[a] = fmaxf(mx[a], __shfl_xor(mx[a], off));
         }
-    if (__lane_id() == 0) {
+    int w = threadIdx.x >> 6;
+    if (__lane_id() == 0)
         for (int a = 0; a < 3; a++) {
-            if (mn[a] <= mx[a]) {
-                atomicMin(&bb[a], f2ord(mn[a]));
-                atomicMax(&bb[3 + a], f2ord(mx[a]));
-            }
+            red[w][a] = mn[a];
+            red[w][3 + a] = mx[a];
+        }
+    __syncthreads();
+    // one set of atomics per block
+    if (threadIdx.x < 6) {
+        int a = threadIdx.x;
+        float v = red[0][a];
+        for (int x = 1; x < 4; x++) v = a < 3 ? fminf(v, red[x][a]) : fmaxf(v, red[x][a]);
+        bool finite = a < 3 ? v < INFINITY : v > -INFINITY;
+        if (finite) {
+            if (a < 3) atomicMin(&bb[a], f2ord(v));
+            else atomicMax(&bb[a], f2ord(v));
         }
     }
 }
@@ -323,7 +334,7 @@ __global__ void __launch_bounds__(1024) k_level_scan(int32_t *__restrict__ lb, i
 __global__ void __launch_bounds__(kLvlThreads) k_level_scatter(const uint32_t *__restrict__ slev, int64_t n,
                                                              const GridParams *__restrict__ P,
                                                              const int32_t *__restrict__ lb,
-                                                             NodeHdr *__restrict__ hdr, NodeBox *__restrict__ box)
+                                                             Node *__restrict__ nodes)
 {
     constexpr int W = kLvlThreads / 64;
     __shared__ int32_t running[kLevels];
@@ -358,12 +369,8 @@ __global__ void __launch_bounds__(kLvlThreads) k_level_scatter(const uint32_t *_
                 h.start = (uint32_t)i;
                 h.count = 0;
                 h.first_child = (l > lmin) ? (uint32_t)prev : 0xffffffffu;
-                h.nchild = 0;
-                hdr[node] = h;
-                NodeBox bx;
-                bx.cx = bx.cy = bx.cz = 0;
-                bx.level = (uint16_t)l;
-                box[node] = bx;
+                h.meta = (uint32_t)l << 8;
+                nodes[node].h = h;
             }
             prev = node;
         }
@@ -377,52 +384,78 @@ __global__ void __launch_bounds__(kLvlThreads) k_level_scatter(const uint32_t *_
     }
 }
 
-__global__ void k_hash_clear(const GridParams *__restrict__ P, uint64_t *__restrict__ hk)
+__global__ void k_hash_clear(const GridParams *__restrict__ P, HSlot *__restrict__ hs)
 {
     uint32_t cap = P->hash_mask + 1;
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cap; i += gridDim.x * blockDim.x)
-        hk[i] = kEmptyKey;
+        hs[i].key = kEmptyKey;
 }
 
-// node counts, child counts, cell coordinates, hash insertion
+// node counts, child counts, hash insertion
 __global__ void k_nodes_finish(const GridParams *__restrict__ P, const uint64_t *__restrict__ keys,
-                               NodeHdr *__restrict__ hdr, NodeBox *__restrict__ box,
-                               uint64_t *__restrict__ hk, uint32_t *__restrict__ hv)
+                               Node *__restrict__ nodes, HSlot *__restrict__ hs)
 {
     int32_t total = P->n_nodes, n = P->n, lmin = P->lmin;
     uint32_t mask = P->hash_mask;
     for (int32_t m = blockIdx.x * blockDim.x + threadIdx.x; m < total; m += gridDim.x * blockDim.x) {
-        int l = box[m].level;
+        // start, first_child and the level were written by the scatter pass
+        // and are only read here; each thread writes its own node's counts
+        uint32_t start = nodes[m].h.start;
+        uint32_t meta = nodes[m].h.meta;
+        int l = (int)(meta >> 8);
         int32_t lend = P->level_off[l] + P->level_count[l];
-        // start and first_child were written by the scatter pass and are only
-        // read here; each thread writes the count fields of its own node
-        uint32_t start = hdr[m].start;
-        uint32_t next_start = (m + 1 < lend) ? hdr[m + 1].start : (uint32_t)n;
-        hdr[m].count = next_start - start;
+        uint32_t next_start = (m + 1 < lend) ? nodes[m + 1].h.start : (uint32_t)n;
+        nodes[m].h.count = next_start - start;
         if (l > lmin) {
-            uint32_t fc = hdr[m].first_child;
-            uint32_t next_fc = (m + 1 < lend) ? hdr[m + 1].first_child
+            uint32_t fc = nodes[m].h.first_child;
+            uint32_t next_fc = (m + 1 < lend) ? nodes[m + 1].h.first_child
                                               : (uint32_t)(P->level_off[l - 1] + P->level_count[l - 1]);
-            hdr[m].nchild = next_fc - fc;
+            nodes[m].h.meta = meta | (next_fc - fc);
         }
-        uint64_t ck = keys[start] >> (3 * l);
-        NodeBox bx;
-        bx.cx = (uint16_t)compact3(ck);
-        bx.cy = (uint16_t)compact3(ck >> 1);
-        bx.cz = (uint16_t)compact3(ck >> 2);
-        bx.level = (uint16_t)l;
-        box[m] = bx;
-        uint64_t key = hash_key(l, ck);
+        uint64_t key = hash_key(l, keys[start] >> (3 * l));
         uint32_t s = hash_slot(key, mask);
         for (uint32_t it = 0; it <= mask; it++) {
-            unsigned long long prev =
-                atomicCAS((unsigned long long *)&hk[s], (unsigned long long)kEmptyKey, (unsigned long long)key);
+            unsigned long long prev = atomicCAS((unsigned long long *)&hs[s].key, (unsigned long long)kEmptyKey,
+                                                (unsigned long long)key);
             if (prev == kEmptyKey) {
-                hv[s] = (uint32_t)m;
+                hs[s].val = (uint32_t)m;
                 break;
             }
             s = (s + 1) & mask;
         }
+    }
+}
+
+// tight boxes of the level-l nodes in level-0 cells: from their points'
+// cells at the finest level, from their children's boxes above it
+__global__ void k_node_boxes(const GridParams *__restrict__ P, int l, const uint64_t *__restrict__ keys,
+                             Node *__restrict__ nodes)
+{
+    int lmin = P->lmin;
+    if (l < lmin) return;
+    int32_t off = P->level_off[l], end = off + P->level_count[l];
+    for (int32_t m = off + blockIdx.x * blockDim.x + threadIdx.x; m < end; m += gridDim.x * blockDim.x) {
+        NodeHdr h = nodes[m].h;
+        uint32_t lx = 0xffffu, ly = 0xffffu, lz = 0xffffu, hx = 0, hy = 0, hz = 0;
+        if (l == lmin) {
+            for (uint32_t j = h.start; j < h.start + h.count; j++) {
+                uint64_t k = keys[j];
+                uint32_t x = compact3(k), y = compact3(k >> 1), z = compact3(k >> 2);
+                lx = min(lx, x); ly = min(ly, y); lz = min(lz, z);
+                hx = max(hx, x); hy = max(hy, y); hz = max(hz, z);
+            }
+        } else {
+            uint32_t nc = node_nchild(h);
+            for (uint32_t c = 0; c < nc; c++) {
+                const Node &ch = nodes[h.first_child + c];
+                lx = min(lx, ch.bx & 0xffffu); ly = min(ly, ch.bx >> 16); lz = min(lz, ch.by & 0xffffu);
+                hx = max(hx, ch.by >> 16); hy = max(hy, ch.bz & 0xffffu); hz = max(hz, ch.bz >> 16);
+            }
+        }
+        nodes[m].bx = lx | (ly << 16);
+        nodes[m].by = lz | (hx << 16);
+        nodes[m].bz = hy | (hz << 16);
+        nodes[m].pad = 0;
     }
 }
 
@@ -469,10 +502,8 @@ void grid_carve(Carver &c, int64_t n, GridStore &g)
     g.slev = c.take<uint32_t>(nn);
     g.radix_hist = c.take<uint32_t>((size_t)g.nblk_sort * kRadix);
     g.level_block = c.take<int32_t>((size_t)g.nblk_lvl * kLevels);
-    g.hdr = c.take<NodeHdr>(g.max_nodes);
-    g.box = c.take<NodeBox>(g.max_nodes);
-    g.hkeys = c.take<uint64_t>(g.hash_cap_max);
-    g.hvals = c.take<uint32_t>(g.hash_cap_max);
+    g.node = c.take<Node>(g.max_nodes);
+    g.hash = c.take<HSlot>(g.hash_cap_max);
 }
 
 size_t grid_bytes(int64_t n)
@@ -489,7 +520,7 @@ hipError_t grid_build(GridStore &g, const float *xyz, hipStream_t s)
     const int T = 256;
     k_bbox_init<<<1, 64, 0, s>>>(g.bbox);
     int bb_blocks = blocks_for(n, T);
-    if (bb_blocks > 1024) bb_blocks = 1024;
+    if (bb_blocks > 256) bb_blocks = 256;
     if (bb_blocks < 1) bb_blocks = 1;
     k_bbox<<<bb_blocks, T, 0, s>>>(xyz, n, g.bbox);
     k_params<<<1, 1, 0, s>>>(g.bbox, g.params, n);
@@ -515,13 +546,16 @@ hipError_t grid_build(GridStore &g, const float *xyz, hipStream_t s)
     if (n > 0) {
         k_level_count<<<g.nblk_lvl, kLvlThreads, 0, s>>>(g.slev, n, g.params, g.level_block);
         k_level_scan<<<1, 1024, 0, s>>>(g.level_block, g.nblk_lvl);
-        k_level_scatter<<<g.nblk_lvl, kLvlThreads, 0, s>>>(g.slev, n, g.params, g.level_block, g.hdr, g.box);
+        k_level_scatter<<<g.nblk_lvl, kLvlThreads, 0, s>>>(g.slev, n, g.params, g.level_block, g.node);
         int hb = blocks_for(g.hash_cap_max, T);
         if (hb > 4096) hb = 4096;
-        k_hash_clear<<<hb, T, 0, s>>>(g.params, g.hkeys);
+        k_hash_clear<<<hb, T, 0, s>>>(g.params, g.hash);
         int nb = blocks_for(g.max_nodes, T);
         if (nb > 4096) nb = 4096;
-        k_nodes_finish<<<nb, T, 0, s>>>(g.params, g.keys, g.hdr, g.box, g.hkeys, g.hvals);
+        k_nodes_finish<<<nb, T, 0, s>>>(g.params, g.keys, g.node, g.hash);
+        int bxb = blocks_for(n, T);
+        if (bxb > 2048) bxb = 2048;
+        for (int l = 0; l < kLevels; l++) k_node_boxes<<<bxb, T, 0, s>>>(g.params, l, g.keys, g.node);
     }
     return hipGetLastError();
 }

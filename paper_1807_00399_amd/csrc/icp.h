@@ -14,6 +14,10 @@ struct IcpStore {
     IcpState *st;       // pose and loop state
     float2 *part;       // per block: compensated partial sums
     uint32_t *pcnt;     // per block: inlier counts
+    float2 *gpart;      // per group of blocks: merged partial sums
+    uint32_t *gcnt;     // per group of blocks: inlier counts
+    uint32_t *gctr;     // per group of blocks: arrival counter
+    int ngrp;
     double *hist;       // per iteration: increment, inliers, sum r^2
     int nblk, ppt;
 };

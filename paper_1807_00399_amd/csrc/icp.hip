@@ -26,6 +26,7 @@ namespace pcg {
 constexpr int kAcc = 28;            // 21 (A) + 6 (b) + 1 (sum r^2)
 constexpr int kIcpThreads = 256;
 constexpr int kFinThreads = 1024;
+constexpr int kGroup = 64;          // blocks merged by a group's last block
 
 struct IcpState {
     double T[16];          // current pose, float64 row-major
@@ -183,17 +184,36 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v)
         p[i] = v;
 }
 
-// correspondences + linearised system, partial sums per block
+__device__ inline void store_f2(float2 *p, CSum v)
+{
+    uint64_t bits = ((uint64_t)__float_as_uint(v.lo) << 32) | __float_as_uint(v.hi);
+    __hip_atomic_store((uint64_t *)p, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline CSum load_f2(const float2 *p)
+{
+    uint64_t bits = __hip_atomic_load((const uint64_t *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return CSum{__uint_as_float((uint32_t)bits), __uint_as_float((uint32_t)(bits >> 32))};
+}
+
+// Correspondences + linearised system.  One source point per lane: the
+// search is bound by memory latency, so parallelism comes from many lanes.
+// Each block writes its compensated partial sums; the last block of every
+// group of kGroup blocks to finish merges the group's partials in block
+// order, so the result does not depend on scheduling.
 template <int PPT>
 __global__ void __launch_bounds__(kIcpThreads) k_icp_accum(GridView g, const float *__restrict__ src, int64_t ns,
                                                          const float4 *__restrict__ nrm,
                                                          int32_t *__restrict__ prev, const IcpState *__restrict__ st,
                                                          float dmax, int final_pass, float2 *__restrict__ part,
-                                                         uint32_t *__restrict__ pcnt)
+                                                         uint32_t *__restrict__ pcnt, float2 *__restrict__ gpart,
+                                                         uint32_t *__restrict__ gcnt, uint32_t *__restrict__ gctr,
+                                                         int nblk)
 {
-    __shared__ uint2 stk[kStack * kIcpThreads];
+    __shared__ uint32_t stk[kStack * kIcpThreads];
     __shared__ float2 wsum[kIcpThreads / 64][kAcc];
     __shared__ uint32_t wcnt[kIcpThreads / 64];
+    __shared__ int s_last;
     if (!final_pass && st->stop) return;   // uniform across the grid
     const GridParams P = *g.params;
     float Rh[12], Rl[12];
@@ -204,14 +224,14 @@ __global__ void __launch_bounds__(kIcpThreads) k_icp_accum(GridView g, const flo
     }
     const double dmax64 = (double)dmax;
     const float dmax2 = dmax * dmax;
-    CSum acc[kAcc];
+    const int lblk = xcd_block(blockIdx.x, nblk);
+    const int64_t base = (int64_t)lblk * (kIcpThreads * PPT) + threadIdx.x;
+    int32_t jsel[PPT];
 #pragma unroll
-    for (int a = 0; a < kAcc; a++) acc[a] = CSum{0.f, 0.f};
-    uint32_t cnt = 0;
-    int64_t base = (int64_t)blockIdx.x * (kIcpThreads * PPT) + threadIdx.x;
     for (int r = 0; r < PPT; r++) {
+        jsel[r] = -1;
         int64_t i = base + (int64_t)r * kIcpThreads;
-        if (i >= ns) break;
+        if (i >= ns) continue;
         float px = src[3 * i], py = src[3 * i + 1], pz = src[3 * i + 2];
         float hx, lx, hy, ly, hz, lz;
         df_row(Rh, Rl, px, py, pz, hx, lx);
@@ -253,18 +273,34 @@ __global__ void __launch_bounds__(kIcpThreads) k_icp_accum(GridView g, const flo
                 j = w.best_pos;
             }
         }
+        jsel[r] = j;
+    }
+    CSum acc[kAcc];
+#pragma unroll
+    for (int a = 0; a < kAcc; a++) acc[a] = CSum{0.f, 0.f};
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int r = 0; r < PPT; r++) {
+        int32_t j = jsel[r];
         if (j < 0) continue;
+        int64_t i = base + (int64_t)r * kIcpThreads;
         float4 n = nrm[j];
         if (n.x == 0.f && n.y == 0.f && n.z == 0.f) continue;
         float4 t = g.pts[j];
+        float px = src[3 * i], py = src[3 * i + 1], pz = src[3 * i + 2];
+        float hx, lx, hy, ly, hz, lz;
+        df_row(Rh, Rl, px, py, pz, hx, lx);
+        df_row(Rh + 4, Rl + 4, px, py, pz, hy, ly);
+        df_row(Rh + 8, Rl + 8, px, py, pz, hz, lz);
+        float qx = hx + lx, qy = hy + ly, qz = hz + lz;
         // residual vector from the double-float p': (hi - q) is exact for
         // nearby points, so it keeps the full accuracy of hi + lo
         float dx = (hx - t.x) + lx, dy = (hy - t.y) + ly, dz = (hz - t.z) + lz;
         float res = __fmaf_rn(dz, n.z, __fmaf_rn(dy, n.y, dx * n.x));
         float J[6];
-        J[0] = __fmaf_rn(q.y, n.z, -q.z * n.y);
-        J[1] = __fmaf_rn(q.z, n.x, -q.x * n.z);
-        J[2] = __fmaf_rn(q.x, n.y, -q.y * n.x);
+        J[0] = __fmaf_rn(qy, n.z, -qz * n.y);
+        J[1] = __fmaf_rn(qz, n.x, -qx * n.z);
+        J[2] = __fmaf_rn(qx, n.y, -qy * n.x);
         J[3] = n.x;
         J[4] = n.y;
         J[5] = n.z;
@@ -300,11 +336,34 @@ __global__ void __launch_bounds__(kIcpThreads) k_icp_accum(GridView g, const flo
     if (threadIdx.x < kAcc) {
         CSum s{0.f, 0.f};
         for (int x = 0; x < kIcpThreads / 64; x++) s = csum_merge(s, CSum{wsum[x][threadIdx.x].x, wsum[x][threadIdx.x].y});
-        part[(int64_t)blockIdx.x * kAcc + threadIdx.x] = make_float2(s.hi, s.lo);
+        store_f2(&part[(int64_t)lblk * kAcc + threadIdx.x], s);
     } else if (threadIdx.x == kAcc) {
         uint32_t c = 0;
         for (int x = 0; x < kIcpThreads / 64; x++) c += wcnt[x];
-        pcnt[blockIdx.x] = c;
+        __hip_atomic_store(&pcnt[lblk], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __threadfence();
+    __syncthreads();
+    const int grp = lblk / kGroup, b0 = grp * kGroup;
+    const int gsz = (nblk - b0) < kGroup ? (nblk - b0) : kGroup;
+    if (threadIdx.x == 0) {
+        uint32_t old = __hip_atomic_fetch_add(&gctr[grp], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        s_last = (old == (uint32_t)gsz - 1);
+    }
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    if (threadIdx.x < kAcc) {
+        CSum s{0.f, 0.f};
+        for (int b = 0; b < gsz; b++) s = csum_merge(s, load_f2(&part[(int64_t)(b0 + b) * kAcc + threadIdx.x]));
+        gpart[(int64_t)grp * kAcc + threadIdx.x] = make_float2(s.hi, s.lo);
+    } else if (threadIdx.x == kAcc) {
+        uint32_t c = 0;
+        for (int b = 0; b < gsz; b++)
+            c += __hip_atomic_load(&pcnt[b0 + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        gcnt[grp] = c;
+    } else if (threadIdx.x == kAcc + 1) {
+        __hip_atomic_store(&gctr[grp], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);   // ready for the next pass
     }
 }
 
@@ -475,6 +534,12 @@ int icp_timer_count() { return g_tcount; }
 
 static int icp_ppt(int64_t ns)
 {
+    (void)ns;
+    return 1;   // one point per lane: the search is latency bound
+}
+
+[[maybe_unused]] static int icp_ppt_wide(int64_t ns)
+{
     int64_t per = (ns + (int64_t)kIcpThreads * 1024 - 1) / ((int64_t)kIcpThreads * 1024);
     if (per <= 1) return 1;
     if (per <= 2) return 2;
@@ -494,6 +559,10 @@ void icp_carve(Carver &c, int64_t ns, int64_t nt, int max_iters, IcpStore &s)
     s.nblk = (int)((ns1 + (int64_t)kIcpThreads * s.ppt - 1) / ((int64_t)kIcpThreads * s.ppt));
     s.part = c.take<float2>((size_t)s.nblk * kAcc);
     s.pcnt = c.take<uint32_t>((size_t)s.nblk);
+    s.ngrp = (s.nblk + kGroup - 1) / kGroup;
+    s.gpart = c.take<float2>((size_t)s.ngrp * kAcc);
+    s.gcnt = c.take<uint32_t>((size_t)s.ngrp);
+    s.gctr = c.take<uint32_t>((size_t)s.ngrp);
     s.hist = c.take<double>((size_t)8 * (max_iters > 0 ? max_iters : 1));
 }
 
@@ -501,7 +570,7 @@ template <int PPT>
 static void launch_accum(IcpStore &s, const float *src, int64_t ns, float dmax, int final_pass, hipStream_t st)
 {
     k_icp_accum<PPT><<<s.nblk, kIcpThreads, 0, st>>>(s.grid.view(), src, ns, s.nrm, s.prev, s.st, dmax,
-                                                     final_pass, s.part, s.pcnt);
+                                                     final_pass, s.part, s.pcnt, s.gpart, s.gcnt, s.gctr, s.nblk);
 }
 
 static void accum(IcpStore &s, const float *src, int64_t ns, float dmax, int final_pass, hipStream_t st)
@@ -529,20 +598,21 @@ hipError_t icp_run(IcpStore &s, const float *src, int64_t ns, const float *tgt, 
     e = grid_gather3(s.grid, tgt_n, s.nrm, st);
     if (e != hipSuccess) return e;
     k_fill_i32<<<(int)((ns + 255) / 256 < 2048 ? (ns + 255) / 256 : 2048), 256, 0, st>>>(s.prev, ns, -1);
+    k_fill_i32<<<(s.ngrp + 255) / 256, 256, 0, st>>>((int32_t *)s.gctr, s.ngrp, 0);
     g_tcount = 0;
     for (int it = 0; it < max_iters; it++) {
         bool timed = it < g_tcap;
-        if (timed) hipEventRecord(g_tbeg[it], st);
+        if (timed) (void)hipEventRecord(g_tbeg[it], st);
         accum(s, src, ns, dmax, 0, st);
         if (timed) {
-            hipEventRecord(g_tend[it], st);
+            (void)hipEventRecord(g_tend[it], st);
             g_tcount = it + 1;
         }
-        k_icp_finalize<<<1, kFinThreads, 0, st>>>(s.part, s.pcnt, s.nblk, s.st, 0, conv_tol, out_T, out_stats,
+        k_icp_finalize<<<1, kFinThreads, 0, st>>>(s.gpart, s.gcnt, s.ngrp, s.st, 0, conv_tol, out_T, out_stats,
                                                   s.hist);
     }
     accum(s, src, ns, dmax, 1, st);
-    k_icp_finalize<<<1, kFinThreads, 0, st>>>(s.part, s.pcnt, s.nblk, s.st, 1, conv_tol, out_T, out_stats, s.hist);
+    k_icp_finalize<<<1, kFinThreads, 0, st>>>(s.gpart, s.gcnt, s.ngrp, s.st, 1, conv_tol, out_T, out_stats, s.hist);
     return hipGetLastError();
 }
 

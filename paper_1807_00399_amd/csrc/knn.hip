@@ -27,9 +27,9 @@ template <int KT>
 __global__ void __launch_bounds__(kQThreads) k_knn(GridView g, const float *__restrict__ qry, int64_t nq, int k,
                                                  int32_t *__restrict__ out_idx, float *__restrict__ out_d2)
 {
-    __shared__ uint2 stk[kStack * kQThreads];
+    __shared__ uint32_t stk[kStack * kQThreads];
     const GridParams P = *g.params;
-    int64_t i = blockIdx.x * (int64_t)kQThreads + threadIdx.x;
+    int64_t i = xcd_block(blockIdx.x, gridDim.x) * (int64_t)kQThreads + threadIdx.x;
     if (i >= nq) return;
     Query q{qry[3 * i], qry[3 * i + 1], qry[3 * i + 2]};
     TopK<KT> top;
@@ -124,9 +124,9 @@ __global__ void __launch_bounds__(kQThreads) k_normals(GridView g, const float *
                                                      float vy, float vz, float *__restrict__ out_n,
                                                      float *__restrict__ out_c)
 {
-    __shared__ uint2 stk[kStack * kQThreads];
+    __shared__ uint32_t stk[kStack * kQThreads];
     const GridParams P = *g.params;
-    int64_t s = blockIdx.x * (int64_t)kQThreads + threadIdx.x;
+    int64_t s = xcd_block(blockIdx.x, gridDim.x) * (int64_t)kQThreads + threadIdx.x;
     if (s >= P.n) return;
     float4 p = g.pts[s];
     uint32_t qi = __float_as_uint(p.w);

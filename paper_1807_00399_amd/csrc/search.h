@@ -4,7 +4,7 @@
 // visitor V (the ranking and the running search radius live there):
 //   bool  V::have()          a finite radius is already known (warm start)
 //   float V::bound2()        current search radius^2 (float32, inclusive)
-//   void  V::visit(j, p)     offer sorted point j with coordinates p
+//   void  V::visit(x,y,z,j,p) offer sorted point j with coordinates p
 //
 // The search has two phases:
 //   seed  - the smallest cell containing the query that holds `need` points
@@ -16,13 +16,17 @@
 // Cell boxes are shrunk by an absolute margin and a relative factor, so a
 // cell is skipped only when every point in it is strictly outside the
 // radius: no candidate inside the radius is ever missed, ties included.
+//
+// The traversal is bound by memory latency, so independent loads are issued
+// together: the up-to-8 children of a node, the up-to-8 cells of the cover
+// and groups of seed levels each cost one round trip, not one per item.
 #pragma once
 
 #include "common.h"
 
 namespace pcg {
 
-constexpr int kStack = 16;              // per-lane DFS stack entries (LDS)
+constexpr int kStack = 16;              // per-lane DFS stack entries (LDS, 4 bytes each)
 constexpr int kVisitBudget = 1 << 20;   // node pops per DFS; only a corrupted tree reaches it
 
 __device__ inline uint64_t enc_cand(float key, float w) { return ((uint64_t)__float_as_uint(key) << 32) | __float_as_uint(w); }
@@ -78,47 +82,100 @@ __device__ inline void scan_range(const float4 *__restrict__ pts, uint32_t s, ui
     for (uint32_t j = b0; j < b1; j++) v.visit(q.x, q.y, q.z, j, pts[j]);
 }
 
-// Depth-first search from the entries already on the stack.
+// continue a linear probe of `key` from slot s (first slot held another key)
+__device__ inline int32_t probe_from(const GridView &g, uint32_t mask, uint64_t key, uint32_t s)
+{
+    for (uint32_t it = 0; it < mask; it++) {
+        s = (s + 1) & mask;
+        HSlot e = g.hash[s];
+        if (e.key == key) return (int32_t)e.val;
+        if (e.key == kEmptyKey) return -1;
+    }
+    return -1;
+}
+
+__device__ inline void cmp_swap(float *d, uint32_t *id, int i, int j)
+{
+    bool sw = d[j] < d[i];
+    float td = sw ? d[j] : d[i];
+    uint32_t ti = sw ? id[j] : id[i];
+    d[j] = sw ? d[i] : d[j];
+    id[j] = sw ? id[i] : id[j];
+    d[i] = td;
+    id[i] = ti;
+}
+
+// ascending sort of 8 (distance, node) pairs: Batcher's odd-even merge network
+__device__ inline void sort8(float *d, uint32_t *id)
+{
+    cmp_swap(d, id, 0, 1); cmp_swap(d, id, 2, 3); cmp_swap(d, id, 4, 5); cmp_swap(d, id, 6, 7);
+    cmp_swap(d, id, 0, 2); cmp_swap(d, id, 1, 3); cmp_swap(d, id, 4, 6); cmp_swap(d, id, 5, 7);
+    cmp_swap(d, id, 1, 2); cmp_swap(d, id, 5, 6);
+    cmp_swap(d, id, 0, 4); cmp_swap(d, id, 1, 5); cmp_swap(d, id, 2, 6); cmp_swap(d, id, 3, 7);
+    cmp_swap(d, id, 2, 4); cmp_swap(d, id, 3, 5);
+    cmp_swap(d, id, 1, 2); cmp_swap(d, id, 3, 4); cmp_swap(d, id, 5, 6);
+}
+
+// Depth-first search from the nodes already on the stack.
 // stk: this lane's stack column (stride `stride` entries).
 template <class V, int LEAF>
-__device__ inline void dfs(const GridView &g, const GridParams &P, const Query &q, V &v, uint2 *stk, int stride,
+__device__ inline void dfs(const GridView &g, const GridParams &P, const Query &q, V &v, uint32_t *stk, int stride,
                            int sp, uint32_t xs, uint32_t xe)
 {
     for (int visits = 0; sp > 0 && visits < kVisitBudget; visits++) {
         --sp;
-        uint2 e = stk[sp * stride];
+        uint32_t m = stk[sp * stride];
+        Node nd = g.node[m];
+        const NodeHdr &h = nd.h;
         float b2 = v.bound2();
-        if (__uint_as_float(e.y) > b2) continue;
-        uint32_t m = e.x;
-        NodeHdr h = g.hdr[m];
+        if (node_mindist2(P, nd, q.x, q.y, q.z) > b2) continue;
         if (h.start >= xs && h.start + h.count <= xe) continue;      // already searched
-        int lvl = g.box[m].level;
-        bool leaf = (h.count <= (uint32_t)LEAF) || lvl == P.lmin || sp + (int)h.nchild > kStack;
+        uint32_t nc = node_nchild(h);
+        bool leaf = (h.count <= (uint32_t)LEAF) || node_level(h) == P.lmin || sp + (int)nc > kStack;
         if (leaf) {
             scan_range(g.pts, h.start, h.start + h.count, xs, xe, q, v);
             continue;
         }
-        // push children: those not containing q first, so the one holding
-        // q (mindist 0) is searched next
-        for (int pass = 0; pass < 2; pass++) {
-            for (uint32_t c = 0; c < h.nchild; c++) {
-                uint32_t ch = h.first_child + c;
-                NodeBox bx = g.box[ch];
-                float d2 = cell_mindist2(P, q.x, q.y, q.z, bx.cx, bx.cy, bx.cz, bx.level);
-                bool inside = d2 == 0.f;
-                if ((pass == 0) == inside) continue;
-                if (d2 > b2) continue;
-                stk[sp * stride] = make_uint2(ch, __float_as_uint(d2));
+        // all children boxes in one round trip, nearest pushed last (searched next)
+        float d[8];
+        uint32_t id[8];
+#pragma unroll
+        for (int c = 0; c < 8; c++) {
+            // padding slots sort last and are never pushed, even when the
+            // bound is still infinite
+            d[c] = INFINITY;
+            id[c] = 0xffffffffu;
+            if (c < (int)nc) {
+                d[c] = node_mindist2(P, g.node[h.first_child + c], q.x, q.y, q.z);
+                id[c] = h.first_child + c;
+            }
+        }
+        sort8(d, id);
+#pragma unroll
+        for (int c = 7; c >= 0; c--) {
+            if (id[c] != 0xffffffffu && d[c] <= b2) {
+                stk[sp * stride] = id[c];
                 ++sp;
             }
         }
     }
 }
 
+// level whose cells are at least 2R wide for the radius of b2 (17 when b2 is
+// not finite)
+__device__ inline int cover_level(const GridParams &P, float b2)
+{
+    if (!(b2 < INFINITY)) return kLevels;
+    float R = sqrtf(b2) * (1.0f + 1.0f / (1 << 20)) + P.margin;
+    int l = P.lmin;
+    while (l < kLevels - 1 && P.h0 * (float)(1u << l) * (1.0f - 1.0f / 1024) < 2.0f * R) l++;
+    return l;
+}
+
 // Cover phase: every cell meeting the ball of the visitor's current radius.
 template <class V, int LEAF>
-__device__ inline void cover(const GridView &g, const GridParams &P, const Query &q, V &v, uint2 *stk, int stride,
-                             uint32_t xs, uint32_t xe)
+__device__ inline void cover(const GridView &g, const GridParams &P, const Query &q, V &v, uint32_t *stk,
+                             int stride, uint32_t xs, uint32_t xe)
 {
     const float inv = P.inv_h0;
     float b2 = v.bound2();
@@ -126,58 +183,112 @@ __device__ inline void cover(const GridView &g, const GridParams &P, const Query
     float R = sqrtf(b2) * (1.0f + 1.0f / (1 << 20)) + P.margin;
     // coarsest needed level: cell width >= 2R (with slack) so the ball box
     // meets at most two cells per axis
-    int l = P.lmin;
-    while (l < kLevels - 1 && P.h0 * (float)(1u << l) * (1.0f - 1.0f / 1024) < 2.0f * R) l++;
-    uint32_t lo[3], hi[3];
-    lo[0] = cell0(q.x - R, P.ox, inv) >> l;
-    hi[0] = cell0(q.x + R, P.ox, inv) >> l;
-    lo[1] = cell0(q.y - R, P.oy, inv) >> l;
-    hi[1] = cell0(q.y + R, P.oy, inv) >> l;
-    lo[2] = cell0(q.z - R, P.oz, inv) >> l;
-    hi[2] = cell0(q.z + R, P.oz, inv) >> l;
+    int l = cover_level(P, b2);
+    uint32_t lx = cell0(q.x - R, P.ox, inv) >> l, hx = cell0(q.x + R, P.ox, inv) >> l;
+    uint32_t ly = cell0(q.y - R, P.oy, inv) >> l, hy = cell0(q.y + R, P.oy, inv) >> l;
+    uint32_t lz = cell0(q.z - R, P.oz, inv) >> l, hz = cell0(q.z + R, P.oz, inv) >> l;
     int sp = 0;
-    for (uint32_t cz = lo[2]; cz <= hi[2]; cz++)
-        for (uint32_t cy = lo[1]; cy <= hi[1]; cy++)
-            for (uint32_t cx = lo[0]; cx <= hi[0]; cx++) {
-                int32_t m = find_cell(g, P.hash_mask, l, cx, cy, cz);
-                if (m < 0) continue;
-                float d2 = cell_mindist2(P, q.x, q.y, q.z, cx, cy, cz, l);
-                if (d2 > b2) continue;
-                if (sp < kStack) {
-                    stk[sp * stride] = make_uint2((uint32_t)m, __float_as_uint(d2));
+    const uint32_t mask = P.hash_mask;
+    if (hx - lx <= 1 && hy - ly <= 1 && hz - lz <= 1) {
+        // up to 8 cells: first hash probes issued together
+        uint64_t key[8];
+        uint32_t slot[8];
+        uint64_t hk[8];
+        int32_t node[8];
+#pragma unroll
+        for (int c = 0; c < 8; c++) {
+            uint32_t cx = lx + (c & 1), cy = ly + ((c >> 1) & 1), cz = lz + (c >> 2);
+            bool ok = cx <= hx && cy <= hy && cz <= hz;
+            key[c] = hash_key(l, morton3(cx, cy, cz));
+            slot[c] = hash_slot(key[c], mask);
+            HSlot e = ok ? g.hash[slot[c]] : HSlot{kEmptyKey, 0u, 0u};
+            hk[c] = e.key;
+            node[c] = (e.key == key[c]) ? (int32_t)e.val : -1;
+        }
+#pragma unroll
+        for (int c = 0; c < 8; c++) {
+            if (hk[c] != key[c] && hk[c] != kEmptyKey) node[c] = probe_from(g, mask, key[c], slot[c]);
+            if (node[c] >= 0) {
+                uint32_t cx = lx + (c & 1), cy = ly + ((c >> 1) & 1), cz = lz + (c >> 2);
+                if (cell_mindist2(P, q.x, q.y, q.z, cx, cy, cz, l) <= b2) {
+                    stk[sp * stride] = (uint32_t)node[c];
                     ++sp;
-                } else {
-                    NodeHdr h = g.hdr[m];
-                    scan_range(g.pts, h.start, h.start + h.count, xs, xe, q, v);
                 }
             }
+        }
+    } else {
+        // rounding made the ball box span three cells on some axis
+        for (uint32_t cz = lz; cz <= hz; cz++)
+            for (uint32_t cy = ly; cy <= hy; cy++)
+                for (uint32_t cx = lx; cx <= hx; cx++) {
+                    int32_t m = find_cell(g, mask, l, cx, cy, cz);
+                    if (m < 0 || cell_mindist2(P, q.x, q.y, q.z, cx, cy, cz, l) > b2) continue;
+                    if (sp < kStack) {
+                        stk[sp * stride] = (uint32_t)m;
+                        ++sp;
+                    } else {
+                        NodeHdr h = g.node[m].h;
+                        scan_range(g.pts, h.start, h.start + h.count, xs, xe, q, v);
+                    }
+                }
+    }
     dfs<V, LEAF>(g, P, q, v, stk, stride, sp, xs, xe);
+}
+
+// smallest cell (level lmin and up) around q holding >= need points, or -1;
+// levels are probed four at a time
+__device__ inline int32_t seed_cell(const GridView &g, const GridParams &P, const Query &q, int need)
+{
+    const float inv = P.inv_h0;
+    uint32_t c0x = cell0(q.x, P.ox, inv), c0y = cell0(q.y, P.oy, inv), c0z = cell0(q.z, P.oz, inv);
+    const uint32_t mask = P.hash_mask;
+    for (int l0 = P.lmin; l0 < kLevels; l0 += 4) {
+        uint64_t key[4];
+        uint32_t slot[4];
+        uint64_t hk[4];
+        int32_t node[4];
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            int l = l0 + t;
+            bool ok = l < kLevels;
+            int ls = ok ? l : 0;
+            key[t] = hash_key(ls, morton3(c0x >> ls, c0y >> ls, c0z >> ls));
+            slot[t] = hash_slot(key[t], mask);
+            HSlot e = ok ? g.hash[slot[t]] : HSlot{kEmptyKey, 0u, 0u};
+            hk[t] = e.key;
+            node[t] = (e.key == key[t]) ? (int32_t)e.val : -1;
+        }
+#pragma unroll
+        for (int t = 0; t < 4; t++)
+            if (hk[t] != key[t] && hk[t] != kEmptyKey) node[t] = probe_from(g, mask, key[t], slot[t]);
+        uint32_t cnt[4];
+#pragma unroll
+        for (int t = 0; t < 4; t++) cnt[t] = node[t] >= 0 ? g.node[node[t]].h.count : 0u;
+#pragma unroll
+        for (int t = 0; t < 4; t++)
+            if (cnt[t] >= (uint32_t)need) return node[t];
+    }
+    return -1;
 }
 
 // Full search.  `need` = number of points the seed cell must hold (k, or 1
 // for the nearest neighbour).  When the visitor already has a finite radius
 // (a warm start) the seed phase is skipped.
 template <class V, int LEAF>
-__device__ inline void search(const GridView &g, const GridParams &P, const Query &q, V &v, int need, uint2 *stk,
-                              int stride)
+__device__ inline void search(const GridView &g, const GridParams &P, const Query &q, V &v, int need,
+                              uint32_t *stk, int stride)
 {
-    const float inv = P.inv_h0;
     uint32_t xs = 0, xe = 0;
-    if (!v.have()) {
-        // seed: smallest cell around q (level lmin and up) holding >= need points
-        uint32_t c0x = cell0(q.x, P.ox, inv), c0y = cell0(q.y, P.oy, inv), c0z = cell0(q.z, P.oz, inv);
-        int32_t seed = -1;
-        for (int l = P.lmin; l < kLevels; l++) {
-            int32_t m = find_cell(g, P.hash_mask, l, c0x >> l, c0y >> l, c0z >> l);
-            if (m >= 0 && g.hdr[m].count >= (uint32_t)need) {
-                seed = m;
-                break;
-            }
-        }
+    // with a finite cap no larger than a few finest cells, the cover alone is
+    // cheap; otherwise a seed cell first gives a small radius
+    float cap2 = v.bound2();
+    bool direct = cap2 < INFINITY && cover_level(P, cap2) <= P.lmin + 2;
+    if (!v.have() && !direct) {
+        int32_t seed = seed_cell(g, P, q, need);
         if (seed < 0) return;   // fewer than `need` points in the cloud
-        stk[0] = make_uint2((uint32_t)seed, 0u);
+        stk[0] = (uint32_t)seed;
         dfs<V, LEAF>(g, P, q, v, stk, stride, 1, 0u, 0u);
-        NodeHdr hs = g.hdr[seed];
+        NodeHdr hs = g.node[seed].h;
         xs = hs.start;
         xe = hs.start + hs.count;
     }
