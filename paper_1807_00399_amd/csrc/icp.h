@@ -10,13 +10,12 @@ struct IcpState;
 struct IcpStore {
     GridStore grid;     // pyramid over the target
     float4 *nrm;        // target normals in sorted order
-    int32_t *prev;      // per source point: previous match (sorted position) or -1
+    int2 *prev;         // per source point: previous match (sorted position, node) or -1
     IcpState *st;       // pose and loop state
     float2 *part;       // per block: compensated partial sums
     uint32_t *pcnt;     // per block: inlier counts
     float2 *gpart;      // per group of blocks: merged partial sums
     uint32_t *gcnt;     // per group of blocks: inlier counts
-    uint32_t *gctr;     // per group of blocks: arrival counter
     int ngrp;
     double *hist;       // per iteration: increment, inliers, sum r^2
     int nblk, ppt;

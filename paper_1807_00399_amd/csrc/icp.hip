@@ -26,7 +26,7 @@ namespace pcg {
 constexpr int kAcc = 28;            // 21 (A) + 6 (b) + 1 (sum r^2)
 constexpr int kIcpThreads = 256;
 constexpr int kFinThreads = 1024;
-constexpr int kGroup = 64;          // blocks merged by a group's last block
+constexpr int kGroup = 64;          // block partials merged per k_icp_reduce block
 
 struct IcpState {
     double T[16];          // current pose, float64 row-major
@@ -77,6 +77,7 @@ __device__ inline CSum csum_merge(CSum a, CSum b)
 struct NearBand {
     uint64_t best;       // (key bits << 32) | original index
     int32_t best_pos;    // sorted position, -1 if none within the cap
+    uint32_t best_node;  // node whose scan produced best_pos
     float second;        // smallest key of any other candidate seen
     float delta;         // bound on |p'(float32) - p'(float64)| per axis
 
@@ -85,6 +86,7 @@ struct NearBand {
         delta = dlt;
         best = enc_cand(cap2 + err(cap2), __uint_as_float(0xffffffffu));
         best_pos = -1;
+        best_node = 0xffffffffu;
         second = INFINITY;
     }
     __device__ float err(float key) const
@@ -98,7 +100,7 @@ struct NearBand {
         float b = best_key();
         return b + 2.f * err(b);
     }
-    __device__ void visit(float qx, float qy, float qz, uint32_t j, const float4 &p)
+    __device__ void visit(float qx, float qy, float qz, uint32_t j, const float4 &p, uint32_t m)
     {
         float key = knn_key(p.x, p.y, p.z, qx, qy, qz);
         uint64_t c = enc_cand(key, p.w);
@@ -106,6 +108,7 @@ struct NearBand {
             if (best_pos >= 0) second = fminf(second, best_key());
             best = c;
             best_pos = (int32_t)j;
+            best_node = m;
         } else if ((int32_t)j != best_pos) {
             second = fminf(second, key);
         }
@@ -122,7 +125,7 @@ struct Near64 {
 
     __device__ bool have() const { return true; }
     __device__ float bound2() const { return r2; }
-    __device__ void visit(float, float, float, uint32_t j, const float4 &p)
+    __device__ void visit(float, float, float, uint32_t j, const float4 &p, uint32_t)
     {
         double dx = px - (double)p.x, dy = py - (double)p.y, dz = pz - (double)p.z;
         double d2 = dx * dx + dy * dy + dz * dz;
@@ -184,36 +187,24 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v)
         p[i] = v;
 }
 
-__device__ inline void store_f2(float2 *p, CSum v)
-{
-    uint64_t bits = ((uint64_t)__float_as_uint(v.lo) << 32) | __float_as_uint(v.hi);
-    __hip_atomic_store((uint64_t *)p, bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ inline CSum load_f2(const float2 *p)
-{
-    uint64_t bits = __hip_atomic_load((const uint64_t *)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    return CSum{__uint_as_float((uint32_t)bits), __uint_as_float((uint32_t)(bits >> 32))};
-}
-
 // Correspondences + linearised system.  One source point per lane: the
 // search is bound by memory latency, so parallelism comes from many lanes.
-// Each block writes its compensated partial sums; the last block of every
-// group of kGroup blocks to finish merges the group's partials in block
-// order, so the result does not depend on scheduling.
+// Each block writes its compensated partial sums; k_icp_reduce and the
+// finalize kernel merge them in block order, so the result does not depend
+// on scheduling (no atomics, no fences in the hot kernel).
 template <int PPT>
 __global__ void __launch_bounds__(kIcpThreads) k_icp_accum(GridView g, const float *__restrict__ src, int64_t ns,
                                                          const float4 *__restrict__ nrm,
-                                                         int32_t *__restrict__ prev, const IcpState *__restrict__ st,
+                                                         int2 *__restrict__ prev, const IcpState *__restrict__ st,
                                                          float dmax, int final_pass, float2 *__restrict__ part,
-                                                         uint32_t *__restrict__ pcnt, float2 *__restrict__ gpart,
-                                                         uint32_t *__restrict__ gcnt, uint32_t *__restrict__ gctr,
-                                                         int nblk)
+                                                         uint32_t *__restrict__ pcnt, int nblk)
 {
+    // the DFS stack and, after the search, the reduction buffer share LDS
+    constexpr int kHalf = kAcc / 2;                       // accumulators per reduction pass
+    constexpr int kRow = kIcpThreads + 1;                 // padded row (bank spread)
+    static_assert(kHalf * kRow <= kStack * kIcpThreads, "reduction buffer must fit in the stack");
     __shared__ uint32_t stk[kStack * kIcpThreads];
-    __shared__ float2 wsum[kIcpThreads / 64][kAcc];
     __shared__ uint32_t wcnt[kIcpThreads / 64];
-    __shared__ int s_last;
     if (!final_pass && st->stop) return;   // uniform across the grid
     const GridParams P = *g.params;
     float Rh[12], Rl[12];
@@ -227,6 +218,7 @@ __global__ void __launch_bounds__(kIcpThreads) k_icp_accum(GridView g, const flo
     const int lblk = xcd_block(blockIdx.x, nblk);
     const int64_t base = (int64_t)lblk * (kIcpThreads * PPT) + threadIdx.x;
     int32_t jsel[PPT];
+    float tr[PPT][6];     // double-float p' of each point, reused by the accumulation
 #pragma unroll
     for (int r = 0; r < PPT; r++) {
         jsel[r] = -1;
@@ -237,6 +229,7 @@ __global__ void __launch_bounds__(kIcpThreads) k_icp_accum(GridView g, const flo
         df_row(Rh, Rl, px, py, pz, hx, lx);
         df_row(Rh + 4, Rl + 4, px, py, pz, hy, ly);
         df_row(Rh + 8, Rl + 8, px, py, pz, hz, lz);
+        tr[r][0] = hx; tr[r][1] = lx; tr[r][2] = hy; tr[r][3] = ly; tr[r][4] = hz; tr[r][5] = lz;
         Query q{hx + lx, hy + ly, hz + lz};
         // q is p' rounded to float32 (plus ~2^-44 relative): per axis it is
         // within half an ulp, bounded here with slack, of the float64 p'
@@ -245,10 +238,15 @@ __global__ void __launch_bounds__(kIcpThreads) k_icp_accum(GridView g, const flo
                         (1.0f / (1 << 30)) + 1e-30f;
         NearBand v;
         v.init(dmax2, dlt);
-        int32_t j0 = prev[i];
-        if (j0 >= 0) v.visit(q.x, q.y, q.z, (uint32_t)j0, g.pts[j0]);
-        search<NearBand, 16>(g, P, q, v, 1, stk + threadIdx.x, kIcpThreads);
-        prev[i] = v.best_pos;
+        int2 pv = prev[i];          // previous best (sorted position) and its node
+        bool done = false;
+        if (pv.x >= 0) {
+            float4 p0 = g.pts[pv.x];
+            v.visit(q.x, q.y, q.z, (uint32_t)pv.x, p0, (uint32_t)pv.y);
+            if (v.best_pos >= 0) done = search_in_node(g, P, q, v, (uint32_t)pv.y, p0);
+        }
+        if (!done) search<NearBand, 16>(g, P, q, v, 1, stk + threadIdx.x, kIcpThreads);
+        prev[i] = v.best_pos >= 0 ? make_int2(v.best_pos, (int32_t)v.best_node) : make_int2(-1, -1);
         int32_t j = -1;
         if (v.best_pos >= 0) {
             float b = v.best_key();
@@ -275,9 +273,12 @@ __global__ void __launch_bounds__(kIcpThreads) k_icp_accum(GridView g, const flo
         }
         jsel[r] = j;
     }
-    CSum acc[kAcc];
-#pragma unroll
-    for (int a = 0; a < kAcc; a++) acc[a] = CSum{0.f, 0.f};
+    // Row of the linearised system for this lane's point (zero when it is
+    // not an inlier).  With one point per lane the 28 sums start at the wave
+    // level: each product is merged across the wave error-free (TwoSum on
+    // (hi, lo) pairs), one accumulator at a time, so only a handful of
+    // registers are live here.
+    float J[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, res = 0.f;
     uint32_t cnt = 0;
 #pragma unroll
     for (int r = 0; r < PPT; r++) {
@@ -287,83 +288,86 @@ __global__ void __launch_bounds__(kIcpThreads) k_icp_accum(GridView g, const flo
         float4 n = nrm[j];
         if (n.x == 0.f && n.y == 0.f && n.z == 0.f) continue;
         float4 t = g.pts[j];
-        float px = src[3 * i], py = src[3 * i + 1], pz = src[3 * i + 2];
-        float hx, lx, hy, ly, hz, lz;
-        df_row(Rh, Rl, px, py, pz, hx, lx);
-        df_row(Rh + 4, Rl + 4, px, py, pz, hy, ly);
-        df_row(Rh + 8, Rl + 8, px, py, pz, hz, lz);
+        float hx = tr[r][0], lx = tr[r][1], hy = tr[r][2], ly = tr[r][3], hz = tr[r][4], lz = tr[r][5];
         float qx = hx + lx, qy = hy + ly, qz = hz + lz;
         // residual vector from the double-float p': (hi - q) is exact for
         // nearby points, so it keeps the full accuracy of hi + lo
         float dx = (hx - t.x) + lx, dy = (hy - t.y) + ly, dz = (hz - t.z) + lz;
-        float res = __fmaf_rn(dz, n.z, __fmaf_rn(dy, n.y, dx * n.x));
-        float J[6];
+        res = __fmaf_rn(dz, n.z, __fmaf_rn(dy, n.y, dx * n.x));
         J[0] = __fmaf_rn(qy, n.z, -qz * n.y);
         J[1] = __fmaf_rn(qz, n.x, -qx * n.z);
         J[2] = __fmaf_rn(qx, n.y, -qy * n.x);
         J[3] = n.x;
         J[4] = n.y;
         J[5] = n.z;
-        int a = 0;
-#pragma unroll
-        for (int u = 0; u < 6; u++)
-#pragma unroll
-            for (int v = u; v < 6; v++) two_sum_add(acc[a++], J[u] * J[v]);
-#pragma unroll
-        for (int u = 0; u < 6; u++) two_sum_add(acc[21 + u], J[u] * res);
-        two_sum_add(acc[27], res * res);
-        cnt++;
+        cnt = 1;
     }
-    // error-free merge across the wave (every lane ends with the same sums)
+    // Block reduction of the 28 sums, error-free in (hi, lo) float pairs and
+    // in a fixed order: in two passes of 14 sums, every lane stores its
+    // products in LDS, then 16 lanes per sum each accumulate 16 of them with
+    // TwoSum and merge their pairs across the 16 lanes.
+    const int tid = threadIdx.x, w = tid >> 6;
+    float *red = reinterpret_cast<float *>(stk);
+    const int ra = tid >> 4, rk = tid & 15;               // sum handled, sixteenth
+    __syncthreads();                                      // stack no longer in use
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) {
+    for (int half = 0; half < 2; half++) {
+        {
+            int a = 0;
 #pragma unroll
-        for (int a = 0; a < kAcc; a++) {
-            CSum o;
-            o.hi = __shfl_xor(acc[a].hi, off);
-            o.lo = __shfl_xor(acc[a].lo, off);
-            acc[a] = csum_merge(acc[a], o);
+            for (int u = 0; u < 6; u++)
+#pragma unroll
+                for (int v = u; v < 7; v++) {
+                    int slot = (v < 6) ? a++ : 21 + u;
+                    float x = (v < 6) ? J[u] * J[v] : J[u] * res;
+                    if (slot / kHalf == half) red[(slot % kHalf) * kRow + tid] = x;
+                }
+            if (half == 1) red[(27 % kHalf) * kRow + tid] = res * res;
         }
-        cnt += __shfl_xor(cnt, off);
-    }
-    int w = threadIdx.x >> 6;
-    if (__lane_id() == 0) {
+        __syncthreads();
+        if (ra < kHalf) {
+            CSum c{0.f, 0.f};
 #pragma unroll
-        for (int a = 0; a < kAcc; a++) wsum[w][a] = make_float2(acc[a].hi, acc[a].lo);
-        wcnt[w] = cnt;
+            for (int i = 0; i < kIcpThreads / 16; i++) two_sum_add(c, red[ra * kRow + rk + 16 * i]);
+#pragma unroll
+            for (int off = 8; off > 0; off >>= 1) {
+                CSum o{__shfl_xor(c.hi, off), __shfl_xor(c.lo, off)};
+                c = csum_merge(c, o);
+            }
+            if (rk == 0) part[(int64_t)lblk * kAcc + half * kHalf + ra] = make_float2(c.hi, c.lo);
+        }
+        __syncthreads();
     }
+    uint64_t ib = __ballot(cnt != 0);
+    if (__lane_id() == 0) wcnt[w] = (uint32_t)__popcll(ib);
     __syncthreads();
-    if (threadIdx.x < kAcc) {
-        CSum s{0.f, 0.f};
-        for (int x = 0; x < kIcpThreads / 64; x++) s = csum_merge(s, CSum{wsum[x][threadIdx.x].x, wsum[x][threadIdx.x].y});
-        store_f2(&part[(int64_t)lblk * kAcc + threadIdx.x], s);
-    } else if (threadIdx.x == kAcc) {
+    if (tid == 0) {
         uint32_t c = 0;
         for (int x = 0; x < kIcpThreads / 64; x++) c += wcnt[x];
-        __hip_atomic_store(&pcnt[lblk], c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        pcnt[lblk] = c;
     }
-    __threadfence();
-    __syncthreads();
-    const int grp = lblk / kGroup, b0 = grp * kGroup;
+}
+
+// merges the partials of kGroup consecutive blocks in block order
+__global__ void __launch_bounds__(64) k_icp_reduce(const float2 *__restrict__ part, const uint32_t *__restrict__ pcnt,
+                                                 int nblk, const IcpState *__restrict__ st, int final_pass,
+                                                 float2 *__restrict__ gpart, uint32_t *__restrict__ gcnt)
+{
+    if (!final_pass && st->stop) return;
+    const int grp = blockIdx.x, b0 = grp * kGroup;
     const int gsz = (nblk - b0) < kGroup ? (nblk - b0) : kGroup;
-    if (threadIdx.x == 0) {
-        uint32_t old = __hip_atomic_fetch_add(&gctr[grp], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        s_last = (old == (uint32_t)gsz - 1);
-    }
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    if (threadIdx.x < kAcc) {
+    int t = threadIdx.x;
+    if (t < kAcc) {
         CSum s{0.f, 0.f};
-        for (int b = 0; b < gsz; b++) s = csum_merge(s, load_f2(&part[(int64_t)(b0 + b) * kAcc + threadIdx.x]));
-        gpart[(int64_t)grp * kAcc + threadIdx.x] = make_float2(s.hi, s.lo);
-    } else if (threadIdx.x == kAcc) {
+        for (int b = 0; b < gsz; b++) {
+            float2 v = part[(int64_t)(b0 + b) * kAcc + t];
+            s = csum_merge(s, CSum{v.x, v.y});
+        }
+        gpart[(int64_t)grp * kAcc + t] = make_float2(s.hi, s.lo);
+    } else if (t == kAcc) {
         uint32_t c = 0;
-        for (int b = 0; b < gsz; b++)
-            c += __hip_atomic_load(&pcnt[b0 + b], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        for (int b = 0; b < gsz; b++) c += pcnt[b0 + b];
         gcnt[grp] = c;
-    } else if (threadIdx.x == kAcc + 1) {
-        __hip_atomic_store(&gctr[grp], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);   // ready for the next pass
     }
 }
 
@@ -553,7 +557,7 @@ void icp_carve(Carver &c, int64_t ns, int64_t nt, int max_iters, IcpStore &s)
     grid_carve(c, nt, s.grid);
     int64_t nt1 = nt > 0 ? nt : 1, ns1 = ns > 0 ? ns : 1;
     s.nrm = c.take<float4>(nt1);
-    s.prev = c.take<int32_t>(ns1);
+    s.prev = c.take<int2>(ns1);
     s.st = c.take<IcpState>(1);
     s.ppt = icp_ppt(ns1);
     s.nblk = (int)((ns1 + (int64_t)kIcpThreads * s.ppt - 1) / ((int64_t)kIcpThreads * s.ppt));
@@ -562,7 +566,6 @@ void icp_carve(Carver &c, int64_t ns, int64_t nt, int max_iters, IcpStore &s)
     s.ngrp = (s.nblk + kGroup - 1) / kGroup;
     s.gpart = c.take<float2>((size_t)s.ngrp * kAcc);
     s.gcnt = c.take<uint32_t>((size_t)s.ngrp);
-    s.gctr = c.take<uint32_t>((size_t)s.ngrp);
     s.hist = c.take<double>((size_t)8 * (max_iters > 0 ? max_iters : 1));
 }
 
@@ -570,7 +573,8 @@ template <int PPT>
 static void launch_accum(IcpStore &s, const float *src, int64_t ns, float dmax, int final_pass, hipStream_t st)
 {
     k_icp_accum<PPT><<<s.nblk, kIcpThreads, 0, st>>>(s.grid.view(), src, ns, s.nrm, s.prev, s.st, dmax,
-                                                     final_pass, s.part, s.pcnt, s.gpart, s.gcnt, s.gctr, s.nblk);
+                                                     final_pass, s.part, s.pcnt, s.nblk);
+    k_icp_reduce<<<s.ngrp, 64, 0, st>>>(s.part, s.pcnt, s.nblk, s.st, final_pass, s.gpart, s.gcnt);
 }
 
 static void accum(IcpStore &s, const float *src, int64_t ns, float dmax, int final_pass, hipStream_t st)
@@ -597,8 +601,8 @@ hipError_t icp_run(IcpStore &s, const float *src, int64_t ns, const float *tgt, 
     if (e != hipSuccess) return e;
     e = grid_gather3(s.grid, tgt_n, s.nrm, st);
     if (e != hipSuccess) return e;
-    k_fill_i32<<<(int)((ns + 255) / 256 < 2048 ? (ns + 255) / 256 : 2048), 256, 0, st>>>(s.prev, ns, -1);
-    k_fill_i32<<<(s.ngrp + 255) / 256, 256, 0, st>>>((int32_t *)s.gctr, s.ngrp, 0);
+    k_fill_i32<<<(int)((2 * ns + 255) / 256 < 2048 ? (2 * ns + 255) / 256 : 2048), 256, 0, st>>>((int32_t *)s.prev,
+                                                                                             2 * ns, -1);
     g_tcount = 0;
     for (int it = 0; it < max_iters; it++) {
         bool timed = it < g_tcap;

@@ -4,7 +4,7 @@
 // visitor V (the ranking and the running search radius live there):
 //   bool  V::have()          a finite radius is already known (warm start)
 //   float V::bound2()        current search radius^2 (float32, inclusive)
-//   void  V::visit(x,y,z,j,p) offer sorted point j with coordinates p
+//   void  V::visit(x,y,z,j,p,m) offer sorted point j (coordinates p) of node m
 //
 // The search has two phases:
 //   seed  - the smallest cell containing the query that holds `need` points
@@ -58,7 +58,7 @@ struct TopK {
             h[0] = (c < h[0]) ? c : h[0];
         }
     }
-    __device__ void visit(float qx, float qy, float qz, uint32_t, const float4 &p)
+    __device__ void visit(float qx, float qy, float qz, uint32_t, const float4 &p, uint32_t)
     {
         insert(enc_cand(knn_key(p.x, p.y, p.z, qx, qy, qz), p.w));
     }
@@ -68,18 +68,35 @@ struct Query {
     float x, y, z;
 };
 
-// scan sorted points [s, e) minus the excluded run [xs, xe)
+// scan sorted points [s, e) of node m minus the excluded run [xs, xe)
 template <class V>
 __device__ inline void scan_range(const float4 *__restrict__ pts, uint32_t s, uint32_t e, uint32_t xs,
-                                  uint32_t xe, const Query &q, V &v)
+                                  uint32_t xe, const Query &q, V &v, uint32_t m)
 {
     uint32_t a0 = s, a1 = e, b0 = e, b1 = e;
     if (xs < xe && xs < e && xe > s) {   // overlap with the excluded run (nested or disjoint)
         a1 = xs > s ? xs : s;
         b0 = xe < e ? xe : e;
     }
-    for (uint32_t j = a0; j < a1; j++) v.visit(q.x, q.y, q.z, j, pts[j]);
-    for (uint32_t j = b0; j < b1; j++) v.visit(q.x, q.y, q.z, j, pts[j]);
+    // four independent loads per round trip
+    for (uint32_t j = a0; j < a1; j += 4) {
+        float4 p[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            if (j + u < a1) p[u] = pts[j + u];
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            if (j + u < a1) v.visit(q.x, q.y, q.z, j + u, p[u], m);
+    }
+    for (uint32_t j = b0; j < b1; j += 4) {
+        float4 p[4];
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            if (j + u < b1) p[u] = pts[j + u];
+#pragma unroll
+        for (int u = 0; u < 4; u++)
+            if (j + u < b1) v.visit(q.x, q.y, q.z, j + u, p[u], m);
+    }
 }
 
 // continue a linear probe of `key` from slot s (first slot held another key)
@@ -133,7 +150,7 @@ __device__ inline void dfs(const GridView &g, const GridParams &P, const Query &
         uint32_t nc = node_nchild(h);
         bool leaf = (h.count <= (uint32_t)LEAF) || node_level(h) == P.lmin || sp + (int)nc > kStack;
         if (leaf) {
-            scan_range(g.pts, h.start, h.start + h.count, xs, xe, q, v);
+            scan_range(g.pts, h.start, h.start + h.count, xs, xe, q, v, m);
             continue;
         }
         // all children boxes in one round trip, nearest pushed last (searched next)
@@ -228,7 +245,7 @@ __device__ inline void cover(const GridView &g, const GridParams &P, const Query
                         ++sp;
                     } else {
                         NodeHdr h = g.node[m].h;
-                        scan_range(g.pts, h.start, h.start + h.count, xs, xe, q, v);
+                        scan_range(g.pts, h.start, h.start + h.count, xs, xe, q, v, (uint32_t)m);
                     }
                 }
     }
@@ -269,6 +286,29 @@ __device__ inline int32_t seed_cell(const GridView &g, const GridParams &P, cons
             if (cnt[t] >= (uint32_t)need) return node[t];
     }
     return -1;
+}
+
+// Warm start: when the ball of the visitor's radius around q lies inside the
+// cell of node m (a node holding the previous answer, whose point p0 fixes
+// the cell), every candidate is in m, so scanning m alone is exact.  Returns
+// false (nothing scanned) when the ball leaves the cell.
+template <class V>
+__device__ inline bool search_in_node(const GridView &g, const GridParams &P, const Query &q, V &v, uint32_t m,
+                                      const float4 &p0)
+{
+    float b2 = v.bound2();
+    if (!(b2 < INFINITY)) return false;
+    Node nd = g.node[m];
+    int l = node_level(nd.h);
+    const float inv = P.inv_h0;
+    float R = sqrtf(b2) * (1.0f + 1.0f / (1 << 20)) + P.margin;
+    uint32_t cx = cell0(p0.x, P.ox, inv) >> l, cy = cell0(p0.y, P.oy, inv) >> l, cz = cell0(p0.z, P.oz, inv) >> l;
+    bool inside = (cell0(q.x - R, P.ox, inv) >> l) == cx && (cell0(q.x + R, P.ox, inv) >> l) == cx &&
+                  (cell0(q.y - R, P.oy, inv) >> l) == cy && (cell0(q.y + R, P.oy, inv) >> l) == cy &&
+                  (cell0(q.z - R, P.oz, inv) >> l) == cz && (cell0(q.z + R, P.oz, inv) >> l) == cz;
+    if (!inside) return false;
+    scan_range(g.pts, nd.h.start, nd.h.start + nd.h.count, 0u, 0u, q, v, m);
+    return true;
 }
 
 // Full search.  `need` = number of points the seed cell must hold (k, or 1
