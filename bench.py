@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="room")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="time a plain 1 GiB device copy (bandwidth and counter calibration) and exit")
     return ap.parse_args()
 
 
@@ -73,17 +75,54 @@ class HipEvents:
         return ms.value
 
 
+KERNEL_SOURCES = ("icp.hip", "search.h", "common.h")
+
+
+def kernel_digest():
+    """Digest of the sources the ICP kernel is built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, "paper_1807_00399_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
 def traffic_from_profiles(kernel_tag, workload):
-    """HBM bytes per launch from committed rocprofv3 counter summaries, if
-    they were taken for this kernel and workload (else None)."""
+    """HBM bytes per launch from the committed rocprofv3 counter summary for
+    this kernel and workload, provided the kernel sources have not changed
+    since the counters were taken (else None)."""
     path = os.path.join(PROFILES, f"{kernel_tag}_{workload}_counters.json")
     if not os.path.exists(path):
         return None
     try:
         d = json.load(open(path))
-        return d.get("hbm_bytes_per_launch")
     except Exception:
         return None
+    if d.get("kernel_digest") != kernel_digest():
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def copy_probe():
+    """Plain device copy of 1 GiB, 10 times: achievable bandwidth, and a
+    kernel of known traffic for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    from paper_1807_00399_amd import pcgpu
+    nbytes = 1 << 30
+    a = torch.empty(nbytes, dtype=torch.uint8, device="cuda").fill_(1)
+    b = torch.empty_like(a)
+    pcgpu.copy_probe(b, a)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    reps = 10
+    for _ in range(reps):
+        pcgpu.copy_probe(b, a)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    gbs = 2 * nbytes * reps / el / 1e9
+    print(json.dumps({"copy_probe": {"bytes_read_per_launch": nbytes, "bytes_written_per_launch": nbytes,
+                                     "launches": reps + 1, "achieved_GBps": gbs, "peak_GBps": HBM_PEAK_GBS}}),
+          flush=True)
 
 
 def cpu_baseline(w, budget_s):
@@ -121,6 +160,9 @@ def main():
     from paper_1807_00399_amd import pcgpu
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_probe:
+        copy_probe()
+        return
     dev = torch.device("cuda:0")
     w = make_workload(WORKLOADS[args.workload])
     src = torch.from_numpy(w.source).to(dev)
