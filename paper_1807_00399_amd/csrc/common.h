@@ -229,6 +229,7 @@ struct GridStore {
     HSlot *hash;
     uint32_t *slev;           // per sorted point: top level at which it starts a cell (or 0xff)
     uint32_t *radix_hist;     // radix histograms / scan space
+    uint32_t *radix_tot;      // per-digit totals of a pass
     int32_t *level_block;     // per block, per level: counts then offsets
     uint32_t *bbox;           // 6 ordered-uint min/max
     int64_t n;

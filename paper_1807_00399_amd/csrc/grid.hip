@@ -141,29 +141,27 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint64_t *__r
     hist[(int64_t)t * gridDim.x + blockIdx.x] = cnt[t];
 }
 
-// exclusive scan of m values in place, one block of 1024 threads
-__global__ void __launch_bounds__(1024) k_scan_excl(uint32_t *__restrict__ v, int64_t m)
+// Per-digit exclusive scan over tiles (one wave per digit, 64 tiles per
+// step): hist[d * nblk + b] becomes the offset of tile b within digit d;
+// tot[d] receives the digit's total.
+__global__ void __launch_bounds__(256) k_radix_colscan(uint32_t *__restrict__ hist, int nblk,
+                                                     uint32_t *__restrict__ tot)
 {
-    __shared__ uint32_t part[1024];
-    int t = threadIdx.x;
-    int64_t chunk = (m + 1023) / 1024;
-    int64_t b = t * chunk, e = b + chunk < m ? b + chunk : m;
-    uint32_t s = 0;
-    for (int64_t i = b; i < e; i++) s += v[i];
-    part[t] = s;
-    __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {
-        uint32_t x = (t >= off) ? part[t - off] : 0u;
-        __syncthreads();
-        part[t] += x;
-        __syncthreads();
+    const int d = blockIdx.x * 4 + (threadIdx.x >> 6), lane = __lane_id();
+    uint32_t carry = 0;
+    for (int b0 = 0; b0 < nblk; b0 += 64) {
+        int b = b0 + lane;
+        uint32_t v = (b < nblk) ? hist[(int64_t)d * nblk + b] : 0u;
+        uint32_t x = v;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            uint32_t y = __shfl_up(x, off);
+            if (lane >= off) x += y;
+        }
+        if (b < nblk) hist[(int64_t)d * nblk + b] = carry + x - v;
+        carry += __shfl(x, 63);
     }
-    uint32_t run = part[t] - s;
-    for (int64_t i = b; i < e; i++) {
-        uint32_t x = v[i];
-        v[i] = run;
-        run += x;
-    }
+    if (lane == 0) tot[d] = carry;
 }
 
 // Stable scatter of one radix pass.  Each block walks its tile in rounds of
@@ -172,13 +170,28 @@ __global__ void __launch_bounds__(1024) k_scan_excl(uint32_t *__restrict__ v, in
 // earlier rounds, so the original order of equal digits is kept.
 __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ iin, int64_t n, int shift,
-    const uint32_t *__restrict__ hist, uint64_t *__restrict__ kout, uint32_t *__restrict__ iout)
+    const uint32_t *__restrict__ hist, const uint32_t *__restrict__ tot, uint64_t *__restrict__ kout,
+    uint32_t *__restrict__ iout)
 {
     constexpr int W = kSortThreads / 64;
     __shared__ uint32_t running[kRadix];
     __shared__ uint32_t wcnt[W][kRadix];
+    __shared__ uint32_t wsum[W];
     int t = threadIdx.x, w = t >> 6;
-    running[t] = hist[(int64_t)t * gridDim.x + blockIdx.x];
+    // digit base = exclusive scan of the digit totals (256 values, in LDS)
+    {
+        uint32_t v = tot[t], x = v;
+#pragma unroll
+        for (int off = 1; off < 64; off <<= 1) {
+            uint32_t y = __shfl_up(x, off);
+            if (__lane_id() >= off) x += y;
+        }
+        if (__lane_id() == 63) wsum[w] = x;
+        __syncthreads();
+        uint32_t before = 0;
+        for (int x2 = 0; x2 < w; x2++) before += wsum[x2];
+        running[t] = before + x - v + hist[(int64_t)t * gridDim.x + blockIdx.x];
+    }
     for (int x = 0; x < W; x++) wcnt[x][t] = 0;
     __syncthreads();
     int64_t base = (int64_t)blockIdx.x * kSortTile;
@@ -501,6 +514,7 @@ void grid_carve(Carver &c, int64_t n, GridStore &g)
     g.pts = c.take<float4>(nn);
     g.slev = c.take<uint32_t>(nn);
     g.radix_hist = c.take<uint32_t>((size_t)g.nblk_sort * kRadix);
+    g.radix_tot = c.take<uint32_t>(kRadix);
     g.level_block = c.take<int32_t>((size_t)g.nblk_lvl * kLevels);
     g.node = c.take<Node>(g.max_nodes);
     g.hash = c.take<HSlot>(g.hash_cap_max);
@@ -531,8 +545,9 @@ hipError_t grid_build(GridStore &g, const float *xyz, hipStream_t s)
         for (int p = 0; p < kPasses; p++) {
             int shift = p * kRadixBits;
             k_radix_hist<<<g.nblk_sort, kSortThreads, 0, s>>>(ka, n, shift, g.radix_hist);
-            k_scan_excl<<<1, 1024, 0, s>>>(g.radix_hist, (int64_t)g.nblk_sort * kRadix);
-            k_radix_scatter<<<g.nblk_sort, kSortThreads, 0, s>>>(ka, ia, n, shift, g.radix_hist, kb, ib);
+            k_radix_colscan<<<kRadix / 4, 256, 0, s>>>(g.radix_hist, g.nblk_sort, g.radix_tot);
+            k_radix_scatter<<<g.nblk_sort, kSortThreads, 0, s>>>(ka, ia, n, shift, g.radix_hist, g.radix_tot,
+                                                                 kb, ib);
             // ping-pong; with an even number of passes the result lands in keys/idx
             uint64_t *tk = ka; ka = kb; kb = tk;
             if (p == 0) { ia = g.idx_alt; ib = g.idx; }

@@ -348,26 +348,53 @@ __global__ void __launch_bounds__(kIcpThreads) k_icp_accum(GridView g, const flo
     }
 }
 
-// merges the partials of kGroup consecutive blocks in block order
-__global__ void __launch_bounds__(64) k_icp_reduce(const float2 *__restrict__ part, const uint32_t *__restrict__ pcnt,
-                                                 int nblk, const IcpState *__restrict__ st, int final_pass,
-                                                 float2 *__restrict__ gpart, uint32_t *__restrict__ gcnt)
+// Merges 32-lane groups of (hi, lo) pairs: lane j of each 32-lane half-wave
+// holds one pair; a fixed xor tree leaves the total in lane 0.
+__device__ inline CSum merge32(CSum c)
 {
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) {
+        CSum o{__shfl_xor(c.hi, off), __shfl_xor(c.lo, off)};
+        c = csum_merge(c, o);
+    }
+    return c;
+}
+
+__device__ inline uint32_t sum32(uint32_t c)
+{
+#pragma unroll
+    for (int off = 16; off > 0; off >>= 1) c += __shfl_xor(c, off);
+    return c;
+}
+
+// Merges the partials of kGroup (64) consecutive blocks: sum a (thread
+// t >> 5) is loaded by 32 lanes, two partials each, and merged by a fixed
+// tree, so the result depends only on the block order.
+__global__ void __launch_bounds__(1024) k_icp_reduce(const float2 *__restrict__ part, const uint32_t *__restrict__ pcnt,
+                                                   int nblk, const IcpState *__restrict__ st, int final_pass,
+                                                   float2 *__restrict__ gpart, uint32_t *__restrict__ gcnt)
+{
+    static_assert(kGroup == 64, "two partials per lane of a 32-lane group");
     if (!final_pass && st->stop) return;
     const int grp = blockIdx.x, b0 = grp * kGroup;
     const int gsz = (nblk - b0) < kGroup ? (nblk - b0) : kGroup;
-    int t = threadIdx.x;
-    if (t < kAcc) {
-        CSum s{0.f, 0.f};
-        for (int b = 0; b < gsz; b++) {
-            float2 v = part[(int64_t)(b0 + b) * kAcc + t];
-            s = csum_merge(s, CSum{v.x, v.y});
+    const int a = threadIdx.x >> 5, j = threadIdx.x & 31;
+    if (a < kAcc) {
+        CSum c{0.f, 0.f};
+        if (j < gsz) {
+            float2 v = part[(int64_t)(b0 + j) * kAcc + a];
+            c = CSum{v.x, v.y};
         }
-        gpart[(int64_t)grp * kAcc + t] = make_float2(s.hi, s.lo);
-    } else if (t == kAcc) {
-        uint32_t c = 0;
-        for (int b = 0; b < gsz; b++) c += pcnt[b0 + b];
-        gcnt[grp] = c;
+        if (j + 32 < gsz) {
+            float2 v = part[(int64_t)(b0 + j + 32) * kAcc + a];
+            c = csum_merge(c, CSum{v.x, v.y});
+        }
+        c = merge32(c);
+        if (j == 0) gpart[(int64_t)grp * kAcc + a] = make_float2(c.hi, c.lo);
+    } else if (a == kAcc) {
+        uint32_t c = (j < gsz ? pcnt[b0 + j] : 0u) + (j + 32 < gsz ? pcnt[b0 + j + 32] : 0u);
+        c = sum32(c);
+        if (j == 0) gcnt[grp] = c;
     }
 }
 
@@ -400,33 +427,31 @@ __global__ void __launch_bounds__(kFinThreads) k_icp_finalize(const float2 *__re
                                                             double *__restrict__ out_T, pc_icp_stats *out_stats,
                                                             double *__restrict__ hist)
 {
-    constexpr int G = kFinThreads / 32;   // block groups
-    __shared__ float2 red[G][32];
-    __shared__ uint32_t credg[G];
+    __shared__ float2 red[32];
+    __shared__ uint32_t redc;
     if (!final_pass && st->stop) return;
-    int t = threadIdx.x, grp = t >> 5, a = t & 31;
-    CSum s{0.f, 0.f};
-    uint32_t c = 0;
-    for (int b = grp; b < nblk; b += G) {
-        if (a < kAcc) {
+    // sum a (thread t >> 5) over the groups: lane j merges groups j, j+32, ...
+    // in order, then a fixed 32-lane tree merges the lanes
+    const int a = threadIdx.x >> 5, j = threadIdx.x & 31;
+    if (a < kAcc) {
+        CSum c{0.f, 0.f};
+        for (int b = j; b < nblk; b += 32) {
             float2 v = part[(int64_t)b * kAcc + a];
-            s = csum_merge(s, CSum{v.x, v.y});
-        } else if (a == kAcc) {
-            c += pcnt[b];
+            c = csum_merge(c, CSum{v.x, v.y});
         }
+        c = merge32(c);
+        if (j == 0) red[a] = make_float2(c.hi, c.lo);
+    } else if (a == kAcc) {
+        uint32_t c = 0;
+        for (int b = j; b < nblk; b += 32) c += pcnt[b];
+        c = sum32(c);
+        if (j == 0) redc = c;
     }
-    red[grp][a] = make_float2(s.hi, s.lo);
-    if (a == kAcc) credg[grp] = c;
     __syncthreads();
-    if (t != 0) return;
+    if (threadIdx.x != 0) return;
     double sum[kAcc];
-    for (int k = 0; k < kAcc; k++) {
-        CSum m{0.f, 0.f};
-        for (int x = 0; x < G; x++) m = csum_merge(m, CSum{red[x][k].x, red[x][k].y});
-        sum[k] = (double)m.hi + (double)m.lo;
-    }
-    int64_t inl = 0;
-    for (int x = 0; x < G; x++) inl += credg[x];
+    for (int k = 0; k < kAcc; k++) sum[k] = (double)red[k].x + (double)red[k].y;
+    int64_t inl = redc;
     st->inliers = inl;
     st->sum_r2 = sum[27];
     if (final_pass) {
@@ -574,7 +599,7 @@ static void launch_accum(IcpStore &s, const float *src, int64_t ns, float dmax, 
 {
     k_icp_accum<PPT><<<s.nblk, kIcpThreads, 0, st>>>(s.grid.view(), src, ns, s.nrm, s.prev, s.st, dmax,
                                                      final_pass, s.part, s.pcnt, s.nblk);
-    k_icp_reduce<<<s.ngrp, 64, 0, st>>>(s.part, s.pcnt, s.nblk, s.st, final_pass, s.gpart, s.gcnt);
+    k_icp_reduce<<<s.ngrp, 1024, 0, st>>>(s.part, s.pcnt, s.nblk, s.st, final_pass, s.gpart, s.gcnt);
 }
 
 static void accum(IcpStore &s, const float *src, int64_t ns, float dmax, int final_pass, hipStream_t st)
