@@ -273,7 +273,9 @@ __global__ void k_slev(const uint64_t *__restrict__ keys, int64_t n, uint32_t *_
 }
 
 // turns the slev histogram into node counts per level, picks the finest
-// level (mean occupancy >= 2), lays out the node arrays and the hash size
+// level such that the pyramid from there up has at most n nodes (so leaves
+// are as small as a node budget of one per point allows, also where the
+// density is far above the mean), lays out the node arrays and the hash size
 __global__ void k_levels(GridParams *P, int64_t n, uint32_t hash_cap_max)
 {
     int32_t cnt[kLevels];
@@ -283,8 +285,12 @@ __global__ void k_levels(GridParams *P, int64_t n, uint32_t hash_cap_max)
         cnt[l] = run;           // points opening a cell at level >= l = cells at level l
     }
     int lmin = kLevels - 1;
-    for (int l = 0; l < kLevels; l++)
-        if (2 * (int64_t)cnt[l] <= n) { lmin = l; break; }
+    int64_t cum = 0;
+    for (int l = kLevels - 1; l >= 0; l--) {
+        cum += cnt[l];
+        if (cum > (n > 1 ? n : 1)) break;
+        lmin = l;
+    }
     int32_t off = 0;
     for (int l = 0; l < kLevels; l++) {
         P->level_count[l] = (l >= lmin) ? cnt[l] : 0;
@@ -478,16 +484,8 @@ inline int blocks_for(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
 int64_t max_pyramid_nodes(int64_t n)
 {
-    // at most floor(n/2) cells per kept level (except the single root), and
-    // never more than the level has cells
-    int64_t tot = 0;
-    for (int l = 0; l < kLevels; l++) {
-        int64_t cells = (l >= 16) ? 1 : (int64_t)1 << (3 * (16 - l) > 62 ? 62 : 3 * (16 - l));
-        int64_t c = n / 2 > 1 ? n / 2 : 1;
-        if (c > n) c = n;
-        tot += c < cells ? c : cells;
-    }
-    return tot + 1;
+    // the kept levels hold at most max(n, 1) nodes in total
+    return (n > 1 ? n : 1) + 1;
 }
 
 static uint32_t hash_cap_for(int64_t nodes)

@@ -24,7 +24,13 @@
 namespace pcg {
 
 constexpr int kAcc = 28;            // 21 (A) + 6 (b) + 1 (sum r^2)
-constexpr int kIcpThreads = 256;
+#ifndef PCG_ICP_THREADS
+#define PCG_ICP_THREADS 128
+#endif
+#ifndef PCG_ICP_ATTR
+#define PCG_ICP_ATTR
+#endif
+constexpr int kIcpThreads = PCG_ICP_THREADS;   // one source point per lane
 constexpr int kFinThreads = 1024;
 constexpr int kGroup = 64;          // block partials merged per k_icp_reduce block
 
@@ -193,7 +199,7 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v)
 // finalize kernel merge them in block order, so the result does not depend
 // on scheduling (no atomics, no fences in the hot kernel).
 template <int PPT>
-__global__ void __launch_bounds__(kIcpThreads) k_icp_accum(GridView g, const float *__restrict__ src, int64_t ns,
+__global__ void __launch_bounds__(kIcpThreads) PCG_ICP_ATTR k_icp_accum(GridView g, const float *__restrict__ src, int64_t ns,
                                                          const float4 *__restrict__ nrm,
                                                          int2 *__restrict__ prev, const IcpState *__restrict__ st,
                                                          float dmax, int final_pass, float2 *__restrict__ part,
@@ -304,11 +310,13 @@ __global__ void __launch_bounds__(kIcpThreads) k_icp_accum(GridView g, const flo
     }
     // Block reduction of the 28 sums, error-free in (hi, lo) float pairs and
     // in a fixed order: in two passes of 14 sums, every lane stores its
-    // products in LDS, then 16 lanes per sum each accumulate 16 of them with
-    // TwoSum and merge their pairs across the 16 lanes.
+    // products in LDS, then kLanes lanes per sum each accumulate 16 of them
+    // with TwoSum and merge their pairs across the kLanes lanes.
+    constexpr int kLanes = kIcpThreads / 16;
+    static_assert(kHalf * kLanes <= kIcpThreads, "one lane per (sum, share)");
     const int tid = threadIdx.x, w = tid >> 6;
     float *red = reinterpret_cast<float *>(stk);
-    const int ra = tid >> 4, rk = tid & 15;               // sum handled, sixteenth
+    const int ra = tid / kLanes, rk = tid % kLanes;       // sum handled, share
     __syncthreads();                                      // stack no longer in use
 #pragma unroll
     for (int half = 0; half < 2; half++) {
@@ -328,9 +336,9 @@ __global__ void __launch_bounds__(kIcpThreads) k_icp_accum(GridView g, const flo
         if (ra < kHalf) {
             CSum c{0.f, 0.f};
 #pragma unroll
-            for (int i = 0; i < kIcpThreads / 16; i++) two_sum_add(c, red[ra * kRow + rk + 16 * i]);
+            for (int i = 0; i < 16; i++) two_sum_add(c, red[ra * kRow + rk + kLanes * i]);
 #pragma unroll
-            for (int off = 8; off > 0; off >>= 1) {
+            for (int off = kLanes / 2; off > 0; off >>= 1) {
                 CSum o{__shfl_xor(c.hi, off), __shfl_xor(c.lo, off)};
                 c = csum_merge(c, o);
             }

@@ -46,20 +46,25 @@ __global__ void __launch_bounds__(kQThreads) k_knn(GridView g, const float *__re
 }
 
 // eigen-decomposition of the symmetric C = [a b c; b d e; c e f] (float64):
-// ascending eigenvalues and the unit eigenvector of the smallest
+// ascending eigenvalues and the unit eigenvector of the smallest.  Written
+// with selects only, so everything stays in registers.
 __device__ void sym3_min_eigvec(double a, double b, double c, double d, double e, double f, double lam[3],
                                 double v[3])
 {
     double p1 = b * b + c * c + e * e;
     if (p1 == 0.0) {
-        double dg[3] = {a, d, f};
-        int o[3] = {0, 1, 2};
-        for (int i = 0; i < 3; i++)
-            for (int j = i + 1; j < 3; j++)
-                if (dg[o[j]] < dg[o[i]]) { int t = o[i]; o[i] = o[j]; o[j] = t; }
-        for (int i = 0; i < 3; i++) lam[i] = dg[o[i]];
-        v[0] = v[1] = v[2] = 0.0;
-        v[o[0]] = 1.0;
+        // diagonal: smallest entry, lowest axis first on ties
+        int i0 = (d < a) ? 1 : 0;
+        double m0 = (d < a) ? d : a;
+        i0 = (f < m0) ? 2 : i0;
+        double lo = (f < m0) ? f : m0;
+        double hi = fmax(a, fmax(d, f));
+        lam[0] = lo;
+        lam[2] = hi;
+        lam[1] = (a + d + f) - lo - hi;
+        v[0] = i0 == 0 ? 1.0 : 0.0;
+        v[1] = i0 == 1 ? 1.0 : 0.0;
+        v[2] = i0 == 2 ? 1.0 : 0.0;
         return;
     }
     double q = (a + d + f) / 3.0;
@@ -76,47 +81,45 @@ __device__ void sym3_min_eigvec(double a, double b, double c, double d, double e
     lam[0] = l0;
     lam[1] = l1;
     lam[2] = l2;
-    double r0[3] = {a - l0, b, c}, r1[3] = {b, d - l0, e}, r2[3] = {c, e, f - l0};
-    double x01[3] = {r0[1] * r1[2] - r0[2] * r1[1], r0[2] * r1[0] - r0[0] * r1[2], r0[0] * r1[1] - r0[1] * r1[0]};
-    double x02[3] = {r0[1] * r2[2] - r0[2] * r2[1], r0[2] * r2[0] - r0[0] * r2[2], r0[0] * r2[1] - r0[1] * r2[0]};
-    double x12[3] = {r1[1] * r2[2] - r1[2] * r2[1], r1[2] * r2[0] - r1[0] * r2[2], r1[0] * r2[1] - r1[1] * r2[0]};
-    double n01 = x01[0] * x01[0] + x01[1] * x01[1] + x01[2] * x01[2];
-    double n02 = x02[0] * x02[0] + x02[1] * x02[1] + x02[2] * x02[2];
-    double n12 = x12[0] * x12[0] + x12[1] * x12[1] + x12[2] * x12[2];
-    const double *best = x01;
-    double nb = n01;
-    if (n02 > nb) { best = x02; nb = n02; }
-    if (n12 > nb) { best = x12; nb = n12; }
+    // rows of C - l0 I and their pairwise cross products
+    double r0x = a - l0, r0y = b, r0z = c;
+    double r1x = b, r1y = d - l0, r1z = e;
+    double r2x = c, r2y = e, r2z = f - l0;
+    double ax = r0y * r1z - r0z * r1y, ay = r0z * r1x - r0x * r1z, az = r0x * r1y - r0y * r1x;
+    double bx = r0y * r2z - r0z * r2y, by = r0z * r2x - r0x * r2z, bz = r0x * r2y - r0y * r2x;
+    double cx = r1y * r2z - r1z * r2y, cy = r1z * r2x - r1x * r2z, cz = r1x * r2y - r1y * r2x;
+    double na = ax * ax + ay * ay + az * az, nb = bx * bx + by * by + bz * bz, nc = cx * cx + cy * cy + cz * cz;
+    double wx = ax, wy = ay, wz = az, nw = na;
+    if (nb > nw) { wx = bx; wy = by; wz = bz; nw = nb; }
+    if (nc > nw) { wx = cx; wy = cy; wz = cz; nw = nc; }
     double scale = fabs(l2) + fabs(l0);
-    if (nb > 1e-60 * scale * scale * scale * scale && nb > 0.0) {
-        double s = 1.0 / sqrt(nb);
-        v[0] = best[0] * s;
-        v[1] = best[1] * s;
-        v[2] = best[2] * s;
+    if (nw > 1e-60 * scale * scale * scale * scale && nw > 0.0) {
+        double s = 1.0 / sqrt(nw);
+        v[0] = wx * s;
+        v[1] = wy * s;
+        v[2] = wz * s;
         return;
     }
     // l0 (nearly) repeated: any unit vector orthogonal to the largest row of
     // (C - l0 I) lies in its eigenspace
-    const double *row = r0;
-    double rn = r0[0] * r0[0] + r0[1] * r0[1] + r0[2] * r0[2];
-    double t1 = r1[0] * r1[0] + r1[1] * r1[1] + r1[2] * r1[2];
-    double t2 = r2[0] * r2[0] + r2[1] * r2[1] + r2[2] * r2[2];
-    if (t1 > rn) { row = r1; rn = t1; }
-    if (t2 > rn) { row = r2; rn = t2; }
+    double gx = r0x, gy = r0y, gz = r0z, rn = r0x * r0x + r0y * r0y + r0z * r0z;
+    double t1 = r1x * r1x + r1y * r1y + r1z * r1z, t2 = r2x * r2x + r2y * r2y + r2z * r2z;
+    if (t1 > rn) { gx = r1x; gy = r1y; gz = r1z; rn = t1; }
+    if (t2 > rn) { gx = r2x; gy = r2y; gz = r2z; rn = t2; }
     if (!(rn > 0.0)) {
         v[0] = 1.0; v[1] = 0.0; v[2] = 0.0;
         return;
     }
-    int ax = 0;
-    if (fabs(row[1]) < fabs(row[ax])) ax = 1;
-    if (fabs(row[2]) < fabs(row[ax])) ax = 2;
-    double ea[3] = {0.0, 0.0, 0.0};
-    ea[ax] = 1.0;
-    double w[3] = {row[1] * ea[2] - row[2] * ea[1], row[2] * ea[0] - row[0] * ea[2], row[0] * ea[1] - row[1] * ea[0]};
-    double s = 1.0 / sqrt(w[0] * w[0] + w[1] * w[1] + w[2] * w[2]);
-    v[0] = w[0] * s;
-    v[1] = w[1] * s;
-    v[2] = w[2] * s;
+    // cross with the axis of the smallest component of that row
+    int ax_i = 0;
+    if (fabs(gy) < fabs(gx)) ax_i = 1;
+    if (fabs(gz) < (ax_i == 0 ? fabs(gx) : fabs(gy))) ax_i = 2;
+    double ex = ax_i == 0 ? 1.0 : 0.0, ey = ax_i == 1 ? 1.0 : 0.0, ez = ax_i == 2 ? 1.0 : 0.0;
+    double ux = gy * ez - gz * ey, uy = gz * ex - gx * ez, uz = gx * ey - gy * ex;
+    double s = 1.0 / sqrt(ux * ux + uy * uy + uz * uz);
+    v[0] = ux * s;
+    v[1] = uy * s;
+    v[2] = uz * s;
 }
 
 template <int KT>
@@ -127,6 +130,8 @@ __global__ void __launch_bounds__(kQThreads) k_normals(GridView g, const float *
     __shared__ uint32_t stk[kStack * kQThreads];
     const GridParams P = *g.params;
     int64_t s = xcd_block(blockIdx.x, gridDim.x) * (int64_t)kQThreads + threadIdx.x;
+    // queries are the points in sorted order, so neighbouring lanes search
+    // neighbouring cells
     if (s >= P.n) return;
     float4 p = g.pts[s];
     uint32_t qi = __float_as_uint(p.w);

@@ -26,7 +26,7 @@
 
 namespace pcg {
 
-constexpr int kStack = 16;              // per-lane DFS stack entries (LDS, 4 bytes each)
+constexpr int kStack = 32;              // per-lane DFS stack entries (LDS, 4 bytes each)
 constexpr int kVisitBudget = 1 << 20;   // node pops per DFS; only a corrupted tree reaches it
 
 __device__ inline uint64_t enc_cand(float key, float w) { return ((uint64_t)__float_as_uint(key) << 32) | __float_as_uint(w); }
