@@ -5,12 +5,14 @@ target (estimate_normals), then point-to-plane ICP (target grid, the fixed
 iteration loop, final statistics pass).  Inputs are resident in HBM before
 the timed region; the timed region is bracketed by device synchronisation.
 
-    python bench.py [--steps K] [--warmup W] [--workload room|street|sphere]
+    python bench.py [--steps K] [--warmup W] [--workload room|street|sphere|batch]
 
 Prints one JSON line.  value = pairs/s; the loop-only Mpt*iter/s, the
 roofline of the dominant kernel (the per-iteration correspondence +
 accumulation kernel, timed with HIP events on the library's stream) and a
-CPU-oracle baseline are reported alongside.
+CPU-oracle baseline are reported alongside.  The batch workload runs 256
+uneven pairs per step through the batched entry points (one step = normals
+of every target + ICP of every pair).
 """
 from __future__ import annotations
 
@@ -27,7 +29,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "ICP pairs/s + Mpt·iter/s at ≤1e-5 rad pose error; learned-init vs plain"
-WORKLOADS = {"sphere": 0, "room": 1, "street": 2}
+WORKLOADS = {"sphere": 0, "room": 1, "street": 2, "batch": 3}
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per source point per ICP iteration: source xyz (12),
 # matched target xyz + normal (24), cell lookup (4)
@@ -148,6 +150,131 @@ def cpu_baseline(w, budget_s):
             "mpt_iter_per_s": w.n * w.iters * pairs / loop_s / 1e6}
 
 
+def cpu_baseline_batch(b, budget_s):
+    """The CPU oracle on the batch's pairs in order (normals + ICP each),
+    until about budget_s seconds have passed."""
+    import oracle
+    oracle.build(force=False)
+    t0 = time.perf_counter()
+    pairs, pts_iter, loop_s = 0, 0, 0.0
+    for w in b.pairs:
+        nrm, _, _ = oracle.normals(w.target, w.k, (0.0, 0.0, 0.0), method="kdtree")
+        t1 = time.perf_counter()
+        oracle.icp(w.source, w.target, nrm.astype(np.float32), None, float(np.float32(w.d_max)), w.iters)
+        loop_s += time.perf_counter() - t1
+        pairs += 1
+        pts_iter += w.n * w.iters
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    el = time.perf_counter() - t0
+    return {"value": pairs / el, "unit": "pairs/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"the first {pairs} of {b.n_pairs} pairs (normals + ICP incl. kd-tree builds), "
+                      f"{el:.1f} s wall",
+            "mpt_iter_per_s": pts_iter / loop_s / 1e6}
+
+
+def bench_batch(args):
+    """Batched workload: all pairs per step through the batched entry points."""
+    import torch
+    from gen import batch_workload
+    from paper_1807_00399_amd import pcgpu
+    dev = torch.device("cuda:0")
+    b = batch_workload(3)
+    off = b.offsets
+    kc = b.param("k").astype(np.int32)
+    dm = b.param("d_max").astype(np.float32)
+    it = b.param("iters").astype(np.int32)
+    src = torch.from_numpy(b.source).to(dev)
+    tgt = torch.from_numpy(b.target).to(dev)
+    m = b.n_pairs
+    T = torch.empty((m, 4, 4), dtype=torch.float64, device=dev)
+    stats = torch.zeros(24 * m, dtype=torch.uint8, device=dev)
+    ws_n = torch.empty(pcgpu.lib.estimate_normals_batched_workspace_size(m, off.ctypes.data), dtype=torch.uint8,
+                       device=dev)
+    ws_i = torch.empty(pcgpu.lib.icp_point_to_plane_batched_workspace_size(m, off.ctypes.data, off.ctypes.data,
+                                                                            int(it.max())),
+                       dtype=torch.uint8, device=dev)
+
+    def step():
+        nrm, _ = pcgpu.estimate_normals_batched(tgt, off, kc, curvature=False, workspace=ws_n)
+        pcgpu.icp_point_to_plane_batched(src, off, tgt, nrm, off, None, dm, it, workspace=ws_i, out_T=T,
+                                         out_stats=stats, read_stats=False)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st = pcgpu.decode_stats_batched(stats)
+
+    # per-iteration accumulate kernel: events recorded by the library
+    iters_max = int(it.max())
+    ev = HipEvents(iters_max)
+    pcgpu.lib.pc_set_kernel_timer(ev.beg, ev.end, iters_max)
+    kern, loop_ms = [], []
+    for _ in range(3):
+        step()
+        torch.cuda.synchronize()
+        cnt = pcgpu.lib.pc_kernel_timer_count()
+        kern.append([ev.elapsed_ms(i) for i in range(cnt)])
+        loop_ms.append(ev.span_ms(0, cnt - 1))
+    pcgpu.lib.pc_set_kernel_timer(None, None, 0)
+    kern = np.median(np.array(kern), axis=0) * 1e-3
+    # source points processed by launch i: pairs still iterating
+    ran = np.array([r["iterations_run"] for r in st])
+    sizes = np.diff(off)
+    active = np.array([int(sizes[ran > i].sum()) for i in range(len(kern))])
+    achieved = ICP_BYTES_PER_POINT * active.sum() / kern.sum() / 1e9
+    pts_iter = int((sizes * ran).sum())
+
+    # the same pairs one call each (single-pair entry points), for comparison
+    seq_pairs = min(m, 64)
+    srcs = [src[off[j]:off[j + 1]] for j in range(seq_pairs)]
+    tgts = [tgt[off[j]:off[j + 1]] for j in range(seq_pairs)]
+    for rep in range(2):                       # the first round grows the workspace
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for j in range(seq_pairs):
+            nrm, _ = pcgpu.estimate_normals(tgts[j], int(kc[j]), curvature=False)
+            pcgpu.icp_point_to_plane(srcs[j], tgts[j], nrm, None, float(dm[j]), int(it[j]), read_stats=False)
+        torch.cuda.synchronize()
+        seq_el = time.perf_counter() - t1
+
+    out = {
+        "metric": METRIC,
+        "value": m * args.steps / el,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * el / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{b.name}: {m} uneven pairs per step, {b.n} points per side, "
+                               f"sphere+plane (k=10, d_max 0.1, 20 iterations) or room (k=16, d_max 0.05, "
+                               f"30 iterations) pairs",
+                   "pairs": m, "points_per_side": b.n},
+        "mpt_iter_per_s": pts_iter / (float(np.median(loop_ms)) * 1e-3) / 1e6,
+        "loop_ms": float(np.median(loop_ms)),
+        "single_call_pairs_per_s": seq_pairs / seq_el,
+        "icp_status_counts": {str(k): int(v) for k, v in zip(*np.unique([r["status"] for r in st],
+                                                                        return_counts=True))},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profiles("icp_accum", "batch"),
+                     "kernel": "k_icp_accum", "avg_kernel_us": float(kern.mean()) * 1e6,
+                     "algorithmic_bytes_per_launch": float(ICP_BYTES_PER_POINT * active.mean())},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_batch(b, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -162,6 +289,9 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if args.copy_probe:
         copy_probe()
+        return
+    if args.workload == "batch":
+        bench_batch(args)
         return
     dev = torch.device("cuda:0")
     w = make_workload(WORKLOADS[args.workload])

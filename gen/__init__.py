@@ -8,6 +8,8 @@ oracle and the GPU path can consume it without sharing any method code.
 from .scenes import (  # noqa: F401
     CONFIGS,
     Workload,
+    BatchWorkload,
+    batch_workload,
     make_workload,
     random_rigid,
     apply_rigid,

@@ -89,7 +89,7 @@ def _slab_hits(d: np.ndarray, lo: np.ndarray, hi: np.ndarray) -> np.ndarray:
 
 
 def room_scan(rng: np.random.Generator, width: int = 640, height: int = 480,
-              n_boxes: int = 20, depth_noise: float = 0.003) -> np.ndarray:
+              n_boxes: int = 20, depth_noise: float = 0.003, pixels: np.ndarray | None = None) -> np.ndarray:
     """Depth-camera frame of a room with boxes, back-projected to 3-D.
 
     Room [-3,3]x[-1.5,1.5]x[-0.5,5.5] in camera coordinates (x right, y down,
@@ -98,13 +98,17 @@ def room_scan(rng: np.random.Generator, width: int = 640, height: int = 480,
     the origin (fx=fy=525, cx=319.5, cy=239.5 at 640x480, scaled for other
     sizes) casts one ray per pixel; depth gets N(0, (depth_noise*z^2)^2)
     noise.  Every ray hits, so the result has exactly width*height points,
-    float32, pixel raster order.
+    float32, pixel raster order.  With ``pixels`` (raster indices), only those
+    pixels are cast, in the given order.
     """
     s = width / 640.0
     fx = fy = 525.0 * s
     cx, cy = (width - 1) / 2.0, (height - 1) / 2.0
-    u, v = np.meshgrid(np.arange(width, dtype=np.float64), np.arange(height, dtype=np.float64))
-    d = np.column_stack([((u - cx) / fx).ravel(), ((v - cy) / fy).ravel(), np.ones(width * height)])
+    if pixels is None:
+        pixels = np.arange(width * height)
+    pixels = np.asarray(pixels, dtype=np.int64)
+    u, v = (pixels % width).astype(np.float64), (pixels // width).astype(np.float64)
+    d = np.column_stack([(u - cx) / fx, (v - cy) / fy, np.ones(len(pixels))])
     room_lo = np.array([-3.0, -1.5, -0.5])
     room_hi = np.array([3.0, 1.5, 5.5])
     with np.errstate(divide="ignore"):
@@ -214,6 +218,82 @@ CONFIGS = {
     1: dict(name="room_vga_307200", k=16, d_max=0.05, iters=30, angle=15.0, t=0.1),
     2: dict(name="street_lidar_2097152", k=16, d_max=1.0, iters=40, angle=5.0, t=0.5),
 }
+
+
+@dataclasses.dataclass
+class BatchWorkload:
+    """Many independent pairs of uneven sizes, packed back to back."""
+    name: str
+    pairs: list                 # list of Workload
+
+    @property
+    def n_pairs(self) -> int:
+        return len(self.pairs)
+
+    def _pack(self, attr):
+        return np.ascontiguousarray(np.vstack([getattr(w, attr) for w in self.pairs]).astype(np.float32))
+
+    @property
+    def source(self) -> np.ndarray:
+        return self._pack("source")
+
+    @property
+    def target(self) -> np.ndarray:
+        return self._pack("target")
+
+    @property
+    def offsets(self) -> np.ndarray:
+        """(n_pairs + 1) int64 offsets, shared by sources and targets."""
+        return np.concatenate([[0], np.cumsum([w.n for w in self.pairs])]).astype(np.int64)
+
+    @property
+    def n(self) -> int:
+        return int(sum(w.n for w in self.pairs))
+
+    def param(self, attr) -> np.ndarray:
+        return np.array([getattr(w, attr) for w in self.pairs])
+
+
+# parent configurations of the batched workload: sphere + plane, room
+BATCH_PARENTS = {0: dict(k=10, d_max=0.1, iters=20, t=0.05), 1: dict(k=16, d_max=0.05, iters=30, t=0.1)}
+BATCH_CONFIG = dict(name="uneven_pairs", n_pairs=256, n_lo=5_000, n_hi=200_000, angle=(5.0, 20.0),
+                    small_n_pairs=12, small_n_lo=300, small_n_hi=3_000)
+
+
+def batch_workload(config: int = 3, size: str = "full", n_pairs: int | None = None) -> BatchWorkload:
+    """Workload 3: uneven pairs.  Pair j (generator rng_for(3, j)) is either a
+    sphere + plane cloud or a new random room scan, each with probability
+    1/2; its size is round(exp U(ln n_lo, ln n_hi)) points (rooms: that many
+    of the frame's pixels, drawn without replacement, kept in raster order);
+    target = T * source with a rotation angle U(5, 20) degrees and the
+    parent's translation length; k, d_max and the iteration count come from
+    the parent.  ``size="small"`` uses 12 pairs of 300-3000 points (rooms at
+    160x120) for tests the oracle finishes quickly."""
+    if config != 3:
+        raise ValueError(f"unknown batched workload {config}")
+    c = BATCH_CONFIG
+    full = size == "full"
+    m = n_pairs if n_pairs is not None else (c["n_pairs"] if full else c["small_n_pairs"])
+    lo, hi = (c["n_lo"], c["n_hi"]) if full else (c["small_n_lo"], c["small_n_hi"])
+    width, height = (640, 480) if full else (160, 120)
+    pairs = []
+    for j in range(m):
+        rng = rng_for(config, j)
+        kind = 0 if rng.random() < 0.5 else 1
+        n = int(round(math.exp(rng.uniform(math.log(lo), math.log(hi)))))
+        if kind == 0:
+            src = sphere_plane(rng, n)
+        else:
+            n = min(n, width * height)
+            pix = np.sort(rng.choice(width * height, size=n, replace=False))
+            src = room_scan(rng, width, height, pixels=pix)
+        par = BATCH_PARENTS[kind]
+        T = random_rigid(rng, rng.uniform(*c["angle"]), par["t"])
+        tgt = apply_rigid(T, src)
+        pairs.append(Workload(f"{c['name']}_{j}_{'sphere' if kind == 0 else 'room'}", src, tgt, T, par["k"],
+                              par["d_max"], par["iters"]))
+    name = f"{c['name']}_{m}" + ("" if full else "_small")
+    return BatchWorkload(name, pairs)
 
 
 def make_workload(config: int, pair: int = 0, size: str = "full") -> Workload:

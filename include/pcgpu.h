@@ -111,9 +111,10 @@ pc_status estimate_normals(const float *xyz, int64_t n, int k, const float viewp
  * distance and a fixed iteration count).
  *
  * T maps source to target (target ~ R * source + t), starting at init_T.
- * Each iteration: p'_i = R p_i + t (float32 copy of T), q_j = nearest target
- * point of p'_i; the pair is an inlier when |p'_i - q_j| <= max_corr_dist
- * and n_j != 0; r_i = (p'_i - q_j) . n_j, J_i = [p'_i x n_j, n_j];
+ * Each iteration: p'_i = R p_i + t, q_j = nearest target point of p'_i
+ * (squared distance in float64, ties to the lower target index); the pair
+ * is an inlier when |p'_i - q_j|^2 <= max_corr_dist^2 (float64) and
+ * n_j != 0; r_i = (p'_i - q_j) . n_j, J_i = [p'_i x n_j, n_j];
  * x = -(sum J^T J)^{-1} sum J^T r = (alpha, beta, gamma, tau) solved in
  * float64 by Cholesky; R <- Rz(gamma) Ry(beta) Rx(alpha) R,
  * t <- Rz Ry Rx t + tau in float64.  The loop stops after max_iters
@@ -133,6 +134,13 @@ pc_status estimate_normals(const float *xyz, int64_t n, int k, const float viewp
  *   out_T          16 float64 row-major (may alias init_T)
  *   out_stats      one pc_icp_stats (device), or NULL
  * When n_src or n_tgt is 0, out_T = init_T and status = PC_ICP_NO_INLIERS.
+ *
+ * On the device p'_i is formed in double-float arithmetic (float32 hi + lo
+ * pairs of the float64 pose, about 2^-44 relative); the nearest point and
+ * the d_max test are decided in float32 when an error bound proves the
+ * float64 decision equal, and re-decided in float64 otherwise.  The sums are
+ * compensated float32 (hi, lo) pairs merged in a fixed order, so the result
+ * does not depend on scheduling.
  * ---------------------------------------------------------------------- */
 typedef struct {
     int32_t status;          /* PC_ICP_*                          */
@@ -149,6 +157,49 @@ pc_status icp_point_to_plane(const float *src_xyz, int64_t n_src,
                              void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Batched forms: many clouds or pairs of uneven sizes in one call, each
+ * computed exactly as the single form would compute it alone.  Clouds are
+ * packed back to back; offsets (host, m + 1 entries, offsets[0] = 0,
+ * non-decreasing, total below 2^31) give cloud c as rows
+ * [offsets[c], offsets[c+1]) of the packed array.  The offsets and the
+ * per-item parameters are copied to the device during the call (so the
+ * host arrays may be freed on return); everything else is asynchronous.
+ * ---------------------------------------------------------------------- */
+
+/* estimate_normals on n_clouds clouds (neighbourhoods never cross clouds).
+ *   xyz            (offsets[n_clouds], 3) float32, packed clouds
+ *   offsets        (host) n_clouds + 1 int64
+ *   k              (host) n_clouds int32, 1 <= k[c] <= min(n_c, PCGPU_KMAX)
+ *                  (any value in range for an empty cloud)
+ *   viewpoint      (host) 3 floats, shared by all clouds
+ *   out_normals    (offsets[n_clouds], 3) float32, packed like xyz
+ *   out_curvature  (offsets[n_clouds]) float32, or NULL */
+size_t estimate_normals_batched_workspace_size(int n_clouds, const int64_t *offsets);
+pc_status estimate_normals_batched(int n_clouds, const float *xyz, const int64_t *offsets,
+                                   const int32_t *k, const float viewpoint[3],
+                                   float *out_normals, float *out_curvature,
+                                   void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* icp_point_to_plane on n_pairs independent pairs: pair p registers source
+ * rows [src_off[p], src_off[p+1]) to target rows [tgt_off[p], tgt_off[p+1])
+ * with its own pose, max_corr_dist[p] and max_iters[p]; conv_tol is shared.
+ *   src_off, tgt_off   (host) n_pairs + 1 int64
+ *   init_T             (n_pairs, 16) float64 row-major (device), or NULL
+ *   max_corr_dist      (host) n_pairs float32, finite, > 0
+ *   max_iters          (host) n_pairs int32, >= 0
+ *   out_T              (n_pairs, 16) float64 (device)
+ *   out_stats          n_pairs pc_icp_stats (device), or NULL
+ * The workspace size takes the largest max_iters of the batch. */
+size_t icp_point_to_plane_batched_workspace_size(int n_pairs, const int64_t *src_off,
+                                                 const int64_t *tgt_off, int max_iters_max);
+pc_status icp_point_to_plane_batched(int n_pairs, const float *src_xyz, const int64_t *src_off,
+                                     const float *tgt_xyz, const float *tgt_normals,
+                                     const int64_t *tgt_off, const double *init_T,
+                                     const float *max_corr_dist, const int32_t *max_iters,
+                                     double conv_tol, double *out_T, pc_icp_stats *out_stats,
+                                     void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Diagnostics
  * ---------------------------------------------------------------------- */
 /* Streams n_bytes (multiple of 16) from src to dst with one read and one
@@ -163,8 +214,9 @@ const double *icp_history(void *workspace, size_t workspace_bytes,
                           int64_t n_src, int64_t n_tgt, int max_iters);
 
 /* Registers caller-owned HIP events (created with timing enabled) that
-   icp_point_to_plane records on its stream immediately before and after the
-   correspondence/accumulation kernel of iteration i, for i < capacity.  Pass
+   icp_point_to_plane and icp_point_to_plane_batched record on their stream
+   immediately before and after the correspondence/accumulation kernel of
+   iteration i, for i < capacity.  Pass
    capacity 0 to stop.  pc_kernel_timer_count() returns how many pairs the
    last call recorded.  For measurement only; not thread-safe. */
 pc_status pc_set_kernel_timer(hipEvent_t *begin, hipEvent_t *end, int capacity);

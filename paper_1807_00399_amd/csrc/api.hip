@@ -2,6 +2,8 @@
 
 #include <math.h>
 
+#include <vector>
+
 #include "icp.h"
 
 using namespace pcg;
@@ -11,6 +13,20 @@ namespace {
 constexpr int64_t kMaxPoints = (int64_t)1 << 31;
 
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+// host offsets of m items: off[0] = 0, non-decreasing, total below kMaxPoints
+bool valid_offsets(const int64_t *off, int m)
+{
+    if (!off || m < 1 || off[0] != 0) return false;
+    for (int i = 0; i < m; i++)
+        if (off[i + 1] < off[i]) return false;
+    return off[m] < kMaxPoints;
+}
+
+bool upload(void *dst, const void *src, size_t bytes, hipStream_t s)
+{
+    return bytes == 0 || hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s) == hipSuccess;
+}
 
 __global__ void k_copy16(const uint4 *__restrict__ src, uint4 *__restrict__ dst, size_t n)
 {
@@ -38,7 +54,7 @@ size_t knn_search_workspace_size(int64_t n_ref, int64_t n_qry, int k)
     (void)n_qry;
     (void)k;
     if (n_ref < 0 || n_ref >= kMaxPoints) return 0;
-    return grid_bytes(n_ref);
+    return grid_bytes(n_ref, 1);
 }
 
 pc_status knn_search(const float *ref_xyz, int64_t n_ref, const float *qry_xyz, int64_t n_qry, int k,
@@ -53,8 +69,9 @@ pc_status knn_search(const float *ref_xyz, int64_t n_ref, const float *qry_xyz, 
     if (workspace_bytes < knn_search_workspace_size(n_ref, n_qry, k)) return PC_EWORKSPACE;
     Carver c(workspace, workspace_bytes);
     GridStore g;
-    grid_carve(c, n_ref, g);
+    grid_carve(c, n_ref, 1, g);
     if (!c.ok) return PC_EWORKSPACE;
+    if (grid_set_single_cloud(g, stream) != hipSuccess) return PC_EDEVICE;
     if (grid_build(g, ref_xyz, stream) != hipSuccess) return PC_EDEVICE;
     if (knn_run(g, qry_xyz, n_qry, k, out_idx, out_d2, stream) != hipSuccess) return PC_EDEVICE;
     return PC_OK;
@@ -64,7 +81,7 @@ size_t estimate_normals_workspace_size(int64_t n, int k)
 {
     (void)k;
     if (n < 0 || n >= kMaxPoints) return 0;
-    return grid_bytes(n);
+    return grid_bytes(n, 1);
 }
 
 pc_status estimate_normals(const float *xyz, int64_t n, int k, const float viewpoint[3], float *out_normals,
@@ -81,19 +98,99 @@ pc_status estimate_normals(const float *xyz, int64_t n, int k, const float viewp
     if (workspace_bytes < estimate_normals_workspace_size(n, k)) return PC_EWORKSPACE;
     Carver c(workspace, workspace_bytes);
     GridStore g;
-    grid_carve(c, n, g);
+    grid_carve(c, n, 1, g);
     if (!c.ok) return PC_EWORKSPACE;
+    if (grid_set_single_cloud(g, stream) != hipSuccess) return PC_EDEVICE;
     if (grid_build(g, xyz, stream) != hipSuccess) return PC_EDEVICE;
-    if (normals_run(g, xyz, k, viewpoint, out_normals, out_curvature, stream) != hipSuccess) return PC_EDEVICE;
+    if (normals_run(g, xyz, k, nullptr, viewpoint, out_normals, out_curvature, stream) != hipSuccess)
+        return PC_EDEVICE;
     return PC_OK;
 }
+
+namespace {
+
+// the batched normals carve: the grid, then the per-cloud k
+int32_t *carve_normals_batched(Carver &c, int n_clouds, const int64_t *offsets, GridStore &g)
+{
+    grid_carve(c, offsets[n_clouds], n_clouds, g);
+    return c.take<int32_t>(n_clouds);
+}
+
+}  // namespace
+
+size_t estimate_normals_batched_workspace_size(int n_clouds, const int64_t *offsets)
+{
+    if (n_clouds < 1 || !valid_offsets(offsets, n_clouds)) return 0;
+    Carver c(nullptr, ~(size_t)0 >> 1);
+    GridStore g;
+    carve_normals_batched(c, n_clouds, offsets, g);
+    return c.used();
+}
+
+pc_status estimate_normals_batched(int n_clouds, const float *xyz, const int64_t *offsets, const int32_t *k,
+                                   const float viewpoint[3], float *out_normals, float *out_curvature,
+                                   void *workspace, size_t workspace_bytes, hipStream_t stream)
+{
+    if (n_clouds < 1 || !valid_offsets(offsets, n_clouds) || !k || !viewpoint) return PC_EINVAL;
+    const int64_t n = offsets[n_clouds];
+    int k_max = 1;
+    for (int c = 0; c < n_clouds; c++) {
+        int64_t nc = offsets[c + 1] - offsets[c];
+        if (k[c] < 1 || k[c] > PCGPU_KMAX || (nc > 0 && k[c] > nc)) return PC_EINVAL;
+        k_max = k[c] > k_max ? k[c] : k_max;
+    }
+    if (!isfinite(viewpoint[0]) || !isfinite(viewpoint[1]) || !isfinite(viewpoint[2])) return PC_EINVAL;
+    if (n == 0) return PC_OK;
+    if (!xyz || !out_normals || !workspace) return PC_EINVAL;
+    if (!aligned(xyz, 4) || !aligned(out_normals, 4) || !aligned(out_curvature, 4) || !aligned(workspace, 256))
+        return PC_EINVAL;
+    if (workspace_bytes < estimate_normals_batched_workspace_size(n_clouds, offsets)) return PC_EWORKSPACE;
+    Carver c(workspace, workspace_bytes);
+    GridStore g;
+    int32_t *kc = carve_normals_batched(c, n_clouds, offsets, g);
+    if (!c.ok) return PC_EWORKSPACE;
+    if (!upload(g.off, offsets, sizeof(int64_t) * (n_clouds + 1), stream)) return PC_EDEVICE;
+    if (!upload(kc, k, sizeof(int32_t) * n_clouds, stream)) return PC_EDEVICE;
+    if (grid_build(g, xyz, stream) != hipSuccess) return PC_EDEVICE;
+    if (normals_run(g, xyz, k_max, kc, viewpoint, out_normals, out_curvature, stream) != hipSuccess)
+        return PC_EDEVICE;
+    return PC_OK;
+}
+
+namespace {
+
+// the single-pair carve, shared by the size query, the call and the history
+void carve_single(Carver &c, int64_t n_src, int64_t n_tgt, int max_iters, IcpStore &s)
+{
+    int64_t nblk = icp_blocks(n_src);
+    icp_carve(c, 1, n_src, n_tgt, nblk, icp_groups(nblk), max_iters, s);
+}
+
+// the batched carve: blocks and groups per pair from the host offsets
+void carve_batched(Carver &c, int n_pairs, const int64_t *src_off, const int64_t *tgt_off, int iters_max,
+                   IcpStore &s, std::vector<int32_t> *boff, std::vector<int32_t> *goff)
+{
+    int64_t nblk = 0, ngrp = 0;
+    if (boff) boff->assign(1, 0);
+    if (goff) goff->assign(1, 0);
+    for (int p = 0; p < n_pairs; p++) {
+        int64_t b = icp_blocks(src_off[p + 1] - src_off[p]);
+        nblk += b;
+        ngrp += icp_groups(b);
+        if (boff) boff->push_back((int32_t)nblk);
+        if (goff) goff->push_back((int32_t)ngrp);
+    }
+    icp_carve(c, n_pairs, src_off[n_pairs], tgt_off[n_pairs], nblk, ngrp, iters_max, s);
+}
+
+}  // namespace
 
 size_t icp_point_to_plane_workspace_size(int64_t n_src, int64_t n_tgt, int max_iters)
 {
     if (n_src < 0 || n_tgt < 0 || n_src >= kMaxPoints || n_tgt >= kMaxPoints || max_iters < 0) return 0;
     Carver c(nullptr, ~(size_t)0 >> 1);
     IcpStore s;
-    icp_carve(c, n_src, n_tgt, max_iters, s);
+    carve_single(c, n_src, n_tgt, max_iters, s);
     return c.used();
 }
 
@@ -113,10 +210,59 @@ pc_status icp_point_to_plane(const float *src_xyz, int64_t n_src, const float *t
     if (workspace_bytes < icp_point_to_plane_workspace_size(n_src, n_tgt, max_iters)) return PC_EWORKSPACE;
     Carver c(workspace, workspace_bytes);
     IcpStore s;
-    icp_carve(c, n_src, n_tgt, max_iters, s);
+    carve_single(c, n_src, n_tgt, max_iters, s);
     if (!c.ok) return PC_EWORKSPACE;
-    hipError_t e = icp_run(s, src_xyz, n_src, tgt_xyz, tgt_normals, n_tgt, init_T, max_corr_dist, max_iters,
-                           conv_tol, out_T, out_stats, stream);
+    if (icp_layout_single(s, n_src, n_tgt, max_corr_dist, max_iters, stream) != hipSuccess) return PC_EDEVICE;
+    hipError_t e = icp_run(s, src_xyz, n_src, tgt_xyz, tgt_normals, init_T, conv_tol, out_T, out_stats, stream);
+    return e == hipSuccess ? PC_OK : PC_EDEVICE;
+}
+
+size_t icp_point_to_plane_batched_workspace_size(int n_pairs, const int64_t *src_off, const int64_t *tgt_off,
+                                                 int max_iters_max)
+{
+    if (n_pairs < 1 || max_iters_max < 0 || !valid_offsets(src_off, n_pairs) || !valid_offsets(tgt_off, n_pairs))
+        return 0;
+    Carver c(nullptr, ~(size_t)0 >> 1);
+    IcpStore s;
+    carve_batched(c, n_pairs, src_off, tgt_off, max_iters_max, s, nullptr, nullptr);
+    return c.used();
+}
+
+pc_status icp_point_to_plane_batched(int n_pairs, const float *src_xyz, const int64_t *src_off,
+                                     const float *tgt_xyz, const float *tgt_normals, const int64_t *tgt_off,
+                                     const double *init_T, const float *max_corr_dist, const int32_t *max_iters,
+                                     double conv_tol, double *out_T, pc_icp_stats *out_stats, void *workspace,
+                                     size_t workspace_bytes, hipStream_t stream)
+{
+    if (n_pairs < 1 || !valid_offsets(src_off, n_pairs) || !valid_offsets(tgt_off, n_pairs)) return PC_EINVAL;
+    if (!max_corr_dist || !max_iters) return PC_EINVAL;
+    int iters_max = 0;
+    for (int p = 0; p < n_pairs; p++) {
+        if (max_iters[p] < 0 || !(max_corr_dist[p] > 0.f) || !isfinite(max_corr_dist[p])) return PC_EINVAL;
+        iters_max = max_iters[p] > iters_max ? max_iters[p] : iters_max;
+    }
+    if (!(conv_tol >= 0.0) || !isfinite(conv_tol)) return PC_EINVAL;
+    const int64_t ns = src_off[n_pairs], nt = tgt_off[n_pairs];
+    if (!out_T || !workspace) return PC_EINVAL;
+    if ((ns > 0 && !src_xyz) || (nt > 0 && (!tgt_xyz || !tgt_normals))) return PC_EINVAL;
+    if (!aligned(src_xyz, 4) || !aligned(tgt_xyz, 4) || !aligned(tgt_normals, 4) || !aligned(init_T, 8) ||
+        !aligned(out_T, 8) || !aligned(out_stats, 8) || !aligned(workspace, 256))
+        return PC_EINVAL;
+    if (workspace_bytes < icp_point_to_plane_batched_workspace_size(n_pairs, src_off, tgt_off, iters_max))
+        return PC_EWORKSPACE;
+    Carver c(workspace, workspace_bytes);
+    IcpStore s;
+    std::vector<int32_t> boff, goff;
+    carve_batched(c, n_pairs, src_off, tgt_off, iters_max, s, &boff, &goff);
+    if (!c.ok) return PC_EWORKSPACE;
+    if (!upload(s.soff, src_off, sizeof(int64_t) * (n_pairs + 1), stream) ||
+        !upload(s.grid.off, tgt_off, sizeof(int64_t) * (n_pairs + 1), stream) ||
+        !upload(s.boff, boff.data(), sizeof(int32_t) * (n_pairs + 1), stream) ||
+        !upload(s.goff, goff.data(), sizeof(int32_t) * (n_pairs + 1), stream) ||
+        !upload(s.dmax, max_corr_dist, sizeof(float) * n_pairs, stream) ||
+        !upload(s.maxit, max_iters, sizeof(int32_t) * n_pairs, stream))
+        return PC_EDEVICE;
+    hipError_t e = icp_run(s, src_xyz, ns, tgt_xyz, tgt_normals, init_T, conv_tol, out_T, out_stats, stream);
     return e == hipSuccess ? PC_OK : PC_EDEVICE;
 }
 
@@ -125,7 +271,7 @@ const double *icp_history(void *workspace, size_t workspace_bytes, int64_t n_src
     if (!workspace || workspace_bytes < icp_point_to_plane_workspace_size(n_src, n_tgt, max_iters)) return nullptr;
     Carver c(workspace, workspace_bytes);
     IcpStore s;
-    icp_carve(c, n_src, n_tgt, max_iters, s);
+    carve_single(c, n_src, n_tgt, max_iters, s);
     return s.hist;
 }
 

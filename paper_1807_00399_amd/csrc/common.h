@@ -16,23 +16,36 @@ namespace pcg {
 // its key is the level-0 Morton key shifted right by 3L, and level 16 is the
 // whole cube.  Points are stored sorted by level-0 Morton key, which makes
 // every cell at every level a contiguous run of the sorted array.
+//
+// One grid can hold a batch of clouds: the sort key is (cloud << 48 | Morton
+// key), so each cloud is a contiguous run of the sorted array with its own
+// cube, its own finest level and its own region of the cell hash.
 // ---------------------------------------------------------------------------
 constexpr int kBits = 16;                 // bits per axis at level 0
 constexpr int kLevels = kBits + 1;        // levels 0..16
 constexpr uint32_t kMaxCoord = (1u << kBits) - 1u;
 constexpr uint64_t kEmptyKey = ~0ull;     // empty hash slot
 
-struct GridParams {        // written on the device by the grid builder
+constexpr int kCloudShift = 48;           // cloud index position in sort keys
+
+struct GridParams {        // one per cloud, written on the device by the grid builder
     float ox, oy, oz;      // origin (cube corner)
     float inv_h0;          // 1 / level-0 cell width
     float h0;              // level-0 cell width
     float margin;          // absolute slack for cell-range tests (a few ulps of the extent)
-    int32_t n;             // points in the grid
-    int32_t lmin;          // finest level kept in the pyramid
-    int32_t level_count[kLevels];   // nodes per level (valid for L >= lmin)
-    int32_t level_off[kLevels];     // first node of each level in the node arrays
+    int32_t n;             // points of this cloud
+    int32_t base;          // its first position in the sorted arrays
+    int32_t lmin;          // finest level kept for this cloud
+    int32_t n_nodes;       // nodes of this cloud
+    uint32_t hash_base;    // first slot of its hash region
+    uint32_t hash_cap;     // slots of its hash region (at least twice its nodes)
+};
+
+struct GridLayout {        // whole grid, written on the device by the grid builder
+    int32_t level_count[kLevels];   // nodes per level, all clouds
+    int32_t level_off[kLevels];     // first node of each level in the node array
     int32_t n_nodes;       // total nodes
-    uint32_t hash_mask;    // hash capacity - 1 (capacity is a power of two)
+    uint32_t hash_slots;   // total hash slots in use
 };
 
 // Node header: start/count of its run in the sorted arrays, first child
@@ -60,9 +73,9 @@ struct HSlot {
 
 // Views of the workspace the grid lives in.
 struct GridView {
-    GridParams *params;
+    const GridParams *params;  // per cloud
     const float4 *pts;         // sorted points; .w = original index (bit pattern)
-    const uint64_t *keys;      // sorted level-0 Morton keys
+    const uint64_t *keys;      // sorted (cloud << 48 | level-0 Morton key)
     const Node *node;
     const HSlot *hash;
 };
@@ -100,32 +113,50 @@ __device__ inline uint64_t hash_key(int level, uint64_t cellkey)
     return ((uint64_t)level << 48) | cellkey;
 }
 
-__device__ inline uint32_t hash_slot(uint64_t k, uint32_t mask)
+// home slot of a key in a region of `cap` slots: the 64-bit splitmix64
+// finaliser, then its high 32 bits scaled to [0, cap) (no power-of-two size)
+__device__ inline uint32_t hash_slot(uint64_t k, uint32_t cap)
 {
-    // 64-bit finaliser (splitmix64)
     k ^= k >> 30;
     k *= 0xbf58476d1ce4e5b9ull;
     k ^= k >> 27;
     k *= 0x94d049bb133111ebull;
     k ^= k >> 31;
-    return (uint32_t)k & mask;
+    return (uint32_t)(((k >> 32) * (uint64_t)cap) >> 32);
 }
 
-// Node index of cell (level, cx, cy, cz), or -1 when the cell is empty.
-__device__ inline int32_t find_cell(const GridView &g, uint32_t mask, int level,
+__device__ inline uint32_t next_slot(uint32_t s, uint32_t cap) { return (s + 1 == cap) ? 0u : s + 1; }
+
+// Node index of cell (level, cx, cy, cz) of cloud P, or -1 when the cell is empty.
+__device__ inline int32_t find_cell(const GridView &g, const GridParams &P, int level,
                                     uint32_t cx, uint32_t cy, uint32_t cz)
 {
     uint64_t key = hash_key(level, morton3(cx, cy, cz));
-    uint32_t s = hash_slot(key, mask);
-    // the table is at most half full, so an empty slot ends every probe;
+    const HSlot *hs = g.hash + P.hash_base;
+    uint32_t s = hash_slot(key, P.hash_cap);
+    // the region is at most half full, so an empty slot ends every probe;
     // the bound only guards against a corrupted table
-    for (uint32_t it = 0; it <= mask; it++) {
-        HSlot e = g.hash[s];
+    for (uint32_t it = 0; it < P.hash_cap; it++) {
+        HSlot e = hs[s];
         if (e.key == key) return (int32_t)e.val;
         if (e.key == kEmptyKey) return -1;
-        s = (s + 1) & mask;
+        s = next_slot(s, P.hash_cap);
     }
     return -1;
+}
+
+__host__ __device__ inline int key_cloud(uint64_t key) { return (int)(key >> kCloudShift); }
+
+// cloud holding sorted position (or input index) i, for offsets off[0..nc]
+__device__ inline int cloud_of(const int64_t *off, int nc, int64_t i)
+{
+    int lo = 0, hi = nc - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= i) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
 }
 
 // float32 squared distance, the ranking key of the k-NN definition
@@ -221,7 +252,10 @@ struct Carver {
 // Grid storage inside a caller workspace and its builder (grid.hip)
 // ---------------------------------------------------------------------------
 struct GridStore {
-    GridParams *params;
+    GridParams *params;       // per cloud
+    GridLayout *layout;
+    int64_t *off;             // cloud offsets into the input (n_clouds + 1)
+    int32_t *clev;            // per cloud and level: slev histogram, then node counts
     uint64_t *keys, *keys_alt;
     uint32_t *idx, *idx_alt;
     float4 *pts;
@@ -231,10 +265,11 @@ struct GridStore {
     uint32_t *radix_hist;     // radix histograms / scan space
     uint32_t *radix_tot;      // per-digit totals of a pass
     int32_t *level_block;     // per block, per level: counts then offsets
-    uint32_t *bbox;           // 6 ordered-uint min/max
-    int64_t n;
+    uint32_t *bbox;           // per cloud: 6 ordered-uint min/max
+    int64_t n;                // points of all clouds
+    int n_clouds;
     int64_t max_nodes;
-    uint32_t hash_cap_max;
+    int64_t hash_slots_max;
     int nblk_sort, nblk_lvl;
     GridView view() const
     {
@@ -242,13 +277,17 @@ struct GridStore {
     }
 };
 
-size_t grid_bytes(int64_t n);
-void grid_carve(Carver &c, int64_t n, GridStore &g);
-// Builds the pyramid over xyz (n x 3 float32, device).  Asynchronous.
+size_t grid_bytes(int64_t n, int n_clouds);
+void grid_carve(Carver &c, int64_t n, int n_clouds, GridStore &g);
+// Builds the pyramid over xyz (n x 3 float32, device), clouds split by
+// g.off (device, n_clouds + 1 entries, written by the caller beforehand or
+// by grid_set_single_cloud).  Asynchronous.
 hipError_t grid_build(GridStore &g, const float *xyz, hipStream_t s);
+// Writes the offsets of a grid holding one cloud of g.n points.
+hipError_t grid_set_single_cloud(GridStore &g, hipStream_t s);
 // Gathers an (n x 3) per-point array into sorted order as float4 (w = 0).
 hipError_t grid_gather3(const GridStore &g, const float *src3, float4 *dst, hipStream_t s);
 
-int64_t max_pyramid_nodes(int64_t n);
+int64_t max_pyramid_nodes(int64_t n, int n_clouds);
 
 }  // namespace pcg

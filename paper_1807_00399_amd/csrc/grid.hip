@@ -25,8 +25,6 @@ constexpr int kSortItems = 16;
 constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kRadixBits = 8;
 constexpr int kRadix = 1 << kRadixBits;
-constexpr int kKeyBits = 3 * kBits;                      // 48
-constexpr int kPasses = (kKeyBits + kRadixBits - 1) / kRadixBits;  // 6
 constexpr int kLvlThreads = 256;
 constexpr int kLvlItems = 4;
 constexpr int kLvlTile = kLvlThreads * kLvlItems;
@@ -39,57 +37,81 @@ __device__ inline uint64_t lanemask_lt()
 }
 
 // ---------------------------------------------------------------- bbox
-__global__ void k_bbox_init(uint32_t *bb)
+// per cloud: bbox as ordered uints (min x,y,z then max x,y,z), slev histogram
+__global__ void k_cloud_init(int nc, uint32_t *__restrict__ bb, int32_t *__restrict__ clev)
 {
-    int t = threadIdx.x;
-    if (t < 3) bb[t] = 0xffffffffu;       // min (ordered)
-    else if (t < 6) bb[t] = 0u;          // max (ordered)
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nc * 6; i += gridDim.x * blockDim.x)
+        bb[i] = (i % 6) < 3 ? 0xffffffffu : 0u;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nc * kLevels; i += gridDim.x * blockDim.x)
+        clev[i] = 0;
 }
 
-__global__ void __launch_bounds__(256) k_bbox(const float *__restrict__ xyz, int64_t n, uint32_t *bb)
+__global__ void k_single_cloud(int64_t *off, int64_t n)
+{
+    off[0] = 0;
+    off[1] = n;
+}
+
+// Tiles of kBoxTile points; a tile is reduced separately for each cloud it
+// meets (clouds are contiguous, so usually one or two), one set of atomics
+// per (tile, cloud).
+constexpr int kBoxTile = 4096;
+
+__global__ void __launch_bounds__(256) k_bbox(const float *__restrict__ xyz, const int64_t *__restrict__ off,
+                                              int nc, uint32_t *bb)
 {
     __shared__ float red[4][6];
-    float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
-    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
-         i += (int64_t)gridDim.x * blockDim.x) {
-        for (int a = 0; a < 3; a++) {
-            float v = xyz[3 * i + a];
-            mn[a] = fminf(mn[a], v);
-            mx[a] = fmaxf(mx[a], v);
-        }
-    }
-    for (int off = 32; off > 0; off >>= 1)
-        for (int a = 0; a < 3; a++) {
-            mn[a] = fminf(mn[a], __shfl_xor(mn[a], off));
-            mx[a] = fmaxf(mx[a], __shfl_xor(mx[a], off));
-        }
-    int w = threadIdx.x >> 6;
-    if (__lane_id() == 0)
-        for (int a = 0; a < 3; a++) {
-            red[w][a] = mn[a];
-            red[w][3 + a] = mx[a];
-        }
-    __syncthreads();
-    // one set of atomics per block
-    if (threadIdx.x < 6) {
-        int a = threadIdx.x;
-        float v = red[0][a];
-        for (int x = 1; x < 4; x++) v = a < 3 ? fminf(v, red[x][a]) : fmaxf(v, red[x][a]);
-        bool finite = a < 3 ? v < INFINITY : v > -INFINITY;
-        if (finite) {
-            if (a < 3) atomicMin(&bb[a], f2ord(v));
-            else atomicMax(&bb[a], f2ord(v));
+    const int64_t n = off[nc];
+    for (int64_t t0 = (int64_t)blockIdx.x * kBoxTile; t0 < n; t0 += (int64_t)gridDim.x * kBoxTile) {
+        int64_t t1 = t0 + kBoxTile < n ? t0 + kBoxTile : n;
+        int c0 = cloud_of(off, nc, t0), c1 = cloud_of(off, nc, t1 - 1);
+        for (int c = c0; c <= c1; c++) {
+            int64_t a = off[c] > t0 ? off[c] : t0, b = off[c + 1] < t1 ? off[c + 1] : t1;
+            float mn[3] = {INFINITY, INFINITY, INFINITY}, mx[3] = {-INFINITY, -INFINITY, -INFINITY};
+            for (int64_t i = a + threadIdx.x; i < b; i += blockDim.x)
+                for (int k = 0; k < 3; k++) {
+                    float v = xyz[3 * i + k];
+                    mn[k] = fminf(mn[k], v);
+                    mx[k] = fmaxf(mx[k], v);
+                }
+            for (int o = 32; o > 0; o >>= 1)
+                for (int k = 0; k < 3; k++) {
+                    mn[k] = fminf(mn[k], __shfl_xor(mn[k], o));
+                    mx[k] = fmaxf(mx[k], __shfl_xor(mx[k], o));
+                }
+            int w = threadIdx.x >> 6;
+            if (__lane_id() == 0)
+                for (int k = 0; k < 3; k++) {
+                    red[w][k] = mn[k];
+                    red[w][3 + k] = mx[k];
+                }
+            __syncthreads();
+            if (threadIdx.x < 6) {
+                int k = threadIdx.x;
+                float v = red[0][k];
+                for (int x = 1; x < 4; x++) v = k < 3 ? fminf(v, red[x][k]) : fmaxf(v, red[x][k]);
+                bool finite = k < 3 ? v < INFINITY : v > -INFINITY;
+                if (finite) {
+                    if (k < 3) atomicMin(&bb[6 * c + k], f2ord(v));
+                    else atomicMax(&bb[6 * c + k], f2ord(v));
+                }
+            }
+            __syncthreads();
         }
     }
 }
 
-__global__ void k_params(uint32_t *bb, GridParams *P, int64_t n)
+__global__ void k_params(const uint32_t *__restrict__ bb, const int64_t *__restrict__ off, int nc,
+                         GridParams *__restrict__ P)
 {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    int64_t n = off[c + 1] - off[c];
     float lo[3], hi[3];
     float ext = 0.f, mag = 0.f;
     for (int a = 0; a < 3; a++) {
-        lo[a] = ord2f(bb[a]);
-        hi[a] = ord2f(bb[3 + a]);
+        lo[a] = ord2f(bb[6 * c + a]);
+        hi[a] = ord2f(bb[6 * c + 3 + a]);
         if (n == 0) lo[a] = hi[a] = 0.f;
         ext = fmaxf(ext, hi[a] - lo[a]);
         mag = fmaxf(mag, fmaxf(fabsf(lo[a]), fabsf(hi[a])));
@@ -97,30 +119,34 @@ __global__ void k_params(uint32_t *bb, GridParams *P, int64_t n)
     if (!(ext > 0.f)) ext = 1.0f;
     // cube side: a little larger than the extent so the top face bins below 2^16
     float side = ext * (1.0f + 1.0f / 1024.0f) + mag * 1e-6f + 1e-30f;
-    P->ox = lo[0];
-    P->oy = lo[1];
-    P->oz = lo[2];
-    P->inv_h0 = (float)(1u << kBits) / side;
-    P->h0 = side / (float)(1u << kBits);
-    P->margin = (mag + side) * (1.0f / (1 << 20));
-    P->n = (int32_t)n;
-    for (int l = 0; l < kLevels; l++) {
-        P->level_count[l] = 0;
-        P->level_off[l] = 0;
-    }
+    GridParams p;
+    p.ox = lo[0];
+    p.oy = lo[1];
+    p.oz = lo[2];
+    p.inv_h0 = (float)(1u << kBits) / side;
+    p.h0 = side / (float)(1u << kBits);
+    p.margin = (mag + side) * (1.0f / (1 << 20));
+    p.n = (int32_t)n;
+    p.base = (int32_t)off[c];
+    p.lmin = kLevels - 1;
+    p.n_nodes = 0;
+    p.hash_base = 0;
+    p.hash_cap = 0;
+    P[c] = p;
 }
 
 // ---------------------------------------------------------------- keys
-__global__ void k_keys(const float *__restrict__ xyz, int64_t n, const GridParams *__restrict__ P,
-                       uint64_t *__restrict__ keys)
+__global__ void k_keys(const float *__restrict__ xyz, const int64_t *__restrict__ off, int nc,
+                       const GridParams *__restrict__ P, uint64_t *__restrict__ keys)
 {
     int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    float ox = P->ox, oy = P->oy, oz = P->oz, inv = P->inv_h0;
-    uint32_t cx = cell0(xyz[3 * i + 0], ox, inv);
-    uint32_t cy = cell0(xyz[3 * i + 1], oy, inv);
-    uint32_t cz = cell0(xyz[3 * i + 2], oz, inv);
-    keys[i] = morton3(cx, cy, cz);
+    if (i >= off[nc]) return;
+    int c = nc > 1 ? cloud_of(off, nc, i) : 0;
+    const GridParams &p = P[c];
+    uint32_t cx = cell0(xyz[3 * i + 0], p.ox, p.inv_h0);
+    uint32_t cy = cell0(xyz[3 * i + 1], p.oy, p.inv_h0);
+    uint32_t cz = cell0(xyz[3 * i + 2], p.oz, p.inv_h0);
+    keys[i] = ((uint64_t)c << kCloudShift) | morton3(cx, cy, cz);
 }
 
 // ---------------------------------------------------------------- radix sort
@@ -247,43 +273,58 @@ __global__ void k_gather3(const float *__restrict__ src, const uint32_t *__restr
 }
 
 // ---------------------------------------------------------------- levels
-// slev[i] = highest level at which sorted point i opens a new cell
-// (kNoStart if it opens none); P->level_count[s] counts points with slev == s
+// slev[i] = highest level at which sorted point i opens a new cell of its
+// cloud (kNoStart if it opens none; the first point of a cloud opens its
+// root, level 16); clev[c * kLevels + s] counts cloud c's points with slev == s
 __global__ void k_slev(const uint64_t *__restrict__ keys, int64_t n, uint32_t *__restrict__ slev,
-                       GridParams *P)
+                       int32_t *__restrict__ clev)
 {
-    __shared__ uint32_t h[kLevels];
+    __shared__ int32_t h[kLevels];
     int t = threadIdx.x;
     if (t < kLevels) h[t] = 0;
     __syncthreads();
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + t;
+    int64_t i0 = (int64_t)blockIdx.x * blockDim.x;
+    int c0 = key_cloud(keys[i0 < n ? i0 : n - 1]);
+    int64_t i = i0 + t;
     if (i < n) {
+        uint64_t k = keys[i];
         uint32_t s;
         if (i == 0) {
             s = kLevels - 1;
         } else {
-            uint64_t x = keys[i] ^ keys[i - 1];
+            uint64_t x = k ^ keys[i - 1];
             s = x ? (uint32_t)((63 - __clzll(x)) / 3) : kNoStart;
+            if (s != kNoStart && s > (uint32_t)(kLevels - 1)) s = kLevels - 1;   // a new cloud
         }
         slev[i] = s;
-        if (s != kNoStart) atomicAdd(&h[s], 1u);
+        if (s != kNoStart) {
+            int c = key_cloud(k);
+            // the block's first cloud is counted in LDS, later ones directly
+            if (c == c0) atomicAdd(&h[s], 1);
+            else atomicAdd(&clev[c * kLevels + s], 1);
+        }
     }
     __syncthreads();
-    if (t < kLevels && h[t]) atomicAdd(&P->level_count[t], (int)h[t]);
+    if (t < kLevels && h[t]) atomicAdd(&clev[c0 * kLevels + t], h[t]);
 }
 
-// turns the slev histogram into node counts per level, picks the finest
-// level such that the pyramid from there up has at most n nodes (so leaves
-// are as small as a node budget of one per point allows, also where the
-// density is far above the mean), lays out the node arrays and the hash size
-__global__ void k_levels(GridParams *P, int64_t n, uint32_t hash_cap_max)
+// Per cloud: node counts per level from the slev histogram, the finest level
+// (the finest such that the levels from there up hold at most n nodes, so
+// leaves are as small as a node budget of one per point allows, also where
+// the density is far above the mean), and the size of its hash region.
+// clev[c] becomes the cloud's node count per level (0 below its lmin).
+__global__ void k_cloud_levels(int nc, int32_t *__restrict__ clev, GridParams *__restrict__ P)
 {
+    int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nc) return;
+    int32_t *cl = clev + (int64_t)c * kLevels;
     int32_t cnt[kLevels];
     int32_t run = 0;
     for (int l = kLevels - 1; l >= 0; l--) {
-        run += P->level_count[l];
+        run += cl[l];
         cnt[l] = run;           // points opening a cell at level >= l = cells at level l
     }
+    int64_t n = P[c].n;
     int lmin = kLevels - 1;
     int64_t cum = 0;
     for (int l = kLevels - 1; l >= 0; l--) {
@@ -291,21 +332,76 @@ __global__ void k_levels(GridParams *P, int64_t n, uint32_t hash_cap_max)
         if (cum > (n > 1 ? n : 1)) break;
         lmin = l;
     }
-    int32_t off = 0;
+    int32_t nodes = 0;
     for (int l = 0; l < kLevels; l++) {
-        P->level_count[l] = (l >= lmin) ? cnt[l] : 0;
-        P->level_off[l] = off;
-        if (l >= lmin) off += cnt[l];
+        cl[l] = (l >= lmin && n > 0) ? cnt[l] : 0;
+        nodes += cl[l];
     }
-    P->lmin = lmin;
-    P->n_nodes = off;
-    uint32_t cap = 1024;
-    while (cap < 2u * (uint32_t)off && cap < hash_cap_max) cap <<= 1;
-    P->hash_mask = cap - 1;
+    P[c].lmin = lmin;
+    P[c].n_nodes = nodes;
+    P[c].hash_cap = (uint32_t)(2 * nodes > 64 ? 2 * nodes : 64);
+}
+
+// Whole-grid layout: nodes per level summed over clouds, level offsets, and
+// the hash regions of the clouds laid out one after another.
+__global__ void __launch_bounds__(1024) k_layout(int nc, const int32_t *__restrict__ clev,
+                                                 GridParams *__restrict__ P, GridLayout *__restrict__ L)
+{
+    __shared__ int32_t lsum[kLevels];
+    __shared__ uint32_t wsum[16];
+    __shared__ uint32_t carry;
+    int t = threadIdx.x, w = t >> 6, lane = __lane_id();
+    if (t < kLevels) lsum[t] = 0;
+    if (t == 0) carry = 0;
+    __syncthreads();
+    for (int c0 = 0; c0 < nc; c0 += 1024) {
+        int c = c0 + t;
+        // level sums
+        for (int l = 0; l < kLevels; l++) {
+            int32_t v = c < nc ? clev[(int64_t)c * kLevels + l] : 0;
+            for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+            if (lane == 0 && v) atomicAdd(&lsum[l], v);
+        }
+        // exclusive scan of hash region sizes
+        uint32_t v = c < nc ? P[c].hash_cap : 0u, x = v;
+        for (int o = 1; o < 64; o <<= 1) {
+            uint32_t y = __shfl_up(x, o);
+            if (lane >= o) x += y;
+        }
+        if (lane == 63) wsum[w] = x;
+        __syncthreads();
+        uint32_t before = carry;
+        for (int k = 0; k < w; k++) before += wsum[k];
+        if (c < nc) P[c].hash_base = before + x - v;
+        __syncthreads();
+        if (t == 0) {
+            uint32_t tot = 0;
+            for (int k = 0; k < 16; k++) tot += wsum[k];
+            carry += tot;
+        }
+        __syncthreads();
+    }
+    if (t == 0) {
+        int32_t off = 0;
+        for (int l = 0; l < kLevels; l++) {
+            L->level_count[l] = lsum[l];
+            L->level_off[l] = off;
+            off += lsum[l];
+        }
+        L->n_nodes = off;
+        L->hash_slots = carry;
+    }
+}
+
+__device__ inline int point_lmin(const GridParams *__restrict__ P, const uint64_t *__restrict__ keys, int64_t i,
+                                 int64_t n)
+{
+    return i < n ? P[key_cloud(keys[i])].lmin : kLevels;
 }
 
 // per tile of kLvlTile sorted points: number of cells each level opens
-__global__ void __launch_bounds__(kLvlThreads) k_level_count(const uint32_t *__restrict__ slev, int64_t n,
+__global__ void __launch_bounds__(kLvlThreads) k_level_count(const uint32_t *__restrict__ slev,
+                                                           const uint64_t *__restrict__ keys, int64_t n,
                                                            const GridParams *__restrict__ P,
                                                            int32_t *__restrict__ lb)
 {
@@ -313,15 +409,14 @@ __global__ void __launch_bounds__(kLvlThreads) k_level_count(const uint32_t *__r
     int t = threadIdx.x;
     if (t < kLevels) c[t] = 0;
     __syncthreads();
-    int lmin = P->lmin;
     int64_t base = (int64_t)blockIdx.x * kLvlTile;
     for (int r = 0; r < kLvlItems; r++) {
         int64_t i = base + r * kLvlThreads + t;
         uint32_t s = (i < n) ? slev[i] : kNoStart;
+        int lmin = (s != kNoStart) ? point_lmin(P, keys, i, n) : kLevels;
 #pragma unroll
         for (int l = 0; l < kLevels; l++) {
-            if (l < lmin) continue;
-            uint64_t b = __ballot(s != kNoStart && (int)s >= l);
+            uint64_t b = __ballot(s != kNoStart && (int)s >= l && l >= lmin);
             if (__lane_id() == 0 && b) atomicAdd(&c[l], __popcll(b));
         }
     }
@@ -350,8 +445,10 @@ __global__ void __launch_bounds__(1024) k_level_scan(int32_t *__restrict__ lb, i
 }
 
 // writes node starts, levels and first children
-__global__ void __launch_bounds__(kLvlThreads) k_level_scatter(const uint32_t *__restrict__ slev, int64_t n,
+__global__ void __launch_bounds__(kLvlThreads) k_level_scatter(const uint32_t *__restrict__ slev,
+                                                             const uint64_t *__restrict__ keys, int64_t n,
                                                              const GridParams *__restrict__ P,
+                                                             const GridLayout *__restrict__ L,
                                                              const int32_t *__restrict__ lb,
                                                              Node *__restrict__ nodes)
 {
@@ -359,7 +456,6 @@ __global__ void __launch_bounds__(kLvlThreads) k_level_scatter(const uint32_t *_
     __shared__ int32_t running[kLevels];
     __shared__ int32_t wtot[kLevels][W];
     int t = threadIdx.x, w = t >> 6;
-    int lmin = P->lmin;
     if (t < kLevels) running[t] = lb[(int64_t)blockIdx.x * kLevels + t];
     __syncthreads();
     int64_t base = (int64_t)blockIdx.x * kLvlTile;
@@ -367,22 +463,23 @@ __global__ void __launch_bounds__(kLvlThreads) k_level_scatter(const uint32_t *_
     for (int r = 0; r < kLvlItems; r++) {
         int64_t i = base + r * kLvlThreads + t;
         uint32_t s = (i < n) ? slev[i] : kNoStart;
+        int lmin = (s != kNoStart) ? point_lmin(P, keys, i, n) : kLevels;
         int32_t rank[kLevels];
 #pragma unroll
         for (int l = 0; l < kLevels; l++) {
-            bool f = l >= lmin && s != kNoStart && (int)s >= l;
+            bool f = s != kNoStart && (int)s >= l && l >= lmin;
             uint64_t b = __ballot(f);
             rank[l] = __popcll(b & lt);
-            if (__lane_id() == 0 && l >= lmin) wtot[l][w] = __popcll(b);
+            if (__lane_id() == 0) wtot[l][w] = __popcll(b);
         }
         __syncthreads();
         int32_t prev = -1;
 #pragma unroll
         for (int l = 0; l < kLevels; l++) {
-            bool f = l >= lmin && s != kNoStart && (int)s >= l;
+            bool f = s != kNoStart && (int)s >= l && l >= lmin;
             int32_t pos = running[l] + rank[l];
             for (int x = 0; x < w; x++) pos += wtot[l][x];
-            int32_t node = P->level_off[l] + pos;
+            int32_t node = L->level_off[l] + pos;
             if (f) {
                 NodeHdr h;
                 h.start = (uint32_t)i;
@@ -394,7 +491,7 @@ __global__ void __launch_bounds__(kLvlThreads) k_level_scatter(const uint32_t *_
             prev = node;
         }
         __syncthreads();
-        if (t < kLevels && t >= lmin) {
+        if (t < kLevels) {
             int32_t s2 = 0;
             for (int x = 0; x < W; x++) s2 += wtot[t][x];
             running[t] += s2;
@@ -403,60 +500,65 @@ __global__ void __launch_bounds__(kLvlThreads) k_level_scatter(const uint32_t *_
     }
 }
 
-__global__ void k_hash_clear(const GridParams *__restrict__ P, HSlot *__restrict__ hs)
+__global__ void k_hash_clear(const GridLayout *__restrict__ L, HSlot *__restrict__ hs, int64_t cap_max)
 {
-    uint32_t cap = P->hash_mask + 1;
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < cap; i += gridDim.x * blockDim.x)
+    int64_t cap = L->hash_slots < cap_max ? L->hash_slots : cap_max;
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < cap; i += (int64_t)gridDim.x * blockDim.x)
         hs[i].key = kEmptyKey;
 }
 
-// node counts, child counts, hash insertion
-__global__ void k_nodes_finish(const GridParams *__restrict__ P, const uint64_t *__restrict__ keys,
-                               Node *__restrict__ nodes, HSlot *__restrict__ hs)
+// node counts, child counts, hash insertion.  A node's run ends at the next
+// node of its level or at the end of its cloud; its children are the nodes
+// of the level below that start inside its run (at most 8, contiguous).
+__global__ void k_nodes_finish(const GridParams *__restrict__ P, const GridLayout *__restrict__ L,
+                               const uint64_t *__restrict__ keys, Node *__restrict__ nodes, HSlot *__restrict__ hs)
 {
-    int32_t total = P->n_nodes, n = P->n, lmin = P->lmin;
-    uint32_t mask = P->hash_mask;
+    int32_t total = L->n_nodes;
     for (int32_t m = blockIdx.x * blockDim.x + threadIdx.x; m < total; m += gridDim.x * blockDim.x) {
         // start, first_child and the level were written by the scatter pass
         // and are only read here; each thread writes its own node's counts
         uint32_t start = nodes[m].h.start;
         uint32_t meta = nodes[m].h.meta;
         int l = (int)(meta >> 8);
-        int32_t lend = P->level_off[l] + P->level_count[l];
-        uint32_t next_start = (m + 1 < lend) ? nodes[m + 1].h.start : (uint32_t)n;
-        nodes[m].h.count = next_start - start;
-        if (l > lmin) {
+        int c = key_cloud(keys[start]);
+        const GridParams &p = P[c];
+        uint32_t cend = (uint32_t)(p.base + p.n);
+        int32_t lend = L->level_off[l] + L->level_count[l];
+        uint32_t next_start = (m + 1 < lend) ? nodes[m + 1].h.start : cend;
+        uint32_t end = next_start < cend ? next_start : cend;
+        nodes[m].h.count = end - start;
+        if (l > p.lmin) {
             uint32_t fc = nodes[m].h.first_child;
-            uint32_t next_fc = (m + 1 < lend) ? nodes[m + 1].h.first_child
-                                              : (uint32_t)(P->level_off[l - 1] + P->level_count[l - 1]);
-            nodes[m].h.meta = meta | (next_fc - fc);
+            int32_t cend_lvl = L->level_off[l - 1] + L->level_count[l - 1];
+            uint32_t nc = 1;
+            while (nc < 8 && (int32_t)(fc + nc) < cend_lvl && nodes[fc + nc].h.start < end) nc++;
+            nodes[m].h.meta = meta | nc;
         }
-        uint64_t key = hash_key(l, keys[start] >> (3 * l));
-        uint32_t s = hash_slot(key, mask);
-        for (uint32_t it = 0; it <= mask; it++) {
-            unsigned long long prev = atomicCAS((unsigned long long *)&hs[s].key, (unsigned long long)kEmptyKey,
+        uint64_t key = hash_key(l, (keys[start] & ((1ull << kCloudShift) - 1)) >> (3 * l));
+        HSlot *region = hs + p.hash_base;
+        uint32_t s = hash_slot(key, p.hash_cap);
+        for (uint32_t it = 0; it < p.hash_cap; it++) {
+            unsigned long long prev = atomicCAS((unsigned long long *)&region[s].key, (unsigned long long)kEmptyKey,
                                                 (unsigned long long)key);
             if (prev == kEmptyKey) {
-                hs[s].val = (uint32_t)m;
+                region[s].val = (uint32_t)m;
                 break;
             }
-            s = (s + 1) & mask;
+            s = next_slot(s, p.hash_cap);
         }
     }
 }
 
 // tight boxes of the level-l nodes in level-0 cells: from their points'
-// cells at the finest level, from their children's boxes above it
-__global__ void k_node_boxes(const GridParams *__restrict__ P, int l, const uint64_t *__restrict__ keys,
-                             Node *__restrict__ nodes)
+// cells at their cloud's finest level, from their children's boxes above it
+__global__ void k_node_boxes(const GridParams *__restrict__ P, const GridLayout *__restrict__ L, int l,
+                             const uint64_t *__restrict__ keys, Node *__restrict__ nodes)
 {
-    int lmin = P->lmin;
-    if (l < lmin) return;
-    int32_t off = P->level_off[l], end = off + P->level_count[l];
+    int32_t off = L->level_off[l], end = off + L->level_count[l];
     for (int32_t m = off + blockIdx.x * blockDim.x + threadIdx.x; m < end; m += gridDim.x * blockDim.x) {
         NodeHdr h = nodes[m].h;
         uint32_t lx = 0xffffu, ly = 0xffffu, lz = 0xffffu, hx = 0, hy = 0, hz = 0;
-        if (l == lmin) {
+        if (l == P[key_cloud(keys[h.start])].lmin) {
             for (uint32_t j = h.start; j < h.start + h.count; j++) {
                 uint64_t k = keys[j];
                 uint32_t x = compact3(k), y = compact3(k >> 1), z = compact3(k >> 2);
@@ -482,29 +584,28 @@ inline int blocks_for(int64_t n, int t) { return (int)((n + t - 1) / t); }
 
 }  // namespace
 
-int64_t max_pyramid_nodes(int64_t n)
+int64_t max_pyramid_nodes(int64_t n, int n_clouds)
 {
-    // the kept levels hold at most max(n, 1) nodes in total
-    return (n > 1 ? n : 1) + 1;
+    // each cloud keeps at most max(n_c, 1) nodes
+    return n + n_clouds + 1;
 }
 
-static uint32_t hash_cap_for(int64_t nodes)
-{
-    uint64_t cap = 1024;
-    while (cap < 2ull * (uint64_t)nodes && cap < (1ull << 31)) cap <<= 1;
-    return (uint32_t)cap;
-}
-
-void grid_carve(Carver &c, int64_t n, GridStore &g)
+void grid_carve(Carver &c, int64_t n, int n_clouds, GridStore &g)
 {
     int64_t nn = n > 0 ? n : 1;
+    int nc = n_clouds > 0 ? n_clouds : 1;
     g.n = n;
+    g.n_clouds = nc;
     g.nblk_sort = (int)((nn + kSortTile - 1) / kSortTile);
     g.nblk_lvl = (int)((nn + kLvlTile - 1) / kLvlTile);
-    g.max_nodes = max_pyramid_nodes(nn);
-    g.hash_cap_max = hash_cap_for(g.max_nodes);
-    g.params = c.take<GridParams>(1);
-    g.bbox = c.take<uint32_t>(8);
+    g.max_nodes = max_pyramid_nodes(nn, nc);
+    // a cloud's region holds max(64, 2 x its nodes) slots
+    g.hash_slots_max = 2 * g.max_nodes + 64 * (int64_t)nc;
+    g.params = c.take<GridParams>(nc);
+    g.layout = c.take<GridLayout>(1);
+    g.off = c.take<int64_t>(nc + 1);
+    g.clev = c.take<int32_t>((size_t)nc * kLevels);
+    g.bbox = c.take<uint32_t>((size_t)nc * 6);
     g.keys = c.take<uint64_t>(nn);
     g.keys_alt = c.take<uint64_t>(nn);
     g.idx = c.take<uint32_t>(nn);
@@ -515,60 +616,72 @@ void grid_carve(Carver &c, int64_t n, GridStore &g)
     g.radix_tot = c.take<uint32_t>(kRadix);
     g.level_block = c.take<int32_t>((size_t)g.nblk_lvl * kLevels);
     g.node = c.take<Node>(g.max_nodes);
-    g.hash = c.take<HSlot>(g.hash_cap_max);
+    g.hash = c.take<HSlot>(g.hash_slots_max);
 }
 
-size_t grid_bytes(int64_t n)
+size_t grid_bytes(int64_t n, int n_clouds)
 {
     Carver c(nullptr, ~(size_t)0 >> 1);
     GridStore g;
-    grid_carve(c, n, g);
+    grid_carve(c, n, n_clouds, g);
     return c.used();
+}
+
+hipError_t grid_set_single_cloud(GridStore &g, hipStream_t s)
+{
+    k_single_cloud<<<1, 1, 0, s>>>(g.off, g.n);
+    return hipGetLastError();
 }
 
 hipError_t grid_build(GridStore &g, const float *xyz, hipStream_t s)
 {
     const int64_t n = g.n;
+    const int nc = g.n_clouds;
     const int T = 256;
-    k_bbox_init<<<1, 64, 0, s>>>(g.bbox);
-    int bb_blocks = blocks_for(n, T);
-    if (bb_blocks > 256) bb_blocks = 256;
+    int ib = blocks_for((int64_t)nc * kLevels, T);
+    k_cloud_init<<<ib < 1024 ? ib : 1024, T, 0, s>>>(nc, g.bbox, g.clev);
+    int bb_blocks = blocks_for(n, kBoxTile);
+    if (bb_blocks > 1024) bb_blocks = 1024;
     if (bb_blocks < 1) bb_blocks = 1;
-    k_bbox<<<bb_blocks, T, 0, s>>>(xyz, n, g.bbox);
-    k_params<<<1, 1, 0, s>>>(g.bbox, g.params, n);
+    k_bbox<<<bb_blocks, T, 0, s>>>(xyz, g.off, nc, g.bbox);
+    k_params<<<blocks_for(nc, T), T, 0, s>>>(g.bbox, g.off, nc, g.params);
     if (n > 0) {
-        k_keys<<<blocks_for(n, T), T, 0, s>>>(xyz, n, g.params, g.keys);
+        k_keys<<<blocks_for(n, T), T, 0, s>>>(xyz, g.off, nc, g.params, g.keys);
+        // a single cloud needs the 48 Morton bits only; a batch also sorts by cloud
+        const int passes = nc > 1 ? 8 : 6;
         uint64_t *ka = g.keys, *kb = g.keys_alt;
-        uint32_t *ia = nullptr, *ib = g.idx_alt;
-        for (int p = 0; p < kPasses; p++) {
+        uint32_t *ia = nullptr, *ib2 = g.idx_alt;
+        for (int p = 0; p < passes; p++) {
             int shift = p * kRadixBits;
             k_radix_hist<<<g.nblk_sort, kSortThreads, 0, s>>>(ka, n, shift, g.radix_hist);
             k_radix_colscan<<<kRadix / 4, 256, 0, s>>>(g.radix_hist, g.nblk_sort, g.radix_tot);
             k_radix_scatter<<<g.nblk_sort, kSortThreads, 0, s>>>(ka, ia, n, shift, g.radix_hist, g.radix_tot,
-                                                                 kb, ib);
+                                                                 kb, ib2);
             // ping-pong; with an even number of passes the result lands in keys/idx
             uint64_t *tk = ka; ka = kb; kb = tk;
-            if (p == 0) { ia = g.idx_alt; ib = g.idx; }
-            else { uint32_t *ti = ia; ia = ib; ib = ti; }
+            if (p == 0) { ia = g.idx_alt; ib2 = g.idx; }
+            else { uint32_t *ti = ia; ia = ib2; ib2 = ti; }
         }
-        static_assert(kPasses % 2 == 0, "sorted keys must end in the primary buffers");
         k_gather_pts<<<blocks_for(n, T), T, 0, s>>>(xyz, g.idx, n, g.pts);
-        k_slev<<<blocks_for(n, T), T, 0, s>>>(g.keys, n, g.slev, g.params);
+        k_slev<<<blocks_for(n, T), T, 0, s>>>(g.keys, n, g.slev, g.clev);
     }
-    k_levels<<<1, 1, 0, s>>>(g.params, n, g.hash_cap_max);
+    k_cloud_levels<<<blocks_for(nc, T), T, 0, s>>>(nc, g.clev, g.params);
+    k_layout<<<1, 1024, 0, s>>>(nc, g.clev, g.params, g.layout);
     if (n > 0) {
-        k_level_count<<<g.nblk_lvl, kLvlThreads, 0, s>>>(g.slev, n, g.params, g.level_block);
+        k_level_count<<<g.nblk_lvl, kLvlThreads, 0, s>>>(g.slev, g.keys, n, g.params, g.level_block);
         k_level_scan<<<1, 1024, 0, s>>>(g.level_block, g.nblk_lvl);
-        k_level_scatter<<<g.nblk_lvl, kLvlThreads, 0, s>>>(g.slev, n, g.params, g.level_block, g.node);
-        int hb = blocks_for(g.hash_cap_max, T);
+        k_level_scatter<<<g.nblk_lvl, kLvlThreads, 0, s>>>(g.slev, g.keys, n, g.params, g.layout, g.level_block,
+                                                           g.node);
+        int hb = blocks_for(g.hash_slots_max, T);
         if (hb > 4096) hb = 4096;
-        k_hash_clear<<<hb, T, 0, s>>>(g.params, g.hash);
+        k_hash_clear<<<hb, T, 0, s>>>(g.layout, g.hash, g.hash_slots_max);
         int nb = blocks_for(g.max_nodes, T);
         if (nb > 4096) nb = 4096;
-        k_nodes_finish<<<nb, T, 0, s>>>(g.params, g.keys, g.node, g.hash);
+        k_nodes_finish<<<nb, T, 0, s>>>(g.params, g.layout, g.keys, g.node, g.hash);
         int bxb = blocks_for(n, T);
         if (bxb > 2048) bxb = 2048;
-        for (int l = 0; l < kLevels; l++) k_node_boxes<<<bxb, T, 0, s>>>(g.params, l, g.keys, g.node);
+        for (int l = 0; l < kLevels; l++)
+            k_node_boxes<<<bxb, T, 0, s>>>(g.params, g.layout, l, g.keys, g.node);
     }
     return hipGetLastError();
 }

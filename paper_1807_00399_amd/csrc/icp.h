@@ -7,30 +7,48 @@ namespace pcg {
 
 struct IcpState;
 
+// One ICP call over np pairs (np = 1 for icp_point_to_plane).  Source points
+// of pair p are [soff[p], soff[p+1]) of the source array, target points are
+// the grid's cloud p.  Every block of the accumulate kernel belongs to one
+// pair: pair p owns blocks [boff[p], boff[p+1]) and reduction groups
+// [goff[p], goff[p+1]).
 struct IcpStore {
-    GridStore grid;     // pyramid over the target
+    GridStore grid;     // pyramid over the targets, one cloud per pair
     float4 *nrm;        // target normals in sorted order
     int2 *prev;         // per source point: previous match (sorted position, node) or -1
-    IcpState *st;       // pose and loop state
+    IcpState *st;       // per pair: pose and loop state
+    int64_t *soff;      // source offsets (np + 1)
+    int32_t *boff;      // block offsets (np + 1)
+    int32_t *goff;      // reduction group offsets (np + 1)
+    float *dmax;        // per pair: rejection distance
+    int32_t *maxit;     // per pair: iteration limit
     float2 *part;       // per block: compensated partial sums
     uint32_t *pcnt;     // per block: inlier counts
     float2 *gpart;      // per group of blocks: merged partial sums
     uint32_t *gcnt;     // per group of blocks: inlier counts
-    int ngrp;
-    double *hist;       // per iteration: increment, inliers, sum r^2
-    int nblk, ppt;
+    double *hist;       // per pair and iteration: increment, inliers, sum r^2
+    int hist_stride;    // doubles per pair in hist
+    int np, nblk, ngrp, iters_max;
 };
 
-void icp_carve(Carver &c, int64_t ns, int64_t nt, int max_iters, IcpStore &s);
-hipError_t icp_run(IcpStore &s, const float *src, int64_t ns, const float *tgt, const float *tgt_n, int64_t nt,
-                   const double *init_T, float dmax, int max_iters, double conv_tol, double *out_T,
-                   pc_icp_stats *out_stats, hipStream_t st);
+// blocks of the accumulate kernel for ns source points, groups for nblk blocks
+int64_t icp_blocks(int64_t ns);
+int64_t icp_groups(int64_t nblk);
+void icp_carve(Carver &c, int np, int64_t ns, int64_t nt, int64_t nblk, int64_t ngrp, int iters_max,
+               IcpStore &s);
+// device-side layout of a single pair (offsets, blocks, groups, parameters)
+hipError_t icp_layout_single(IcpStore &s, int64_t ns, int64_t nt, float dmax, int max_iters, hipStream_t st);
+// Runs iters_max passes (pairs stop at their own limit) plus the final
+// statistics pass.  The layout arrays must already be on the device.
+hipError_t icp_run(IcpStore &s, const float *src, int64_t ns, const float *tgt, const float *tgt_n,
+                   const double *init_T, double conv_tol, double *out_T, pc_icp_stats *out_stats, hipStream_t st);
 
 void icp_set_timer(hipEvent_t *b, hipEvent_t *e, int cap);
 int icp_timer_count();
 
 hipError_t knn_run(const GridStore &g, const float *qry, int64_t nq, int k, int32_t *oi, float *od, hipStream_t s);
-hipError_t normals_run(const GridStore &g, const float *xyz, int k, const float *vp, float *on, float *oc,
-                       hipStream_t s);
+// k_max: the largest k of any cloud; kc: per-cloud k (device), or null to use k_max for all
+hipError_t normals_run(const GridStore &g, const float *xyz, int k_max, const int32_t *kc, const float *vp,
+                       float *on, float *oc, hipStream_t s);
 
 }  // namespace pcg

@@ -176,15 +176,42 @@ __device__ inline void df_row(const float *h, const float *l, float px, float py
 
 namespace {
 
-__global__ void k_icp_setup(const double *__restrict__ init_T, IcpState *st)
+// Per pair: pose from init_T (identity when null) and loop state.  A pair
+// with no source or no target point starts stopped with NO_INLIERS.
+__global__ void k_icp_setup(const double *__restrict__ init_T, const int64_t *__restrict__ soff,
+                            const int64_t *__restrict__ toff, const int32_t *__restrict__ max_iters, int np,
+                            IcpState *__restrict__ st)
 {
-    for (int i = 0; i < 16; i++) st->T[i] = init_T ? init_T[i] : ((i % 5 == 0) ? 1.0 : 0.0);
-    split_pose(st);
-    st->status = PC_ICP_MAXITER;
-    st->iters = 0;
-    st->stop = 0;
-    st->inliers = 0;
-    st->sum_r2 = 0.0;
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= np) return;
+    IcpState *s = st + p;
+    for (int i = 0; i < 16; i++) s->T[i] = init_T ? init_T[16 * p + i] : ((i % 5 == 0) ? 1.0 : 0.0);
+    split_pose(s);
+    bool empty = soff[p + 1] == soff[p] || toff[p + 1] == toff[p];
+    s->status = empty ? PC_ICP_NO_INLIERS : PC_ICP_MAXITER;
+    s->iters = 0;
+    s->stop = (empty || max_iters[p] <= 0) ? 1 : 0;
+    s->inliers = 0;
+    s->sum_r2 = 0.0;
+}
+
+// One pair's layout, written on the device for single-pair calls: source and
+// target offsets, blocks and reduction groups, rejection distance and
+// iteration limit.
+__global__ void k_single_pair(int64_t ns, int64_t nt, int nblk, int ngrp, float dmax, int max_iters,
+                              int64_t *__restrict__ soff, int64_t *__restrict__ toff, int32_t *__restrict__ boff,
+                              int32_t *__restrict__ goff, float *__restrict__ dm, int32_t *__restrict__ mi)
+{
+    soff[0] = 0;
+    soff[1] = ns;
+    toff[0] = 0;
+    toff[1] = nt;
+    boff[0] = 0;
+    boff[1] = nblk;
+    goff[0] = 0;
+    goff[1] = ngrp;
+    dm[0] = dmax;
+    mi[0] = max_iters;
 }
 
 __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v)
@@ -193,17 +220,29 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v)
         p[i] = v;
 }
 
+// pair owning block b (or group b) for block offsets off[0..np]
+__device__ inline int pair_of(const int32_t *__restrict__ off, int np, int b)
+{
+    int lo = 0, hi = np - 1;
+    while (lo < hi) {
+        int mid = (lo + hi + 1) >> 1;
+        if (off[mid] <= b) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
 // Correspondences + linearised system.  One source point per lane: the
 // search is bound by memory latency, so parallelism comes from many lanes.
-// Each block writes its compensated partial sums; k_icp_reduce and the
-// finalize kernel merge them in block order, so the result does not depend
-// on scheduling (no atomics, no fences in the hot kernel).
-template <int PPT>
-__global__ void __launch_bounds__(kIcpThreads) PCG_ICP_ATTR k_icp_accum(GridView g, const float *__restrict__ src, int64_t ns,
-                                                         const float4 *__restrict__ nrm,
-                                                         int2 *__restrict__ prev, const IcpState *__restrict__ st,
-                                                         float dmax, int final_pass, float2 *__restrict__ part,
-                                                         uint32_t *__restrict__ pcnt, int nblk)
+// Every block belongs to one pair (its source points, its target cloud and
+// its pose).  Each block writes its compensated partial sums; k_icp_reduce
+// and the finalize kernel merge them in block order, so the result does not
+// depend on scheduling (no atomics, no fences in the hot kernel).
+__global__ void __launch_bounds__(kIcpThreads) PCG_ICP_ATTR
+k_icp_accum(GridView g, const float *__restrict__ src, const int64_t *__restrict__ soff,
+            const int32_t *__restrict__ boff, int np, const float4 *__restrict__ nrm, int2 *__restrict__ prev,
+            const IcpState *__restrict__ state, const float *__restrict__ dmaxv, int final_pass,
+            float2 *__restrict__ part, uint32_t *__restrict__ pcnt, int nblk)
 {
     // the DFS stack and, after the search, the reduction buffer share LDS
     constexpr int kHalf = kAcc / 2;                       // accumulators per reduction pass
@@ -211,31 +250,29 @@ __global__ void __launch_bounds__(kIcpThreads) PCG_ICP_ATTR k_icp_accum(GridView
     static_assert(kHalf * kRow <= kStack * kIcpThreads, "reduction buffer must fit in the stack");
     __shared__ uint32_t stk[kStack * kIcpThreads];
     __shared__ uint32_t wcnt[kIcpThreads / 64];
-    if (!final_pass && st->stop) return;   // uniform across the grid
-    const GridParams P = *g.params;
+    const int lblk = xcd_block(blockIdx.x, nblk);
+    const int pr = np > 1 ? pair_of(boff, np, lblk) : 0;
+    const IcpState *st = state + pr;
+    if (!final_pass && st->stop) return;   // uniform across the block
+    const GridParams P = g.params[pr];
     float Rh[12], Rl[12];
 #pragma unroll
     for (int i = 0; i < 12; i++) {
         Rh[i] = st->Thi[i];
         Rl[i] = st->Tlo[i];
     }
+    const float dmax = dmaxv[pr];
     const double dmax64 = (double)dmax;
     const float dmax2 = dmax * dmax;
-    const int lblk = xcd_block(blockIdx.x, nblk);
-    const int64_t base = (int64_t)lblk * (kIcpThreads * PPT) + threadIdx.x;
-    int32_t jsel[PPT];
-    float tr[PPT][6];     // double-float p' of each point, reused by the accumulation
-#pragma unroll
-    for (int r = 0; r < PPT; r++) {
-        jsel[r] = -1;
-        int64_t i = base + (int64_t)r * kIcpThreads;
-        if (i >= ns) continue;
+    const int64_t i = soff[pr] + (int64_t)(lblk - boff[pr]) * kIcpThreads + threadIdx.x;
+    const bool active = i < soff[pr + 1] && P.n > 0;
+    int32_t j = -1;
+    float hx = 0.f, lx = 0.f, hy = 0.f, ly = 0.f, hz = 0.f, lz = 0.f;   // double-float p'
+    if (active) {
         float px = src[3 * i], py = src[3 * i + 1], pz = src[3 * i + 2];
-        float hx, lx, hy, ly, hz, lz;
         df_row(Rh, Rl, px, py, pz, hx, lx);
         df_row(Rh + 4, Rl + 4, px, py, pz, hy, ly);
         df_row(Rh + 8, Rl + 8, px, py, pz, hz, lz);
-        tr[r][0] = hx; tr[r][1] = lx; tr[r][2] = hy; tr[r][3] = ly; tr[r][4] = hz; tr[r][5] = lz;
         Query q{hx + lx, hy + ly, hz + lz};
         // q is p' rounded to float32 (plus ~2^-44 relative): per axis it is
         // within half an ulp, bounded here with slack, of the float64 p'
@@ -253,7 +290,6 @@ __global__ void __launch_bounds__(kIcpThreads) PCG_ICP_ATTR k_icp_accum(GridView
         }
         if (!done) search<NearBand, 16>(g, P, q, v, 1, stk + threadIdx.x, kIcpThreads);
         prev[i] = v.best_pos >= 0 ? make_int2(v.best_pos, (int32_t)v.best_node) : make_int2(-1, -1);
-        int32_t j = -1;
         if (v.best_pos >= 0) {
             float b = v.best_key();
             float e = v.err(b);
@@ -277,36 +313,28 @@ __global__ void __launch_bounds__(kIcpThreads) PCG_ICP_ATTR k_icp_accum(GridView
                 j = w.best_pos;
             }
         }
-        jsel[r] = j;
     }
     // Row of the linearised system for this lane's point (zero when it is
-    // not an inlier).  With one point per lane the 28 sums start at the wave
-    // level: each product is merged across the wave error-free (TwoSum on
-    // (hi, lo) pairs), one accumulator at a time, so only a handful of
-    // registers are live here.
+    // not an inlier).
     float J[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, res = 0.f;
     uint32_t cnt = 0;
-#pragma unroll
-    for (int r = 0; r < PPT; r++) {
-        int32_t j = jsel[r];
-        if (j < 0) continue;
-        int64_t i = base + (int64_t)r * kIcpThreads;
+    if (j >= 0) {
         float4 n = nrm[j];
-        if (n.x == 0.f && n.y == 0.f && n.z == 0.f) continue;
-        float4 t = g.pts[j];
-        float hx = tr[r][0], lx = tr[r][1], hy = tr[r][2], ly = tr[r][3], hz = tr[r][4], lz = tr[r][5];
-        float qx = hx + lx, qy = hy + ly, qz = hz + lz;
-        // residual vector from the double-float p': (hi - q) is exact for
-        // nearby points, so it keeps the full accuracy of hi + lo
-        float dx = (hx - t.x) + lx, dy = (hy - t.y) + ly, dz = (hz - t.z) + lz;
-        res = __fmaf_rn(dz, n.z, __fmaf_rn(dy, n.y, dx * n.x));
-        J[0] = __fmaf_rn(qy, n.z, -qz * n.y);
-        J[1] = __fmaf_rn(qz, n.x, -qx * n.z);
-        J[2] = __fmaf_rn(qx, n.y, -qy * n.x);
-        J[3] = n.x;
-        J[4] = n.y;
-        J[5] = n.z;
-        cnt = 1;
+        if (n.x != 0.f || n.y != 0.f || n.z != 0.f) {
+            float4 t = g.pts[j];
+            float qx = hx + lx, qy = hy + ly, qz = hz + lz;
+            // residual vector from the double-float p': (hi - q) is exact for
+            // nearby points, so it keeps the full accuracy of hi + lo
+            float dx = (hx - t.x) + lx, dy = (hy - t.y) + ly, dz = (hz - t.z) + lz;
+            res = __fmaf_rn(dz, n.z, __fmaf_rn(dy, n.y, dx * n.x));
+            J[0] = __fmaf_rn(qy, n.z, -qz * n.y);
+            J[1] = __fmaf_rn(qz, n.x, -qx * n.z);
+            J[2] = __fmaf_rn(qx, n.y, -qy * n.x);
+            J[3] = n.x;
+            J[4] = n.y;
+            J[5] = n.z;
+            cnt = 1;
+        }
     }
     // Block reduction of the 28 sums, error-free in (hi, lo) float pairs and
     // in a fixed order: in two passes of 14 sums, every lane stores its
@@ -336,7 +364,7 @@ __global__ void __launch_bounds__(kIcpThreads) PCG_ICP_ATTR k_icp_accum(GridView
         if (ra < kHalf) {
             CSum c{0.f, 0.f};
 #pragma unroll
-            for (int i = 0; i < 16; i++) two_sum_add(c, red[ra * kRow + rk + kLanes * i]);
+            for (int k = 0; k < 16; k++) two_sum_add(c, red[ra * kRow + rk + kLanes * k]);
 #pragma unroll
             for (int off = kLanes / 2; off > 0; off >>= 1) {
                 CSum o{__shfl_xor(c.hi, off), __shfl_xor(c.lo, off)};
@@ -375,17 +403,20 @@ __device__ inline uint32_t sum32(uint32_t c)
     return c;
 }
 
-// Merges the partials of kGroup (64) consecutive blocks: sum a (thread
-// t >> 5) is loaded by 32 lanes, two partials each, and merged by a fixed
-// tree, so the result depends only on the block order.
+// Merges the partials of up to kGroup (64) consecutive blocks of one pair:
+// sum a (thread t >> 5) is loaded by 32 lanes, two partials each, and merged
+// by a fixed tree, so the result depends only on the block order.
 __global__ void __launch_bounds__(1024) k_icp_reduce(const float2 *__restrict__ part, const uint32_t *__restrict__ pcnt,
-                                                   int nblk, const IcpState *__restrict__ st, int final_pass,
+                                                   const int32_t *__restrict__ boff, const int32_t *__restrict__ goff,
+                                                   int np, const IcpState *__restrict__ state, int final_pass,
                                                    float2 *__restrict__ gpart, uint32_t *__restrict__ gcnt)
 {
     static_assert(kGroup == 64, "two partials per lane of a 32-lane group");
-    if (!final_pass && st->stop) return;
-    const int grp = blockIdx.x, b0 = grp * kGroup;
-    const int gsz = (nblk - b0) < kGroup ? (nblk - b0) : kGroup;
+    const int grp = blockIdx.x;
+    const int pr = np > 1 ? pair_of(goff, np, grp) : 0;
+    if (!final_pass && state[pr].stop) return;
+    const int b0 = boff[pr] + (grp - goff[pr]) * kGroup;
+    const int gsz = (boff[pr + 1] - b0) < kGroup ? (boff[pr + 1] - b0) : kGroup;
     const int a = threadIdx.x >> 5, j = threadIdx.x & 31;
     if (a < kAcc) {
         CSum c{0.f, 0.f};
@@ -427,36 +458,45 @@ __device__ bool chol6(double A[36])
     return true;
 }
 
-// reduces the block partials in a fixed order; iteration: solve and update
-// the pose; final pass: publish pose and statistics
-__global__ void __launch_bounds__(kFinThreads) k_icp_finalize(const float2 *__restrict__ part,
-                                                            const uint32_t *__restrict__ pcnt, int nblk,
-                                                            IcpState *st, int final_pass, double conv_tol,
+// One block per pair: merges the pair's group partials in a fixed order;
+// iteration: solve and update the pose; final pass: publish pose and
+// statistics.
+__global__ void __launch_bounds__(kFinThreads) k_icp_finalize(const float2 *__restrict__ gpart,
+                                                            const uint32_t *__restrict__ gcnt,
+                                                            const int32_t *__restrict__ goff,
+                                                            IcpState *state, const int32_t *__restrict__ max_iters,
+                                                            int final_pass, double conv_tol,
                                                             double *__restrict__ out_T, pc_icp_stats *out_stats,
-                                                            double *__restrict__ hist)
+                                                            double *__restrict__ hist, int hist_stride)
 {
     __shared__ float2 red[32];
     __shared__ uint32_t redc;
+    const int pr = blockIdx.x;
+    IcpState *st = state + pr;
     if (!final_pass && st->stop) return;
+    const int g0 = goff[pr], g1 = goff[pr + 1];
     // sum a (thread t >> 5) over the groups: lane j merges groups j, j+32, ...
     // in order, then a fixed 32-lane tree merges the lanes
     const int a = threadIdx.x >> 5, j = threadIdx.x & 31;
     if (a < kAcc) {
         CSum c{0.f, 0.f};
-        for (int b = j; b < nblk; b += 32) {
-            float2 v = part[(int64_t)b * kAcc + a];
+        for (int b = g0 + j; b < g1; b += 32) {
+            float2 v = gpart[(int64_t)b * kAcc + a];
             c = csum_merge(c, CSum{v.x, v.y});
         }
         c = merge32(c);
         if (j == 0) red[a] = make_float2(c.hi, c.lo);
     } else if (a == kAcc) {
         uint32_t c = 0;
-        for (int b = j; b < nblk; b += 32) c += pcnt[b];
+        for (int b = g0 + j; b < g1; b += 32) c += gcnt[b];
         c = sum32(c);
         if (j == 0) redc = c;
     }
     __syncthreads();
     if (threadIdx.x != 0) return;
+    out_T += 16 * pr;
+    if (out_stats) out_stats += pr;
+    if (hist) hist += (int64_t)hist_stride * pr;
     double sum[kAcc];
     for (int k = 0; k < kAcc; k++) sum[k] = (double)red[k].x + (double)red[k].y;
     int64_t inl = redc;
@@ -535,19 +575,7 @@ __global__ void __launch_bounds__(kFinThreads) k_icp_finalize(const float2 *__re
             st->stop = 1;
         }
     }
-}
-
-__global__ void k_icp_empty(const double *__restrict__ init_T, double *out_T, pc_icp_stats *out_stats)
-{
-    for (int i = 0; i < 16; i++) out_T[i] = init_T ? init_T[i] : ((i % 5 == 0) ? 1.0 : 0.0);
-    if (out_stats) {
-        pc_icp_stats o;
-        o.status = PC_ICP_NO_INLIERS;
-        o.iterations_run = 0;
-        o.inliers = 0;
-        o.rms = 0.0;
-        *out_stats = o;
-    }
+    if (!st->stop && st->iters >= max_iters[pr]) st->stop = 1;   // status stays MAXITER
 }
 
 }  // namespace
@@ -569,87 +597,72 @@ void icp_set_timer(hipEvent_t *b, hipEvent_t *e, int cap)
 
 int icp_timer_count() { return g_tcount; }
 
-static int icp_ppt(int64_t ns)
+void icp_carve(Carver &c, int np, int64_t ns, int64_t nt, int64_t nblk, int64_t ngrp, int iters_max,
+               IcpStore &s)
 {
-    (void)ns;
-    return 1;   // one point per lane: the search is latency bound
-}
-
-[[maybe_unused]] static int icp_ppt_wide(int64_t ns)
-{
-    int64_t per = (ns + (int64_t)kIcpThreads * 1024 - 1) / ((int64_t)kIcpThreads * 1024);
-    if (per <= 1) return 1;
-    if (per <= 2) return 2;
-    if (per <= 4) return 4;
-    if (per <= 8) return 8;
-    return 16;
-}
-
-void icp_carve(Carver &c, int64_t ns, int64_t nt, int max_iters, IcpStore &s)
-{
-    grid_carve(c, nt, s.grid);
+    int np1 = np > 0 ? np : 1;
+    grid_carve(c, nt, np1, s.grid);
     int64_t nt1 = nt > 0 ? nt : 1, ns1 = ns > 0 ? ns : 1;
+    s.np = np1;
+    s.nblk = (int)nblk;
+    s.ngrp = (int)ngrp;
+    s.iters_max = iters_max > 0 ? iters_max : 0;
     s.nrm = c.take<float4>(nt1);
     s.prev = c.take<int2>(ns1);
-    s.st = c.take<IcpState>(1);
-    s.ppt = icp_ppt(ns1);
-    s.nblk = (int)((ns1 + (int64_t)kIcpThreads * s.ppt - 1) / ((int64_t)kIcpThreads * s.ppt));
-    s.part = c.take<float2>((size_t)s.nblk * kAcc);
-    s.pcnt = c.take<uint32_t>((size_t)s.nblk);
-    s.ngrp = (s.nblk + kGroup - 1) / kGroup;
-    s.gpart = c.take<float2>((size_t)s.ngrp * kAcc);
-    s.gcnt = c.take<uint32_t>((size_t)s.ngrp);
-    s.hist = c.take<double>((size_t)8 * (max_iters > 0 ? max_iters : 1));
+    s.st = c.take<IcpState>(np1);
+    s.soff = c.take<int64_t>(np1 + 1);
+    s.boff = c.take<int32_t>(np1 + 1);
+    s.goff = c.take<int32_t>(np1 + 1);
+    s.dmax = c.take<float>(np1);
+    s.maxit = c.take<int32_t>(np1);
+    s.part = c.take<float2>((size_t)(nblk > 0 ? nblk : 1) * kAcc);
+    s.pcnt = c.take<uint32_t>((size_t)(nblk > 0 ? nblk : 1));
+    s.gpart = c.take<float2>((size_t)(ngrp > 0 ? ngrp : 1) * kAcc);
+    s.gcnt = c.take<uint32_t>((size_t)(ngrp > 0 ? ngrp : 1));
+    s.hist_stride = 8 * (s.iters_max > 0 ? s.iters_max : 1);
+    s.hist = c.take<double>((size_t)s.hist_stride * np1);
 }
 
-template <int PPT>
-static void launch_accum(IcpStore &s, const float *src, int64_t ns, float dmax, int final_pass, hipStream_t st)
+int64_t icp_blocks(int64_t ns) { return (ns + kIcpThreads - 1) / kIcpThreads; }
+int64_t icp_groups(int64_t nblk) { return (nblk + kGroup - 1) / kGroup; }
+
+hipError_t icp_layout_single(IcpStore &s, int64_t ns, int64_t nt, float dmax, int max_iters, hipStream_t st)
 {
-    k_icp_accum<PPT><<<s.nblk, kIcpThreads, 0, st>>>(s.grid.view(), src, ns, s.nrm, s.prev, s.st, dmax,
-                                                     final_pass, s.part, s.pcnt, s.nblk);
-    k_icp_reduce<<<s.ngrp, 1024, 0, st>>>(s.part, s.pcnt, s.nblk, s.st, final_pass, s.gpart, s.gcnt);
+    k_single_pair<<<1, 1, 0, st>>>(ns, nt, s.nblk, s.ngrp, dmax, max_iters, s.soff, s.grid.off, s.boff, s.goff,
+                                   s.dmax, s.maxit);
+    return hipGetLastError();
 }
 
-static void accum(IcpStore &s, const float *src, int64_t ns, float dmax, int final_pass, hipStream_t st)
+hipError_t icp_run(IcpStore &s, const float *src, int64_t ns, const float *tgt, const float *tgt_n,
+                   const double *init_T, double conv_tol, double *out_T, pc_icp_stats *out_stats, hipStream_t st)
 {
-    switch (s.ppt) {
-    case 1: launch_accum<1>(s, src, ns, dmax, final_pass, st); break;
-    case 2: launch_accum<2>(s, src, ns, dmax, final_pass, st); break;
-    case 4: launch_accum<4>(s, src, ns, dmax, final_pass, st); break;
-    case 8: launch_accum<8>(s, src, ns, dmax, final_pass, st); break;
-    default: launch_accum<16>(s, src, ns, dmax, final_pass, st); break;
-    }
-}
-
-hipError_t icp_run(IcpStore &s, const float *src, int64_t ns, const float *tgt, const float *tgt_n, int64_t nt,
-                   const double *init_T, float dmax, int max_iters, double conv_tol, double *out_T,
-                   pc_icp_stats *out_stats, hipStream_t st)
-{
-    if (ns <= 0 || nt <= 0) {
-        k_icp_empty<<<1, 1, 0, st>>>(init_T, out_T, out_stats);
-        return hipGetLastError();
-    }
-    k_icp_setup<<<1, 1, 0, st>>>(init_T, s.st);
+    const int np = s.np;
+    k_icp_setup<<<(np + 63) / 64, 64, 0, st>>>(init_T, s.soff, s.grid.off, s.maxit, np, s.st);
     hipError_t e = grid_build(s.grid, tgt, st);
     if (e != hipSuccess) return e;
     e = grid_gather3(s.grid, tgt_n, s.nrm, st);
     if (e != hipSuccess) return e;
-    k_fill_i32<<<(int)((2 * ns + 255) / 256 < 2048 ? (2 * ns + 255) / 256 : 2048), 256, 0, st>>>((int32_t *)s.prev,
-                                                                                             2 * ns, -1);
-    g_tcount = 0;
-    for (int it = 0; it < max_iters; it++) {
-        bool timed = it < g_tcap;
-        if (timed) (void)hipEventRecord(g_tbeg[it], st);
-        accum(s, src, ns, dmax, 0, st);
-        if (timed) {
-            (void)hipEventRecord(g_tend[it], st);
-            g_tcount = it + 1;
-        }
-        k_icp_finalize<<<1, kFinThreads, 0, st>>>(s.gpart, s.gcnt, s.ngrp, s.st, 0, conv_tol, out_T, out_stats,
-                                                  s.hist);
+    if (ns > 0) {
+        int fb = (int)((2 * ns + 255) / 256 < 2048 ? (2 * ns + 255) / 256 : 2048);
+        k_fill_i32<<<fb, 256, 0, st>>>((int32_t *)s.prev, 2 * ns, -1);
     }
-    accum(s, src, ns, dmax, 1, st);
-    k_icp_finalize<<<1, kFinThreads, 0, st>>>(s.gpart, s.gcnt, s.ngrp, s.st, 1, conv_tol, out_T, out_stats, s.hist);
+    g_tcount = 0;
+    for (int pass = 0; pass <= s.iters_max; pass++) {
+        const int fin = pass == s.iters_max;   // the last pass gives the statistics
+        const bool timed = !fin && pass < g_tcap;
+        if (s.nblk > 0) {
+            if (timed) (void)hipEventRecord(g_tbeg[pass], st);
+            k_icp_accum<<<s.nblk, kIcpThreads, 0, st>>>(s.grid.view(), src, s.soff, s.boff, np, s.nrm, s.prev,
+                                                        s.st, s.dmax, fin, s.part, s.pcnt, s.nblk);
+            if (timed) {
+                (void)hipEventRecord(g_tend[pass], st);
+                g_tcount = pass + 1;
+            }
+            k_icp_reduce<<<s.ngrp, 1024, 0, st>>>(s.part, s.pcnt, s.boff, s.goff, np, s.st, fin, s.gpart, s.gcnt);
+        }
+        k_icp_finalize<<<np, kFinThreads, 0, st>>>(s.gpart, s.gcnt, s.goff, s.st, s.maxit, fin, conv_tol, out_T,
+                                                   out_stats, s.hist, s.hist_stride);
+    }
     return hipGetLastError();
 }
 

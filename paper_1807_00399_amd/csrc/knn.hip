@@ -28,7 +28,7 @@ __global__ void __launch_bounds__(kQThreads) k_knn(GridView g, const float *__re
                                                  int32_t *__restrict__ out_idx, float *__restrict__ out_d2)
 {
     __shared__ uint32_t stk[kStack * kQThreads];
-    const GridParams P = *g.params;
+    const GridParams P = g.params[0];   // the reference cloud
     int64_t i = xcd_block(blockIdx.x, gridDim.x) * (int64_t)kQThreads + threadIdx.x;
     if (i >= nq) return;
     Query q{qry[3 * i], qry[3 * i + 1], qry[3 * i + 2]};
@@ -122,17 +122,22 @@ __device__ void sym3_min_eigvec(double a, double b, double c, double d, double e
     v[2] = uz * s;
 }
 
+// One query per lane over every point of every cloud in the grid; the
+// neighbourhood of a point is taken in its own cloud, with that cloud's k
+// (kc[cloud], or k for all when kc is null).
 template <int KT>
-__global__ void __launch_bounds__(kQThreads) k_normals(GridView g, const float *__restrict__ xyz, int k, float vx,
-                                                     float vy, float vz, float *__restrict__ out_n,
-                                                     float *__restrict__ out_c)
+__global__ void __launch_bounds__(kQThreads) k_normals(GridView g, int64_t n_all, const float *__restrict__ xyz, int k,
+                                                     const int32_t *__restrict__ kc, float vx, float vy, float vz,
+                                                     float *__restrict__ out_n, float *__restrict__ out_c)
 {
     __shared__ uint32_t stk[kStack * kQThreads];
-    const GridParams P = *g.params;
     int64_t s = xcd_block(blockIdx.x, gridDim.x) * (int64_t)kQThreads + threadIdx.x;
     // queries are the points in sorted order, so neighbouring lanes search
     // neighbouring cells
-    if (s >= P.n) return;
+    if (s >= n_all) return;
+    const int cl = key_cloud(g.keys[s]);
+    const GridParams P = g.params[cl];
+    if (kc) k = kc[cl];
     float4 p = g.pts[s];
     uint32_t qi = __float_as_uint(p.w);
     Query q{p.x, p.y, p.z};
@@ -147,7 +152,7 @@ __global__ void __launch_bounds__(kQThreads) k_normals(GridView g, const float *
     for (int t = 0; t < KT; t++) {
         if (t < KT - k) continue;
         uint32_t j = (uint32_t)top.h[t];
-        if (j >= (uint32_t)P.n) continue;   // unfilled slot (cannot happen for k <= n)
+        if (j >= (uint32_t)n_all) continue;   // unfilled slot (cannot happen for k <= n)
         mx += (double)xyz[3 * (int64_t)j] - qx;
         my += (double)xyz[3 * (int64_t)j + 1] - qy;
         mz += (double)xyz[3 * (int64_t)j + 2] - qz;
@@ -160,7 +165,7 @@ __global__ void __launch_bounds__(kQThreads) k_normals(GridView g, const float *
     for (int t = 0; t < KT; t++) {
         if (t < KT - k) continue;
         uint32_t j = (uint32_t)top.h[t];
-        if (j >= (uint32_t)P.n) continue;
+        if (j >= (uint32_t)n_all) continue;
         double ex = ((double)xyz[3 * (int64_t)j] - qx) - mx;
         double ey = ((double)xyz[3 * (int64_t)j + 1] - qy) - my;
         double ez = ((double)xyz[3 * (int64_t)j + 2] - qz) - mz;
@@ -201,11 +206,11 @@ void launch_knn(const GridStore &g, const float *qry, int64_t nq, int k, int32_t
 }
 
 template <int KT>
-void launch_normals(const GridStore &g, const float *xyz, int k, const float *vp, float *on, float *oc,
-                    hipStream_t s)
+void launch_normals(const GridStore &g, const float *xyz, int k, const int32_t *kc, const float *vp, float *on,
+                    float *oc, hipStream_t s)
 {
     int blocks = (int)((g.n + kQThreads - 1) / kQThreads);
-    k_normals<KT><<<blocks, kQThreads, 0, s>>>(g.view(), xyz, k, vp[0], vp[1], vp[2], on, oc);
+    k_normals<KT><<<blocks, kQThreads, 0, s>>>(g.view(), g.n, xyz, k, kc, vp[0], vp[1], vp[2], on, oc);
 }
 
 }  // namespace
@@ -221,14 +226,14 @@ hipError_t knn_run(const GridStore &g, const float *qry, int64_t nq, int k, int3
     return hipGetLastError();
 }
 
-hipError_t normals_run(const GridStore &g, const float *xyz, int k, const float *vp, float *on, float *oc,
-                       hipStream_t s)
+hipError_t normals_run(const GridStore &g, const float *xyz, int k_max, const int32_t *kc, const float *vp,
+                       float *on, float *oc, hipStream_t s)
 {
     if (g.n <= 0) return hipSuccess;
-    if (k <= 4) launch_normals<4>(g, xyz, k, vp, on, oc, s);
-    else if (k <= 8) launch_normals<8>(g, xyz, k, vp, on, oc, s);
-    else if (k <= 16) launch_normals<16>(g, xyz, k, vp, on, oc, s);
-    else launch_normals<32>(g, xyz, k, vp, on, oc, s);
+    if (k_max <= 4) launch_normals<4>(g, xyz, k_max, kc, vp, on, oc, s);
+    else if (k_max <= 8) launch_normals<8>(g, xyz, k_max, kc, vp, on, oc, s);
+    else if (k_max <= 16) launch_normals<16>(g, xyz, k_max, kc, vp, on, oc, s);
+    else launch_normals<32>(g, xyz, k_max, kc, vp, on, oc, s);
     return hipGetLastError();
 }
 

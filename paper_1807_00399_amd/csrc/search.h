@@ -99,12 +99,14 @@ __device__ inline void scan_range(const float4 *__restrict__ pts, uint32_t s, ui
     }
 }
 
-// continue a linear probe of `key` from slot s (first slot held another key)
-__device__ inline int32_t probe_from(const GridView &g, uint32_t mask, uint64_t key, uint32_t s)
+// continue a linear probe of `key` from slot s of cloud P's hash region
+// (the first slot held another key)
+__device__ inline int32_t probe_from(const GridView &g, const GridParams &P, uint64_t key, uint32_t s)
 {
-    for (uint32_t it = 0; it < mask; it++) {
-        s = (s + 1) & mask;
-        HSlot e = g.hash[s];
+    const HSlot *hs = g.hash + P.hash_base;
+    for (uint32_t it = 1; it < P.hash_cap; it++) {
+        s = next_slot(s, P.hash_cap);
+        HSlot e = hs[s];
         if (e.key == key) return (int32_t)e.val;
         if (e.key == kEmptyKey) return -1;
     }
@@ -205,7 +207,7 @@ __device__ inline void cover(const GridView &g, const GridParams &P, const Query
     uint32_t ly = cell0(q.y - R, P.oy, inv) >> l, hy = cell0(q.y + R, P.oy, inv) >> l;
     uint32_t lz = cell0(q.z - R, P.oz, inv) >> l, hz = cell0(q.z + R, P.oz, inv) >> l;
     int sp = 0;
-    const uint32_t mask = P.hash_mask;
+    const HSlot *hs = g.hash + P.hash_base;
     if (hx - lx <= 1 && hy - ly <= 1 && hz - lz <= 1) {
         // up to 8 cells: first hash probes issued together
         uint64_t key[8];
@@ -217,14 +219,14 @@ __device__ inline void cover(const GridView &g, const GridParams &P, const Query
             uint32_t cx = lx + (c & 1), cy = ly + ((c >> 1) & 1), cz = lz + (c >> 2);
             bool ok = cx <= hx && cy <= hy && cz <= hz;
             key[c] = hash_key(l, morton3(cx, cy, cz));
-            slot[c] = hash_slot(key[c], mask);
-            HSlot e = ok ? g.hash[slot[c]] : HSlot{kEmptyKey, 0u, 0u};
+            slot[c] = hash_slot(key[c], P.hash_cap);
+            HSlot e = ok ? hs[slot[c]] : HSlot{kEmptyKey, 0u, 0u};
             hk[c] = e.key;
             node[c] = (e.key == key[c]) ? (int32_t)e.val : -1;
         }
 #pragma unroll
         for (int c = 0; c < 8; c++) {
-            if (hk[c] != key[c] && hk[c] != kEmptyKey) node[c] = probe_from(g, mask, key[c], slot[c]);
+            if (hk[c] != key[c] && hk[c] != kEmptyKey) node[c] = probe_from(g, P, key[c], slot[c]);
             if (node[c] >= 0) {
                 uint32_t cx = lx + (c & 1), cy = ly + ((c >> 1) & 1), cz = lz + (c >> 2);
                 if (cell_mindist2(P, q.x, q.y, q.z, cx, cy, cz, l) <= b2) {
@@ -238,7 +240,7 @@ __device__ inline void cover(const GridView &g, const GridParams &P, const Query
         for (uint32_t cz = lz; cz <= hz; cz++)
             for (uint32_t cy = ly; cy <= hy; cy++)
                 for (uint32_t cx = lx; cx <= hx; cx++) {
-                    int32_t m = find_cell(g, mask, l, cx, cy, cz);
+                    int32_t m = find_cell(g, P, l, cx, cy, cz);
                     if (m < 0 || cell_mindist2(P, q.x, q.y, q.z, cx, cy, cz, l) > b2) continue;
                     if (sp < kStack) {
                         stk[sp * stride] = (uint32_t)m;
@@ -258,7 +260,7 @@ __device__ inline int32_t seed_cell(const GridView &g, const GridParams &P, cons
 {
     const float inv = P.inv_h0;
     uint32_t c0x = cell0(q.x, P.ox, inv), c0y = cell0(q.y, P.oy, inv), c0z = cell0(q.z, P.oz, inv);
-    const uint32_t mask = P.hash_mask;
+    const HSlot *hs = g.hash + P.hash_base;
     for (int l0 = P.lmin; l0 < kLevels; l0 += 4) {
         uint64_t key[4];
         uint32_t slot[4];
@@ -270,14 +272,14 @@ __device__ inline int32_t seed_cell(const GridView &g, const GridParams &P, cons
             bool ok = l < kLevels;
             int ls = ok ? l : 0;
             key[t] = hash_key(ls, morton3(c0x >> ls, c0y >> ls, c0z >> ls));
-            slot[t] = hash_slot(key[t], mask);
-            HSlot e = ok ? g.hash[slot[t]] : HSlot{kEmptyKey, 0u, 0u};
+            slot[t] = hash_slot(key[t], P.hash_cap);
+            HSlot e = ok ? hs[slot[t]] : HSlot{kEmptyKey, 0u, 0u};
             hk[t] = e.key;
             node[t] = (e.key == key[t]) ? (int32_t)e.val : -1;
         }
 #pragma unroll
         for (int t = 0; t < 4; t++)
-            if (hk[t] != key[t] && hk[t] != kEmptyKey) node[t] = probe_from(g, mask, key[t], slot[t]);
+            if (hk[t] != key[t] && hk[t] != kEmptyKey) node[t] = probe_from(g, P, key[t], slot[t]);
         uint32_t cnt[4];
 #pragma unroll
         for (int t = 0; t < 4; t++) cnt[t] = node[t] >= 0 ? g.node[node[t]].h.count : 0u;

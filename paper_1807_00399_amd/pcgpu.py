@@ -25,6 +25,8 @@ EXPORTS = (
     "knn_search_workspace_size", "knn_search",
     "estimate_normals_workspace_size", "estimate_normals",
     "icp_point_to_plane_workspace_size", "icp_point_to_plane",
+    "estimate_normals_batched_workspace_size", "estimate_normals_batched",
+    "icp_point_to_plane_batched_workspace_size", "icp_point_to_plane_batched",
     "pc_copy_probe", "icp_history", "pc_set_kernel_timer", "pc_kernel_timer_count",
 )
 
@@ -55,6 +57,14 @@ def _load() -> ctypes.CDLL:
     lib.icp_point_to_plane_workspace_size.restype = sz
     lib.icp_point_to_plane.argtypes = [vp, i64, vp, vp, i64, vp, f32, i32, f64, vp, vp, vp, sz, vp]
     lib.icp_point_to_plane.restype = ctypes.c_int
+    lib.estimate_normals_batched_workspace_size.argtypes = [i32, vp]
+    lib.estimate_normals_batched_workspace_size.restype = sz
+    lib.estimate_normals_batched.argtypes = [i32, vp, vp, vp, ctypes.POINTER(ctypes.c_float), vp, vp, vp, sz, vp]
+    lib.estimate_normals_batched.restype = ctypes.c_int
+    lib.icp_point_to_plane_batched_workspace_size.argtypes = [i32, vp, vp, i32]
+    lib.icp_point_to_plane_batched_workspace_size.restype = sz
+    lib.icp_point_to_plane_batched.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, vp, f64, vp, vp, vp, sz, vp]
+    lib.icp_point_to_plane_batched.restype = ctypes.c_int
     lib.pc_copy_probe.argtypes = [vp, vp, sz, vp]
     lib.pc_copy_probe.restype = ctypes.c_int
     lib.icp_history.argtypes = [vp, sz, i64, i64, i32]
@@ -198,6 +208,86 @@ def icp_history(workspace: torch.Tensor, n_src: int, n_tgt: int, max_iters: int,
 def workspace_for_icp(n_src: int, n_tgt: int, max_iters: int, device) -> torch.Tensor:
     need = lib.icp_point_to_plane_workspace_size(n_src, n_tgt, max_iters)
     return torch.empty(need, dtype=torch.uint8, device=device)
+
+
+def _offsets(sizes_or_offsets, what: str):
+    """int64 host offsets (m + 1) from a list of sizes or of offsets."""
+    import numpy as np
+    a = np.ascontiguousarray(np.asarray(sizes_or_offsets, dtype=np.int64))
+    if a.ndim != 1:
+        raise ValueError(f"{what} must be 1-D")
+    return a
+
+
+def offsets_from_sizes(sizes):
+    import numpy as np
+    sizes = np.asarray(sizes, dtype=np.int64)
+    return np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+
+
+def estimate_normals_batched(xyz: torch.Tensor, offsets, k, viewpoint=(0.0, 0.0, 0.0), curvature: bool = True,
+                             stream=None, workspace: torch.Tensor | None = None):
+    """PCA normals of packed clouds: offsets (m+1 int64), k per cloud (int or m ints)."""
+    import numpy as np
+    xyz = _pts(xyz, "xyz")
+    off = _offsets(offsets, "offsets")
+    m = off.shape[0] - 1
+    if m < 1 or off[-1] != xyz.shape[0]:
+        raise ValueError("offsets must have m + 1 entries ending at len(xyz)")
+    kc = np.ascontiguousarray(np.broadcast_to(np.asarray(k, dtype=np.int32), (m,)))
+    n = xyz.shape[0]
+    nrm = torch.empty((n, 3), dtype=torch.float32, device=xyz.device)
+    cur = torch.empty((n,), dtype=torch.float32, device=xyz.device) if curvature else None
+    vp = (ctypes.c_float * 3)(*[float(v) for v in viewpoint])
+    need = lib.estimate_normals_batched_workspace_size(m, off.ctypes.data)
+    ws = workspace if workspace is not None else _ws.get(need, xyz.device)
+    st = lib.estimate_normals_batched(m, xyz.data_ptr(), off.ctypes.data, kc.ctypes.data, vp, nrm.data_ptr(),
+                                      _ptr(cur), ws.data_ptr(), ws.numel(), _stream(stream))
+    _check(st, "estimate_normals_batched")
+    return nrm, cur
+
+
+def icp_point_to_plane_batched(src: torch.Tensor, src_off, tgt: torch.Tensor, tgt_normals: torch.Tensor, tgt_off,
+                               init_T=None, max_corr_dist=0.05, max_iters=30, conv_tol: float = 0.0, stream=None,
+                               workspace: torch.Tensor | None = None, out_T: torch.Tensor | None = None,
+                               out_stats: torch.Tensor | None = None, read_stats: bool = True):
+    """Batched point-to-plane ICP over packed pairs.  Returns (T (m,4,4)
+    float64 device tensor, stats): a list of dicts when read_stats (this
+    synchronises), else the raw (m * 24)-byte device tensor."""
+    import numpy as np
+    src = _pts(src, "src")
+    tgt = _pts(tgt, "tgt")
+    tgt_normals = _pts(tgt_normals, "tgt_normals")
+    so, to = _offsets(src_off, "src_off"), _offsets(tgt_off, "tgt_off")
+    m = so.shape[0] - 1
+    if m < 1 or to.shape[0] != m + 1 or so[-1] != src.shape[0] or to[-1] != tgt.shape[0]:
+        raise ValueError("offsets must have m + 1 entries ending at the array lengths")
+    if tgt_normals.shape[0] != tgt.shape[0]:
+        raise ValueError("tgt_normals must match tgt")
+    dm = np.ascontiguousarray(np.broadcast_to(np.asarray(max_corr_dist, dtype=np.float32), (m,)))
+    mi = np.ascontiguousarray(np.broadcast_to(np.asarray(max_iters, dtype=np.int32), (m,)))
+    dev = src.device
+    T0 = None
+    if init_T is not None:
+        T0 = torch.as_tensor(init_T, dtype=torch.float64).reshape(m, 4, 4).to(dev).contiguous()
+    T = out_T if out_T is not None else torch.empty((m, 4, 4), dtype=torch.float64, device=dev)
+    stats = out_stats if out_stats is not None else torch.zeros(24 * m, dtype=torch.uint8, device=dev)
+    need = lib.icp_point_to_plane_batched_workspace_size(m, so.ctypes.data, to.ctypes.data, int(mi.max()))
+    ws = workspace if workspace is not None else _ws.get(need, dev)
+    st = lib.icp_point_to_plane_batched(m, src.data_ptr(), so.ctypes.data, tgt.data_ptr(), tgt_normals.data_ptr(),
+                                        to.ctypes.data, _ptr(T0), dm.ctypes.data, mi.ctypes.data, float(conv_tol),
+                                        T.data_ptr(), stats.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream))
+    _check(st, "icp_point_to_plane_batched")
+    if not read_stats:
+        return T, stats
+    return T, decode_stats_batched(stats)
+
+
+def decode_stats_batched(stats: torch.Tensor) -> list:
+    import numpy as np
+    raw = stats.cpu().numpy().tobytes()
+    recs = np.frombuffer(raw, dtype=np.dtype(STATS_DTYPE))
+    return [{name: r[name].item() for name, _ in STATS_DTYPE} for r in recs]
 
 
 def copy_probe(dst: torch.Tensor, src: torch.Tensor, stream=None):

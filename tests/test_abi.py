@@ -107,3 +107,64 @@ def test_copy_probe_rejects_bad_arguments(pc):
     assert pc.lib.pc_copy_probe(FAKE, FAKE, 17, None) == pc.PC_EINVAL
     assert pc.lib.pc_copy_probe(None, FAKE, 16, None) == pc.PC_EINVAL
     assert pc.lib.pc_copy_probe(FAKE, FAKE, 0, None) == pc.PC_OK
+
+
+def _i64(vals):
+    return (ctypes.c_int64 * len(vals))(*vals)
+
+
+def _i32(vals):
+    return (ctypes.c_int32 * len(vals))(*vals)
+
+
+def _f32(vals):
+    return (ctypes.c_float * len(vals))(*vals)
+
+
+def test_batched_normals_rejects_bad_arguments(pc):
+    L = pc.lib
+    vp = (ctypes.c_float * 3)(0, 0, 0)
+    off = _i64([0, 40, 40, 100])
+    k = _i32([8, 5, 10])
+    ws = L.estimate_normals_batched_workspace_size(3, off)
+    assert ws > L.estimate_normals_workspace_size(100, 10)
+
+    def call(m=3, o=off, kk=k, x=FAKE, v=vp, out=FAKE, w=FAKE, wb=ws):
+        return L.estimate_normals_batched(m, x, o, kk, v, out, None, w, wb, None)
+
+    assert call(wb=ws - 1) == pc.PC_EWORKSPACE
+    assert call(m=0) == pc.PC_EINVAL
+    assert call(o=_i64([1, 40, 40, 100])) == pc.PC_EINVAL          # does not start at 0
+    assert call(o=_i64([0, 40, 30, 100])) == pc.PC_EINVAL          # decreasing
+    assert call(kk=_i32([41, 5, 10])) == pc.PC_EINVAL              # k above the cloud's size
+    assert call(kk=_i32([8, 5, 0])) == pc.PC_EINVAL
+    assert call(kk=None) == pc.PC_EINVAL
+    assert call(x=None) == pc.PC_EINVAL
+    assert call(v=None) == pc.PC_EINVAL
+    assert L.estimate_normals_batched_workspace_size(3, _i64([0, 5, 4, 9])) == 0
+    # all clouds empty: a valid no-op
+    assert call(o=_i64([0, 0, 0, 0]), x=None, out=None, w=None, wb=0) == pc.PC_OK
+
+
+def test_batched_icp_rejects_bad_arguments(pc):
+    L = pc.lib
+    so, to = _i64([0, 50, 50, 120]), _i64([0, 60, 70, 70])
+    dm, mi = _f32([0.1, 0.05, 0.2]), _i32([5, 9, 0])
+    ws = L.icp_point_to_plane_batched_workspace_size(3, so, to, 9)
+    assert ws > 0
+
+    def call(m=3, s=so, t=to, d=dm, it=mi, tol=0.0, out=FAKE, w=FAKE, wb=ws, T0=None):
+        return L.icp_point_to_plane_batched(m, FAKE, s, FAKE, FAKE, t, T0, d, it, tol, out, None, w, wb, None)
+
+    assert call(wb=ws - 1) == pc.PC_EWORKSPACE
+    assert call(d=_f32([0.1, 0.0, 0.2])) == pc.PC_EINVAL
+    assert call(d=_f32([0.1, float("nan"), 0.2])) == pc.PC_EINVAL
+    assert call(it=_i32([5, -1, 0])) == pc.PC_EINVAL
+    assert call(t=_i64([0, 60, 50, 70])) == pc.PC_EINVAL
+    assert call(m=0) == pc.PC_EINVAL
+    assert call(d=None) == pc.PC_EINVAL
+    assert call(out=None) == pc.PC_EINVAL
+    assert call(tol=-1.0) == pc.PC_EINVAL
+    assert call(T0=FAKE + 4) == pc.PC_EINVAL
+    # the size query takes the largest iteration count of the batch
+    assert L.icp_point_to_plane_batched_workspace_size(3, so, to, 30) > ws
