@@ -35,6 +35,22 @@ HBM_PEAK_GBS = 8000.0
 # matched target xyz + normal (24), cell lookup (4)
 ICP_BYTES_PER_POINT = 40
 PROFILES = os.path.join(ROOT, "profiles")
+TUNING_CACHE = os.path.join(ROOT, "paper_1807_00399_amd", "tuning_cache.json")
+
+
+def autotune_step(args, step, tag, n_points):
+    """Sets the tuning for this workload (cached choice, or timed now)."""
+    from paper_1807_00399_amd import autotune, pcgpu
+    if args.no_autotune:
+        return {"tuning": pcgpu.get_tuning(), "source": "default"}
+    r = autotune.tune(step, tag, n_points, cache_file=TUNING_CACHE, use_cache=not args.retune)
+    if not r["from_cache"]:
+        # record the timings where a GPU run keeps its outputs
+        out = os.path.join(ROOT, "gpurun_out")
+        if os.path.isdir(out):
+            with open(os.path.join(out, f"tuning_{tag}.json"), "w") as f:
+                json.dump({autotune.cache_key(autotune._device_name(None), tag, n_points): r}, f, indent=1)
+    return {"tuning": r["tuning"], "source": "cache" if r["from_cache"] else "timed"}
 
 
 def parse():
@@ -45,6 +61,10 @@ def parse():
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="room")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default tuning instead of the autotuner's choice")
+    ap.add_argument("--retune", action="store_true",
+                    help="time every tuning candidate even when the tuning cache has this workload")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain 1 GiB device copy (bandwidth and counter calibration) and exit")
     return ap.parse_args()
@@ -200,6 +220,7 @@ def bench_batch(args):
         pcgpu.icp_point_to_plane_batched(src, off, tgt, nrm, off, None, dm, it, workspace=ws_i, out_T=T,
                                          out_stats=stats, read_stats=False)
 
+    tuning = autotune_step(args, step, "uneven_pairs_256", b.n)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -263,6 +284,7 @@ def bench_batch(args):
         "mpt_iter_per_s": pts_iter / (float(np.median(loop_ms)) * 1e-3) / 1e6,
         "loop_ms": float(np.median(loop_ms)),
         "single_call_pairs_per_s": seq_pairs / seq_el,
+        "tuning": tuning,
         "icp_status_counts": {str(k): int(v) for k, v in zip(*np.unique([r["status"] for r in st],
                                                                         return_counts=True))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -309,6 +331,7 @@ def main():
                                  out_stats=stats, read_stats=False)
         return nrm
 
+    tuning = autotune_step(args, step, w.name, w.n)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -359,6 +382,7 @@ def main():
         "mpt_iter_per_s": w.n * w.iters / loop_s / 1e6,
         "loop_ms": loop_s * 1e3,
         "icp_status": st,
+        "tuning": tuning,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_icp_accum", "avg_kernel_us": avg_kernel_s * 1e6,

@@ -200,6 +200,30 @@ pc_status icp_point_to_plane_batched(int n_pairs, const float *src_xyz, const in
                                      void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Tuning (process-wide; not thread-safe): launch shape and pyramid depth of
+ * later calls.  Every setting finds the same exact neighbours and
+ * correspondences; the block size only regroups the compensated per-block
+ * sums, which moves them by about 1e-14 relative.  Workspace sizes do not
+ * depend on the tuning.
+ *   icp_block_threads  64, 128 or 256: source points per accumulate block
+ *   icp_leaf           8, 16 or 32: nodes holding at most this many points
+ *                      are scanned whole by the ICP correspondence search
+ *   node_budget        0.125 .. 1: the finest pyramid level of a cloud is
+ *                      the finest one whose levels hold at most
+ *                      node_budget * n nodes (smaller: coarser leaves); used
+ *                      by estimate_normals* and icp_point_to_plane*
+ * Defaults: 128, 16, 1.  pc_set_tuning returns PC_EINVAL for other values.
+ * ---------------------------------------------------------------------- */
+typedef struct {
+    int32_t icp_block_threads;
+    int32_t icp_leaf;
+    float node_budget;
+} pc_tuning;
+
+pc_status pc_set_tuning(const pc_tuning *t);
+void pc_get_tuning(pc_tuning *t);
+
+/* ------------------------------------------------------------------------
  * Diagnostics
  * ---------------------------------------------------------------------- */
 /* Streams n_bytes (multiple of 16) from src to dst with one read and one

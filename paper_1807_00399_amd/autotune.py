@@ -1,0 +1,111 @@
+"""Autotuner for the ICP path: launch shape and pyramid depth.
+
+The paper chose its implementation variants by benchmarking the
+alternatives (Section 2, "Performance"); this module does the same at run
+time for the knobs of the GPU path (pc_tuning: accumulate block size, the
+leaf size of the correspondence search, the node budget that sets the
+pyramid's finest level).  Every candidate computes the same
+correspondences, so the choice only affects speed.
+
+    from paper_1807_00399_amd import autotune
+    best = autotune.tune(step, tag="uneven_pairs", n_points=b.n)
+
+`step` runs the work to be tuned on the current stream; each candidate is
+timed over a few runs (after one warm-up run) and the fastest is set with
+pc_set_tuning and stored in a JSON cache keyed by (device name, workload
+tag, size bucket = floor(log2(points))), so later processes reuse it.  The
+cache file is $PCGPU_TUNE_CACHE or ~/.cache/pcgpu/tuning.json.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+import tempfile
+import time
+
+from . import pcgpu
+
+BLOCK_THREADS = (64, 128, 256)
+LEAVES = (8, 16, 32)
+NODE_BUDGETS = (0.5, 1.0)
+CANDIDATES = tuple((b, l, nb) for b in BLOCK_THREADS for l in LEAVES for nb in NODE_BUDGETS)
+
+
+def cache_path() -> str:
+    p = os.environ.get("PCGPU_TUNE_CACHE")
+    if p:
+        return p
+    return os.path.join(os.path.expanduser("~"), ".cache", "pcgpu", "tuning.json")
+
+
+def cache_key(device_name: str, tag: str, n_points: int) -> str:
+    bucket = int(math.floor(math.log2(max(int(n_points), 1))))
+    return f"{device_name}|{tag}|{bucket}"
+
+
+def load_cache(path: str | None = None) -> dict:
+    path = path or cache_path()
+    try:
+        with open(path) as f:
+            d = json.load(f)
+        return d if isinstance(d, dict) else {}
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(key: str, entry: dict, path: str | None = None):
+    path = path or cache_path()
+    d = load_cache(path)
+    d[key] = entry
+    os.makedirs(os.path.dirname(os.path.abspath(path)), exist_ok=True)
+    fd, tmp = tempfile.mkstemp(dir=os.path.dirname(os.path.abspath(path)), suffix=".tmp")
+    with os.fdopen(fd, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+
+
+def _device_name(device_name):
+    if device_name is not None:
+        return device_name
+    import torch
+    return torch.cuda.get_device_name() if torch.cuda.is_available() else "cpu"
+
+
+def _sync():
+    import torch
+    if torch.cuda.is_available():
+        torch.cuda.synchronize()
+
+
+def tune(step, tag: str, n_points: int, device_name: str | None = None, candidates=CANDIDATES, reps: int = 2,
+         use_cache: bool = True, cache_file: str | None = None, sync=_sync, clock=time.perf_counter) -> dict:
+    """Pick the fastest pc_tuning for `step` and set it.  Returns
+    {"tuning": {...}, "seconds": best time, "from_cache": bool, "timings": [...]}."""
+    key = cache_key(_device_name(device_name), tag, n_points)
+    if use_cache:
+        hit = load_cache(cache_file).get(key)
+        if hit and "tuning" in hit:
+            t = hit["tuning"]
+            pcgpu.set_tuning(t["icp_block_threads"], t["icp_leaf"], t["node_budget"])
+            return {**hit, "from_cache": True}
+    timings = []
+    for b, l, nb in candidates:
+        pcgpu.set_tuning(b, l, nb)
+        step()                      # warm-up (the workspace does not depend on the tuning)
+        sync()
+        best = math.inf
+        for _ in range(max(1, reps)):
+            t0 = clock()
+            step()
+            sync()
+            best = min(best, clock() - t0)
+        timings.append({"icp_block_threads": b, "icp_leaf": l, "node_budget": nb, "seconds": best})
+    win = min(timings, key=lambda r: r["seconds"])
+    tuning = {"icp_block_threads": win["icp_block_threads"], "icp_leaf": win["icp_leaf"],
+              "node_budget": win["node_budget"]}
+    pcgpu.set_tuning(**tuning)
+    entry = {"tuning": tuning, "seconds": win["seconds"], "timings": timings}
+    if use_cache:
+        _store(key, entry, cache_file)
+    return {**entry, "from_cache": False}

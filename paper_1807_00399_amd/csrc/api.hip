@@ -23,6 +23,9 @@ bool valid_offsets(const int64_t *off, int m)
     return off[m] < kMaxPoints;
 }
 
+// process-wide tuning of the ICP kernels and the pyramid (pc_set_tuning)
+pc_tuning g_tune = {128, 16, 1.0f};
+
 bool upload(void *dst, const void *src, size_t bytes, hipStream_t s)
 {
     return bytes == 0 || hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s) == hipSuccess;
@@ -100,6 +103,7 @@ pc_status estimate_normals(const float *xyz, int64_t n, int k, const float viewp
     GridStore g;
     grid_carve(c, n, 1, g);
     if (!c.ok) return PC_EWORKSPACE;
+    g.node_budget = g_tune.node_budget;
     if (grid_set_single_cloud(g, stream) != hipSuccess) return PC_EDEVICE;
     if (grid_build(g, xyz, stream) != hipSuccess) return PC_EDEVICE;
     if (normals_run(g, xyz, k, nullptr, viewpoint, out_normals, out_curvature, stream) != hipSuccess)
@@ -149,6 +153,7 @@ pc_status estimate_normals_batched(int n_clouds, const float *xyz, const int64_t
     GridStore g;
     int32_t *kc = carve_normals_batched(c, n_clouds, offsets, g);
     if (!c.ok) return PC_EWORKSPACE;
+    g.node_budget = g_tune.node_budget;
     if (!upload(g.off, offsets, sizeof(int64_t) * (n_clouds + 1), stream)) return PC_EDEVICE;
     if (!upload(kc, k, sizeof(int32_t) * n_clouds, stream)) return PC_EDEVICE;
     if (grid_build(g, xyz, stream) != hipSuccess) return PC_EDEVICE;
@@ -159,28 +164,47 @@ pc_status estimate_normals_batched(int n_clouds, const float *xyz, const int64_t
 
 namespace {
 
+// The workspace layout does not depend on the tuning: block partials are
+// carved for the smallest block size.  The launch shape is set afterwards.
+void tune(IcpStore &s)
+{
+    s.threads = g_tune.icp_block_threads;
+    s.leaf = g_tune.icp_leaf;
+    s.grid.node_budget = g_tune.node_budget;
+}
+
 // the single-pair carve, shared by the size query, the call and the history
 void carve_single(Carver &c, int64_t n_src, int64_t n_tgt, int max_iters, IcpStore &s)
 {
-    int64_t nblk = icp_blocks(n_src);
-    icp_carve(c, 1, n_src, n_tgt, nblk, icp_groups(nblk), max_iters, s);
+    int64_t cap = icp_blocks_max(n_src);
+    icp_carve(c, 1, n_src, n_tgt, cap, icp_groups(cap), max_iters, s);
+    tune(s);
+    s.nblk = (int)icp_blocks(n_src, s.threads);
+    s.ngrp = (int)icp_groups(s.nblk);
 }
 
 // the batched carve: blocks and groups per pair from the host offsets
 void carve_batched(Carver &c, int n_pairs, const int64_t *src_off, const int64_t *tgt_off, int iters_max,
                    IcpStore &s, std::vector<int32_t> *boff, std::vector<int32_t> *goff)
 {
-    int64_t nblk = 0, ngrp = 0;
+    int64_t cap_b = 0, cap_g = 0, nblk = 0, ngrp = 0;
+    const int threads = g_tune.icp_block_threads;
     if (boff) boff->assign(1, 0);
     if (goff) goff->assign(1, 0);
     for (int p = 0; p < n_pairs; p++) {
-        int64_t b = icp_blocks(src_off[p + 1] - src_off[p]);
+        int64_t ns = src_off[p + 1] - src_off[p];
+        cap_b += icp_blocks_max(ns);
+        cap_g += icp_groups(icp_blocks_max(ns));
+        int64_t b = icp_blocks(ns, threads);
         nblk += b;
         ngrp += icp_groups(b);
         if (boff) boff->push_back((int32_t)nblk);
         if (goff) goff->push_back((int32_t)ngrp);
     }
-    icp_carve(c, n_pairs, src_off[n_pairs], tgt_off[n_pairs], nblk, ngrp, iters_max, s);
+    icp_carve(c, n_pairs, src_off[n_pairs], tgt_off[n_pairs], cap_b, cap_g, iters_max, s);
+    tune(s);
+    s.nblk = (int)nblk;
+    s.ngrp = (int)ngrp;
 }
 
 }  // namespace
@@ -293,5 +317,21 @@ pc_status pc_set_kernel_timer(hipEvent_t *begin, hipEvent_t *end, int capacity)
 }
 
 int pc_kernel_timer_count(void) { return icp_timer_count(); }
+
+pc_status pc_set_tuning(const pc_tuning *t)
+{
+    if (!t) return PC_EINVAL;
+    int b = t->icp_block_threads, l = t->icp_leaf;
+    if (b != 64 && b != 128 && b != 256) return PC_EINVAL;
+    if (l != 8 && l != 16 && l != 32) return PC_EINVAL;
+    if (!(t->node_budget >= 0.125f && t->node_budget <= 1.0f)) return PC_EINVAL;
+    g_tune = *t;
+    return PC_OK;
+}
+
+void pc_get_tuning(pc_tuning *t)
+{
+    if (t) *t = g_tune;
+}
 
 }  // extern "C"

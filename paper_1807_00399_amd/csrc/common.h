@@ -270,6 +270,7 @@ struct GridStore {
     int n_clouds;
     int64_t max_nodes;
     int64_t hash_slots_max;
+    float node_budget;        // nodes allowed per point when picking a cloud's finest level (<= 1)
     int nblk_sort, nblk_lvl;
     GridView view() const
     {

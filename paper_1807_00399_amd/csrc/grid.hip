@@ -309,11 +309,11 @@ __global__ void k_slev(const uint64_t *__restrict__ keys, int64_t n, uint32_t *_
 }
 
 // Per cloud: node counts per level from the slev histogram, the finest level
-// (the finest such that the levels from there up hold at most n nodes, so
-// leaves are as small as a node budget of one per point allows, also where
-// the density is far above the mean), and the size of its hash region.
+// (the finest such that the levels from there up hold at most budget * n
+// nodes, so leaves are as small as that node budget allows, also where the
+// density is far above the mean), and the size of its hash region.
 // clev[c] becomes the cloud's node count per level (0 below its lmin).
-__global__ void k_cloud_levels(int nc, int32_t *__restrict__ clev, GridParams *__restrict__ P)
+__global__ void k_cloud_levels(int nc, int32_t *__restrict__ clev, GridParams *__restrict__ P, float budget)
 {
     int c = blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= nc) return;
@@ -325,11 +325,13 @@ __global__ void k_cloud_levels(int nc, int32_t *__restrict__ clev, GridParams *_
         cnt[l] = run;           // points opening a cell at level >= l = cells at level l
     }
     int64_t n = P[c].n;
+    int64_t cap = (int64_t)((double)budget * (double)n);
+    if (cap < 1) cap = 1;
     int lmin = kLevels - 1;
     int64_t cum = 0;
     for (int l = kLevels - 1; l >= 0; l--) {
         cum += cnt[l];
-        if (cum > (n > 1 ? n : 1)) break;
+        if (cum > cap) break;
         lmin = l;
     }
     int32_t nodes = 0;
@@ -601,6 +603,7 @@ void grid_carve(Carver &c, int64_t n, int n_clouds, GridStore &g)
     g.max_nodes = max_pyramid_nodes(nn, nc);
     // a cloud's region holds max(64, 2 x its nodes) slots
     g.hash_slots_max = 2 * g.max_nodes + 64 * (int64_t)nc;
+    g.node_budget = 1.0f;
     g.params = c.take<GridParams>(nc);
     g.layout = c.take<GridLayout>(1);
     g.off = c.take<int64_t>(nc + 1);
@@ -665,7 +668,8 @@ hipError_t grid_build(GridStore &g, const float *xyz, hipStream_t s)
         k_gather_pts<<<blocks_for(n, T), T, 0, s>>>(xyz, g.idx, n, g.pts);
         k_slev<<<blocks_for(n, T), T, 0, s>>>(g.keys, n, g.slev, g.clev);
     }
-    k_cloud_levels<<<blocks_for(nc, T), T, 0, s>>>(nc, g.clev, g.params);
+    float budget = g.node_budget > 0.f && g.node_budget <= 1.f ? g.node_budget : 1.f;
+    k_cloud_levels<<<blocks_for(nc, T), T, 0, s>>>(nc, g.clev, g.params, budget);
     k_layout<<<1, 1024, 0, s>>>(nc, g.clev, g.params, g.layout);
     if (n > 0) {
         k_level_count<<<g.nblk_lvl, kLvlThreads, 0, s>>>(g.slev, g.keys, n, g.params, g.level_block);

@@ -29,10 +29,15 @@ struct IcpStore {
     double *hist;       // per pair and iteration: increment, inliers, sum r^2
     int hist_stride;    // doubles per pair in hist
     int np, nblk, ngrp, iters_max;
+    int threads;        // accumulate block size (64, 128 or 256)
+    int leaf;           // largest node scanned as a leaf by the search (8, 16 or 32)
 };
 
-// blocks of the accumulate kernel for ns source points, groups for nblk blocks
-int64_t icp_blocks(int64_t ns);
+// blocks of the accumulate kernel for ns source points with `threads` per
+// block (icp_blocks_max: the smallest block size, which sizes the
+// workspace); groups for nblk blocks
+int64_t icp_blocks(int64_t ns, int threads);
+int64_t icp_blocks_max(int64_t ns);
 int64_t icp_groups(int64_t nblk);
 void icp_carve(Carver &c, int np, int64_t ns, int64_t nt, int64_t nblk, int64_t ngrp, int iters_max,
                IcpStore &s);

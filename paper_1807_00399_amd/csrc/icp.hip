@@ -24,13 +24,7 @@
 namespace pcg {
 
 constexpr int kAcc = 28;            // 21 (A) + 6 (b) + 1 (sum r^2)
-#ifndef PCG_ICP_THREADS
-#define PCG_ICP_THREADS 128
-#endif
-#ifndef PCG_ICP_ATTR
-#define PCG_ICP_ATTR
-#endif
-constexpr int kIcpThreads = PCG_ICP_THREADS;   // one source point per lane
+constexpr int kIcpMinThreads = 64;  // smallest accumulate block: sizes the workspace
 constexpr int kFinThreads = 1024;
 constexpr int kGroup = 64;          // block partials merged per k_icp_reduce block
 
@@ -238,7 +232,8 @@ __device__ inline int pair_of(const int32_t *__restrict__ off, int np, int b)
 // its pose).  Each block writes its compensated partial sums; k_icp_reduce
 // and the finalize kernel merge them in block order, so the result does not
 // depend on scheduling (no atomics, no fences in the hot kernel).
-__global__ void __launch_bounds__(kIcpThreads) PCG_ICP_ATTR
+template <int NT, int LEAF>
+__global__ void __launch_bounds__(NT)
 k_icp_accum(GridView g, const float *__restrict__ src, const int64_t *__restrict__ soff,
             const int32_t *__restrict__ boff, int np, const float4 *__restrict__ nrm, int2 *__restrict__ prev,
             const IcpState *__restrict__ state, const float *__restrict__ dmaxv, int final_pass,
@@ -246,10 +241,10 @@ k_icp_accum(GridView g, const float *__restrict__ src, const int64_t *__restrict
 {
     // the DFS stack and, after the search, the reduction buffer share LDS
     constexpr int kHalf = kAcc / 2;                       // accumulators per reduction pass
-    constexpr int kRow = kIcpThreads + 1;                 // padded row (bank spread)
-    static_assert(kHalf * kRow <= kStack * kIcpThreads, "reduction buffer must fit in the stack");
-    __shared__ uint32_t stk[kStack * kIcpThreads];
-    __shared__ uint32_t wcnt[kIcpThreads / 64];
+    constexpr int kRow = NT + 1;                          // padded row (bank spread)
+    static_assert(kHalf * kRow <= kStack * NT, "reduction buffer must fit in the stack");
+    __shared__ uint32_t stk[kStack * NT];
+    __shared__ uint32_t wcnt[NT / 64];
     const int lblk = xcd_block(blockIdx.x, nblk);
     const int pr = np > 1 ? pair_of(boff, np, lblk) : 0;
     const IcpState *st = state + pr;
@@ -264,7 +259,7 @@ k_icp_accum(GridView g, const float *__restrict__ src, const int64_t *__restrict
     const float dmax = dmaxv[pr];
     const double dmax64 = (double)dmax;
     const float dmax2 = dmax * dmax;
-    const int64_t i = soff[pr] + (int64_t)(lblk - boff[pr]) * kIcpThreads + threadIdx.x;
+    const int64_t i = soff[pr] + (int64_t)(lblk - boff[pr]) * NT + threadIdx.x;
     const bool active = i < soff[pr + 1] && P.n > 0;
     int32_t j = -1;
     float hx = 0.f, lx = 0.f, hy = 0.f, ly = 0.f, hz = 0.f, lz = 0.f;   // double-float p'
@@ -288,7 +283,7 @@ k_icp_accum(GridView g, const float *__restrict__ src, const int64_t *__restrict
             v.visit(q.x, q.y, q.z, (uint32_t)pv.x, p0, (uint32_t)pv.y);
             if (v.best_pos >= 0) done = search_in_node(g, P, q, v, (uint32_t)pv.y, p0);
         }
-        if (!done) search<NearBand, 16>(g, P, q, v, 1, stk + threadIdx.x, kIcpThreads);
+        if (!done) search<NearBand, LEAF>(g, P, q, v, 1, stk + threadIdx.x, NT);
         prev[i] = v.best_pos >= 0 ? make_int2(v.best_pos, (int32_t)v.best_node) : make_int2(-1, -1);
         if (v.best_pos >= 0) {
             float b = v.best_key();
@@ -309,7 +304,7 @@ k_icp_accum(GridView g, const float *__restrict__ src, const int64_t *__restrict
                 w.best_orig = 0xffffffffu;
                 w.best_pos = -1;
                 w.r2 = b + 2.f * e;
-                cover<Near64, 16>(g, P, q, w, stk + threadIdx.x, kIcpThreads, 0u, 0u);
+                cover<Near64, LEAF>(g, P, q, w, stk + threadIdx.x, NT, 0u, 0u);
                 j = w.best_pos;
             }
         }
@@ -340,8 +335,8 @@ k_icp_accum(GridView g, const float *__restrict__ src, const int64_t *__restrict
     // in a fixed order: in two passes of 14 sums, every lane stores its
     // products in LDS, then kLanes lanes per sum each accumulate 16 of them
     // with TwoSum and merge their pairs across the kLanes lanes.
-    constexpr int kLanes = kIcpThreads / 16;
-    static_assert(kHalf * kLanes <= kIcpThreads, "one lane per (sum, share)");
+    constexpr int kLanes = NT / 16;
+    static_assert(kHalf * kLanes <= NT, "one lane per (sum, share)");
     const int tid = threadIdx.x, w = tid >> 6;
     float *red = reinterpret_cast<float *>(stk);
     const int ra = tid / kLanes, rk = tid % kLanes;       // sum handled, share
@@ -379,7 +374,7 @@ k_icp_accum(GridView g, const float *__restrict__ src, const int64_t *__restrict
     __syncthreads();
     if (tid == 0) {
         uint32_t c = 0;
-        for (int x = 0; x < kIcpThreads / 64; x++) c += wcnt[x];
+        for (int x = 0; x < NT / 64; x++) c += wcnt[x];
         pcnt[lblk] = c;
     }
 }
@@ -606,6 +601,8 @@ void icp_carve(Carver &c, int np, int64_t ns, int64_t nt, int64_t nblk, int64_t 
     s.np = np1;
     s.nblk = (int)nblk;
     s.ngrp = (int)ngrp;
+    s.threads = kIcpMinThreads;
+    s.leaf = 16;
     s.iters_max = iters_max > 0 ? iters_max : 0;
     s.nrm = c.take<float4>(nt1);
     s.prev = c.take<int2>(ns1);
@@ -623,7 +620,8 @@ void icp_carve(Carver &c, int np, int64_t ns, int64_t nt, int64_t nblk, int64_t 
     s.hist = c.take<double>((size_t)s.hist_stride * np1);
 }
 
-int64_t icp_blocks(int64_t ns) { return (ns + kIcpThreads - 1) / kIcpThreads; }
+int64_t icp_blocks(int64_t ns, int threads) { return (ns + threads - 1) / threads; }
+int64_t icp_blocks_max(int64_t ns) { return icp_blocks(ns, kIcpMinThreads); }
 int64_t icp_groups(int64_t nblk) { return (nblk + kGroup - 1) / kGroup; }
 
 hipError_t icp_layout_single(IcpStore &s, int64_t ns, int64_t nt, float dmax, int max_iters, hipStream_t st)
@@ -631,6 +629,28 @@ hipError_t icp_layout_single(IcpStore &s, int64_t ns, int64_t nt, float dmax, in
     k_single_pair<<<1, 1, 0, st>>>(ns, nt, s.nblk, s.ngrp, dmax, max_iters, s.soff, s.grid.off, s.boff, s.goff,
                                    s.dmax, s.maxit);
     return hipGetLastError();
+}
+
+template <int NT, int LEAF>
+static void launch_accum_t(IcpStore &s, const float *src, int fin, hipStream_t st)
+{
+    k_icp_accum<NT, LEAF><<<s.nblk, NT, 0, st>>>(s.grid.view(), src, s.soff, s.boff, s.np, s.nrm, s.prev, s.st,
+                                                 s.dmax, fin, s.part, s.pcnt, s.nblk);
+}
+
+template <int NT>
+static void launch_accum_leaf(IcpStore &s, const float *src, int fin, hipStream_t st)
+{
+    if (s.leaf <= 8) launch_accum_t<NT, 8>(s, src, fin, st);
+    else if (s.leaf <= 16) launch_accum_t<NT, 16>(s, src, fin, st);
+    else launch_accum_t<NT, 32>(s, src, fin, st);
+}
+
+static void launch_accum(IcpStore &s, const float *src, int fin, hipStream_t st)
+{
+    if (s.threads <= 64) launch_accum_leaf<64>(s, src, fin, st);
+    else if (s.threads <= 128) launch_accum_leaf<128>(s, src, fin, st);
+    else launch_accum_leaf<256>(s, src, fin, st);
 }
 
 hipError_t icp_run(IcpStore &s, const float *src, int64_t ns, const float *tgt, const float *tgt_n,
@@ -652,8 +672,7 @@ hipError_t icp_run(IcpStore &s, const float *src, int64_t ns, const float *tgt, 
         const bool timed = !fin && pass < g_tcap;
         if (s.nblk > 0) {
             if (timed) (void)hipEventRecord(g_tbeg[pass], st);
-            k_icp_accum<<<s.nblk, kIcpThreads, 0, st>>>(s.grid.view(), src, s.soff, s.boff, np, s.nrm, s.prev,
-                                                        s.st, s.dmax, fin, s.part, s.pcnt, s.nblk);
+            launch_accum(s, src, fin, st);
             if (timed) {
                 (void)hipEventRecord(g_tend[pass], st);
                 g_tcount = pass + 1;

@@ -28,7 +28,14 @@ EXPORTS = (
     "estimate_normals_batched_workspace_size", "estimate_normals_batched",
     "icp_point_to_plane_batched_workspace_size", "icp_point_to_plane_batched",
     "pc_copy_probe", "icp_history", "pc_set_kernel_timer", "pc_kernel_timer_count",
+    "pc_set_tuning", "pc_get_tuning",
 )
+
+
+class Tuning(ctypes.Structure):
+    """pc_tuning: accumulate block size, ICP leaf size, pyramid node budget."""
+    _fields_ = [("icp_block_threads", ctypes.c_int32), ("icp_leaf", ctypes.c_int32),
+                ("node_budget", ctypes.c_float)]
 
 
 class PcgpuError(RuntimeError):
@@ -73,6 +80,10 @@ def _load() -> ctypes.CDLL:
     lib.pc_set_kernel_timer.restype = ctypes.c_int
     lib.pc_kernel_timer_count.argtypes = []
     lib.pc_kernel_timer_count.restype = ctypes.c_int
+    lib.pc_set_tuning.argtypes = [ctypes.POINTER(Tuning)]
+    lib.pc_set_tuning.restype = ctypes.c_int
+    lib.pc_get_tuning.argtypes = [ctypes.POINTER(Tuning)]
+    lib.pc_get_tuning.restype = None
     return lib
 
 
@@ -288,6 +299,17 @@ def decode_stats_batched(stats: torch.Tensor) -> list:
     raw = stats.cpu().numpy().tobytes()
     recs = np.frombuffer(raw, dtype=np.dtype(STATS_DTYPE))
     return [{name: r[name].item() for name, _ in STATS_DTYPE} for r in recs]
+
+
+def set_tuning(icp_block_threads: int = 128, icp_leaf: int = 16, node_budget: float = 1.0):
+    t = Tuning(int(icp_block_threads), int(icp_leaf), float(node_budget))
+    _check(lib.pc_set_tuning(ctypes.byref(t)), "pc_set_tuning")
+
+
+def get_tuning() -> dict:
+    t = Tuning()
+    lib.pc_get_tuning(ctypes.byref(t))
+    return {"icp_block_threads": t.icp_block_threads, "icp_leaf": t.icp_leaf, "node_budget": t.node_budget}
 
 
 def copy_probe(dst: torch.Tensor, src: torch.Tensor, stream=None):

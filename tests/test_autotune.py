@@ -1,0 +1,49 @@
+"""Autotuner logic on the CPU: tuning validation through the C ABI, choice of
+the fastest candidate, and the cache round trip (no device work)."""
+import pytest
+
+
+@pytest.fixture(scope="module")
+def pc():
+    from paper_1807_00399_amd import pcgpu
+    yield pcgpu
+    pcgpu.set_tuning(128, 16, 1.0)
+
+
+def test_tuning_validation(pc):
+    pc.set_tuning(64, 32, 0.5)
+    assert pc.get_tuning() == {"icp_block_threads": 64, "icp_leaf": 32, "node_budget": 0.5}
+    for bad in ((96, 16, 1.0), (128, 12, 1.0), (128, 16, 1.5), (128, 16, 0.0)):
+        with pytest.raises(pc.PcgpuError):
+            pc.set_tuning(*bad)
+    assert pc.get_tuning()["icp_block_threads"] == 64      # unchanged by rejected calls
+    pc.set_tuning(128, 16, 1.0)
+
+
+def test_tune_picks_fastest_and_caches(pc, tmp_path):
+    from paper_1807_00399_amd import autotune
+    # a fake step whose cost depends on the current tuning
+    cost = {(b, l, nb): 1.0 + abs(b - 256) / 64 + abs(l - 8) / 8 + (1.0 - nb) for b, l, nb in autotune.CANDIDATES}
+    clock = {"t": 0.0}
+
+    def step():
+        t = pc.get_tuning()
+        clock["t"] += cost[(t["icp_block_threads"], t["icp_leaf"], t["node_budget"])]
+
+    cache = str(tmp_path / "tune.json")
+    r = autotune.tune(step, "fake", 1 << 20, device_name="dev0", cache_file=cache, sync=lambda: None,
+                      clock=lambda: clock["t"])
+    assert not r["from_cache"]
+    assert r["tuning"] == {"icp_block_threads": 256, "icp_leaf": 8, "node_budget": 1.0}
+    assert pc.get_tuning() == r["tuning"]
+    assert len(r["timings"]) == len(autotune.CANDIDATES)
+    pc.set_tuning(128, 16, 1.0)
+    # same device, tag and size bucket: served from the cache and applied
+    r2 = autotune.tune(step, "fake", (1 << 20) + 5, device_name="dev0", cache_file=cache, sync=lambda: None,
+                       clock=lambda: clock["t"])
+    assert r2["from_cache"] and r2["tuning"] == r["tuning"] and pc.get_tuning() == r["tuning"]
+    # another size bucket is tuned again
+    r3 = autotune.tune(step, "fake", 1 << 10, device_name="dev0", cache_file=cache, sync=lambda: None,
+                       clock=lambda: clock["t"])
+    assert not r3["from_cache"]
+    assert set(autotune.load_cache(cache)) == {"dev0|fake|20", "dev0|fake|10"}

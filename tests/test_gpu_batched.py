@@ -171,3 +171,51 @@ def test_batched_full_workload_sampled(gpu, oracle_mod):
         ro = oracle_mod.icp(w.source, w.target, bn[off[j]:off[j + 1]], None, float(np.float32(w.d_max)), w.iters)
         ea, et = pose_err(T[j], ro["T"])
         assert ea <= ROT_TOL and et <= TRANS_TOL, (j, ea, et)
+
+
+def test_tunings_give_the_same_results(gpu, oracle_mod, small_batch):
+    # every launch shape and pyramid depth finds the same correspondences;
+    # the block size only regroups the compensated sums (~1e-14 relative)
+    b = small_batch
+    off = b.offsets
+    nrms = np.vstack([oracle_mod.normals(w.target, w.k, (0, 0, 0))[0].astype(np.float32) for w in b.pairs])
+    args = (_dev(b.source), off, _dev(b.target), _dev(nrms), off, None, b.param("d_max").astype(np.float32),
+            b.param("iters").astype(np.int32))
+    ref_T, ref_st = None, None
+    try:
+        for tb in (64, 128, 256):
+            for leaf in (8, 16, 32):
+                for nb in (0.25, 1.0):
+                    gpu.set_tuning(tb, leaf, nb)
+                    _say(f"tuning {tb} {leaf} {nb}")
+                    T, st = gpu.icp_point_to_plane_batched(*args)
+                    T = T.cpu().numpy()
+                    nn, _ = gpu.estimate_normals_batched(_dev(b.target), off, b.param("k").astype(np.int32))
+                    if ref_T is None:
+                        ref_T, ref_st, ref_n = T, st, nn.cpu().numpy()
+                        continue
+                    assert np.array_equal(nn.cpu().numpy(), ref_n)
+                    assert np.abs(T - ref_T).max() < 1e-10, (tb, leaf, nb)
+                    assert [s["inliers"] for s in st] == [s["inliers"] for s in ref_st]
+                    assert [s["status"] for s in st] == [s["status"] for s in ref_st]
+    finally:
+        gpu.set_tuning(128, 16, 1.0)
+
+
+def test_autotune_on_device(gpu, small_batch, tmp_path):
+    from paper_1807_00399_amd import autotune
+    b = small_batch
+    off = b.offsets
+    src, tgt = _dev(b.source), _dev(b.target)
+    kc, dm, it = b.param("k").astype(np.int32), b.param("d_max").astype(np.float32), b.param("iters").astype(np.int32)
+
+    def step():
+        nrm, _ = gpu.estimate_normals_batched(tgt, off, kc, curvature=False)
+        gpu.icp_point_to_plane_batched(src, off, tgt, nrm, off, None, dm, it, read_stats=False)
+
+    try:
+        r = autotune.tune(step, "test_small", b.n, cache_file=str(tmp_path / "t.json"), reps=1,
+                          candidates=autotune.CANDIDATES[:4])
+        assert not r["from_cache"] and gpu.get_tuning() == r["tuning"]
+    finally:
+        gpu.set_tuning(128, 16, 1.0)
