@@ -12,9 +12,10 @@ correspondences, so the choice only affects speed.
 
 `step` runs the work to be tuned on the current stream; each candidate is
 timed over a few runs (after one warm-up run) and the fastest is set with
-pc_set_tuning and stored in a JSON cache keyed by (device name, workload
-tag, size bucket = floor(log2(points))), so later processes reuse it.  The
-cache file is $PCGPU_TUNE_CACHE or ~/.cache/pcgpu/tuning.json.
+pc_set_tuning and stored in a JSON cache keyed by (device = gfx
+architecture and compute units, workload tag, size bucket =
+floor(log2(points))), so later processes reuse it.  The cache file is
+$PCGPU_TUNE_CACHE or ~/.cache/pcgpu/tuning.json.
 """
 from __future__ import annotations
 
@@ -66,10 +67,16 @@ def _store(key: str, entry: dict, path: str | None = None):
 
 
 def _device_name(device_name):
+    """Cache key of the current device: gfx architecture and compute units
+    (e.g. "gfx950:256cu"), which marketing names do not pin down."""
     if device_name is not None:
         return device_name
     import torch
-    return torch.cuda.get_device_name() if torch.cuda.is_available() else "cpu"
+    if not torch.cuda.is_available():
+        return "cpu"
+    props = torch.cuda.get_device_properties(torch.cuda.current_device())
+    arch = getattr(props, "gcnArchName", props.name).split(":")[0]
+    return f"{arch}:{props.multi_processor_count}cu"
 
 
 def _sync():
