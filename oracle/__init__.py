@@ -17,6 +17,16 @@ Parity status of each function (what pins it lives in ``tests/``):
   icp                 pinned by closed-form Kabsch alignment on noiseless
                       copies, recovery of known transforms, equivariance and
                       quadratic convergence.
+  rigid_fit           pinned by exact recovery of known motions, Horn's
+                      quaternion method (numpy eigh), reflections, and
+                      brute-force search over nearby rotations.
+  icp_p2p             pinned by one-step recovery from exact correspondences
+                      and convergence to the ground truth.
+  combined_system     pinned to p2plane_system at weights (0, 1), to the
+                      analytic point-to-point blocks, and by finite
+                      differences of the weighted objective.
+  icp_combined        pinned by recovery of known transforms and by equality
+                      with icp at weights (0, 1).
 """
 from __future__ import annotations
 
@@ -74,6 +84,16 @@ def _load():
         lib.oracle_icp.argtypes = [_f32p, ctypes.c_int64, _f32p, _f32p, ctypes.c_int64,
                                    ctypes.c_void_p, ctypes.c_double, ctypes.c_int, ctypes.c_double,
                                    ctypes.c_int, _f64p, _i32p, _i64p, _f64p, ctypes.c_void_p]
+        lib.oracle_rigid_fit.argtypes = [_f64p, _f64p, ctypes.c_int64, _f64p, _f64p, _f64p, _f64p]
+        lib.oracle_icp_p2p.argtypes = [_f32p, ctypes.c_int64, _f32p, ctypes.c_int64, ctypes.c_void_p,
+                                       ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_int, _f64p,
+                                       _i32p, _i64p, _f64p]
+        lib.oracle_combined_system.argtypes = [_f32p, ctypes.c_int64, _f32p, _f32p, ctypes.c_int64, _f64p,
+                                               ctypes.c_double, ctypes.c_double, ctypes.c_double, _f64p, _f64p,
+                                               _i64p, _f64p]
+        lib.oracle_icp_combined.argtypes = [_f32p, ctypes.c_int64, _f32p, _f32p, ctypes.c_int64, ctypes.c_void_p,
+                                            ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
+                                            ctypes.c_double, ctypes.c_int, _f64p, _i32p, _i64p, _f64p]
         lib.oracle_num_threads.argtypes = []
         _lib = lib
     return _lib
@@ -175,3 +195,62 @@ def icp(src, tgt, tgt_normals, T_init=None, d_max: float = 0.1, max_iters: int =
     it = int(si[1])
     return dict(T=T.reshape(4, 4), status=int(si[0]), iterations=it, inliers=int(si64[0]),
                 rms=float(sd[0]), x_hist=xh[:it].copy())
+
+
+def rigid_fit(p, q):
+    """Least-squares rigid motion p -> q (closed form).  Returns (R (3,3),
+    t (3,), top, gap): the rotation is unique when gap > 0."""
+    p = np.ascontiguousarray(p, dtype=np.float64).reshape(-1, 3)
+    q = np.ascontiguousarray(q, dtype=np.float64).reshape(-1, 3)
+    R, t, top, gap = np.empty(9), np.empty(3), np.empty(1), np.empty(1)
+    if _load().oracle_rigid_fit(p, q, p.shape[0], R, t, top, gap):
+        raise ValueError("rigid_fit needs at least one pair")
+    return R.reshape(3, 3), t, float(top[0]), float(gap[0])
+
+
+def _stats(T, si, si64, sd):
+    return dict(T=T.reshape(4, 4), status=int(si[0]), iterations=int(si[1]), inliers=int(si64[0]),
+                rms=float(sd[0]))
+
+
+def icp_p2p(src, tgt, T_init=None, d_max: float = 0.1, max_iters: int = 20, conv_tol: float = 0.0,
+            method: str = "kdtree"):
+    """Point-to-point ICP with the closed-form fit.  Returns dict(T, status,
+    iterations, inliers, rms)."""
+    src, tgt = _pts(src), _pts(tgt)
+    T0 = None if T_init is None else np.ascontiguousarray(T_init, dtype=np.float64).reshape(16)
+    T, si, si64, sd = np.empty(16), np.zeros(2, np.int32), np.zeros(1, np.int64), np.zeros(1)
+    rc = _load().oracle_icp_p2p(src, src.shape[0], tgt, tgt.shape[0], None if T0 is None else T0.ctypes.data,
+                                float(d_max), int(max_iters), float(conv_tol), int(method == "kdtree"), T, si,
+                                si64, sd)
+    if rc:
+        raise ValueError(f"oracle icp_p2p failed ({rc})")
+    return _stats(T, si, si64, sd)
+
+
+def combined_system(src, tgt, tgt_normals, T, d_max: float, w_point: float, w_plane: float):
+    """(A (6,6), b (6,), inliers, weighted sum of squared residuals)."""
+    src, tgt = _pts(src), _pts(tgt)
+    nrm = _pts(tgt_normals)
+    T = np.ascontiguousarray(T, dtype=np.float64).reshape(16)
+    A, b, inl, s2 = np.empty(36), np.empty(6), np.zeros(1, np.int64), np.zeros(1)
+    rc = _load().oracle_combined_system(src, src.shape[0], tgt, nrm, tgt.shape[0], T, float(d_max), float(w_point),
+                                        float(w_plane), A, b, inl, s2)
+    if rc:
+        raise ValueError(f"oracle combined_system failed ({rc})")
+    return A.reshape(6, 6), b, int(inl[0]), float(s2[0])
+
+
+def icp_combined(src, tgt, tgt_normals, T_init=None, w_point: float = 0.5, w_plane: float = 1.0,
+                 d_max: float = 0.1, max_iters: int = 20, conv_tol: float = 0.0, method: str = "kdtree"):
+    """ICP with the weighted point-to-point + point-to-plane metric."""
+    src, tgt, nrm = _pts(src), _pts(tgt), _pts(tgt_normals)
+    T0 = None if T_init is None else np.ascontiguousarray(T_init, dtype=np.float64).reshape(16)
+    T, si, si64, sd = np.empty(16), np.zeros(2, np.int32), np.zeros(1, np.int64), np.zeros(1)
+    rc = _load().oracle_icp_combined(src, src.shape[0], tgt, nrm, tgt.shape[0],
+                                     None if T0 is None else T0.ctypes.data, float(w_point), float(w_plane),
+                                     float(d_max), int(max_iters), float(conv_tol), int(method == "kdtree"), T, si,
+                                     si64, sd)
+    if rc:
+        raise ValueError(f"oracle icp_combined failed ({rc})")
+    return _stats(T, si, si64, sd)

@@ -646,3 +646,380 @@ int oracle_num_threads(void)
     return 1;
 #endif
 }
+
+/* ------------------------------------------------------------------------ */
+/* point-to-point rigid fit (closed form) and the metric variants of ICP     */
+/* (Section 3, "Iterative geometric registration": optimizers for the       */
+/* point-to-point and point-to-plane metrics and weighted combinations)      */
+/* ------------------------------------------------------------------------ */
+
+/* Singular value decomposition of a 3x3 matrix by one-sided Jacobi
+   rotations (Hestenes 1958): the columns of W = A V are made orthogonal by
+   plane rotations applied on the right.  Then s[c] = |W col c| in descending
+   order, u col c = W col c / s[c] (completed to a right-handed orthonormal
+   basis where s[c] is 0), a = u diag(s) v^T; u, v row-major. */
+static void svd3(const double a[9], double u[9], double s[3], double v[9])
+{
+    double w[9];
+    memcpy(w, a, sizeof w);
+    for (int i = 0; i < 9; i++) v[i] = (i % 4 == 0) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 64; sweep++) {
+        int rotated = 0;
+        for (int p = 0; p < 2; p++)
+            for (int q = p + 1; q < 3; q++) {
+                double alpha = 0, beta = 0, gamma = 0;
+                for (int r = 0; r < 3; r++) {
+                    alpha += w[r * 3 + p] * w[r * 3 + p];
+                    beta += w[r * 3 + q] * w[r * 3 + q];
+                    gamma += w[r * 3 + p] * w[r * 3 + q];
+                }
+                if (gamma == 0.0 || fabs(gamma) <= 1e-17 * sqrt(alpha * beta)) continue;
+                rotated = 1;
+                double zeta = (beta - alpha) / (2.0 * gamma);
+                double tt = (zeta >= 0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                double c = 1.0 / sqrt(1.0 + tt * tt), sn = c * tt;
+                for (int r = 0; r < 3; r++) {
+                    double wp = w[r * 3 + p], wq = w[r * 3 + q];
+                    w[r * 3 + p] = c * wp - sn * wq;
+                    w[r * 3 + q] = sn * wp + c * wq;
+                    double vp = v[r * 3 + p], vq = v[r * 3 + q];
+                    v[r * 3 + p] = c * vp - sn * vq;
+                    v[r * 3 + q] = sn * vp + c * vq;
+                }
+            }
+        if (!rotated) break;
+    }
+    double nrm[3];
+    for (int c = 0; c < 3; c++) nrm[c] = sqrt(w[c] * w[c] + w[3 + c] * w[3 + c] + w[6 + c] * w[6 + c]);
+    int ord[3] = {0, 1, 2};
+    for (int i = 0; i < 3; i++)
+        for (int j = i + 1; j < 3; j++)
+            if (nrm[ord[j]] > nrm[ord[i]]) { int tmp = ord[i]; ord[i] = ord[j]; ord[j] = tmp; }
+    double vs[9];
+    memcpy(vs, v, sizeof vs);
+    for (int c = 0; c < 3; c++) {
+        s[c] = nrm[ord[c]];
+        for (int r = 0; r < 3; r++) {
+            v[r * 3 + c] = vs[r * 3 + ord[c]];
+            u[r * 3 + c] = s[c] > 0 ? w[r * 3 + ord[c]] / s[c] : 0.0;
+        }
+    }
+    /* complete u where columns vanished: u2 = u0 x u1, and if needed
+       u1 = any unit vector orthogonal to u0 */
+    if (!(s[1] > 0)) {
+        double a0 = fabs(u[0]), a1 = fabs(u[3]), a2 = fabs(u[6]);
+        double e[3] = {0, 0, 0};
+        e[(a0 <= a1 && a0 <= a2) ? 0 : (a1 <= a2 ? 1 : 2)] = 1.0;
+        if (!(s[0] > 0)) { u[0] = 1; u[3] = 0; u[6] = 0; e[0] = 0; e[1] = 1; e[2] = 0; }
+        double x[3] = {u[3] * e[2] - u[6] * e[1], u[6] * e[0] - u[0] * e[2], u[0] * e[1] - u[3] * e[0]};
+        double xn = sqrt(x[0] * x[0] + x[1] * x[1] + x[2] * x[2]);
+        for (int r = 0; r < 3; r++) u[r * 3 + 1] = x[r] / xn;
+    }
+    if (!(s[2] > 0)) {
+        u[2] = u[3] * u[7] - u[6] * u[4];
+        u[5] = u[6] * u[1] - u[0] * u[7];
+        u[8] = u[0] * u[4] - u[3] * u[1];
+    }
+}
+
+static double det3(const double m[9])
+{
+    return m[0] * (m[4] * m[8] - m[5] * m[7]) - m[1] * (m[3] * m[8] - m[5] * m[6]) +
+           m[2] * (m[3] * m[7] - m[4] * m[6]);
+}
+
+/* Least-squares rigid motion between corresponding point sets p_i -> q_i
+   (Arun, Huang and Blostein 1987; the reflection case as in Umeyama 1991):
+   H = sum (p - pbar)(q - qbar)^T = U S V^T, R = V diag(1, 1, d) U^T with
+   d = sign det(V U^T), t = qbar - R pbar.  *top = s0 + s1 + d s2 and
+   *gap = 2 (s1 + d s2) are the largest eigenvalue of Horn's (1987) 4x4
+   quaternion matrix and its distance to the next one: the rotation is
+   unique when the gap is positive.  Returns 1 when n < 1. */
+int oracle_rigid_fit(const double *p, const double *q, int64_t n, double R[9], double t[3], double *top,
+                     double *gap)
+{
+    if (n < 1) return 1;
+    double pb[3] = {0, 0, 0}, qb[3] = {0, 0, 0};
+    for (int64_t i = 0; i < n; i++)
+        for (int a = 0; a < 3; a++) {
+            pb[a] += p[3 * i + a];
+            qb[a] += q[3 * i + a];
+        }
+    for (int a = 0; a < 3; a++) {
+        pb[a] /= (double)n;
+        qb[a] /= (double)n;
+    }
+    double H[9] = {0};
+    for (int64_t i = 0; i < n; i++)
+        for (int a = 0; a < 3; a++)
+            for (int b = 0; b < 3; b++) H[a * 3 + b] += (p[3 * i + a] - pb[a]) * (q[3 * i + b] - qb[b]);
+    double U[9], S[3], V[9], VUt[9];
+    svd3(H, U, S, V);
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++) {
+            double acc = 0;
+            for (int k = 0; k < 3; k++) acc += V[r * 3 + k] * U[c * 3 + k];
+            VUt[r * 3 + c] = acc;
+        }
+    double d = det3(VUt) < 0 ? -1.0 : 1.0;
+    for (int r = 0; r < 3; r++)
+        for (int c = 0; c < 3; c++)
+            R[r * 3 + c] = V[r * 3 + 0] * U[c * 3 + 0] + V[r * 3 + 1] * U[c * 3 + 1] + d * V[r * 3 + 2] * U[c * 3 + 2];
+    for (int r = 0; r < 3; r++) t[r] = qb[r] - (R[r * 3] * pb[0] + R[r * 3 + 1] * pb[1] + R[r * 3 + 2] * pb[2]);
+    if (top) *top = S[0] + S[1] + d * S[2];
+    if (gap) *gap = 2.0 * (S[1] + d * S[2]);
+    return 0;
+}
+
+/* transformed source point p' = R p + t (float64, from the float32 source) */
+static void transform_point(const double T[16], const float *ps, double p[3])
+{
+    for (int a = 0; a < 3; a++) p[a] = T[a * 4 + 0] * ps[0] + T[a * 4 + 1] * ps[1] + T[a * 4 + 2] * ps[2] + T[a * 4 + 3];
+}
+
+/* nearest target point within d_max (index or -1), as in p2plane_system */
+static int32_t nearest_within(const float *tgt, int64_t nt, const kd_tree *tree, const double p[3], double dmax2)
+{
+    double best = dmax2;
+    int32_t bj = -1;
+    if (tree) kd_nn64_rec(tree, 0, p, &best, &bj);
+    else nn64_brute(tgt, nt, p, &best, &bj);
+    return bj;
+}
+
+/* left-compose the increment (dR, dt) onto T */
+static void compose_left(double T[16], const double dR[9], const double dt[3])
+{
+    double R[9], t[3];
+    for (int r = 0; r < 3; r++) {
+        for (int c = 0; c < 3; c++) R[r * 3 + c] = T[r * 4 + c];
+        t[r] = T[r * 4 + 3];
+    }
+    for (int r = 0; r < 3; r++) {
+        for (int c = 0; c < 3; c++) {
+            double acc = 0;
+            for (int k = 0; k < 3; k++) acc += dR[r * 3 + k] * R[k * 3 + c];
+            T[r * 4 + c] = acc;
+        }
+        double acc = 0;
+        for (int k = 0; k < 3; k++) acc += dR[r * 3 + k] * t[k];
+        T[r * 4 + 3] = acc + dt[r];
+    }
+    T[12] = T[13] = T[14] = 0.0;
+    T[15] = 1.0;
+}
+
+/* Point-to-point ICP (Besl and McKay 1992).  Correspondences as in
+   oracle_icp: the nearest target point by float64 distance, ties to the
+   lower index, kept when |p' - q|^2 <= d_max^2 (normals are not used).
+   Each iteration fits the closed-form rigid motion (oracle_rigid_fit) of the
+   inlier pairs (p'_i, q_j(i)) and composes it on the left of the pose.
+   Fewer than 3 inliers, or gap <= 1e-12 top: DEGENERATE (pose kept).
+   Converged when max(|dR - I|, |dt|) < conv_tol (conv_tol > 0).  The final
+   pass gives the inliers and rms = sqrt(sum |p' - q|^2 / inliers). */
+int oracle_icp_p2p(const float *src, int64_t ns, const float *tgt, int64_t nt, const double *T_init, double d_max,
+                   int max_iters, double conv_tol, int use_kdtree, double T_out[16], int32_t stats_i[2],
+                   int64_t stats_i64[1], double stats_d[1])
+{
+    double T[16];
+    for (int i = 0; i < 16; i++) T[i] = T_init ? T_init[i] : ((i % 5 == 0) ? 1.0 : 0.0);
+    kd_tree tree;
+    int have_tree = 0;
+    if (use_kdtree) {
+        if (kd_build(&tree, tgt, nt)) { kd_free(&tree); return 2; }
+        have_tree = 1;
+    }
+    double *P = (double *)malloc(sizeof(double) * 3 * (size_t)(ns > 0 ? ns : 1));
+    double *Q = (double *)malloc(sizeof(double) * 3 * (size_t)(ns > 0 ? ns : 1));
+    int32_t *jj = (int32_t *)malloc(sizeof(int32_t) * (size_t)(ns > 0 ? ns : 1));
+    if (!P || !Q || !jj) { free(P); free(Q); free(jj); if (have_tree) kd_free(&tree); return 2; }
+    double dmax2 = d_max * d_max;
+    int status = ICP_MAXITER, it = 0;
+    int64_t inl = 0;
+    double s2 = 0;
+    for (int pass = 0;; pass++) {
+        int last = pass == max_iters;
+#pragma omp parallel for schedule(dynamic, 256)
+        for (int64_t i = 0; i < ns; i++) {
+            double p[3];
+            transform_point(T, src + 3 * i, p);
+            jj[i] = nearest_within(tgt, nt, have_tree ? &tree : NULL, p, dmax2);
+            for (int a = 0; a < 3; a++) P[3 * i + a] = p[a];
+        }
+        inl = 0;
+        s2 = 0;
+        for (int64_t i = 0; i < ns; i++) {
+            if (jj[i] < 0) continue;
+            const float *q = tgt + 3 * (int64_t)jj[i];
+            double e = 0;
+            for (int a = 0; a < 3; a++) {
+                double d = P[3 * i + a] - q[a];
+                e += d * d;
+                P[3 * inl + a] = P[3 * i + a];
+                Q[3 * inl + a] = q[a];
+            }
+            s2 += e;
+            inl++;
+        }
+        if (last) break;
+        /* stopping keeps the pose, so this pass's sums are the final ones */
+        if (inl == 0) { status = ICP_NO_INLIERS; break; }
+        double dR[9], dt[3], top, gap;
+        oracle_rigid_fit(P, Q, inl, dR, dt, &top, &gap);
+        if (inl < 3 || !(gap > 1e-12 * top)) { status = ICP_DEGENERATE; break; }
+        compose_left(T, dR, dt);
+        it++;
+        if (conv_tol > 0) {
+            double m = 0;
+            for (int r = 0; r < 3; r++) {
+                for (int c = 0; c < 3; c++) m = fmax(m, fabs(dR[r * 3 + c] - (r == c ? 1.0 : 0.0)));
+                m = fmax(m, fabs(dt[r]));
+            }
+            if (m < conv_tol) { status = ICP_CONVERGED; max_iters = pass + 1; }
+        }
+    }
+    free(P);
+    free(Q);
+    free(jj);
+    if (have_tree) kd_free(&tree);
+    memcpy(T_out, T, sizeof T);
+    stats_i[0] = status;
+    stats_i[1] = it;
+    stats_i64[0] = inl;
+    stats_d[0] = inl > 0 ? sqrt(s2 / (double)inl) : 0.0;
+    return 0;
+}
+
+/* The linearised system of the combined metric at pose T:
+       w_plane * sum ((p' - q) . n)^2 + w_point * sum |p' - q|^2
+   with the motion p' -> p' + omega x p' + tau, x = (omega, tau):
+       J_plane = [p' x n, n]              (1 x 6), r_plane = (p' - q) . n
+       J_point = [-[p']_x, I]             (3 x 6), r_point = p' - q
+   where [a]_x b = a x b;  A = w_plane J_plane^T J_plane + w_point J_point^T J_point,
+   b = w_plane J_plane^T r_plane + w_point J_point^T r_point, and the weighted
+   residual sum w_plane r_plane^2 + w_point |r_point|^2.  Inliers as in
+   p2plane_system (n != 0 required only when w_plane > 0); sums in source
+   order. */
+static int combined_system(const float *src, int64_t ns, const float *tgt, const float *nrm, int64_t nt,
+                           const kd_tree *tree, const double T[16], double d_max, double w_point, double w_plane,
+                           double A[36], double b[6], int64_t *inliers, double *sum_r2)
+{
+    double *rows = (double *)malloc(sizeof(double) * 43 * (size_t)(ns > 0 ? ns : 1));
+    int32_t *jj = (int32_t *)malloc(sizeof(int32_t) * (size_t)(ns > 0 ? ns : 1));
+    if (!rows || !jj) { free(rows); free(jj); return 2; }
+    double dmax2 = d_max * d_max;
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < ns; i++) {
+        double p[3];
+        transform_point(T, src + 3 * i, p);
+        int32_t bj = nearest_within(tgt, nt, tree, p, dmax2);
+        int ok = bj >= 0;
+        const float *q = tgt + 3 * (int64_t)(ok ? bj : 0);
+        if (ok && w_plane > 0) {
+            const float *nq = nrm + 3 * (int64_t)bj;
+            ok = nq[0] != 0.f || nq[1] != 0.f || nq[2] != 0.f;
+        }
+        jj[i] = ok ? bj : -1;
+        if (!ok) continue;
+        /* rows: [0..5] J_plane, [6] r_plane, [7..24] J_point (3 x 6),
+           [25..27] r_point */
+        double *R = rows + 43 * i;
+        double n[3] = {0, 0, 0};
+        if (w_plane > 0) {
+            const float *nq = nrm + 3 * (int64_t)bj;
+            n[0] = nq[0]; n[1] = nq[1]; n[2] = nq[2];
+        }
+        R[0] = p[1] * n[2] - p[2] * n[1];
+        R[1] = p[2] * n[0] - p[0] * n[2];
+        R[2] = p[0] * n[1] - p[1] * n[0];
+        R[3] = n[0]; R[4] = n[1]; R[5] = n[2];
+        R[6] = (p[0] - q[0]) * n[0] + (p[1] - q[1]) * n[1] + (p[2] - q[2]) * n[2];
+        double skew[9] = {0, -p[2], p[1], p[2], 0, -p[0], -p[1], p[0], 0};   /* [p']_x */
+        for (int r = 0; r < 3; r++)
+            for (int c = 0; c < 6; c++)
+                R[7 + r * 6 + c] = c < 3 ? -skew[r * 3 + c] : (c - 3 == r ? 1.0 : 0.0);
+        for (int a = 0; a < 3; a++) R[25 + a] = p[a] - q[a];
+    }
+    for (int i = 0; i < 36; i++) A[i] = 0;
+    for (int i = 0; i < 6; i++) b[i] = 0;
+    int64_t cnt = 0;
+    double s2 = 0;
+    for (int64_t i = 0; i < ns; i++) {
+        if (jj[i] < 0) continue;
+        const double *R = rows + 43 * i;
+        const double *Jpl = R, *Jpt = R + 7, *rpt = R + 25;
+        for (int r = 0; r < 6; r++) {
+            for (int c = 0; c < 6; c++) {
+                double pt = 0;
+                for (int k = 0; k < 3; k++) pt += Jpt[k * 6 + r] * Jpt[k * 6 + c];
+                A[r * 6 + c] += w_plane * Jpl[r] * Jpl[c] + w_point * pt;
+            }
+            double bpt = 0;
+            for (int k = 0; k < 3; k++) bpt += Jpt[k * 6 + r] * rpt[k];
+            b[r] += w_plane * Jpl[r] * R[6] + w_point * bpt;
+        }
+        s2 += w_plane * R[6] * R[6] + w_point * (rpt[0] * rpt[0] + rpt[1] * rpt[1] + rpt[2] * rpt[2]);
+        cnt++;
+    }
+    free(rows);
+    free(jj);
+    *inliers = cnt;
+    *sum_r2 = s2;
+    return 0;
+}
+
+int oracle_combined_system(const float *src, int64_t ns, const float *tgt, const float *nrm, int64_t nt,
+                           const double T[16], double d_max, double w_point, double w_plane, double A[36],
+                           double b[6], int64_t *inliers, double *sum_r2)
+{
+    return combined_system(src, ns, tgt, nrm, nt, NULL, T, d_max, w_point, w_plane, A, b, inliers, sum_r2);
+}
+
+/* ICP with the combined metric: as oracle_icp with combined_system in place
+   of the point-to-plane system (Cholesky solve, Rz(gamma) Ry(beta) Rx(alpha)
+   applied on the left, fewer than 6 inliers or a failed pivot:
+   DEGENERATE); rms = sqrt(weighted residual sum / inliers). */
+int oracle_icp_combined(const float *src, int64_t ns, const float *tgt, const float *nrm, int64_t nt,
+                        const double *T_init, double w_point, double w_plane, double d_max, int max_iters,
+                        double conv_tol, int use_kdtree, double T_out[16], int32_t stats_i[2],
+                        int64_t stats_i64[1], double stats_d[1])
+{
+    double T[16];
+    for (int i = 0; i < 16; i++) T[i] = T_init ? T_init[i] : ((i % 5 == 0) ? 1.0 : 0.0);
+    kd_tree tree;
+    int have_tree = 0;
+    if (use_kdtree) {
+        if (kd_build(&tree, tgt, nt)) { kd_free(&tree); return 2; }
+        have_tree = 1;
+    }
+    int status = ICP_MAXITER, it = 0;
+    double A[36], b[6], L[36], x[6];
+    int64_t inl;
+    double s2;
+    for (it = 0; it < max_iters; it++) {
+        int rc = combined_system(src, ns, tgt, nrm, nt, have_tree ? &tree : NULL, T, d_max, w_point, w_plane, A, b,
+                                 &inl, &s2);
+        if (rc) { if (have_tree) kd_free(&tree); return rc; }
+        if (inl == 0) { status = ICP_NO_INLIERS; break; }
+        if (inl < 6 || oracle_cholesky6(A, L)) { status = ICP_DEGENERATE; break; }
+        chol_solve6(L, b, x);
+        double dR[9];
+        oracle_euler_zyx(x[0], x[1], x[2], dR);
+        compose_left(T, dR, x + 3);
+        if (conv_tol > 0) {
+            double m = 0;
+            for (int a = 0; a < 6; a++) if (fabs(x[a]) > m) m = fabs(x[a]);
+            if (m < conv_tol) { status = ICP_CONVERGED; it++; break; }
+        }
+    }
+    int rc = combined_system(src, ns, tgt, nrm, nt, have_tree ? &tree : NULL, T, d_max, w_point, w_plane, A, b,
+                             &inl, &s2);
+    if (have_tree) kd_free(&tree);
+    if (rc) return rc;
+    memcpy(T_out, T, sizeof T);
+    stats_i[0] = status;
+    stats_i[1] = it;
+    stats_i64[0] = inl;
+    stats_d[0] = inl > 0 ? sqrt(s2 / (double)inl) : 0.0;
+    return 0;
+}
