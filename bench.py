@@ -65,6 +65,8 @@ def parse():
                     help="keep the default tuning instead of the autotuner's choice")
     ap.add_argument("--retune", action="store_true",
                     help="time every tuning candidate even when the tuning cache has this workload")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="batch workload: skip the one-call-per-pair comparison")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain 1 GiB device copy (bandwidth and counter calibration) and exit")
     return ap.parse_args()
@@ -252,10 +254,11 @@ def bench_batch(args):
     pts_iter = int((sizes * ran).sum())
 
     # the same pairs one call each (single-pair entry points), for comparison
-    seq_pairs = min(m, 64)
+    seq_pairs = 0 if args.no_compare else min(m, 64)
     srcs = [src[off[j]:off[j + 1]] for j in range(seq_pairs)]
     tgts = [tgt[off[j]:off[j + 1]] for j in range(seq_pairs)]
-    for rep in range(2):                       # the first round grows the workspace
+    seq_el = 0.0
+    for rep in range(2 if seq_pairs else 0):   # the first round grows the workspace
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for j in range(seq_pairs):
@@ -283,7 +286,7 @@ def bench_batch(args):
                    "pairs": m, "points_per_side": b.n},
         "mpt_iter_per_s": pts_iter / (float(np.median(loop_ms)) * 1e-3) / 1e6,
         "loop_ms": float(np.median(loop_ms)),
-        "single_call_pairs_per_s": seq_pairs / seq_el,
+        "single_call_pairs_per_s": seq_pairs / seq_el if seq_pairs else None,
         "tuning": tuning,
         "icp_status_counts": {str(k): int(v) for k, v in zip(*np.unique([r["status"] for r in st],
                                                                         return_counts=True))},
