@@ -76,12 +76,14 @@ def sphere_plane(rng: np.random.Generator, n: int = 10_000, sigma: float = 0.002
     return pts.astype(np.float32)
 
 
-def _slab_hits(d: np.ndarray, lo: np.ndarray, hi: np.ndarray) -> np.ndarray:
-    """Ray parameter of the first hit of rays from the origin with direction
-    ``d`` (m, 3) on the axis-aligned box [lo, hi]; +inf where missed."""
+def _slab_hits(d: np.ndarray, lo: np.ndarray, hi: np.ndarray, origin=None) -> np.ndarray:
+    """Ray parameter of the first hit of rays from ``origin`` (default the
+    coordinate origin) with direction ``d`` (m, 3) on the axis-aligned box
+    [lo, hi]; +inf where missed."""
+    o = np.zeros(3) if origin is None else np.asarray(origin, np.float64)
     with np.errstate(divide="ignore", invalid="ignore"):
-        t1 = (lo[None, :] - 0.0) / d
-        t2 = (hi[None, :] - 0.0) / d
+        t1 = (lo[None, :] - o[None, :]) / d
+        t2 = (hi[None, :] - o[None, :]) / d
     tn = np.max(np.minimum(t1, t2), axis=1)
     tf = np.min(np.maximum(t1, t2), axis=1)
     hit = (tn <= tf) & (tn > 0.0)
@@ -124,6 +126,47 @@ def room_scan(rng: np.random.Generator, width: int = 640, height: int = 480,
     z = t  # d.z == 1, so the ray parameter is the depth
     z = z + rng.standard_normal(z.shape) * (depth_noise * z * z)
     return (d * z[:, None]).astype(np.float32)
+
+
+def room_views(rng: np.random.Generator, width: int = 640, height: int = 480, angle_deg: float = 3.0,
+               t_norm: float = 0.03, n_boxes: int = 20, depth_noise: float = 0.003):
+    """Two depth frames of one room (the room of ``room_scan``) from two
+    cameras: camera 1 at the origin, camera 2 at the pose C = random_rigid
+    (angle_deg, t_norm) of camera 1's frame.  Returns (source, target, C,
+    intrinsics): source = frame 2 back-projected in camera 2's frame,
+    target = frame 1 in camera 1's frame, both (height*width, 3) float32 in
+    pixel raster order (an organized image; every ray hits); C maps source
+    to target coordinates; intrinsics = (fx, fy, cx, cy) of both cameras.
+    Depth noise N(0, (depth_noise z^2)^2) is drawn per frame."""
+    s = width / 640.0
+    fx = fy = 525.0 * s
+    cx, cy = (width - 1) / 2.0, (height - 1) / 2.0
+    pix = np.arange(width * height)
+    u, v = (pix % width).astype(np.float64), (pix // width).astype(np.float64)
+    d = np.column_stack([(u - cx) / fx, (v - cy) / fy, np.ones(len(pix))])
+    room_lo = np.array([-3.0, -1.5, -0.5])
+    room_hi = np.array([3.0, 1.5, 5.5])
+    boxes = []
+    for _ in range(n_boxes):
+        side = rng.uniform(0.2, 1.0, size=3)
+        cxz = np.array([rng.uniform(-2.5, 2.5), rng.uniform(1.0, 5.0)])
+        boxes.append((np.array([cxz[0] - side[0] / 2, 1.5 - side[1], cxz[1] - side[2] / 2]),
+                      np.array([cxz[0] + side[0] / 2, 1.5, cxz[1] + side[2] / 2])))
+    C = random_rigid(rng, angle_deg, t_norm)
+
+    def render(R, o):
+        dw = d @ R.T                       # ray directions in the room frame
+        with np.errstate(divide="ignore"):
+            t = np.min(np.where(dw > 0, (room_hi - o) / dw, np.where(dw < 0, (room_lo - o) / dw, np.inf)), axis=1)
+        for lo, hi in boxes:
+            t = np.minimum(t, _slab_hits(dw, lo, hi, o))
+        assert np.all(np.isfinite(t))
+        z = t + rng.standard_normal(t.shape) * (depth_noise * t * t)   # d.z == 1: t is the depth
+        return (d * z[:, None]).astype(np.float32)
+
+    target = render(np.eye(3), np.zeros(3))
+    source = render(C[:3, :3], C[:3, 3])
+    return source, target, C, (fx, fy, cx, cy)
 
 
 def street_scan(rng: np.random.Generator, n_beams: int = 64, n_az: int = 32768,

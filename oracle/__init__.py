@@ -27,6 +27,12 @@ Parity status of each function (what pins it lives in ``tests/``):
                       differences of the weighted objective.
   icp_combined        pinned by recovery of known transforms and by equality
                       with icp at weights (0, 1).
+  projective_pixels   pinned by round trips of back-projected pixels,
+                      rounding at half-pixel boundaries, points behind the
+                      camera and outside the image.
+  icp_projective      pinned by the identity pose on a frame and itself, the
+                      point-to-plane system of explicit pairs, and recovery
+                      of a camera motion from noiseless views.
 """
 from __future__ import annotations
 
@@ -94,6 +100,11 @@ def _load():
         lib.oracle_icp_combined.argtypes = [_f32p, ctypes.c_int64, _f32p, _f32p, ctypes.c_int64, ctypes.c_void_p,
                                             ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int,
                                             ctypes.c_double, ctypes.c_int, _f64p, _i32p, _i64p, _f64p]
+        lib.oracle_projective_pixels.argtypes = [_f32p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, _f64p, _f64p,
+                                                 _i64p]
+        lib.oracle_icp_projective.argtypes = [_f32p, ctypes.c_int64, _f32p, _f32p, ctypes.c_int, ctypes.c_int,
+                                              _f64p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int,
+                                              ctypes.c_double, _f64p, _i32p, _i64p, _f64p]
         lib.oracle_num_threads.argtypes = []
         _lib = lib
     return _lib
@@ -253,4 +264,35 @@ def icp_combined(src, tgt, tgt_normals, T_init=None, w_point: float = 0.5, w_pla
                                      si64, sd)
     if rc:
         raise ValueError(f"oracle icp_combined failed ({rc})")
+    return _stats(T, si, si64, sd)
+
+
+def _intrinsics(K):
+    """float32-rounded intrinsics as float64 (the C ABI takes float32)."""
+    return np.ascontiguousarray(np.asarray(K, dtype=np.float32).astype(np.float64))
+
+
+def projective_pixels(src, width: int, height: int, K, T):
+    """Candidate pixel (raster index) of every source point at pose T, -1 if none."""
+    src = _pts(src)
+    pix = np.empty(src.shape[0], np.int64)
+    _load().oracle_projective_pixels(src, src.shape[0], int(width), int(height), _intrinsics(K),
+                                     np.ascontiguousarray(T, dtype=np.float64).reshape(16), pix)
+    return pix
+
+
+def icp_projective(src, tgt, tgt_normals, width: int, height: int, K, T_init=None, d_max: float = 0.2,
+                   max_iters: int = 15, conv_tol: float = 0.0):
+    """Point-to-plane ICP with projective correspondences into the organized
+    target image (height*width, 3)."""
+    src = _pts(src)
+    tgt = np.ascontiguousarray(tgt, dtype=np.float32).reshape(-1, 3)
+    nrm = np.ascontiguousarray(tgt_normals, dtype=np.float32).reshape(-1, 3)
+    if tgt.shape[0] != width * height or nrm.shape[0] != width * height:
+        raise ValueError("organized target must have width*height points and normals")
+    T0 = None if T_init is None else np.ascontiguousarray(T_init, dtype=np.float64).reshape(16)
+    T, si, si64, sd = np.empty(16), np.zeros(2, np.int32), np.zeros(1, np.int64), np.zeros(1)
+    _load().oracle_icp_projective(src, src.shape[0], tgt, nrm, int(width), int(height), _intrinsics(K),
+                                  None if T0 is None else T0.ctypes.data, float(d_max), int(max_iters),
+                                  float(conv_tol), T, si, si64, sd)
     return _stats(T, si, si64, sd)

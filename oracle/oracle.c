@@ -1023,3 +1023,114 @@ int oracle_icp_combined(const float *src, int64_t ns, const float *tgt, const fl
     stats_d[0] = inl > 0 ? sqrt(s2 / (double)inl) : 0.0;
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* projective data association (Section 3, "Iterative geometric             */
+/* registration": correspondences by projective data association in 3D)    */
+/* ------------------------------------------------------------------------ */
+
+/* The target is an organized image: width x height pixels in raster order
+   from a pinhole camera at the target frame's origin looking along +z, with
+   intrinsics K = (fx, fy, cx, cy).  A pixel is valid when its point is
+   finite with z > 0.  The candidate of a transformed source point p' is the
+   pixel it projects to:
+       u = fx * p'x / p'z + cx,  v = fy * p'y / p'z + cy   (float64, this order)
+       iu = floor(u + 0.5),  iv = floor(v + 0.5)
+   when p'z > 0 and (iu, iv) lies in the image; -1 otherwise. */
+static int64_t project_pixel(const double p[3], int W, int H, const double K[4])
+{
+    if (!(p[2] > 0.0)) return -1;
+    double u = K[0] * p[0] / p[2] + K[2];
+    double v = K[1] * p[1] / p[2] + K[3];
+    double fu = floor(u + 0.5), fv = floor(v + 0.5);
+    if (!(fu >= 0.0 && fu < (double)W && fv >= 0.0 && fv < (double)H)) return -1;
+    return (int64_t)fv * W + (int64_t)fu;
+}
+
+static int pixel_valid(const float *q)
+{
+    return isfinite(q[0]) && isfinite(q[1]) && isfinite(q[2]) && q[2] > 0.f;
+}
+
+/* Candidate pixel of every source point at pose T (for the pins). */
+int oracle_projective_pixels(const float *src, int64_t ns, int W, int H, const double K[4], const double T[16],
+                             int64_t *pix)
+{
+    for (int64_t i = 0; i < ns; i++) {
+        double p[3];
+        transform_point(T, src + 3 * i, p);
+        pix[i] = project_pixel(p, W, H, K);
+    }
+    return 0;
+}
+
+/* The point-to-plane system of p2plane_system with projective
+   correspondences: the candidate pixel's point q and normal n, kept when the
+   pixel is valid, n != 0 and |p' - q|^2 <= d_max^2. */
+static void projective_system(const float *src, int64_t ns, const float *tgt, const float *nrm, int W, int H,
+                              const double K[4], const double T[16], double d_max, double A[36], double b[6],
+                              int64_t *inliers, double *sum_r2)
+{
+    double dmax2 = d_max * d_max;
+    for (int i = 0; i < 36; i++) A[i] = 0;
+    for (int i = 0; i < 6; i++) b[i] = 0;
+    int64_t cnt = 0;
+    double s2 = 0;
+    for (int64_t i = 0; i < ns; i++) {
+        double p[3];
+        transform_point(T, src + 3 * i, p);
+        int64_t k = project_pixel(p, W, H, K);
+        if (k < 0) continue;
+        const float *q = tgt + 3 * k, *nq = nrm + 3 * k;
+        if (!pixel_valid(q) || !(nq[0] != 0.f || nq[1] != 0.f || nq[2] != 0.f)) continue;
+        double dx = p[0] - q[0], dy = p[1] - q[1], dz = p[2] - q[2];
+        if (dx * dx + dy * dy + dz * dz > dmax2) continue;
+        double n[3] = {nq[0], nq[1], nq[2]};
+        double J[6] = {p[1] * n[2] - p[2] * n[1], p[2] * n[0] - p[0] * n[2], p[0] * n[1] - p[1] * n[0],
+                       n[0], n[1], n[2]};
+        double r = dx * n[0] + dy * n[1] + dz * n[2];
+        for (int rr = 0; rr < 6; rr++) {
+            for (int c = 0; c < 6; c++) A[rr * 6 + c] += J[rr] * J[c];
+            b[rr] += J[rr] * r;
+        }
+        s2 += r * r;
+        cnt++;
+    }
+    *inliers = cnt;
+    *sum_r2 = s2;
+}
+
+/* Point-to-plane ICP with projective correspondences: the loop of oracle_icp
+   (Cholesky, Rz Ry Rx on the left, same stopping rules and statistics). */
+int oracle_icp_projective(const float *src, int64_t ns, const float *tgt, const float *nrm, int W, int H,
+                          const double K[4], const double *T_init, double d_max, int max_iters, double conv_tol,
+                          double T_out[16], int32_t stats_i[2], int64_t stats_i64[1], double stats_d[1])
+{
+    double T[16];
+    for (int i = 0; i < 16; i++) T[i] = T_init ? T_init[i] : ((i % 5 == 0) ? 1.0 : 0.0);
+    int status = ICP_MAXITER, it = 0;
+    double A[36], b[6], L[36], x[6];
+    int64_t inl;
+    double s2;
+    for (it = 0; it < max_iters; it++) {
+        projective_system(src, ns, tgt, nrm, W, H, K, T, d_max, A, b, &inl, &s2);
+        if (inl == 0) { status = ICP_NO_INLIERS; break; }
+        if (inl < 6 || oracle_cholesky6(A, L)) { status = ICP_DEGENERATE; break; }
+        chol_solve6(L, b, x);
+        double dR[9];
+        oracle_euler_zyx(x[0], x[1], x[2], dR);
+        compose_left(T, dR, x + 3);
+        if (conv_tol > 0) {
+            double m = 0;
+            for (int a = 0; a < 6; a++) if (fabs(x[a]) > m) m = fabs(x[a]);
+            if (m < conv_tol) { status = ICP_CONVERGED; it++; break; }
+        }
+    }
+    projective_system(src, ns, tgt, nrm, W, H, K, T, d_max, A, b, &inl, &s2);
+    memcpy(T_out, T, sizeof T);
+    stats_i[0] = status;
+    stats_i[1] = it;
+    stats_i64[0] = inl;
+    stats_d[0] = inl > 0 ? sqrt(s2 / (double)inl) : 0.0;
+    return 0;
+}
