@@ -157,6 +157,69 @@ pc_status icp_point_to_plane(const float *src_xyz, int64_t n_src,
                              void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Metric variants of the same loop (Section 3, "Iterative geometric
+ * registration": point-to-point and point-to-plane metrics and weighted
+ * combinations).  Correspondences, rejection, stopping rules, statuses and
+ * the workspace (icp_point_to_plane_workspace_size) are those of
+ * icp_point_to_plane.
+ *
+ * icp_point_to_point -- Besl and McKay (1992): each iteration fits the
+ * least-squares rigid motion of the inlier pairs in closed form (centroids
+ * and cross-covariance H = sum (p' - pbar)(q - qbar)^T; rotation by Horn's
+ * 1987 unit-quaternion method, the same solution as Arun et al.'s SVD with
+ * the reflection case excluded) and composes it on the left of the pose.
+ * Fewer than 3 inliers, or a top-eigenvalue gap of Horn's matrix not above
+ * 1e-6 times that eigenvalue (no unique rotation to that relative level,
+ * e.g. nearly collinear pairs): PC_ICP_DEGENERATE.  Converged when max(|dR - I|, |dt|) < conv_tol.
+ * rms = sqrt(sum |p' - q|^2 / inliers).  No normals are used.
+ *
+ * icp_combined -- the linearised least squares of
+ *     w_plane * sum ((p' - q) . n)^2 + w_point * sum |p' - q|^2
+ * under p' -> p' + omega x p' + tau: J_plane = [p' x n, n], J_point =
+ * [-[p']_x, I]; A = w_plane J_plane^T J_plane + w_point J_point^T J_point,
+ * b likewise, solved and applied as in icp_point_to_plane;
+ * rms = sqrt(weighted sum / inliers).  w_point, w_plane finite, >= 0, not
+ * both 0; tgt_normals may be NULL when w_plane is 0.  Weights (0, 1) give
+ * icp_point_to_plane exactly.
+ * ---------------------------------------------------------------------- */
+pc_status icp_point_to_point(const float *src_xyz, int64_t n_src,
+                             const float *tgt_xyz, int64_t n_tgt,
+                             const double *init_T, float max_corr_dist, int max_iters,
+                             double conv_tol, double *out_T, pc_icp_stats *out_stats,
+                             void *workspace, size_t workspace_bytes, hipStream_t stream);
+pc_status icp_combined(const float *src_xyz, int64_t n_src,
+                       const float *tgt_xyz, const float *tgt_normals, int64_t n_tgt,
+                       const double *init_T, float w_point, float w_plane,
+                       float max_corr_dist, int max_iters, double conv_tol,
+                       double *out_T, pc_icp_stats *out_stats,
+                       void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
+ * icp_projective -- point-to-plane ICP with projective data association
+ * (Section 3, "Iterative geometric registration": correspondences by
+ * projective data association for the 3D case), for an organized target:
+ * one point per pixel of a width x height image in raster order, taken by
+ * a pinhole camera at the target frame's origin looking along +z.  A pixel
+ * is valid when its point is finite with z > 0.  Each iteration, for
+ * p' = T p in float64:
+ *     u = fx * p'x / p'z + cx,  v = fy * p'y / p'z + cy   (float64, this order)
+ *     pixel (floor(u + 0.5), floor(v + 0.5)) when p'z > 0 and inside the image;
+ * the pair (p', q = that pixel's point) is an inlier when the pixel is valid,
+ * its normal n != 0 and |p' - q|^2 <= max_corr_dist^2 (float64).  The
+ * estimator, stopping rules and statistics are those of icp_point_to_plane.
+ * No spatial index is built.
+ *   tgt_xyz, tgt_normals   (height * width, 3) float32, organized
+ *   intrinsics             (host) fx, fy (> 0), cx, cy
+ * ---------------------------------------------------------------------- */
+size_t icp_projective_workspace_size(int64_t n_src, int max_iters);
+pc_status icp_projective(const float *src_xyz, int64_t n_src,
+                         const float *tgt_xyz, const float *tgt_normals, int width, int height,
+                         const float intrinsics[4], const double *init_T,
+                         float max_corr_dist, int max_iters, double conv_tol,
+                         double *out_T, pc_icp_stats *out_stats,
+                         void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Batched forms: many clouds or pairs of uneven sizes in one call, each
  * computed exactly as the single form would compute it alone.  Clouds are
  * packed back to back; offsets (host, m + 1 entries, offsets[0] = 0,

@@ -814,7 +814,9 @@ static void compose_left(double T[16], const double dR[9], const double dt[3])
    lower index, kept when |p' - q|^2 <= d_max^2 (normals are not used).
    Each iteration fits the closed-form rigid motion (oracle_rigid_fit) of the
    inlier pairs (p'_i, q_j(i)) and composes it on the left of the pose.
-   Fewer than 3 inliers, or gap <= 1e-12 top: DEGENERATE (pose kept).
+   Fewer than 3 inliers, or gap <= 1e-6 top: DEGENERATE (pose kept): a
+   rotation fixed only to that relative level (nearly collinear pairs; float32
+   inputs are collinear only to ~1e-8) is taken as undetermined.
    Converged when max(|dR - I|, |dt|) < conv_tol (conv_tol > 0).  The final
    pass gives the inliers and rms = sqrt(sum |p' - q|^2 / inliers). */
 int oracle_icp_p2p(const float *src, int64_t ns, const float *tgt, int64_t nt, const double *T_init, double d_max,
@@ -866,7 +868,7 @@ int oracle_icp_p2p(const float *src, int64_t ns, const float *tgt, int64_t nt, c
         if (inl == 0) { status = ICP_NO_INLIERS; break; }
         double dR[9], dt[3], top, gap;
         oracle_rigid_fit(P, Q, inl, dR, dt, &top, &gap);
-        if (inl < 3 || !(gap > 1e-12 * top)) { status = ICP_DEGENERATE; break; }
+        if (inl < 3 || !(gap > 1e-6 * top)) { status = ICP_DEGENERATE; break; }
         compose_left(T, dR, dt);
         it++;
         if (conv_tol > 0) {

@@ -25,6 +25,10 @@ namespace pcg {
 
 constexpr int kAcc = 28;            // 21 (A) + 6 (b) + 1 (sum r^2)
 constexpr int kIcpMinThreads = 64;  // smallest accumulate block: sizes the workspace
+
+// ICP metrics (Section 3, "Iterative geometric registration": point-to-point
+// and point-to-plane metrics and weighted combinations of them)
+enum { kMetricPlane = 0, kMetricPoint = 1, kMetricCombined = 2 };
 constexpr int kFinThreads = 1024;
 constexpr int kGroup = 64;          // block partials merged per k_icp_reduce block
 
@@ -232,19 +236,96 @@ __device__ inline int pair_of(const int32_t *__restrict__ off, int np, int b)
 // its pose).  Each block writes its compensated partial sums; k_icp_reduce
 // and the finalize kernel merge them in block order, so the result does not
 // depend on scheduling (no atomics, no fences in the hot kernel).
-template <int NT, int LEAF>
+// Block reduction of the 28 per-lane values, error-free in (hi, lo) float
+// pairs and in a fixed order: in two passes of 14 sums, every lane stores
+// its values in LDS (red: at least 14 * (NT + 1) floats, free on entry),
+// then NT / 16 lanes per sum each accumulate 16 of them with TwoSum and
+// merge their pairs across those lanes.  Writes part[lblk] and the block's
+// inlier count pcnt[lblk].
+template <int NT>
+__device__ inline void block_partials(const float (&val)[kAcc], uint32_t cnt, float *red, float2 *__restrict__ part,
+                                      uint32_t *__restrict__ pcnt, int lblk)
+{
+    constexpr int kHalf = kAcc / 2;
+    constexpr int kRow = NT + 1;                          // padded row (bank spread)
+    constexpr int kLanes = NT / 16;
+    static_assert(kHalf * kLanes <= NT, "one lane per (sum, share)");
+    __shared__ uint32_t wcnt[NT / 64];
+    const int tid = threadIdx.x, w = tid >> 6;
+    const int ra = tid / kLanes, rk = tid % kLanes;       // sum handled, share
+#pragma unroll
+    for (int half = 0; half < 2; half++) {
+#pragma unroll
+        for (int a = 0; a < kHalf; a++) red[a * kRow + tid] = val[half * kHalf + a];
+        __syncthreads();
+        if (ra < kHalf) {
+            CSum c{0.f, 0.f};
+#pragma unroll
+            for (int k = 0; k < 16; k++) two_sum_add(c, red[ra * kRow + rk + kLanes * k]);
+#pragma unroll
+            for (int off = kLanes / 2; off > 0; off >>= 1) {
+                CSum o{__shfl_xor(c.hi, off), __shfl_xor(c.lo, off)};
+                c = csum_merge(c, o);
+            }
+            if (rk == 0) part[(int64_t)lblk * kAcc + half * kHalf + ra] = make_float2(c.hi, c.lo);
+        }
+        __syncthreads();
+    }
+    uint64_t ib = __ballot(cnt != 0);
+    if (__lane_id() == 0) wcnt[w] = (uint32_t)__popcll(ib);
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t c = 0;
+        for (int x = 0; x < NT / 64; x++) c += wcnt[x];
+        pcnt[lblk] = c;
+    }
+}
+
+// point-to-plane values of one inlier: the 21 upper-triangle entries of
+// J^T J, J^T r and r^2 for J = [p' x n, n], r = (p' - q) . n, from the
+// double-float p' = (h + l) and the target point t
+__device__ inline void plane_values(float hx, float lx, float hy, float ly, float hz, float lz, const float4 &t,
+                                    const float4 &n, float (&val)[kAcc])
+{
+    float qx = hx + lx, qy = hy + ly, qz = hz + lz;
+    // residual vector from the double-float p': (hi - q) is exact for
+    // nearby points, so it keeps the full accuracy of hi + lo
+    float dx = (hx - t.x) + lx, dy = (hy - t.y) + ly, dz = (hz - t.z) + lz;
+    float J[6], res;
+    res = __fmaf_rn(dz, n.z, __fmaf_rn(dy, n.y, dx * n.x));
+    J[0] = __fmaf_rn(qy, n.z, -qz * n.y);
+    J[1] = __fmaf_rn(qz, n.x, -qx * n.z);
+    J[2] = __fmaf_rn(qx, n.y, -qy * n.x);
+    J[3] = n.x;
+    J[4] = n.y;
+    J[5] = n.z;
+    int a = 0;
+#pragma unroll
+    for (int u = 0; u < 6; u++)
+#pragma unroll
+        for (int v = u; v < 6; v++) val[a++] = J[u] * J[v];
+#pragma unroll
+    for (int u = 0; u < 6; u++) val[21 + u] = J[u] * res;
+    val[27] = res * res;
+}
+
+// The 28 per-point values summed per block, by metric:
+//   plane, combined: the 21 upper-triangle entries of A (row-major), the 6
+//       of b, the (weighted) squared residual;
+//   point: p' - c (3), q - c (3), (p' - c)(q - c)^T (9, row-major),
+//       |p' - q|^2, zeros; c = the target cloud's cube centre.
+template <int NT, int LEAF, int METRIC>
 __global__ void __launch_bounds__(NT)
 k_icp_accum(GridView g, const float *__restrict__ src, const int64_t *__restrict__ soff,
             const int32_t *__restrict__ boff, int np, const float4 *__restrict__ nrm, int2 *__restrict__ prev,
             const IcpState *__restrict__ state, const float *__restrict__ dmaxv, int final_pass,
-            float2 *__restrict__ part, uint32_t *__restrict__ pcnt, int nblk)
+            float2 *__restrict__ part, uint32_t *__restrict__ pcnt, int nblk, float w_point, float w_plane)
 {
     // the DFS stack and, after the search, the reduction buffer share LDS
     constexpr int kHalf = kAcc / 2;                       // accumulators per reduction pass
     constexpr int kRow = NT + 1;                          // padded row (bank spread)
     static_assert(kHalf * kRow <= kStack * NT, "reduction buffer must fit in the stack");
     __shared__ uint32_t stk[kStack * NT];
-    __shared__ uint32_t wcnt[NT / 64];
     const int lblk = xcd_block(blockIdx.x, nblk);
     const int pr = np > 1 ? pair_of(boff, np, lblk) : 0;
     const IcpState *st = state + pr;
@@ -309,74 +390,117 @@ k_icp_accum(GridView g, const float *__restrict__ src, const int64_t *__restrict
             }
         }
     }
-    // Row of the linearised system for this lane's point (zero when it is
-    // not an inlier).
-    float J[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f}, res = 0.f;
+    // This lane's values of the sums (zero when it is not an inlier).
+    float val[kAcc];
+#pragma unroll
+    for (int a = 0; a < kAcc; a++) val[a] = 0.f;
     uint32_t cnt = 0;
     if (j >= 0) {
-        float4 n = nrm[j];
-        if (n.x != 0.f || n.y != 0.f || n.z != 0.f) {
+        float4 n = make_float4(0.f, 0.f, 0.f, 0.f);
+        bool use = true;
+        if (METRIC == kMetricPlane || (METRIC == kMetricCombined && w_plane > 0.f)) {
+            n = nrm[j];
+            use = n.x != 0.f || n.y != 0.f || n.z != 0.f;
+        }
+        if (use) {
             float4 t = g.pts[j];
             float qx = hx + lx, qy = hy + ly, qz = hz + lz;
             // residual vector from the double-float p': (hi - q) is exact for
             // nearby points, so it keeps the full accuracy of hi + lo
             float dx = (hx - t.x) + lx, dy = (hy - t.y) + ly, dz = (hz - t.z) + lz;
-            res = __fmaf_rn(dz, n.z, __fmaf_rn(dy, n.y, dx * n.x));
-            J[0] = __fmaf_rn(qy, n.z, -qz * n.y);
-            J[1] = __fmaf_rn(qz, n.x, -qx * n.z);
-            J[2] = __fmaf_rn(qx, n.y, -qy * n.x);
-            J[3] = n.x;
-            J[4] = n.y;
-            J[5] = n.z;
             cnt = 1;
-        }
-    }
-    // Block reduction of the 28 sums, error-free in (hi, lo) float pairs and
-    // in a fixed order: in two passes of 14 sums, every lane stores its
-    // products in LDS, then kLanes lanes per sum each accumulate 16 of them
-    // with TwoSum and merge their pairs across the kLanes lanes.
-    constexpr int kLanes = NT / 16;
-    static_assert(kHalf * kLanes <= NT, "one lane per (sum, share)");
-    const int tid = threadIdx.x, w = tid >> 6;
-    float *red = reinterpret_cast<float *>(stk);
-    const int ra = tid / kLanes, rk = tid % kLanes;       // sum handled, share
-    __syncthreads();                                      // stack no longer in use
+            if (METRIC == kMetricPoint) {
+                // offsets from the cube centre keep the cross-covariance sums
+                // well conditioned
+                const float half = 0.5f * (float)(1u << kBits) * P.h0;
+                const float cx = P.ox + half, cy = P.oy + half, cz = P.oz + half;
+                float px = (hx - cx) + lx, py = (hy - cy) + ly, pz = (hz - cz) + lz;
+                float tx = t.x - cx, ty = t.y - cy, tz = t.z - cz;
+                val[0] = px; val[1] = py; val[2] = pz;
+                val[3] = tx; val[4] = ty; val[5] = tz;
+                val[6] = px * tx; val[7] = px * ty; val[8] = px * tz;
+                val[9] = py * tx; val[10] = py * ty; val[11] = py * tz;
+                val[12] = pz * tx; val[13] = pz * ty; val[14] = pz * tz;
+                val[15] = __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx));
+            } else {
+                plane_values(hx, lx, hy, ly, hz, lz, t, n, val);
+                if (METRIC == kMetricCombined) {
+                    // point-to-point part: J = [-[p']_x, I], r = p' - q, so
+                    // J^T J = [[|p'|^2 I - p' p'^T, [p']_x], [-[p']_x, I]] and
+                    // J^T r = [p' x r; r]
+                    float Apt[21] = {qy * qy + qz * qz, -qx * qy, -qx * qz, 0.f, -qz, qy,
+                                     qx * qx + qz * qz, -qy * qz, qz, 0.f, -qx,
+                                     qx * qx + qy * qy, -qy, qx, 0.f,
+                                     1.f, 0.f, 0.f,
+                                     1.f, 0.f,
+                                     1.f};
+                    float bpt[6] = {__fmaf_rn(qy, dz, -qz * dy), __fmaf_rn(qz, dx, -qx * dz),
+                                    __fmaf_rn(qx, dy, -qy * dx), dx, dy, dz};
 #pragma unroll
-    for (int half = 0; half < 2; half++) {
-        {
-            int a = 0;
+                    for (int k = 0; k < 21; k++) val[k] = __fmaf_rn(w_point, Apt[k], w_plane * val[k]);
 #pragma unroll
-            for (int u = 0; u < 6; u++)
-#pragma unroll
-                for (int v = u; v < 7; v++) {
-                    int slot = (v < 6) ? a++ : 21 + u;
-                    float x = (v < 6) ? J[u] * J[v] : J[u] * res;
-                    if (slot / kHalf == half) red[(slot % kHalf) * kRow + tid] = x;
+                    for (int k = 0; k < 6; k++) val[21 + k] = __fmaf_rn(w_point, bpt[k], w_plane * val[21 + k]);
+                    val[27] = __fmaf_rn(w_point, __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, dx * dx)), w_plane * val[27]);
                 }
-            if (half == 1) red[(27 % kHalf) * kRow + tid] = res * res;
-        }
-        __syncthreads();
-        if (ra < kHalf) {
-            CSum c{0.f, 0.f};
-#pragma unroll
-            for (int k = 0; k < 16; k++) two_sum_add(c, red[ra * kRow + rk + kLanes * k]);
-#pragma unroll
-            for (int off = kLanes / 2; off > 0; off >>= 1) {
-                CSum o{__shfl_xor(c.hi, off), __shfl_xor(c.lo, off)};
-                c = csum_merge(c, o);
             }
-            if (rk == 0) part[(int64_t)lblk * kAcc + half * kHalf + ra] = make_float2(c.hi, c.lo);
         }
-        __syncthreads();
     }
-    uint64_t ib = __ballot(cnt != 0);
-    if (__lane_id() == 0) wcnt[w] = (uint32_t)__popcll(ib);
-    __syncthreads();
-    if (tid == 0) {
-        uint32_t c = 0;
-        for (int x = 0; x < NT / 64; x++) c += wcnt[x];
-        pcnt[lblk] = c;
+    __syncthreads();                                      // stack no longer in use
+    block_partials<NT>(val, cnt, reinterpret_cast<float *>(stk), part, pcnt, lblk);
+}
+
+// Projective correspondences (the organized-target association of
+// Section 3): p' = T p in float64 (the pose's float64 rows, left to right),
+// pixel (floor(u + 0.5), floor(v + 0.5)) of u = fx * p'x / p'z + cx,
+// v = fy * p'y / p'z + cy when p'z > 0; an inlier when the pixel is in the
+// image and valid (finite, z > 0), its normal is nonzero and
+// |p' - q|^2 <= d_max^2 (float64).  The values summed are the point-to-plane
+// ones.  No search: one gather of the pixel's point and normal per point.
+template <int NT>
+__global__ void __launch_bounds__(NT)
+k_icp_accum_proj(const float *__restrict__ src, const int64_t *__restrict__ soff, const int32_t *__restrict__ boff,
+                 int np, const float *__restrict__ tgt, const float *__restrict__ tnrm, int W, int H, float fx,
+                 float fy, float cx, float cy, const IcpState *__restrict__ state, const float *__restrict__ dmaxv,
+                 int final_pass, float2 *__restrict__ part, uint32_t *__restrict__ pcnt, int nblk)
+{
+    __shared__ float red[(kAcc / 2) * (NT + 1)];
+    const int lblk = xcd_block(blockIdx.x, nblk);
+    const int pr = np > 1 ? pair_of(boff, np, lblk) : 0;
+    const IcpState *st = state + pr;
+    if (!final_pass && st->stop) return;   // uniform across the block
+    const double dmax64 = (double)dmaxv[pr];
+    const int64_t i = soff[pr] + (int64_t)(lblk - boff[pr]) * NT + threadIdx.x;
+    float val[kAcc];
+#pragma unroll
+    for (int a = 0; a < kAcc; a++) val[a] = 0.f;
+    uint32_t cnt = 0;
+    if (i < soff[pr + 1]) {
+        const double *T = st->T;
+        const double sx = src[3 * i], sy = src[3 * i + 1], sz = src[3 * i + 2];
+        const double px = T[0] * sx + T[1] * sy + T[2] * sz + T[3];
+        const double py = T[4] * sx + T[5] * sy + T[6] * sz + T[7];
+        const double pz = T[8] * sx + T[9] * sy + T[10] * sz + T[11];
+        if (pz > 0.0) {
+            const double u = (double)fx * px / pz + (double)cx;
+            const double v = (double)fy * py / pz + (double)cy;
+            const double fu = floor(u + 0.5), fv = floor(v + 0.5);
+            if (fu >= 0.0 && fu < (double)W && fv >= 0.0 && fv < (double)H) {
+                const int64_t k = (int64_t)fv * W + (int64_t)fu;
+                const float4 q = make_float4(tgt[3 * k], tgt[3 * k + 1], tgt[3 * k + 2], 0.f);
+                const float4 n = make_float4(tnrm[3 * k], tnrm[3 * k + 1], tnrm[3 * k + 2], 0.f);
+                const bool valid = isfinite(q.x) && isfinite(q.y) && isfinite(q.z) && q.z > 0.f;
+                const bool has_n = n.x != 0.f || n.y != 0.f || n.z != 0.f;
+                const double dx = px - q.x, dy = py - q.y, dz = pz - q.z;
+                if (valid && has_n && !(dx * dx + dy * dy + dz * dz > dmax64 * dmax64)) {
+                    const float hx = (float)px, hy = (float)py, hz = (float)pz;
+                    plane_values(hx, (float)(px - (double)hx), hy, (float)(py - (double)hy), hz,
+                                 (float)(pz - (double)hz), q, n, val);
+                    cnt = 1;
+                }
+            }
+        }
     }
+    block_partials<NT>(val, cnt, red, part, pcnt, lblk);
 }
 
 // Merges 32-lane groups of (hi, lo) pairs: lane j of each 32-lane half-wave
@@ -453,6 +577,85 @@ __device__ bool chol6(double A[36])
     return true;
 }
 
+// Cyclic Jacobi rotations on a symmetric 4x4 (row-major, destroyed): on
+// return the diagonal holds the eigenvalues and column c of v the unit
+// eigenvector of a[c][c].
+__device__ void jacobi4(double a[16], double v[16])
+{
+    for (int i = 0; i < 16; i++) v[i] = (i % 5 == 0) ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 50; sweep++) {
+        double off = 0.0, dg = 0.0;
+        for (int p = 0; p < 4; p++) {
+            dg += a[p * 5] * a[p * 5];
+            for (int q = p + 1; q < 4; q++) off += a[p * 4 + q] * a[p * 4 + q];
+        }
+        if (!(off > 1e-36 * dg)) break;
+        for (int p = 0; p < 3; p++)
+            for (int q = p + 1; q < 4; q++) {
+                double apq = a[p * 4 + q];
+                if (apq == 0.0) continue;
+                double th = (a[q * 5] - a[p * 5]) / (2.0 * apq);
+                double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));
+                double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+                for (int r = 0; r < 4; r++) {
+                    double x = a[r * 4 + p], y = a[r * 4 + q];
+                    a[r * 4 + p] = c * x - sn * y;
+                    a[r * 4 + q] = sn * x + c * y;
+                }
+                for (int r = 0; r < 4; r++) {
+                    double x = a[p * 4 + r], y = a[q * 4 + r];
+                    a[p * 4 + r] = c * x - sn * y;
+                    a[q * 4 + r] = sn * x + c * y;
+                }
+                a[p * 4 + q] = a[q * 4 + p] = 0.0;
+                for (int r = 0; r < 4; r++) {
+                    double x = v[r * 4 + p], y = v[r * 4 + q];
+                    v[r * 4 + p] = c * x - sn * y;
+                    v[r * 4 + q] = sn * x + c * y;
+                }
+            }
+    }
+}
+
+// Rotation best aligning p - pbar to q - qbar for the cross-covariance
+// H[a][b] = sum (p - pbar)_a (q - qbar)_b, by Horn's (1987) unit-quaternion
+// method: the eigenvector of the largest eigenvalue of his symmetric 4x4
+// matrix.  *top is that eigenvalue and *gap its distance to the next one
+// (the rotation is unique when the gap is positive); q4 = (w, x, y, z).
+__device__ void horn_rotation(const double H[9], double dR[9], double *top, double *gap, double q4[4])
+{
+    const double Sxx = H[0], Sxy = H[1], Sxz = H[2], Syx = H[3], Syy = H[4], Syz = H[5], Szx = H[6], Szy = H[7],
+                 Szz = H[8];
+    double N[16] = {Sxx + Syy + Szz, Syz - Szy,       Szx - Sxz,        Sxy - Syx,
+                    Syz - Szy,       Sxx - Syy - Szz, Sxy + Syx,        Szx + Sxz,
+                    Szx - Sxz,       Sxy + Syx,       -Sxx + Syy - Szz, Syz + Szy,
+                    Sxy - Syx,       Szx + Sxz,       Syz + Szy,        -Sxx - Syy + Szz};
+    double V[16];
+    jacobi4(N, V);
+    int i1 = 0;
+    for (int c = 1; c < 4; c++)
+        if (N[c * 5] > N[i1 * 5]) i1 = c;
+    double second = -INFINITY;
+    for (int c = 0; c < 4; c++)
+        if (c != i1) second = fmax(second, N[c * 5]);
+    *top = N[i1 * 5];
+    *gap = N[i1 * 5] - second;
+    double w = V[i1], x = V[4 + i1], y = V[8 + i1], z = V[12 + i1];
+    double nq = sqrt(w * w + x * x + y * y + z * z);
+    w /= nq; x /= nq; y /= nq; z /= nq;
+    if (w < 0.0) { w = -w; x = -x; y = -y; z = -z; }
+    q4[0] = w; q4[1] = x; q4[2] = y; q4[3] = z;
+    dR[0] = w * w + x * x - y * y - z * z;
+    dR[1] = 2.0 * (x * y - w * z);
+    dR[2] = 2.0 * (x * z + w * y);
+    dR[3] = 2.0 * (x * y + w * z);
+    dR[4] = w * w - x * x + y * y - z * z;
+    dR[5] = 2.0 * (y * z - w * x);
+    dR[6] = 2.0 * (x * z - w * y);
+    dR[7] = 2.0 * (y * z + w * x);
+    dR[8] = w * w - x * x - y * y + z * z;
+}
+
 // One block per pair: merges the pair's group partials in a fixed order;
 // iteration: solve and update the pose; final pass: publish pose and
 // statistics.
@@ -462,7 +665,8 @@ __global__ void __launch_bounds__(kFinThreads) k_icp_finalize(const float2 *__re
                                                             IcpState *state, const int32_t *__restrict__ max_iters,
                                                             int final_pass, double conv_tol,
                                                             double *__restrict__ out_T, pc_icp_stats *out_stats,
-                                                            double *__restrict__ hist, int hist_stride)
+                                                            double *__restrict__ hist, int hist_stride, int metric,
+                                                            const GridParams *__restrict__ params)
 {
     __shared__ float2 red[32];
     __shared__ uint32_t redc;
@@ -495,8 +699,9 @@ __global__ void __launch_bounds__(kFinThreads) k_icp_finalize(const float2 *__re
     double sum[kAcc];
     for (int k = 0; k < kAcc; k++) sum[k] = (double)red[k].x + (double)red[k].y;
     int64_t inl = redc;
+    const double r2 = metric == kMetricPoint ? sum[15] : sum[27];
     st->inliers = inl;
-    st->sum_r2 = sum[27];
+    st->sum_r2 = r2;
     if (final_pass) {
         for (int i = 0; i < 16; i++) out_T[i] = st->T[i];
         if (out_stats) {
@@ -504,7 +709,7 @@ __global__ void __launch_bounds__(kFinThreads) k_icp_finalize(const float2 *__re
             o.status = st->status;
             o.iterations_run = st->iters;
             o.inliers = inl;
-            o.rms = inl > 0 ? sqrt(sum[27] / (double)inl) : 0.0;
+            o.rms = inl > 0 ? sqrt(r2 / (double)inl) : 0.0;
             *out_stats = o;
         }
         return;
@@ -512,6 +717,64 @@ __global__ void __launch_bounds__(kFinThreads) k_icp_finalize(const float2 *__re
     if (inl == 0) {
         st->status = PC_ICP_NO_INLIERS;
         st->stop = 1;
+        return;
+    }
+    if (metric == kMetricPoint) {
+        // closed-form fit of the inlier pairs (centroids and cross-covariance
+        // from the offsets to the cube centre c, as summed)
+        const GridParams &P = params[pr];
+        const float half = 0.5f * (float)(1u << kBits) * P.h0;
+        const double c[3] = {(double)(P.ox + half), (double)(P.oy + half), (double)(P.oz + half)};
+        const double n = (double)inl;
+        double H[9], pb[3], qb[3];
+        for (int u = 0; u < 3; u++) {
+            pb[u] = sum[u] / n;
+            qb[u] = sum[3 + u] / n;
+        }
+        for (int u = 0; u < 3; u++)
+            for (int v = 0; v < 3; v++) H[u * 3 + v] = sum[6 + u * 3 + v] - sum[u] * sum[3 + v] / n;
+        double dR[9], top, gap, q4[4];
+        horn_rotation(H, dR, &top, &gap, q4);
+        if (inl < 3 || !(gap > 1e-6 * top)) {
+            st->status = PC_ICP_DEGENERATE;
+            st->stop = 1;
+            return;
+        }
+        double dt[3];
+        for (int r = 0; r < 3; r++) {
+            double Rp = dR[r * 3] * (c[0] + pb[0]) + dR[r * 3 + 1] * (c[1] + pb[1]) + dR[r * 3 + 2] * (c[2] + pb[2]);
+            dt[r] = (c[r] + qb[r]) - Rp;
+        }
+        double T[16];
+        for (int i = 0; i < 16; i++) T[i] = st->T[i];
+        for (int r = 0; r < 3; r++) {
+            for (int cc = 0; cc < 3; cc++)
+                st->T[r * 4 + cc] = dR[r * 3] * T[cc] + dR[r * 3 + 1] * T[4 + cc] + dR[r * 3 + 2] * T[8 + cc];
+            st->T[r * 4 + 3] = dR[r * 3] * T[3] + dR[r * 3 + 1] * T[7] + dR[r * 3 + 2] * T[11] + dt[r];
+        }
+        split_pose(st);
+        if (hist) {
+            double *h = hist + 8 * st->iters;
+            for (int u = 0; u < 3; u++) {
+                h[u] = 2.0 * q4[1 + u];
+                h[3 + u] = dt[u];
+            }
+            h[6] = (double)inl;
+            h[7] = r2;
+        }
+        st->iters++;
+        if (conv_tol > 0) {
+            double m = 0;
+            for (int r = 0; r < 3; r++) {
+                for (int cc = 0; cc < 3; cc++) m = fmax(m, fabs(dR[r * 3 + cc] - (r == cc ? 1.0 : 0.0)));
+                m = fmax(m, fabs(dt[r]));
+            }
+            if (m < conv_tol) {
+                st->status = PC_ICP_CONVERGED;
+                st->stop = 1;
+            }
+        }
+        if (!st->stop && st->iters >= max_iters[pr]) st->stop = 1;
         return;
     }
     double A[36], bv[6];
@@ -603,6 +866,13 @@ void icp_carve(Carver &c, int np, int64_t ns, int64_t nt, int64_t nblk, int64_t 
     s.ngrp = (int)ngrp;
     s.threads = kIcpMinThreads;
     s.leaf = 16;
+    s.metric = kMetricPlane;
+    s.w_point = 0.f;
+    s.w_plane = 1.f;
+    s.assoc = kAssocNearest;
+    s.ptgt = s.pnrm = nullptr;
+    s.width = s.height = 0;
+    s.K[0] = s.K[1] = s.K[2] = s.K[3] = 0.f;
     s.iters_max = iters_max > 0 ? iters_max : 0;
     s.nrm = c.take<float4>(nt1);
     s.prev = c.take<int2>(ns1);
@@ -631,23 +901,45 @@ hipError_t icp_layout_single(IcpStore &s, int64_t ns, int64_t nt, float dmax, in
     return hipGetLastError();
 }
 
-template <int NT, int LEAF>
+template <int NT, int LEAF, int M>
 static void launch_accum_t(IcpStore &s, const float *src, int fin, hipStream_t st)
 {
-    k_icp_accum<NT, LEAF><<<s.nblk, NT, 0, st>>>(s.grid.view(), src, s.soff, s.boff, s.np, s.nrm, s.prev, s.st,
-                                                 s.dmax, fin, s.part, s.pcnt, s.nblk);
+    k_icp_accum<NT, LEAF, M><<<s.nblk, NT, 0, st>>>(s.grid.view(), src, s.soff, s.boff, s.np, s.nrm, s.prev,
+                                                    s.st, s.dmax, fin, s.part, s.pcnt, s.nblk, s.w_point,
+                                                    s.w_plane);
+}
+
+template <int NT, int LEAF>
+static void launch_accum_metric(IcpStore &s, const float *src, int fin, hipStream_t st)
+{
+    if (s.metric == kMetricPoint) launch_accum_t<NT, LEAF, kMetricPoint>(s, src, fin, st);
+    else if (s.metric == kMetricCombined) launch_accum_t<NT, LEAF, kMetricCombined>(s, src, fin, st);
+    else launch_accum_t<NT, LEAF, kMetricPlane>(s, src, fin, st);
 }
 
 template <int NT>
 static void launch_accum_leaf(IcpStore &s, const float *src, int fin, hipStream_t st)
 {
-    if (s.leaf <= 8) launch_accum_t<NT, 8>(s, src, fin, st);
-    else if (s.leaf <= 16) launch_accum_t<NT, 16>(s, src, fin, st);
-    else launch_accum_t<NT, 32>(s, src, fin, st);
+    if (s.leaf <= 8) launch_accum_metric<NT, 8>(s, src, fin, st);
+    else if (s.leaf <= 16) launch_accum_metric<NT, 16>(s, src, fin, st);
+    else launch_accum_metric<NT, 32>(s, src, fin, st);
+}
+
+template <int NT>
+static void launch_accum_proj(IcpStore &s, const float *src, int fin, hipStream_t st)
+{
+    k_icp_accum_proj<NT><<<s.nblk, NT, 0, st>>>(src, s.soff, s.boff, s.np, s.ptgt, s.pnrm, s.width, s.height, s.K[0],
+                                                s.K[1], s.K[2], s.K[3], s.st, s.dmax, fin, s.part, s.pcnt, s.nblk);
 }
 
 static void launch_accum(IcpStore &s, const float *src, int fin, hipStream_t st)
 {
+    if (s.assoc == kAssocProjective) {
+        if (s.threads <= 64) launch_accum_proj<64>(s, src, fin, st);
+        else if (s.threads <= 128) launch_accum_proj<128>(s, src, fin, st);
+        else launch_accum_proj<256>(s, src, fin, st);
+        return;
+    }
     if (s.threads <= 64) launch_accum_leaf<64>(s, src, fin, st);
     else if (s.threads <= 128) launch_accum_leaf<128>(s, src, fin, st);
     else launch_accum_leaf<256>(s, src, fin, st);
@@ -658,10 +950,18 @@ hipError_t icp_run(IcpStore &s, const float *src, int64_t ns, const float *tgt, 
 {
     const int np = s.np;
     k_icp_setup<<<(np + 63) / 64, 64, 0, st>>>(init_T, s.soff, s.grid.off, s.maxit, np, s.st);
-    hipError_t e = grid_build(s.grid, tgt, st);
-    if (e != hipSuccess) return e;
-    e = grid_gather3(s.grid, tgt_n, s.nrm, st);
-    if (e != hipSuccess) return e;
+    hipError_t e = hipSuccess;
+    if (s.assoc == kAssocNearest) {
+        e = grid_build(s.grid, tgt, st);
+        if (e != hipSuccess) return e;
+        if (tgt_n) {
+            e = grid_gather3(s.grid, tgt_n, s.nrm, st);
+            if (e != hipSuccess) return e;
+        }
+    } else {
+        s.ptgt = tgt;
+        s.pnrm = tgt_n;
+    }
     if (ns > 0) {
         int fb = (int)((2 * ns + 255) / 256 < 2048 ? (2 * ns + 255) / 256 : 2048);
         k_fill_i32<<<fb, 256, 0, st>>>((int32_t *)s.prev, 2 * ns, -1);
@@ -680,7 +980,7 @@ hipError_t icp_run(IcpStore &s, const float *src, int64_t ns, const float *tgt, 
             k_icp_reduce<<<s.ngrp, 1024, 0, st>>>(s.part, s.pcnt, s.boff, s.goff, np, s.st, fin, s.gpart, s.gcnt);
         }
         k_icp_finalize<<<np, kFinThreads, 0, st>>>(s.gpart, s.gcnt, s.goff, s.st, s.maxit, fin, conv_tol, out_T,
-                                                   out_stats, s.hist, s.hist_stride);
+                                                   out_stats, s.hist, s.hist_stride, s.metric, s.grid.params);
     }
     return hipGetLastError();
 }
