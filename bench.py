@@ -29,11 +29,14 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "ICP pairs/s + Mpt·iter/s at ≤1e-5 rad pose error; learned-init vs plain"
-WORKLOADS = {"sphere": 0, "room": 1, "street": 2, "batch": 3}
+WORKLOADS = {"sphere": 0, "room": 1, "street": 2, "batch": 3, "projective": 5}
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per source point per ICP iteration: source xyz (12),
-# matched target xyz + normal (24), cell lookup (4)
+# matched target xyz + normal (24), cell lookup (4); the projective
+# association reads the pixel's point and normal directly (no cell lookup)
 ICP_BYTES_PER_POINT = 40
+PROJ_BYTES_PER_POINT = 36
+PROJECTIVE = dict(name="room_views_vga", width=640, height=480, angle=3.0, t=0.03, k=16, d_max=0.2, iters=15)
 PROFILES = os.path.join(ROOT, "profiles")
 TUNING_CACHE = os.path.join(ROOT, "paper_1807_00399_amd", "tuning_cache.json")
 
@@ -195,6 +198,89 @@ def cpu_baseline_batch(b, budget_s):
             "mpt_iter_per_s": pts_iter / loop_s / 1e6}
 
 
+def bench_projective(args):
+    """Projective workload: two VGA depth frames of one room; one step =
+    normals of the target frame + projective-association ICP."""
+    import torch
+    from gen.scenes import room_views, rng_for
+    from paper_1807_00399_amd import pcgpu
+    c = PROJECTIVE
+    dev = torch.device("cuda:0")
+    src_np, tgt_np, C, K = room_views(rng_for(5, 0), c["width"], c["height"], c["angle"], c["t"])
+    src = torch.from_numpy(src_np).to(dev)
+    tgt = torch.from_numpy(tgt_np).to(dev)
+    n = src_np.shape[0]
+    T = torch.empty((4, 4), dtype=torch.float64, device=dev)
+    stats = torch.zeros(24, dtype=torch.uint8, device=dev)
+    ws_n = torch.empty(pcgpu.lib.estimate_normals_workspace_size(n, c["k"]), dtype=torch.uint8, device=dev)
+    ws_i = torch.empty(pcgpu.lib.icp_projective_workspace_size(n, c["iters"]), dtype=torch.uint8, device=dev)
+
+    def step():
+        nrm, _ = pcgpu.estimate_normals(tgt, c["k"], curvature=False, workspace=ws_n)
+        pcgpu.icp_projective(src, tgt, nrm, c["width"], c["height"], K, None, c["d_max"], c["iters"],
+                             workspace=ws_i, out_T=T, out_stats=stats, read_stats=False)
+
+    tuning = autotune_step(args, step, c["name"], n)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    st = pcgpu.decode_stats(stats)
+    ev = HipEvents(c["iters"])
+    pcgpu.lib.pc_set_kernel_timer(ev.beg, ev.end, c["iters"])
+    kern, loop_ms = [], []
+    for _ in range(max(3, min(args.steps, 10))):
+        step()
+        torch.cuda.synchronize()
+        cnt = pcgpu.lib.pc_kernel_timer_count()
+        kern += [ev.elapsed_ms(i) for i in range(cnt)]
+        loop_ms.append(ev.span_ms(0, cnt - 1))
+    pcgpu.lib.pc_set_kernel_timer(None, None, 0)
+    avg_kernel_s = float(np.mean(kern)) * 1e-3
+    algo = PROJ_BYTES_PER_POINT * n
+    achieved = algo / avg_kernel_s / 1e9
+    out = {
+        "metric": METRIC, "value": args.steps / el, "unit": "pairs/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"{c['name']}: two {c['width']}x{c['height']} depth frames of one room, "
+                               f"projective association, k={c['k']} normals, d_max {c['d_max']}, "
+                               f"{c['iters']} iterations",
+                   "points_per_cloud": n, "iters": c["iters"]},
+        "mpt_iter_per_s": n * c["iters"] / (float(np.median(loop_ms)) * 1e-3) / 1e6,
+        "loop_ms": float(np.median(loop_ms)),
+        "icp_status": st,
+        "tuning": tuning,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profiles("icp_accum", "projective"),
+                     "kernel": "k_icp_accum_proj", "avg_kernel_us": avg_kernel_s * 1e6,
+                     "algorithmic_bytes_per_launch": algo},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        t1 = time.perf_counter()
+        pairs, loop_s = 0, 0.0
+        while True:
+            nrm, _, _ = oracle.normals(tgt_np, c["k"], (0.0, 0.0, 0.0), method="kdtree")
+            t2 = time.perf_counter()
+            oracle.icp_projective(src_np, tgt_np, nrm.astype(np.float32), c["width"], c["height"], K, None,
+                                  float(np.float32(c["d_max"])), c["iters"])
+            loop_s += time.perf_counter() - t2
+            pairs += 1
+            if time.perf_counter() - t1 >= args.cpu_seconds:
+                break
+        el1 = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": pairs / el1, "unit": "pairs/s", "cores": oracle.num_threads(),
+                               "kind": "oracle", "sample": f"{pairs} full pair(s) (normals + ICP), {el1:.1f} s wall",
+                               "mpt_iter_per_s": n * c["iters"] * pairs / loop_s / 1e6}
+    print(json.dumps(out), flush=True)
+
+
 def bench_batch(args):
     """Batched workload: all pairs per step through the batched entry points."""
     import torch
@@ -317,6 +403,9 @@ def main():
         return
     if args.workload == "batch":
         bench_batch(args)
+        return
+    if args.workload == "projective":
+        bench_projective(args)
         return
     dev = torch.device("cuda:0")
     w = make_workload(WORKLOADS[args.workload])

@@ -218,16 +218,20 @@ size_t icp_point_to_plane_workspace_size(int64_t n_src, int64_t n_tgt, int max_i
     return c.used();
 }
 
-pc_status icp_point_to_plane(const float *src_xyz, int64_t n_src, const float *tgt_xyz, const float *tgt_normals,
-                             int64_t n_tgt, const double *init_T, float max_corr_dist, int max_iters,
-                             double conv_tol, double *out_T, pc_icp_stats *out_stats, void *workspace,
-                             size_t workspace_bytes, hipStream_t stream)
+namespace {
+
+// single-pair ICP with any metric (0 point-to-plane, 1 point-to-point, 2 combined)
+pc_status icp_single(const float *src_xyz, int64_t n_src, const float *tgt_xyz, const float *tgt_normals,
+                     int64_t n_tgt, const double *init_T, float max_corr_dist, int max_iters, double conv_tol,
+                     double *out_T, pc_icp_stats *out_stats, void *workspace, size_t workspace_bytes,
+                     hipStream_t stream, int metric, float w_point, float w_plane)
 {
+    const bool need_normals = metric == 0 || (metric == 2 && w_plane > 0.f);
     if (n_src < 0 || n_tgt < 0 || n_src >= kMaxPoints || n_tgt >= kMaxPoints) return PC_EINVAL;
     if (max_iters < 0 || !(max_corr_dist > 0.f) || !isfinite(max_corr_dist)) return PC_EINVAL;
     if (!(conv_tol >= 0.0) || !isfinite(conv_tol)) return PC_EINVAL;
     if (!out_T || !workspace) return PC_EINVAL;
-    if ((n_src > 0 && !src_xyz) || (n_tgt > 0 && (!tgt_xyz || !tgt_normals))) return PC_EINVAL;
+    if ((n_src > 0 && !src_xyz) || (n_tgt > 0 && (!tgt_xyz || (need_normals && !tgt_normals)))) return PC_EINVAL;
     if (!aligned(src_xyz, 4) || !aligned(tgt_xyz, 4) || !aligned(tgt_normals, 4) || !aligned(init_T, 8) ||
         !aligned(out_T, 8) || !aligned(out_stats, 8) || !aligned(workspace, 256))
         return PC_EINVAL;
@@ -236,7 +240,83 @@ pc_status icp_point_to_plane(const float *src_xyz, int64_t n_src, const float *t
     IcpStore s;
     carve_single(c, n_src, n_tgt, max_iters, s);
     if (!c.ok) return PC_EWORKSPACE;
+    s.metric = metric;
+    s.w_point = w_point;
+    s.w_plane = w_plane;
     if (icp_layout_single(s, n_src, n_tgt, max_corr_dist, max_iters, stream) != hipSuccess) return PC_EDEVICE;
+    hipError_t e = icp_run(s, src_xyz, n_src, tgt_xyz, need_normals ? tgt_normals : nullptr, init_T, conv_tol,
+                           out_T, out_stats, stream);
+    return e == hipSuccess ? PC_OK : PC_EDEVICE;
+}
+
+}  // namespace
+
+pc_status icp_point_to_plane(const float *src_xyz, int64_t n_src, const float *tgt_xyz, const float *tgt_normals,
+                             int64_t n_tgt, const double *init_T, float max_corr_dist, int max_iters,
+                             double conv_tol, double *out_T, pc_icp_stats *out_stats, void *workspace,
+                             size_t workspace_bytes, hipStream_t stream)
+{
+    return icp_single(src_xyz, n_src, tgt_xyz, tgt_normals, n_tgt, init_T, max_corr_dist, max_iters, conv_tol,
+                      out_T, out_stats, workspace, workspace_bytes, stream, 0, 0.f, 1.f);
+}
+
+pc_status icp_point_to_point(const float *src_xyz, int64_t n_src, const float *tgt_xyz, int64_t n_tgt,
+                             const double *init_T, float max_corr_dist, int max_iters, double conv_tol,
+                             double *out_T, pc_icp_stats *out_stats, void *workspace, size_t workspace_bytes,
+                             hipStream_t stream)
+{
+    return icp_single(src_xyz, n_src, tgt_xyz, nullptr, n_tgt, init_T, max_corr_dist, max_iters, conv_tol, out_T,
+                      out_stats, workspace, workspace_bytes, stream, 1, 1.f, 0.f);
+}
+
+pc_status icp_combined(const float *src_xyz, int64_t n_src, const float *tgt_xyz, const float *tgt_normals,
+                       int64_t n_tgt, const double *init_T, float w_point, float w_plane, float max_corr_dist,
+                       int max_iters, double conv_tol, double *out_T, pc_icp_stats *out_stats, void *workspace,
+                       size_t workspace_bytes, hipStream_t stream)
+{
+    if (!(w_point >= 0.f) || !(w_plane >= 0.f) || !isfinite(w_point) || !isfinite(w_plane) ||
+        !(w_point + w_plane > 0.f))
+        return PC_EINVAL;
+    return icp_single(src_xyz, n_src, tgt_xyz, tgt_normals, n_tgt, init_T, max_corr_dist, max_iters, conv_tol,
+                      out_T, out_stats, workspace, workspace_bytes, stream, 2, w_point, w_plane);
+}
+
+size_t icp_projective_workspace_size(int64_t n_src, int max_iters)
+{
+    if (n_src < 0 || n_src >= kMaxPoints || max_iters < 0) return 0;
+    Carver c(nullptr, ~(size_t)0 >> 1);
+    IcpStore s;
+    carve_single(c, n_src, 0, max_iters, s);
+    return c.used();
+}
+
+pc_status icp_projective(const float *src_xyz, int64_t n_src, const float *tgt_xyz, const float *tgt_normals,
+                         int width, int height, const float intrinsics[4], const double *init_T,
+                         float max_corr_dist, int max_iters, double conv_tol, double *out_T,
+                         pc_icp_stats *out_stats, void *workspace, size_t workspace_bytes, hipStream_t stream)
+{
+    if (n_src < 0 || n_src >= kMaxPoints || width < 1 || height < 1 || !intrinsics) return PC_EINVAL;
+    if ((int64_t)width * height >= kMaxPoints) return PC_EINVAL;
+    for (int i = 0; i < 4; i++)
+        if (!isfinite(intrinsics[i])) return PC_EINVAL;
+    if (!(intrinsics[0] > 0.f) || !(intrinsics[1] > 0.f)) return PC_EINVAL;
+    if (max_iters < 0 || !(max_corr_dist > 0.f) || !isfinite(max_corr_dist)) return PC_EINVAL;
+    if (!(conv_tol >= 0.0) || !isfinite(conv_tol)) return PC_EINVAL;
+    if (!out_T || !workspace || !tgt_xyz || !tgt_normals || (n_src > 0 && !src_xyz)) return PC_EINVAL;
+    if (!aligned(src_xyz, 4) || !aligned(tgt_xyz, 4) || !aligned(tgt_normals, 4) || !aligned(init_T, 8) ||
+        !aligned(out_T, 8) || !aligned(out_stats, 8) || !aligned(workspace, 256))
+        return PC_EINVAL;
+    if (workspace_bytes < icp_projective_workspace_size(n_src, max_iters)) return PC_EWORKSPACE;
+    Carver c(workspace, workspace_bytes);
+    IcpStore s;
+    carve_single(c, n_src, 0, max_iters, s);
+    if (!c.ok) return PC_EWORKSPACE;
+    s.assoc = kAssocProjective;
+    s.width = width;
+    s.height = height;
+    for (int i = 0; i < 4; i++) s.K[i] = intrinsics[i];
+    const int64_t npix = (int64_t)width * height;
+    if (icp_layout_single(s, n_src, npix, max_corr_dist, max_iters, stream) != hipSuccess) return PC_EDEVICE;
     hipError_t e = icp_run(s, src_xyz, n_src, tgt_xyz, tgt_normals, init_T, conv_tol, out_T, out_stats, stream);
     return e == hipSuccess ? PC_OK : PC_EDEVICE;
 }

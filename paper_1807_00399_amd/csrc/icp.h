@@ -31,7 +31,15 @@ struct IcpStore {
     int np, nblk, ngrp, iters_max;
     int threads;        // accumulate block size (64, 128 or 256)
     int leaf;           // largest node scanned as a leaf by the search (8, 16 or 32)
+    int metric;         // 0 point-to-plane, 1 point-to-point (closed form), 2 combined
+    float w_point, w_plane;   // weights of the combined metric
+    int assoc;          // kAssocNearest (grid search) or kAssocProjective (organized target)
+    const float *ptgt, *pnrm;  // projective: organized target points and normals (height * width, 3)
+    int width, height;
+    float K[4];         // projective: fx, fy, cx, cy
 };
+
+enum { kAssocNearest = 0, kAssocProjective = 1 };
 
 // blocks of the accumulate kernel for ns source points with `threads` per
 // block (icp_blocks_max: the smallest block size, which sizes the

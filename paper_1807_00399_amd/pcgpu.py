@@ -24,7 +24,8 @@ EXPORTS = (
     "pc_status_string",
     "knn_search_workspace_size", "knn_search",
     "estimate_normals_workspace_size", "estimate_normals",
-    "icp_point_to_plane_workspace_size", "icp_point_to_plane",
+    "icp_point_to_plane_workspace_size", "icp_point_to_plane", "icp_point_to_point", "icp_combined",
+    "icp_projective_workspace_size", "icp_projective",
     "estimate_normals_batched_workspace_size", "estimate_normals_batched",
     "icp_point_to_plane_batched_workspace_size", "icp_point_to_plane_batched",
     "pc_copy_probe", "icp_history", "pc_set_kernel_timer", "pc_kernel_timer_count",
@@ -64,6 +65,15 @@ def _load() -> ctypes.CDLL:
     lib.icp_point_to_plane_workspace_size.restype = sz
     lib.icp_point_to_plane.argtypes = [vp, i64, vp, vp, i64, vp, f32, i32, f64, vp, vp, vp, sz, vp]
     lib.icp_point_to_plane.restype = ctypes.c_int
+    lib.icp_point_to_point.argtypes = [vp, i64, vp, i64, vp, f32, i32, f64, vp, vp, vp, sz, vp]
+    lib.icp_point_to_point.restype = ctypes.c_int
+    lib.icp_combined.argtypes = [vp, i64, vp, vp, i64, vp, f32, f32, f32, i32, f64, vp, vp, vp, sz, vp]
+    lib.icp_combined.restype = ctypes.c_int
+    lib.icp_projective_workspace_size.argtypes = [i64, i32]
+    lib.icp_projective_workspace_size.restype = sz
+    lib.icp_projective.argtypes = [vp, i64, vp, vp, i32, i32, ctypes.POINTER(ctypes.c_float), vp, f32, i32, f64,
+                                   vp, vp, vp, sz, vp]
+    lib.icp_projective.restype = ctypes.c_int
     lib.estimate_normals_batched_workspace_size.argtypes = [i32, vp]
     lib.estimate_normals_batched_workspace_size.restype = sz
     lib.estimate_normals_batched.argtypes = [i32, vp, vp, vp, ctypes.POINTER(ctypes.c_float), vp, vp, vp, sz, vp]
@@ -194,6 +204,79 @@ def icp_point_to_plane(src: torch.Tensor, tgt: torch.Tensor, tgt_normals: torch.
                                 tgt.shape[0], _ptr(T0), float(max_corr_dist), int(max_iters), float(conv_tol),
                                 T.data_ptr(), stats.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream))
     _check(st, "icp_point_to_plane")
+    if not read_stats:
+        return T, stats
+    return T, decode_stats(stats)
+
+
+def _icp_variant(fn, what, src, tgt, tgt_normals, init_T, max_corr_dist, max_iters, conv_tol, stream, workspace,
+                 weights=None):
+    src = _pts(src, "src")
+    tgt = _pts(tgt, "tgt")
+    if tgt_normals is not None:
+        tgt_normals = _pts(tgt_normals, "tgt_normals")
+        if tgt_normals.shape[0] != tgt.shape[0]:
+            raise ValueError("tgt_normals must match tgt")
+    dev = src.device
+    T0 = None
+    if init_T is not None:
+        T0 = torch.as_tensor(init_T, dtype=torch.float64).reshape(4, 4).to(dev).contiguous()
+    T = torch.empty((4, 4), dtype=torch.float64, device=dev)
+    stats = torch.zeros(24, dtype=torch.uint8, device=dev)
+    need = lib.icp_point_to_plane_workspace_size(src.shape[0], tgt.shape[0], int(max_iters))
+    ws = workspace if workspace is not None else _ws.get(need, dev)
+    if weights is None:
+        st = fn(src.data_ptr(), src.shape[0], tgt.data_ptr(), tgt.shape[0], _ptr(T0), float(max_corr_dist),
+                int(max_iters), float(conv_tol), T.data_ptr(), stats.data_ptr(), ws.data_ptr(), ws.numel(),
+                _stream(stream))
+    else:
+        st = fn(src.data_ptr(), src.shape[0], tgt.data_ptr(), _ptr(tgt_normals), tgt.shape[0], _ptr(T0),
+                float(weights[0]), float(weights[1]), float(max_corr_dist), int(max_iters), float(conv_tol),
+                T.data_ptr(), stats.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream))
+    _check(st, what)
+    return T, decode_stats(stats)
+
+
+def icp_point_to_point(src: torch.Tensor, tgt: torch.Tensor, init_T=None, max_corr_dist: float = 0.05,
+                       max_iters: int = 30, conv_tol: float = 0.0, stream=None,
+                       workspace: torch.Tensor | None = None):
+    """Point-to-point ICP (closed-form fit per iteration).  Returns (T, stats dict)."""
+    return _icp_variant(lib.icp_point_to_point, "icp_point_to_point", src, tgt, None, init_T, max_corr_dist,
+                        max_iters, conv_tol, stream, workspace)
+
+
+def icp_combined(src: torch.Tensor, tgt: torch.Tensor, tgt_normals, init_T=None, w_point: float = 0.5,
+                 w_plane: float = 1.0, max_corr_dist: float = 0.05, max_iters: int = 30, conv_tol: float = 0.0,
+                 stream=None, workspace: torch.Tensor | None = None):
+    """ICP with the weighted point-to-point + point-to-plane metric.  Returns (T, stats dict)."""
+    return _icp_variant(lib.icp_combined, "icp_combined", src, tgt, tgt_normals, init_T, max_corr_dist, max_iters,
+                        conv_tol, stream, workspace, weights=(w_point, w_plane))
+
+
+def icp_projective(src: torch.Tensor, tgt: torch.Tensor, tgt_normals: torch.Tensor, width: int, height: int,
+                   intrinsics, init_T=None, max_corr_dist: float = 0.2, max_iters: int = 15, conv_tol: float = 0.0,
+                   stream=None, workspace: torch.Tensor | None = None, out_T: torch.Tensor | None = None,
+                   out_stats: torch.Tensor | None = None, read_stats: bool = True):
+    """Point-to-plane ICP with projective association into the organized
+    target (height*width, 3).  Returns (T, stats dict or raw device tensor)."""
+    src = _pts(src, "src")
+    tgt = _pts(tgt, "tgt")
+    tgt_normals = _pts(tgt_normals, "tgt_normals")
+    if tgt.shape[0] != width * height or tgt_normals.shape[0] != width * height:
+        raise ValueError("organized target must have width*height points and normals")
+    dev = src.device
+    T0 = None
+    if init_T is not None:
+        T0 = torch.as_tensor(init_T, dtype=torch.float64).reshape(4, 4).to(dev).contiguous()
+    T = out_T if out_T is not None else torch.empty((4, 4), dtype=torch.float64, device=dev)
+    stats = out_stats if out_stats is not None else torch.zeros(24, dtype=torch.uint8, device=dev)
+    K = (ctypes.c_float * 4)(*[float(v) for v in intrinsics])
+    need = lib.icp_projective_workspace_size(src.shape[0], int(max_iters))
+    ws = workspace if workspace is not None else _ws.get(need, dev)
+    st = lib.icp_projective(src.data_ptr(), src.shape[0], tgt.data_ptr(), tgt_normals.data_ptr(), int(width),
+                            int(height), K, _ptr(T0), float(max_corr_dist), int(max_iters), float(conv_tol),
+                            T.data_ptr(), stats.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream))
+    _check(st, "icp_projective")
     if not read_stats:
         return T, stats
     return T, decode_stats(stats)

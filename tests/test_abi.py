@@ -168,3 +168,42 @@ def test_batched_icp_rejects_bad_arguments(pc):
     assert call(T0=FAKE + 4) == pc.PC_EINVAL
     # the size query takes the largest iteration count of the batch
     assert L.icp_point_to_plane_batched_workspace_size(3, so, to, 30) > ws
+
+
+def test_metric_variants_reject_bad_arguments(pc):
+    L = pc.lib
+    ws = L.icp_point_to_plane_workspace_size(100, 100, 5)
+
+    def p2p(tgt=FAKE, d=0.1, it=5, w=FAKE, wb=ws):
+        return L.icp_point_to_point(FAKE, 100, tgt, 100, None, d, it, 0.0, FAKE, None, w, wb, None)
+
+    def comb(wpt=0.5, wpl=1.0, nrm=FAKE, wb=ws):
+        return L.icp_combined(FAKE, 100, FAKE, nrm, 100, None, wpt, wpl, 0.1, 5, 0.0, FAKE, None, FAKE, wb, None)
+
+    assert p2p(d=0.0) == pc.PC_EINVAL
+    assert p2p(it=-1) == pc.PC_EINVAL
+    assert p2p(tgt=None) == pc.PC_EINVAL
+    assert p2p(wb=ws - 1) == pc.PC_EWORKSPACE
+    assert comb(wpt=-1.0) == pc.PC_EINVAL
+    assert comb(wpt=0.0, wpl=0.0) == pc.PC_EINVAL
+    assert comb(wpl=float("nan")) == pc.PC_EINVAL
+    assert comb(nrm=None) == pc.PC_EINVAL                 # normals needed when w_plane > 0
+    assert comb(wpl=0.0, nrm=None, wb=ws - 1) == pc.PC_EWORKSPACE   # ... but not at w_plane = 0
+
+
+def test_projective_rejects_bad_arguments(pc):
+    L = pc.lib
+    ws = L.icp_projective_workspace_size(100, 5)
+    K = (ctypes.c_float * 4)(525.0, 525.0, 319.5, 239.5)
+
+    def call(W=64, H=48, k=K, d=0.1, nrm=FAKE, wb=ws):
+        return L.icp_projective(FAKE, 100, FAKE, nrm, W, H, k, None, d, 5, 0.0, FAKE, None, FAKE, wb, None)
+
+    assert call(W=0) == pc.PC_EINVAL
+    assert call(H=-1) == pc.PC_EINVAL
+    assert call(k=None) == pc.PC_EINVAL
+    assert call(k=(ctypes.c_float * 4)(0.0, 525.0, 319.5, 239.5)) == pc.PC_EINVAL
+    assert call(k=(ctypes.c_float * 4)(525.0, 525.0, float("nan"), 239.5)) == pc.PC_EINVAL
+    assert call(d=0.0) == pc.PC_EINVAL
+    assert call(nrm=None) == pc.PC_EINVAL
+    assert call(wb=ws - 1) == pc.PC_EWORKSPACE

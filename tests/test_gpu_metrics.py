@@ -1,0 +1,89 @@
+"""GPU parity of the ICP metric variants (point-to-point with the closed-form
+fit, weighted point-to-point + point-to-plane) through the C ABI against the
+oracle: pose within 1e-5 rad / 1e-6, same status and iteration count."""
+import numpy as np
+import pytest
+
+from gen import apply_rigid, make_workload, random_rigid, rng_for, sphere_plane
+from tests.helpers import pose_err
+
+pytestmark = pytest.mark.gpu
+
+ROT_TOL = 1e-5
+TRANS_TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1807_00399_amd import pcgpu
+    return pcgpu
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _check(Tg, sg, ro, n):
+    ea, et = pose_err(Tg, ro["T"])
+    assert sg["status"] == ro["status"], (sg, ro["status"])
+    assert sg["iterations_run"] == ro["iterations"]
+    assert ea <= ROT_TOL and et <= TRANS_TOL, f"pose differs: {ea:.3g} rad, {et:.3g}"
+    assert abs(sg["inliers"] - ro["inliers"]) <= max(2, 1e-5 * n)
+
+
+@pytest.mark.parametrize("cfg,size", [(0, "small"), (0, "full"), (1, "small"), (2, "small")])
+def test_point_to_point_workloads(gpu, oracle_mod, cfg, size):
+    w = make_workload(cfg, size=size)
+    _say(f"p2p {w.name} n={w.n} d_max={w.d_max} iters={w.iters}")
+    T, st = gpu.icp_point_to_point(_dev(w.source), _dev(w.target), None, w.d_max, w.iters)
+    ro = oracle_mod.icp_p2p(w.source, w.target, None, float(np.float32(w.d_max)), w.iters)
+    _check(T.cpu().numpy(), st, ro, w.n)
+
+
+@pytest.mark.parametrize("cfg,size", [(0, "small"), (1, "small"), (2, "small")])
+@pytest.mark.parametrize("wpt,wpl", [(0.5, 1.0), (1.0, 0.0), (2.0, 0.3)])
+def test_combined_workloads(gpu, oracle_mod, cfg, size, wpt, wpl):
+    w = make_workload(cfg, size=size)
+    nrm = oracle_mod.normals(w.target, w.k, (0, 0, 0))[0].astype(np.float32)
+    _say(f"combined {w.name} n={w.n} weights=({wpt}, {wpl})")
+    T, st = gpu.icp_combined(_dev(w.source), _dev(w.target), _dev(nrm), None, wpt, wpl, w.d_max, w.iters)
+    ro = oracle_mod.icp_combined(w.source, w.target, nrm, None, wpt, wpl, float(np.float32(w.d_max)), w.iters)
+    _check(T.cpu().numpy(), st, ro, w.n)
+
+
+def test_combined_plane_weights_equal_point_to_plane(gpu, oracle_mod):
+    w = make_workload(0, size="small")
+    nrm = _dev(oracle_mod.normals(w.target, w.k, (0, 0, 0))[0].astype(np.float32))
+    src, tgt = _dev(w.source), _dev(w.target)
+    Ta, sa = gpu.icp_combined(src, tgt, nrm, None, 0.0, 1.0, w.d_max, w.iters)
+    Tb, sb = gpu.icp_point_to_plane(src, tgt, nrm, None, w.d_max, w.iters)
+    assert np.array_equal(Ta.cpu().numpy(), Tb.cpu().numpy()) and sa == sb
+
+
+def test_point_to_point_degenerate_and_converged(gpu, oracle_mod):
+    rng = rng_for(500)
+    # two points: fewer than 3 inliers
+    a = sphere_plane(rng, 2)
+    T, st = gpu.icp_point_to_point(_dev(a), _dev(apply_rigid(random_rigid(rng, 1.0, 0.01), a)), None, 1.0, 5)
+    assert st["status"] == 2 and st["iterations_run"] == 0 and np.array_equal(T.cpu().numpy(), np.eye(4))
+    # collinear points: no unique rotation
+    s = np.linspace(-1, 1, 50, dtype=np.float32)[:, None] * np.array([[1.0, 0.5, 0.2]], np.float32)
+    T, st = gpu.icp_point_to_point(_dev(s), _dev(s + np.float32(0.01)), None, 0.5, 5)
+    ro = oracle_mod.icp_p2p(s, s + np.float32(0.01), None, 0.5, 5)
+    assert st["status"] == ro["status"] == 2
+    # early convergence on an easy pair
+    src = sphere_plane(rng, 4000)
+    Tgt = random_rigid(rng, 3.0, 0.02)
+    tgt = apply_rigid(Tgt, src)
+    T, st = gpu.icp_point_to_point(_dev(src), _dev(tgt), None, 0.3, 200, conv_tol=1e-9)
+    ro = oracle_mod.icp_p2p(src, tgt, None, 0.3, 200, conv_tol=1e-9)
+    _check(T.cpu().numpy(), st, ro, 4000)
+    assert st["status"] == 0

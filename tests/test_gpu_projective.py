@@ -1,0 +1,73 @@
+"""GPU parity of projective-association ICP through the C ABI against the
+oracle: pose within 1e-5 rad / 1e-6, same status and iteration count,
+inlier counts equal up to pixel decisions on a rounding boundary."""
+import numpy as np
+import pytest
+
+from gen.scenes import room_views, rng_for
+from tests.helpers import pose_err
+
+pytestmark = pytest.mark.gpu
+
+ROT_TOL = 1e-5
+TRANS_TOL = 1e-6
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1807_00399_amd import pcgpu
+    return pcgpu
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _parity(gpu, oracle_mod, src, tgt, nrm, W, H, K, d_max, iters, T0=None):
+    _say(f"projective {W}x{H} n_src={len(src)} d_max={d_max} iters={iters}")
+    T, st = gpu.icp_projective(_dev(src), _dev(tgt), _dev(nrm), W, H, K, T0, d_max, iters)
+    ro = oracle_mod.icp_projective(src, tgt, nrm, W, H, K, T0, float(np.float32(d_max)), iters)
+    ea, et = pose_err(T.cpu().numpy(), ro["T"])
+    assert st["status"] == ro["status"] and st["iterations_run"] == ro["iterations"], (st, ro)
+    assert ea <= ROT_TOL and et <= TRANS_TOL, f"pose differs: {ea:.3g} rad, {et:.3g}"
+    assert abs(st["inliers"] - ro["inliers"]) <= max(2, 1e-5 * len(src))
+    return T.cpu().numpy(), st, ro
+
+
+@pytest.mark.parametrize("W,H,noise", [(160, 120, 0.003), (160, 120, 0.0), (640, 480, 0.003)])
+def test_projective_room_views(gpu, oracle_mod, W, H, noise):
+    src, tgt, C, K = room_views(rng_for(610, W), W, H, depth_noise=noise)
+    nrm = oracle_mod.normals(tgt, 16, (0, 0, 0), method="kdtree")[0].astype(np.float32)
+    _parity(gpu, oracle_mod, src, tgt, nrm, W, H, K, 0.2, 15)
+
+
+def test_projective_invalid_pixels_and_init_pose(gpu, oracle_mod):
+    src, tgt, C, K = room_views(rng_for(611), 160, 120)
+    nrm = oracle_mod.normals(tgt, 16, (0, 0, 0))[0].astype(np.float32)
+    bad = tgt.copy()
+    bad[::3] = np.nan
+    bad[1::7, 2] = -1.0                    # behind the camera: invalid too
+    nrm[5::11] = 0.0                       # zero normals are rejected
+    T0 = np.eye(4)
+    T0[:3, 3] = (0.01, -0.01, 0.005)
+    _parity(gpu, oracle_mod, src, bad, nrm, 160, 120, K, 0.2, 10, T0)
+
+
+def test_projective_identity_and_no_valid_pixels(gpu, oracle_mod):
+    _, tgt, _, K = room_views(rng_for(612), 160, 120)
+    nrm = oracle_mod.normals(tgt, 16, (0, 0, 0))[0].astype(np.float32)
+    T, st = gpu.icp_projective(_dev(tgt), _dev(tgt), _dev(nrm), 160, 120, K, None, 0.05, 3)
+    assert np.array_equal(T.cpu().numpy(), np.eye(4)) and st["rms"] == 0.0
+    assert st["inliers"] == int(np.any(nrm != 0, axis=1).sum())
+    zero = tgt.copy()
+    zero[:, 2] = 0.0
+    T, st = gpu.icp_projective(_dev(tgt), _dev(zero), _dev(nrm), 160, 120, K, None, 0.2, 4)
+    assert st["status"] == 3 and st["iterations_run"] == 0 and st["inliers"] == 0
