@@ -33,6 +33,10 @@ Parity status of each function (what pins it lives in ``tests/``):
   icp_projective      pinned by the identity pose on a frame and itself, the
                       point-to-plane system of explicit pairs, and recovery
                       of a camera motion from noiseless views.
+  normals_radius      pinned by lattice neighbourhoods counted by hand,
+                      kd-tree against brute-force membership, equality with
+                      k-NN normals when the radius holds exactly k points,
+                      planes and spheres.
 """
 from __future__ import annotations
 
@@ -105,6 +109,8 @@ def _load():
         lib.oracle_icp_projective.argtypes = [_f32p, ctypes.c_int64, _f32p, _f32p, ctypes.c_int, ctypes.c_int,
                                               _f64p, ctypes.c_void_p, ctypes.c_double, ctypes.c_int,
                                               ctypes.c_double, _f64p, _i32p, _i64p, _f64p]
+        lib.oracle_normals_radius.argtypes = [_f32p, ctypes.c_int64, ctypes.c_float, ctypes.c_int, _f64p,
+                                              ctypes.c_int, _f64p, _f64p, _f64p, _i32p]
         lib.oracle_num_threads.argtypes = []
         _lib = lib
     return _lib
@@ -296,3 +302,19 @@ def icp_projective(src, tgt, tgt_normals, width: int, height: int, K, T_init=Non
                                   None if T0 is None else T0.ctypes.data, float(d_max), int(max_iters),
                                   float(conv_tol), T, si, si64, sd)
     return _stats(T, si, si64, sd)
+
+
+def normals_radius(xyz, radius: float, k: int = 0, viewpoint=(0.0, 0.0, 0.0), method: str = "kdtree"):
+    """Normals from radius (k = 0) or hybrid (k nearest within the radius)
+    neighbourhoods.  Returns (normals (n,3) f64, curvature (n,), eigenvalues
+    (n,3), counts (n,) int32)."""
+    xyz = _pts(xyz)
+    n = xyz.shape[0]
+    nrm, curv, ev = np.empty((n, 3)), np.empty(n), np.empty((n, 3))
+    cnt = np.empty(n, np.int32)
+    rc = _load().oracle_normals_radius(xyz, n, float(np.float32(radius)), int(k),
+                                       np.ascontiguousarray(viewpoint, dtype=np.float64), int(method == "kdtree"),
+                                       nrm, curv, ev, cnt)
+    if rc:
+        raise ValueError(f"oracle normals_radius failed ({rc})")
+    return nrm, curv, ev, cnt

@@ -1136,3 +1136,154 @@ int oracle_icp_projective(const float *src, int64_t ns, const float *tgt, const 
     stats_d[0] = inl > 0 ? sqrt(s2 / (double)inl) : 0.0;
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* radius and hybrid neighbourhoods for normals (Section 3, "Core           */
+/* operations": radius and hybrid queries; Section 4: normals from a 1 cm    */
+/* radius neighbourhood)                                                     */
+/* ------------------------------------------------------------------------ */
+
+typedef struct {
+    int32_t *idx;
+    int64_t n, cap;
+} idx_list;
+
+static int list_push(idx_list *l, int32_t j)
+{
+    if (l->n == l->cap) {
+        int64_t cap = l->cap ? 2 * l->cap : 64;
+        int32_t *p = (int32_t *)realloc(l->idx, sizeof(int32_t) * (size_t)cap);
+        if (!p) return 1;
+        l->idx = p;
+        l->cap = cap;
+    }
+    l->idx[l->n++] = j;
+    return 0;
+}
+
+static int cmp_i32(const void *a, const void *b)
+{
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* every reference point with float32 key <= r2 (the kNN key of the
+   definition), pruned like kd_knn_rec */
+static void kd_radius_rec(const kd_tree *t, int32_t id, const float *q, float r2, idx_list *out)
+{
+    const kd_node *nd = &t->nodes[id];
+    if (nd->left < 0) {
+        for (int32_t i = nd->lo; i < nd->hi; i++) {
+            int32_t j = t->perm[i];
+            if (knn_key(t->pts + 3 * (int64_t)j, q) <= r2) list_push(out, j);
+        }
+        return;
+    }
+    double diff = (double)q[nd->axis] - (double)nd->split;
+    int32_t near = diff <= 0 ? nd->left : nd->right;
+    int32_t far = diff <= 0 ? nd->right : nd->left;
+    kd_radius_rec(t, near, q, r2, out);
+    if (diff * diff * (1.0 - 1e-6) <= (double)r2) kd_radius_rec(t, far, q, r2, out);
+}
+
+/* PCA normal of point i from the neighbour set idx[0..m) (as oracle_normals:
+   mean-centred covariance of the offsets from p_i, 1/m, cyclic Jacobi,
+   viewpoint orientation, curvature); m < 3 gives normal 0 and curvature 0
+   (fewer than three points do not fix a plane). */
+static void pca_normal(const float *xyz, int64_t i, const int32_t *idx, int64_t m, const double vp[3],
+                       double nn[3], double *curv, double ev[3])
+{
+    nn[0] = nn[1] = nn[2] = 0.0;
+    double w[3] = {0.0, 0.0, 0.0};
+    if (m >= 3) {
+        double mu[3] = {0, 0, 0};
+        for (int64_t s = 0; s < m; s++)
+            for (int a = 0; a < 3; a++) mu[a] += (double)xyz[3 * (int64_t)idx[s] + a] - (double)xyz[3 * i + a];
+        for (int a = 0; a < 3; a++) mu[a] /= (double)m;
+        double c[9] = {0};
+        for (int64_t s = 0; s < m; s++) {
+            double e[3];
+            for (int a = 0; a < 3; a++) e[a] = ((double)xyz[3 * (int64_t)idx[s] + a] - (double)xyz[3 * i + a]) - mu[a];
+            for (int r = 0; r < 3; r++)
+                for (int cc = 0; cc < 3; cc++) c[r * 3 + cc] += e[r] * e[cc];
+        }
+        for (int r = 0; r < 9; r++) c[r] /= (double)m;
+        int zero = 1;
+        for (int r = 0; r < 9; r++) if (c[r] != 0.0) zero = 0;
+        if (!zero) {
+            double v[9];
+            oracle_jacobi3(c, w, v);
+            for (int a = 0; a < 3; a++) nn[a] = v[a * 3 + 0];
+            double nrm = sqrt(nn[0] * nn[0] + nn[1] * nn[1] + nn[2] * nn[2]);
+            for (int a = 0; a < 3; a++) nn[a] /= nrm;
+            double dot = 0;
+            for (int a = 0; a < 3; a++) dot += nn[a] * (vp[a] - (double)xyz[3 * i + a]);
+            int flip = dot < 0;
+            if (dot == 0) {
+                for (int a = 0; a < 3; a++)
+                    if (nn[a] != 0) { flip = nn[a] < 0; break; }
+            }
+            if (flip) for (int a = 0; a < 3; a++) nn[a] = -nn[a];
+        }
+    }
+    double tr = w[0] + w[1] + w[2];
+    *curv = tr > 0 ? w[0] / tr : 0.0;
+    for (int a = 0; a < 3; a++) ev[a] = w[a];
+}
+
+/* Normals from radius neighbourhoods N(i) = {j : key(p_j, p_i) <= r2}
+   (k == 0), or hybrid ones: the k nearest points of i that have
+   key <= r2 (k > 0; the k nearest by the kNN definition, then those within
+   the radius).  r2 is the float32 square of the radius, as the GPU takes it.
+   out_count (nullable) receives |N(i)|. */
+int oracle_normals_radius(const float *xyz, int64_t n, float radius, int k, const double viewpoint[3],
+                          int use_kdtree, double *out_normals, double *out_curv, double *out_evals,
+                          int32_t *out_count)
+{
+    if (!(radius > 0.f) || k < 0 || k > 64 || (k > 0 && k > n)) return 1;
+    const float r2 = radius * radius;
+    int32_t *nbr = NULL;
+    float *nd2 = NULL;
+    if (k > 0) {
+        nbr = (int32_t *)malloc(sizeof(int32_t) * (size_t)(n > 0 ? n : 1) * (size_t)k);
+        nd2 = (float *)malloc(sizeof(float) * (size_t)(n > 0 ? n : 1) * (size_t)k);
+        if (!nbr || !nd2) { free(nbr); free(nd2); return 2; }
+        int rc = use_kdtree ? oracle_knn_kdtree(xyz, n, xyz, n, k, nbr, nd2)
+                            : oracle_knn_brute(xyz, n, xyz, n, k, nbr, nd2);
+        if (rc) { free(nbr); free(nd2); return rc; }
+    }
+    kd_tree t;
+    int have_tree = 0;
+    if (k == 0 && use_kdtree) {
+        if (kd_build(&t, xyz, n)) { kd_free(&t); return 2; }
+        have_tree = 1;
+    }
+    int failed = 0;
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; i++) {
+        idx_list l = {NULL, 0, 0};
+        if (k > 0) {
+            for (int s = 0; s < k; s++)
+                if (nd2[i * k + s] <= r2) list_push(&l, nbr[i * k + s]);
+        } else if (have_tree) {
+            kd_radius_rec(&t, 0, xyz + 3 * i, r2, &l);
+        } else {
+            for (int64_t j = 0; j < n; j++)
+                if (knn_key(xyz + 3 * j, xyz + 3 * i) <= r2) list_push(&l, (int32_t)j);
+        }
+        if (l.n > 0 && !l.idx) failed = 1;
+        /* one summation order whatever found the set: ascending index */
+        if (l.n > 1) qsort(l.idx, (size_t)l.n, sizeof(int32_t), cmp_i32);
+        double nn[3], curv, ev[3];
+        pca_normal(xyz, i, l.idx, l.n, viewpoint, nn, &curv, ev);
+        for (int a = 0; a < 3; a++) out_normals[3 * i + a] = nn[a];
+        if (out_curv) out_curv[i] = curv;
+        if (out_evals) for (int a = 0; a < 3; a++) out_evals[3 * i + a] = ev[a];
+        if (out_count) out_count[i] = (int32_t)l.n;
+        free(l.idx);
+    }
+    if (have_tree) kd_free(&t);
+    free(nbr);
+    free(nd2);
+    return failed ? 2 : 0;
+}
