@@ -104,6 +104,24 @@ pc_status estimate_normals(const float *xyz, int64_t n, int k, const float viewp
                            void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * estimate_normals_radius -- normals from radius neighbourhoods (Section 3,
+ * "Core operations": radius and hybrid queries; Section 4: normals from the
+ * points within 1 cm).
+ *
+ * k == 0: N(i) = every point with key(p_j, p_i) <= r2, where key is the
+ * knn_search key and r2 = radius * radius rounded to float32 (so membership
+ * is exact).  k > 0 (hybrid): the k nearest points of i with key <= r2.
+ * Covariance, normal, orientation and curvature as in estimate_normals over
+ * N(i); fewer than 3 points in N(i) give normal (0, 0, 0) and curvature 0.
+ *   radius     finite, > 0
+ *   k          0, or 1 <= k <= min(n, PCGPU_KMAX)
+ * The workspace is estimate_normals_workspace_size(n, k).
+ * ---------------------------------------------------------------------- */
+pc_status estimate_normals_radius(const float *xyz, int64_t n, float radius, int k,
+                                  const float viewpoint[3], float *out_normals, float *out_curvature,
+                                  void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * icp_point_to_plane -- rigid point-to-plane ICP (Section 3, "Iterative
  * geometric registration": alternate correspondence search and transform
  * estimation; the linear least-squares point-to-plane estimator of Low 2004

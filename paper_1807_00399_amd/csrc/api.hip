@@ -122,6 +122,32 @@ int32_t *carve_normals_batched(Carver &c, int n_clouds, const int64_t *offsets, 
 
 }  // namespace
 
+pc_status estimate_normals_radius(const float *xyz, int64_t n, float radius, int k, const float viewpoint[3],
+                                  float *out_normals, float *out_curvature, void *workspace, size_t workspace_bytes,
+                                  hipStream_t stream)
+{
+    if (n < 0 || n >= kMaxPoints || !viewpoint) return PC_EINVAL;
+    if (!(radius > 0.f) || !isfinite(radius) || k < 0 || k > PCGPU_KMAX) return PC_EINVAL;
+    if (!isfinite(viewpoint[0]) || !isfinite(viewpoint[1]) || !isfinite(viewpoint[2])) return PC_EINVAL;
+    if (n == 0) return PC_OK;
+    if (k > n) return PC_EINVAL;
+    if (!xyz || !out_normals || !workspace) return PC_EINVAL;
+    if (!aligned(xyz, 4) || !aligned(out_normals, 4) || !aligned(out_curvature, 4) || !aligned(workspace, 256))
+        return PC_EINVAL;
+    if (workspace_bytes < estimate_normals_workspace_size(n, k)) return PC_EWORKSPACE;
+    Carver c(workspace, workspace_bytes);
+    GridStore g;
+    grid_carve(c, n, 1, g);
+    if (!c.ok) return PC_EWORKSPACE;
+    g.node_budget = g_tune.node_budget;
+    if (grid_set_single_cloud(g, stream) != hipSuccess) return PC_EDEVICE;
+    if (grid_build(g, xyz, stream) != hipSuccess) return PC_EDEVICE;
+    const float r2 = radius * radius;
+    hipError_t e = k == 0 ? normals_radius_run(g, r2, viewpoint, out_normals, out_curvature, stream)
+                          : normals_run(g, xyz, k, nullptr, viewpoint, out_normals, out_curvature, stream, r2, 3);
+    return e == hipSuccess ? PC_OK : PC_EDEVICE;
+}
+
 size_t estimate_normals_batched_workspace_size(int n_clouds, const int64_t *offsets)
 {
     if (n_clouds < 1 || !valid_offsets(offsets, n_clouds)) return 0;

@@ -60,8 +60,12 @@ void icp_set_timer(hipEvent_t *b, hipEvent_t *e, int cap);
 int icp_timer_count();
 
 hipError_t knn_run(const GridStore &g, const float *qry, int64_t nq, int k, int32_t *oi, float *od, hipStream_t s);
-// k_max: the largest k of any cloud; kc: per-cloud k (device), or null to use k_max for all
+// k_max: the largest k of any cloud; kc: per-cloud k (device), or null to
+// use k_max for all; cap2: inclusive key limit of neighbours (hybrid), with
+// fewer than min_pts neighbours giving normal 0
 hipError_t normals_run(const GridStore &g, const float *xyz, int k_max, const int32_t *kc, const float *vp,
-                       float *on, float *oc, hipStream_t s);
+                       float *on, float *oc, hipStream_t s, float cap2 = INFINITY, int min_pts = 0);
+// radius neighbourhoods: every point with key <= r2
+hipError_t normals_radius_run(const GridStore &g, float r2, const float *vp, float *on, float *oc, hipStream_t s);
 
 }  // namespace pcg

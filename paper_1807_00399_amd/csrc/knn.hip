@@ -122,61 +122,15 @@ __device__ void sym3_min_eigvec(double a, double b, double c, double d, double e
     v[2] = uz * s;
 }
 
-// One query per lane over every point of every cloud in the grid; the
-// neighbourhood of a point is taken in its own cloud, with that cloud's k
-// (kc[cloud], or k for all when kc is null).
-template <int KT>
-__global__ void __launch_bounds__(kQThreads) k_normals(GridView g, int64_t n_all, const float *__restrict__ xyz, int k,
-                                                     const int32_t *__restrict__ kc, float vx, float vy, float vz,
-                                                     float *__restrict__ out_n, float *__restrict__ out_c)
+// Normal and curvature of the point (qx, qy, qz) (original index qi) from
+// its neighbourhood covariance: the unit eigenvector of the smallest
+// eigenvalue, flipped toward the viewpoint (first nonzero component made
+// positive when the product is exactly zero), curvature l0 / trace.  An
+// all-zero covariance gives normal 0 and curvature 0.
+__device__ void finish_normal(double cxx, double cxy, double cxz, double cyy, double cyz, double czz, double qx,
+                              double qy, double qz, float vx, float vy, float vz, uint32_t qi,
+                              float *__restrict__ out_n, float *__restrict__ out_c)
 {
-    __shared__ uint32_t stk[kStack * kQThreads];
-    int64_t s = xcd_block(blockIdx.x, gridDim.x) * (int64_t)kQThreads + threadIdx.x;
-    // queries are the points in sorted order, so neighbouring lanes search
-    // neighbouring cells
-    if (s >= n_all) return;
-    const int cl = key_cloud(g.keys[s]);
-    const GridParams P = g.params[cl];
-    if (kc) k = kc[cl];
-    float4 p = g.pts[s];
-    uint32_t qi = __float_as_uint(p.w);
-    Query q{p.x, p.y, p.z};
-    TopK<KT> top;
-    top.init(k);
-    search<TopK<KT>, 32>(g, P, q, top, k, stk + threadIdx.x, kQThreads);
-    // offsets from the query point are exact in float64 (differences of
-    // float32 values); covariance is translation invariant
-    double qx = p.x, qy = p.y, qz = p.z;
-    double mx = 0.0, my = 0.0, mz = 0.0;
-#pragma unroll
-    for (int t = 0; t < KT; t++) {
-        if (t < KT - k) continue;
-        uint32_t j = (uint32_t)top.h[t];
-        if (j >= (uint32_t)n_all) continue;   // unfilled slot (cannot happen for k <= n)
-        mx += (double)xyz[3 * (int64_t)j] - qx;
-        my += (double)xyz[3 * (int64_t)j + 1] - qy;
-        mz += (double)xyz[3 * (int64_t)j + 2] - qz;
-    }
-    mx /= k;
-    my /= k;
-    mz /= k;
-    double cxx = 0, cxy = 0, cxz = 0, cyy = 0, cyz = 0, czz = 0;
-#pragma unroll
-    for (int t = 0; t < KT; t++) {
-        if (t < KT - k) continue;
-        uint32_t j = (uint32_t)top.h[t];
-        if (j >= (uint32_t)n_all) continue;
-        double ex = ((double)xyz[3 * (int64_t)j] - qx) - mx;
-        double ey = ((double)xyz[3 * (int64_t)j + 1] - qy) - my;
-        double ez = ((double)xyz[3 * (int64_t)j + 2] - qz) - mz;
-        cxx += ex * ex;
-        cxy += ex * ey;
-        cxz += ex * ez;
-        cyy += ey * ey;
-        cyz += ey * ez;
-        czz += ez * ez;
-    }
-    cxx /= k; cxy /= k; cxz /= k; cyy /= k; cyz /= k; czz /= k;
     double n[3] = {0.0, 0.0, 0.0}, lam[3] = {0.0, 0.0, 0.0};
     bool zero = cxx == 0.0 && cxy == 0.0 && cxz == 0.0 && cyy == 0.0 && cyz == 0.0 && czz == 0.0;
     if (!zero) {
@@ -198,6 +152,103 @@ __global__ void __launch_bounds__(kQThreads) k_normals(GridView g, int64_t n_all
     }
 }
 
+// One query per lane over every point of every cloud in the grid; the
+// neighbourhood of a point is taken in its own cloud, with that cloud's k
+// (kc[cloud], or k for all when kc is null).  With a finite cap2 (hybrid
+// neighbourhoods) only neighbours with key <= cap2 count, and fewer than
+// min_pts of them give normal 0.
+template <int KT>
+__global__ void __launch_bounds__(kQThreads) k_normals(GridView g, int64_t n_all, const float *__restrict__ xyz, int k,
+                                                     const int32_t *__restrict__ kc, float cap2, int min_pts,
+                                                     float vx, float vy, float vz, float *__restrict__ out_n,
+                                                     float *__restrict__ out_c)
+{
+    __shared__ uint32_t stk[kStack * kQThreads];
+    int64_t s = xcd_block(blockIdx.x, gridDim.x) * (int64_t)kQThreads + threadIdx.x;
+    // queries are the points in sorted order, so neighbouring lanes search
+    // neighbouring cells
+    if (s >= n_all) return;
+    const int cl = key_cloud(g.keys[s]);
+    const GridParams P = g.params[cl];
+    if (kc) k = kc[cl];
+    float4 p = g.pts[s];
+    uint32_t qi = __float_as_uint(p.w);
+    Query q{p.x, p.y, p.z};
+    TopK<KT> top;
+    top.init(k, cap2);
+    search<TopK<KT>, 32>(g, P, q, top, k, stk + threadIdx.x, kQThreads);
+    // offsets from the query point are exact in float64 (differences of
+    // float32 values); covariance is translation invariant
+    double qx = p.x, qy = p.y, qz = p.z;
+    double mx = 0.0, my = 0.0, mz = 0.0;
+    int m = 0;
+#pragma unroll
+    for (int t = 0; t < KT; t++) {
+        if (t < KT - k) continue;
+        uint32_t j = (uint32_t)top.h[t];
+        if (j >= (uint32_t)n_all) continue;   // unfilled slot (only under a cap)
+        m++;
+        mx += (double)xyz[3 * (int64_t)j] - qx;
+        my += (double)xyz[3 * (int64_t)j + 1] - qy;
+        mz += (double)xyz[3 * (int64_t)j + 2] - qz;
+    }
+    if (m < min_pts || m == 0) {
+        finish_normal(0.0, 0.0, 0.0, 0.0, 0.0, 0.0, qx, qy, qz, vx, vy, vz, qi, out_n, out_c);
+        return;
+    }
+    mx /= m;
+    my /= m;
+    mz /= m;
+    double cxx = 0, cxy = 0, cxz = 0, cyy = 0, cyz = 0, czz = 0;
+#pragma unroll
+    for (int t = 0; t < KT; t++) {
+        if (t < KT - k) continue;
+        uint32_t j = (uint32_t)top.h[t];
+        if (j >= (uint32_t)n_all) continue;
+        double ex = ((double)xyz[3 * (int64_t)j] - qx) - mx;
+        double ey = ((double)xyz[3 * (int64_t)j + 1] - qy) - my;
+        double ez = ((double)xyz[3 * (int64_t)j + 2] - qz) - mz;
+        cxx += ex * ex;
+        cxy += ex * ey;
+        cxz += ex * ez;
+        cyy += ey * ey;
+        cyz += ey * ez;
+        czz += ez * ez;
+    }
+    cxx /= m; cxy /= m; cxz /= m; cyy /= m; cyz /= m; czz /= m;
+    finish_normal(cxx, cxy, cxz, cyy, cyz, czz, qx, qy, qz, vx, vy, vz, qi, out_n, out_c);
+}
+
+// Radius neighbourhoods: every point of the cloud with key <= r2; the
+// covariance from the one-pass sums, C = S / m - mu mu^T with mu = s / m;
+// fewer than three points give normal 0.
+__global__ void __launch_bounds__(kQThreads) k_normals_radius(GridView g, int64_t n_all, float r2, float vx,
+                                                            float vy, float vz, float *__restrict__ out_n,
+                                                            float *__restrict__ out_c)
+{
+    __shared__ uint32_t stk[kStack * kQThreads];
+    int64_t s = xcd_block(blockIdx.x, gridDim.x) * (int64_t)kQThreads + threadIdx.x;
+    if (s >= n_all) return;
+    const GridParams P = g.params[key_cloud(g.keys[s])];
+    float4 p = g.pts[s];
+    uint32_t qi = __float_as_uint(p.w);
+    Query q{p.x, p.y, p.z};
+    RadiusCov v;
+    v.init(r2);
+    search<RadiusCov, 32>(g, P, q, v, 1, stk + threadIdx.x, kQThreads);
+    double cxx = 0, cxy = 0, cxz = 0, cyy = 0, cyz = 0, czz = 0;
+    if (v.m >= 3) {
+        const double m = v.m, mx = v.sx / m, my = v.sy / m, mz = v.sz / m;
+        cxx = v.sxx / m - mx * mx;
+        cxy = v.sxy / m - mx * my;
+        cxz = v.sxz / m - mx * mz;
+        cyy = v.syy / m - my * my;
+        cyz = v.syz / m - my * mz;
+        czz = v.szz / m - mz * mz;
+    }
+    finish_normal(cxx, cxy, cxz, cyy, cyz, czz, p.x, p.y, p.z, vx, vy, vz, qi, out_n, out_c);
+}
+
 template <int KT>
 void launch_knn(const GridStore &g, const float *qry, int64_t nq, int k, int32_t *oi, float *od, hipStream_t s)
 {
@@ -206,11 +257,12 @@ void launch_knn(const GridStore &g, const float *qry, int64_t nq, int k, int32_t
 }
 
 template <int KT>
-void launch_normals(const GridStore &g, const float *xyz, int k, const int32_t *kc, const float *vp, float *on,
-                    float *oc, hipStream_t s)
+void launch_normals(const GridStore &g, const float *xyz, int k, const int32_t *kc, float cap2, int min_pts,
+                    const float *vp, float *on, float *oc, hipStream_t s)
 {
     int blocks = (int)((g.n + kQThreads - 1) / kQThreads);
-    k_normals<KT><<<blocks, kQThreads, 0, s>>>(g.view(), g.n, xyz, k, kc, vp[0], vp[1], vp[2], on, oc);
+    k_normals<KT><<<blocks, kQThreads, 0, s>>>(g.view(), g.n, xyz, k, kc, cap2, min_pts, vp[0], vp[1], vp[2], on,
+                                               oc);
 }
 
 }  // namespace
@@ -227,13 +279,21 @@ hipError_t knn_run(const GridStore &g, const float *qry, int64_t nq, int k, int3
 }
 
 hipError_t normals_run(const GridStore &g, const float *xyz, int k_max, const int32_t *kc, const float *vp,
-                       float *on, float *oc, hipStream_t s)
+                       float *on, float *oc, hipStream_t s, float cap2, int min_pts)
 {
     if (g.n <= 0) return hipSuccess;
-    if (k_max <= 4) launch_normals<4>(g, xyz, k_max, kc, vp, on, oc, s);
-    else if (k_max <= 8) launch_normals<8>(g, xyz, k_max, kc, vp, on, oc, s);
-    else if (k_max <= 16) launch_normals<16>(g, xyz, k_max, kc, vp, on, oc, s);
-    else launch_normals<32>(g, xyz, k_max, kc, vp, on, oc, s);
+    if (k_max <= 4) launch_normals<4>(g, xyz, k_max, kc, cap2, min_pts, vp, on, oc, s);
+    else if (k_max <= 8) launch_normals<8>(g, xyz, k_max, kc, cap2, min_pts, vp, on, oc, s);
+    else if (k_max <= 16) launch_normals<16>(g, xyz, k_max, kc, cap2, min_pts, vp, on, oc, s);
+    else launch_normals<32>(g, xyz, k_max, kc, cap2, min_pts, vp, on, oc, s);
+    return hipGetLastError();
+}
+
+hipError_t normals_radius_run(const GridStore &g, float r2, const float *vp, float *on, float *oc, hipStream_t s)
+{
+    if (g.n <= 0) return hipSuccess;
+    int blocks = (int)((g.n + kQThreads - 1) / kQThreads);
+    k_normals_radius<<<blocks, kQThreads, 0, s>>>(g.view(), g.n, r2, vp[0], vp[1], vp[2], on, oc);
     return hipGetLastError();
 }
 

@@ -31,20 +31,24 @@ constexpr int kVisitBudget = 1 << 20;   // node pops per DFS; only a corrupted t
 
 __device__ inline uint64_t enc_cand(float key, float w) { return ((uint64_t)__float_as_uint(key) << 32) | __float_as_uint(w); }
 
-// k best candidates by (float32 key, original index): the k-NN definition.
+// k best candidates by (float32 key, original index): the k-NN definition;
+// with a finite cap2, only candidates with key <= cap2 (hybrid
+// neighbourhoods: the k nearest within a radius).
 template <int KT>
 struct TopK {
     uint64_t h[KT];     // ascending; ~0 = empty; 0 = padding when k < KT
+    float cap2;         // inclusive key limit, +inf for plain k-NN
 
-    __device__ void init(int k)
+    __device__ void init(int k, float cap = INFINITY)
     {
 #pragma unroll
         for (int s = 0; s < KT; s++) h[s] = (s < KT - k) ? 0ull : ~0ull;
+        cap2 = cap;
     }
     __device__ bool have() const { return h[KT - 1] != ~0ull; }
     __device__ float bound2() const
     {
-        return have() ? __uint_as_float((uint32_t)(h[KT - 1] >> 32)) : INFINITY;
+        return have() ? fminf(__uint_as_float((uint32_t)(h[KT - 1] >> 32)), cap2) : cap2;
     }
     __device__ void insert(uint64_t c)
     {
@@ -60,7 +64,36 @@ struct TopK {
     }
     __device__ void visit(float qx, float qy, float qz, uint32_t, const float4 &p, uint32_t)
     {
-        insert(enc_cand(knn_key(p.x, p.y, p.z, qx, qy, qz), p.w));
+        float key = knn_key(p.x, p.y, p.z, qx, qy, qz);
+        if (key <= cap2) insert(enc_cand(key, p.w));
+    }
+};
+
+// Every candidate with key <= r2 (radius neighbourhoods): count, sums of
+// the offsets d = p - q and of their products, in float64 (offsets of
+// float32 values are exact in float64).
+struct RadiusCov {
+    float r2;
+    int32_t m;
+    double sx, sy, sz, sxx, sxy, sxz, syy, syz, szz;
+
+    __device__ void init(float radius2)
+    {
+        r2 = radius2;
+        m = 0;
+        sx = sy = sz = sxx = sxy = sxz = syy = syz = szz = 0.0;
+    }
+    __device__ bool have() const { return true; }
+    __device__ float bound2() const { return r2; }
+    __device__ void visit(float qx, float qy, float qz, uint32_t, const float4 &p, uint32_t)
+    {
+        if (knn_key(p.x, p.y, p.z, qx, qy, qz) <= r2) {
+            double dx = (double)p.x - (double)qx, dy = (double)p.y - (double)qy, dz = (double)p.z - (double)qz;
+            m++;
+            sx += dx; sy += dy; sz += dz;
+            sxx += dx * dx; sxy += dx * dy; sxz += dx * dz;
+            syy += dy * dy; syz += dy * dz; szz += dz * dz;
+        }
     }
 };
 

@@ -23,7 +23,7 @@ KMAX = 32
 EXPORTS = (
     "pc_status_string",
     "knn_search_workspace_size", "knn_search",
-    "estimate_normals_workspace_size", "estimate_normals",
+    "estimate_normals_workspace_size", "estimate_normals", "estimate_normals_radius",
     "icp_point_to_plane_workspace_size", "icp_point_to_plane", "icp_point_to_point", "icp_combined",
     "icp_projective_workspace_size", "icp_projective",
     "estimate_normals_batched_workspace_size", "estimate_normals_batched",
@@ -61,6 +61,8 @@ def _load() -> ctypes.CDLL:
     lib.estimate_normals_workspace_size.restype = sz
     lib.estimate_normals.argtypes = [vp, i64, i32, ctypes.POINTER(ctypes.c_float), vp, vp, vp, sz, vp]
     lib.estimate_normals.restype = ctypes.c_int
+    lib.estimate_normals_radius.argtypes = [vp, i64, f32, i32, ctypes.POINTER(ctypes.c_float), vp, vp, vp, sz, vp]
+    lib.estimate_normals_radius.restype = ctypes.c_int
     lib.icp_point_to_plane_workspace_size.argtypes = [i64, i64, i32]
     lib.icp_point_to_plane_workspace_size.restype = sz
     lib.icp_point_to_plane.argtypes = [vp, i64, vp, vp, i64, vp, f32, i32, f64, vp, vp, vp, sz, vp]
@@ -173,6 +175,23 @@ def estimate_normals(xyz: torch.Tensor, k: int, viewpoint=(0.0, 0.0, 0.0), curva
     st = lib.estimate_normals(xyz.data_ptr(), n, int(k), vp, nrm.data_ptr(), _ptr(cur), ws.data_ptr(),
                               ws.numel(), _stream(stream))
     _check(st, "estimate_normals")
+    return nrm, cur
+
+
+def estimate_normals_radius(xyz: torch.Tensor, radius: float, k: int = 0, viewpoint=(0.0, 0.0, 0.0),
+                            curvature: bool = True, stream=None, workspace: torch.Tensor | None = None):
+    """Normals from radius (k = 0) or hybrid (k nearest within the radius)
+    neighbourhoods: (n,3) float32 and curvature (n,) or None."""
+    xyz = _pts(xyz, "xyz")
+    n = xyz.shape[0]
+    nrm = torch.empty((n, 3), dtype=torch.float32, device=xyz.device)
+    cur = torch.empty((n,), dtype=torch.float32, device=xyz.device) if curvature else None
+    vp = (ctypes.c_float * 3)(*[float(v) for v in viewpoint])
+    need = lib.estimate_normals_workspace_size(n, max(int(k), 1))
+    ws = workspace if workspace is not None else _ws.get(need, xyz.device)
+    st = lib.estimate_normals_radius(xyz.data_ptr(), n, float(radius), int(k), vp, nrm.data_ptr(), _ptr(cur),
+                                     ws.data_ptr(), ws.numel(), _stream(stream))
+    _check(st, "estimate_normals_radius")
     return nrm, cur
 
 

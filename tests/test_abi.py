@@ -207,3 +207,22 @@ def test_projective_rejects_bad_arguments(pc):
     assert call(d=0.0) == pc.PC_EINVAL
     assert call(nrm=None) == pc.PC_EINVAL
     assert call(wb=ws - 1) == pc.PC_EWORKSPACE
+
+
+def test_radius_normals_reject_bad_arguments(pc):
+    L = pc.lib
+    vp = (ctypes.c_float * 3)(0, 0, 0)
+    ws = L.estimate_normals_workspace_size(100, 10)
+
+    def call(r=0.01, k=0, x=FAKE, v=vp, wb=ws):
+        return L.estimate_normals_radius(x, 100, r, k, v, FAKE, None, FAKE, wb, None)
+
+    assert call(r=0.0) == pc.PC_EINVAL
+    assert call(r=float("inf")) == pc.PC_EINVAL
+    assert call(k=-1) == pc.PC_EINVAL
+    assert call(k=101) == pc.PC_EINVAL
+    assert call(k=33) == pc.PC_EINVAL
+    assert call(x=None) == pc.PC_EINVAL
+    assert call(v=None) == pc.PC_EINVAL
+    assert call(wb=ws - 1) == pc.PC_EWORKSPACE
+    assert L.estimate_normals_radius(None, 0, 0.01, 0, vp, None, None, None, 0, None) == pc.PC_OK
