@@ -1,0 +1,94 @@
+"""Pins for the oracle of the learned initialiser (CPU): the forward pass
+against an explicit per-point loop, the bfloat16 rounding rule, the
+quaternion map and start rotations against scipy, and multi-start selection
+on a pair whose basins are known."""
+import math
+
+import numpy as np
+from scipy.spatial.transform import Rotation
+
+from gen import apply_rigid, random_rigid, rng_for, sphere_plane
+from oracle import pose_net as pn
+from tests.helpers import pose_err, rot_angle
+
+
+def _params(seed):
+    rng = np.random.default_rng(seed)
+    out = []
+    for name, shp in pn.SHAPES:
+        fan_in = shp[0] if len(shp) == 2 else 1
+        scale = math.sqrt(2.0 / fan_in) if name.startswith("W") else 0.1
+        out.append((rng.standard_normal(int(np.prod(shp))) * scale).astype(np.float32))
+    return np.concatenate(out)
+
+
+def test_bf16_rounding_rule():
+    x = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 2 ** -7 + 2 ** -9, 3.0 + 2 ** -7, -2.5, 0.0], np.float32)
+    # 1 + 2^-8 is halfway between 1 and 1 + 2^-7: ties to even -> 1
+    assert pn.bf16(x).tolist() == [1.0, 1.0, 1.0 + 2 ** -7, 3.0, -2.5, 0.0]   # ulp at 1 is 2^-7
+    r = np.random.default_rng(1).standard_normal(10000).astype(np.float32)
+    b = pn.bf16(r)
+    assert np.all(np.abs(b - r) <= np.abs(r) * 2 ** -8 + 1e-38)
+    assert np.all((b.astype(np.float32).view(np.uint32) & 0xFFFF) == 0)
+
+
+def test_encoder_matches_per_point_loop():
+    params = _params(2)
+    P = pn.unpack(params)
+    pts = sphere_plane(rng_for(800), 300)
+    f, arg, c = pn.encode(params, pts)
+    x, c2, s = pn.normalise(pts)
+    assert np.allclose(c, pts.astype(np.float64).mean(0)) and np.array_equal(c, c2)
+    W2, W3 = pn.bf16(P["W2"]), pn.bf16(P["W3"])
+    best = np.full(256, -1.0)
+    bi = np.zeros(256, int)
+    for i in range(len(x)):
+        a1 = [max(0.0, sum(float(x[i, k]) * float(P["W1"][k, j]) for k in range(3)) + float(P["b1"][j]))
+              for j in range(64)]
+        a1 = pn.bf16(np.array(a1, np.float32))
+        a2 = pn.bf16(np.maximum(a1 @ W2 + P["b2"], 0.0).astype(np.float32))
+        a3 = np.maximum(a2 @ W3 + P["b3"], 0.0)
+        up = a3 > best
+        best[up] = a3[up]
+        bi[up] = i
+    assert np.allclose(f, best, rtol=1e-12, atol=1e-12) and np.array_equal(arg, bi)
+
+
+def test_quaternion_map_and_start_rotations():
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        q = rng.standard_normal(4)
+        R = pn.quat_to_R(q)
+        ref = Rotation.from_quat([q[1], q[2], q[3], q[0]]).as_matrix()      # scipy: (x, y, z, w)
+        assert np.allclose(R, ref, atol=1e-14)
+    rots = pn.start_rotations()
+    assert len(rots) == 8 and np.array_equal(rots[0], np.eye(3))
+    ax = pn.fibonacci_axes(7)
+    assert np.allclose(np.linalg.norm(ax, axis=1), 1.0)
+    for R, a in zip(rots[1:], ax):
+        rv = Rotation.from_matrix(R).as_rotvec()
+        assert abs(np.linalg.norm(rv) - math.radians(60)) < 1e-12
+        assert np.allclose(rv / np.linalg.norm(rv), a, atol=1e-12)
+
+
+def test_multi_start_picks_the_right_basin(oracle_mod):
+    # an asymmetric room subsample turned by start rotation 3 and 8 degrees
+    # more: the identity start is far outside the basin, start 3 inside it,
+    # and the exact copy gives rms ~ 0 there
+    from gen.scenes import room_scan
+    rng = rng_for(801)
+    pix = np.sort(rng.choice(640 * 480, size=4096, replace=False))
+    src = room_scan(rng, pixels=pix)
+    R = pn.axis_angle(rng.standard_normal(3), math.radians(8.0)) @ pn.start_rotations()[3]
+    cs = src.astype(np.float64).mean(0)
+    T = np.eye(4)
+    T[:3, :3] = R
+    T[:3, 3] = cs - R @ cs + np.array([0.05, -0.02, 0.03])
+    tgt = apply_rigid(T, src)
+    nrm = oracle_mod.normals(tgt, 10, (0, 0, 0))[0].astype(np.float32)
+    best, bi = pn.multi_start_icp(oracle_mod, src, tgt, nrm, 0.2, 40)
+    assert bi == 3
+    ea, et = pose_err(best["T"], T)
+    assert ea < 1e-6 and et < 1e-6 and best["rms"] < 1e-5
+    plain = oracle_mod.icp(src, tgt, nrm, pn.start_poses(src, tgt)[0], 0.2, 40)
+    assert plain["rms"] > best["rms"] and rot_angle(plain["T"][:3, :3], T[:3, :3]) > 0.1
