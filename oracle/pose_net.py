@@ -19,6 +19,10 @@ initialiser in front of the paper's ICP:
     q = W5^T h + b5 (4), the unit quaternion q / |q| (w, x, y, z) is the
     rotation R; the initial pose is T0 = [R, c_tgt - R c_src] with c the
     centroids.
+  * training loss of a pair: |R(q) - R_label|_F^2, weighted per pair and
+    summed; its gradient (loss_and_grad) is the dense chain rule over every
+    point of every cloud, with the bfloat16 roundings taken as the identity
+    (straight-through) and the rounded W2, W3 standing in for W2, W3.
   * multi-start ICP: point-to-plane ICP (oracle.icp) from the identity
     rotation and from 7 rotations of 60 degrees about Fibonacci-sphere axes,
     each about the source centroid onto the target centroid; the result with
@@ -26,8 +30,9 @@ initialiser in front of the paper's ICP:
 
 Pinned in tests/test_oracle_pose_net.py: the forward against an explicit
 per-point loop, the rounding rule, the quaternion map against scipy, the
-start rotations' angles and axes, and multi-start selection on pairs whose
-basins are known.
+start rotations' angles and axes, multi-start selection on pairs whose
+basins are known, and the gradient (without rounding) against central
+finite differences of the loss.
 """
 from __future__ import annotations
 
@@ -85,6 +90,85 @@ def encode(params, pts):
     a2 = bf16(a2.astype(np.float32))
     a3 = np.maximum(a2 @ bf16(P["W3"]) + P["b3"], 0.0)
     return a3.max(axis=0), a3.argmax(axis=0), c
+
+
+def _encoder(P, pts, round_bf16=True):
+    """Per-point activations of one cloud (float64): x, pre-activations
+    z1..z3, activations a1..a3, the weights used for layers 2, 3, the
+    feature and arg-max."""
+    rnd = bf16 if round_bf16 else (lambda v: np.asarray(v, np.float64))
+    x, c, _ = normalise(pts)
+    x = x.astype(np.float64)
+    W2 = rnd(P["W2"])
+    W3 = rnd(P["W3"])
+    z1 = x @ np.asarray(P["W1"], np.float64) + P["b1"]
+    a1 = rnd(np.maximum(z1, 0.0).astype(np.float32)) if round_bf16 else np.maximum(z1, 0.0)
+    z2 = a1 @ W2 + P["b2"]
+    a2 = rnd(np.maximum(z2, 0.0).astype(np.float32)) if round_bf16 else np.maximum(z2, 0.0)
+    z3 = a2 @ W3 + P["b3"]
+    a3 = np.maximum(z3, 0.0)
+    return dict(x=x, z1=z1, a1=a1, z2=z2, a2=a2, z3=z3, W2=W2, W3=W3, f=a3.max(axis=0),
+                arg=a3.argmax(axis=0), c=c)
+
+
+def _quat_loss_grad(q, R_label):
+    """|R(q/|q|) - R_label|_F^2 and its gradient in q, from
+    R(u) = (w^2 - v.v) I + 2 v v^T + 2 w [v]_x with u = (w, v)."""
+    q = np.asarray(q, np.float64)
+    nq = np.linalg.norm(q)
+    if not nq > 0:
+        return 0.0, np.zeros(4)
+    u = q / nq
+    w, v = u[0], u[1:]
+    D = 2.0 * (quat_to_R(u) - R_label)          # dL/dR
+    L = float(np.sum((quat_to_R(u) - R_label) ** 2))
+    cross = np.array([D[2, 1] - D[1, 2], D[0, 2] - D[2, 0], D[1, 0] - D[0, 1]])
+    du = np.empty(4)
+    du[0] = 2.0 * w * np.trace(D) + 2.0 * (v @ cross)
+    du[1:] = -2.0 * v * np.trace(D) + 2.0 * (D + D.T) @ v + 2.0 * w * cross
+    return L, (du - u * (u @ du)) / nq
+
+
+def loss_and_grad(params, pairs, labels, weights=None, round_bf16=True):
+    """Sum over pairs of weight * |R(q) - R_label|^2 and its gradient in the
+    flat parameters.  pairs: list of (src, tgt) point arrays; labels: 3x3
+    rotations (or 4x4 poses); weights: per pair, default 1."""
+    params = np.asarray(params)
+    P = unpack(params.astype(np.float64))
+    G = {k: np.zeros_like(v, dtype=np.float64) for k, v in P.items()}
+    total = 0.0
+    for p, (src, tgt) in enumerate(pairs):
+        wgt = 1.0 if weights is None else float(weights[p])
+        if wgt == 0.0:
+            continue
+        enc = [_encoder(P, src, round_bf16), _encoder(P, tgt, round_bf16)]
+        fcat = np.concatenate([enc[0]["f"], enc[1]["f"]])
+        z4 = fcat @ P["W4"] + P["b4"]
+        h = np.maximum(z4, 0.0)
+        q = h @ P["W5"] + P["b5"]
+        L, dq = _quat_loss_grad(q, np.asarray(labels[p], np.float64)[:3, :3])
+        total += wgt * L
+        dq = wgt * dq
+        G["W5"] += np.outer(h, dq)
+        G["b5"] += dq
+        dz4 = (P["W5"] @ dq) * (z4 > 0)
+        G["W4"] += np.outer(fcat, dz4)
+        G["b4"] += dz4
+        dfcat = P["W4"] @ dz4
+        for side, e in enumerate(enc):
+            df = dfcat[side * C3:(side + 1) * C3]
+            dz3 = np.zeros_like(e["z3"])
+            cols = np.arange(C3)
+            dz3[e["arg"], cols] = np.where(e["f"] > 0, df, 0.0)
+            G["W3"] += e["a2"].T @ dz3
+            G["b3"] += dz3.sum(axis=0)
+            dz2 = (dz3 @ e["W3"].T) * (e["z2"] > 0)
+            G["W2"] += e["a1"].T @ dz2
+            G["b2"] += dz2.sum(axis=0)
+            dz1 = (dz2 @ e["W2"].T) * (e["z1"] > 0)
+            G["W1"] += e["x"].T @ dz1
+            G["b1"] += dz1.sum(axis=0)
+    return total, np.concatenate([G[name].ravel() for name, _ in SHAPES])
 
 
 def quat_to_R(q):

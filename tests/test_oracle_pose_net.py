@@ -92,3 +92,51 @@ def test_multi_start_picks_the_right_basin(oracle_mod):
     assert ea < 1e-6 and et < 1e-6 and best["rms"] < 1e-5
     plain = oracle_mod.icp(src, tgt, nrm, pn.start_poses(src, tgt)[0], 0.2, 40)
     assert plain["rms"] > best["rms"] and rot_angle(plain["T"][:3, :3], T[:3, :3]) > 0.1
+
+
+def _pair_set(seed, n=150, count=2):
+    rng = rng_for(seed)
+    out, labels = [], []
+    for _ in range(count):
+        src = sphere_plane(rng, n)
+        T = random_rigid(rng, 40.0, 0.1)
+        out.append((src, apply_rigid(T, src)))
+        labels.append(T)
+    return out, labels
+
+
+def test_gradient_matches_finite_differences():
+    params = _params(4).astype(np.float64)
+    pairs, labels = _pair_set(802)
+    w = [1.0, 0.5]
+    L, g = pn.loss_and_grad(params, pairs, labels, w, round_bf16=False)
+    assert L > 0.1
+    rng = np.random.default_rng(5)
+    offs = np.cumsum([0] + [int(np.prod(s)) for _, s in pn.SHAPES])
+    idx = []
+    for a, b in zip(offs[:-1], offs[1:]):          # every tensor, largest |g| and random entries
+        seg = np.abs(g[a:b])
+        idx += [a + int(np.argmax(seg))] + list(a + rng.integers(0, b - a, 3))
+    for i in idx:
+        h = 1e-6 * max(1.0, abs(params[i]))
+        pp, pm = params.copy(), params.copy()
+        pp[i] += h
+        pm[i] -= h
+        fd = (pn.loss_and_grad(pp, pairs, labels, w, round_bf16=False)[0] -
+              pn.loss_and_grad(pm, pairs, labels, w, round_bf16=False)[0]) / (2 * h)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(g[i])) + 1e-7, (i, fd, g[i])
+
+
+def test_gradient_zero_weight_and_exact_label():
+    params = _params(5)
+    pairs, labels = _pair_set(803)
+    L, g = pn.loss_and_grad(params, pairs, labels, [0.0, 0.0])
+    assert L == 0.0 and not g.any()
+    # the network's own prediction as the label: zero loss, zero gradient
+    Rp = [pn.predict(params, s, t)[:3, :3] for s, t in pairs]
+    L, g = pn.loss_and_grad(params, pairs, Rp)
+    assert L < 1e-20 and np.abs(g).max() < 1e-8
+    # loss value: the rotation angle theta between prediction and label gives 8 sin^2(theta / 2)
+    lab = [pn.axis_angle([0, 0, 1], 0.7) @ R for R in Rp]
+    L, _ = pn.loss_and_grad(params, pairs[:1], lab[:1])
+    assert abs(L - 8 * math.sin(0.35) ** 2) < 1e-12
