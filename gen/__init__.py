@@ -10,6 +10,10 @@ from .scenes import (  # noqa: F401
     Workload,
     BatchWorkload,
     batch_workload,
+    pose_pairs,
+    pose_net_init,
+    POSE_CONFIG,
+    POSE_NET_SHAPES,
     make_workload,
     random_rigid,
     apply_rigid,

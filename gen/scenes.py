@@ -339,6 +339,56 @@ def batch_workload(config: int = 3, size: str = "full", n_pairs: int | None = No
     return BatchWorkload(name, pairs)
 
 
+# learned-initialiser workload: evaluation pairs come from config 4,
+# training pairs from config 40 (disjoint generator streams)
+POSE_CONFIG = dict(name="pose_pairs", n_pairs=512, n_points=4096, angle=(0.0, 90.0), t=(0.0, 0.3), k=10,
+                   d_max=0.3, iters=30, accept_rms=0.004, eval_config=4, train_config=40)
+
+
+def pose_pairs(config: int = 4, n_pairs: int | None = None, n_points: int | None = None,
+               first: int = 0) -> BatchWorkload:
+    """Pairs for the learned initialiser.  Pair j (generator rng_for(config,
+    first + j)) is a sphere + plane cloud or a new random room scan, each
+    with probability 1/2, of n_points points (rooms: that many of a 640x480
+    frame's pixels, drawn without replacement, kept in raster order); the
+    target is T * source exactly (the same points), with a rotation angle
+    U(0, 90) degrees about a random axis and a translation of length
+    U(0, 0.3)."""
+    c = POSE_CONFIG
+    m = c["n_pairs"] if n_pairs is None else n_pairs
+    n = c["n_points"] if n_points is None else n_points
+    pairs = []
+    for j in range(first, first + m):
+        rng = rng_for(config, j)
+        kind = 0 if rng.random() < 0.5 else 1
+        if kind == 0:
+            src = sphere_plane(rng, n)
+        else:
+            pix = np.sort(rng.choice(640 * 480, size=min(n, 640 * 480), replace=False))
+            src = room_scan(rng, 640, 480, pixels=pix)
+        T = random_rigid(rng, rng.uniform(*c["angle"]), rng.uniform(*c["t"]))
+        pairs.append(Workload(f"{c['name']}_{j}_{'sphere' if kind == 0 else 'room'}", src, apply_rigid(T, src), T,
+                              c["k"], c["d_max"], c["iters"]))
+    return BatchWorkload(f"{c['name']}_{m}", pairs)
+
+
+# layer shapes of the learned initialiser's flat parameter vector (W[in][out], then b)
+POSE_NET_SHAPES = ((3, 64), (64,), (64, 128), (128,), (128, 256), (256,), (512, 256), (256,), (256, 4), (4,))
+
+
+def pose_net_init(rng: np.random.Generator) -> np.ndarray:
+    """Initial parameters: weights N(0, 2 / fan_in), biases 0 except the last
+    (1, 0, 0, 0), the identity quaternion.  float32, flat."""
+    out = []
+    for shp in POSE_NET_SHAPES:
+        if len(shp) == 2:
+            out.append(rng.standard_normal(shp[0] * shp[1]) * math.sqrt(2.0 / shp[0]))
+        else:
+            out.append(np.zeros(shp[0]))
+    out[-1][0] = 1.0
+    return np.concatenate(out).astype(np.float32)
+
+
 def make_workload(config: int, pair: int = 0, size: str = "full") -> Workload:
     """Build workload ``config`` (0, 1 or 2).
 

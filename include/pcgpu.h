@@ -281,6 +281,82 @@ pc_status icp_point_to_plane_batched(int n_pairs, const float *src_xyz, const in
                                      void *workspace, size_t workspace_bytes, hipStream_t stream);
 
 /* ------------------------------------------------------------------------
+ * Learned pose initialiser and multi-start ICP.  Not part of the paper's
+ * method, whose ICP starts from a given pose (Section 3, "Iterative
+ * geometric registration"); these entry points supply that pose.
+ *
+ * Network (flat float32 parameters, pose_net_param_count() of them, in this
+ * order, row-major W[in][out]): W1 3x64, b1 64, W2 64x128, b2 128, W3
+ * 128x256, b3 256, W4 512x256, b4 256, W5 256x4, b5 4.  Per cloud, points
+ * are centred on the centroid and scaled by the inverse RMS distance to it;
+ * per point 3 -> 64 -> 128 -> 256 with ReLU after each layer, the inputs of
+ * the second and third layers and W2, W3 rounded to bfloat16 (matrix cores,
+ * float32 accumulation); the cloud feature f is the per-channel maximum.
+ * Per pair: h = ReLU(W4^T [f_src; f_tgt] + b4), q = W5^T h + b5, R the
+ * rotation of the unit quaternion q / |q| (w, x, y, z; the identity when
+ * q = 0) and T0 = [R, c_tgt - R c_src] with c the centroids.  Pairs are
+ * packed as in the batched forms (host offsets src_off, tgt_off).
+ * ---------------------------------------------------------------------- */
+int pose_net_param_count(void);
+/* workspace of pose_net_predict and pose_net_train_step */
+size_t pose_net_workspace_size(int n_pairs, const int64_t *src_off, const int64_t *tgt_off);
+/* T0 of every pair into out_T (n_pairs, 16) float64. */
+pc_status pose_net_predict(const float *params, int n_pairs,
+                           const float *src_xyz, const int64_t *src_off,
+                           const float *tgt_xyz, const int64_t *tgt_off,
+                           double *out_T, void *workspace, size_t workspace_bytes,
+                           hipStream_t stream);
+/* One training step on n_pairs pairs with label poses label_T (n_pairs,
+ * 16; only the rotation is used): loss_p = w_p |R_p - R_label,p|_F^2 with
+ * w_p = pair_weight[p] (NULL: all 1).  The gradient of sum_p loss_p is taken
+ * with the bfloat16 roundings passed through unchanged; when lr > 0, Adam
+ * (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected with `step` >= 1)
+ * updates params in place with that gradient divided by sum_p w_p, using
+ * and updating the caller's moment arrays adam_m, adam_v (pose_net_param_count
+ * floats each, zero before step 1).  lr = 0 leaves params, adam_m and adam_v
+ * untouched (they may be NULL).  Optional outputs: out_loss (n_pairs
+ * float32, loss_p), out_grad (pose_net_param_count float32, the summed
+ * gradient).  Deterministic: no atomics. */
+pc_status pose_net_train_step(float *params, float *adam_m, float *adam_v, int step, float lr,
+                              int n_pairs, const float *src_xyz, const int64_t *src_off,
+                              const float *tgt_xyz, const int64_t *tgt_off,
+                              const double *label_T, const float *pair_weight,
+                              float *out_loss, float *out_grad,
+                              void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* Registration of n_pairs packed pairs by icp_point_to_plane_batched
+ * (shared max_corr_dist and max_iters) from:
+ *   PC_INIT_LEARNED       T0 of the network; pairs whose result is not
+ *                         (status CONVERGED or MAXITER, inliers > 0 and
+ *                         rms <= accept_rms) are registered again by
+ *                         multi-start ICP and take its result;
+ *   PC_INIT_MULTI_START   multi-start ICP for every pair (params unused,
+ *                         may be NULL);
+ *   PC_INIT_LEARNED_ONLY  T0 of the network, no fallback.
+ * Multi-start ICP runs kStarts = 8 registrations per pair, from the
+ * rotations identity and 60 degrees about each of the 7 Fibonacci-sphere
+ * axes a_i = (r cos(i g), r sin(i g), z), z = 1 - (2i + 1) / 7,
+ * r = sqrt(1 - z^2), g = pi (3 - sqrt 5), each about the source centroid
+ * onto the target centroid, and keeps the first start unless a later one
+ * has inliers and either the kept one has none or a lower rms.
+ *   out_T      (n_pairs, 16) float64
+ *   out_stats  n_pairs pc_icp_stats, or NULL
+ *   out_start  n_pairs int32 (device), or NULL: -1 when the learned start
+ *              was kept, else the multi-start index 0..7
+ * With PC_INIT_LEARNED the call waits for the stream once (the fallback
+ * set depends on the first results).  Points per side times 8 must stay
+ * below 2^31. */
+enum { PC_INIT_LEARNED = 0, PC_INIT_MULTI_START = 1, PC_INIT_LEARNED_ONLY = 2 };
+size_t icp_learned_batched_workspace_size(int n_pairs, const int64_t *src_off, const int64_t *tgt_off,
+                                          int max_iters);
+pc_status icp_learned_batched(int mode, const float *params, int n_pairs,
+                              const float *src_xyz, const int64_t *src_off,
+                              const float *tgt_xyz, const float *tgt_normals, const int64_t *tgt_off,
+                              float max_corr_dist, int max_iters, double conv_tol, float accept_rms,
+                              double *out_T, pc_icp_stats *out_stats, int32_t *out_start,
+                              void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/* ------------------------------------------------------------------------
  * Tuning (process-wide; not thread-safe): launch shape and pyramid depth of
  * later calls.  Every setting finds the same exact neighbours and
  * correspondences; the block size only regroups the compensated per-block

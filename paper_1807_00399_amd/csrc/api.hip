@@ -5,6 +5,7 @@
 #include <vector>
 
 #include "icp.h"
+#include "pose_net.h"
 
 using namespace pcg;
 
@@ -358,6 +359,34 @@ size_t icp_point_to_plane_batched_workspace_size(int n_pairs, const int64_t *src
     return c.used();
 }
 
+namespace {
+
+// batched point-to-plane ICP in a workspace region (arguments already checked)
+pc_status batched_core(int n_pairs, const float *src_xyz, const int64_t *src_off, const float *tgt_xyz,
+                       const float *tgt_normals, const int64_t *tgt_off, const double *init_T,
+                       const float *max_corr_dist, const int32_t *max_iters, int iters_max, double conv_tol,
+                       double *out_T, pc_icp_stats *out_stats, void *workspace, size_t workspace_bytes,
+                       hipStream_t stream)
+{
+    Carver c(workspace, workspace_bytes);
+    IcpStore s;
+    std::vector<int32_t> boff, goff;
+    carve_batched(c, n_pairs, src_off, tgt_off, iters_max, s, &boff, &goff);
+    if (!c.ok) return PC_EWORKSPACE;
+    if (!upload(s.soff, src_off, sizeof(int64_t) * (n_pairs + 1), stream) ||
+        !upload(s.grid.off, tgt_off, sizeof(int64_t) * (n_pairs + 1), stream) ||
+        !upload(s.boff, boff.data(), sizeof(int32_t) * (n_pairs + 1), stream) ||
+        !upload(s.goff, goff.data(), sizeof(int32_t) * (n_pairs + 1), stream) ||
+        !upload(s.dmax, max_corr_dist, sizeof(float) * n_pairs, stream) ||
+        !upload(s.maxit, max_iters, sizeof(int32_t) * n_pairs, stream))
+        return PC_EDEVICE;
+    hipError_t e = icp_run(s, src_xyz, src_off[n_pairs], tgt_xyz, tgt_normals, init_T, conv_tol, out_T, out_stats,
+                           stream);
+    return e == hipSuccess ? PC_OK : PC_EDEVICE;
+}
+
+}  // namespace
+
 pc_status icp_point_to_plane_batched(int n_pairs, const float *src_xyz, const int64_t *src_off,
                                      const float *tgt_xyz, const float *tgt_normals, const int64_t *tgt_off,
                                      const double *init_T, const float *max_corr_dist, const int32_t *max_iters,
@@ -380,20 +409,284 @@ pc_status icp_point_to_plane_batched(int n_pairs, const float *src_xyz, const in
         return PC_EINVAL;
     if (workspace_bytes < icp_point_to_plane_batched_workspace_size(n_pairs, src_off, tgt_off, iters_max))
         return PC_EWORKSPACE;
-    Carver c(workspace, workspace_bytes);
-    IcpStore s;
-    std::vector<int32_t> boff, goff;
-    carve_batched(c, n_pairs, src_off, tgt_off, iters_max, s, &boff, &goff);
+    return batched_core(n_pairs, src_xyz, src_off, tgt_xyz, tgt_normals, tgt_off, init_T, max_corr_dist, max_iters,
+                        iters_max, conv_tol, out_T, out_stats, workspace, workspace_bytes, stream);
+}
+
+// ---------------------------------------------------------------------------
+// Learned pose initialiser and multi-start ICP
+// ---------------------------------------------------------------------------
+namespace {
+
+// per cloud row ranges (source p -> cloud 2p, target p -> cloud 2p + 1) and
+// encoder tile offsets
+bool pose_layout(int n_pairs, const int64_t *src_off, const int64_t *tgt_off, std::vector<int64_t> &cr,
+                 std::vector<int32_t> &toff, int &ntile)
+{
+    cr.assign((size_t)4 * n_pairs, 0);
+    toff.assign((size_t)2 * n_pairs + 1, 0);
+    int64_t tiles = 0;
+    for (int p = 0; p < n_pairs; p++) {
+        cr[4 * p] = src_off[p];
+        cr[4 * p + 1] = src_off[p + 1];
+        cr[4 * p + 2] = tgt_off[p];
+        cr[4 * p + 3] = tgt_off[p + 1];
+        tiles += pose_net_tiles(src_off[p + 1] - src_off[p]);
+        toff[2 * p + 1] = (int32_t)tiles;
+        tiles += pose_net_tiles(tgt_off[p + 1] - tgt_off[p]);
+        toff[2 * p + 2] = (int32_t)tiles;
+        if (tiles >= ((int64_t)1 << 30)) return false;
+    }
+    ntile = (int)tiles;
+    return true;
+}
+
+bool pose_args_ok(int n_pairs, const float *src_xyz, const int64_t *src_off, const float *tgt_xyz,
+                  const int64_t *tgt_off)
+{
+    if (n_pairs < 1 || n_pairs > (1 << 24) || !valid_offsets(src_off, n_pairs) || !valid_offsets(tgt_off, n_pairs))
+        return false;
+    if ((src_off[n_pairs] > 0 && !src_xyz) || (tgt_off[n_pairs] > 0 && !tgt_xyz)) return false;
+    return aligned(src_xyz, 4) && aligned(tgt_xyz, 4);
+}
+
+size_t pose_store_bytes(int n_pairs, int ntile, bool train)
+{
+    Carver c(nullptr, ~(size_t)0 >> 1);
+    PoseNetStore s;
+    pose_net_carve(c, n_pairs, ntile, train, s);
+    return c.used();
+}
+
+// carve the pose store at the front of the workspace and upload its layout
+pc_status pose_setup(Carver &c, int n_pairs, const int64_t *src_off, const int64_t *tgt_off, bool train,
+                     PoseNetStore &s, hipStream_t stream)
+{
+    std::vector<int64_t> cr;
+    std::vector<int32_t> toff;
+    int ntile = 0;
+    if (!pose_layout(n_pairs, src_off, tgt_off, cr, toff, ntile)) return PC_EINVAL;
+    pose_net_carve(c, n_pairs, ntile, train, s);
     if (!c.ok) return PC_EWORKSPACE;
-    if (!upload(s.soff, src_off, sizeof(int64_t) * (n_pairs + 1), stream) ||
-        !upload(s.grid.off, tgt_off, sizeof(int64_t) * (n_pairs + 1), stream) ||
-        !upload(s.boff, boff.data(), sizeof(int32_t) * (n_pairs + 1), stream) ||
-        !upload(s.goff, goff.data(), sizeof(int32_t) * (n_pairs + 1), stream) ||
-        !upload(s.dmax, max_corr_dist, sizeof(float) * n_pairs, stream) ||
-        !upload(s.maxit, max_iters, sizeof(int32_t) * n_pairs, stream))
+    if (!upload(s.cr, cr.data(), sizeof(int64_t) * cr.size(), stream) ||
+        !upload(s.toff, toff.data(), sizeof(int32_t) * toff.size(), stream))
         return PC_EDEVICE;
-    hipError_t e = icp_run(s, src_xyz, ns, tgt_xyz, tgt_normals, init_T, conv_tol, out_T, out_stats, stream);
-    return e == hipSuccess ? PC_OK : PC_EDEVICE;
+    return PC_OK;
+}
+
+// replicated offsets of every pair kStarts times (pair-major)
+void replicate_offsets(int n, const int32_t *sel, const int64_t *off, std::vector<int64_t> &rep)
+{
+    rep.assign(1, 0);
+    for (int i = 0; i < n; i++) {
+        const int p = sel ? sel[i] : i;
+        for (int j = 0; j < kStarts; j++) rep.push_back(rep.back() + (off[p + 1] - off[p]));
+    }
+}
+
+struct LearnedLayout {
+    PoseNetStore pose;
+    pc_icp_stats *st1, *st_all;
+    int32_t *sel;
+    int64_t *seg_s, *seg_t;
+    float *rs, *rt, *rn;
+    double *T_start, *T_all;
+    void *icp;
+    size_t icp_bytes;
+};
+
+size_t icp_region_bytes(int n_pairs, const int64_t *src_off, const int64_t *tgt_off, int max_iters)
+{
+    std::vector<int64_t> rs, rt;
+    replicate_offsets(n_pairs, nullptr, src_off, rs);
+    replicate_offsets(n_pairs, nullptr, tgt_off, rt);
+    size_t a = icp_point_to_plane_batched_workspace_size(n_pairs, src_off, tgt_off, max_iters);
+    size_t b = icp_point_to_plane_batched_workspace_size(kStarts * n_pairs, rs.data(), rt.data(), max_iters);
+    return a > b ? a : b;
+}
+
+// everything but the pose store's layout upload; returns false when the
+// workspace is too small
+bool learned_carve(Carver &c, int n_pairs, const int64_t *src_off, const int64_t *tgt_off, int max_iters, int ntile,
+                   LearnedLayout &L)
+{
+    pose_net_carve(c, n_pairs, ntile, false, L.pose);
+    const int64_t ns = src_off[n_pairs], nt = tgt_off[n_pairs];
+    const size_t R = (size_t)kStarts * n_pairs;
+    L.st1 = c.take<pc_icp_stats>(n_pairs);
+    L.st_all = c.take<pc_icp_stats>(R);
+    L.sel = c.take<int32_t>(n_pairs);
+    L.seg_s = c.take<int64_t>(3 * R);
+    L.seg_t = c.take<int64_t>(3 * R);
+    L.rs = c.take<float>((size_t)3 * kStarts * ns);
+    L.rt = c.take<float>((size_t)3 * kStarts * nt);
+    L.rn = c.take<float>((size_t)3 * kStarts * nt);
+    L.T_start = c.take<double>(16 * R);
+    L.T_all = c.take<double>(16 * R);
+    L.icp_bytes = icp_region_bytes(n_pairs, src_off, tgt_off, max_iters);
+    L.icp = c.take<uint8_t>(L.icp_bytes);
+    return c.ok;
+}
+
+}  // namespace
+
+int pose_net_param_count(void) { return kParams; }
+
+size_t pose_net_workspace_size(int n_pairs, const int64_t *src_off, const int64_t *tgt_off)
+{
+    std::vector<int64_t> cr;
+    std::vector<int32_t> toff;
+    int ntile = 0;
+    if (n_pairs < 1 || !valid_offsets(src_off, n_pairs) || !valid_offsets(tgt_off, n_pairs)) return 0;
+    if (!pose_layout(n_pairs, src_off, tgt_off, cr, toff, ntile)) return 0;
+    return pose_store_bytes(n_pairs, ntile, true);
+}
+
+pc_status pose_net_predict(const float *params, int n_pairs, const float *src_xyz, const int64_t *src_off,
+                           const float *tgt_xyz, const int64_t *tgt_off, double *out_T, void *workspace,
+                           size_t workspace_bytes, hipStream_t stream)
+{
+    if (!params || !aligned(params, 4) || !pose_args_ok(n_pairs, src_xyz, src_off, tgt_xyz, tgt_off)) return PC_EINVAL;
+    if (!out_T || !aligned(out_T, 8) || !workspace || !aligned(workspace, 256)) return PC_EINVAL;
+    if (workspace_bytes < pose_net_workspace_size(n_pairs, src_off, tgt_off)) return PC_EWORKSPACE;
+    Carver c(workspace, workspace_bytes);
+    PoseNetStore s;
+    pc_status r = pose_setup(c, n_pairs, src_off, tgt_off, false, s, stream);
+    if (r != PC_OK) return r;
+    return pose_net_forward(s, params, src_xyz, tgt_xyz, out_T, stream) == hipSuccess ? PC_OK : PC_EDEVICE;
+}
+
+pc_status pose_net_train_step(float *params, float *adam_m, float *adam_v, int step, float lr, int n_pairs,
+                              const float *src_xyz, const int64_t *src_off, const float *tgt_xyz,
+                              const int64_t *tgt_off, const double *label_T, const float *pair_weight,
+                              float *out_loss, float *out_grad, void *workspace, size_t workspace_bytes,
+                              hipStream_t stream)
+{
+    if (!params || !aligned(params, 4) || !pose_args_ok(n_pairs, src_xyz, src_off, tgt_xyz, tgt_off)) return PC_EINVAL;
+    if (step < 1 || !(lr >= 0.f) || !isfinite(lr)) return PC_EINVAL;
+    if (lr > 0.f && (!adam_m || !adam_v || !aligned(adam_m, 4) || !aligned(adam_v, 4))) return PC_EINVAL;
+    if (!label_T || !aligned(label_T, 8) || !aligned(pair_weight, 4) || !aligned(out_loss, 4) ||
+        !aligned(out_grad, 4))
+        return PC_EINVAL;
+    if (!workspace || !aligned(workspace, 256)) return PC_EINVAL;
+    if (workspace_bytes < pose_net_workspace_size(n_pairs, src_off, tgt_off)) return PC_EWORKSPACE;
+    Carver c(workspace, workspace_bytes);
+    PoseNetStore s;
+    pc_status r = pose_setup(c, n_pairs, src_off, tgt_off, true, s, stream);
+    if (r != PC_OK) return r;
+    if (pose_net_train(s, params, adam_m, adam_v, step, lr, src_xyz, tgt_xyz, label_T, pair_weight, out_loss,
+                       stream) != hipSuccess)
+        return PC_EDEVICE;
+    if (out_grad && hipMemcpyAsync(out_grad, s.grad, sizeof(float) * kParams, hipMemcpyDeviceToDevice, stream) !=
+                        hipSuccess)
+        return PC_EDEVICE;
+    return PC_OK;
+}
+
+size_t icp_learned_batched_workspace_size(int n_pairs, const int64_t *src_off, const int64_t *tgt_off,
+                                          int max_iters)
+{
+    std::vector<int64_t> cr;
+    std::vector<int32_t> toff;
+    int ntile = 0;
+    if (n_pairs < 1 || max_iters < 0 || !valid_offsets(src_off, n_pairs) || !valid_offsets(tgt_off, n_pairs))
+        return 0;
+    if ((int64_t)kStarts * src_off[n_pairs] >= kMaxPoints || (int64_t)kStarts * tgt_off[n_pairs] >= kMaxPoints)
+        return 0;
+    if (!pose_layout(n_pairs, src_off, tgt_off, cr, toff, ntile)) return 0;
+    Carver c(nullptr, ~(size_t)0 >> 1);
+    LearnedLayout L;
+    learned_carve(c, n_pairs, src_off, tgt_off, max_iters, ntile, L);
+    return c.used();
+}
+
+pc_status icp_learned_batched(int mode, const float *params, int n_pairs, const float *src_xyz,
+                              const int64_t *src_off, const float *tgt_xyz, const float *tgt_normals,
+                              const int64_t *tgt_off, float max_corr_dist, int max_iters, double conv_tol,
+                              float accept_rms, double *out_T, pc_icp_stats *out_stats, int32_t *out_start,
+                              void *workspace, size_t workspace_bytes, hipStream_t stream)
+{
+    if (mode != PC_INIT_LEARNED && mode != PC_INIT_MULTI_START && mode != PC_INIT_LEARNED_ONLY) return PC_EINVAL;
+    if (mode != PC_INIT_MULTI_START && (!params || !aligned(params, 4))) return PC_EINVAL;
+    if (!pose_args_ok(n_pairs, src_xyz, src_off, tgt_xyz, tgt_off)) return PC_EINVAL;
+    if (tgt_off[n_pairs] > 0 && (!tgt_normals || !aligned(tgt_normals, 4))) return PC_EINVAL;
+    if (max_iters < 0 || !(max_corr_dist > 0.f) || !isfinite(max_corr_dist)) return PC_EINVAL;
+    if (!(conv_tol >= 0.0) || !isfinite(conv_tol) || isnan(accept_rms)) return PC_EINVAL;
+    if (!out_T || !aligned(out_T, 8) || !aligned(out_stats, 8) || !aligned(out_start, 4)) return PC_EINVAL;
+    if (!workspace || !aligned(workspace, 256)) return PC_EINVAL;
+    const size_t need = icp_learned_batched_workspace_size(n_pairs, src_off, tgt_off, max_iters);
+    if (need == 0) return PC_EINVAL;
+    if (workspace_bytes < need) return PC_EWORKSPACE;
+
+    Carver c(workspace, workspace_bytes);
+    LearnedLayout L;
+    std::vector<int64_t> cr;
+    std::vector<int32_t> toff;
+    int ntile = 0;
+    if (!pose_layout(n_pairs, src_off, tgt_off, cr, toff, ntile)) return PC_EINVAL;
+    if (!learned_carve(c, n_pairs, src_off, tgt_off, max_iters, ntile, L)) return PC_EWORKSPACE;
+    if (!upload(L.pose.cr, cr.data(), sizeof(int64_t) * cr.size(), stream) ||
+        !upload(L.pose.toff, toff.data(), sizeof(int32_t) * toff.size(), stream))
+        return PC_EDEVICE;
+    std::vector<float> dmax(kStarts * (size_t)n_pairs, max_corr_dist);
+    std::vector<int32_t> maxit(kStarts * (size_t)n_pairs, max_iters);
+    if (out_start && fill_i32(out_start, n_pairs, -1, stream) != hipSuccess) return PC_EDEVICE;
+
+    std::vector<int32_t> sel;
+    if (mode == PC_INIT_MULTI_START) {
+        if (pose_net_stats(L.pose, src_xyz, tgt_xyz, stream) != hipSuccess) return PC_EDEVICE;
+        for (int p = 0; p < n_pairs; p++) sel.push_back(p);
+    } else {
+        // learned initial pose, then ICP from it
+        if (pose_net_forward(L.pose, params, src_xyz, tgt_xyz, L.pose.T, stream) != hipSuccess) return PC_EDEVICE;
+        pc_status r = batched_core(n_pairs, src_xyz, src_off, tgt_xyz, tgt_normals, tgt_off, L.pose.T, dmax.data(),
+                                   maxit.data(), max_iters, conv_tol, out_T, L.st1, L.icp, L.icp_bytes, stream);
+        if (r != PC_OK) return r;
+        if (out_stats && hipMemcpyAsync(out_stats, L.st1, sizeof(pc_icp_stats) * n_pairs, hipMemcpyDeviceToDevice,
+                                        stream) != hipSuccess)
+            return PC_EDEVICE;
+        if (mode == PC_INIT_LEARNED_ONLY) return PC_OK;
+        // pairs whose refinement did not reach the accepted residual
+        std::vector<pc_icp_stats> h(n_pairs);
+        if (hipMemcpyAsync(h.data(), L.st1, sizeof(pc_icp_stats) * n_pairs, hipMemcpyDeviceToHost, stream) !=
+                hipSuccess ||
+            hipStreamSynchronize(stream) != hipSuccess)
+            return PC_EDEVICE;
+        for (int p = 0; p < n_pairs; p++) {
+            const pc_icp_stats &t = h[p];
+            const bool ok = (t.status == PC_ICP_CONVERGED || t.status == PC_ICP_MAXITER) && t.inliers > 0 &&
+                            t.rms <= (double)accept_rms;
+            if (!ok) sel.push_back(p);
+        }
+    }
+    const int F = (int)sel.size();
+    if (F == 0) return PC_OK;
+    // the selected pairs, each kStarts times, gathered into contiguous clouds
+    std::vector<int64_t> rso, rto, seg_s, seg_t;
+    replicate_offsets(F, sel.data(), src_off, rso);
+    replicate_offsets(F, sel.data(), tgt_off, rto);
+    for (int i = 0; i < F; i++)
+        for (int j = 0; j < kStarts; j++) {
+            const int p = sel[i], r = i * kStarts + j;
+            seg_s.insert(seg_s.end(), {rso[r], src_off[p], src_off[p + 1] - src_off[p]});
+            seg_t.insert(seg_t.end(), {rto[r], tgt_off[p], tgt_off[p + 1] - tgt_off[p]});
+        }
+    const int R = F * kStarts;
+    if (!upload(L.sel, sel.data(), sizeof(int32_t) * F, stream) ||
+        !upload(L.seg_s, seg_s.data(), sizeof(int64_t) * seg_s.size(), stream) ||
+        !upload(L.seg_t, seg_t.data(), sizeof(int64_t) * seg_t.size(), stream))
+        return PC_EDEVICE;
+    if (gather_rows3(src_xyz, L.rs, L.seg_s, R, stream) != hipSuccess ||
+        gather_rows3(tgt_xyz, L.rt, L.seg_t, R, stream) != hipSuccess ||
+        gather_rows3(tgt_normals, L.rn, L.seg_t, R, stream) != hipSuccess ||
+        multi_start_poses(L.pose.cen, L.sel, F, L.T_start, stream) != hipSuccess)
+        return PC_EDEVICE;
+    pc_status r = batched_core(R, L.rs, rso.data(), L.rt, L.rn, rto.data(), L.T_start, dmax.data(), maxit.data(),
+                               max_iters, conv_tol, L.T_all, L.st_all, L.icp, L.icp_bytes, stream);
+    if (r != PC_OK) return r;
+    return multi_start_select(L.T_all, L.st_all, L.sel, F, out_T, out_stats, out_start, stream) == hipSuccess
+               ? PC_OK
+               : PC_EDEVICE;
 }
 
 const double *icp_history(void *workspace, size_t workspace_bytes, int64_t n_src, int64_t n_tgt, int max_iters)

@@ -1,0 +1,746 @@
+// Learned pose initialiser in front of ICP: a point-wise MLP encoder with a
+// max-pool (per cloud) and a small head (per pair) that predicts the
+// rotation; the translation aligns the centroids.  Also the pieces of
+// multi-start ICP that run on the device: start poses, replication of the
+// pairs that need them, and selection of the best start.
+//
+// Not part of the paper's method: its ICP starts from a given pose
+// (Section 3, "Iterative geometric registration").  This network proposes
+// that pose, batched ICP refines it, and pairs whose refinement does not
+// reach a small residual fall back to multi-start ICP.
+//
+// Encoder per point (centred on the cloud centroid, scaled by the inverse
+// RMS radius): 3 -> 64 (ReLU) -> 128 (ReLU) -> 256 (ReLU), then the
+// per-channel maximum over the cloud's points.  The 64 -> 128 and
+// 128 -> 256 layers are dense contractions over every point and run on the
+// bfloat16 matrix cores (v_mfma_f32_16x16x32_bf16, float32 accumulation),
+// with their inputs rounded to bfloat16; the first layer (3 inputs) and the
+// head are float32 vector code.
+//
+// Training: the loss of a pair is w_p |R(q) - R_label|_F^2.  The max-pool
+// routes each channel's gradient to one point, so the encoder's backward
+// recomputes one row per (cloud, channel) instead of keeping activations of
+// every point; the bfloat16 roundings pass gradients unchanged.  Weight
+// gradients are sums over those rows (or over pairs) formed in a fixed order
+// by chunked outer-product kernels and a second pass over the chunks: no
+// atomics, so a step is deterministic.  Adam updates the float32 master
+// parameters.
+
+#include <math.h>
+
+#include "common.h"
+#include "pose_net.h"
+
+namespace pcg {
+
+namespace {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+constexpr int kT = 128;          // points per encoder workgroup
+constexpr int kThreads = 256;    // 4 waves; wave w owns rows 32w .. 32w + 31
+constexpr int kP1 = kC1 + 8;     // padded LDS row lengths (bank spread)
+constexpr int kP2 = kC2 + 8;
+constexpr int kChunk = 128;      // rows per outer-product chunk
+
+__device__ inline __bf16 to_bf16(float x) { return (__bf16)x; }
+
+// rows of cloud c: [cr[2c], cr[2c + 1]) of the source buffer (even c) or
+// the target buffer (odd c)
+__device__ inline const float *cloud_xyz(const float *xs, const float *xt, int c) { return (c & 1) ? xt : xs; }
+
+// per cloud: centroid (float64) and inverse RMS radius
+__global__ void k_norm_stats(const float *__restrict__ xs, const float *__restrict__ xt,
+                             const int64_t *__restrict__ cr, int nc, double *__restrict__ cen,
+                             float *__restrict__ scale)
+{
+    __shared__ double red[4][4];
+    const int c = blockIdx.x;
+    if (c >= nc) return;
+    const float *X = cloud_xyz(xs, xt, c);
+    const int64_t a = cr[2 * c], b = cr[2 * c + 1];
+    double s[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = a + threadIdx.x; i < b; i += blockDim.x)
+        for (int k = 0; k < 3; k++) s[k] += X[3 * i + k];
+    for (int o = 32; o > 0; o >>= 1)
+        for (int k = 0; k < 3; k++) s[k] += __shfl_xor(s[k], o);
+    const int w = threadIdx.x >> 6;
+    if (__lane_id() == 0)
+        for (int k = 0; k < 3; k++) red[w][k] = s[k];
+    __syncthreads();
+    const double n = (double)(b - a);
+    double m[3];
+    for (int k = 0; k < 3; k++) m[k] = n > 0 ? (red[0][k] + red[1][k] + red[2][k] + red[3][k]) / n : 0.0;
+    double r2 = 0.0;
+    for (int64_t i = a + threadIdx.x; i < b; i += blockDim.x)
+        for (int k = 0; k < 3; k++) {
+            double d = X[3 * i + k] - m[k];
+            r2 += d * d;
+        }
+    for (int o = 32; o > 0; o >>= 1) r2 += __shfl_xor(r2, o);
+    if (__lane_id() == 0) red[w][3] = r2;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int k = 0; k < 3; k++) cen[3 * c + k] = m[k];
+        double rms = n > 0 ? sqrt((red[0][3] + red[1][3] + red[2][3] + red[3][3]) / n) : 0.0;
+        scale[c] = rms > 0.0 ? (float)(1.0 / rms) : 1.0f;
+    }
+}
+
+// bfloat16 copies of W2 and W3, column-major (k contiguous per output
+// column): the layout of the matrix cores' B operand
+__global__ void k_weights_bf16(const float *__restrict__ params, __bf16 *__restrict__ w2t, __bf16 *__restrict__ w3t)
+{
+    const float *W2 = params + kOffW2, *W3 = params + kOffW3;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kC1 * kC2 + kC2 * kC3; i += gridDim.x * blockDim.x) {
+        if (i < kC1 * kC2) {
+            int n = i / kC1, k = i % kC1;
+            w2t[i] = to_bf16(W2[k * kC2 + n]);
+        } else {
+            int j = i - kC1 * kC2, n = j / kC2, k = j % kC2;
+            w3t[j] = to_bf16(W3[k * kC3 + n]);
+        }
+    }
+}
+
+// normalised coordinates of row i of cloud c
+__device__ inline void norm_point(const float *X, int64_t i, const double *cen, float s, int c, float &x, float &y,
+                                  float &z)
+{
+    x = (float)(X[3 * i] - cen[3 * c]) * s;
+    y = (float)(X[3 * i + 1] - cen[3 * c + 1]) * s;
+    z = (float)(X[3 * i + 2] - cen[3 * c + 2]) * s;
+}
+
+// Encoder forward over one tile of kT points of one cloud: per channel, the
+// tile's maximum activation and the lowest point index reaching it.
+__global__ void __launch_bounds__(kThreads) k_enc_forward(const float *__restrict__ xs, const float *__restrict__ xt,
+                                                        const int64_t *__restrict__ cr,
+                                                        const int32_t *__restrict__ toff, int nc,
+                                                        const double *__restrict__ cen,
+                                                        const float *__restrict__ scale,
+                                                        const float *__restrict__ params,
+                                                        const __bf16 *__restrict__ w2t,
+                                                        const __bf16 *__restrict__ w3t,
+                                                        float *__restrict__ pmax, int32_t *__restrict__ parg)
+{
+    __shared__ __attribute__((aligned(16))) __bf16 sW2[kC2 * kP1];   // [n][k], k < 64
+    __shared__ __attribute__((aligned(16))) __bf16 sW3[kC3 * kP2];   // [n][k], k < 128
+    __shared__ __attribute__((aligned(16))) __bf16 sX1[kT * kP1];    // [row][k]
+    __shared__ __attribute__((aligned(16))) __bf16 sX2[kT * kP2];
+    __shared__ float sMax[4][kC3];
+    __shared__ int32_t sArg[4][kC3];
+    const int tile = blockIdx.x;
+    int c = 0;
+    {   // cloud of this tile: the last c with toff[c] <= tile
+        int lo = 0, hi = nc - 1;
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (toff[mid] <= tile) lo = mid;
+            else hi = mid - 1;
+        }
+        c = lo;
+    }
+    const float *X = cloud_xyz(xs, xt, c);
+    const int64_t p0 = cr[2 * c] + (int64_t)(tile - toff[c]) * kT;
+    const int64_t pend = cr[2 * c + 1];
+    const int t = threadIdx.x, w = t >> 6, l = __lane_id();
+    // weights into LDS (16-byte chunks)
+    for (int i = t; i < kC2 * (kC1 / 8); i += kThreads) {
+        int n = i / (kC1 / 8), k8 = i % (kC1 / 8);
+        *reinterpret_cast<bf16x8 *>(&sW2[n * kP1 + 8 * k8]) = *reinterpret_cast<const bf16x8 *>(&w2t[n * kC1 + 8 * k8]);
+    }
+    for (int i = t; i < kC3 * (kC2 / 8); i += kThreads) {
+        int n = i / (kC2 / 8), k8 = i % (kC2 / 8);
+        *reinterpret_cast<bf16x8 *>(&sW3[n * kP2 + 8 * k8]) = *reinterpret_cast<const bf16x8 *>(&w3t[n * kC2 + 8 * k8]);
+    }
+    // layer 1 (float32): thread t handles row t % kT, channels 32 (t / kT) .. +31
+    {
+        const float *W1 = params + kOffW1, *b1 = params + kOffB1;
+        const int row = t % kT, c0 = 32 * (t / kT);
+        const int64_t i = p0 + row;
+        float x = 0.f, y = 0.f, z = 0.f;
+        if (i < pend) norm_point(X, i, cen, scale[c], c, x, y, z);
+        for (int j = c0; j < c0 + 32; j++) {
+            float a = __fmaf_rn(z, W1[2 * kC1 + j], __fmaf_rn(y, W1[kC1 + j], __fmaf_rn(x, W1[j], b1[j])));
+            sX1[row * kP1 + j] = to_bf16(fmaxf(a, 0.f));
+        }
+    }
+    __syncthreads();
+    // Matrix-core operands of v_mfma_f32_16x16x32_bf16 (wave of 64 lanes):
+    // lane l supplies A[l % 16][8 (l / 16) + i] and B[8 (l / 16) + i][l % 16]
+    // for i < 8, and receives C[4 (l / 16) + i][l % 16] for i < 4.
+    const int r0 = 32 * w;                 // this wave's rows
+    const int lr = l & 15, lk = 8 * (l >> 4);
+    // layer 2: rows r0..r0+31 (two 16-row tiles) x 128 columns (8 tiles), K = 64
+    {
+        const float *b2 = params + kOffB2;
+        bf16x8 a[2][2];
+        for (int m = 0; m < 2; m++)
+            for (int ks = 0; ks < 2; ks++)
+                a[m][ks] = *reinterpret_cast<const bf16x8 *>(&sX1[(r0 + 16 * m + lr) * kP1 + 32 * ks + lk]);
+        for (int nt = 0; nt < kC2 / 16; nt++) {
+            f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+            for (int ks = 0; ks < 2; ks++) {
+                bf16x8 b = *reinterpret_cast<const bf16x8 *>(&sW2[(16 * nt + lr) * kP1 + 32 * ks + lk]);
+                for (int m = 0; m < 2; m++) acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m][ks], b, acc[m], 0, 0, 0);
+            }
+            const int col = 16 * nt + lr;
+            const float bias = b2[col];
+            for (int m = 0; m < 2; m++)
+                for (int i = 0; i < 4; i++)
+                    sX2[(r0 + 16 * m + 4 * (l >> 4) + i) * kP2 + col] = to_bf16(fmaxf(acc[m][i] + bias, 0.f));
+        }
+    }
+    __syncthreads();
+    // layer 3: rows r0..r0+31 x 256 columns (16 tiles), K = 128; ReLU, then
+    // the maximum over the wave's rows (rows past the cloud's end excluded)
+    {
+        const float *b3 = params + kOffB3;
+        bf16x8 a[2][4];
+        for (int m = 0; m < 2; m++)
+            for (int ks = 0; ks < 4; ks++)
+                a[m][ks] = *reinterpret_cast<const bf16x8 *>(&sX2[(r0 + 16 * m + lr) * kP2 + 32 * ks + lk]);
+        for (int nt = 0; nt < kC3 / 16; nt++) {
+            f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
+            for (int ks = 0; ks < 4; ks++) {
+                bf16x8 b = *reinterpret_cast<const bf16x8 *>(&sW3[(16 * nt + lr) * kP2 + 32 * ks + lk]);
+                for (int m = 0; m < 2; m++) acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m][ks], b, acc[m], 0, 0, 0);
+            }
+            const int col = 16 * nt + lr;
+            const float bias = b3[col];
+            float best = -INFINITY;
+            int32_t barg = 0x7fffffff;
+            for (int m = 0; m < 2; m++)
+                for (int i = 0; i < 4; i++) {
+                    const int row = r0 + 16 * m + 4 * (l >> 4) + i;
+                    if (p0 + row >= pend) continue;
+                    float v = fmaxf(acc[m][i] + bias, 0.f);
+                    if (v > best) { best = v; barg = row; }   // rows ascend: first maximum kept
+                }
+            for (int o = 16; o <= 32; o <<= 1) {
+                float ob = __shfl_xor(best, o);
+                int32_t oa = __shfl_xor(barg, o);
+                if (ob > best || (ob == best && oa < barg)) { best = ob; barg = oa; }
+            }
+            if (l < 16) {
+                sMax[w][col] = best;
+                sArg[w][col] = barg;
+            }
+        }
+    }
+    __syncthreads();
+    {   // across the 4 waves (rows ascend with the wave index)
+        const int col = t;
+        float best = sMax[0][col];
+        int32_t barg = sArg[0][col];
+        for (int x = 1; x < 4; x++)
+            if (sMax[x][col] > best) { best = sMax[x][col]; barg = sArg[x][col]; }
+        pmax[(int64_t)tile * kC3 + col] = best;
+        parg[(int64_t)tile * kC3 + col] = barg == 0x7fffffff ? -1 : (int32_t)(p0 - cr[2 * c]) + barg;
+    }
+}
+
+// per cloud: maximum over its tiles (ties: the lower point index)
+__global__ void k_enc_pool(const float *__restrict__ pmax, const int32_t *__restrict__ parg,
+                           const int32_t *__restrict__ toff, int nc, float *__restrict__ feat,
+                           int32_t *__restrict__ arg)
+{
+    const int c = blockIdx.x, col = threadIdx.x;
+    if (c >= nc) return;
+    float best = 0.f;     // an empty cloud has the zero feature
+    int32_t barg = -1;
+    for (int tl = toff[c]; tl < toff[c + 1]; tl++) {
+        float v = pmax[(int64_t)tl * kC3 + col];
+        int32_t a = parg[(int64_t)tl * kC3 + col];
+        if (a >= 0 && (barg < 0 || v > best)) { best = v; barg = a; }
+    }
+    feat[(int64_t)c * kC3 + col] = best;
+    arg[(int64_t)c * kC3 + col] = barg;
+}
+
+__device__ inline void quat_rotation(double w, double x, double y, double z, double R[9])
+{
+    R[0] = w * w + x * x - y * y - z * z;
+    R[1] = 2 * (x * y - w * z);
+    R[2] = 2 * (x * z + w * y);
+    R[3] = 2 * (x * y + w * z);
+    R[4] = w * w - x * x + y * y - z * z;
+    R[5] = 2 * (y * z - w * x);
+    R[6] = 2 * (x * z - w * y);
+    R[7] = 2 * (y * z + w * x);
+    R[8] = w * w - x * x - y * y + z * z;
+}
+
+// T = [R, c_tgt - R c_src]
+__device__ inline void pose_about_centroids(const double R[9], const double *cs, const double *ct, double *T)
+{
+    for (int r = 0; r < 3; r++) {
+        for (int cc = 0; cc < 3; cc++) T[r * 4 + cc] = R[r * 3 + cc];
+        T[r * 4 + 3] = ct[r] - (R[r * 3] * cs[0] + R[r * 3 + 1] * cs[1] + R[r * 3 + 2] * cs[2]);
+    }
+    T[12] = T[13] = T[14] = 0.0;
+    T[15] = 1.0;
+}
+
+// Head per pair (clouds 2p = source, 2p + 1 = target): h = ReLU(W4^T f + b4),
+// q = W5^T h + b5, R = rotation of q / |q|, T0 = [R, c_tgt - R c_src].
+__global__ void __launch_bounds__(kH) k_head_forward(const float *__restrict__ feat, const double *__restrict__ cen,
+                                                   const float *__restrict__ params, int np,
+                                                   float *__restrict__ zbuf, float *__restrict__ qbuf,
+                                                   double *__restrict__ out_T)
+{
+    __shared__ float f[2 * kC3];
+    __shared__ float h[kH];
+    const int p = blockIdx.x, j = threadIdx.x;
+    if (p >= np) return;
+    f[j] = feat[(int64_t)(2 * p) * kC3 + j];
+    f[kC3 + j] = feat[(int64_t)(2 * p + 1) * kC3 + j];
+    __syncthreads();
+    const float *W4 = params + kOffW4, *b4 = params + kOffB4, *W5 = params + kOffW5, *b5 = params + kOffB5;
+    float a = b4[j];
+    for (int i = 0; i < 2 * kC3; i++) a = __fmaf_rn(f[i], W4[i * kH + j], a);
+    h[j] = fmaxf(a, 0.f);
+    zbuf[(int64_t)p * kH + j] = a;
+    __syncthreads();
+    if (j == 0) {
+        double q[4];
+        for (int o = 0; o < 4; o++) {
+            float s = b5[o];
+            for (int i = 0; i < kH; i++) s = __fmaf_rn(h[i], W5[i * 4 + o], s);
+            q[o] = s;
+            qbuf[(int64_t)p * 4 + o] = s;
+        }
+        double nq = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+        if (!(nq > 0.0)) { q[0] = 1.0; q[1] = q[2] = q[3] = 0.0; nq = 1.0; }
+        double R[9];
+        quat_rotation(q[0] / nq, q[1] / nq, q[2] / nq, q[3] / nq, R);
+        pose_about_centroids(R, cen + 3 * (2 * p), cen + 3 * (2 * p + 1), out_T + 16 * (int64_t)p);
+    }
+}
+
+// Per pair: weighted loss w_p |R(q / |q|) - R_label|_F^2 and the backward of
+// the head: dq (4), dz4 (256, through the ReLU) and df (512, source then
+// target features).
+__global__ void __launch_bounds__(kH) k_head_backward(const float *__restrict__ params, int np,
+                                                    const float *__restrict__ zbuf, const float *__restrict__ qbuf,
+                                                    const double *__restrict__ label_T,
+                                                    const float *__restrict__ pair_w, float *__restrict__ loss,
+                                                    float *__restrict__ dq_out, float *__restrict__ dz_out,
+                                                    float *__restrict__ df_out)
+{
+    __shared__ float dq[4];
+    __shared__ float dz[kH];
+    const int p = blockIdx.x, j = threadIdx.x;
+    if (p >= np) return;
+    if (j == 0) {
+        const double wp = pair_w ? (double)pair_w[p] : 1.0;
+        double q[4];
+        for (int o = 0; o < 4; o++) q[o] = qbuf[(int64_t)p * 4 + o];
+        double nq = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+        double g[4] = {0.0, 0.0, 0.0, 0.0}, L = 0.0;
+        if (nq > 0.0 && wp != 0.0) {
+            double u[4] = {q[0] / nq, q[1] / nq, q[2] / nq, q[3] / nq};
+            double R[9], G[9];
+            quat_rotation(u[0], u[1], u[2], u[3], R);
+            const double *Tl = label_T + 16 * (int64_t)p;
+            for (int r = 0; r < 3; r++)
+                for (int cc = 0; cc < 3; cc++) {
+                    double e = R[r * 3 + cc] - Tl[r * 4 + cc];
+                    L += e * e;
+                    G[r * 3 + cc] = 2.0 * e;
+                }
+            // partial derivatives of R in w, x, y, z (row-major 3x3 each)
+            const double w = u[0], x = u[1], y = u[2], z = u[3];
+            const double D[4][9] = {{2 * w, -2 * z, 2 * y, 2 * z, 2 * w, -2 * x, -2 * y, 2 * x, 2 * w},
+                                    {2 * x, 2 * y, 2 * z, 2 * y, -2 * x, -2 * w, 2 * z, 2 * w, -2 * x},
+                                    {-2 * y, 2 * x, 2 * w, 2 * x, 2 * y, 2 * z, -2 * w, 2 * z, -2 * y},
+                                    {-2 * z, -2 * w, 2 * x, 2 * w, -2 * z, 2 * y, 2 * x, 2 * y, 2 * z}};
+            double gu[4], dot = 0.0;
+            for (int k = 0; k < 4; k++) {
+                gu[k] = 0.0;
+                for (int e = 0; e < 9; e++) gu[k] += G[e] * D[k][e];
+                dot += gu[k] * u[k];
+            }
+            // through the normalisation u = q / |q|
+            for (int k = 0; k < 4; k++) g[k] = wp * (gu[k] - u[k] * dot) / nq;
+            L *= wp;
+        }
+        for (int o = 0; o < 4; o++) {
+            dq[o] = (float)g[o];
+            dq_out[(int64_t)p * 4 + o] = (float)g[o];
+        }
+        loss[p] = (float)L;
+    }
+    __syncthreads();
+    const float *W4 = params + kOffW4, *W5 = params + kOffW5;
+    {
+        float a = 0.f;
+        for (int o = 0; o < 4; o++) a = __fmaf_rn(W5[j * 4 + o], dq[o], a);
+        dz[j] = zbuf[(int64_t)p * kH + j] > 0.f ? a : 0.f;
+        dz_out[(int64_t)p * kH + j] = dz[j];
+    }
+    __syncthreads();
+    for (int i = j; i < 2 * kC3; i += kH) {
+        float a = 0.f;
+        for (int k = 0; k < kH; k++) a = __fmaf_rn(W4[i * kH + k], dz[k], a);
+        df_out[(int64_t)(2 * p + i / kC3) * kC3 + (i % kC3)] = a;
+    }
+}
+
+// Head weight gradients, one thread per weight, summed over pairs in order:
+// W4 and b4 from [features, 1] x dz4, W5 and b5 from [h, 1] x dq.
+__global__ void k_head_grads(const float *__restrict__ feat, const float *__restrict__ zbuf,
+                             const float *__restrict__ dq, const float *__restrict__ dz, int np,
+                             float *__restrict__ grad)
+{
+    const int nW4 = 2 * kC3 * kH, nW5 = kH * 4;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nW4 + kH + nW5 + 4; e += gridDim.x * blockDim.x) {
+        float a = 0.f;
+        if (e < nW4) {
+            int i = e / kH, j = e % kH;
+            for (int p = 0; p < np; p++)
+                a = __fmaf_rn(feat[(int64_t)(2 * p + i / kC3) * kC3 + (i % kC3)], dz[(int64_t)p * kH + j], a);
+            grad[kOffW4 + e] = a;
+        } else if (e < nW4 + kH) {
+            int j = e - nW4;
+            for (int p = 0; p < np; p++) a += dz[(int64_t)p * kH + j];
+            grad[kOffB4 + j] = a;
+        } else if (e < nW4 + kH + nW5) {
+            int k = e - nW4 - kH, i = k / 4, o = k % 4;
+            for (int p = 0; p < np; p++)
+                a = __fmaf_rn(fmaxf(zbuf[(int64_t)p * kH + i], 0.f), dq[(int64_t)p * 4 + o], a);
+            grad[kOffW5 + k] = a;
+        } else {
+            int o = e - nW4 - kH - nW5;
+            for (int p = 0; p < np; p++) a += dq[(int64_t)p * 4 + o];
+            grad[kOffB5 + o] = a;
+        }
+    }
+}
+
+// Per (cloud c, channel ch) = row e of E = nc * 256: the channel's arg-max
+// point, recomputed (bfloat16 inputs and weights as in the forward), and
+// the gradient flowing into it.  Writes, k-major with stride E:
+//   U1 (4 rows): x, y, z, 1          V1 (64): dz1
+//   U2 (65 rows): a1, 1              V2 (128): dz2
+//   A2 (128): a2                     G3 (1): dz3 at channel ch
+// so that dW1|b1 = U1 V1^T, dW2|b2 = U2 V2^T and dW3[k][ch] = sum over
+// clouds of A2[k] G3.  Rows without gradient are all zero.
+__global__ void __launch_bounds__(kC3) k_enc_backward(const float *__restrict__ xs, const float *__restrict__ xt,
+                                                    const int64_t *__restrict__ cr, int nc,
+                                                    const double *__restrict__ cen, const float *__restrict__ scale,
+                                                    const float *__restrict__ params,
+                                                    const __bf16 *__restrict__ w2t, const __bf16 *__restrict__ w3t,
+                                                    const float *__restrict__ feat, const int32_t *__restrict__ arg,
+                                                    const float *__restrict__ df, float *__restrict__ U1,
+                                                    float *__restrict__ V1, float *__restrict__ U2,
+                                                    float *__restrict__ V2, float *__restrict__ A2,
+                                                    float *__restrict__ G3)
+{
+    const int c = blockIdx.x, ch = threadIdx.x;
+    if (c >= nc) return;
+    const int64_t E = (int64_t)nc * kC3;
+    const int64_t e = (int64_t)c * kC3 + ch;
+    const int32_t r = arg[e];
+    const float g = (r >= 0 && feat[e] > 0.f) ? df[e] : 0.f;
+    G3[e] = g;
+    if (g == 0.f) {
+        for (int d = 0; d < 4; d++) U1[d * E + e] = 0.f;
+        for (int j = 0; j < kC1; j++) V1[j * E + e] = 0.f;
+        for (int j = 0; j <= kC1; j++) U2[j * E + e] = 0.f;
+        for (int k = 0; k < kC2; k++) V2[k * E + e] = A2[k * E + e] = 0.f;
+        return;
+    }
+    const float *X = cloud_xyz(xs, xt, c);
+    float x, y, z;
+    norm_point(X, cr[2 * c] + r, cen, scale[c], c, x, y, z);
+    const float *W1 = params + kOffW1, *b1 = params + kOffB1, *b2 = params + kOffB2;
+    float a1[kC1], d1[kC1];
+    for (int j = 0; j < kC1; j++) {
+        float a = __fmaf_rn(z, W1[2 * kC1 + j], __fmaf_rn(y, W1[kC1 + j], __fmaf_rn(x, W1[j], b1[j])));
+        a1[j] = (float)to_bf16(fmaxf(a, 0.f));
+        d1[j] = 0.f;
+    }
+    const __bf16 *w3c = w3t + (int64_t)ch * kC2;          // W3[k][ch], k contiguous
+    for (int k = 0; k < kC2; k++) {
+        const __bf16 *w2c = w2t + (int64_t)k * kC1;       // W2[j][k], j contiguous
+        float a = 0.f;
+        for (int j = 0; j < kC1; j++) a = __fmaf_rn(a1[j], (float)w2c[j], a);
+        const float a2 = (float)to_bf16(fmaxf(a + b2[k], 0.f));
+        const float dz2 = a2 > 0.f ? g * (float)w3c[k] : 0.f;
+        A2[k * E + e] = a2;
+        V2[k * E + e] = dz2;
+        for (int j = 0; j < kC1; j++) d1[j] = __fmaf_rn((float)w2c[j], dz2, d1[j]);
+    }
+    U1[0 * E + e] = x;
+    U1[1 * E + e] = y;
+    U1[2 * E + e] = z;
+    U1[3 * E + e] = 1.f;
+    for (int j = 0; j < kC1; j++) {
+        V1[j * E + e] = a1[j] > 0.f ? d1[j] : 0.f;
+        U2[j * E + e] = a1[j];
+    }
+    U2[kC1 * E + e] = 1.f;
+}
+
+// Partial sums of out[a][b] = sum over rows e of U[a][e] V[b][e], one chunk
+// of kChunk rows per workgroup: part[chunk][a * NB + b].
+template <int NA, int NB>
+__global__ void __launch_bounds__(256) k_outer_partial(const float *__restrict__ U, const float *__restrict__ V,
+                                                     int64_t E, float *__restrict__ part)
+{
+    constexpr int kOut = (NA * NB + 255) / 256;
+    constexpr int kS = kChunk + 1;              // padded row stride (bank spread)
+    __shared__ float sU[NA * kS];
+    __shared__ float sV[NB * kS];
+    const int64_t e0 = (int64_t)blockIdx.x * kChunk;
+    const int t = threadIdx.x;
+    for (int i = t; i < NA * kChunk; i += 256) {
+        int a = i / kChunk, r = i % kChunk;
+        sU[a * kS + r] = e0 + r < E ? U[a * E + e0 + r] : 0.f;
+    }
+    for (int i = t; i < NB * kChunk; i += 256) {
+        int b = i / kChunk, r = i % kChunk;
+        sV[b * kS + r] = e0 + r < E ? V[b * E + e0 + r] : 0.f;
+    }
+    __syncthreads();
+    float acc[kOut];
+    for (int o = 0; o < kOut; o++) acc[o] = 0.f;
+    for (int r = 0; r < kChunk; r++)
+        for (int o = 0; o < kOut; o++) {
+            const int idx = t + 256 * o;
+            if (idx < NA * NB) acc[o] = __fmaf_rn(sU[(idx / NB) * kS + r], sV[(idx % NB) * kS + r], acc[o]);
+        }
+    for (int o = 0; o < kOut; o++) {
+        const int idx = t + 256 * o;
+        if (idx < NA * NB) part[(int64_t)blockIdx.x * (NA * NB) + idx] = acc[o];
+    }
+}
+
+// sum of the chunk partials, in chunk order
+__global__ void k_outer_reduce(const float *__restrict__ part, int nchunk, int nout, float *__restrict__ out)
+{
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nout; i += gridDim.x * blockDim.x) {
+        float a = 0.f;
+        for (int ch = 0; ch < nchunk; ch++) a += part[(int64_t)ch * nout + i];
+        out[i] = a;
+    }
+}
+
+// third-layer gradients, one thread per weight, summed over clouds in order
+__global__ void k_w3_grads(const float *__restrict__ A2, const float *__restrict__ G3, int nc,
+                           float *__restrict__ grad)
+{
+    const int64_t E = (int64_t)nc * kC3;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kC2 * kC3 + kC3; i += gridDim.x * blockDim.x) {
+        float a = 0.f;
+        if (i < kC2 * kC3) {
+            const int k = i / kC3, ch = i % kC3;
+            for (int c = 0; c < nc; c++)
+                a = __fmaf_rn(A2[k * E + (int64_t)c * kC3 + ch], G3[(int64_t)c * kC3 + ch], a);
+            grad[kOffW3 + i] = a;
+        } else {
+            const int ch = i - kC2 * kC3;
+            for (int c = 0; c < nc; c++) a += G3[(int64_t)c * kC3 + ch];
+            grad[kOffB3 + ch] = a;
+        }
+    }
+}
+
+// Adam on every parameter with the gradient of the weighted mean loss
+// (the summed gradient divided by the sum of the pair weights).
+__global__ void k_adam(float *__restrict__ params, float *__restrict__ m, float *__restrict__ v,
+                       const float *__restrict__ grad, const float *__restrict__ pair_w, int np, int step, float lr)
+{
+    float wsum = 0.f;
+    for (int p = 0; p < np; p++) wsum += pair_w ? pair_w[p] : 1.f;
+    if (!(wsum > 0.f)) return;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float c1 = 1.f - powf(b1, (float)step), c2 = 1.f - powf(b2, (float)step);
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kParams; i += gridDim.x * blockDim.x) {
+        float g = grad[i] / wsum;
+        float mi = b1 * m[i] + (1.f - b1) * g;
+        float vi = b2 * v[i] + (1.f - b2) * g * g;
+        m[i] = mi;
+        v[i] = vi;
+        params[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    }
+}
+
+// Multi-start poses for the listed pairs: start j = 0 is the identity
+// rotation, start j >= 1 the rotation by 60 degrees about Fibonacci-sphere
+// axis j - 1 of 7 (height 1 - (2i + 1) / 7, azimuth i times the golden
+// angle), each about the source centroid onto the target centroid.
+__global__ void k_start_poses(const double *__restrict__ cen, const int32_t *__restrict__ sel, int nsel,
+                              double *__restrict__ out_T)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nsel * kStarts) return;
+    const int p = sel[i / kStarts], j = i % kStarts;
+    double R[9] = {1, 0, 0, 0, 1, 0, 0, 0, 1};
+    if (j > 0) {
+        const int a = j - 1;
+        const double golden = M_PI * (3.0 - sqrt(5.0));
+        const double zc = 1.0 - (2.0 * a + 1.0) / (kStarts - 1);
+        const double rc = sqrt(fmax(0.0, 1.0 - zc * zc));
+        const double ax[3] = {rc * cos(a * golden), rc * sin(a * golden), zc};
+        const double th = M_PI / 3.0, s = sin(th), c1 = 1.0 - cos(th);
+        // Rodrigues: I + sin(th) K + (1 - cos(th)) K^2, K the cross-product matrix
+        const double K[9] = {0, -ax[2], ax[1], ax[2], 0, -ax[0], -ax[1], ax[0], 0};
+        for (int r = 0; r < 3; r++)
+            for (int cc = 0; cc < 3; cc++) {
+                double k2 = 0.0;
+                for (int m = 0; m < 3; m++) k2 += K[r * 3 + m] * K[m * 3 + cc];
+                R[r * 3 + cc] = (r == cc ? 1.0 : 0.0) + s * K[r * 3 + cc] + c1 * k2;
+            }
+    }
+    pose_about_centroids(R, cen + 3 * (2 * p), cen + 3 * (2 * p + 1), out_T + 16 * (int64_t)i);
+}
+
+// Best start per listed pair: the first start, replaced by a later one that
+// has inliers and either the best so far has none or its RMS is lower.
+__global__ void k_select_start(const double *__restrict__ T_all, const pc_icp_stats *__restrict__ st_all,
+                               const int32_t *__restrict__ sel, int nsel, double *__restrict__ out_T,
+                               pc_icp_stats *__restrict__ out_stats, int32_t *__restrict__ out_start)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nsel) return;
+    const pc_icp_stats *s = st_all + (int64_t)i * kStarts;
+    int best = 0;
+    for (int j = 1; j < kStarts; j++)
+        if (s[j].inliers > 0 && (s[best].inliers == 0 || s[j].rms < s[best].rms)) best = j;
+    const int p = sel[i];
+    for (int k = 0; k < 16; k++) out_T[16 * (int64_t)p + k] = T_all[16 * ((int64_t)i * kStarts + best) + k];
+    if (out_stats) out_stats[p] = s[best];
+    if (out_start) out_start[p] = best;
+}
+
+// rows of 3 floats: segment q copies seg[3q + 2] rows from row seg[3q + 1]
+// of `in` to row seg[3q] of `out`
+__global__ void k_gather_rows3(const float *__restrict__ in, float *__restrict__ out,
+                               const int64_t *__restrict__ seg, int nseg)
+{
+    for (int q = blockIdx.x; q < nseg; q += gridDim.x) {
+        const int64_t d = 3 * seg[3 * q], s = 3 * seg[3 * q + 1], n = 3 * seg[3 * q + 2];
+        for (int64_t k = threadIdx.x; k < n; k += blockDim.x) out[d + k] = in[s + k];
+    }
+}
+
+__global__ void k_fill_i32(int32_t *__restrict__ p, int n, int32_t v)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+}  // namespace
+
+int pose_net_tiles(int64_t n_cloud) { return (int)((n_cloud + kT - 1) / kT); }
+
+void pose_net_carve(Carver &c, int np, int ntile, bool train, PoseNetStore &s)
+{
+    const int np1 = np > 0 ? np : 1, nc = 2 * np1, nt1 = ntile > 0 ? ntile : 1;
+    const int64_t E = (int64_t)nc * kC3;
+    s = PoseNetStore{};
+    s.np = np1;
+    s.nc = nc;
+    s.ntile = ntile;
+    s.cr = c.take<int64_t>((size_t)2 * nc);
+    s.toff = c.take<int32_t>(nc + 1);
+    s.cen = c.take<double>((size_t)nc * 3);
+    s.scale = c.take<float>(nc);
+    s.w2t = c.take<__bf16>(kC1 * kC2);
+    s.w3t = c.take<__bf16>(kC2 * kC3);
+    s.pmax = c.take<float>((size_t)nt1 * kC3);
+    s.parg = c.take<int32_t>((size_t)nt1 * kC3);
+    s.feat = c.take<float>((size_t)nc * kC3);
+    s.arg = c.take<int32_t>((size_t)nc * kC3);
+    s.z4 = c.take<float>((size_t)np1 * kH);
+    s.q = c.take<float>((size_t)np1 * 4);
+    s.T = c.take<double>((size_t)np1 * 16);
+    if (!train) return;
+    s.nchunk = (int)((E + kChunk - 1) / kChunk);
+    s.grad = c.take<float>(kParams);
+    s.loss = c.take<float>(np1);
+    s.dq = c.take<float>((size_t)np1 * 4);
+    s.dz = c.take<float>((size_t)np1 * kH);
+    s.df = c.take<float>((size_t)nc * kC3);
+    s.U1 = c.take<float>((size_t)4 * E);
+    s.V1 = c.take<float>((size_t)kC1 * E);
+    s.U2 = c.take<float>((size_t)(kC1 + 1) * E);
+    s.V2 = c.take<float>((size_t)kC2 * E);
+    s.A2 = c.take<float>((size_t)kC2 * E);
+    s.G3 = c.take<float>((size_t)E);
+    s.part = c.take<float>((size_t)s.nchunk * (kC1 + 1) * kC2);
+}
+
+hipError_t pose_net_stats(PoseNetStore &s, const float *xs, const float *xt, hipStream_t st)
+{
+    k_norm_stats<<<s.nc, 256, 0, st>>>(xs, xt, s.cr, s.nc, s.cen, s.scale);
+    return hipGetLastError();
+}
+
+hipError_t pose_net_forward(PoseNetStore &s, const float *params, const float *xs, const float *xt, double *out_T,
+                            hipStream_t st)
+{
+    k_norm_stats<<<s.nc, 256, 0, st>>>(xs, xt, s.cr, s.nc, s.cen, s.scale);
+    k_weights_bf16<<<64, 256, 0, st>>>(params, s.w2t, s.w3t);
+    if (s.ntile > 0)
+        k_enc_forward<<<s.ntile, kThreads, 0, st>>>(xs, xt, s.cr, s.toff, s.nc, s.cen, s.scale, params, s.w2t,
+                                                    s.w3t, s.pmax, s.parg);
+    k_enc_pool<<<s.nc, kC3, 0, st>>>(s.pmax, s.parg, s.toff, s.nc, s.feat, s.arg);
+    k_head_forward<<<s.np, kH, 0, st>>>(s.feat, s.cen, params, s.np, s.z4, s.q, out_T ? out_T : s.T);
+    return hipGetLastError();
+}
+
+hipError_t pose_net_train(PoseNetStore &s, float *params, float *adam_m, float *adam_v, int step, float lr,
+                          const float *xs, const float *xt, const double *label_T, const float *pair_w,
+                          float *out_loss, hipStream_t st)
+{
+    hipError_t e = pose_net_forward(s, params, xs, xt, nullptr, st);
+    if (e != hipSuccess) return e;
+    const int64_t E = (int64_t)s.nc * kC3;
+    k_head_backward<<<s.np, kH, 0, st>>>(params, s.np, s.z4, s.q, label_T, pair_w, out_loss ? out_loss : s.loss,
+                                        s.dq, s.dz, s.df);
+    k_head_grads<<<512, 256, 0, st>>>(s.feat, s.z4, s.dq, s.dz, s.np, s.grad);
+    k_enc_backward<<<s.nc, kC3, 0, st>>>(xs, xt, s.cr, s.nc, s.cen, s.scale, params, s.w2t, s.w3t, s.feat, s.arg,
+                                         s.df, s.U1, s.V1, s.U2, s.V2, s.A2, s.G3);
+    k_w3_grads<<<128, 256, 0, st>>>(s.A2, s.G3, s.nc, s.grad);
+    k_outer_partial<4, kC1><<<s.nchunk, 256, 0, st>>>(s.U1, s.V1, E, s.part);
+    k_outer_reduce<<<1, 256, 0, st>>>(s.part, s.nchunk, 4 * kC1, s.grad + kOffW1);
+    k_outer_partial<kC1 + 1, kC2><<<s.nchunk, 256, 0, st>>>(s.U2, s.V2, E, s.part);
+    k_outer_reduce<<<(((kC1 + 1) * kC2) + 255) / 256, 256, 0, st>>>(s.part, s.nchunk, (kC1 + 1) * kC2,
+                                                                      s.grad + kOffW2);
+    if (lr > 0.f) k_adam<<<256, 256, 0, st>>>(params, adam_m, adam_v, s.grad, pair_w, s.np, step, lr);
+    return hipGetLastError();
+}
+
+hipError_t multi_start_poses(const double *cen, const int32_t *sel, int nsel, double *out_T, hipStream_t st)
+{
+    const int n = nsel * kStarts;
+    if (n > 0) k_start_poses<<<(n + 63) / 64, 64, 0, st>>>(cen, sel, nsel, out_T);
+    return hipGetLastError();
+}
+
+hipError_t multi_start_select(const double *T_all, const pc_icp_stats *st_all, const int32_t *sel, int nsel,
+                              double *out_T, pc_icp_stats *out_stats, int32_t *out_start, hipStream_t st)
+{
+    if (nsel > 0)
+        k_select_start<<<(nsel + 63) / 64, 64, 0, st>>>(T_all, st_all, sel, nsel, out_T, out_stats, out_start);
+    return hipGetLastError();
+}
+
+hipError_t gather_rows3(const float *in, float *out, const int64_t *seg, int nseg, hipStream_t st)
+{
+    if (nseg > 0) k_gather_rows3<<<nseg < 4096 ? nseg : 4096, 256, 0, st>>>(in, out, seg, nseg);
+    return hipGetLastError();
+}
+
+hipError_t fill_i32(int32_t *p, int n, int32_t v, hipStream_t st)
+{
+    if (n > 0) k_fill_i32<<<(n + 255) / 256, 256, 0, st>>>(p, n, v);
+    return hipGetLastError();
+}
+
+}  // namespace pcg

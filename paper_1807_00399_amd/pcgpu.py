@@ -30,7 +30,10 @@ EXPORTS = (
     "icp_point_to_plane_batched_workspace_size", "icp_point_to_plane_batched",
     "pc_copy_probe", "icp_history", "pc_set_kernel_timer", "pc_kernel_timer_count",
     "pc_set_tuning", "pc_get_tuning",
+    "pose_net_param_count", "pose_net_workspace_size", "pose_net_predict", "pose_net_train_step",
+    "icp_learned_batched_workspace_size", "icp_learned_batched",
 )
+PC_INIT_LEARNED, PC_INIT_MULTI_START, PC_INIT_LEARNED_ONLY = 0, 1, 2
 
 
 class Tuning(ctypes.Structure):
@@ -96,6 +99,18 @@ def _load() -> ctypes.CDLL:
     lib.pc_set_tuning.restype = ctypes.c_int
     lib.pc_get_tuning.argtypes = [ctypes.POINTER(Tuning)]
     lib.pc_get_tuning.restype = None
+    lib.pose_net_param_count.argtypes = []
+    lib.pose_net_param_count.restype = ctypes.c_int
+    lib.pose_net_workspace_size.argtypes = [i32, vp, vp]
+    lib.pose_net_workspace_size.restype = sz
+    lib.pose_net_predict.argtypes = [vp, i32, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.pose_net_predict.restype = ctypes.c_int
+    lib.pose_net_train_step.argtypes = [vp, vp, vp, i32, f32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
+    lib.pose_net_train_step.restype = ctypes.c_int
+    lib.icp_learned_batched_workspace_size.argtypes = [i32, vp, vp, i32]
+    lib.icp_learned_batched_workspace_size.restype = sz
+    lib.icp_learned_batched.argtypes = [i32, vp, i32, vp, vp, vp, vp, vp, f32, i32, f64, f32, vp, vp, vp, vp, sz, vp]
+    lib.icp_learned_batched.restype = ctypes.c_int
     return lib
 
 
@@ -417,3 +432,99 @@ def get_tuning() -> dict:
 def copy_probe(dst: torch.Tensor, src: torch.Tensor, stream=None):
     _check(lib.pc_copy_probe(dst.data_ptr(), src.data_ptr(), src.numel() * src.element_size(), _stream(stream)),
            "pc_copy_probe")
+
+
+# ---------------------------------------------------------------------------
+# Learned pose initialiser and multi-start ICP
+# ---------------------------------------------------------------------------
+def _pair_offsets(src, src_off, tgt, tgt_off):
+    so, to = _offsets(src_off, "src_off"), _offsets(tgt_off, "tgt_off")
+    m = so.shape[0] - 1
+    if m < 1 or to.shape[0] != m + 1 or so[-1] != src.shape[0] or to[-1] != tgt.shape[0]:
+        raise ValueError("offsets must have m + 1 entries ending at the array lengths")
+    return so, to, m
+
+
+def _params(params: torch.Tensor, what: str) -> torch.Tensor:
+    n = lib.pose_net_param_count()
+    if params.dtype != torch.float32 or params.numel() != n or not params.is_contiguous() or not params.is_cuda:
+        raise ValueError(f"{what} must be a contiguous float32 CUDA tensor of {n} values")
+    return params
+
+
+def pose_net_param_count() -> int:
+    return lib.pose_net_param_count()
+
+
+def pose_net_predict(params: torch.Tensor, src: torch.Tensor, src_off, tgt: torch.Tensor, tgt_off, stream=None,
+                     workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """Initial pose (m, 4, 4) float64 of every packed pair."""
+    params = _params(params, "params")
+    src, tgt = _pts(src, "src"), _pts(tgt, "tgt")
+    so, to, m = _pair_offsets(src, src_off, tgt, tgt_off)
+    T = torch.empty((m, 4, 4), dtype=torch.float64, device=src.device)
+    need = lib.pose_net_workspace_size(m, so.ctypes.data, to.ctypes.data)
+    ws = workspace if workspace is not None else _ws.get(need, src.device)
+    _check(lib.pose_net_predict(params.data_ptr(), m, src.data_ptr(), so.ctypes.data, tgt.data_ptr(), to.ctypes.data,
+                                T.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream)), "pose_net_predict")
+    return T
+
+
+def pose_net_train_step(params: torch.Tensor, adam_m, adam_v, step: int, lr: float, src: torch.Tensor, src_off,
+                        tgt: torch.Tensor, tgt_off, label_T: torch.Tensor, pair_weight=None, want_grad=False,
+                        stream=None, workspace: torch.Tensor | None = None):
+    """One training step (Adam when lr > 0).  Returns (per-pair loss tensor,
+    summed gradient tensor or None)."""
+    params = _params(params, "params")
+    if lr > 0:
+        adam_m, adam_v = _params(adam_m, "adam_m"), _params(adam_v, "adam_v")
+    src, tgt = _pts(src, "src"), _pts(tgt, "tgt")
+    so, to, m = _pair_offsets(src, src_off, tgt, tgt_off)
+    dev = src.device
+    lab = torch.as_tensor(label_T, dtype=torch.float64).reshape(m, 4, 4).to(dev).contiguous()
+    w = None
+    if pair_weight is not None:
+        w = torch.as_tensor(pair_weight, dtype=torch.float32).reshape(m).to(dev).contiguous()
+    loss = torch.empty(m, dtype=torch.float32, device=dev)
+    grad = torch.empty(lib.pose_net_param_count(), dtype=torch.float32, device=dev) if want_grad else None
+    need = lib.pose_net_workspace_size(m, so.ctypes.data, to.ctypes.data)
+    ws = workspace if workspace is not None else _ws.get(need, dev)
+    _check(lib.pose_net_train_step(params.data_ptr(), _ptr(adam_m) if lr > 0 else None,
+                                   _ptr(adam_v) if lr > 0 else None, int(step), float(lr), m, src.data_ptr(),
+                                   so.ctypes.data, tgt.data_ptr(), to.ctypes.data, lab.data_ptr(), _ptr(w),
+                                   loss.data_ptr(), _ptr(grad), ws.data_ptr(), ws.numel(), _stream(stream)),
+           "pose_net_train_step")
+    return loss, grad
+
+
+def icp_learned_batched(mode: int, params, src: torch.Tensor, src_off, tgt: torch.Tensor, tgt_normals: torch.Tensor,
+                        tgt_off, max_corr_dist: float, max_iters: int, conv_tol: float = 0.0,
+                        accept_rms: float = 0.0, stream=None, workspace: torch.Tensor | None = None,
+                        read_stats: bool = True):
+    """Registration from the learned start with multi-start fallback
+    (PC_INIT_LEARNED), multi-start only or learned only.  Returns (T (m,4,4),
+    stats (list of dicts, or the raw device tensor), start index per pair
+    (int32 device tensor; -1 = learned))."""
+    if mode != PC_INIT_MULTI_START:
+        params = _params(params, "params")
+    src, tgt = _pts(src, "src"), _pts(tgt, "tgt")
+    tgt_normals = _pts(tgt_normals, "tgt_normals")
+    if tgt_normals.shape[0] != tgt.shape[0]:
+        raise ValueError("tgt_normals must match tgt")
+    so, to, m = _pair_offsets(src, src_off, tgt, tgt_off)
+    dev = src.device
+    T = torch.empty((m, 4, 4), dtype=torch.float64, device=dev)
+    stats = torch.zeros(24 * m, dtype=torch.uint8, device=dev)
+    start = torch.empty(m, dtype=torch.int32, device=dev)
+    need = lib.icp_learned_batched_workspace_size(m, so.ctypes.data, to.ctypes.data, int(max_iters))
+    if need == 0:
+        raise ValueError("icp_learned_batched: sizes out of range")
+    ws = workspace if workspace is not None else _ws.get(need, dev)
+    _check(lib.icp_learned_batched(int(mode), _ptr(params) if mode != PC_INIT_MULTI_START else None, m,
+                                   src.data_ptr(), so.ctypes.data, tgt.data_ptr(), tgt_normals.data_ptr(),
+                                   to.ctypes.data, float(max_corr_dist), int(max_iters), float(conv_tol),
+                                   float(accept_rms), T.data_ptr(), stats.data_ptr(), start.data_ptr(),
+                                   ws.data_ptr(), ws.numel(), _stream(stream)), "icp_learned_batched")
+    if not read_stats:
+        return T, stats, start
+    return T, decode_stats_batched(stats), start

@@ -226,3 +226,52 @@ def test_radius_normals_reject_bad_arguments(pc):
     assert call(v=None) == pc.PC_EINVAL
     assert call(wb=ws - 1) == pc.PC_EWORKSPACE
     assert L.estimate_normals_radius(None, 0, 0.01, 0, vp, None, None, None, 0, None) == pc.PC_OK
+
+
+def test_pose_net_and_learned_icp_reject_bad_arguments(pc):
+    L = pc.lib
+    assert L.pose_net_param_count() == 3 * 64 + 64 + 64 * 128 + 128 + 128 * 256 + 256 + 512 * 256 + 256 + 256 * 4 + 4
+    so, to = _i64([0, 50, 50, 120]), _i64([0, 60, 70, 70])
+    ws = L.pose_net_workspace_size(3, so, to)
+    assert ws > 0 and L.pose_net_workspace_size(0, so, to) == 0
+    assert L.pose_net_workspace_size(3, so, _i64([0, 60, 50, 70])) == 0
+
+    def predict(m=3, params=FAKE, out=FAKE, wb=ws, t=to):
+        return L.pose_net_predict(params, m, FAKE, so, FAKE, t, out, FAKE, wb, None)
+
+    assert predict(wb=ws - 1) == pc.PC_EWORKSPACE
+    assert predict(params=None) == pc.PC_EINVAL
+    assert predict(out=None) == pc.PC_EINVAL
+    assert predict(out=FAKE + 4) == pc.PC_EINVAL
+    assert predict(m=0) == pc.PC_EINVAL
+    assert predict(t=_i64([1, 60, 70, 70])) == pc.PC_EINVAL
+
+    def train(step=1, lr=1e-3, m_=FAKE, v_=FAKE, lab=FAKE, wb=ws):
+        return L.pose_net_train_step(FAKE, m_, v_, step, lr, 3, FAKE, so, FAKE, to, lab, None, None, None, FAKE, wb,
+                                     None)
+
+    assert train(wb=ws - 1) == pc.PC_EWORKSPACE
+    assert train(step=0) == pc.PC_EINVAL
+    assert train(lr=-1.0) == pc.PC_EINVAL
+    assert train(lr=float("inf")) == pc.PC_EINVAL
+    assert train(m_=None) == pc.PC_EINVAL
+    assert train(lr=0.0, m_=None, v_=None, wb=ws - 1) == pc.PC_EWORKSPACE   # moments not needed without a step
+    assert train(lab=None) == pc.PC_EINVAL
+
+    wl = L.icp_learned_batched_workspace_size(3, so, to, 10)
+    assert wl > L.icp_point_to_plane_batched_workspace_size(3, so, to, 10)
+    assert L.icp_learned_batched_workspace_size(3, so, to, -1) == 0
+
+    def run(mode=0, params=FAKE, d=0.1, it=10, acc=0.01, nrm=FAKE, out=FAKE, wb=wl):
+        return L.icp_learned_batched(mode, params, 3, FAKE, so, FAKE, nrm, to, d, it, 0.0, acc, out, None, None,
+                                     FAKE, wb, None)
+
+    assert run(wb=wl - 1) == pc.PC_EWORKSPACE
+    assert run(mode=3) == pc.PC_EINVAL
+    assert run(params=None) == pc.PC_EINVAL
+    assert run(mode=2, params=None) == pc.PC_EINVAL
+    assert run(mode=1, params=None, wb=wl - 1) == pc.PC_EWORKSPACE      # multi-start needs no network
+    assert run(d=0.0) == pc.PC_EINVAL
+    assert run(acc=float("nan")) == pc.PC_EINVAL
+    assert run(nrm=None) == pc.PC_EINVAL
+    assert run(out=None) == pc.PC_EINVAL
