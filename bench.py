@@ -5,14 +5,16 @@ target (estimate_normals), then point-to-plane ICP (target grid, the fixed
 iteration loop, final statistics pass).  Inputs are resident in HBM before
 the timed region; the timed region is bracketed by device synchronisation.
 
-    python bench.py [--steps K] [--warmup W] [--workload room|street|sphere|batch]
+    python bench.py [--steps K] [--warmup W] [--workload room|street|sphere|batch|projective|learned]
 
 Prints one JSON line.  value = pairs/s; the loop-only Mpt*iter/s, the
 roofline of the dominant kernel (the per-iteration correspondence +
 accumulation kernel, timed with HIP events on the library's stream) and a
 CPU-oracle baseline are reported alongside.  The batch workload runs 256
 uneven pairs per step through the batched entry points (one step = normals
-of every target + ICP of every pair).
+of every target + ICP of every pair).  The learned workload registers 512
+exact-copy pairs from four starts (plain, 8-start, learned with 8-start
+fallback, learned only); the default run appends a summary of it.
 """
 from __future__ import annotations
 
@@ -29,7 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "ICP pairs/s + Mpt·iter/s at ≤1e-5 rad pose error; learned-init vs plain"
-WORKLOADS = {"sphere": 0, "room": 1, "street": 2, "batch": 3, "projective": 5}
+WORKLOADS = {"sphere": 0, "room": 1, "street": 2, "batch": 3, "projective": 5, "learned": 4}
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per source point per ICP iteration: source xyz (12),
 # matched target xyz + normal (24), cell lookup (4); the projective
@@ -37,6 +39,10 @@ HBM_PEAK_GBS = 8000.0
 ICP_BYTES_PER_POINT = 40
 PROJ_BYTES_PER_POINT = 36
 PROJECTIVE = dict(name="room_views_vga", width=640, height=480, angle=3.0, t=0.03, k=16, d_max=0.2, iters=15)
+# matrix-core work of the learned initialiser's encoder per point: the
+# 64 -> 128 and 128 -> 256 layers, 2 flops per multiply-add
+ENC_FLOPS_PER_POINT = 2 * (64 * 128 + 128 * 256)
+BF16_PEAK_TFLOPS = 2500.0
 PROFILES = os.path.join(ROOT, "profiles")
 TUNING_CACHE = os.path.join(ROOT, "paper_1807_00399_amd", "tuning_cache.json")
 
@@ -70,6 +76,8 @@ def parse():
                     help="time every tuning candidate even when the tuning cache has this workload")
     ap.add_argument("--no-compare", action="store_true",
                     help="batch workload: skip the one-call-per-pair comparison")
+    ap.add_argument("--no-learned", action="store_true",
+                    help="default run: skip the learned-initialiser comparison")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain 1 GiB device copy (bandwidth and counter calibration) and exit")
     return ap.parse_args()
@@ -281,6 +289,148 @@ def bench_projective(args):
     print(json.dumps(out), flush=True)
 
 
+def cpu_baseline_learned(b, gpu_T, budget_s):
+    """The oracle's 8-start ICP (kd-tree normals + 8 registrations per pair)
+    on the first pairs of the workload until about budget_s seconds have
+    passed, and how many of the GPU's learned-initialiser results agree
+    with it (1e-5 rad, 1e-6)."""
+    import oracle
+    from oracle import pose_net as opn
+    oracle.build(force=False)
+
+    def pose_err(Ta, Tb):
+        c = (np.trace(Ta[:3, :3] @ Tb[:3, :3].T) - 1.0) / 2.0
+        return float(np.arccos(np.clip(c, -1.0, 1.0))), float(np.linalg.norm(Ta[:3, 3] - Tb[:3, 3]))
+
+    t0 = time.perf_counter()
+    pairs, agree = 0, 0
+    for j, w in enumerate(b.pairs):
+        nrm, _, _ = oracle.normals(w.target, w.k, (0.0, 0.0, 0.0), method="kdtree")
+        ro, _ = opn.multi_start_icp(oracle, w.source, w.target, nrm.astype(np.float32), float(np.float32(w.d_max)),
+                                    w.iters)
+        ea, et = pose_err(gpu_T[j], ro["T"])
+        agree += int(ea <= 1e-5 and et <= 1e-6)
+        pairs += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    el = time.perf_counter() - t0
+    return {"value": pairs / el, "unit": "pairs/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": f"the first {pairs} of {b.n_pairs} pairs, 8-start ICP each (normals + 8 registrations), "
+                      f"{el:.1f} s wall",
+            "gpu_learned_agrees_with_oracle_8_start": f"{agree}/{pairs}"}
+
+
+def learned_legs(steps, warmup):
+    """The learned-initialiser workload through four starts: plain (identity),
+    8-start, learned with 8-start fallback, learned only.  One step = target
+    normals + registration of every pair.  Success = final pose within
+    1e-5 rad and 1e-6 of the generating transform (the pairs are exact
+    copies, so the optimum is that transform)."""
+    import torch
+    from gen import POSE_CONFIG, pose_pairs
+    from paper_1807_00399_amd import pcgpu
+    from paper_1807_00399_amd.train_pose_net import load_params
+    dev = torch.device("cuda:0")
+    cfg = POSE_CONFIG
+    b = pose_pairs(cfg["eval_config"])
+    off = b.offsets
+    m = b.n_pairs
+    src = torch.from_numpy(b.source).to(dev)
+    tgt = torch.from_numpy(b.target).to(dev)
+    params = torch.from_numpy(load_params()).to(dev)
+    gt = np.stack([w.T_gt for w in b.pairs])
+    ws_n = torch.empty(pcgpu.lib.estimate_normals_batched_workspace_size(m, off.ctypes.data), dtype=torch.uint8,
+                       device=dev)
+    ws_l = torch.empty(pcgpu.lib.icp_learned_batched_workspace_size(m, off.ctypes.data, off.ctypes.data,
+                                                                    cfg["iters"]), dtype=torch.uint8, device=dev)
+    T = torch.empty((m, 4, 4), dtype=torch.float64, device=dev)
+    stats = torch.zeros(24 * m, dtype=torch.uint8, device=dev)
+
+    def run(mode):
+        nrm, _ = pcgpu.estimate_normals_batched(tgt, off, cfg["k"], curvature=False, workspace=ws_n)
+        if mode == "plain":
+            Tm, sm = pcgpu.icp_point_to_plane_batched(src, off, tgt, nrm, off, None, cfg["d_max"], cfg["iters"],
+                                                      workspace=ws_l, out_T=T, out_stats=stats, read_stats=False)
+            return Tm, sm, None
+        code = {"multi_start": pcgpu.PC_INIT_MULTI_START, "learned": pcgpu.PC_INIT_LEARNED,
+                "learned_only": pcgpu.PC_INIT_LEARNED_ONLY}[mode]
+        return pcgpu.icp_learned_batched(code, params, src, off, tgt, nrm, off, cfg["d_max"], cfg["iters"],
+                                         accept_rms=cfg["accept_rms"], workspace=ws_l, read_stats=False)
+
+    legs = {}
+    for mode in ("plain", "multi_start", "learned", "learned_only"):
+        for _ in range(warmup):
+            run(mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            Tm, sm, start = run(mode)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        Tn = Tm.cpu().numpy()
+        ea = np.array([np.arccos(np.clip((np.trace(Tn[j, :3, :3] @ gt[j, :3, :3].T) - 1) / 2, -1, 1))
+                       for j in range(m)])
+        et = np.linalg.norm(Tn[:, :3, 3] - gt[:, :3, 3], axis=1)
+        leg = {"pairs_per_s": m * steps / el, "ms_per_step": 1e3 * el / steps,
+               "success": float(np.mean((ea <= 1e-5) & (et <= 1e-6)))}
+        if start is not None and mode == "learned":
+            leg["fallback_fraction"] = float(np.mean(start.cpu().numpy() >= 0))
+        legs[mode] = leg
+        if mode == "learned":
+            learned_T = Tn
+    # encoder forward alone (torch events: the library runs on torch's stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    pcgpu.pose_net_predict(params, src, off, tgt, off)
+    e0.record()
+    for _ in range(10):
+        T0 = pcgpu.pose_net_predict(params, src, off, tgt, off)
+    e1.record()
+    torch.cuda.synchronize()
+    pred_s = e0.elapsed_time(e1) / 10 * 1e-3
+    e_init = np.array([np.degrees(np.arccos(np.clip((np.trace(a[:3, :3] @ g[:3, :3].T) - 1) / 2, -1, 1)))
+                       for a, g in zip(T0.cpu().numpy(), gt)])
+    info = {"workload": f"{b.name}: {m} exact-copy pairs of {cfg['n_points']} points, sphere+plane or room, "
+                        f"rotation U(0, 90) deg, |t| U(0, 0.3); k={cfg['k']}, d_max {cfg['d_max']}, "
+                        f"{cfg['iters']} iterations, accepted rms {cfg['accept_rms']}",
+            "pairs": m, "points_per_side": b.n, "legs": legs,
+            "learned_init_rotation_error_deg": {"median": float(np.median(e_init)),
+                                                "within_30": float(np.mean(e_init < 30))},
+            "predict_ms": pred_s * 1e3}
+    return info, b, learned_T, pred_s
+
+
+def bench_learned(args):
+    info, b, learned_T, pred_s = learned_legs(args.steps, args.warmup)
+    leg = info["legs"]["learned"]
+    flops = ENC_FLOPS_PER_POINT * 2 * b.n
+    achieved = flops / pred_s / 1e12
+    out = {
+        "metric": METRIC,
+        "value": leg["pairs_per_s"],
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": leg["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32 (encoder bf16 matrix cores, f32 accumulation)",
+        "data": "synthetic",
+        "config": {"workload": info["workload"], "pairs": info["pairs"], "points_per_side": info["points_per_side"]},
+        "success": leg["success"],
+        "learned_vs_plain": info["legs"],
+        "learned_init_rotation_error_deg": info["learned_init_rotation_error_deg"],
+        "roofline": {"bound": "mfma", "achieved": achieved, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / BF16_PEAK_TFLOPS, "traffic": None,
+                     "kernel": "pose_net_predict (encoder forward, both clouds of every pair)",
+                     "avg_call_us": pred_s * 1e6, "algorithmic_flops_per_call": float(flops)},
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_learned(b, learned_T, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
 def bench_batch(args):
     """Batched workload: all pairs per step through the batched entry points."""
     import torch
@@ -407,6 +557,9 @@ def main():
     if args.workload == "projective":
         bench_projective(args)
         return
+    if args.workload == "learned":
+        bench_learned(args)
+        return
     dev = torch.device("cuda:0")
     w = make_workload(WORKLOADS[args.workload])
     src = torch.from_numpy(w.source).to(dev)
@@ -480,6 +633,10 @@ def main():
                      "kernel": "k_icp_accum", "avg_kernel_us": avg_kernel_s * 1e6,
                      "algorithmic_bytes_per_launch": algo_bytes},
     }
+    if not args.no_learned:
+        info = learned_legs(min(args.steps, 5), 1)[0]
+        out["learned_vs_plain"] = {"workload": info["workload"], "legs": info["legs"],
+                                   "learned_init_rotation_error_deg": info["learned_init_rotation_error_deg"]}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out), flush=True)
