@@ -324,8 +324,8 @@ k_icp_accum(GridView g, const float *__restrict__ src, const int64_t *__restrict
     // the DFS stack and, after the search, the reduction buffer share LDS
     constexpr int kHalf = kAcc / 2;                       // accumulators per reduction pass
     constexpr int kRow = NT + 1;                          // padded row (bank spread)
-    static_assert(kHalf * kRow <= kStack * NT, "reduction buffer must fit in the stack");
-    __shared__ uint32_t stk[kStack * NT];
+    static_assert(kHalf * kRow <= kStackNear * NT, "reduction buffer must fit in the stack");
+    __shared__ uint32_t stk[kStackNear * NT];
     const int lblk = xcd_block(blockIdx.x, nblk);
     const int pr = np > 1 ? pair_of(boff, np, lblk) : 0;
     const IcpState *st = state + pr;
@@ -361,10 +361,11 @@ k_icp_accum(GridView g, const float *__restrict__ src, const int64_t *__restrict
         bool done = false;
         if (pv.x >= 0) {
             float4 p0 = g.pts[pv.x];
+            Node nm = g.node[pv.y];     // issued with p0: one round trip for both
             v.visit(q.x, q.y, q.z, (uint32_t)pv.x, p0, (uint32_t)pv.y);
-            if (v.best_pos >= 0) done = search_in_node(g, P, q, v, (uint32_t)pv.y, p0);
+            if (v.best_pos >= 0) done = search_in_node(g, P, q, v, (uint32_t)pv.y, nm, p0);
         }
-        if (!done) search<NearBand, LEAF>(g, P, q, v, 1, stk + threadIdx.x, NT);
+        if (!done) search<NearBand, LEAF, kStackNear>(g, P, q, v, 1, stk + threadIdx.x, NT);
         prev[i] = v.best_pos >= 0 ? make_int2(v.best_pos, (int32_t)v.best_node) : make_int2(-1, -1);
         if (v.best_pos >= 0) {
             float b = v.best_key();
@@ -385,7 +386,7 @@ k_icp_accum(GridView g, const float *__restrict__ src, const int64_t *__restrict
                 w.best_orig = 0xffffffffu;
                 w.best_pos = -1;
                 w.r2 = b + 2.f * e;
-                cover<Near64, LEAF>(g, P, q, w, stk + threadIdx.x, NT, 0u, 0u);
+                cover<Near64, LEAF, kStackNear>(g, P, q, w, stk + threadIdx.x, NT, 0u, 0u);
                 j = w.best_pos;
             }
         }

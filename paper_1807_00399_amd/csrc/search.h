@@ -26,7 +26,8 @@
 
 namespace pcg {
 
-constexpr int kStack = 32;              // per-lane DFS stack entries (LDS, 4 bytes each)
+constexpr int kStack = 32;              // default per-lane DFS stack entries (LDS, 4 bytes each)
+constexpr int kStackNear = 16;          // nearest-neighbour searches of ICP: shallow stacks, higher occupancy
 constexpr int kVisitBudget = 1 << 20;   // node pops per DFS; only a corrupted tree reaches it
 
 __device__ inline uint64_t enc_cand(float key, float w) { return ((uint64_t)__float_as_uint(key) << 32) | __float_as_uint(w); }
@@ -169,8 +170,9 @@ __device__ inline void sort8(float *d, uint32_t *id)
 }
 
 // Depth-first search from the nodes already on the stack.
-// stk: this lane's stack column (stride `stride` entries).
-template <class V, int LEAF>
+// stk: this lane's stack column (stride `stride` entries, STK of them); a
+// node whose children would overflow the stack is scanned as a leaf.
+template <class V, int LEAF, int STK = kStack>
 __device__ inline void dfs(const GridView &g, const GridParams &P, const Query &q, V &v, uint32_t *stk, int stride,
                            int sp, uint32_t xs, uint32_t xe)
 {
@@ -183,7 +185,7 @@ __device__ inline void dfs(const GridView &g, const GridParams &P, const Query &
         if (node_mindist2(P, nd, q.x, q.y, q.z) > b2) continue;
         if (h.start >= xs && h.start + h.count <= xe) continue;      // already searched
         uint32_t nc = node_nchild(h);
-        bool leaf = (h.count <= (uint32_t)LEAF) || node_level(h) == P.lmin || sp + (int)nc > kStack;
+        bool leaf = (h.count <= (uint32_t)LEAF) || node_level(h) == P.lmin || sp + (int)nc > STK;
         if (leaf) {
             scan_range(g.pts, h.start, h.start + h.count, xs, xe, q, v, m);
             continue;
@@ -224,8 +226,9 @@ __device__ inline int cover_level(const GridParams &P, float b2)
     return l;
 }
 
-// Cover phase: every cell meeting the ball of the visitor's current radius.
-template <class V, int LEAF>
+// Cover phase: every cell meeting the ball of the visitor's current radius,
+// nearest cell searched first.
+template <class V, int LEAF, int STK = kStack>
 __device__ inline void cover(const GridView &g, const GridParams &P, const Query &q, V &v, uint32_t *stk,
                              int stride, uint32_t xs, uint32_t xe)
 {
@@ -257,15 +260,28 @@ __device__ inline void cover(const GridView &g, const GridParams &P, const Query
             hk[c] = e.key;
             node[c] = (e.key == key[c]) ? (int32_t)e.val : -1;
         }
+        float d[8];
+        uint32_t id[8];
 #pragma unroll
         for (int c = 0; c < 8; c++) {
             if (hk[c] != key[c] && hk[c] != kEmptyKey) node[c] = probe_from(g, P, key[c], slot[c]);
+            d[c] = INFINITY;
+            id[c] = 0xffffffffu;
             if (node[c] >= 0) {
                 uint32_t cx = lx + (c & 1), cy = ly + ((c >> 1) & 1), cz = lz + (c >> 2);
-                if (cell_mindist2(P, q.x, q.y, q.z, cx, cy, cz, l) <= b2) {
-                    stk[sp * stride] = (uint32_t)node[c];
-                    ++sp;
+                float dc = cell_mindist2(P, q.x, q.y, q.z, cx, cy, cz, l);
+                if (dc <= b2) {
+                    d[c] = dc;
+                    id[c] = (uint32_t)node[c];
                 }
+            }
+        }
+        sort8(d, id);
+#pragma unroll
+        for (int c = 7; c >= 0; c--) {
+            if (id[c] != 0xffffffffu) {
+                stk[sp * stride] = id[c];
+                ++sp;
             }
         }
     } else {
@@ -274,8 +290,9 @@ __device__ inline void cover(const GridView &g, const GridParams &P, const Query
             for (uint32_t cy = ly; cy <= hy; cy++)
                 for (uint32_t cx = lx; cx <= hx; cx++) {
                     int32_t m = find_cell(g, P, l, cx, cy, cz);
-                    if (m < 0 || cell_mindist2(P, q.x, q.y, q.z, cx, cy, cz, l) > b2) continue;
-                    if (sp < kStack) {
+                    float dc = cell_mindist2(P, q.x, q.y, q.z, cx, cy, cz, l);
+                    if (m < 0 || dc > b2) continue;
+                    if (sp < STK) {
                         stk[sp * stride] = (uint32_t)m;
                         ++sp;
                     } else {
@@ -284,7 +301,7 @@ __device__ inline void cover(const GridView &g, const GridParams &P, const Query
                     }
                 }
     }
-    dfs<V, LEAF>(g, P, q, v, stk, stride, sp, xs, xe);
+    dfs<V, LEAF, STK>(g, P, q, v, stk, stride, sp, xs, xe);
 }
 
 // smallest cell (level lmin and up) around q holding >= need points, or -1;
@@ -324,16 +341,15 @@ __device__ inline int32_t seed_cell(const GridView &g, const GridParams &P, cons
 }
 
 // Warm start: when the ball of the visitor's radius around q lies inside the
-// cell of node m (a node holding the previous answer, whose point p0 fixes
-// the cell), every candidate is in m, so scanning m alone is exact.  Returns
+// cell of node m (record nd, a node holding the previous answer, whose point
+// p0 fixes the cell), every candidate is in m, so scanning m alone is exact.  Returns
 // false (nothing scanned) when the ball leaves the cell.
 template <class V>
 __device__ inline bool search_in_node(const GridView &g, const GridParams &P, const Query &q, V &v, uint32_t m,
-                                      const float4 &p0)
+                                      const Node &nd, const float4 &p0)
 {
     float b2 = v.bound2();
     if (!(b2 < INFINITY)) return false;
-    Node nd = g.node[m];
     int l = node_level(nd.h);
     const float inv = P.inv_h0;
     float R = sqrtf(b2) * (1.0f + 1.0f / (1 << 20)) + P.margin;
@@ -349,7 +365,7 @@ __device__ inline bool search_in_node(const GridView &g, const GridParams &P, co
 // Full search.  `need` = number of points the seed cell must hold (k, or 1
 // for the nearest neighbour).  When the visitor already has a finite radius
 // (a warm start) the seed phase is skipped.
-template <class V, int LEAF>
+template <class V, int LEAF, int STK = kStack>
 __device__ inline void search(const GridView &g, const GridParams &P, const Query &q, V &v, int need,
                               uint32_t *stk, int stride)
 {
@@ -362,12 +378,12 @@ __device__ inline void search(const GridView &g, const GridParams &P, const Quer
         int32_t seed = seed_cell(g, P, q, need);
         if (seed < 0) return;   // fewer than `need` points in the cloud
         stk[0] = (uint32_t)seed;
-        dfs<V, LEAF>(g, P, q, v, stk, stride, 1, 0u, 0u);
+        dfs<V, LEAF, STK>(g, P, q, v, stk, stride, 1, 0u, 0u);
         NodeHdr hs = g.node[seed].h;
         xs = hs.start;
         xe = hs.start + hs.count;
     }
-    cover<V, LEAF>(g, P, q, v, stk, stride, xs, xe);
+    cover<V, LEAF, STK>(g, P, q, v, stk, stride, xs, xe);
 }
 
 }  // namespace pcg
