@@ -1,8 +1,9 @@
 """Benchmark of the point-to-plane ICP hot path on one MI355X.
 
-One step = one pair through the whole path: grid + PCA normals of the
-target (estimate_normals), then point-to-plane ICP (target grid, the fixed
-iteration loop, final statistics pass).  Inputs are resident in HBM before
+One step = one pair through the whole path: the target pyramid, PCA normals
+of the target, then point-to-plane ICP (the fixed iteration loop and the
+final statistics pass), in one call (icp_point_to_plane_with_normals, which
+builds the target pyramid once for both).  Inputs are resident in HBM before
 the timed region; the timed region is bracketed by device synchronisation.
 
     python bench.py [--steps K] [--warmup W] [--workload room|street|sphere|batch|projective|learned]
@@ -567,14 +568,13 @@ def main():
     stream = torch.cuda.current_stream()
     T = torch.empty((4, 4), dtype=torch.float64, device=dev)
     stats = torch.zeros(24, dtype=torch.uint8, device=dev)
-    ws_n = torch.empty(pcgpu.lib.estimate_normals_workspace_size(w.n, w.k), dtype=torch.uint8, device=dev)
-    ws_i = pcgpu.workspace_for_icp(w.n, w.n, w.iters, dev)
+    ws = torch.empty(pcgpu.lib.icp_point_to_plane_with_normals_workspace_size(w.n, w.n, w.iters),
+                     dtype=torch.uint8, device=dev)
 
     def step():
-        nrm, _ = pcgpu.estimate_normals(tgt, w.k, curvature=False, workspace=ws_n)
-        pcgpu.icp_point_to_plane(src, tgt, nrm, None, w.d_max, w.iters, workspace=ws_i, out_T=T,
-                                 out_stats=stats, read_stats=False)
-        return nrm
+        # target normals and ICP in one call: one target pyramid serves both
+        pcgpu.icp_point_to_plane_with_normals(src, tgt, w.k, (0.0, 0.0, 0.0), None, w.d_max, w.iters,
+                                              workspace=ws, out_T=T, out_stats=stats, read_stats=False)
 
     tuning = autotune_step(args, step, w.name, w.n)
     for _ in range(args.warmup):

@@ -174,6 +174,22 @@ pc_status icp_point_to_plane(const float *src_xyz, int64_t n_src,
                              double conv_tol, double *out_T, pc_icp_stats *out_stats,
                              void *workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* icp_point_to_plane with the target normals estimated in the same call:
+ * the target pyramid is built once and serves both the normals
+ * (estimate_normals with k and viewpoint) and the correspondences.  The
+ * result equals estimate_normals followed by icp_point_to_plane with those
+ * normals, bit for bit.
+ *   k            1 <= k <= min(n_tgt, PCGPU_KMAX)
+ *   out_normals  (n_tgt, 3) float32 target normals, or NULL (then kept in
+ *                the workspace only) */
+size_t icp_point_to_plane_with_normals_workspace_size(int64_t n_src, int64_t n_tgt, int max_iters);
+pc_status icp_point_to_plane_with_normals(const float *src_xyz, int64_t n_src,
+                                          const float *tgt_xyz, int64_t n_tgt, int k,
+                                          const float viewpoint[3], const double *init_T,
+                                          float max_corr_dist, int max_iters, double conv_tol,
+                                          double *out_T, pc_icp_stats *out_stats, float *out_normals,
+                                          void *workspace, size_t workspace_bytes, hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Metric variants of the same loop (Section 3, "Iterative geometric
  * registration": point-to-point and point-to-plane metrics and weighted

@@ -287,6 +287,50 @@ pc_status icp_point_to_plane(const float *src_xyz, int64_t n_src, const float *t
                       out_T, out_stats, workspace, workspace_bytes, stream, 0, 0.f, 1.f);
 }
 
+size_t icp_point_to_plane_with_normals_workspace_size(int64_t n_src, int64_t n_tgt, int max_iters)
+{
+    if (n_src < 0 || n_tgt < 0 || n_src >= kMaxPoints || n_tgt >= kMaxPoints || max_iters < 0) return 0;
+    Carver c(nullptr, ~(size_t)0 >> 1);
+    IcpStore s;
+    carve_single(c, n_src, n_tgt, max_iters, s);
+    c.take<float>((size_t)3 * (n_tgt > 0 ? n_tgt : 1));
+    return c.used();
+}
+
+pc_status icp_point_to_plane_with_normals(const float *src_xyz, int64_t n_src, const float *tgt_xyz, int64_t n_tgt,
+                                          int k, const float viewpoint[3], const double *init_T, float max_corr_dist,
+                                          int max_iters, double conv_tol, double *out_T, pc_icp_stats *out_stats,
+                                          float *out_normals, void *workspace, size_t workspace_bytes,
+                                          hipStream_t stream)
+{
+    if (n_src < 0 || n_tgt < 0 || n_src >= kMaxPoints || n_tgt >= kMaxPoints || !viewpoint) return PC_EINVAL;
+    if (k < 1 || k > PCGPU_KMAX || (n_tgt > 0 && k > n_tgt)) return PC_EINVAL;
+    if (!isfinite(viewpoint[0]) || !isfinite(viewpoint[1]) || !isfinite(viewpoint[2])) return PC_EINVAL;
+    if (max_iters < 0 || !(max_corr_dist > 0.f) || !isfinite(max_corr_dist)) return PC_EINVAL;
+    if (!(conv_tol >= 0.0) || !isfinite(conv_tol)) return PC_EINVAL;
+    if (!out_T || !workspace) return PC_EINVAL;
+    if ((n_src > 0 && !src_xyz) || (n_tgt > 0 && !tgt_xyz)) return PC_EINVAL;
+    if (!aligned(src_xyz, 4) || !aligned(tgt_xyz, 4) || !aligned(out_normals, 4) || !aligned(init_T, 8) ||
+        !aligned(out_T, 8) || !aligned(out_stats, 8) || !aligned(workspace, 256))
+        return PC_EINVAL;
+    if (workspace_bytes < icp_point_to_plane_with_normals_workspace_size(n_src, n_tgt, max_iters))
+        return PC_EWORKSPACE;
+    Carver c(workspace, workspace_bytes);
+    IcpStore s;
+    carve_single(c, n_src, n_tgt, max_iters, s);
+    float *nb = c.take<float>((size_t)3 * (n_tgt > 0 ? n_tgt : 1));
+    if (!c.ok) return PC_EWORKSPACE;
+    if (out_normals) nb = out_normals;
+    if (icp_layout_single(s, n_src, n_tgt, max_corr_dist, max_iters, stream) != hipSuccess) return PC_EDEVICE;
+    // one pyramid over the target serves its normals and the correspondences
+    if (grid_build(s.grid, tgt_xyz, stream) != hipSuccess) return PC_EDEVICE;
+    if (n_tgt > 0 && normals_run(s.grid, tgt_xyz, k, nullptr, viewpoint, nb, nullptr, stream) != hipSuccess)
+        return PC_EDEVICE;
+    s.grid_built = true;
+    hipError_t e = icp_run(s, src_xyz, n_src, tgt_xyz, nb, init_T, conv_tol, out_T, out_stats, stream);
+    return e == hipSuccess ? PC_OK : PC_EDEVICE;
+}
+
 pc_status icp_point_to_point(const float *src_xyz, int64_t n_src, const float *tgt_xyz, int64_t n_tgt,
                              const double *init_T, float max_corr_dist, int max_iters, double conv_tol,
                              double *out_T, pc_icp_stats *out_stats, void *workspace, size_t workspace_bytes,

@@ -37,6 +37,7 @@ struct IcpStore {
     const float *ptgt, *pnrm;  // projective: organized target points and normals (height * width, 3)
     int width, height;
     float K[4];         // projective: fx, fy, cx, cy
+    bool grid_built;    // the target pyramid is already built (by the caller, e.g. for its normals)
 };
 
 enum { kAssocNearest = 0, kAssocProjective = 1 };

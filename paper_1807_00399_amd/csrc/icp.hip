@@ -874,6 +874,7 @@ void icp_carve(Carver &c, int np, int64_t ns, int64_t nt, int64_t nblk, int64_t 
     s.ptgt = s.pnrm = nullptr;
     s.width = s.height = 0;
     s.K[0] = s.K[1] = s.K[2] = s.K[3] = 0.f;
+    s.grid_built = false;
     s.iters_max = iters_max > 0 ? iters_max : 0;
     s.nrm = c.take<float4>(nt1);
     s.prev = c.take<int2>(ns1);
@@ -953,8 +954,10 @@ hipError_t icp_run(IcpStore &s, const float *src, int64_t ns, const float *tgt, 
     k_icp_setup<<<(np + 63) / 64, 64, 0, st>>>(init_T, s.soff, s.grid.off, s.maxit, np, s.st);
     hipError_t e = hipSuccess;
     if (s.assoc == kAssocNearest) {
-        e = grid_build(s.grid, tgt, st);
-        if (e != hipSuccess) return e;
+        if (!s.grid_built) {
+            e = grid_build(s.grid, tgt, st);
+            if (e != hipSuccess) return e;
+        }
         if (tgt_n) {
             e = grid_gather3(s.grid, tgt_n, s.nrm, st);
             if (e != hipSuccess) return e;

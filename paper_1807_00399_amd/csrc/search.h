@@ -27,7 +27,7 @@
 namespace pcg {
 
 constexpr int kStack = 32;              // default per-lane DFS stack entries (LDS, 4 bytes each)
-constexpr int kStackNear = 16;          // nearest-neighbour searches of ICP: shallow stacks, higher occupancy
+constexpr int kStackNear = 24;          // nearest-neighbour searches of ICP: shallower stacks, higher occupancy
 constexpr int kVisitBudget = 1 << 20;   // node pops per DFS; only a corrupted tree reaches it
 
 __device__ inline uint64_t enc_cand(float key, float w) { return ((uint64_t)__float_as_uint(key) << 32) | __float_as_uint(w); }

@@ -25,6 +25,7 @@ EXPORTS = (
     "knn_search_workspace_size", "knn_search",
     "estimate_normals_workspace_size", "estimate_normals", "estimate_normals_radius",
     "icp_point_to_plane_workspace_size", "icp_point_to_plane", "icp_point_to_point", "icp_combined",
+    "icp_point_to_plane_with_normals_workspace_size", "icp_point_to_plane_with_normals",
     "icp_projective_workspace_size", "icp_projective",
     "estimate_normals_batched_workspace_size", "estimate_normals_batched",
     "icp_point_to_plane_batched_workspace_size", "icp_point_to_plane_batched",
@@ -70,6 +71,11 @@ def _load() -> ctypes.CDLL:
     lib.icp_point_to_plane_workspace_size.restype = sz
     lib.icp_point_to_plane.argtypes = [vp, i64, vp, vp, i64, vp, f32, i32, f64, vp, vp, vp, sz, vp]
     lib.icp_point_to_plane.restype = ctypes.c_int
+    lib.icp_point_to_plane_with_normals_workspace_size.argtypes = [i64, i64, i32]
+    lib.icp_point_to_plane_with_normals_workspace_size.restype = sz
+    lib.icp_point_to_plane_with_normals.argtypes = [vp, i64, vp, i64, i32, ctypes.POINTER(ctypes.c_float), vp, f32,
+                                                    i32, f64, vp, vp, vp, vp, sz, vp]
+    lib.icp_point_to_plane_with_normals.restype = ctypes.c_int
     lib.icp_point_to_point.argtypes = [vp, i64, vp, i64, vp, f32, i32, f64, vp, vp, vp, sz, vp]
     lib.icp_point_to_point.restype = ctypes.c_int
     lib.icp_combined.argtypes = [vp, i64, vp, vp, i64, vp, f32, f32, f32, i32, f64, vp, vp, vp, sz, vp]
@@ -241,6 +247,34 @@ def icp_point_to_plane(src: torch.Tensor, tgt: torch.Tensor, tgt_normals: torch.
     if not read_stats:
         return T, stats
     return T, decode_stats(stats)
+
+
+def icp_point_to_plane_with_normals(src: torch.Tensor, tgt: torch.Tensor, k: int, viewpoint=(0.0, 0.0, 0.0),
+                                    init_T=None, max_corr_dist: float = 0.05, max_iters: int = 30,
+                                    conv_tol: float = 0.0, return_normals: bool = False, stream=None,
+                                    workspace: torch.Tensor | None = None, out_T: torch.Tensor | None = None,
+                                    out_stats: torch.Tensor | None = None, read_stats: bool = True):
+    """Target normals (k, viewpoint) and point-to-plane ICP in one call over
+    one target pyramid.  Returns (T, stats) or (T, stats, normals)."""
+    src = _pts(src, "src")
+    tgt = _pts(tgt, "tgt")
+    dev = src.device
+    T0 = None
+    if init_T is not None:
+        T0 = torch.as_tensor(init_T, dtype=torch.float64).reshape(4, 4).to(dev).contiguous()
+    T = out_T if out_T is not None else torch.empty((4, 4), dtype=torch.float64, device=dev)
+    stats = out_stats if out_stats is not None else torch.zeros(24, dtype=torch.uint8, device=dev)
+    nrm = torch.empty((tgt.shape[0], 3), dtype=torch.float32, device=dev) if return_normals else None
+    vp = (ctypes.c_float * 3)(*[float(v) for v in viewpoint])
+    need = lib.icp_point_to_plane_with_normals_workspace_size(src.shape[0], tgt.shape[0], int(max_iters))
+    ws = workspace if workspace is not None else _ws.get(need, dev)
+    st = lib.icp_point_to_plane_with_normals(src.data_ptr(), src.shape[0], tgt.data_ptr(), tgt.shape[0], int(k), vp,
+                                             _ptr(T0), float(max_corr_dist), int(max_iters), float(conv_tol),
+                                             T.data_ptr(), stats.data_ptr(), _ptr(nrm), ws.data_ptr(), ws.numel(),
+                                             _stream(stream))
+    _check(st, "icp_point_to_plane_with_normals")
+    out = (T, stats if not read_stats else decode_stats(stats))
+    return out + (nrm,) if return_normals else out
 
 
 def _icp_variant(fn, what, src, tgt, tgt_normals, init_T, max_corr_dist, max_iters, conv_tol, stream, workspace,

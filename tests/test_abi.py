@@ -275,3 +275,24 @@ def test_pose_net_and_learned_icp_reject_bad_arguments(pc):
     assert run(acc=float("nan")) == pc.PC_EINVAL
     assert run(nrm=None) == pc.PC_EINVAL
     assert run(out=None) == pc.PC_EINVAL
+
+
+def test_icp_with_normals_rejects_bad_arguments(pc):
+    L = pc.lib
+    ws = L.icp_point_to_plane_with_normals_workspace_size(100, 80, 5)
+    assert ws > L.icp_point_to_plane_workspace_size(100, 80, 5)
+    assert L.icp_point_to_plane_with_normals_workspace_size(-1, 80, 5) == 0
+    vp = (ctypes.c_float * 3)(0.0, 0.0, 0.0)
+
+    def call(k=10, nt=80, d=0.05, out=FAKE, wb=ws, v=vp):
+        return L.icp_point_to_plane_with_normals(FAKE, 100, FAKE, nt, k, v, None, d, 5, 0.0, out, None, None, FAKE,
+                                                 wb, None)
+
+    assert call(wb=ws - 1) == pc.PC_EWORKSPACE
+    assert call(k=0) == pc.PC_EINVAL
+    assert call(k=33) == pc.PC_EINVAL
+    assert call(k=81) == pc.PC_EINVAL           # more neighbours than target points
+    assert call(d=0.0) == pc.PC_EINVAL
+    assert call(out=None) == pc.PC_EINVAL
+    assert call(v=None) == pc.PC_EINVAL
+    assert call(v=(ctypes.c_float * 3)(0.0, float("nan"), 0.0)) == pc.PC_EINVAL

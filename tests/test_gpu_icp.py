@@ -85,6 +85,27 @@ def test_icp_end_to_end_own_normals(gpu, oracle_mod):
     assert ea <= ROT_TOL and et <= TRANS_TOL
 
 
+@pytest.mark.parametrize("cfg,size", [(0, "full"), (1, "small"), (2, "small")])
+def test_icp_with_normals_equals_two_calls(gpu, cfg, size):
+    # one pyramid for normals and correspondences gives exactly the result
+    # of estimate_normals followed by icp_point_to_plane
+    import torch
+    w = make_workload(cfg, size=size)
+    _say(f"icp_with_normals {w.name} n={w.n}")
+    S, T = _dev(w.source), _dev(w.target)
+    n2, _ = gpu.estimate_normals(T, w.k, curvature=False)
+    Ta, sa = gpu.icp_point_to_plane(S, T, n2, None, w.d_max, w.iters, read_stats=False)
+    Tb, sb, nb = gpu.icp_point_to_plane_with_normals(S, T, w.k, init_T=None, max_corr_dist=w.d_max,
+                                                     max_iters=w.iters, return_normals=True, read_stats=False)
+    assert torch.equal(nb, n2) and torch.equal(Ta, Tb) and torch.equal(sa, sb)
+    # without the normals output, and with an empty target
+    Tc, sc = gpu.icp_point_to_plane_with_normals(S, T, w.k, max_corr_dist=w.d_max, max_iters=w.iters,
+                                                 read_stats=False)
+    assert torch.equal(Tc, Ta) and torch.equal(sc, sa)
+    Te, se = gpu.icp_point_to_plane_with_normals(S, T[:0], 1, max_corr_dist=w.d_max, max_iters=3)
+    assert se["status"] == 3 and np.array_equal(Te.cpu().numpy(), np.eye(4))
+
+
 def test_icp_identity_pair_bit_exact(gpu, oracle_mod):
     pts = sphere_plane(rng_for(600), 3000)
     nrm = _oracle_normals(oracle_mod, pts, 10)
