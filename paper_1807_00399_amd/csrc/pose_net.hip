@@ -38,8 +38,9 @@ namespace {
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
 
-constexpr int kT = 128;          // points per encoder workgroup
-constexpr int kThreads = 256;    // 4 waves; wave w owns rows 32w .. 32w + 31
+constexpr int kT = 512;          // points per encoder tile
+constexpr int kEncWaves = 8;     // waves per encoder workgroup; wave w owns rows 64w .. 64w + 63
+constexpr int kEncThreads = 64 * kEncWaves;
 constexpr int kP1 = kC1 + 8;     // padded LDS row lengths (bank spread)
 constexpr int kP2 = kC2 + 8;
 constexpr int kChunk = 128;      // rows per outer-product chunk
@@ -88,18 +89,31 @@ __global__ void k_norm_stats(const float *__restrict__ xs, const float *__restri
     }
 }
 
-// bfloat16 copies of W2 and W3, column-major (k contiguous per output
-// column): the layout of the matrix cores' B operand
-__global__ void k_weights_bf16(const float *__restrict__ params, __bf16 *__restrict__ w2t, __bf16 *__restrict__ w3t)
+// Layer 3 takes its K operand straight from layer 2's output registers,
+// whose channel order per lane differs from the natural one: slot s of
+// 32-wide k-block kb carries channel w3_slot_channel(kb, s).
+__device__ inline int w3_slot_channel(int kb, int s)
+{
+    const int g = s >> 3, j = s & 7;
+    return 32 * kb + (j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4));
+}
+
+// bfloat16 copies of W2 and W3 with k contiguous per output column (w2t,
+// w3t: [n][k]), and W3 in the slot order of the forward (w3p: [n][slot])
+__global__ void k_weights_bf16(const float *__restrict__ params, __bf16 *__restrict__ w2t, __bf16 *__restrict__ w3t,
+                               __bf16 *__restrict__ w3p)
 {
     const float *W2 = params + kOffW2, *W3 = params + kOffW3;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kC1 * kC2 + kC2 * kC3; i += gridDim.x * blockDim.x) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kC1 * kC2 + 2 * kC2 * kC3; i += gridDim.x * blockDim.x) {
         if (i < kC1 * kC2) {
             int n = i / kC1, k = i % kC1;
             w2t[i] = to_bf16(W2[k * kC2 + n]);
-        } else {
+        } else if (i < kC1 * kC2 + kC2 * kC3) {
             int j = i - kC1 * kC2, n = j / kC2, k = j % kC2;
             w3t[j] = to_bf16(W3[k * kC3 + n]);
+        } else {
+            int j = i - kC1 * kC2 - kC2 * kC3, n = j / kC2, sl = j % kC2;
+            w3p[j] = to_bf16(W3[w3_slot_channel(sl / 32, sl % 32) * kC3 + n]);
         }
     }
 }
@@ -113,132 +127,224 @@ __device__ inline void norm_point(const float *X, int64_t i, const double *cen, 
     z = (float)(X[3 * i + 2] - cen[3 * c + 2]) * s;
 }
 
-// Encoder forward over one tile of kT points of one cloud: per channel, the
-// tile's maximum activation and the lowest point index reaching it.
-__global__ void __launch_bounds__(kThreads) k_enc_forward(const float *__restrict__ xs, const float *__restrict__ xt,
-                                                        const int64_t *__restrict__ cr,
-                                                        const int32_t *__restrict__ toff, int nc,
-                                                        const double *__restrict__ cen,
-                                                        const float *__restrict__ scale,
-                                                        const float *__restrict__ params,
-                                                        const __bf16 *__restrict__ w2t,
-                                                        const __bf16 *__restrict__ w3t,
-                                                        float *__restrict__ pmax, int32_t *__restrict__ parg)
+// Encoder forward.  Persistent workgroups (kEncWaves waves) load the
+// bfloat16 weights into LDS once and then take tiles of kT points of one
+// cloud each; per tile and channel they write the tile's maximum activation
+// and, with ARG (training), the lowest point index reaching it (without it,
+// the tile's first point stands in).
+//
+// Matrix-core operands of v_mfma_f32_16x16x32_bf16 (wave of 64 lanes, g =
+// l / 16): lane l supplies A[l % 16][8 g + j] and B[8 g + j][l % 16] for
+// j < 8 and receives C[4 g + i][l % 16] for i < 4.  Each wave owns 64 rows
+// as four 16-row tiles m, and every weight fragment read from LDS feeds the
+// four of them.
+//   layer 2, transposed: C2^T[ch][row] = sum_k W2^T[ch][k] a1^T[k][row]; the
+//     B operand (a1 of row l % 16, channels 32 kb + 8 g + j) is computed by
+//     the lane itself from the point, so layer 1 never leaves registers;
+//   the lane then holds channels 16 t + 4 g + i of row l % 16 (tiles t < 8),
+//     which, paired as tiles (2 kb, 2 kb + 1), are the A operand of layer 3
+//     in slot order (w3_slot_channel); W3 is stored in that order;
+//   layer 3: C3[row][ch] = sum_k a2[row][k] W3[k][ch], 16 column tiles.
+template <bool ARG>
+__global__ void __launch_bounds__(kEncThreads) k_enc_forward(const float *__restrict__ xs, const float *__restrict__ xt,
+                                                           const int64_t *__restrict__ cr,
+                                                           const int32_t *__restrict__ toff, int nc, int ntile,
+                                                           const double *__restrict__ cen,
+                                                           const float *__restrict__ scale,
+                                                           const float *__restrict__ params,
+                                                           const __bf16 *__restrict__ w2t,
+                                                           const __bf16 *__restrict__ w3p,
+                                                           float *__restrict__ pmax, int32_t *__restrict__ parg)
 {
-    __shared__ __attribute__((aligned(16))) __bf16 sW2[kC2 * kP1];   // [n][k], k < 64
-    __shared__ __attribute__((aligned(16))) __bf16 sW3[kC3 * kP2];   // [n][k], k < 128
-    __shared__ __attribute__((aligned(16))) __bf16 sX1[kT * kP1];    // [row][k]
-    __shared__ __attribute__((aligned(16))) __bf16 sX2[kT * kP2];
-    __shared__ float sMax[4][kC3];
-    __shared__ int32_t sArg[4][kC3];
-    const int tile = blockIdx.x;
-    int c = 0;
-    {   // cloud of this tile: the last c with toff[c] <= tile
-        int lo = 0, hi = nc - 1;
-        while (lo < hi) {
-            int mid = (lo + hi + 1) >> 1;
-            if (toff[mid] <= tile) lo = mid;
-            else hi = mid - 1;
-        }
-        c = lo;
-    }
-    const float *X = cloud_xyz(xs, xt, c);
-    const int64_t p0 = cr[2 * c] + (int64_t)(tile - toff[c]) * kT;
-    const int64_t pend = cr[2 * c + 1];
+    __shared__ __attribute__((aligned(16))) __bf16 sW2[kC2 * kP1];   // W2^T: [ch][k], k < 64
+    __shared__ __attribute__((aligned(16))) __bf16 sW3[kC3 * kP2];   // W3: [n][slot], slot < 128
+    __shared__ __attribute__((aligned(16))) float4 sW1[kC1];         // (w1x, w1y, w1z, b1) per channel
+    __shared__ float sB2[kC2], sB3[kC3];
+    __shared__ float sMax[4 * kEncWaves][kC3 + 1];   // per wave and lane group g (padded rows)
+    __shared__ int32_t sArg[4 * kEncWaves][kC3 + 1];
+    __shared__ float sFinMax[kC3];                   // upper half of the combine
+    __shared__ int32_t sFinArg[kC3];
     const int t = threadIdx.x, w = t >> 6, l = __lane_id();
-    // weights into LDS (16-byte chunks)
-    for (int i = t; i < kC2 * (kC1 / 8); i += kThreads) {
+    const int lr = l & 15, g = l >> 4;
+    for (int i = t; i < kC2 * (kC1 / 8); i += kEncThreads) {
         int n = i / (kC1 / 8), k8 = i % (kC1 / 8);
         *reinterpret_cast<bf16x8 *>(&sW2[n * kP1 + 8 * k8]) = *reinterpret_cast<const bf16x8 *>(&w2t[n * kC1 + 8 * k8]);
     }
-    for (int i = t; i < kC3 * (kC2 / 8); i += kThreads) {
+    for (int i = t; i < kC3 * (kC2 / 8); i += kEncThreads) {
         int n = i / (kC2 / 8), k8 = i % (kC2 / 8);
-        *reinterpret_cast<bf16x8 *>(&sW3[n * kP2 + 8 * k8]) = *reinterpret_cast<const bf16x8 *>(&w3t[n * kC2 + 8 * k8]);
+        *reinterpret_cast<bf16x8 *>(&sW3[n * kP2 + 8 * k8]) = *reinterpret_cast<const bf16x8 *>(&w3p[n * kC2 + 8 * k8]);
     }
-    // layer 1 (float32): thread t handles row t % kT, channels 32 (t / kT) .. +31
     {
-        const float *W1 = params + kOffW1, *b1 = params + kOffB1;
-        const int row = t % kT, c0 = 32 * (t / kT);
-        const int64_t i = p0 + row;
-        float x = 0.f, y = 0.f, z = 0.f;
-        if (i < pend) norm_point(X, i, cen, scale[c], c, x, y, z);
-        for (int j = c0; j < c0 + 32; j++) {
-            float a = __fmaf_rn(z, W1[2 * kC1 + j], __fmaf_rn(y, W1[kC1 + j], __fmaf_rn(x, W1[j], b1[j])));
-            sX1[row * kP1 + j] = to_bf16(fmaxf(a, 0.f));
-        }
+        const float *W1 = params + kOffW1, *b1 = params + kOffB1, *b2 = params + kOffB2, *b3 = params + kOffB3;
+        for (int c = t; c < kC1; c += kEncThreads) sW1[c] = make_float4(W1[c], W1[kC1 + c], W1[2 * kC1 + c], b1[c]);
+        for (int c = t; c < kC2; c += kEncThreads) sB2[c] = b2[c];
+        for (int c = t; c < kC3; c += kEncThreads) sB3[c] = b3[c];
     }
     __syncthreads();
-    // Matrix-core operands of v_mfma_f32_16x16x32_bf16 (wave of 64 lanes):
-    // lane l supplies A[l % 16][8 (l / 16) + i] and B[8 (l / 16) + i][l % 16]
-    // for i < 8, and receives C[4 (l / 16) + i][l % 16] for i < 4.
-    const int r0 = 32 * w;                 // this wave's rows
-    const int lr = l & 15, lk = 8 * (l >> 4);
-    // layer 2: rows r0..r0+31 (two 16-row tiles) x 128 columns (8 tiles), K = 64
-    {
-        const float *b2 = params + kOffB2;
-        bf16x8 a[2][2];
-        for (int m = 0; m < 2; m++)
-            for (int ks = 0; ks < 2; ks++)
-                a[m][ks] = *reinterpret_cast<const bf16x8 *>(&sX1[(r0 + 16 * m + lr) * kP1 + 32 * ks + lk]);
-        for (int nt = 0; nt < kC2 / 16; nt++) {
-            f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
-            for (int ks = 0; ks < 2; ks++) {
-                bf16x8 b = *reinterpret_cast<const bf16x8 *>(&sW2[(16 * nt + lr) * kP1 + 32 * ks + lk]);
-                for (int m = 0; m < 2; m++) acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m][ks], b, acc[m], 0, 0, 0);
+    const int r0 = 64 * w;
+    // the tile's cloud and the raw coordinates of this lane's four rows;
+    // the next tile's are loaded while the current one is computed
+    auto cloud_of = [&](int tl) {
+        int lo = 0, hi = nc - 1;      // the last cloud c with toff[c] <= tl
+        while (lo < hi) {
+            int mid = (lo + hi + 1) >> 1;
+            if (toff[mid] <= tl) lo = mid;
+            else hi = mid - 1;
+        }
+        return lo;
+    };
+    auto load_rows = [&](int tl, int cl, float *px, float *py, float *pz) {
+        const float *X = cloud_xyz(xs, xt, cl);
+        const int64_t q0 = cr[2 * cl] + (int64_t)(tl - toff[cl]) * kT, qe = cr[2 * cl + 1];
+#pragma unroll
+        for (int m = 0; m < 4; m++) {
+            const int64_t i = q0 + r0 + 16 * m + lr;
+            const bool ok = i < qe;
+            px[m] = ok ? X[3 * i] : 0.f;
+            py[m] = ok ? X[3 * i + 1] : 0.f;
+            pz[m] = ok ? X[3 * i + 2] : 0.f;
+        }
+    };
+    int tile = blockIdx.x;
+    int c = tile < ntile ? cloud_of(tile) : 0;
+    float px[4], py[4], pz[4];
+    if (tile < ntile) load_rows(tile, c, px, py, pz);
+    for (; tile < ntile; tile += gridDim.x) {
+        const int tn = tile + gridDim.x;
+        int cn = c;
+        float nx[4], ny[4], nz[4];
+        if (tn < ntile) {
+            cn = cloud_of(tn);
+            load_rows(tn, cn, nx, ny, nz);
+        }
+        const int64_t p0 = cr[2 * c] + (int64_t)(tile - toff[c]) * kT;
+        const int64_t pend = cr[2 * c + 1];
+        // layer 1 into the B operand of layer 2: rows r0 + 16 m + lr,
+        // channels 32 kb + 8 g + j
+        bf16x8 x1[4][2];
+        {
+            const float s = scale[c];
+            const double cx = cen[3 * c], cy = cen[3 * c + 1], cz = cen[3 * c + 2];
+#pragma unroll
+            for (int m = 0; m < 4; m++) {
+                const bool ok = p0 + r0 + 16 * m + lr < pend;
+                const float x = ok ? (float)(px[m] - cx) * s : 0.f;
+                const float y = ok ? (float)(py[m] - cy) * s : 0.f;
+                const float z = ok ? (float)(pz[m] - cz) * s : 0.f;
+#pragma unroll
+                for (int kb = 0; kb < 2; kb++)
+#pragma unroll
+                    for (int j = 0; j < 8; j++) {
+                        const float4 wv = sW1[32 * kb + 8 * g + j];
+                        float a = __fmaf_rn(z, wv.z, __fmaf_rn(y, wv.y, __fmaf_rn(x, wv.x, wv.w)));
+                        x1[m][kb][j] = to_bf16(fmaxf(a, 0.f));
+                    }
             }
-            const int col = 16 * nt + lr;
-            const float bias = b2[col];
-            for (int m = 0; m < 2; m++)
+        }
+        // layer 2 (transposed): per 16-channel tile, bias, ReLU, bfloat16,
+        // stored straight into the layer-3 A operands (tiles 2 kb, 2 kb + 1)
+        bf16x8 x2[4][4];
+#pragma unroll
+        for (int tc = 0; tc < kC2 / 16; tc++) {
+            f32x4 acc[4];
+            const f32x4 b2v = {sB2[16 * tc + 4 * g], sB2[16 * tc + 4 * g + 1], sB2[16 * tc + 4 * g + 2],
+                               sB2[16 * tc + 4 * g + 3]};
+#pragma unroll
+            for (int m = 0; m < 4; m++) acc[m] = b2v;        // the bias starts the sum
+#pragma unroll
+            for (int kb = 0; kb < 2; kb++) {
+                const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&sW2[(16 * tc + lr) * kP1 + 32 * kb + 8 * g]);
+#pragma unroll
+                for (int m = 0; m < 4; m++) acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, x1[m][kb], acc[m], 0, 0, 0);
+            }
+#pragma unroll
+            for (int m = 0; m < 4; m++)
+#pragma unroll
                 for (int i = 0; i < 4; i++)
-                    sX2[(r0 + 16 * m + 4 * (l >> 4) + i) * kP2 + col] = to_bf16(fmaxf(acc[m][i] + bias, 0.f));
+                    x2[m][tc >> 1][4 * (tc & 1) + i] = to_bf16(fmaxf(acc[m][i], 0.f));
         }
-    }
-    __syncthreads();
-    // layer 3: rows r0..r0+31 x 256 columns (16 tiles), K = 128; ReLU, then
-    // the maximum over the wave's rows (rows past the cloud's end excluded)
-    {
-        const float *b3 = params + kOffB3;
-        bf16x8 a[2][4];
-        for (int m = 0; m < 2; m++)
-            for (int ks = 0; ks < 4; ks++)
-                a[m][ks] = *reinterpret_cast<const bf16x8 *>(&sX2[(r0 + 16 * m + lr) * kP2 + 32 * ks + lk]);
-        for (int nt = 0; nt < kC3 / 16; nt++) {
-            f32x4 acc[2] = {{0.f, 0.f, 0.f, 0.f}, {0.f, 0.f, 0.f, 0.f}};
-            for (int ks = 0; ks < 4; ks++) {
-                bf16x8 b = *reinterpret_cast<const bf16x8 *>(&sW3[(16 * nt + lr) * kP2 + 32 * ks + lk]);
-                for (int m = 0; m < 2; m++) acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[m][ks], b, acc[m], 0, 0, 0);
+        // layer 3 and, per channel, the maximum over this lane's 16 rows
+        // (ascending, first maximum kept; rows past the cloud's end, only in
+        // a cloud's last tile, are excluded).  Bias and ReLU are monotone,
+        // so both are applied after the maximum: the feature is unchanged,
+        // and its arg-max matters only where it is positive, where it is the
+        // arg-max of the pre-activation.
+        const bool all_valid = p0 + r0 + 63 < pend;     // uniform over the wave
+#pragma unroll 2
+        for (int n3 = 0; n3 < kC3 / 16; n3++) {
+            const int col = 16 * n3 + lr;
+            f32x4 acc[4];
+#pragma unroll
+            for (int m = 0; m < 4; m++) acc[m] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < 4; kb++) {
+                const bf16x8 bw = *reinterpret_cast<const bf16x8 *>(&sW3[(16 * n3 + lr) * kP2 + 32 * kb + 8 * g]);
+#pragma unroll
+                for (int m = 0; m < 4; m++) acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x2[m][kb], bw, acc[m], 0, 0, 0);
             }
-            const int col = 16 * nt + lr;
-            const float bias = b3[col];
             float best = -INFINITY;
             int32_t barg = 0x7fffffff;
-            for (int m = 0; m < 2; m++)
-                for (int i = 0; i < 4; i++) {
-                    const int row = r0 + 16 * m + 4 * (l >> 4) + i;
-                    if (p0 + row >= pend) continue;
-                    float v = fmaxf(acc[m][i] + bias, 0.f);
-                    if (v > best) { best = v; barg = row; }   // rows ascend: first maximum kept
+            if (all_valid) {
+                if (ARG) {
+#pragma unroll
+                    for (int m = 0; m < 4; m++)
+#pragma unroll
+                        for (int i = 0; i < 4; i++)
+                            if (acc[m][i] > best) { best = acc[m][i]; barg = r0 + 16 * m + 4 * g + i; }
+                } else {
+#pragma unroll
+                    for (int m = 0; m < 4; m++)
+                        best = fmaxf(fmaxf(best, fmaxf(acc[m][0], acc[m][1])), fmaxf(acc[m][2], acc[m][3]));
+                    barg = r0 + 4 * g;
                 }
-            for (int o = 16; o <= 32; o <<= 1) {
-                float ob = __shfl_xor(best, o);
-                int32_t oa = __shfl_xor(barg, o);
-                if (ob > best || (ob == best && oa < barg)) { best = ob; barg = oa; }
+            } else {
+#pragma unroll
+                for (int m = 0; m < 4; m++)
+#pragma unroll
+                    for (int i = 0; i < 4; i++) {
+                        const int row = r0 + 16 * m + 4 * g + i;
+                        if (p0 + row < pend && acc[m][i] > best) { best = acc[m][i]; barg = row; }
+                    }
             }
-            if (l < 16) {
-                sMax[w][col] = best;
-                sArg[w][col] = barg;
+            sMax[4 * w + g][col] = best + sB3[col];
+            sArg[4 * w + g][col] = barg;
+        }
+        __syncthreads();
+        // across lanes and waves, ties to the lower row: each column's 32
+        // partials in two halves of 16, one per thread
+        static_assert(kEncThreads == 2 * kC3, "two threads per column");
+        {
+            const int col = t & (kC3 - 1), h = t / kC3;
+            float best = -INFINITY;
+            int32_t barg = 0x7fffffff;
+#pragma unroll
+            for (int x = 0; x < 2 * kEncWaves; x++) {
+                const float v = sMax[2 * kEncWaves * h + x][col];
+                const int32_t a = sArg[2 * kEncWaves * h + x][col];
+                if (v > best || (v == best && a < barg)) { best = v; barg = a; }
+            }
+            if (h == 1) {
+                sFinMax[col] = best;
+                sFinArg[col] = barg;
+            }
+            __syncthreads();
+            if (h == 0) {
+                const float v = sFinMax[col];
+                const int32_t a = sFinArg[col];
+                if (v > best || (v == best && a < barg)) { best = v; barg = a; }
+                pmax[(int64_t)tile * kC3 + col] = fmaxf(best, 0.f);
+                parg[(int64_t)tile * kC3 + col] =
+                    barg == 0x7fffffff ? -1 : (int32_t)(p0 - cr[2 * c]) + (ARG ? barg : 0);
             }
         }
-    }
-    __syncthreads();
-    {   // across the 4 waves (rows ascend with the wave index)
-        const int col = t;
-        float best = sMax[0][col];
-        int32_t barg = sArg[0][col];
-        for (int x = 1; x < 4; x++)
-            if (sMax[x][col] > best) { best = sMax[x][col]; barg = sArg[x][col]; }
-        pmax[(int64_t)tile * kC3 + col] = best;
-        parg[(int64_t)tile * kC3 + col] = barg == 0x7fffffff ? -1 : (int32_t)(p0 - cr[2 * c]) + barg;
+        __syncthreads();
+#pragma unroll
+        for (int m = 0; m < 4; m++) {
+            px[m] = nx[m];
+            py[m] = ny[m];
+            pz[m] = nz[m];
+        }
+        c = cn;
     }
 }
 
@@ -652,6 +758,7 @@ void pose_net_carve(Carver &c, int np, int ntile, bool train, PoseNetStore &s)
     s.scale = c.take<float>(nc);
     s.w2t = c.take<__bf16>(kC1 * kC2);
     s.w3t = c.take<__bf16>(kC2 * kC3);
+    s.w3p = c.take<__bf16>(kC2 * kC3);
     s.pmax = c.take<float>((size_t)nt1 * kC3);
     s.parg = c.take<int32_t>((size_t)nt1 * kC3);
     s.feat = c.take<float>((size_t)nc * kC3);
@@ -681,24 +788,41 @@ hipError_t pose_net_stats(PoseNetStore &s, const float *xs, const float *xt, hip
     return hipGetLastError();
 }
 
-hipError_t pose_net_forward(PoseNetStore &s, const float *params, const float *xs, const float *xt, double *out_T,
-                            hipStream_t st)
+namespace {
+
+hipError_t forward_impl(PoseNetStore &s, const float *params, const float *xs, const float *xt, double *out_T,
+                        bool want_arg, hipStream_t st)
 {
     k_norm_stats<<<s.nc, 256, 0, st>>>(xs, xt, s.cr, s.nc, s.cen, s.scale);
-    k_weights_bf16<<<64, 256, 0, st>>>(params, s.w2t, s.w3t);
-    if (s.ntile > 0)
-        k_enc_forward<<<s.ntile, kThreads, 0, st>>>(xs, xt, s.cr, s.toff, s.nc, s.cen, s.scale, params, s.w2t,
-                                                    s.w3t, s.pmax, s.parg);
+    k_weights_bf16<<<64, 256, 0, st>>>(params, s.w2t, s.w3t, s.w3p);
+    if (s.ntile > 0) {
+        // one persistent workgroup per compute unit (LDS holds one), or fewer
+        const int grid = s.ntile < 256 ? s.ntile : 256;
+        if (want_arg)
+            k_enc_forward<true><<<grid, kEncThreads, 0, st>>>(xs, xt, s.cr, s.toff, s.nc, s.ntile, s.cen, s.scale,
+                                                              params, s.w2t, s.w3p, s.pmax, s.parg);
+        else
+            k_enc_forward<false><<<grid, kEncThreads, 0, st>>>(xs, xt, s.cr, s.toff, s.nc, s.ntile, s.cen, s.scale,
+                                                               params, s.w2t, s.w3p, s.pmax, s.parg);
+    }
     k_enc_pool<<<s.nc, kC3, 0, st>>>(s.pmax, s.parg, s.toff, s.nc, s.feat, s.arg);
     k_head_forward<<<s.np, kH, 0, st>>>(s.feat, s.cen, params, s.np, s.z4, s.q, out_T ? out_T : s.T);
     return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t pose_net_forward(PoseNetStore &s, const float *params, const float *xs, const float *xt, double *out_T,
+                            hipStream_t st)
+{
+    return forward_impl(s, params, xs, xt, out_T, false, st);
 }
 
 hipError_t pose_net_train(PoseNetStore &s, float *params, float *adam_m, float *adam_v, int step, float lr,
                           const float *xs, const float *xt, const double *label_T, const float *pair_w,
                           float *out_loss, hipStream_t st)
 {
-    hipError_t e = pose_net_forward(s, params, xs, xt, nullptr, st);
+    hipError_t e = forward_impl(s, params, xs, xt, nullptr, true, st);
     if (e != hipSuccess) return e;
     const int64_t E = (int64_t)s.nc * kC3;
     k_head_backward<<<s.np, kH, 0, st>>>(params, s.np, s.z4, s.q, label_T, pair_w, out_loss ? out_loss : s.loss,
