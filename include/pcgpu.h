@@ -385,12 +385,20 @@ pc_status icp_learned_batched(int mode, const float *params, int n_pairs,
  *                      the finest one whose levels hold at most
  *                      node_budget * n nodes (smaller: coarser leaves); used
  *                      by estimate_normals* and icp_point_to_plane*
- * Defaults: 128, 16, 1.  pc_set_tuning returns PC_EINVAL for other values.
+ *   sort_queries       0 or 1: ICP with nearest-neighbour correspondences
+ *                      visits the source points of each pair in the Morton
+ *                      order of their own cube (sorted once per call) rather
+ *                      than in input order, so neighbouring lanes search
+ *                      neighbouring cells; pays off when the input order is
+ *                      not already spatially coherent.  Changes only the
+ *                      order of the compensated sums.
+ * Defaults: 128, 16, 1, 1.  pc_set_tuning returns PC_EINVAL for other values.
  * ---------------------------------------------------------------------- */
 typedef struct {
     int32_t icp_block_threads;
     int32_t icp_leaf;
     float node_budget;
+    int32_t sort_queries;
 } pc_tuning;
 
 pc_status pc_set_tuning(const pc_tuning *t);

@@ -25,7 +25,7 @@ bool valid_offsets(const int64_t *off, int m)
 }
 
 // process-wide tuning of the ICP kernels and the pyramid (pc_set_tuning)
-pc_tuning g_tune = {128, 16, 1.0f};
+pc_tuning g_tune = {128, 16, 1.0f, 1};
 
 bool upload(void *dst, const void *src, size_t bytes, hipStream_t s)
 {
@@ -198,6 +198,7 @@ void tune(IcpStore &s)
     s.threads = g_tune.icp_block_threads;
     s.leaf = g_tune.icp_leaf;
     s.grid.node_budget = g_tune.node_budget;
+    s.sort_src = g_tune.sort_queries != 0;
 }
 
 // the single-pair carve, shared by the size query, the call and the history
@@ -768,6 +769,7 @@ pc_status pc_set_tuning(const pc_tuning *t)
     if (b != 64 && b != 128 && b != 256) return PC_EINVAL;
     if (l != 8 && l != 16 && l != 32) return PC_EINVAL;
     if (!(t->node_budget >= 0.125f && t->node_budget <= 1.0f)) return PC_EINVAL;
+    if (t->sort_queries != 0 && t->sort_queries != 1) return PC_EINVAL;
     g_tune = *t;
     return PC_OK;
 }

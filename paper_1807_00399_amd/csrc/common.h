@@ -280,6 +280,13 @@ struct GridStore {
 
 size_t grid_bytes(int64_t n, int n_clouds);
 void grid_carve(Carver &c, int64_t n, int n_clouds, GridStore &g);
+// the part of a grid store that sorting needs (grid_sort_points)
+void grid_carve_sort(Carver &c, int64_t n, int n_clouds, GridStore &g);
+// Sorts the points of every cloud by (cloud, Morton key of the cloud's
+// cube) into g.pts (float4, .w = original index); g.off as for grid_build.
+hipError_t grid_sort_points(GridStore &g, const float *xyz, hipStream_t s);
+// The same points in input order into g.pts (.w = index).
+hipError_t grid_pack_points(GridStore &g, const float *xyz, hipStream_t s);
 // Builds the pyramid over xyz (n x 3 float32, device), clouds split by
 // g.off (device, n_clouds + 1 entries, written by the caller beforehand or
 // by grid_set_single_cloud).  Asynchronous.

@@ -622,6 +622,28 @@ void grid_carve(Carver &c, int64_t n, int n_clouds, GridStore &g)
     g.hash = c.take<HSlot>(g.hash_slots_max);
 }
 
+void grid_carve_sort(Carver &c, int64_t n, int n_clouds, GridStore &g)
+{
+    int64_t nn = n > 0 ? n : 1;
+    int nc = n_clouds > 0 ? n_clouds : 1;
+    g = GridStore{};
+    g.n = n;
+    g.n_clouds = nc;
+    g.nblk_sort = (int)((nn + kSortTile - 1) / kSortTile);
+    g.node_budget = 1.0f;
+    g.params = c.take<GridParams>(nc);
+    g.off = c.take<int64_t>(nc + 1);
+    g.clev = c.take<int32_t>((size_t)nc * kLevels);
+    g.bbox = c.take<uint32_t>((size_t)nc * 6);
+    g.keys = c.take<uint64_t>(nn);
+    g.keys_alt = c.take<uint64_t>(nn);
+    g.idx = c.take<uint32_t>(nn);
+    g.idx_alt = c.take<uint32_t>(nn);
+    g.pts = c.take<float4>(nn);
+    g.radix_hist = c.take<uint32_t>((size_t)g.nblk_sort * kRadix);
+    g.radix_tot = c.take<uint32_t>(kRadix);
+}
+
 size_t grid_bytes(int64_t n, int n_clouds)
 {
     Carver c(nullptr, ~(size_t)0 >> 1);
@@ -636,7 +658,7 @@ hipError_t grid_set_single_cloud(GridStore &g, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t grid_build(GridStore &g, const float *xyz, hipStream_t s)
+hipError_t grid_sort_points(GridStore &g, const float *xyz, hipStream_t s)
 {
     const int64_t n = g.n;
     const int nc = g.n_clouds;
@@ -666,8 +688,37 @@ hipError_t grid_build(GridStore &g, const float *xyz, hipStream_t s)
             else { uint32_t *ti = ia; ia = ib2; ib2 = ti; }
         }
         k_gather_pts<<<blocks_for(n, T), T, 0, s>>>(xyz, g.idx, n, g.pts);
-        k_slev<<<blocks_for(n, T), T, 0, s>>>(g.keys, n, g.slev, g.clev);
     }
+    return hipGetLastError();
+}
+
+namespace {
+
+__global__ void k_pack_pts(const float *__restrict__ xyz, int64_t n, float4 *__restrict__ pts)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        pts[i] = make_float4(xyz[3 * i], xyz[3 * i + 1], xyz[3 * i + 2], __uint_as_float((uint32_t)i));
+}
+
+}  // namespace
+
+hipError_t grid_pack_points(GridStore &g, const float *xyz, hipStream_t s)
+{
+    if (g.n > 0) {
+        int b = blocks_for(g.n, 256);
+        k_pack_pts<<<b < 4096 ? b : 4096, 256, 0, s>>>(xyz, g.n, g.pts);
+    }
+    return hipGetLastError();
+}
+
+hipError_t grid_build(GridStore &g, const float *xyz, hipStream_t s)
+{
+    const int64_t n = g.n;
+    const int nc = g.n_clouds;
+    const int T = 256;
+    hipError_t e = grid_sort_points(g, xyz, s);
+    if (e != hipSuccess) return e;
+    if (n > 0) k_slev<<<blocks_for(n, T), T, 0, s>>>(g.keys, n, g.slev, g.clev);
     float budget = g.node_budget > 0.f && g.node_budget <= 1.f ? g.node_budget : 1.f;
     k_cloud_levels<<<blocks_for(nc, T), T, 0, s>>>(nc, g.clev, g.params, budget);
     k_layout<<<1, 1024, 0, s>>>(nc, g.clev, g.params, g.layout);

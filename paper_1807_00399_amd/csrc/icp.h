@@ -14,6 +14,7 @@ struct IcpState;
 // [goff[p], goff[p+1]).
 struct IcpStore {
     GridStore grid;     // pyramid over the targets, one cloud per pair
+    GridStore ssrc;     // the sources sorted by Morton key per pair (nearest association)
     float4 *nrm;        // target normals in sorted order
     int2 *prev;         // per source point: previous match (sorted position, node) or -1
     IcpState *st;       // per pair: pose and loop state
@@ -38,6 +39,7 @@ struct IcpStore {
     int width, height;
     float K[4];         // projective: fx, fy, cx, cy
     bool grid_built;    // the target pyramid is already built (by the caller, e.g. for its normals)
+    bool sort_src;      // nearest association: visit the sources in Morton order (else input order)
 };
 
 enum { kAssocNearest = 0, kAssocProjective = 1 };

@@ -316,7 +316,7 @@ __device__ inline void plane_values(float hx, float lx, float hy, float ly, floa
 //       |p' - q|^2, zeros; c = the target cloud's cube centre.
 template <int NT, int LEAF, int METRIC>
 __global__ void __launch_bounds__(NT)
-k_icp_accum(GridView g, const float *__restrict__ src, const int64_t *__restrict__ soff,
+k_icp_accum(GridView g, const float4 *__restrict__ srcp, const int64_t *__restrict__ soff,
             const int32_t *__restrict__ boff, int np, const float4 *__restrict__ nrm, int2 *__restrict__ prev,
             const IcpState *__restrict__ state, const float *__restrict__ dmaxv, int final_pass,
             float2 *__restrict__ part, uint32_t *__restrict__ pcnt, int nblk, float w_point, float w_plane)
@@ -345,7 +345,8 @@ k_icp_accum(GridView g, const float *__restrict__ src, const int64_t *__restrict
     int32_t j = -1;
     float hx = 0.f, lx = 0.f, hy = 0.f, ly = 0.f, hz = 0.f, lz = 0.f;   // double-float p'
     if (active) {
-        float px = src[3 * i], py = src[3 * i + 1], pz = src[3 * i + 2];
+        const float4 sp = srcp[i];
+        float px = sp.x, py = sp.y, pz = sp.z;
         df_row(Rh, Rl, px, py, pz, hx, lx);
         df_row(Rh + 4, Rl + 4, px, py, pz, hy, ly);
         df_row(Rh + 8, Rl + 8, px, py, pz, hz, lz);
@@ -875,6 +876,7 @@ void icp_carve(Carver &c, int np, int64_t ns, int64_t nt, int64_t nblk, int64_t 
     s.width = s.height = 0;
     s.K[0] = s.K[1] = s.K[2] = s.K[3] = 0.f;
     s.grid_built = false;
+    s.sort_src = true;
     s.iters_max = iters_max > 0 ? iters_max : 0;
     s.nrm = c.take<float4>(nt1);
     s.prev = c.take<int2>(ns1);
@@ -884,6 +886,8 @@ void icp_carve(Carver &c, int np, int64_t ns, int64_t nt, int64_t nblk, int64_t 
     s.goff = c.take<int32_t>(np1 + 1);
     s.dmax = c.take<float>(np1);
     s.maxit = c.take<int32_t>(np1);
+    grid_carve_sort(c, ns, np1, s.ssrc);
+    s.ssrc.off = s.soff;            // the sort splits the sources by pair
     s.part = c.take<float2>((size_t)(nblk > 0 ? nblk : 1) * kAcc);
     s.pcnt = c.take<uint32_t>((size_t)(nblk > 0 ? nblk : 1));
     s.gpart = c.take<float2>((size_t)(ngrp > 0 ? ngrp : 1) * kAcc);
@@ -906,7 +910,7 @@ hipError_t icp_layout_single(IcpStore &s, int64_t ns, int64_t nt, float dmax, in
 template <int NT, int LEAF, int M>
 static void launch_accum_t(IcpStore &s, const float *src, int fin, hipStream_t st)
 {
-    k_icp_accum<NT, LEAF, M><<<s.nblk, NT, 0, st>>>(s.grid.view(), src, s.soff, s.boff, s.np, s.nrm, s.prev,
+    k_icp_accum<NT, LEAF, M><<<s.nblk, NT, 0, st>>>(s.grid.view(), s.ssrc.pts, s.soff, s.boff, s.np, s.nrm, s.prev,
                                                     s.st, s.dmax, fin, s.part, s.pcnt, s.nblk, s.w_point,
                                                     s.w_plane);
 }
@@ -958,6 +962,11 @@ hipError_t icp_run(IcpStore &s, const float *src, int64_t ns, const float *tgt, 
             e = grid_build(s.grid, tgt, st);
             if (e != hipSuccess) return e;
         }
+        // queries in Morton order: the lanes of a wave search neighbouring
+        // cells in every iteration (a rigid motion keeps them together);
+        // otherwise in input order
+        e = s.sort_src ? grid_sort_points(s.ssrc, src, st) : grid_pack_points(s.ssrc, src, st);
+        if (e != hipSuccess) return e;
         if (tgt_n) {
             e = grid_gather3(s.grid, tgt_n, s.nrm, st);
             if (e != hipSuccess) return e;

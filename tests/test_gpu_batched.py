@@ -174,8 +174,9 @@ def test_batched_full_workload_sampled(gpu, oracle_mod):
 
 
 def test_tunings_give_the_same_results(gpu, oracle_mod, small_batch):
-    # every launch shape and pyramid depth finds the same correspondences;
-    # the block size only regroups the compensated sums (~1e-14 relative)
+    # every launch shape, pyramid depth and query order finds the same
+    # correspondences; the block size and the query order only regroup the
+    # compensated sums (~1e-14 relative)
     b = small_batch
     off = b.offsets
     nrms = np.vstack([oracle_mod.normals(w.target, w.k, (0, 0, 0))[0].astype(np.float32) for w in b.pairs])
@@ -185,9 +186,9 @@ def test_tunings_give_the_same_results(gpu, oracle_mod, small_batch):
     try:
         for tb in (64, 128, 256):
             for leaf in (8, 16, 32):
-                for nb in (0.25, 1.0):
-                    gpu.set_tuning(tb, leaf, nb)
-                    _say(f"tuning {tb} {leaf} {nb}")
+                for nb, sq in ((0.25, 0), (1.0, 1), (1.0, 0)):
+                    gpu.set_tuning(tb, leaf, nb, sq)
+                    _say(f"tuning {tb} {leaf} {nb} {sq}")
                     T, st = gpu.icp_point_to_plane_batched(*args)
                     T = T.cpu().numpy()
                     nn, _ = gpu.estimate_normals_batched(_dev(b.target), off, b.param("k").astype(np.int32))
@@ -195,7 +196,7 @@ def test_tunings_give_the_same_results(gpu, oracle_mod, small_batch):
                         ref_T, ref_st, ref_n = T, st, nn.cpu().numpy()
                         continue
                     assert np.array_equal(nn.cpu().numpy(), ref_n)
-                    assert np.abs(T - ref_T).max() < 1e-10, (tb, leaf, nb)
+                    assert np.abs(T - ref_T).max() < 1e-10, (tb, leaf, nb, sq)
                     assert [s["inliers"] for s in st] == [s["inliers"] for s in ref_st]
                     assert [s["status"] for s in st] == [s["status"] for s in ref_st]
     finally:
