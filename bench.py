@@ -321,7 +321,7 @@ def cpu_baseline_learned(b, gpu_T, budget_s):
             "gpu_learned_agrees_with_oracle_8_start": f"{agree}/{pairs}"}
 
 
-def learned_legs(steps, warmup):
+def learned_legs(steps, warmup, args=None):
     """The learned-initialiser workload through four starts: plain (identity),
     8-start, learned with 8-start fallback, learned only.  One step = target
     normals + registration of every pair.  Success = final pose within
@@ -358,6 +358,8 @@ def learned_legs(steps, warmup):
         return pcgpu.icp_learned_batched(code, params, src, off, tgt, nrm, off, cfg["d_max"], cfg["iters"],
                                          accept_rms=cfg["accept_rms"], workspace=ws_l, read_stats=False)
 
+    # one tuning for all legs: the learned path's (its fallback is 8-start ICP)
+    tuning = autotune_step(args, lambda: run("learned"), "pose_pairs_512", b.n) if args is not None else None
     legs = {}
     for mode in ("plain", "multi_start", "learned", "learned_only"):
         for _ in range(warmup):
@@ -393,7 +395,7 @@ def learned_legs(steps, warmup):
     info = {"workload": f"{b.name}: {m} exact-copy pairs of {cfg['n_points']} points, sphere+plane or room, "
                         f"rotation U(0, 90) deg, |t| U(0, 0.3); k={cfg['k']}, d_max {cfg['d_max']}, "
                         f"{cfg['iters']} iterations, accepted rms {cfg['accept_rms']}",
-            "pairs": m, "points_per_side": b.n, "legs": legs,
+            "pairs": m, "points_per_side": b.n, "legs": legs, "tuning": tuning,
             "learned_init_rotation_error_deg": {"median": float(np.median(e_init)),
                                                 "within_30": float(np.mean(e_init < 30))},
             "predict_ms": pred_s * 1e3}
@@ -401,7 +403,7 @@ def learned_legs(steps, warmup):
 
 
 def bench_learned(args):
-    info, b, learned_T, pred_s = learned_legs(args.steps, args.warmup)
+    info, b, learned_T, pred_s = learned_legs(args.steps, args.warmup, args)
     leg = info["legs"]["learned"]
     flops = ENC_FLOPS_PER_POINT * 2 * b.n
     achieved = flops / pred_s / 1e12
@@ -422,6 +424,7 @@ def bench_learned(args):
         "success": leg["success"],
         "learned_vs_plain": info["legs"],
         "learned_init_rotation_error_deg": info["learned_init_rotation_error_deg"],
+        "tuning": info["tuning"],
         "roofline": {"bound": "mfma", "achieved": achieved, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": achieved / BF16_PEAK_TFLOPS, "traffic": None,
                      "kernel": "pose_net_predict (encoder forward, both clouds of every pair)",
@@ -634,7 +637,7 @@ def main():
                      "algorithmic_bytes_per_launch": algo_bytes},
     }
     if not args.no_learned:
-        info = learned_legs(min(args.steps, 5), 1)[0]
+        info = learned_legs(min(args.steps, 5), 1, args)[0]
         out["learned_vs_plain"] = {"workload": info["workload"], "legs": info["legs"],
                                    "learned_init_rotation_error_deg": info["learned_init_rotation_error_deg"]}
     if not args.no_cpu_baseline:
