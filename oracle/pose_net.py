@@ -23,6 +23,10 @@ initialiser in front of the paper's ICP:
     summed; its gradient (loss_and_grad) is the dense chain rule over every
     point of every cloud, with the bfloat16 roundings taken as the identity
     (straight-through) and the rounded W2, W3 standing in for W2, W3.
+  * learned registration: ICP from the predicted pose; a result counts as
+    accepted when its status is converged or max-iterations, it has inliers
+    and its RMS is at most the accepted RMS; otherwise multi-start ICP
+    decides.
   * multi-start ICP: point-to-plane ICP (oracle.icp) from the identity
     rotation and from 7 rotations of 60 degrees about Fibonacci-sphere axes,
     each about the source centroid onto the target centroid; the result with
@@ -172,7 +176,12 @@ def loss_and_grad(params, pairs, labels, weights=None, round_bf16=True):
 
 
 def quat_to_R(q):
-    w, x, y, z = np.asarray(q, np.float64) / np.linalg.norm(q)
+    """Rotation of the unit quaternion q / |q| (w, x, y, z); q = 0 gives the identity."""
+    q = np.asarray(q, np.float64)
+    nq = np.linalg.norm(q)
+    if not nq > 0:
+        return np.eye(3)
+    w, x, y, z = q / nq
     return np.array([[w * w + x * x - y * y - z * z, 2 * (x * y - w * z), 2 * (x * z + w * y)],
                      [2 * (x * y + w * z), w * w - x * x + y * y - z * z, 2 * (y * z - w * x)],
                      [2 * (x * z - w * y), 2 * (y * z + w * x), w * w - x * x - y * y + z * z]])
@@ -239,3 +248,12 @@ def multi_start_icp(oracle_mod, src, tgt, tgt_normals, d_max, iters):
         if best is None or (r["inliers"] > 0 and (best["inliers"] == 0 or r["rms"] < best["rms"])):
             best, bi = r, i
     return best, bi
+
+
+def learned_icp(oracle_mod, params, src, tgt, tgt_normals, d_max, iters, accept_rms):
+    """(result dict, start index: -1 = the learned start was kept)."""
+    r = oracle_mod.icp(src, tgt, tgt_normals, predict(params, src, tgt), d_max, iters)
+    ok = r["status"] in (oracle_mod.ICP_CONVERGED, oracle_mod.ICP_MAXITER) and r["inliers"] > 0
+    if ok and r["rms"] <= accept_rms:
+        return r, -1
+    return multi_start_icp(oracle_mod, src, tgt, tgt_normals, d_max, iters)

@@ -244,3 +244,32 @@ def test_init_modes_are_consistent(gpu, oracle_mod):
         assert (int(bx[j]) == -1) == kept
         src_T = T2 if kept else Tm
         assert torch.equal(Tx[j], src_T[j])
+
+
+def test_learned_pipeline_matches_oracle(gpu, oracle_mod):
+    # trained weights on evaluation pairs: the same keep-or-fall-back
+    # decision as the oracle's composition, and the same pose
+    from paper_1807_00399_amd.train_pose_net import load_params
+    pairs = pose_pairs(4, 6, n_points=2048).pairs
+    params = load_params()
+    src, tgt, off = _pack(pairs)
+    nrm = _normals(oracle_mod, pairs)
+    d, it, acc = POSE_CONFIG["d_max"], POSE_CONFIG["iters"], POSE_CONFIG["accept_rms"]
+    T, st, start = gpu.icp_learned_batched(gpu.PC_INIT_LEARNED, _dev(params), _dev(src), off, _dev(tgt), _dev(nrm),
+                                           off, d, it, accept_rms=acc)
+    T, start = T.cpu().numpy(), start.cpu().numpy()
+    kept = 0
+    for j, p in enumerate(pairs):
+        tn = nrm[off[j]:off[j + 1]]
+        ro, bo = pn.learned_icp(oracle_mod, params, p.source, p.target, tn, float(np.float32(d)), it, acc)
+        _say(f"  {p.name}: oracle start {bo} rms {ro['rms']:.3g}; gpu start {start[j]} rms {st[j]['rms']:.3g}")
+        assert (start[j] == -1) == (bo == -1)
+        kept += int(bo == -1)
+        if bo == -1:
+            ea, et = pose_err(T[j], ro["T"])
+            assert ea <= 1e-5 and et <= 1e-6, (ea, et)
+        elif ro["rms"] < acc:
+            # multi-start: the pose is unique when a start converged
+            ea, et = pose_err(T[j], ro["T"])
+            assert ea <= 1e-5 and et <= 1e-6, (ea, et)
+    _say(f"  learned start kept on {kept} of {len(pairs)} pairs")

@@ -140,3 +140,29 @@ def test_gradient_zero_weight_and_exact_label():
     lab = [pn.axis_angle([0, 0, 1], 0.7) @ R for R in Rp]
     L, _ = pn.loss_and_grad(params, pairs[:1], lab[:1])
     assert abs(L - 8 * math.sin(0.35) ** 2) < 1e-12
+
+
+def test_learned_icp_keeps_or_falls_back(oracle_mod):
+    # a zero head output predicts the identity rotation about the centroids:
+    # on a pair turned by 5 degrees ICP converges from it (kept); turned by
+    # start 3 and 8 degrees more it does not, and multi-start takes over
+    from gen.scenes import room_scan
+    rng = rng_for(804)
+    pix = np.sort(rng.choice(640 * 480, size=3000, replace=False))
+    src = room_scan(rng, pixels=pix)
+    params = _params(6)
+    P = pn.unpack(params)
+    P["W5"][:] = 0.0
+    P["b5"][:] = 0.0
+    cs = src.astype(np.float64).mean(0)
+    for R, kept in ((pn.axis_angle([0.3, 1.0, 0.2], math.radians(5.0)), True),
+                    (pn.axis_angle(rng.standard_normal(3), math.radians(8.0)) @ pn.start_rotations()[3], False)):
+        T = np.eye(4)
+        T[:3, :3] = R
+        T[:3, 3] = cs - R @ cs
+        tgt = apply_rigid(T, src)
+        nrm = oracle_mod.normals(tgt, 10, (0, 0, 0))[0].astype(np.float32)
+        r, start = pn.learned_icp(oracle_mod, params, src, tgt, nrm, 0.3, 30, 0.004)
+        assert (start == -1) == kept, start
+        ea, et = pose_err(r["T"], T)
+        assert ea < 1e-6 and et < 1e-6 and r["rms"] < 1e-5
