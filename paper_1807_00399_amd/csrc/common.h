@@ -182,16 +182,30 @@ __device__ inline uint32_t lane_id() { return __lane_id(); }
 // Squared distance from q to a node's box (level-0 cells lo..hi per axis),
 // computed in float32 and shrunk by the binning margin and a relative factor,
 // so it never exceeds the float32 key of any point the node holds.
-__device__ inline float node_mindist2(const GridParams &P, const Node &nd, float qx, float qy, float qz)
+__device__ inline float box_mindist2(const GridParams &P, uint32_t bx, uint32_t by, uint32_t bz, float qx, float qy,
+                                    float qz)
 {
     float h = P.h0;
-    float lx = P.ox + (float)(nd.bx & 0xffffu) * h, hx = P.ox + (float)((nd.by >> 16) + 1u) * h;
-    float ly = P.oy + (float)(nd.bx >> 16) * h, hy = P.oy + (float)((nd.bz & 0xffffu) + 1u) * h;
-    float lz = P.oz + (float)(nd.by & 0xffffu) * h, hz = P.oz + (float)((nd.bz >> 16) + 1u) * h;
+    float lx = P.ox + (float)(bx & 0xffffu) * h, hx = P.ox + (float)((by >> 16) + 1u) * h;
+    float ly = P.oy + (float)(bx >> 16) * h, hy = P.oy + (float)((bz & 0xffffu) + 1u) * h;
+    float lz = P.oz + (float)(by & 0xffffu) * h, hz = P.oz + (float)((bz >> 16) + 1u) * h;
     float dx = fmaxf(fmaxf(lx - qx, qx - hx) - P.margin, 0.f);
     float dy = fmaxf(fmaxf(ly - qy, qy - hy) - P.margin, 0.f);
     float dz = fmaxf(fmaxf(lz - qz, qz - hz) - P.margin, 0.f);
     return (dx * dx + dy * dy + dz * dz) * (1.0f - 1e-5f);
+}
+
+__device__ inline float node_mindist2(const GridParams &P, const Node &nd, float qx, float qy, float qz)
+{
+    return box_mindist2(P, nd.bx, nd.by, nd.bz, qx, qy, qz);
+}
+
+// lower bound of node m's distance from its box alone (12 of its 32 bytes)
+__device__ inline float node_box_mindist2(const GridParams &P, const Node *node, uint32_t m, float qx, float qy,
+                                         float qz)
+{
+    const uint32_t *b = reinterpret_cast<const uint32_t *>(node + m) + 4;
+    return box_mindist2(P, b[0], b[1], b[2], qx, qy, qz);
 }
 
 // Blocks are dispatched round-robin over the 8 XCDs, each with its own L2:

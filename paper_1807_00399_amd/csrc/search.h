@@ -200,7 +200,7 @@ __device__ inline void dfs(const GridView &g, const GridParams &P, const Query &
             d[c] = INFINITY;
             id[c] = 0xffffffffu;
             if (c < (int)nc) {
-                d[c] = node_mindist2(P, g.node[h.first_child + c], q.x, q.y, q.z);
+                d[c] = node_box_mindist2(P, g.node, h.first_child + c, q.x, q.y, q.z);
                 id[c] = h.first_child + c;
             }
         }
@@ -227,7 +227,10 @@ __device__ inline int cover_level(const GridParams &P, float b2)
 }
 
 // Cover phase: every cell meeting the ball of the visitor's current radius,
-// nearest cell searched first.
+// nearest cell searched first.  Which of the (at most 8) cells meet the ball
+// is decided from their boxes before any memory access; their hash probes
+// go out four at a time, which keeps the live registers (and so the
+// occupancy of the kernels that search) lower than eight probes in flight.
 template <class V, int LEAF, int STK = kStack>
 __device__ inline void cover(const GridView &g, const GridParams &P, const Query &q, V &v, uint32_t *stk,
                              int stride, uint32_t xs, uint32_t xe)
@@ -245,42 +248,49 @@ __device__ inline void cover(const GridView &g, const GridParams &P, const Query
     int sp = 0;
     const HSlot *hs = g.hash + P.hash_base;
     if (hx - lx <= 1 && hy - ly <= 1 && hz - lz <= 1) {
-        // up to 8 cells: first hash probes issued together
-        uint64_t key[8];
-        uint32_t slot[8];
-        uint64_t hk[8];
-        int32_t node[8];
-#pragma unroll
-        for (int c = 0; c < 8; c++) {
-            uint32_t cx = lx + (c & 1), cy = ly + ((c >> 1) & 1), cz = lz + (c >> 2);
-            bool ok = cx <= hx && cy <= hy && cz <= hz;
-            key[c] = hash_key(l, morton3(cx, cy, cz));
-            slot[c] = hash_slot(key[c], P.hash_cap);
-            HSlot e = ok ? hs[slot[c]] : HSlot{kEmptyKey, 0u, 0u};
-            hk[c] = e.key;
-            node[c] = (e.key == key[c]) ? (int32_t)e.val : -1;
-        }
+        // up to 8 cells; only those meeting the ball are probed, nearest
+        // first, four hash probes in flight at a time
         float d[8];
         uint32_t id[8];
 #pragma unroll
         for (int c = 0; c < 8; c++) {
-            if (hk[c] != key[c] && hk[c] != kEmptyKey) node[c] = probe_from(g, P, key[c], slot[c]);
-            d[c] = INFINITY;
-            id[c] = 0xffffffffu;
-            if (node[c] >= 0) {
-                uint32_t cx = lx + (c & 1), cy = ly + ((c >> 1) & 1), cz = lz + (c >> 2);
-                float dc = cell_mindist2(P, q.x, q.y, q.z, cx, cy, cz, l);
-                if (dc <= b2) {
-                    d[c] = dc;
-                    id[c] = (uint32_t)node[c];
-                }
-            }
+            uint32_t cx = lx + (c & 1), cy = ly + ((c >> 1) & 1), cz = lz + (c >> 2);
+            bool ok = cx <= hx && cy <= hy && cz <= hz;
+            float dc = ok ? cell_mindist2(P, q.x, q.y, q.z, cx, cy, cz, l) : INFINITY;
+            d[c] = dc <= b2 ? dc : INFINITY;
+            id[c] = (uint32_t)c;
         }
         sort8(d, id);
+        int32_t node[8];
+#pragma unroll
+        for (int h = 0; h < 8; h += 4) {
+            if (!(d[h] < INFINITY)) {
+#pragma unroll
+                for (int u = 0; u < 4; u++) node[h + u] = -1;
+                continue;
+            }
+            uint64_t key[4];
+            uint32_t slot[4];
+            uint64_t hk[4];
+#pragma unroll
+            for (int u = 0; u < 4; u++) {
+                const uint32_t c = id[h + u];
+                uint32_t cx = lx + (c & 1), cy = ly + ((c >> 1) & 1), cz = lz + (c >> 2);
+                key[u] = hash_key(l, morton3(cx, cy, cz));
+                slot[u] = hash_slot(key[u], P.hash_cap);
+                HSlot e = d[h + u] < INFINITY ? hs[slot[u]] : HSlot{kEmptyKey, 0u, 0u};
+                hk[u] = e.key;
+                node[h + u] = (e.key == key[u]) ? (int32_t)e.val : -1;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; u++)
+                if (d[h + u] < INFINITY && hk[u] != key[u] && hk[u] != kEmptyKey)
+                    node[h + u] = probe_from(g, P, key[u], slot[u]);
+        }
 #pragma unroll
         for (int c = 7; c >= 0; c--) {
-            if (id[c] != 0xffffffffu) {
-                stk[sp * stride] = id[c];
+            if (node[c] >= 0) {
+                stk[sp * stride] = (uint32_t)node[c];
                 ++sp;
             }
         }
