@@ -3,7 +3,9 @@
 One step = one pair through the whole path: the target pyramid, PCA normals
 of the target, then point-to-plane ICP (the fixed iteration loop and the
 final statistics pass), in one call (icp_point_to_plane_with_normals, which
-builds the target pyramid once for both).  Inputs are resident in HBM before
+builds the target pyramid once for both).  The call launches kernels only;
+the timed steps replay it captured as a graph (--no-graph: eager launches,
+also reported as eager_pairs_per_s).  Inputs are resident in HBM before
 the timed region; the timed region is bracketed by device synchronisation.
 
     python bench.py [--steps K] [--warmup W] [--workload room|street|sphere|batch|projective|learned]
@@ -77,6 +79,8 @@ def parse():
                     help="time every tuning candidate even when the tuning cache has this workload")
     ap.add_argument("--no-compare", action="store_true",
                     help="batch workload: skip the one-call-per-pair comparison")
+    ap.add_argument("--no-graph", action="store_true",
+                    help="single-pair workloads: time eager launches instead of replays of a captured graph")
     ap.add_argument("--no-learned", action="store_true",
                     help="default run: skip the learned-initialiser comparison")
     ap.add_argument("--copy-probe", action="store_true",
@@ -584,12 +588,36 @@ def main():
         step()
     torch.cuda.synchronize()
 
-    # timed region: K whole steps
+    # K whole steps launched eagerly
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    el_eager = time.perf_counter() - t0
+    el = el_eager
+    launch = "eager"
+    if not args.no_graph:
+        # the step launches kernels only: captured once as a graph and
+        # replayed, the same kernels run without per-launch host overhead
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        for _ in range(args.warmup):
+            graph.replay()
+        torch.cuda.synchronize()
+        # timed region: K whole steps
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            graph.replay()
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        launch = "graph replay"
     ms_per_step = 1e3 * el / args.steps
     st = pcgpu.decode_stats(stats)
 
@@ -626,7 +654,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{w.name}: one pair, {w.n} points per cloud, k={w.k} normals, "
                                f"d_max {w.d_max}, {w.iters} iterations",
-                   "points_per_cloud": w.n, "k": w.k, "d_max": w.d_max, "iters": w.iters},
+                   "points_per_cloud": w.n, "k": w.k, "d_max": w.d_max, "iters": w.iters, "launch": launch},
+        "eager_pairs_per_s": args.steps / el_eager,
         "mpt_iter_per_s": w.n * w.iters / loop_s / 1e6,
         "loop_ms": loop_s * 1e3,
         "icp_status": st,

@@ -254,9 +254,12 @@ def icp_point_to_plane_with_normals(src: torch.Tensor, tgt: torch.Tensor, k: int
                                     init_T=None, max_corr_dist: float = 0.05, max_iters: int = 30,
                                     conv_tol: float = 0.0, return_normals: bool = False, stream=None,
                                     workspace: torch.Tensor | None = None, out_T: torch.Tensor | None = None,
-                                    out_stats: torch.Tensor | None = None, read_stats: bool = True):
+                                    out_stats: torch.Tensor | None = None, read_stats: bool = True,
+                                    out_normals: torch.Tensor | None = None):
     """Target normals (k, viewpoint) and point-to-plane ICP in one call over
-    one target pyramid.  Returns (T, stats) or (T, stats, normals)."""
+    one target pyramid.  Returns (T, stats) or (T, stats, normals).  With
+    preallocated workspace and outputs the call launches kernels only, so it
+    can be captured in a graph."""
     src = _pts(src, "src")
     tgt = _pts(tgt, "tgt")
     dev = src.device
@@ -265,7 +268,9 @@ def icp_point_to_plane_with_normals(src: torch.Tensor, tgt: torch.Tensor, k: int
         T0 = torch.as_tensor(init_T, dtype=torch.float64).reshape(4, 4).to(dev).contiguous()
     T = out_T if out_T is not None else torch.empty((4, 4), dtype=torch.float64, device=dev)
     stats = out_stats if out_stats is not None else torch.zeros(24, dtype=torch.uint8, device=dev)
-    nrm = torch.empty((tgt.shape[0], 3), dtype=torch.float32, device=dev) if return_normals else None
+    nrm = out_normals
+    if nrm is None and return_normals:
+        nrm = torch.empty((tgt.shape[0], 3), dtype=torch.float32, device=dev)
     vp = (ctypes.c_float * 3)(*[float(v) for v in viewpoint])
     need = lib.icp_point_to_plane_with_normals_workspace_size(src.shape[0], tgt.shape[0], int(max_iters))
     ws = workspace if workspace is not None else _ws.get(need, dev)
@@ -275,7 +280,7 @@ def icp_point_to_plane_with_normals(src: torch.Tensor, tgt: torch.Tensor, k: int
                                              _stream(stream))
     _check(st, "icp_point_to_plane_with_normals")
     out = (T, stats if not read_stats else decode_stats(stats))
-    return out + (nrm,) if return_normals else out
+    return out + (nrm,) if (return_normals or out_normals is not None) else out
 
 
 def _icp_variant(fn, what, src, tgt, tgt_normals, init_T, max_corr_dist, max_iters, conv_tol, stream, workspace,
