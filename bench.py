@@ -455,16 +455,13 @@ def bench_batch(args):
     m = b.n_pairs
     T = torch.empty((m, 4, 4), dtype=torch.float64, device=dev)
     stats = torch.zeros(24 * m, dtype=torch.uint8, device=dev)
-    ws_n = torch.empty(pcgpu.lib.estimate_normals_batched_workspace_size(m, off.ctypes.data), dtype=torch.uint8,
-                       device=dev)
-    ws_i = torch.empty(pcgpu.lib.icp_point_to_plane_batched_workspace_size(m, off.ctypes.data, off.ctypes.data,
-                                                                            int(it.max())),
-                       dtype=torch.uint8, device=dev)
+    ws_i = torch.empty(pcgpu.lib.icp_point_to_plane_with_normals_batched_workspace_size(
+        m, off.ctypes.data, off.ctypes.data, int(it.max())), dtype=torch.uint8, device=dev)
 
     def step():
-        nrm, _ = pcgpu.estimate_normals_batched(tgt, off, kc, curvature=False, workspace=ws_n)
-        pcgpu.icp_point_to_plane_batched(src, off, tgt, nrm, off, None, dm, it, workspace=ws_i, out_T=T,
-                                         out_stats=stats, read_stats=False)
+        # targets' normals and all registrations over one pyramid of the targets
+        pcgpu.icp_point_to_plane_with_normals_batched(src, off, tgt, off, kc, (0.0, 0.0, 0.0), None, dm, it,
+                                                      workspace=ws_i, out_T=T, out_stats=stats, read_stats=False)
 
     tuning = autotune_step(args, step, "uneven_pairs_256", b.n)
     for _ in range(args.warmup):
@@ -506,8 +503,8 @@ def bench_batch(args):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
         for j in range(seq_pairs):
-            nrm, _ = pcgpu.estimate_normals(tgts[j], int(kc[j]), curvature=False)
-            pcgpu.icp_point_to_plane(srcs[j], tgts[j], nrm, None, float(dm[j]), int(it[j]), read_stats=False)
+            pcgpu.icp_point_to_plane_with_normals(srcs[j], tgts[j], int(kc[j]), (0.0, 0.0, 0.0), None, float(dm[j]),
+                                                  int(it[j]), read_stats=False)
         torch.cuda.synchronize()
         seq_el = time.perf_counter() - t1
 
@@ -658,6 +655,8 @@ def main():
         "eager_pairs_per_s": args.steps / el_eager,
         "mpt_iter_per_s": w.n * w.iters / loop_s / 1e6,
         "loop_ms": loop_s * 1e3,
+        "kernel_us_by_iter": [round(float(x) * 1e3, 1) for x in
+                              np.median(np.array(kern_ms).reshape(-1, w.iters), axis=0)],
         "icp_status": st,
         "tuning": tuning,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

@@ -296,6 +296,22 @@ pc_status icp_point_to_plane_batched(int n_pairs, const float *src_xyz, const in
                                      double conv_tol, double *out_T, pc_icp_stats *out_stats,
                                      void *workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* icp_point_to_plane_with_normals on n_pairs independent pairs, packed as
+ * in icp_point_to_plane_batched: the targets' normals (k[p] neighbours for
+ * target p, host array; viewpoint shared) and the registrations share one
+ * pyramid over all targets.  Each pair's pose, statistics and normals equal
+ * those of icp_point_to_plane_with_normals on that pair alone.
+ *   out_normals  (tgt_off[n_pairs], 3) float32 (device), or NULL */
+size_t icp_point_to_plane_with_normals_batched_workspace_size(int n_pairs, const int64_t *src_off,
+                                                              const int64_t *tgt_off, int max_iters_max);
+pc_status icp_point_to_plane_with_normals_batched(int n_pairs, const float *src_xyz, const int64_t *src_off,
+                                                  const float *tgt_xyz, const int64_t *tgt_off,
+                                                  const int32_t *k, const float viewpoint[3],
+                                                  const double *init_T, const float *max_corr_dist,
+                                                  const int32_t *max_iters, double conv_tol, double *out_T,
+                                                  pc_icp_stats *out_stats, float *out_normals,
+                                                  void *workspace, size_t workspace_bytes, hipStream_t stream);
+
 /* ------------------------------------------------------------------------
  * Learned pose initialiser and multi-start ICP.  Not part of the paper's
  * method, whose ICP starts from a given pose (Section 3, "Iterative

@@ -325,9 +325,11 @@ pc_status icp_point_to_plane_with_normals(const float *src_xyz, int64_t n_src, c
     if (icp_layout_single(s, n_src, n_tgt, max_corr_dist, max_iters, stream) != hipSuccess) return PC_EDEVICE;
     // one pyramid over the target serves its normals and the correspondences
     if (grid_build(s.grid, tgt_xyz, stream) != hipSuccess) return PC_EDEVICE;
-    if (n_tgt > 0 && normals_run(s.grid, tgt_xyz, k, nullptr, viewpoint, nb, nullptr, stream) != hipSuccess)
+    if (n_tgt > 0 &&
+        normals_run(s.grid, tgt_xyz, k, nullptr, viewpoint, nb, nullptr, stream, INFINITY, 0, s.nrm) != hipSuccess)
         return PC_EDEVICE;
     s.grid_built = true;
+    s.nrm_ready = true;
     hipError_t e = icp_run(s, src_xyz, n_src, tgt_xyz, nb, init_T, conv_tol, out_T, out_stats, stream);
     return e == hipSuccess ? PC_OK : PC_EDEVICE;
 }
@@ -456,6 +458,74 @@ pc_status icp_point_to_plane_batched(int n_pairs, const float *src_xyz, const in
         return PC_EWORKSPACE;
     return batched_core(n_pairs, src_xyz, src_off, tgt_xyz, tgt_normals, tgt_off, init_T, max_corr_dist, max_iters,
                         iters_max, conv_tol, out_T, out_stats, workspace, workspace_bytes, stream);
+}
+
+size_t icp_point_to_plane_with_normals_batched_workspace_size(int n_pairs, const int64_t *src_off,
+                                                              const int64_t *tgt_off, int max_iters_max)
+{
+    if (n_pairs < 1 || max_iters_max < 0 || !valid_offsets(src_off, n_pairs) || !valid_offsets(tgt_off, n_pairs))
+        return 0;
+    Carver c(nullptr, ~(size_t)0 >> 1);
+    IcpStore s;
+    carve_batched(c, n_pairs, src_off, tgt_off, max_iters_max, s, nullptr, nullptr);
+    c.take<float>((size_t)3 * (tgt_off[n_pairs] > 0 ? tgt_off[n_pairs] : 1));
+    c.take<int32_t>((size_t)n_pairs);
+    return c.used();
+}
+
+pc_status icp_point_to_plane_with_normals_batched(int n_pairs, const float *src_xyz, const int64_t *src_off,
+                                                  const float *tgt_xyz, const int64_t *tgt_off, const int32_t *k,
+                                                  const float viewpoint[3], const double *init_T,
+                                                  const float *max_corr_dist, const int32_t *max_iters,
+                                                  double conv_tol, double *out_T, pc_icp_stats *out_stats,
+                                                  float *out_normals, void *workspace, size_t workspace_bytes,
+                                                  hipStream_t stream)
+{
+    if (n_pairs < 1 || !valid_offsets(src_off, n_pairs) || !valid_offsets(tgt_off, n_pairs)) return PC_EINVAL;
+    if (!max_corr_dist || !max_iters || !k || !viewpoint) return PC_EINVAL;
+    int iters_max = 0, k_max = 1;
+    for (int p = 0; p < n_pairs; p++) {
+        if (max_iters[p] < 0 || !(max_corr_dist[p] > 0.f) || !isfinite(max_corr_dist[p])) return PC_EINVAL;
+        iters_max = max_iters[p] > iters_max ? max_iters[p] : iters_max;
+        const int64_t nc = tgt_off[p + 1] - tgt_off[p];
+        if (k[p] < 1 || k[p] > PCGPU_KMAX || (nc > 0 && k[p] > nc)) return PC_EINVAL;
+        k_max = k[p] > k_max ? k[p] : k_max;
+    }
+    if (!isfinite(viewpoint[0]) || !isfinite(viewpoint[1]) || !isfinite(viewpoint[2])) return PC_EINVAL;
+    if (!(conv_tol >= 0.0) || !isfinite(conv_tol)) return PC_EINVAL;
+    const int64_t ns = src_off[n_pairs], nt = tgt_off[n_pairs];
+    if (!out_T || !workspace) return PC_EINVAL;
+    if ((ns > 0 && !src_xyz) || (nt > 0 && !tgt_xyz)) return PC_EINVAL;
+    if (!aligned(src_xyz, 4) || !aligned(tgt_xyz, 4) || !aligned(out_normals, 4) || !aligned(init_T, 8) ||
+        !aligned(out_T, 8) || !aligned(out_stats, 8) || !aligned(workspace, 256))
+        return PC_EINVAL;
+    if (workspace_bytes < icp_point_to_plane_with_normals_batched_workspace_size(n_pairs, src_off, tgt_off, iters_max))
+        return PC_EWORKSPACE;
+    Carver c(workspace, workspace_bytes);
+    IcpStore s;
+    std::vector<int32_t> boff, goff;
+    carve_batched(c, n_pairs, src_off, tgt_off, iters_max, s, &boff, &goff);
+    float *nb = c.take<float>((size_t)3 * (nt > 0 ? nt : 1));
+    int32_t *kc = c.take<int32_t>((size_t)n_pairs);
+    if (!c.ok) return PC_EWORKSPACE;
+    if (out_normals) nb = out_normals;
+    if (!upload(s.soff, src_off, sizeof(int64_t) * (n_pairs + 1), stream) ||
+        !upload(s.grid.off, tgt_off, sizeof(int64_t) * (n_pairs + 1), stream) ||
+        !upload(s.boff, boff.data(), sizeof(int32_t) * (n_pairs + 1), stream) ||
+        !upload(s.goff, goff.data(), sizeof(int32_t) * (n_pairs + 1), stream) ||
+        !upload(s.dmax, max_corr_dist, sizeof(float) * n_pairs, stream) ||
+        !upload(s.maxit, max_iters, sizeof(int32_t) * n_pairs, stream) ||
+        !upload(kc, k, sizeof(int32_t) * n_pairs, stream))
+        return PC_EDEVICE;
+    // one pyramid over the targets serves their normals and the correspondences
+    if (grid_build(s.grid, tgt_xyz, stream) != hipSuccess) return PC_EDEVICE;
+    if (nt > 0 &&
+        normals_run(s.grid, tgt_xyz, k_max, kc, viewpoint, nb, nullptr, stream, INFINITY, 0, s.nrm) != hipSuccess)
+        return PC_EDEVICE;
+    s.grid_built = true;
+    s.nrm_ready = true;
+    hipError_t e = icp_run(s, src_xyz, ns, tgt_xyz, nb, init_T, conv_tol, out_T, out_stats, stream);
+    return e == hipSuccess ? PC_OK : PC_EDEVICE;
 }
 
 // ---------------------------------------------------------------------------

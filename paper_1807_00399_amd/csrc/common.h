@@ -56,13 +56,13 @@ struct NodeHdr {
 __host__ __device__ inline uint32_t node_nchild(const NodeHdr &h) { return h.meta & 0xffu; }
 __host__ __device__ inline int node_level(const NodeHdr &h) { return (int)(h.meta >> 8); }
 
-// One 32-byte node record: header plus the tight box of the node's points in
-// level-0 grid cells (inclusive), x | y << 16 packed: bx = lo.x,lo.y;
-// by = lo.z,hi.x; bz = hi.y,hi.z.  One load brings everything a traversal
-// step needs.
+// One 48-byte node record: header plus the tight float32 box of the node's
+// points (the minimum and maximum of their coordinates).  One load brings
+// everything a traversal step needs.
 struct Node {
     NodeHdr h;
-    uint32_t bx, by, bz, pad;
+    float lo[3], hi[3];
+    uint32_t pad[2];
 };
 
 // Hash slot: (level << 48 | cell key) and node index in one 16-byte load.
@@ -113,16 +113,27 @@ __device__ inline uint64_t hash_key(int level, uint64_t cellkey)
     return ((uint64_t)level << 48) | cellkey;
 }
 
-// home slot of a key in a region of `cap` slots: the 64-bit splitmix64
-// finaliser, then its high 32 bits scaled to [0, cap) (no power-of-two size)
+// home slot of a key in a region of `cap` slots: the two 32-bit halves
+// mixed by multiplications and xor-shifts (32-bit arithmetic only), then
+// scaled to [0, cap) (no power-of-two size)
 __device__ inline uint32_t hash_slot(uint64_t k, uint32_t cap)
 {
-    k ^= k >> 30;
-    k *= 0xbf58476d1ce4e5b9ull;
-    k ^= k >> 27;
-    k *= 0x94d049bb133111ebull;
-    k ^= k >> 31;
-    return (uint32_t)(((k >> 32) * (uint64_t)cap) >> 32);
+    uint32_t h = (uint32_t)k * 0x9e3779b1u ^ ((uint32_t)(k >> 32) + 0x7f4a7c15u) * 0x85ebca77u;
+    h ^= h >> 15;
+    h *= 0x2c1b3c6du;
+    h ^= h >> 12;
+    h *= 0x297a2d39u;
+    h ^= h >> 15;
+    return (uint32_t)(((uint64_t)h * cap) >> 32);
+}
+
+// Morton key of the cell one step up along x (axis 0), y (1) or z (2):
+// the axis bits are incremented in place (dilated-integer addition)
+template <int AXIS>
+__device__ inline uint64_t morton_inc(uint64_t m)
+{
+    constexpr uint64_t mask = 0x249249249249ull << AXIS;
+    return (m & ~mask) | (((m | ~mask) + (1ull << AXIS)) & mask);
 }
 
 __device__ inline uint32_t next_slot(uint32_t s, uint32_t cap) { return (s + 1 == cap) ? 0u : s + 1; }
@@ -179,33 +190,32 @@ __device__ inline float ord2f(uint32_t u)
 
 __device__ inline uint32_t lane_id() { return __lane_id(); }
 
-// Squared distance from q to a node's box (level-0 cells lo..hi per axis),
-// computed in float32 and shrunk by the binning margin and a relative factor,
-// so it never exceeds the float32 key of any point the node holds.
-__device__ inline float box_mindist2(const GridParams &P, uint32_t bx, uint32_t by, uint32_t bz, float qx, float qy,
-                                    float qz)
+// Squared distance from q to a box, evaluated like knn_key (per-axis
+// differences, then fma in z, y, x order).  Rounding to nearest is monotone,
+// so for every point p inside the box each rounded per-axis difference is at
+// least the box's in magnitude and the result never exceeds knn_key(p, q):
+// a box is skipped (distance > bound) only when every point in it is.
+__device__ inline float box_key(float lx, float ly, float lz, float hx, float hy, float hz, float qx, float qy,
+                                float qz)
 {
-    float h = P.h0;
-    float lx = P.ox + (float)(bx & 0xffffu) * h, hx = P.ox + (float)((by >> 16) + 1u) * h;
-    float ly = P.oy + (float)(bx >> 16) * h, hy = P.oy + (float)((bz & 0xffffu) + 1u) * h;
-    float lz = P.oz + (float)(by & 0xffffu) * h, hz = P.oz + (float)((bz >> 16) + 1u) * h;
-    float dx = fmaxf(fmaxf(lx - qx, qx - hx) - P.margin, 0.f);
-    float dy = fmaxf(fmaxf(ly - qy, qy - hy) - P.margin, 0.f);
-    float dz = fmaxf(fmaxf(lz - qz, qz - hz) - P.margin, 0.f);
-    return (dx * dx + dy * dy + dz * dz) * (1.0f - 1e-5f);
+    float dx = fmaxf(fmaxf(lx - qx, qx - hx), 0.f);
+    float dy = fmaxf(fmaxf(ly - qy, qy - hy), 0.f);
+    float dz = fmaxf(fmaxf(lz - qz, qz - hz), 0.f);
+    return __fmaf_rn(dz, dz, __fmaf_rn(dy, dy, __fmul_rn(dx, dx)));
 }
 
-__device__ inline float node_mindist2(const GridParams &P, const Node &nd, float qx, float qy, float qz)
+__device__ inline float node_mindist2(const Node &nd, float qx, float qy, float qz)
 {
-    return box_mindist2(P, nd.bx, nd.by, nd.bz, qx, qy, qz);
+    return box_key(nd.lo[0], nd.lo[1], nd.lo[2], nd.hi[0], nd.hi[1], nd.hi[2], qx, qy, qz);
 }
 
-// lower bound of node m's distance from its box alone (12 of its 32 bytes)
-__device__ inline float node_box_mindist2(const GridParams &P, const Node *node, uint32_t m, float qx, float qy,
-                                         float qz)
+// distance of node m from its box alone (24 of its 48 bytes)
+__device__ inline float node_box_mindist2(const Node *node, uint32_t m, float qx, float qy, float qz)
 {
-    const uint32_t *b = reinterpret_cast<const uint32_t *>(node + m) + 4;
-    return box_mindist2(P, b[0], b[1], b[2], qx, qy, qz);
+    const char *r = reinterpret_cast<const char *>(node + m);
+    const float4 a = *reinterpret_cast<const float4 *>(r + 16);   // lo x, y, z, hi x
+    const float2 b = *reinterpret_cast<const float2 *>(r + 32);   // hi y, z
+    return box_key(a.x, a.y, a.z, a.w, b.x, b.y, qx, qy, qz);
 }
 
 // Blocks are dispatched round-robin over the 8 XCDs, each with its own L2:

@@ -551,34 +551,33 @@ __global__ void k_nodes_finish(const GridParams *__restrict__ P, const GridLayou
     }
 }
 
-// tight boxes of the level-l nodes in level-0 cells: from their points'
-// cells at their cloud's finest level, from their children's boxes above it
+// tight float32 boxes of the level-l nodes: from their points at their
+// cloud's finest level, from their children's boxes above it
 __global__ void k_node_boxes(const GridParams *__restrict__ P, const GridLayout *__restrict__ L, int l,
-                             const uint64_t *__restrict__ keys, Node *__restrict__ nodes)
+                             const uint64_t *__restrict__ keys, const float4 *__restrict__ pts, Node *__restrict__ nodes)
 {
     int32_t off = L->level_off[l], end = off + L->level_count[l];
     for (int32_t m = off + blockIdx.x * blockDim.x + threadIdx.x; m < end; m += gridDim.x * blockDim.x) {
         NodeHdr h = nodes[m].h;
-        uint32_t lx = 0xffffu, ly = 0xffffu, lz = 0xffffu, hx = 0, hy = 0, hz = 0;
+        float lx = INFINITY, ly = INFINITY, lz = INFINITY, hx = -INFINITY, hy = -INFINITY, hz = -INFINITY;
         if (l == P[key_cloud(keys[h.start])].lmin) {
             for (uint32_t j = h.start; j < h.start + h.count; j++) {
-                uint64_t k = keys[j];
-                uint32_t x = compact3(k), y = compact3(k >> 1), z = compact3(k >> 2);
-                lx = min(lx, x); ly = min(ly, y); lz = min(lz, z);
-                hx = max(hx, x); hy = max(hy, y); hz = max(hz, z);
+                float4 p = pts[j];
+                lx = fminf(lx, p.x); ly = fminf(ly, p.y); lz = fminf(lz, p.z);
+                hx = fmaxf(hx, p.x); hy = fmaxf(hy, p.y); hz = fmaxf(hz, p.z);
             }
         } else {
             uint32_t nc = node_nchild(h);
             for (uint32_t c = 0; c < nc; c++) {
                 const Node &ch = nodes[h.first_child + c];
-                lx = min(lx, ch.bx & 0xffffu); ly = min(ly, ch.bx >> 16); lz = min(lz, ch.by & 0xffffu);
-                hx = max(hx, ch.by >> 16); hy = max(hy, ch.bz & 0xffffu); hz = max(hz, ch.bz >> 16);
+                lx = fminf(lx, ch.lo[0]); ly = fminf(ly, ch.lo[1]); lz = fminf(lz, ch.lo[2]);
+                hx = fmaxf(hx, ch.hi[0]); hy = fmaxf(hy, ch.hi[1]); hz = fmaxf(hz, ch.hi[2]);
             }
         }
-        nodes[m].bx = lx | (ly << 16);
-        nodes[m].by = lz | (hx << 16);
-        nodes[m].bz = hy | (hz << 16);
-        nodes[m].pad = 0;
+        Node &o = nodes[m];
+        o.lo[0] = lx; o.lo[1] = ly; o.lo[2] = lz;
+        o.hi[0] = hx; o.hi[1] = hy; o.hi[2] = hz;
+        o.pad[0] = o.pad[1] = 0u;
     }
 }
 
@@ -736,7 +735,7 @@ hipError_t grid_build(GridStore &g, const float *xyz, hipStream_t s)
         int bxb = blocks_for(n, T);
         if (bxb > 2048) bxb = 2048;
         for (int l = 0; l < kLevels; l++)
-            k_node_boxes<<<bxb, T, 0, s>>>(g.params, g.layout, l, g.keys, g.node);
+            k_node_boxes<<<bxb, T, 0, s>>>(g.params, g.layout, l, g.keys, g.pts, g.node);
     }
     return hipGetLastError();
 }

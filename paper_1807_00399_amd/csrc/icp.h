@@ -15,7 +15,7 @@ struct IcpState;
 struct IcpStore {
     GridStore grid;     // pyramid over the targets, one cloud per pair
     GridStore ssrc;     // the sources sorted by Morton key per pair (nearest association)
-    float4 *nrm;        // target normals in sorted order
+    float4 *nrm;        // target normals in sorted order; w: nearest-other-point gap (squared)
     int2 *prev;         // per source point: previous match (sorted position, node) or -1
     IcpState *st;       // per pair: pose and loop state
     int64_t *soff;      // source offsets (np + 1)
@@ -39,6 +39,7 @@ struct IcpStore {
     int width, height;
     float K[4];         // projective: fx, fy, cx, cy
     bool grid_built;    // the target pyramid is already built (by the caller, e.g. for its normals)
+    bool nrm_ready;     // nrm already holds the sorted normals and gaps (written with the normals)
     bool sort_src;      // nearest association: visit the sources in Morton order (else input order)
 };
 
@@ -66,8 +67,11 @@ hipError_t knn_run(const GridStore &g, const float *qry, int64_t nq, int k, int3
 // k_max: the largest k of any cloud; kc: per-cloud k (device), or null to
 // use k_max for all; cap2: inclusive key limit of neighbours (hybrid), with
 // fewer than min_pts neighbours giving normal 0
+// srt (optional, plain k-NN only): the normals in sorted order with the
+// nearest-other-point gap in w, as the ICP correspondence search reads them
 hipError_t normals_run(const GridStore &g, const float *xyz, int k_max, const int32_t *kc, const float *vp,
-                       float *on, float *oc, hipStream_t s, float cap2 = INFINITY, int min_pts = 0);
+                       float *on, float *oc, hipStream_t s, float cap2 = INFINITY, int min_pts = 0,
+                       float4 *srt = nullptr);
 // radius neighbourhoods: every point with key <= r2
 hipError_t normals_radius_run(const GridStore &g, float r2, const float *vp, float *on, float *oc, hipStream_t s);
 

@@ -79,6 +79,7 @@ __device__ inline CSum csum_merge(CSum a, CSum b)
 // queries (close runners-up or a distance at d_max) are re-decided in
 // float64 with the same expressions as the float64 definition.
 struct NearBand {
+    static constexpr bool kSortChildren = false;
     uint64_t best;       // (key bits << 32) | original index
     int32_t best_pos;    // sorted position, -1 if none within the cap
     uint32_t best_node;  // node whose scan produced best_pos
@@ -122,6 +123,7 @@ struct NearBand {
 // float64 re-decision: nearest point by |p' - q|^2 in float64 among those
 // with |p' - q|^2 <= d_max^2, ties to the lower original index
 struct Near64 {
+    static constexpr bool kSortChildren = false;
     double px, py, pz, dmax2, best;
     uint32_t best_orig;
     int32_t best_pos;
@@ -216,6 +218,39 @@ __global__ void k_fill_i32(int32_t *p, int64_t n, int32_t v)
 {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
         p[i] = v;
+}
+
+// Target normals in sorted order (zero when none are given), with w a lower
+// bound of the squared distance from the point to the nearest other point of
+// its cloud: 0 when it has an exact duplicate, +inf when it is alone.  No
+// other target point can be nearer to anything within half that distance of
+// the point.
+constexpr int kGapThreads = 256;
+__global__ void __launch_bounds__(kGapThreads) k_nrm_gap(GridView g, int64_t n_all, const float *__restrict__ tgt_n,
+                                                        float4 *__restrict__ nrm)
+{
+    __shared__ uint32_t stk[kStack * kGapThreads];
+    const int64_t s = xcd_block(blockIdx.x, gridDim.x) * (int64_t)kGapThreads + threadIdx.x;
+    if (s >= n_all) return;
+    const GridParams P = g.params[key_cloud(g.keys[s])];
+    const float4 p = g.pts[s];
+    const uint32_t qi = __float_as_uint(p.w);
+    TopK<2> top;
+    top.init(2);
+    Query q{p.x, p.y, p.z};
+    search<TopK<2>, 16>(g, P, q, top, 2, stk + threadIdx.x, kGapThreads);
+    // the point itself (or an exact duplicate) is first; the second key is
+    // the squared distance to the nearest other point, rounded to float32
+    // (relative error below 2^-21)
+    const float gap = top.h[1] == ~0ull ? INFINITY
+                                         : __uint_as_float((uint32_t)(top.h[1] >> 32)) * (1.f - 1.f / (1 << 20));
+    float4 o = make_float4(0.f, 0.f, 0.f, gap);
+    if (tgt_n) {
+        o.x = tgt_n[3 * (int64_t)qi];
+        o.y = tgt_n[3 * (int64_t)qi + 1];
+        o.z = tgt_n[3 * (int64_t)qi + 2];
+    }
+    nrm[s] = o;
 }
 
 // pair owning block b (or group b) for block offsets off[0..np]
@@ -356,40 +391,57 @@ k_icp_accum(GridView g, const float4 *__restrict__ srcp, const int64_t *__restri
         float dlt = fmaxf(fmaxf(fabsf(q.x), fabsf(q.y)), fabsf(q.z)) * (1.0f / (1 << 22)) +
                     (fabsf(px) + fabsf(py) + fabsf(pz) + fabsf(Rh[3]) + fabsf(Rh[7]) + fabsf(Rh[11])) *
                         (1.0f / (1 << 30)) + 1e-30f;
+        int2 pv = prev[i];          // previous match (sorted position) and its node
+        bool done = false;
         NearBand v;
         v.init(dmax2, dlt);
-        int2 pv = prev[i];          // previous best (sorted position) and its node
-        bool done = false;
+        bool searched = false;
         if (pv.x >= 0) {
-            float4 p0 = g.pts[pv.x];
-            Node nm = g.node[pv.y];     // issued with p0: one round trip for both
+            // Previous match q0 (its normal's w: a lower bound of the squared
+            // distance from q0 to any other target point of the cloud).  When
+            // |p' - q0| is below half that distance, q0 is strictly the
+            // nearest target point: no search.
+            const float4 p0 = g.pts[pv.x];
+            const float4 n0 = nrm[pv.x];
             v.visit(q.x, q.y, q.z, (uint32_t)pv.x, p0, (uint32_t)pv.y);
-            if (v.best_pos >= 0) done = search_in_node(g, P, q, v, (uint32_t)pv.y, nm, p0);
-        }
-        if (!done) search<NearBand, LEAF, kStackNear>(g, P, q, v, 1, stk + threadIdx.x, NT);
-        prev[i] = v.best_pos >= 0 ? make_int2(v.best_pos, (int32_t)v.best_node) : make_int2(-1, -1);
-        if (v.best_pos >= 0) {
-            float b = v.best_key();
-            float e = v.err(b);
-            bool sure_in = b + e < dmax2 * (1.0f - 1.0f / (1 << 22));
-            bool sure_out = b - e > dmax2 * (1.0f + 1.0f / (1 << 22));
-            bool sure_nn = v.second > b + 2.f * e;
-            if (sure_nn && sure_in) {
-                j = v.best_pos;
-            } else if (!sure_out) {
-                const double *T = st->T;
-                Near64 w;
-                w.px = T[0] * (double)px + T[1] * (double)py + T[2] * (double)pz + T[3];
-                w.py = T[4] * (double)px + T[5] * (double)py + T[6] * (double)pz + T[7];
-                w.pz = T[8] * (double)px + T[9] * (double)py + T[10] * (double)pz + T[11];
-                w.dmax2 = dmax64 * dmax64;
-                w.best = INFINITY;
-                w.best_orig = 0xffffffffu;
-                w.best_pos = -1;
-                w.r2 = b + 2.f * e;
-                cover<Near64, LEAF, kStackNear>(g, P, q, w, stk + threadIdx.x, NT, 0u, 0u);
-                j = w.best_pos;
+            if (v.best_pos >= 0) {
+                const float u = v.best_key() + v.err(v.best_key());   // >= the float64 |p' - q0|^2
+                if (u < dmax2 * (1.0f - 1.0f / (1 << 22)) && 4.f * u * (1.f + 1.f / (1 << 20)) < n0.w) {
+                    j = pv.x;
+                    done = true;
+                } else {
+                    const Node nm = g.node[pv.y];
+                    searched = search_in_node(g, P, q, v, (uint32_t)pv.y, nm, p0);
+                }
             }
+        }
+        if (!done) {
+            if (!searched) search<NearBand, LEAF, kStackNear>(g, P, q, v, 1, stk + threadIdx.x, NT);
+            if (v.best_pos >= 0) {
+                float b = v.best_key();
+                float e = v.err(b);
+                bool sure_in = b + e < dmax2 * (1.0f - 1.0f / (1 << 22));
+                bool sure_out = b - e > dmax2 * (1.0f + 1.0f / (1 << 22));
+                bool sure_nn = v.second > b + 2.f * e;
+                if (sure_nn && sure_in) {
+                    j = v.best_pos;
+                } else if (!sure_out) {
+                    const double *T = st->T;
+                    Near64 w;
+                    w.px = T[0] * (double)px + T[1] * (double)py + T[2] * (double)pz + T[3];
+                    w.py = T[4] * (double)px + T[5] * (double)py + T[6] * (double)pz + T[7];
+                    w.pz = T[8] * (double)px + T[9] * (double)py + T[10] * (double)pz + T[11];
+                    w.dmax2 = dmax64 * dmax64;
+                    w.best = INFINITY;
+                    w.best_orig = 0xffffffffu;
+                    w.best_pos = -1;
+                    w.r2 = b + 2.f * e;
+                    cover<Near64, LEAF, kStackNear>(g, P, q, w, stk + threadIdx.x, NT, 0u, 0u);
+                    j = w.best_pos;
+                }
+            }
+            const int2 pn = v.best_pos >= 0 ? make_int2(v.best_pos, (int32_t)v.best_node) : make_int2(-1, -1);
+            if (pn.x != pv.x || pn.y != pv.y) prev[i] = pn;
         }
     }
     // This lane's values of the sums (zero when it is not an inlier).
@@ -400,12 +452,13 @@ k_icp_accum(GridView g, const float4 *__restrict__ srcp, const int64_t *__restri
     if (j >= 0) {
         float4 n = make_float4(0.f, 0.f, 0.f, 0.f);
         bool use = true;
-        if (METRIC == kMetricPlane || (METRIC == kMetricCombined && w_plane > 0.f)) {
+        const bool need_n = METRIC == kMetricPlane || (METRIC == kMetricCombined && w_plane > 0.f);
+        if (need_n) {
             n = nrm[j];
             use = n.x != 0.f || n.y != 0.f || n.z != 0.f;
         }
         if (use) {
-            float4 t = g.pts[j];
+            const float4 t = g.pts[j];
             float qx = hx + lx, qy = hy + ly, qz = hz + lz;
             // residual vector from the double-float p': (hi - q) is exact for
             // nearby points, so it keeps the full accuracy of hi + lo
@@ -876,6 +929,7 @@ void icp_carve(Carver &c, int np, int64_t ns, int64_t nt, int64_t nblk, int64_t 
     s.width = s.height = 0;
     s.K[0] = s.K[1] = s.K[2] = s.K[3] = 0.f;
     s.grid_built = false;
+    s.nrm_ready = false;
     s.sort_src = true;
     s.iters_max = iters_max > 0 ? iters_max : 0;
     s.nrm = c.take<float4>(nt1);
@@ -967,10 +1021,11 @@ hipError_t icp_run(IcpStore &s, const float *src, int64_t ns, const float *tgt, 
         // otherwise in input order
         e = s.sort_src ? grid_sort_points(s.ssrc, src, st) : grid_pack_points(s.ssrc, src, st);
         if (e != hipSuccess) return e;
-        if (tgt_n) {
-            e = grid_gather3(s.grid, tgt_n, s.nrm, st);
-            if (e != hipSuccess) return e;
-        }
+        // target normals in sorted order, with the gaps of the match certificate
+        if (s.grid.n > 0 && !s.nrm_ready)
+            k_nrm_gap<<<(int)((s.grid.n + kGapThreads - 1) / kGapThreads), kGapThreads, 0, st>>>(s.grid.view(),
+                                                                                                   s.grid.n, tgt_n,
+                                                                                                   s.nrm);
     } else {
         s.ptgt = tgt;
         s.pnrm = tgt_n;

@@ -129,7 +129,8 @@ __device__ void sym3_min_eigvec(double a, double b, double c, double d, double e
 // all-zero covariance gives normal 0 and curvature 0.
 __device__ void finish_normal(double cxx, double cxy, double cxz, double cyy, double cyz, double czz, double qx,
                               double qy, double qz, float vx, float vy, float vz, uint32_t qi,
-                              float *__restrict__ out_n, float *__restrict__ out_c)
+                              float *__restrict__ out_n, float *__restrict__ out_c, float4 *srt_s = nullptr,
+                              float gap = 0.f)
 {
     double n[3] = {0.0, 0.0, 0.0}, lam[3] = {0.0, 0.0, 0.0};
     bool zero = cxx == 0.0 && cxy == 0.0 && cxz == 0.0 && cyy == 0.0 && cyz == 0.0 && czz == 0.0;
@@ -146,6 +147,7 @@ __device__ void finish_normal(double cxx, double cxy, double cxz, double cyy, do
     out_n[3 * (int64_t)qi] = (float)n[0];
     out_n[3 * (int64_t)qi + 1] = (float)n[1];
     out_n[3 * (int64_t)qi + 2] = (float)n[2];
+    if (srt_s) *srt_s = make_float4((float)n[0], (float)n[1], (float)n[2], gap);
     if (out_c) {
         double tr = lam[0] + lam[1] + lam[2];
         out_c[qi] = (float)(tr > 0.0 ? lam[0] / tr : 0.0);
@@ -157,11 +159,15 @@ __device__ void finish_normal(double cxx, double cxy, double cxz, double cyy, do
 // (kc[cloud], or k for all when kc is null).  With a finite cap2 (hybrid
 // neighbourhoods) only neighbours with key <= cap2 count, and fewer than
 // min_pts of them give normal 0.
+// With srt, also the normal in sorted order with, in w, a lower bound of the
+// squared distance to the nearest other point of the cloud (the second
+// neighbour's key less 2^-20 relative; 0 when k < 2): the target record of
+// the ICP correspondence search.
 template <int KT>
 __global__ void __launch_bounds__(kQThreads) k_normals(GridView g, int64_t n_all, const float *__restrict__ xyz, int k,
                                                      const int32_t *__restrict__ kc, float cap2, int min_pts,
                                                      float vx, float vy, float vz, float *__restrict__ out_n,
-                                                     float *__restrict__ out_c)
+                                                     float *__restrict__ out_c, float4 *__restrict__ srt)
 {
     __shared__ uint32_t stk[kStack * kQThreads];
     int64_t s = xcd_block(blockIdx.x, gridDim.x) * (int64_t)kQThreads + threadIdx.x;
@@ -177,6 +183,15 @@ __global__ void __launch_bounds__(kQThreads) k_normals(GridView g, int64_t n_all
     TopK<KT> top;
     top.init(k, cap2);
     search<TopK<KT>, 32>(g, P, q, top, k, stk + threadIdx.x, kQThreads);
+    // the point itself (or an exact duplicate) is first, the nearest other
+    // point second (selected with static indices: the list stays in registers)
+    float gap = 0.f;
+    if (srt) {
+        uint64_t h2 = 0ull;
+#pragma unroll
+        for (int t = 1; t < KT; t++) h2 = (t == KT - k + 1) ? top.h[t] : h2;
+        gap = h2 == ~0ull ? INFINITY : __uint_as_float((uint32_t)(h2 >> 32)) * (1.f - 1.f / (1 << 20));
+    }
     // offsets from the query point are exact in float64 (differences of
     // float32 values); covariance is translation invariant
     double qx = p.x, qy = p.y, qz = p.z;
@@ -193,7 +208,7 @@ __global__ void __launch_bounds__(kQThreads) k_normals(GridView g, int64_t n_all
         mz += (double)xyz[3 * (int64_t)j + 2] - qz;
     }
     if (m < min_pts || m == 0) {
-        finish_normal(0.0, 0.0, 0.0, 0.0, 0.0, 0.0, qx, qy, qz, vx, vy, vz, qi, out_n, out_c);
+        finish_normal(0.0, 0.0, 0.0, 0.0, 0.0, 0.0, qx, qy, qz, vx, vy, vz, qi, out_n, out_c, srt ? srt + s : nullptr, gap);
         return;
     }
     mx /= m;
@@ -216,7 +231,7 @@ __global__ void __launch_bounds__(kQThreads) k_normals(GridView g, int64_t n_all
         czz += ez * ez;
     }
     cxx /= m; cxy /= m; cxz /= m; cyy /= m; cyz /= m; czz /= m;
-    finish_normal(cxx, cxy, cxz, cyy, cyz, czz, qx, qy, qz, vx, vy, vz, qi, out_n, out_c);
+    finish_normal(cxx, cxy, cxz, cyy, cyz, czz, qx, qy, qz, vx, vy, vz, qi, out_n, out_c, srt ? srt + s : nullptr, gap);
 }
 
 // Radius neighbourhoods: every point of the cloud with key <= r2; the
@@ -258,11 +273,11 @@ void launch_knn(const GridStore &g, const float *qry, int64_t nq, int k, int32_t
 
 template <int KT>
 void launch_normals(const GridStore &g, const float *xyz, int k, const int32_t *kc, float cap2, int min_pts,
-                    const float *vp, float *on, float *oc, hipStream_t s)
+                    const float *vp, float *on, float *oc, float4 *srt, hipStream_t s)
 {
     int blocks = (int)((g.n + kQThreads - 1) / kQThreads);
     k_normals<KT><<<blocks, kQThreads, 0, s>>>(g.view(), g.n, xyz, k, kc, cap2, min_pts, vp[0], vp[1], vp[2], on,
-                                               oc);
+                                               oc, srt);
 }
 
 }  // namespace
@@ -279,13 +294,14 @@ hipError_t knn_run(const GridStore &g, const float *qry, int64_t nq, int k, int3
 }
 
 hipError_t normals_run(const GridStore &g, const float *xyz, int k_max, const int32_t *kc, const float *vp,
-                       float *on, float *oc, hipStream_t s, float cap2, int min_pts)
+                       float *on, float *oc, hipStream_t s, float cap2, int min_pts, float4 *srt)
 {
     if (g.n <= 0) return hipSuccess;
-    if (k_max <= 4) launch_normals<4>(g, xyz, k_max, kc, cap2, min_pts, vp, on, oc, s);
-    else if (k_max <= 8) launch_normals<8>(g, xyz, k_max, kc, cap2, min_pts, vp, on, oc, s);
-    else if (k_max <= 16) launch_normals<16>(g, xyz, k_max, kc, cap2, min_pts, vp, on, oc, s);
-    else launch_normals<32>(g, xyz, k_max, kc, cap2, min_pts, vp, on, oc, s);
+    if (!(cap2 == INFINITY)) srt = nullptr;   // the gap needs plain k-NN
+    if (k_max <= 4) launch_normals<4>(g, xyz, k_max, kc, cap2, min_pts, vp, on, oc, srt, s);
+    else if (k_max <= 8) launch_normals<8>(g, xyz, k_max, kc, cap2, min_pts, vp, on, oc, srt, s);
+    else if (k_max <= 16) launch_normals<16>(g, xyz, k_max, kc, cap2, min_pts, vp, on, oc, srt, s);
+    else launch_normals<32>(g, xyz, k_max, kc, cap2, min_pts, vp, on, oc, srt, s);
     return hipGetLastError();
 }
 

@@ -13,9 +13,11 @@
 //           the ball of radius R are searched depth-first, children nearest
 //           first, skipping every cell whose box is farther than the current
 //           radius and every point range the seed already contributed.
-// Cell boxes are shrunk by an absolute margin and a relative factor, so a
-// cell is skipped only when every point in it is strictly outside the
-// radius: no candidate inside the radius is ever missed, ties included.
+// A node is skipped by its tight float32 box, whose distance never exceeds
+// the key of a point inside it; a grid cell (cover phase) by its box shrunk
+// by an absolute margin and a relative factor.  So nothing is skipped unless
+// every point in it is strictly outside the radius: no candidate inside the
+// radius is ever missed, ties included.
 //
 // The traversal is bound by memory latency, so independent loads are issued
 // together: the up-to-8 children of a node, the up-to-8 cells of the cover
@@ -37,6 +39,7 @@ __device__ inline uint64_t enc_cand(float key, float w) { return ((uint64_t)__fl
 // neighbourhoods: the k nearest within a radius).
 template <int KT>
 struct TopK {
+    static constexpr bool kSortChildren = KT > 1;   // see dfs
     uint64_t h[KT];     // ascending; ~0 = empty; 0 = padding when k < KT
     float cap2;         // inclusive key limit, +inf for plain k-NN
 
@@ -74,6 +77,7 @@ struct TopK {
 // the offsets d = p - q and of their products, in float64 (offsets of
 // float32 values are exact in float64).
 struct RadiusCov {
+    static constexpr bool kSortChildren = false;    // every node in the radius is visited anyway
     float r2;
     int32_t m;
     double sx, sy, sz, sxx, sxy, sxz, syy, syz, szz;
@@ -147,6 +151,7 @@ __device__ inline int32_t probe_from(const GridView &g, const GridParams &P, uin
     return -1;
 }
 
+// ascending sort of 8 (distance, cell) pairs: Batcher's odd-even merge network
 __device__ inline void cmp_swap(float *d, uint32_t *id, int i, int j)
 {
     bool sw = d[j] < d[i];
@@ -157,8 +162,6 @@ __device__ inline void cmp_swap(float *d, uint32_t *id, int i, int j)
     d[i] = td;
     id[i] = ti;
 }
-
-// ascending sort of 8 (distance, node) pairs: Batcher's odd-even merge network
 __device__ inline void sort8(float *d, uint32_t *id)
 {
     cmp_swap(d, id, 0, 1); cmp_swap(d, id, 2, 3); cmp_swap(d, id, 4, 5); cmp_swap(d, id, 6, 7);
@@ -182,7 +185,7 @@ __device__ inline void dfs(const GridView &g, const GridParams &P, const Query &
         Node nd = g.node[m];
         const NodeHdr &h = nd.h;
         float b2 = v.bound2();
-        if (node_mindist2(P, nd, q.x, q.y, q.z) > b2) continue;
+        if (node_mindist2(nd, q.x, q.y, q.z) > b2) continue;
         if (h.start >= xs && h.start + h.count <= xe) continue;      // already searched
         uint32_t nc = node_nchild(h);
         bool leaf = (h.count <= (uint32_t)LEAF) || node_level(h) == P.lmin || sp + (int)nc > STK;
@@ -190,7 +193,7 @@ __device__ inline void dfs(const GridView &g, const GridParams &P, const Query &
             scan_range(g.pts, h.start, h.start + h.count, xs, xe, q, v, m);
             continue;
         }
-        // all children boxes in one round trip, nearest pushed last (searched next)
+        // all children boxes in one round trip
         float d[8];
         uint32_t id[8];
 #pragma unroll
@@ -200,17 +203,42 @@ __device__ inline void dfs(const GridView &g, const GridParams &P, const Query &
             d[c] = INFINITY;
             id[c] = 0xffffffffu;
             if (c < (int)nc) {
-                d[c] = node_box_mindist2(P, g.node, h.first_child + c, q.x, q.y, q.z);
+                d[c] = node_box_mindist2(g.node, h.first_child + c, q.x, q.y, q.z);
                 id[c] = h.first_child + c;
             }
         }
-        sort8(d, id);
+        if (V::kSortChildren) {
+            // all children nearest first: the k-th key shrinks fastest
+            sort8(d, id);
 #pragma unroll
-        for (int c = 7; c >= 0; c--) {
-            if (id[c] != 0xffffffffu && d[c] <= b2) {
+            for (int c = 7; c >= 0; c--) {
+                if (id[c] != 0xffffffffu && d[c] <= b2) {
+                    stk[sp * stride] = id[c];
+                    ++sp;
+                }
+            }
+            continue;
+        }
+        // nearest child last (searched next), the others in index order:
+        // one nearest neighbour needs only the first descent to be good
+        int best = 0;
+        float bd = d[0];
+#pragma unroll
+        for (int c = 1; c < 8; c++) {
+            bool lt = d[c] < bd;
+            bd = lt ? d[c] : bd;
+            best = lt ? c : best;
+        }
+#pragma unroll
+        for (int c = 0; c < 8; c++) {
+            if (c != best && id[c] != 0xffffffffu && d[c] <= b2) {
                 stk[sp * stride] = id[c];
                 ++sp;
             }
+        }
+        if (id[best] != 0xffffffffu && bd <= b2) {
+            stk[sp * stride] = id[best];
+            ++sp;
         }
     }
 }
@@ -221,9 +249,13 @@ __device__ inline int cover_level(const GridParams &P, float b2)
 {
     if (!(b2 < INFINITY)) return kLevels;
     float R = sqrtf(b2) * (1.0f + 1.0f / (1 << 20)) + P.margin;
-    int l = P.lmin;
-    while (l < kLevels - 1 && P.h0 * (float)(1u << l) * (1.0f - 1.0f / 1024) < 2.0f * R) l++;
-    return l;
+    // smallest l >= lmin with h0 * 2^l * (1 - 1/1024) >= 2R: the exponent of
+    // the (slightly enlarged) ratio, rounded up
+    float ratio = 2.0f * R / (P.h0 * (1.0f - 1.0f / 1024)) * (1.0f + 1.0f / (1 << 20));
+    uint32_t b = __float_as_uint(ratio);
+    int e = (int)(b >> 23) - 127 + ((b & 0x7fffffu) != 0u);
+    int l = e > P.lmin ? e : P.lmin;
+    return l < kLevels - 1 ? l : kLevels - 1;
 }
 
 // Cover phase: every cell meeting the ball of the visitor's current radius,
@@ -248,23 +280,33 @@ __device__ inline void cover(const GridView &g, const GridParams &P, const Query
     int sp = 0;
     const HSlot *hs = g.hash + P.hash_base;
     if (hx - lx <= 1 && hy - ly <= 1 && hz - lz <= 1) {
-        // up to 8 cells; only those meeting the ball are probed, nearest
-        // first, four hash probes in flight at a time
+        // up to 8 cells (bit 0: x + 1, bit 1: y + 1, bit 2: z + 1); only
+        // those meeting the ball are probed, nearest first, four hash probes
+        // in flight at a time (cells sorted by distance, so a second round is
+        // needed only when more than four meet the ball).  The keys of the
+        // upper neighbours are derived from the lower corner's key.
         float d[8];
-        uint32_t id[8];
 #pragma unroll
         for (int c = 0; c < 8; c++) {
             uint32_t cx = lx + (c & 1), cy = ly + ((c >> 1) & 1), cz = lz + (c >> 2);
             bool ok = cx <= hx && cy <= hy && cz <= hz;
             float dc = ok ? cell_mindist2(P, q.x, q.y, q.z, cx, cy, cz, l) : INFINITY;
             d[c] = dc <= b2 ? dc : INFINITY;
-            id[c] = (uint32_t)c;
         }
+        uint32_t id[8];
+#pragma unroll
+        for (int c = 0; c < 8; c++) id[c] = c;
         sort8(d, id);
+        const uint64_t m0 = morton3(lx, ly, lz);
+        const uint64_t mx = hx > lx ? morton_inc<0>(m0) : m0;
+        const uint64_t ymask = 0x249249249249ull << 1;
+        const uint64_t yd = hy > ly ? morton_inc<1>(m0) & ymask : m0 & ymask;
+        const uint64_t zmask = 0x249249249249ull << 2;
+        const uint64_t zd = hz > lz ? morton_inc<2>(m0) & zmask : m0 & zmask;
         int32_t node[8];
 #pragma unroll
         for (int h = 0; h < 8; h += 4) {
-            if (!(d[h] < INFINITY)) {
+            if (!(d[h] < INFINITY || d[h + 1] < INFINITY || d[h + 2] < INFINITY || d[h + 3] < INFINITY)) {
 #pragma unroll
                 for (int u = 0; u < 4; u++) node[h + u] = -1;
                 continue;
@@ -275,8 +317,10 @@ __device__ inline void cover(const GridView &g, const GridParams &P, const Query
 #pragma unroll
             for (int u = 0; u < 4; u++) {
                 const uint32_t c = id[h + u];
-                uint32_t cx = lx + (c & 1), cy = ly + ((c >> 1) & 1), cz = lz + (c >> 2);
-                key[u] = hash_key(l, morton3(cx, cy, cz));
+                const uint64_t xm = (c & 1) ? mx : m0;
+                const uint64_t mk = (xm & ~(ymask | zmask)) | (((c >> 1) & 1) ? yd : (m0 & ymask)) |
+                                    ((c >> 2) ? zd : (m0 & zmask));
+                key[u] = hash_key(l, mk);
                 slot[u] = hash_slot(key[u], P.hash_cap);
                 HSlot e = d[h + u] < INFINITY ? hs[slot[u]] : HSlot{kEmptyKey, 0u, 0u};
                 hk[u] = e.key;
@@ -320,6 +364,8 @@ __device__ inline int32_t seed_cell(const GridView &g, const GridParams &P, cons
 {
     const float inv = P.inv_h0;
     uint32_t c0x = cell0(q.x, P.ox, inv), c0y = cell0(q.y, P.oy, inv), c0z = cell0(q.z, P.oz, inv);
+    // the level-l cell's key is the level-0 key shifted right by 3l
+    const uint64_t m0 = morton3(c0x, c0y, c0z);
     const HSlot *hs = g.hash + P.hash_base;
     for (int l0 = P.lmin; l0 < kLevels; l0 += 4) {
         uint64_t key[4];
@@ -331,7 +377,7 @@ __device__ inline int32_t seed_cell(const GridView &g, const GridParams &P, cons
             int l = l0 + t;
             bool ok = l < kLevels;
             int ls = ok ? l : 0;
-            key[t] = hash_key(ls, morton3(c0x >> ls, c0y >> ls, c0z >> ls));
+            key[t] = hash_key(ls, m0 >> (3 * ls));
             slot[t] = hash_slot(key[t], P.hash_cap);
             HSlot e = ok ? hs[slot[t]] : HSlot{kEmptyKey, 0u, 0u};
             hk[t] = e.key;

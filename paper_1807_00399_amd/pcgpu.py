@@ -29,6 +29,7 @@ EXPORTS = (
     "icp_projective_workspace_size", "icp_projective",
     "estimate_normals_batched_workspace_size", "estimate_normals_batched",
     "icp_point_to_plane_batched_workspace_size", "icp_point_to_plane_batched",
+    "icp_point_to_plane_with_normals_batched_workspace_size", "icp_point_to_plane_with_normals_batched",
     "pc_copy_probe", "icp_history", "pc_set_kernel_timer", "pc_kernel_timer_count",
     "pc_set_tuning", "pc_get_tuning",
     "pose_net_param_count", "pose_net_workspace_size", "pose_net_predict", "pose_net_train_step",
@@ -94,6 +95,11 @@ def _load() -> ctypes.CDLL:
     lib.icp_point_to_plane_batched_workspace_size.restype = sz
     lib.icp_point_to_plane_batched.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, vp, f64, vp, vp, vp, sz, vp]
     lib.icp_point_to_plane_batched.restype = ctypes.c_int
+    lib.icp_point_to_plane_with_normals_batched_workspace_size.argtypes = [i32, vp, vp, i32]
+    lib.icp_point_to_plane_with_normals_batched_workspace_size.restype = sz
+    lib.icp_point_to_plane_with_normals_batched.argtypes = [i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, f64, vp, vp, vp,
+                                                            vp, sz, vp]
+    lib.icp_point_to_plane_with_normals_batched.restype = ctypes.c_int
     lib.pc_copy_probe.argtypes = [vp, vp, sz, vp]
     lib.pc_copy_probe.restype = ctypes.c_int
     lib.icp_history.argtypes = [vp, sz, i64, i64, i32]
@@ -446,6 +452,48 @@ def icp_point_to_plane_batched(src: torch.Tensor, src_off, tgt: torch.Tensor, tg
                                         to.ctypes.data, _ptr(T0), dm.ctypes.data, mi.ctypes.data, float(conv_tol),
                                         T.data_ptr(), stats.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream))
     _check(st, "icp_point_to_plane_batched")
+    if not read_stats:
+        return T, stats
+    return T, decode_stats_batched(stats)
+
+
+def icp_point_to_plane_with_normals_batched(src: torch.Tensor, src_off, tgt: torch.Tensor, tgt_off, k,
+                                            viewpoint=(0.0, 0.0, 0.0), init_T=None, max_corr_dist=0.05,
+                                            max_iters=30, conv_tol: float = 0.0, stream=None,
+                                            workspace: torch.Tensor | None = None, out_T: torch.Tensor | None = None,
+                                            out_stats: torch.Tensor | None = None, read_stats: bool = True,
+                                            out_normals: torch.Tensor | None = None):
+    """Target normals (k per pair) and batched point-to-plane ICP over one
+    pyramid of all targets.  Returns (T (m,4,4), stats) like
+    icp_point_to_plane_batched; the normals go to out_normals when given."""
+    import numpy as np
+    src = _pts(src, "src")
+    tgt = _pts(tgt, "tgt")
+    so, to = _offsets(src_off, "src_off"), _offsets(tgt_off, "tgt_off")
+    m = so.shape[0] - 1
+    if m < 1 or to.shape[0] != m + 1 or so[-1] != src.shape[0] or to[-1] != tgt.shape[0]:
+        raise ValueError("offsets must have m + 1 entries ending at the array lengths")
+    if out_normals is not None and (out_normals.dtype != torch.float32 or not out_normals.is_contiguous()
+                                    or tuple(out_normals.shape) != (tgt.shape[0], 3)):
+        raise ValueError("out_normals must be a contiguous float32 (n_tgt, 3) tensor")
+    kk = np.ascontiguousarray(np.broadcast_to(np.asarray(k, dtype=np.int32), (m,)))
+    dm = np.ascontiguousarray(np.broadcast_to(np.asarray(max_corr_dist, dtype=np.float32), (m,)))
+    mi = np.ascontiguousarray(np.broadcast_to(np.asarray(max_iters, dtype=np.int32), (m,)))
+    dev = src.device
+    T0 = None
+    if init_T is not None:
+        T0 = torch.as_tensor(init_T, dtype=torch.float64).reshape(m, 4, 4).to(dev).contiguous()
+    T = out_T if out_T is not None else torch.empty((m, 4, 4), dtype=torch.float64, device=dev)
+    stats = out_stats if out_stats is not None else torch.zeros(24 * m, dtype=torch.uint8, device=dev)
+    vpt = (ctypes.c_float * 3)(*[float(v) for v in viewpoint])
+    need = lib.icp_point_to_plane_with_normals_batched_workspace_size(m, so.ctypes.data, to.ctypes.data,
+                                                                      int(mi.max()))
+    ws = workspace if workspace is not None else _ws.get(need, dev)
+    st = lib.icp_point_to_plane_with_normals_batched(m, src.data_ptr(), so.ctypes.data, tgt.data_ptr(),
+                                                     to.ctypes.data, kk.ctypes.data, vpt, _ptr(T0), dm.ctypes.data,
+                                                     mi.ctypes.data, float(conv_tol), T.data_ptr(), stats.data_ptr(),
+                                                     _ptr(out_normals), ws.data_ptr(), ws.numel(), _stream(stream))
+    _check(st, "icp_point_to_plane_with_normals_batched")
     if not read_stats:
         return T, stats
     return T, decode_stats_batched(stats)

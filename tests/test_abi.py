@@ -296,3 +296,29 @@ def test_icp_with_normals_rejects_bad_arguments(pc):
     assert call(out=None) == pc.PC_EINVAL
     assert call(v=None) == pc.PC_EINVAL
     assert call(v=(ctypes.c_float * 3)(0.0, float("nan"), 0.0)) == pc.PC_EINVAL
+
+
+def test_batched_icp_with_normals_rejects_bad_arguments(pc):
+    L = pc.lib
+    so, to = _i64([0, 50, 50, 120]), _i64([0, 60, 70, 70])
+    dm, mi, kk = _f32([0.1, 0.05, 0.2]), _i32([5, 9, 0]), _i32([10, 4, 16])
+    ws = L.icp_point_to_plane_with_normals_batched_workspace_size(3, so, to, 9)
+    assert ws > L.icp_point_to_plane_batched_workspace_size(3, so, to, 9)
+    vp = (ctypes.c_float * 3)(0.0, 0.0, 0.0)
+
+    def call(m=3, s=so, t=to, k=kk, v=vp, d=dm, it=mi, tol=0.0, out=FAKE, w=FAKE, wb=ws):
+        return L.icp_point_to_plane_with_normals_batched(m, FAKE, s, FAKE, t, k, v, None, d, it, tol, out, None, None,
+                                                         w, wb, None)
+
+    assert call(wb=ws - 1) == pc.PC_EWORKSPACE
+    assert call(k=_i32([10, 11, 16])) == pc.PC_EINVAL    # more neighbours than the 10 points of target 1
+    assert call(k=_i32([0, 4, 16])) == pc.PC_EINVAL
+    assert call(k=_i32([10, 4, 33])) == pc.PC_EINVAL
+    assert call(k=None) == pc.PC_EINVAL
+    assert call(v=None) == pc.PC_EINVAL
+    assert call(d=_f32([0.1, 0.0, 0.2])) == pc.PC_EINVAL
+    assert call(it=_i32([5, -1, 0])) == pc.PC_EINVAL
+    assert call(t=_i64([0, 60, 50, 70])) == pc.PC_EINVAL
+    assert call(m=0) == pc.PC_EINVAL
+    assert call(out=None) == pc.PC_EINVAL
+    assert call(tol=float("inf")) == pc.PC_EINVAL

@@ -93,6 +93,32 @@ def test_batched_icp_equal_single_and_oracle(gpu, oracle_mod, small_batch):
         assert stats[j]["status"] == ro["status"] and stats[j]["iterations_run"] == ro["iterations"]
 
 
+def test_batched_icp_with_normals_equal_single_and_oracle(gpu, oracle_mod, small_batch):
+    """One pyramid for the targets' normals and the registrations: every
+    pair's pose, statistics and normals equal the single fused call's; the
+    pose is held to the oracle run on the GPU's own normals."""
+    import torch
+    b = small_batch
+    off = b.offsets
+    _say(f"batched icp with normals {b.name} pairs={b.n_pairs}")
+    nrm = torch.empty((b.target.shape[0], 3), dtype=torch.float32, device="cuda")
+    T, stats = gpu.icp_point_to_plane_with_normals_batched(_dev(b.source), off, _dev(b.target), off,
+                                                           b.param("k").astype(np.int32), (0.0, 0.0, 0.0), None,
+                                                           b.param("d_max").astype(np.float32),
+                                                           b.param("iters").astype(np.int32), out_normals=nrm)
+    T, nrm = T.cpu().numpy(), nrm.cpu().numpy()
+    for j, w in enumerate(b.pairs):
+        Ts, ss, ns = gpu.icp_point_to_plane_with_normals(_dev(w.source), _dev(w.target), w.k, (0.0, 0.0, 0.0), None,
+                                                         w.d_max, w.iters, return_normals=True)
+        assert np.array_equal(T[j], Ts.cpu().numpy()), f"pair {j}: pose differs from the single call"
+        assert stats[j] == ss, (j, stats[j], ss)
+        assert np.array_equal(nrm[off[j]:off[j + 1]], ns.cpu().numpy()), f"pair {j}: normals differ"
+        ro = oracle_mod.icp(w.source, w.target, nrm[off[j]:off[j + 1]], None, float(np.float32(w.d_max)), w.iters)
+        ea, et = pose_err(T[j], ro["T"])
+        assert ea <= ROT_TOL and et <= TRANS_TOL, f"pair {j}: {ea:.3g} rad, {et:.3g}"
+        assert stats[j]["inliers"] == ro["inliers"]
+
+
 def test_batched_icp_edge_pairs(gpu, oracle_mod):
     # a normal pair, an empty source, an empty target, a pair with no
     # iterations, a tiny pair and a pair with its own d_max and init pose
