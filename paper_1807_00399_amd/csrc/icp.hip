@@ -79,17 +79,20 @@ __device__ inline CSum csum_merge(CSum a, CSum b)
 // queries (close runners-up or a distance at d_max) are re-decided in
 // float64 with the same expressions as the float64 definition.
 struct NearBand {
-    static constexpr bool kSortChildren = false;
-    uint64_t best;       // (key bits << 32) | original index
+    float bkey;          // best key (float32), and its original index: the
+    uint32_t bidx;       // candidate order is (key, index)
     int32_t best_pos;    // sorted position, -1 if none within the cap
     uint32_t best_node;  // node whose scan produced best_pos
     float second;        // smallest key of any other candidate seen
     float delta;         // bound on |p'(float32) - p'(float64)| per axis
+    float bnd;           // search radius^2: bkey + 2 err(bkey), updated with bkey
 
     __device__ void init(float cap2, float dlt)
     {
         delta = dlt;
-        best = enc_cand(cap2 + err(cap2), __uint_as_float(0xffffffffu));
+        bkey = cap2 + err(cap2);
+        bidx = 0xffffffffu;
+        bnd = bkey + 2.f * err(bkey);
         best_pos = -1;
         best_node = 0xffffffffu;
         second = INFINITY;
@@ -98,22 +101,20 @@ struct NearBand {
     {
         return 6e-7f * key + 3.5f * delta * sqrtf(key) + 6.f * delta * delta + 1e-30f;
     }
-    __device__ float best_key() const { return __uint_as_float((uint32_t)(best >> 32)); }
+    __device__ float best_key() const { return bkey; }
     __device__ bool have() const { return best_pos >= 0; }
-    __device__ float bound2() const
-    {
-        float b = best_key();
-        return b + 2.f * err(b);
-    }
+    __device__ float bound2() const { return bnd; }
     __device__ void visit(float qx, float qy, float qz, uint32_t j, const float4 &p, uint32_t m)
     {
-        float key = knn_key(p.x, p.y, p.z, qx, qy, qz);
-        uint64_t c = enc_cand(key, p.w);
-        if (c < best) {
-            if (best_pos >= 0) second = fminf(second, best_key());
-            best = c;
+        const float key = knn_key(p.x, p.y, p.z, qx, qy, qz);
+        const uint32_t idx = __float_as_uint(p.w);
+        if (key < bkey || (key == bkey && idx < bidx)) {
+            if (best_pos >= 0) second = fminf(second, bkey);
+            bkey = key;
+            bidx = idx;
             best_pos = (int32_t)j;
             best_node = m;
+            bnd = key + 2.f * err(key);
         } else if ((int32_t)j != best_pos) {
             second = fminf(second, key);
         }
@@ -123,7 +124,6 @@ struct NearBand {
 // float64 re-decision: nearest point by |p' - q|^2 in float64 among those
 // with |p' - q|^2 <= d_max^2, ties to the lower original index
 struct Near64 {
-    static constexpr bool kSortChildren = false;
     double px, py, pz, dmax2, best;
     uint32_t best_orig;
     int32_t best_pos;

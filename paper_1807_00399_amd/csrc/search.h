@@ -39,7 +39,6 @@ __device__ inline uint64_t enc_cand(float key, float w) { return ((uint64_t)__fl
 // neighbourhoods: the k nearest within a radius).
 template <int KT>
 struct TopK {
-    static constexpr bool kSortChildren = KT > 1;   // see dfs
     uint64_t h[KT];     // ascending; ~0 = empty; 0 = padding when k < KT
     float cap2;         // inclusive key limit, +inf for plain k-NN
 
@@ -77,7 +76,6 @@ struct TopK {
 // the offsets d = p - q and of their products, in float64 (offsets of
 // float32 values are exact in float64).
 struct RadiusCov {
-    static constexpr bool kSortChildren = false;    // every node in the radius is visited anyway
     float r2;
     int32_t m;
     double sx, sy, sz, sxx, sxy, sxz, syy, syz, szz;
@@ -207,20 +205,8 @@ __device__ inline void dfs(const GridView &g, const GridParams &P, const Query &
                 id[c] = h.first_child + c;
             }
         }
-        if (V::kSortChildren) {
-            // all children nearest first: the k-th key shrinks fastest
-            sort8(d, id);
-#pragma unroll
-            for (int c = 7; c >= 0; c--) {
-                if (id[c] != 0xffffffffu && d[c] <= b2) {
-                    stk[sp * stride] = id[c];
-                    ++sp;
-                }
-            }
-            continue;
-        }
-        // nearest child last (searched next), the others in index order:
-        // one nearest neighbour needs only the first descent to be good
+        // nearest child last (searched next), the others in index order
+        // (cheaper than sorting all eight, and as fast to tighten the bound)
         int best = 0;
         float bd = d[0];
 #pragma unroll
