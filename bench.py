@@ -143,6 +143,22 @@ def traffic_from_profiles(kernel_tag, workload):
     return d.get("hbm_bytes_per_launch")
 
 
+def valu_from_profiles(workload):
+    """Share of the nominal vector-issue capacity the accumulate kernel used
+    (time-weighted over its launches), from the committed rocprofv3 SQ
+    counter summary, provided the kernel sources have not changed since."""
+    path = os.path.join(PROFILES, f"icp_accum_{workload}_valu.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+    except Exception:
+        return None
+    if d.get("kernel_digest") != kernel_digest():
+        return None
+    return d.get("valu_issue_share_nominal_time_weighted")
+
+
 def copy_probe():
     """Plain device copy of 1 GiB, 10 times: achievable bandwidth, and a
     kernel of known traffic for scaling the FETCH_SIZE / WRITE_SIZE counters."""
@@ -662,7 +678,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_icp_accum", "avg_kernel_us": avg_kernel_s * 1e6,
-                     "algorithmic_bytes_per_launch": algo_bytes},
+                     "algorithmic_bytes_per_launch": algo_bytes,
+                     "valu_issue_share": valu_from_profiles(args.workload)},
     }
     if not args.no_learned:
         info = learned_legs(min(args.steps, 5), 1, args)[0]

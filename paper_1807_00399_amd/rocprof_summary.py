@@ -4,10 +4,18 @@
     python -m paper_1807_00399_amd.rocprof_summary traffic <kernel-regex> <fetch.csv> <write.csv> \\
            <copy_fetch.csv> <copy_write.csv> <copy_bytes> <launches_per_step> <out.json> "<command>"
 
+    python -m paper_1807_00399_amd.rocprof_summary valu <kernel-regex> <sq.csv> <launches_per_call> <out.json> "<command>"
+
 `stats` keeps the per-kernel call count, total and average duration.
 `traffic` turns FETCH_SIZE and WRITE_SIZE (KiB per dispatch) of the matching
 kernel into bytes per launch, each scaled by the ratio between the known
 bytes of a plain copy kernel and what the same counter reported for it.
+`valu` turns SQ_WAVES, SQ_INSTS_VALU and SQ_INSTS_VMEM_RD of each matching
+dispatch into instructions per wave and the share of the chip's vector issue
+slots the dispatch used: a wave64 vector instruction occupies a 16-lane SIMD
+for 4 cycles, and MI355X has 256 CUs x 4 SIMDs at 2.4 GHz, so the nominal share is
+4 * SQ_INSTS_VALU / (1024 * 2.4e9 * duration) (nominal: some vector instructions
+issue in fewer cycles, so it can exceed 1).
 """
 from __future__ import annotations
 
@@ -65,10 +73,38 @@ def traffic(regex, fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_by
     json.dump(res, open(out, "w"), indent=1)
 
 
+def valu(regex, sq_csv, per_call, out, command):
+    per = {}
+    for r in csv.DictReader(open(sq_csv)):
+        if not re.search(regex, r["Kernel_Name"]):
+            continue
+        d = per.setdefault(int(r["Dispatch_Id"]), {"ns": float(r["End_Timestamp"]) - float(r["Start_Timestamp"])})
+        d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    rows = []
+    for k in sorted(per):
+        d = per[k]
+        w = d["SQ_WAVES"]
+        rows.append({"dispatch": k, "us": d["ns"] / 1e3, "waves": w,
+                     "valu_per_wave": d["SQ_INSTS_VALU"] / w, "vmem_rd_per_wave": d["SQ_INSTS_VMEM_RD"] / w,
+                     "valu_issue_share_nominal": 4.0 * d["SQ_INSTS_VALU"] / (1024 * 2.4e9 * d["ns"] * 1e-9)})
+    res = {"kernel_regex": regex, "command": command, "dispatches": len(rows),
+           "valu_issue_share_nominal_time_weighted": sum(r["valu_issue_share_nominal"] * r["us"] for r in rows) /
+           sum(r["us"] for r in rows),
+           "first_call": [{"us": round(r["us"], 1), "valu_per_wave": round(r["valu_per_wave"]),
+                           "vmem_rd_per_wave": round(r["vmem_rd_per_wave"], 1),
+                           "valu_issue_share_nominal": round(r["valu_issue_share_nominal"], 3)}
+                          for r in rows[:int(per_call)]]}
+    from bench import kernel_digest
+    res["kernel_digest"] = kernel_digest()
+    json.dump(res, open(out, "w"), indent=1)
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "stats":
         stats(*sys.argv[2:5])
     elif sys.argv[1] == "traffic":
         traffic(*sys.argv[2:11])
+    elif sys.argv[1] == "valu":
+        valu(*sys.argv[2:7])
     else:
         raise SystemExit(__doc__)
