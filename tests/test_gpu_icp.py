@@ -177,3 +177,41 @@ def test_icp_deterministic(gpu, oracle_mod):
     a, sa = _run_gpu(gpu, w.source, w.target, nrm, None, w.d_max, w.iters)
     b, sb = _run_gpu(gpu, w.source, w.target, nrm, None, w.d_max, w.iters)
     assert np.array_equal(a, b) and sa == sb
+
+
+@pytest.mark.parametrize("fused", [False, True])
+def test_icp_match_certificate_duplicates(gpu, oracle_mod, fused):
+    """A converged point keeps its previous match without a search when it
+    lies within half the distance from that match to the nearest other
+    target point.  A target with exact duplicates (that distance is 0: always
+    searched) and 2 um near-duplicates (the certificate at its margin), with
+    the source an exact copy started at the true pose, so that iterations 1..
+    and the final pass run on certificates: the final statistics must equal
+    the oracle's evaluated at the returned pose.  Residuals are ~1e-7 here, so
+    a single wrong near-duplicate match would move the rms by far more than
+    the tolerance."""
+    rng = rng_for(0, 77)
+    base = sphere_plane(rng, 3000)
+    dup = base[rng.choice(3000, 200, replace=False)]
+    near = base[rng.choice(3000, 200, replace=False)] + rng.normal(size=(200, 3)) * 2e-6
+    tgt = np.vstack([base, dup, near]).astype(np.float32)
+    G = random_rigid(rng, 3.0, 0.02)
+    src = apply_rigid(np.linalg.inv(G), tgt).astype(np.float32)
+    d_max = 0.1
+    _say(f"icp certificate fused={fused} n={len(tgt)}")
+    if fused:
+        T, st, nrm = gpu.icp_point_to_plane_with_normals(_dev(src), _dev(tgt), 10, (0.0, 0.0, 0.0), G, d_max, 4,
+                                                         return_normals=True)
+        nrm = nrm.cpu().numpy()
+    else:
+        nrm = _oracle_normals(oracle_mod, tgt, 10)
+        T, st = gpu.icp_point_to_plane(_dev(src), _dev(tgt), _dev(nrm), G, d_max, 4)
+    T = T.cpu().numpy()
+    sysm = oracle_mod.p2plane_system(src, tgt, nrm, T, float(np.float32(d_max)))
+    assert st["inliers"] == sysm["inliers"] == len(src)
+    rms_o = np.sqrt(sysm["sum_r2"] / sysm["inliers"])
+    assert rms_o < 1e-6
+    assert abs(st["rms"] - rms_o) <= 1e-3 * rms_o, (st["rms"], rms_o)
+    ro = oracle_mod.icp(src, tgt, nrm, G, float(np.float32(d_max)), 4)
+    ea, et = pose_err(T, ro["T"])
+    assert ea <= ROT_TOL and et <= TRANS_TOL
