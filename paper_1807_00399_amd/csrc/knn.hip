@@ -193,9 +193,14 @@ __global__ void __launch_bounds__(kQThreads) k_normals(GridView g, int64_t n_all
         gap = h2 == ~0ull ? INFINITY : __uint_as_float((uint32_t)(h2 >> 32)) * (1.f - 1.f / (1 << 20));
     }
     // offsets from the query point are exact in float64 (differences of
-    // float32 values); covariance is translation invariant
+    // float32 values); covariance is translation invariant.  One pass over
+    // the neighbours (each one's coordinates gathered once): C = S / m -
+    // mu mu^T from the sums of the offsets and of their products, whose
+    // float64 cancellation error (~1e-16 of the neighbourhood's extent
+    // squared) is far below the normal's tolerance.  Neighbours all at the
+    // query give exactly zero.
     double qx = p.x, qy = p.y, qz = p.z;
-    double mx = 0.0, my = 0.0, mz = 0.0;
+    double sx = 0.0, sy = 0.0, sz = 0.0, sxx = 0.0, sxy = 0.0, sxz = 0.0, syy = 0.0, syz = 0.0, szz = 0.0;
     int m = 0;
 #pragma unroll
     for (int t = 0; t < KT; t++) {
@@ -203,34 +208,20 @@ __global__ void __launch_bounds__(kQThreads) k_normals(GridView g, int64_t n_all
         uint32_t j = (uint32_t)top.h[t];
         if (j >= (uint32_t)n_all) continue;   // unfilled slot (only under a cap)
         m++;
-        mx += (double)xyz[3 * (int64_t)j] - qx;
-        my += (double)xyz[3 * (int64_t)j + 1] - qy;
-        mz += (double)xyz[3 * (int64_t)j + 2] - qz;
+        const double dx = (double)xyz[3 * (int64_t)j] - qx;
+        const double dy = (double)xyz[3 * (int64_t)j + 1] - qy;
+        const double dz = (double)xyz[3 * (int64_t)j + 2] - qz;
+        sx += dx; sy += dy; sz += dz;
+        sxx += dx * dx; sxy += dx * dy; sxz += dx * dz;
+        syy += dy * dy; syz += dy * dz; szz += dz * dz;
     }
     if (m < min_pts || m == 0) {
         finish_normal(0.0, 0.0, 0.0, 0.0, 0.0, 0.0, qx, qy, qz, vx, vy, vz, qi, out_n, out_c, srt ? srt + s : nullptr, gap);
         return;
     }
-    mx /= m;
-    my /= m;
-    mz /= m;
-    double cxx = 0, cxy = 0, cxz = 0, cyy = 0, cyz = 0, czz = 0;
-#pragma unroll
-    for (int t = 0; t < KT; t++) {
-        if (t < KT - k) continue;
-        uint32_t j = (uint32_t)top.h[t];
-        if (j >= (uint32_t)n_all) continue;
-        double ex = ((double)xyz[3 * (int64_t)j] - qx) - mx;
-        double ey = ((double)xyz[3 * (int64_t)j + 1] - qy) - my;
-        double ez = ((double)xyz[3 * (int64_t)j + 2] - qz) - mz;
-        cxx += ex * ex;
-        cxy += ex * ey;
-        cxz += ex * ez;
-        cyy += ey * ey;
-        cyz += ey * ez;
-        czz += ez * ez;
-    }
-    cxx /= m; cxy /= m; cxz /= m; cyy /= m; cyz /= m; czz /= m;
+    const double mx = sx / m, my = sy / m, mz = sz / m;
+    double cxx = sxx / m - mx * mx, cxy = sxy / m - mx * my, cxz = sxz / m - mx * mz;
+    double cyy = syy / m - my * my, cyz = syz / m - my * mz, czz = szz / m - mz * mz;
     finish_normal(cxx, cxy, cxz, cyy, cyz, czz, qx, qy, qz, vx, vy, vz, qi, out_n, out_c, srt ? srt + s : nullptr, gap);
 }
 
