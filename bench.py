@@ -14,8 +14,9 @@ Prints one JSON line.  value = pairs/s; the loop-only Mpt*iter/s, the
 roofline of the dominant kernel (the per-iteration correspondence +
 accumulation kernel, timed with HIP events on the library's stream) and a
 CPU-oracle baseline are reported alongside.  The batch workload runs 256
-uneven pairs per step through the batched entry points (one step = normals
-of every target + ICP of every pair).  The learned workload registers 512
+uneven pairs per step through the batched entry point (one step = normals
+of every target + ICP of every pair over one pyramid, also replayed as a
+captured graph).  The learned workload registers 512
 exact-copy pairs from four starts (plain, 8-start, learned with 8-start
 fallback, learned only); the default run appends a summary of it.
 """
@@ -80,7 +81,7 @@ def parse():
     ap.add_argument("--no-compare", action="store_true",
                     help="batch workload: skip the one-call-per-pair comparison")
     ap.add_argument("--no-graph", action="store_true",
-                    help="single-pair workloads: time eager launches instead of replays of a captured graph")
+                    help="single-pair and batch workloads: time eager launches instead of replays of a captured graph")
     ap.add_argument("--no-learned", action="store_true",
                     help="default run: skip the learned-initialiser comparison")
     ap.add_argument("--copy-probe", action="store_true",
@@ -487,7 +488,28 @@ def bench_batch(args):
     for _ in range(args.steps):
         step()
     torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    el_eager = time.perf_counter() - t0
+    el, launch = el_eager, "eager"
+    if not args.no_graph:
+        # the batched call launches kernels only: captured once, replayed
+        side = torch.cuda.Stream()
+        side.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(side):
+            step()
+        torch.cuda.current_stream().wait_stream(side)
+        torch.cuda.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        for _ in range(args.warmup):
+            graph.replay()
+        torch.cuda.synchronize()
+        # timed region: K whole steps
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            graph.replay()
+        torch.cuda.synchronize()
+        el, launch = time.perf_counter() - t0, "graph replay"
     st = pcgpu.decode_stats_batched(stats)
 
     # per-iteration accumulate kernel: events recorded by the library
@@ -540,7 +562,8 @@ def bench_batch(args):
         "config": {"workload": f"{b.name}: {m} uneven pairs per step, {b.n} points per side, "
                                f"sphere+plane (k=10, d_max 0.1, 20 iterations) or room (k=16, d_max 0.05, "
                                f"30 iterations) pairs",
-                   "pairs": m, "points_per_side": b.n},
+                   "pairs": m, "points_per_side": b.n, "launch": launch},
+        "eager_pairs_per_s": m * args.steps / el_eager,
         "mpt_iter_per_s": pts_iter / (float(np.median(loop_ms)) * 1e-3) / 1e6,
         "loop_ms": float(np.median(loop_ms)),
         "single_call_pairs_per_s": seq_pairs / seq_el if seq_pairs else None,

@@ -259,8 +259,12 @@ pc_status icp_projective(const float *src_xyz, int64_t n_src,
  * packed back to back; offsets (host, m + 1 entries, offsets[0] = 0,
  * non-decreasing, total below 2^31) give cloud c as rows
  * [offsets[c], offsets[c+1]) of the packed array.  The offsets and the
- * per-item parameters are copied to the device during the call (so the
- * host arrays may be freed on return); everything else is asynchronous.
+ * per-item parameters travel to the device as kernel arguments of small
+ * copy kernels launched by the call (so the host arrays may be freed on
+ * return); everything else is asynchronous.  estimate_normals_batched,
+ * icp_point_to_plane_batched and icp_point_to_plane_with_normals_batched
+ * launch kernels only (no memset, no host copy): with the workspace and
+ * outputs preallocated, a call can be captured in a graph and replayed.
  * ---------------------------------------------------------------------- */
 
 /* estimate_normals on n_clouds clouds (neighbourhoods never cross clouds).

@@ -1,6 +1,7 @@
 // C-ABI entry points: argument validation, workspace carving, launches.
 
 #include <math.h>
+#include <string.h>
 
 #include <vector>
 
@@ -27,9 +28,34 @@ bool valid_offsets(const int64_t *off, int m)
 // process-wide tuning of the ICP kernels and the pyramid (pc_set_tuning)
 pc_tuning g_tune = {128, 16, 1.0f, 1};
 
+// Small host arrays (offsets, per-pair parameters) reach the device as
+// kernel arguments, kUploadChunk bytes per launch, copied by value when the
+// kernel is launched.  A call then launches kernels only, so it can be
+// captured in a graph (a copy from pageable host memory is not a safe graph
+// node), and the caller's arrays need not outlive the call.  Every array
+// uploaded holds 4- or 8-byte elements, at 4-byte aligned destinations.
+constexpr int kUploadChunk = 2048;
+struct UploadChunk {
+    uint32_t w[kUploadChunk / 4];
+};
+
+__global__ void k_upload(UploadChunk c, uint32_t *__restrict__ dst, uint32_t nwords)
+{
+    for (uint32_t i = threadIdx.x; i < nwords; i += blockDim.x) dst[i] = c.w[i];
+}
+
 bool upload(void *dst, const void *src, size_t bytes, hipStream_t s)
 {
-    return bytes == 0 || hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, s) == hipSuccess;
+    if (bytes % 4 != 0 || ((uintptr_t)dst % 4) != 0) return false;
+    for (size_t off = 0; off < bytes; off += kUploadChunk) {
+        const size_t nb = bytes - off < (size_t)kUploadChunk ? bytes - off : (size_t)kUploadChunk;
+        UploadChunk c;
+        memcpy(c.w, static_cast<const char *>(src) + off, nb);
+        k_upload<<<1, 256, 0, s>>>(c, reinterpret_cast<uint32_t *>(static_cast<char *>(dst) + off),
+                                   (uint32_t)(nb / 4));
+        if (hipGetLastError() != hipSuccess) return false;
+    }
+    return true;
 }
 
 __global__ void k_copy16(const uint4 *__restrict__ src, uint4 *__restrict__ dst, size_t n)
