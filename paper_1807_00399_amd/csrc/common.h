@@ -317,8 +317,6 @@ hipError_t grid_pack_points(GridStore &g, const float *xyz, hipStream_t s);
 hipError_t grid_build(GridStore &g, const float *xyz, hipStream_t s);
 // Writes the offsets of a grid holding one cloud of g.n points.
 hipError_t grid_set_single_cloud(GridStore &g, hipStream_t s);
-// Gathers an (n x 3) per-point array into sorted order as float4 (w = 0).
-hipError_t grid_gather3(const GridStore &g, const float *src3, float4 *dst, hipStream_t s);
 
 int64_t max_pyramid_nodes(int64_t n, int n_clouds);
 

@@ -263,15 +263,6 @@ __global__ void k_gather_pts(const float *__restrict__ xyz, const uint32_t *__re
                          __uint_as_float(j));
 }
 
-__global__ void k_gather3(const float *__restrict__ src, const uint32_t *__restrict__ idx, int64_t n,
-                          float4 *__restrict__ dst)
-{
-    int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    uint32_t j = idx[i];
-    dst[i] = make_float4(src[3 * (int64_t)j], src[3 * (int64_t)j + 1], src[3 * (int64_t)j + 2], 0.f);
-}
-
 // ---------------------------------------------------------------- levels
 // slev[i] = highest level at which sorted point i opens a new cell of its
 // cloud (kNoStart if it opens none; the first point of a cloud opens its
@@ -737,12 +728,6 @@ hipError_t grid_build(GridStore &g, const float *xyz, hipStream_t s)
         for (int l = 0; l < kLevels; l++)
             k_node_boxes<<<bxb, T, 0, s>>>(g.params, g.layout, l, g.keys, g.pts, g.node);
     }
-    return hipGetLastError();
-}
-
-hipError_t grid_gather3(const GridStore &g, const float *src3, float4 *dst, hipStream_t s)
-{
-    if (g.n > 0) k_gather3<<<blocks_for(g.n, 256), 256, 0, s>>>(src3, g.idx, g.n, dst);
     return hipGetLastError();
 }
 
