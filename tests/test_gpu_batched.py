@@ -159,6 +159,48 @@ def test_batched_icp_edge_pairs(gpu, oracle_mod):
         assert ea <= ROT_TOL and et <= TRANS_TOL, (j, ea, et)
 
 
+def test_batched_icp_with_normals_edge_pairs(gpu, oracle_mod):
+    """The fused batched call on the edge pairs: each pair equals the single
+    fused call, including an empty source, an empty target, a pair with no
+    iterations and a 7-point pair (k = 6), and the non-empty registrations
+    match the oracle run on the GPU's own normals."""
+    import torch
+    rng = rng_for(99, 1)
+    a = sphere_plane(rng, 1500)
+    Ta = random_rigid(rng, 8.0, 0.03)
+    tiny = sphere_plane(rng, 7)
+    Ti = random_rigid(rng, 2.0, 0.01)
+    empty = np.zeros((0, 3), np.float32)
+    srcs = [a, empty, a, a, tiny]
+    tgts = [apply_rigid(Ta, a), apply_rigid(Ta, a), empty, apply_rigid(Ta, a), apply_rigid(Ti, tiny)]
+    kk = np.array([10, 10, 10, 10, 6], np.int32)
+    d_max = np.array([0.1, 0.1, 0.1, 0.1, 0.5], np.float32)
+    iters = np.array([15, 15, 15, 0, 10], np.int32)
+    so = np.concatenate([[0], np.cumsum([len(x) for x in srcs])]).astype(np.int64)
+    to = np.concatenate([[0], np.cumsum([len(x) for x in tgts])]).astype(np.int64)
+    _say("batched icp with normals edge pairs", so.tolist(), to.tolist())
+    nrm = torch.empty((int(to[-1]), 3), dtype=torch.float32, device="cuda")
+    T, stats = gpu.icp_point_to_plane_with_normals_batched(_dev(np.vstack(srcs)), so, _dev(np.vstack(tgts)), to, kk,
+                                                           (0.0, 0.0, 0.0), None, d_max, iters, out_normals=nrm)
+    T, nrm = T.cpu().numpy(), nrm.cpu().numpy()
+    for j in range(5):
+        if len(tgts[j]) == 0:
+            continue     # the single fused call needs at least k target points
+        Ts, ss, ns = gpu.icp_point_to_plane_with_normals(_dev(srcs[j]), _dev(tgts[j]), int(kk[j]), (0.0, 0.0, 0.0),
+                                                         None, float(d_max[j]), int(iters[j]), return_normals=True)
+        assert np.array_equal(T[j], Ts.cpu().numpy()), j
+        assert stats[j] == ss, (j, stats[j], ss)
+        assert np.array_equal(nrm[to[j]:to[j + 1]], ns.cpu().numpy()), j
+    assert stats[1]["status"] == 3 and stats[2]["status"] == 3          # no source / no target
+    assert np.array_equal(T[2], np.eye(4))
+    assert stats[3]["iterations_run"] == 0 and np.array_equal(T[3], np.eye(4))
+    for j in (0, 4):
+        ro = oracle_mod.icp(srcs[j], tgts[j], nrm[to[j]:to[j + 1]], None, float(d_max[j]), int(iters[j]))
+        ea, et = pose_err(T[j], ro["T"])
+        assert ea <= ROT_TOL and et <= TRANS_TOL, (j, ea, et)
+        assert stats[j]["inliers"] == ro["inliers"]
+
+
 def test_batched_rejects_bad_offsets(gpu):
     import torch
     x = torch.zeros((10, 3), dtype=torch.float32, device="cuda")
