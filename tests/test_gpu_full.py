@@ -95,3 +95,30 @@ def test_full_icp_pose(gpu, oracle_mod, work):
     assert st["status"] == status and st["iterations_run"] == its
     assert ea <= 1e-5 and et <= 1e-6
     assert abs(st["inliers"] - inl) <= max(2, 1e-5 * w.n)
+
+
+def test_full_icp_with_normals(gpu, oracle_mod, work):
+    # the fused call (normals and ICP over one target pyramid, the path the
+    # benchmark times) at full size: bit-identical to estimate_normals
+    # followed by icp_point_to_plane, and its pose within the same bar as
+    # the oracle's pose from the oracle's normals
+    import torch
+    w, en, _, _ = work
+    print(f"icp with normals full {w.name}", flush=True)
+    S, T = _dev(w.source), _dev(w.target)
+    Tf, sf, nf = gpu.icp_point_to_plane_with_normals(S, T, w.k, (0.0, 0.0, 0.0), None, w.d_max, w.iters,
+                                                     return_normals=True, read_stats=False)
+    n2, _ = gpu.estimate_normals(T, w.k, curvature=False)
+    Ts, ss = gpu.icp_point_to_plane(S, T, n2, None, w.d_max, w.iters, read_stats=False)
+    assert torch.equal(nf, n2) and torch.equal(Tf, Ts) and torch.equal(sf, ss)
+    nrm = en.astype(np.float32)
+    ref = json.load(open(GOLDEN)).get(w.name) if os.path.exists(GOLDEN) else None
+    if not (ref and ref["sha256_source"] == _digest(w.source) and ref["sha256_target"] == _digest(w.target)
+            and ref["sha256_normals"] == _digest(nrm)):
+        pytest.skip("no stored oracle pose for this workload")
+    st = gpu.decode_stats(sf)
+    ea, et = pose_err(Tf.cpu().numpy(), np.array(ref["T"]).reshape(4, 4))
+    print(f"fused pose vs oracle {ea:.3g} rad {et:.3g}; inliers {st['inliers']} vs {ref['inliers']}", flush=True)
+    assert st["status"] == ref["status"]
+    assert ea <= 1e-5 and et <= 1e-6
+    assert abs(st["inliers"] - ref["inliers"]) <= max(2, 1e-5 * w.n)
