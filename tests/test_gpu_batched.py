@@ -241,6 +241,53 @@ def test_batched_full_workload_sampled(gpu, oracle_mod):
         assert ea <= ROT_TOL and et <= TRANS_TOL, (j, ea, et)
 
 
+def test_batched_full_workload_fused_bench_tuning(gpu, oracle_mod):
+    # the benchmark's batch step as it runs: the fused normals+ICP batched
+    # call over the full 256 uneven pairs, in the launch tuning the benchmark
+    # applies (the autotuner's cached choice); sampled pairs against the
+    # single fused call in the default tuning (same correspondences, sums
+    # regrouped) and the oracle on the smallest of them
+    import os
+    import torch
+    from paper_1807_00399_amd import autotune
+    b = batch_workload(3)
+    off = b.offsets
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1807_00399_amd",
+                        "tuning_cache.json")
+    hit = autotune.load_cache(path).get(autotune.cache_key(autotune._device_name(None), "uneven_pairs_256", b.n))
+    if hit is None:
+        pytest.skip("no cached tuning for this device")
+    tun = hit["tuning"]
+    _say(f"full fused batch {b.name} n={b.n} tuned {tun}")
+    nrm = torch.empty((b.target.shape[0], 3), dtype=torch.float32, device="cuda")
+    try:
+        gpu.set_tuning(tun["icp_block_threads"], tun["icp_leaf"], tun["node_budget"], tun["sort_queries"])
+        T, stats = gpu.icp_point_to_plane_with_normals_batched(_dev(b.source), off, _dev(b.target), off,
+                                                               b.param("k").astype(np.int32), (0.0, 0.0, 0.0), None,
+                                                               b.param("d_max").astype(np.float32),
+                                                               b.param("iters").astype(np.int32), out_normals=nrm)
+    finally:
+        gpu.set_tuning(128, 16, 1.0, 1)
+    T, nrm = T.cpu().numpy(), nrm.cpu().numpy()
+    sizes = np.diff(off)
+    rng = np.random.default_rng(11)
+    sample = sorted(set(rng.choice(b.n_pairs, 10, replace=False).tolist()) | {int(np.argmin(sizes)),
+                                                                              int(np.argmax(sizes))})
+    for j in sample:
+        w = b.pairs[j]
+        Ts, ss, ns = gpu.icp_point_to_plane_with_normals(_dev(w.source), _dev(w.target), w.k, (0.0, 0.0, 0.0),
+                                                         None, w.d_max, w.iters, return_normals=True)
+        assert np.array_equal(nrm[off[j]:off[j + 1]], ns.cpu().numpy()), f"pair {j}: normals differ"
+        assert np.abs(T[j] - Ts.cpu().numpy()).max() < 1e-10, f"pair {j}: pose differs"
+        assert stats[j]["inliers"] == ss["inliers"] and stats[j]["status"] == ss["status"], (j, stats[j], ss)
+    for j in sorted(sample, key=lambda q: sizes[q])[:3]:
+        w = b.pairs[j]
+        ro = oracle_mod.icp(w.source, w.target, nrm[off[j]:off[j + 1]], None, float(np.float32(w.d_max)), w.iters)
+        ea, et = pose_err(T[j], ro["T"])
+        assert ea <= ROT_TOL and et <= TRANS_TOL, (j, ea, et)
+        assert stats[j]["inliers"] == ro["inliers"], (j, stats[j]["inliers"], ro["inliers"])
+
+
 def test_tunings_give_the_same_results(gpu, oracle_mod, small_batch):
     # every launch shape, pyramid depth and query order finds the same
     # correspondences; the block size and the query order only regroup the

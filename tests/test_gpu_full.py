@@ -122,3 +122,46 @@ def test_full_icp_with_normals(gpu, oracle_mod, work):
     assert st["status"] == ref["status"]
     assert ea <= 1e-5 and et <= 1e-6
     assert abs(st["inliers"] - ref["inliers"]) <= max(2, 1e-5 * w.n)
+
+
+def _bench_tuning(tag, n):
+    """The launch tuning the benchmark applies to this workload (its cached
+    autotuner choice for this device), or None."""
+    from paper_1807_00399_amd import autotune
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1807_00399_amd",
+                        "tuning_cache.json")
+    hit = autotune.load_cache(path).get(autotune.cache_key(autotune._device_name(None), tag, n))
+    return hit["tuning"] if hit else None
+
+
+def test_full_icp_with_normals_bench_tuning(gpu, oracle_mod, work):
+    # the benchmark's exact launch configuration (block size, leaf size, node
+    # budget, query order from the tuning cache) at full size: the same
+    # correspondences as the default launch, sums regrouped only, and the
+    # pose held to the oracle's
+    w, en, _, _ = work
+    tun = _bench_tuning(w.name, w.n)
+    if tun is None:
+        pytest.skip("no cached tuning for this device")
+    print(f"icp with normals full {w.name} tuned {tun}", flush=True)
+    S, T = _dev(w.source), _dev(w.target)
+    Td, sd = gpu.icp_point_to_plane_with_normals(S, T, w.k, (0.0, 0.0, 0.0), None, w.d_max, w.iters)
+    try:
+        gpu.set_tuning(tun["icp_block_threads"], tun["icp_leaf"], tun["node_budget"], tun["sort_queries"])
+        Tt, st = gpu.icp_point_to_plane_with_normals(S, T, w.k, (0.0, 0.0, 0.0), None, w.d_max, w.iters)
+    finally:
+        gpu.set_tuning(128, 16, 1.0, 1)
+    Tt, Td = Tt.cpu().numpy(), Td.cpu().numpy()
+    assert np.abs(Tt - Td).max() < 1e-10
+    assert st["inliers"] == sd["inliers"] and st["status"] == sd["status"]
+    assert st["iterations_run"] == sd["iterations_run"]
+    nrm = en.astype(np.float32)
+    ref = json.load(open(GOLDEN)).get(w.name) if os.path.exists(GOLDEN) else None
+    if not (ref and ref["sha256_source"] == _digest(w.source) and ref["sha256_target"] == _digest(w.target)
+            and ref["sha256_normals"] == _digest(nrm)):
+        pytest.skip("no stored oracle pose for this workload")
+    ea, et = pose_err(Tt, np.array(ref["T"]).reshape(4, 4))
+    print(f"tuned pose vs oracle {ea:.3g} rad {et:.3g}; inliers {st['inliers']} vs {ref['inliers']}", flush=True)
+    assert st["status"] == ref["status"]
+    assert ea <= 1e-5 and et <= 1e-6
+    assert abs(st["inliers"] - ref["inliers"]) <= max(2, 1e-5 * w.n)
