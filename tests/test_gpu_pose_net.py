@@ -273,3 +273,44 @@ def test_learned_pipeline_matches_oracle(gpu, oracle_mod):
             ea, et = pose_err(T[j], ro["T"])
             assert ea <= 1e-5 and et <= 1e-6, (ea, et)
     _say(f"  learned start kept on {kept} of {len(pairs)} pairs")
+
+
+def test_learned_full_workload_sampled(gpu, oracle_mod):
+    # the benchmark's learned leg as it runs: all 512 pairs of 4096 points,
+    # the targets' normals on the GPU, the learned start with 8-start
+    # fallback, in the launch tuning the benchmark applies; sampled pairs
+    # against the oracle's composition given the same normals
+    import os
+    import torch
+    from paper_1807_00399_amd import autotune
+    from paper_1807_00399_amd.train_pose_net import load_params
+    cfg = POSE_CONFIG
+    b = pose_pairs(cfg["eval_config"])
+    off = b.offsets
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1807_00399_amd",
+                        "tuning_cache.json")
+    hit = autotune.load_cache(path).get(autotune.cache_key(autotune._device_name(None), "pose_pairs_512", b.n))
+    params = load_params()
+    d, it, acc = cfg["d_max"], cfg["iters"], cfg["accept_rms"]
+    _say(f"full learned workload {b.name} pairs={b.n_pairs} n={b.n} tuned {hit and hit['tuning']}")
+    src, tgt = _dev(b.source), _dev(b.target)
+    try:
+        if hit is not None:
+            t = hit["tuning"]
+            gpu.set_tuning(t["icp_block_threads"], t["icp_leaf"], t["node_budget"], t["sort_queries"])
+        nrm, _ = gpu.estimate_normals_batched(tgt, off, cfg["k"], curvature=False)
+        T, st, start = gpu.icp_learned_batched(gpu.PC_INIT_LEARNED, torch.from_numpy(params).cuda(), src, off, tgt,
+                                               nrm, off, d, it, accept_rms=acc)
+    finally:
+        gpu.set_tuning(128, 16, 1.0, 1)
+    T, start, nrm = T.cpu().numpy(), start.cpu().numpy(), nrm.cpu().numpy()
+    sample = sorted(np.random.default_rng(13).choice(b.n_pairs, 6, replace=False).tolist())
+    for j in sample:
+        p = b.pairs[j]
+        ro, bo = pn.learned_icp(oracle_mod, params, p.source, p.target, nrm[off[j]:off[j + 1]], float(np.float32(d)),
+                                it, acc)
+        _say(f"  pair {j}: oracle start {bo} rms {ro['rms']:.3g}; gpu start {start[j]} rms {st[j]['rms']:.3g}")
+        assert (start[j] == -1) == (bo == -1), j
+        if bo == -1 or ro["rms"] < acc:
+            ea, et = pose_err(T[j], ro["T"])
+            assert ea <= 1e-5 and et <= 1e-6, (j, ea, et)
