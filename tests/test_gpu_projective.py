@@ -71,3 +71,26 @@ def test_projective_identity_and_no_valid_pixels(gpu, oracle_mod):
     zero[:, 2] = 0.0
     T, st = gpu.icp_projective(_dev(tgt), _dev(zero), _dev(nrm), 160, 120, K, None, 0.2, 4)
     assert st["status"] == 3 and st["iterations_run"] == 0 and st["inliers"] == 0
+
+
+def test_projective_bench_workload(gpu, oracle_mod):
+    # the benchmark's projective step as it runs: two VGA frames, the target
+    # frame's normals on the GPU, projective-association ICP in the launch
+    # tuning the benchmark applies; held to the oracle given the same normals
+    import os
+    from bench import PROJECTIVE as c
+    from paper_1807_00399_amd import autotune
+    src, tgt, C, K = room_views(rng_for(5, 0), c["width"], c["height"], c["angle"], c["t"])
+    path = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1807_00399_amd",
+                        "tuning_cache.json")
+    hit = autotune.load_cache(path).get(autotune.cache_key(autotune._device_name(None), c["name"], src.shape[0]))
+    _say(f"projective bench workload {c['name']} n={src.shape[0]} tuned {hit and hit['tuning']}")
+    try:
+        if hit is not None:
+            t = hit["tuning"]
+            gpu.set_tuning(t["icp_block_threads"], t["icp_leaf"], t["node_budget"], t["sort_queries"])
+        nrm, _ = gpu.estimate_normals(_dev(tgt), c["k"], curvature=False)
+        nrm = nrm.cpu().numpy()
+        _parity(gpu, oracle_mod, src, tgt, nrm, c["width"], c["height"], K, c["d_max"], c["iters"])
+    finally:
+        gpu.set_tuning(128, 16, 1.0, 1)
