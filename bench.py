@@ -1,24 +1,30 @@
 """Benchmark of the point-to-plane ICP hot path on one MI355X.
 
-One step = one pair through the whole path: the target pyramid, PCA normals
-of the target, then point-to-plane ICP (the fixed iteration loop and the
-final statistics pass), in one call (icp_point_to_plane_with_normals, which
-builds the target pyramid once for both).  The call launches kernels only;
-the timed steps replay it captured as a graph (--no-graph: eager launches,
-also reported as eager_pairs_per_s).  Inputs are resident in HBM before
-the timed region; the timed region is bracketed by device synchronisation.
+Default workload (the largest configuration): 256 pairs of uneven sizes
+(5k-200k points each, 11.98 M points per side).  One step = the targets'
+pyramid, the PCA normals of every target and the point-to-plane ICP of every
+pair (the fixed iteration loops and the final statistics passes) in one
+batched call over one pyramid; the call launches kernels only and the timed
+steps replay it captured as a graph.  The per-pair poses of the timed run
+are compared with the oracle's stored results (tests/golden/), and the
+single-pair LiDAR street (2,097,152 points) is timed the same way and
+reported under "street"; a summary of the learned-initialiser workload is
+appended.
 
-    python bench.py [--steps K] [--warmup W] [--workload room|street|sphere|batch|projective|learned]
+    python bench.py [--steps K] [--warmup W] [--workload batch|room|street|sphere|projective|learned]
+
+A single-pair workload's step is one pair through the same path
+(icp_point_to_plane_with_normals, one target pyramid for normals and ICP).
+Inputs are resident in HBM before the timed region; the timed region is
+bracketed by device synchronisation.
 
 Prints one JSON line.  value = pairs/s; the loop-only Mpt*iter/s, the
 roofline of the dominant kernel (the per-iteration correspondence +
-accumulation kernel, timed with HIP events on the library's stream) and a
-CPU-oracle baseline are reported alongside.  The batch workload runs 256
-uneven pairs per step through the batched entry point (one step = normals
-of every target + ICP of every pair over one pyramid, also replayed as a
-captured graph).  The learned workload registers 512
+accumulation kernel, timed with HIP events on the library's stream), the
+pose check against the oracle and a CPU-oracle baseline (with the host CPU
+model) are reported alongside.  The learned workload registers 512
 exact-copy pairs from four starts (plain, 8-start, learned with 8-start
-fallback, learned only); the default run appends a summary of it.
+fallback, learned only).
 """
 from __future__ import annotations
 
@@ -71,7 +77,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="room")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="batch")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-autotune", action="store_true",
@@ -84,9 +90,83 @@ def parse():
                     help="single-pair and batch workloads: time eager launches instead of replays of a captured graph")
     ap.add_argument("--no-learned", action="store_true",
                     help="default run: skip the learned-initialiser comparison")
+    ap.add_argument("--no-street", action="store_true",
+                    help="default run: skip the single-pair street line reported beside the batch")
     ap.add_argument("--copy-probe", action="store_true",
                     help="time a plain 1 GiB device copy (bandwidth and counter calibration) and exit")
     return ap.parse_args()
+
+
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+POSE_TOL_RAD, POSE_TOL_T = 1e-5, 1e-6
+
+
+def cpu_model():
+    """The host CPU's model name and logical CPU count (lscpu)."""
+    import subprocess
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=20).stdout
+    except Exception:
+        return None
+    info = {}
+    for line in out.splitlines():
+        key, _, val = line.partition(":")
+        if key.strip() in ("Model name", "CPU(s)", "Thread(s) per core", "Socket(s)"):
+            info[key.strip()] = val.strip()
+    return info or None
+
+
+def _sha256(a):
+    import hashlib
+    return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+
+def pose_errors(Ta, Tb):
+    """Rotation angle of Ra Rb^T (atan2 form, no acos near 1) and the
+    translation distance, for stacks of 4x4 poses."""
+    Ta = np.asarray(Ta, np.float64).reshape(-1, 4, 4)
+    Tb = np.asarray(Tb, np.float64).reshape(-1, 4, 4)
+    M = Ta[:, :3, :3] @ np.transpose(Tb[:, :3, :3], (0, 2, 1))
+    v = np.stack([M[:, 2, 1] - M[:, 1, 2], M[:, 0, 2] - M[:, 2, 0], M[:, 1, 0] - M[:, 0, 1]], axis=1)
+    rot = np.arctan2(0.5 * np.linalg.norm(v, axis=1), 0.5 * (np.trace(M, axis1=1, axis2=2) - 1.0))
+    tr = np.linalg.norm(Ta[:, :3, 3] - Tb[:, :3, 3], axis=1)
+    return rot, tr
+
+
+def pose_check(T_gpu, T_ref, inl_gpu=None, inl_ref=None, source=""):
+    """The timed poses against the oracle's: worst errors and the number of
+    pairs within the pose tolerance."""
+    rot, tr = pose_errors(T_gpu, T_ref)
+    ok = (rot <= POSE_TOL_RAD) & (tr <= POSE_TOL_T)
+    d = {"oracle": source, "pairs": int(rot.size), "within_tol": int(ok.sum()),
+         "tol": {"rad": POSE_TOL_RAD, "translation": POSE_TOL_T},
+         "max_rot_rad": float(rot.max()), "max_trans": float(tr.max())}
+    if inl_gpu is not None:
+        d["inliers_equal"] = int(np.sum(np.asarray(inl_gpu) == np.asarray(inl_ref)))
+    return d
+
+
+def batch_golden(b):
+    """The oracle's per-pair results for this batch (stored by
+    tests/golden/make_icp_golden.py), if the inputs are the ones it saw."""
+    path = os.path.join(GOLDEN, "icp_batch256.json")
+    if not os.path.exists(path):
+        return None
+    g = json.load(open(path))
+    if (g.get("n_pairs") != b.n_pairs or g.get("sha256_source") != _sha256(b.source)
+            or g.get("sha256_target") != _sha256(b.target) or g.get("sha256_offsets") != _sha256(b.offsets)):
+        return None
+    return g
+
+
+def single_golden(w):
+    path = os.path.join(GOLDEN, "icp_workloads.json")
+    if not os.path.exists(path):
+        return None
+    g = json.load(open(path)).get(w.name)
+    if g is None or g["sha256_source"] != _sha256(w.source) or g["sha256_target"] != _sha256(w.target):
+        return None
+    return g
 
 
 class HipEvents:
@@ -199,7 +279,7 @@ def cpu_baseline(w, budget_s):
         if time.perf_counter() - t0 >= budget_s:
             break
     el = time.perf_counter() - t0
-    return {"value": pairs / el, "unit": "pairs/s", "cores": oracle.num_threads(), "kind": "oracle",
+    return {"value": pairs / el, "unit": "pairs/s", "cores": oracle.num_threads(), "cpu": cpu_model(), "kind": "oracle",
             "sample": f"{pairs} full pair(s) of the same workload (normals + ICP incl. kd-tree builds), "
                       f"{el:.1f} s wall",
             "mpt_iter_per_s": w.n * w.iters * pairs / loop_s / 1e6}
@@ -222,7 +302,7 @@ def cpu_baseline_batch(b, budget_s):
         if time.perf_counter() - t0 >= budget_s:
             break
     el = time.perf_counter() - t0
-    return {"value": pairs / el, "unit": "pairs/s", "cores": oracle.num_threads(), "kind": "oracle",
+    return {"value": pairs / el, "unit": "pairs/s", "cores": oracle.num_threads(), "cpu": cpu_model(), "kind": "oracle",
             "sample": f"the first {pairs} of {b.n_pairs} pairs (normals + ICP incl. kd-tree builds), "
                       f"{el:.1f} s wall",
             "mpt_iter_per_s": pts_iter / loop_s / 1e6}
@@ -306,7 +386,7 @@ def bench_projective(args):
                 break
         el1 = time.perf_counter() - t1
         out["cpu_baseline"] = {"value": pairs / el1, "unit": "pairs/s", "cores": oracle.num_threads(),
-                               "kind": "oracle", "sample": f"{pairs} full pair(s) (normals + ICP), {el1:.1f} s wall",
+                               "cpu": cpu_model(), "kind": "oracle", "sample": f"{pairs} full pair(s) (normals + ICP), {el1:.1f} s wall",
                                "mpt_iter_per_s": n * c["iters"] * pairs / loop_s / 1e6}
     print(json.dumps(out), flush=True)
 
@@ -336,7 +416,7 @@ def cpu_baseline_learned(b, gpu_T, budget_s):
         if time.perf_counter() - t0 >= budget_s:
             break
     el = time.perf_counter() - t0
-    return {"value": pairs / el, "unit": "pairs/s", "cores": oracle.num_threads(), "kind": "oracle",
+    return {"value": pairs / el, "unit": "pairs/s", "cores": oracle.num_threads(), "cpu": cpu_model(), "kind": "oracle",
             "sample": f"the first {pairs} of {b.n_pairs} pairs, 8-start ICP each (normals + 8 registrations), "
                       f"{el:.1f} s wall",
             "gpu_learned_agrees_with_oracle_8_start": f"{agree}/{pairs}"}
@@ -575,40 +655,30 @@ def bench_batch(args):
                      "kernel": "k_icp_accum", "avg_kernel_us": float(kern.mean()) * 1e6,
                      "algorithmic_bytes_per_launch": float(ICP_BYTES_PER_POINT * active.mean())},
     }
+    g = batch_golden(b)
+    Tn = T.cpu().numpy()
+    if g is not None:
+        out["pose_vs_oracle"] = pose_check(
+            Tn, np.array([p["T"] for p in g["pairs"]]), [r["inliers"] for r in st],
+            [p["inliers"] for p in g["pairs"]],
+            source="tests/golden/icp_batch256.json (oracle kd-tree normals + float64 ICP, input digests matched)")
+    else:
+        out["pose_vs_oracle"] = None
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_batch(b, args.cpu_seconds)
-    print(json.dumps(out), flush=True)
+    return out
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path is not sharded across GPUs",
-              file=sys.stderr)
-        sys.exit(2)
+def bench_single(args, workload, with_cpu=True):
+    """One pair per step: target pyramid + normals + ICP in one call."""
     import torch
 
     from gen import make_workload
     from paper_1807_00399_amd import pcgpu
-
-    assert torch.cuda.is_available(), "bench.py needs a GPU"
-    if args.copy_probe:
-        copy_probe()
-        return
-    if args.workload == "batch":
-        bench_batch(args)
-        return
-    if args.workload == "projective":
-        bench_projective(args)
-        return
-    if args.workload == "learned":
-        bench_learned(args)
-        return
     dev = torch.device("cuda:0")
-    w = make_workload(WORKLOADS[args.workload])
+    w = make_workload(WORKLOADS[workload])
     src = torch.from_numpy(w.source).to(dev)
     tgt = torch.from_numpy(w.target).to(dev)
-    stream = torch.cuda.current_stream()
     T = torch.empty((4, 4), dtype=torch.float64, device=dev)
     stats = torch.zeros(24, dtype=torch.uint8, device=dev)
     ws = torch.empty(pcgpu.lib.icp_point_to_plane_with_normals_workspace_size(w.n, w.n, w.iters),
@@ -673,7 +743,7 @@ def main():
     loop_s = float(np.median(loop_ms)) * 1e-3
     algo_bytes = ICP_BYTES_PER_POINT * w.n
     achieved = algo_bytes / avg_kernel_s / 1e9
-    traffic = traffic_from_profiles("icp_accum", args.workload)
+    traffic = traffic_from_profiles("icp_accum", workload)
 
     out = {
         "metric": METRIC,
@@ -702,14 +772,50 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "k_icp_accum", "avg_kernel_us": avg_kernel_s * 1e6,
                      "algorithmic_bytes_per_launch": algo_bytes,
-                     "valu_issue_share": valu_from_profiles(args.workload)},
+                     "valu_issue_share": valu_from_profiles(workload)},
     }
+    g = single_golden(w)
+    out["pose_vs_oracle"] = None if g is None else pose_check(
+        T.cpu().numpy(), np.array(g["T"]), [st["inliers"]], [g["inliers"]],
+        source="tests/golden/icp_workloads.json (oracle kd-tree normals + float64 ICP, input digests matched)")
+    if with_cpu and not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
+    return out
+
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the path is not sharded across GPUs",
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.copy_probe:
+        copy_probe()
+        return
+    if args.workload == "projective":
+        bench_projective(args)
+        return
+    if args.workload == "learned":
+        bench_learned(args)
+        return
+    if args.workload != "batch":
+        print(json.dumps(bench_single(args, args.workload)), flush=True)
+        return
+    out = bench_batch(args)
+    if not args.no_street:
+        # the single-pair LiDAR street (2,097,152 points), timed the same way
+        s = bench_single(args, "street", with_cpu=False)
+        out["street"] = {k: s[k] for k in ("value", "unit", "ms_per_step", "eager_pairs_per_s", "mpt_iter_per_s",
+                                           "loop_ms", "config", "icp_status", "tuning", "roofline",
+                                           "pose_vs_oracle")}
     if not args.no_learned:
         info = learned_legs(min(args.steps, 5), 1, args)[0]
         out["learned_vs_plain"] = {"workload": info["workload"], "legs": info["legs"],
                                    "learned_init_rotation_error_deg": info["learned_init_rotation_error_deg"]}
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(out), flush=True)
 
 

@@ -288,6 +288,53 @@ def test_batched_full_workload_fused_bench_tuning(gpu, oracle_mod):
         assert stats[j]["inliers"] == ro["inliers"], (j, stats[j]["inliers"], ro["inliers"])
 
 
+def test_batched_full_workload_every_pair_vs_oracle(gpu):
+    # the benchmark's batch step as it runs (fused normals + ICP over one
+    # pyramid, the launch tuning the benchmark applies) against the oracle's
+    # end-to-end result for every one of the 256 pairs: its own kd-tree
+    # normals and float64 ICP, stored with input digests by
+    # tests/golden/make_icp_golden.py (oracle only)
+    import hashlib
+    import json
+    import os
+    from paper_1807_00399_amd import autotune
+    b = batch_workload(3)
+    off = b.offsets
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "icp_batch256.json")
+    g = json.load(open(path))
+
+    def digest(a):
+        return hashlib.sha256(np.ascontiguousarray(a).tobytes()).hexdigest()
+
+    assert g["sha256_source"] == digest(b.source) and g["sha256_target"] == digest(b.target) \
+        and g["sha256_offsets"] == digest(off), "stored oracle results are for other inputs"
+    cache = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_1807_00399_amd",
+                         "tuning_cache.json")
+    hit = autotune.load_cache(cache).get(autotune.cache_key(autotune._device_name(None), "uneven_pairs_256", b.n))
+    tun = hit["tuning"] if hit else gpu.get_tuning()
+    _say(f"full fused batch {b.name} n={b.n} every pair vs oracle, tuning {tun}")
+    try:
+        gpu.set_tuning(tun["icp_block_threads"], tun["icp_leaf"], tun["node_budget"], tun["sort_queries"])
+        T, stats = gpu.icp_point_to_plane_with_normals_batched(_dev(b.source), off, _dev(b.target), off,
+                                                               b.param("k").astype(np.int32), (0.0, 0.0, 0.0), None,
+                                                               b.param("d_max").astype(np.float32),
+                                                               b.param("iters").astype(np.int32))
+    finally:
+        gpu.set_tuning(128, 16, 1.0, 1)
+    T = T.cpu().numpy()
+    bad = []
+    worst = (0.0, 0.0)
+    for j, p in enumerate(g["pairs"]):
+        ea, et = pose_err(T[j], np.array(p["T"]).reshape(4, 4))
+        worst = (max(worst[0], ea), max(worst[1], et))
+        s = stats[j]
+        if not (ea <= ROT_TOL and et <= TRANS_TOL and s["inliers"] == p["inliers"] and s["status"] == p["status"]
+                and s["iterations_run"] == p["iterations"]):
+            bad.append((j, ea, et, s["inliers"], p["inliers"], s["status"], p["status"]))
+    _say(f"worst pose error {worst[0]:.3g} rad {worst[1]:.3g}; {len(bad)} pairs off")
+    assert not bad, bad[:8]
+
+
 def test_tunings_give_the_same_results(gpu, oracle_mod, small_batch):
     # every launch shape, pyramid depth and query order finds the same
     # correspondences; the block size and the query order only regroup the

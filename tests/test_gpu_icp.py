@@ -53,9 +53,11 @@ def _parity(gpu, oracle_mod, src, tgt, nrm, T0, d_max, iters, tol=0.0, label="")
     assert sg["status"] == ro["status"], (sg, ro["status"])
     assert sg["iterations_run"] == ro["iterations"]
     assert ea <= ROT_TOL and et <= TRANS_TOL, f"pose differs: {ea:.3g} rad, {et:.3g}"
-    # correspondence decisions are certified in float64, so counts agree
-    # unless the two poses straddle a decision (rare)
-    assert abs(sg["inliers"] - ro["inliers"]) <= max(2, 1e-5 * len(src))
+    # every correspondence decision equals the float64 one at the GPU's own
+    # pose, and that pose agrees with the oracle's to ~1e-11: a count could
+    # differ only through a point that close to d_max or to a tie, and the
+    # seeded inputs have none, so the counts are held equal
+    assert sg["inliers"] == ro["inliers"], (sg["inliers"], ro["inliers"])
     return Tg, sg, ro
 
 

@@ -36,7 +36,11 @@ def _check(Tg, sg, ro, n):
     assert sg["status"] == ro["status"], (sg, ro["status"])
     assert sg["iterations_run"] == ro["iterations"]
     assert ea <= ROT_TOL and et <= TRANS_TOL, f"pose differs: {ea:.3g} rad, {et:.3g}"
-    assert abs(sg["inliers"] - ro["inliers"]) <= max(2, 1e-5 * n)
+    # every correspondence decision equals the float64 one at the GPU's own
+    # pose, and that pose agrees with the oracle's to ~1e-11: a count could
+    # differ only through a point that close to d_max or to a tie, and the
+    # seeded inputs have none, so the counts are held equal
+    assert sg["inliers"] == ro["inliers"], (sg["inliers"], ro["inliers"])
 
 
 @pytest.mark.parametrize("cfg,size", [(0, "small"), (0, "full"), (1, "small"), (2, "small")])

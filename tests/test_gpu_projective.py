@@ -38,7 +38,11 @@ def _parity(gpu, oracle_mod, src, tgt, nrm, W, H, K, d_max, iters, T0=None):
     ea, et = pose_err(T.cpu().numpy(), ro["T"])
     assert st["status"] == ro["status"] and st["iterations_run"] == ro["iterations"], (st, ro)
     assert ea <= ROT_TOL and et <= TRANS_TOL, f"pose differs: {ea:.3g} rad, {et:.3g}"
-    assert abs(st["inliers"] - ro["inliers"]) <= max(2, 1e-5 * len(src))
+    # every correspondence decision equals the float64 one at the GPU's own
+    # pose, and that pose agrees with the oracle's to ~1e-11: a count could
+    # differ only through a point that close to d_max or to a tie, and the
+    # seeded inputs have none, so the counts are held equal
+    assert st["inliers"] == ro["inliers"], (st["inliers"], ro["inliers"])
     return T.cpu().numpy(), st, ro
 
 
