@@ -139,8 +139,20 @@ def _check(st: int, what: str):
         raise PcgpuError(st, what)
 
 
-def _stream(stream=None) -> int:
-    s = stream if stream is not None else torch.cuda.current_stream()
+def _stream(stream=None, scope=None) -> int:
+    """The HIP stream handle to launch on.  Inputs, outputs and workspaces
+    are allocated (and the initial pose copied) on torch's current stream;
+    when another stream is given, it first waits for the current one, and
+    every device tensor in `scope` (the caller's locals) is recorded as in
+    use on it, so the caching allocator does not hand that memory out
+    while the library's kernels may still use it."""
+    cur = torch.cuda.current_stream()
+    s = stream if stream is not None else cur
+    if s != cur:
+        s.wait_stream(cur)
+        for v in (scope or {}).values():
+            if isinstance(v, torch.Tensor) and v.is_cuda:
+                v.record_stream(s)
     return int(s.cuda_stream)
 
 
@@ -185,7 +197,7 @@ def knn_search(ref: torch.Tensor, qry: torch.Tensor, k: int, return_d2: bool = T
     need = lib.knn_search_workspace_size(ref.shape[0], nq, k)
     ws = workspace if workspace is not None else _ws.get(need, ref.device)
     st = lib.knn_search(ref.data_ptr(), ref.shape[0], qry.data_ptr(), nq, int(k), idx.data_ptr(), _ptr(d2),
-                        ws.data_ptr(), ws.numel(), _stream(stream))
+                        ws.data_ptr(), ws.numel(), _stream(stream, locals()))
     _check(st, "knn_search")
     return idx, d2
 
@@ -201,7 +213,7 @@ def estimate_normals(xyz: torch.Tensor, k: int, viewpoint=(0.0, 0.0, 0.0), curva
     need = lib.estimate_normals_workspace_size(n, k)
     ws = workspace if workspace is not None else _ws.get(need, xyz.device)
     st = lib.estimate_normals(xyz.data_ptr(), n, int(k), vp, nrm.data_ptr(), _ptr(cur), ws.data_ptr(),
-                              ws.numel(), _stream(stream))
+                              ws.numel(), _stream(stream, locals()))
     _check(st, "estimate_normals")
     return nrm, cur
 
@@ -218,7 +230,7 @@ def estimate_normals_radius(xyz: torch.Tensor, radius: float, k: int = 0, viewpo
     need = lib.estimate_normals_workspace_size(n, max(int(k), 1))
     ws = workspace if workspace is not None else _ws.get(need, xyz.device)
     st = lib.estimate_normals_radius(xyz.data_ptr(), n, float(radius), int(k), vp, nrm.data_ptr(), _ptr(cur),
-                                     ws.data_ptr(), ws.numel(), _stream(stream))
+                                     ws.data_ptr(), ws.numel(), _stream(stream, locals()))
     _check(st, "estimate_normals_radius")
     return nrm, cur
 
@@ -249,7 +261,7 @@ def icp_point_to_plane(src: torch.Tensor, tgt: torch.Tensor, tgt_normals: torch.
     ws = workspace if workspace is not None else _ws.get(need, dev)
     st = lib.icp_point_to_plane(src.data_ptr(), src.shape[0], tgt.data_ptr(), tgt_normals.data_ptr(),
                                 tgt.shape[0], _ptr(T0), float(max_corr_dist), int(max_iters), float(conv_tol),
-                                T.data_ptr(), stats.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream))
+                                T.data_ptr(), stats.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream, locals()))
     _check(st, "icp_point_to_plane")
     if not read_stats:
         return T, stats
@@ -283,7 +295,7 @@ def icp_point_to_plane_with_normals(src: torch.Tensor, tgt: torch.Tensor, k: int
     st = lib.icp_point_to_plane_with_normals(src.data_ptr(), src.shape[0], tgt.data_ptr(), tgt.shape[0], int(k), vp,
                                              _ptr(T0), float(max_corr_dist), int(max_iters), float(conv_tol),
                                              T.data_ptr(), stats.data_ptr(), _ptr(nrm), ws.data_ptr(), ws.numel(),
-                                             _stream(stream))
+                                             _stream(stream, locals()))
     _check(st, "icp_point_to_plane_with_normals")
     out = (T, stats if not read_stats else decode_stats(stats))
     return out + (nrm,) if (return_normals or out_normals is not None) else out
@@ -308,11 +320,11 @@ def _icp_variant(fn, what, src, tgt, tgt_normals, init_T, max_corr_dist, max_ite
     if weights is None:
         st = fn(src.data_ptr(), src.shape[0], tgt.data_ptr(), tgt.shape[0], _ptr(T0), float(max_corr_dist),
                 int(max_iters), float(conv_tol), T.data_ptr(), stats.data_ptr(), ws.data_ptr(), ws.numel(),
-                _stream(stream))
+                _stream(stream, locals()))
     else:
         st = fn(src.data_ptr(), src.shape[0], tgt.data_ptr(), _ptr(tgt_normals), tgt.shape[0], _ptr(T0),
                 float(weights[0]), float(weights[1]), float(max_corr_dist), int(max_iters), float(conv_tol),
-                T.data_ptr(), stats.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream))
+                T.data_ptr(), stats.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream, locals()))
     _check(st, what)
     return T, decode_stats(stats)
 
@@ -355,7 +367,7 @@ def icp_projective(src: torch.Tensor, tgt: torch.Tensor, tgt_normals: torch.Tens
     ws = workspace if workspace is not None else _ws.get(need, dev)
     st = lib.icp_projective(src.data_ptr(), src.shape[0], tgt.data_ptr(), tgt_normals.data_ptr(), int(width),
                             int(height), K, _ptr(T0), float(max_corr_dist), int(max_iters), float(conv_tol),
-                            T.data_ptr(), stats.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream))
+                            T.data_ptr(), stats.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream, locals()))
     _check(st, "icp_projective")
     if not read_stats:
         return T, stats
@@ -416,7 +428,7 @@ def estimate_normals_batched(xyz: torch.Tensor, offsets, k, viewpoint=(0.0, 0.0,
     need = lib.estimate_normals_batched_workspace_size(m, off.ctypes.data)
     ws = workspace if workspace is not None else _ws.get(need, xyz.device)
     st = lib.estimate_normals_batched(m, xyz.data_ptr(), off.ctypes.data, kc.ctypes.data, vp, nrm.data_ptr(),
-                                      _ptr(cur), ws.data_ptr(), ws.numel(), _stream(stream))
+                                      _ptr(cur), ws.data_ptr(), ws.numel(), _stream(stream, locals()))
     _check(st, "estimate_normals_batched")
     return nrm, cur
 
@@ -450,7 +462,7 @@ def icp_point_to_plane_batched(src: torch.Tensor, src_off, tgt: torch.Tensor, tg
     ws = workspace if workspace is not None else _ws.get(need, dev)
     st = lib.icp_point_to_plane_batched(m, src.data_ptr(), so.ctypes.data, tgt.data_ptr(), tgt_normals.data_ptr(),
                                         to.ctypes.data, _ptr(T0), dm.ctypes.data, mi.ctypes.data, float(conv_tol),
-                                        T.data_ptr(), stats.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream))
+                                        T.data_ptr(), stats.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream, locals()))
     _check(st, "icp_point_to_plane_batched")
     if not read_stats:
         return T, stats
@@ -492,7 +504,7 @@ def icp_point_to_plane_with_normals_batched(src: torch.Tensor, src_off, tgt: tor
     st = lib.icp_point_to_plane_with_normals_batched(m, src.data_ptr(), so.ctypes.data, tgt.data_ptr(),
                                                      to.ctypes.data, kk.ctypes.data, vpt, _ptr(T0), dm.ctypes.data,
                                                      mi.ctypes.data, float(conv_tol), T.data_ptr(), stats.data_ptr(),
-                                                     _ptr(out_normals), ws.data_ptr(), ws.numel(), _stream(stream))
+                                                     _ptr(out_normals), ws.data_ptr(), ws.numel(), _stream(stream, locals()))
     _check(st, "icp_point_to_plane_with_normals_batched")
     if not read_stats:
         return T, stats
@@ -519,7 +531,7 @@ def get_tuning() -> dict:
 
 
 def copy_probe(dst: torch.Tensor, src: torch.Tensor, stream=None):
-    _check(lib.pc_copy_probe(dst.data_ptr(), src.data_ptr(), src.numel() * src.element_size(), _stream(stream)),
+    _check(lib.pc_copy_probe(dst.data_ptr(), src.data_ptr(), src.numel() * src.element_size(), _stream(stream, locals())),
            "pc_copy_probe")
 
 
@@ -555,7 +567,7 @@ def pose_net_predict(params: torch.Tensor, src: torch.Tensor, src_off, tgt: torc
     need = lib.pose_net_workspace_size(m, so.ctypes.data, to.ctypes.data)
     ws = workspace if workspace is not None else _ws.get(need, src.device)
     _check(lib.pose_net_predict(params.data_ptr(), m, src.data_ptr(), so.ctypes.data, tgt.data_ptr(), to.ctypes.data,
-                                T.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream)), "pose_net_predict")
+                                T.data_ptr(), ws.data_ptr(), ws.numel(), _stream(stream, locals())), "pose_net_predict")
     return T
 
 
@@ -581,7 +593,7 @@ def pose_net_train_step(params: torch.Tensor, adam_m, adam_v, step: int, lr: flo
     _check(lib.pose_net_train_step(params.data_ptr(), _ptr(adam_m) if lr > 0 else None,
                                    _ptr(adam_v) if lr > 0 else None, int(step), float(lr), m, src.data_ptr(),
                                    so.ctypes.data, tgt.data_ptr(), to.ctypes.data, lab.data_ptr(), _ptr(w),
-                                   loss.data_ptr(), _ptr(grad), ws.data_ptr(), ws.numel(), _stream(stream)),
+                                   loss.data_ptr(), _ptr(grad), ws.data_ptr(), ws.numel(), _stream(stream, locals())),
            "pose_net_train_step")
     return loss, grad
 
@@ -613,7 +625,7 @@ def icp_learned_batched(mode: int, params, src: torch.Tensor, src_off, tgt: torc
                                    src.data_ptr(), so.ctypes.data, tgt.data_ptr(), tgt_normals.data_ptr(),
                                    to.ctypes.data, float(max_corr_dist), int(max_iters), float(conv_tol),
                                    float(accept_rms), T.data_ptr(), stats.data_ptr(), start.data_ptr(),
-                                   ws.data_ptr(), ws.numel(), _stream(stream)), "icp_learned_batched")
+                                   ws.data_ptr(), ws.numel(), _stream(stream, locals())), "icp_learned_batched")
     if not read_stats:
         return T, stats, start
     return T, decode_stats_batched(stats), start
