@@ -174,6 +174,28 @@ pc_status icp_point_to_plane(const float *src_xyz, int64_t n_src,
                              double conv_tol, double *out_T, pc_icp_stats *out_stats,
                              void *workspace, size_t workspace_bytes, hipStream_t stream);
 
+/* icp_point_to_plane_noalloc -- icp_point_to_plane for callers that
+ * cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc).  Same arguments, results
+ * and kernels as icp_point_to_plane, without the workspace: the library
+ * uses a device scratch array of PCGPU_NOALLOC_SCRATCH_BYTES that it holds
+ * on each GPU it runs on from the first such call until the process ends.
+ * The call itself allocates and frees nothing.
+ *   Returns PC_EWORKSPACE, before any device work, when
+ *   icp_point_to_plane_workspace_size(n_src, n_tgt, max_iters) exceeds
+ *   PCGPU_NOALLOC_SCRATCH_BYTES (about 340,000 points per cloud at 30
+ *   iterations); PC_EDEVICE when the scratch address cannot be obtained.
+ * Every call on one GPU shares that GPU's scratch, and the scratch keeps the
+ * last call's contents (each call initialises what it reads): calls that
+ * overlap on one GPU (concurrent streams or threads) race and must be
+ * serialised by the caller. */
+#define PCGPU_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+pc_status icp_point_to_plane_noalloc(const float *src_xyz, int64_t n_src,
+                                     const float *tgt_xyz, const float *tgt_normals, int64_t n_tgt,
+                                     const double *init_T, float max_corr_dist, int max_iters,
+                                     double conv_tol, double *out_T, pc_icp_stats *out_stats,
+                                     hipStream_t stream);
+
 /* icp_point_to_plane with the target normals estimated in the same call:
  * the target pyramid is built once and serves both the normals
  * (estimate_normals with k and viewpoint) and the correspondences.  The

@@ -3,6 +3,7 @@
 #include <math.h>
 #include <string.h>
 
+#include <mutex>
 #include <vector>
 
 #include "icp.h"
@@ -62,6 +63,31 @@ __global__ void k_copy16(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
 {
     for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
         dst[i] = src[i];
+}
+
+// Scratch of icp_point_to_plane_noalloc: a file-scope device array, one
+// copy per GPU, resident from the code object's load until the process
+// ends.  Host code never uses its name as an address (on the host it is a
+// stand-in symbol); the device address of the current GPU's copy comes from
+// hipGetSymbolAddress, taken once per device with that device current.
+__device__ __align__(256) unsigned char scratch[PCGPU_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+// the current device's scratch address, or nullptr when it cannot be had
+void *noalloc_scratch()
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
 }
 
 }  // namespace
@@ -274,6 +300,20 @@ size_t icp_point_to_plane_workspace_size(int64_t n_src, int64_t n_tgt, int max_i
 
 namespace {
 
+// the single-pair ICP arguments other than the workspace (host only)
+bool icp_single_args_ok(const float *src_xyz, int64_t n_src, const float *tgt_xyz, const float *tgt_normals,
+                        int64_t n_tgt, const double *init_T, float max_corr_dist, int max_iters, double conv_tol,
+                        const double *out_T, const pc_icp_stats *out_stats, bool need_normals)
+{
+    if (n_src < 0 || n_tgt < 0 || n_src >= kMaxPoints || n_tgt >= kMaxPoints) return false;
+    if (max_iters < 0 || !(max_corr_dist > 0.f) || !isfinite(max_corr_dist)) return false;
+    if (!(conv_tol >= 0.0) || !isfinite(conv_tol)) return false;
+    if (!out_T) return false;
+    if ((n_src > 0 && !src_xyz) || (n_tgt > 0 && (!tgt_xyz || (need_normals && !tgt_normals)))) return false;
+    return aligned(src_xyz, 4) && aligned(tgt_xyz, 4) && aligned(tgt_normals, 4) && aligned(init_T, 8) &&
+           aligned(out_T, 8) && aligned(out_stats, 8);
+}
+
 // single-pair ICP with any metric (0 point-to-plane, 1 point-to-point, 2 combined)
 pc_status icp_single(const float *src_xyz, int64_t n_src, const float *tgt_xyz, const float *tgt_normals,
                      int64_t n_tgt, const double *init_T, float max_corr_dist, int max_iters, double conv_tol,
@@ -281,14 +321,10 @@ pc_status icp_single(const float *src_xyz, int64_t n_src, const float *tgt_xyz, 
                      hipStream_t stream, int metric, float w_point, float w_plane)
 {
     const bool need_normals = metric == 0 || (metric == 2 && w_plane > 0.f);
-    if (n_src < 0 || n_tgt < 0 || n_src >= kMaxPoints || n_tgt >= kMaxPoints) return PC_EINVAL;
-    if (max_iters < 0 || !(max_corr_dist > 0.f) || !isfinite(max_corr_dist)) return PC_EINVAL;
-    if (!(conv_tol >= 0.0) || !isfinite(conv_tol)) return PC_EINVAL;
-    if (!out_T || !workspace) return PC_EINVAL;
-    if ((n_src > 0 && !src_xyz) || (n_tgt > 0 && (!tgt_xyz || (need_normals && !tgt_normals)))) return PC_EINVAL;
-    if (!aligned(src_xyz, 4) || !aligned(tgt_xyz, 4) || !aligned(tgt_normals, 4) || !aligned(init_T, 8) ||
-        !aligned(out_T, 8) || !aligned(out_stats, 8) || !aligned(workspace, 256))
+    if (!icp_single_args_ok(src_xyz, n_src, tgt_xyz, tgt_normals, n_tgt, init_T, max_corr_dist, max_iters,
+                            conv_tol, out_T, out_stats, need_normals))
         return PC_EINVAL;
+    if (!workspace || !aligned(workspace, 256)) return PC_EINVAL;
     if (workspace_bytes < icp_point_to_plane_workspace_size(n_src, n_tgt, max_iters)) return PC_EWORKSPACE;
     Carver c(workspace, workspace_bytes);
     IcpStore s;
@@ -312,6 +348,23 @@ pc_status icp_point_to_plane(const float *src_xyz, int64_t n_src, const float *t
 {
     return icp_single(src_xyz, n_src, tgt_xyz, tgt_normals, n_tgt, init_T, max_corr_dist, max_iters, conv_tol,
                       out_T, out_stats, workspace, workspace_bytes, stream, 0, 0.f, 1.f);
+}
+
+pc_status icp_point_to_plane_noalloc(const float *src_xyz, int64_t n_src, const float *tgt_xyz,
+                                     const float *tgt_normals, int64_t n_tgt, const double *init_T,
+                                     float max_corr_dist, int max_iters, double conv_tol, double *out_T,
+                                     pc_icp_stats *out_stats, hipStream_t stream)
+{
+    // every check on the host first: a rejected call does no device work
+    if (!icp_single_args_ok(src_xyz, n_src, tgt_xyz, tgt_normals, n_tgt, init_T, max_corr_dist, max_iters,
+                            conv_tol, out_T, out_stats, true))
+        return PC_EINVAL;
+    if (icp_point_to_plane_workspace_size(n_src, n_tgt, max_iters) > PCGPU_NOALLOC_SCRATCH_BYTES)
+        return PC_EWORKSPACE;
+    void *ws = noalloc_scratch();
+    if (!ws) return PC_EDEVICE;
+    return icp_single(src_xyz, n_src, tgt_xyz, tgt_normals, n_tgt, init_T, max_corr_dist, max_iters, conv_tol,
+                      out_T, out_stats, ws, PCGPU_NOALLOC_SCRATCH_BYTES, stream, 0, 0.f, 1.f);
 }
 
 size_t icp_point_to_plane_with_normals_workspace_size(int64_t n_src, int64_t n_tgt, int max_iters)

@@ -24,7 +24,8 @@ EXPORTS = (
     "pc_status_string",
     "knn_search_workspace_size", "knn_search",
     "estimate_normals_workspace_size", "estimate_normals", "estimate_normals_radius",
-    "icp_point_to_plane_workspace_size", "icp_point_to_plane", "icp_point_to_point", "icp_combined",
+    "icp_point_to_plane_workspace_size", "icp_point_to_plane", "icp_point_to_plane_noalloc",
+    "icp_point_to_point", "icp_combined",
     "icp_point_to_plane_with_normals_workspace_size", "icp_point_to_plane_with_normals",
     "icp_projective_workspace_size", "icp_projective",
     "estimate_normals_batched_workspace_size", "estimate_normals_batched",
@@ -73,6 +74,8 @@ def _load() -> ctypes.CDLL:
     lib.icp_point_to_plane_workspace_size.restype = sz
     lib.icp_point_to_plane.argtypes = [vp, i64, vp, vp, i64, vp, f32, i32, f64, vp, vp, vp, sz, vp]
     lib.icp_point_to_plane.restype = ctypes.c_int
+    lib.icp_point_to_plane_noalloc.argtypes = [vp, i64, vp, vp, i64, vp, f32, i32, f64, vp, vp, vp]
+    lib.icp_point_to_plane_noalloc.restype = ctypes.c_int
     lib.icp_point_to_plane_with_normals_workspace_size.argtypes = [i64, i64, i32]
     lib.icp_point_to_plane_with_normals_workspace_size.restype = sz
     lib.icp_point_to_plane_with_normals.argtypes = [vp, i64, vp, i64, i32, ctypes.POINTER(ctypes.c_float), vp, f32,
@@ -266,6 +269,35 @@ def icp_point_to_plane(src: torch.Tensor, tgt: torch.Tensor, tgt_normals: torch.
     if not read_stats:
         return T, stats
     return T, decode_stats(stats)
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20
+
+
+def icp_point_to_plane_noalloc(src: torch.Tensor, tgt: torch.Tensor, tgt_normals: torch.Tensor, out_T: torch.Tensor,
+                               out_stats: torch.Tensor, init_T: torch.Tensor | None = None,
+                               max_corr_dist: float = 0.05, max_iters: int = 30, conv_tol: float = 0.0,
+                               stream=None):
+    """icp_point_to_plane on the library's static device scratch (no
+    workspace): the caller passes every buffer, outputs included
+    (out_T (4,4) float64, out_stats 24 uint8, init_T (4,4) float64 or
+    None, all on the device), and nothing is allocated here."""
+    for t, name in ((src, "src"), (tgt, "tgt"), (tgt_normals, "tgt_normals")):
+        if not (t.is_cuda and t.dtype == torch.float32 and t.dim() == 2 and t.shape[1] == 3 and t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous float32 (n, 3) device tensor")
+    if tgt_normals.shape[0] != tgt.shape[0]:
+        raise ValueError("tgt_normals must match tgt")
+    if not (out_T.dtype == torch.float64 and out_T.numel() == 16 and out_T.is_cuda):
+        raise ValueError("out_T must be a (4, 4) float64 device tensor")
+    if not (out_stats.dtype == torch.uint8 and out_stats.numel() >= 24 and out_stats.is_cuda):
+        raise ValueError("out_stats must be a 24-byte uint8 device tensor")
+    if init_T is not None and not (init_T.dtype == torch.float64 and init_T.numel() == 16 and init_T.is_cuda):
+        raise ValueError("init_T must be a (4, 4) float64 device tensor")
+    st = lib.icp_point_to_plane_noalloc(src.data_ptr(), src.shape[0], tgt.data_ptr(), tgt_normals.data_ptr(),
+                                        tgt.shape[0], _ptr(init_T), float(max_corr_dist), int(max_iters),
+                                        float(conv_tol), out_T.data_ptr(), out_stats.data_ptr(),
+                                        _stream(stream, locals()))
+    _check(st, "icp_point_to_plane_noalloc")
 
 
 def icp_point_to_plane_with_normals(src: torch.Tensor, tgt: torch.Tensor, k: int, viewpoint=(0.0, 0.0, 0.0),

@@ -103,6 +103,29 @@ def test_icp_rejects_bad_arguments(pc):
     assert call(wb=ws - 1) == pc.PC_EWORKSPACE
 
 
+def test_icp_noalloc_rejects_bad_arguments(pc):
+    # every rejection is decided on the host, before the library touches a
+    # device: bad arguments, and requests beyond the static scratch
+    L = pc.lib
+
+    def call(src=FAKE, ns=100, tgt=FAKE, nrm=FAKE, nt=100, T0=None, d=0.1, it=5, tol=0.0, out=FAKE):
+        return L.icp_point_to_plane_noalloc(src, ns, tgt, nrm, nt, T0, d, it, tol, out, None, None)
+
+    assert call(d=0.0) == pc.PC_EINVAL
+    assert call(it=-1) == pc.PC_EINVAL
+    assert call(out=None) == pc.PC_EINVAL
+    assert call(nrm=None) == pc.PC_EINVAL
+    assert call(ns=-5) == pc.PC_EINVAL
+    assert call(T0=FAKE + 4) == pc.PC_EINVAL
+    m = re.search(r"#define PCGPU_NOALLOC_SCRATCH_BYTES \(\(size_t\)(\d+) << (\d+)\)", open(HEADER).read())
+    assert m and int(m.group(1)) << int(m.group(2)) == pc.NOALLOC_SCRATCH_BYTES
+    big = 400_000
+    assert L.icp_point_to_plane_workspace_size(big, big, 30) > pc.NOALLOC_SCRATCH_BYTES
+    assert call(ns=big, nt=big, it=30) == pc.PC_EWORKSPACE
+    # the largest single cloud pair that fits is about 340k points at 30 iterations
+    assert L.icp_point_to_plane_workspace_size(307_200, 307_200, 30) <= pc.NOALLOC_SCRATCH_BYTES
+
+
 def test_copy_probe_rejects_bad_arguments(pc):
     assert pc.lib.pc_copy_probe(FAKE, FAKE, 17, None) == pc.PC_EINVAL
     assert pc.lib.pc_copy_probe(None, FAKE, 16, None) == pc.PC_EINVAL
