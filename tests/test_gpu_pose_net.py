@@ -17,13 +17,13 @@ pytestmark = pytest.mark.gpu
 
 # forward: both sides round the same activations and weights to bfloat16,
 # but the GPU accumulates in float32 where the oracle uses float64 (relative
-# error ~1e-6 in the features, observed 2e-6 rad in the rotation); an
-# activation on the other side of a bfloat16 rounding boundary moves one
-# term by 2^-8 of itself, which the 1e-4 bound still covers
-FWD_ROT_TOL = 1e-4
-# gradient: float32 sums (observed ~7e-6 relative per tensor) plus the same
-# rare rounding flips; relative L2 error per parameter tensor
-GRAD_REL_TOL = 1e-3
+# error ~1e-6 in the features; observed up to 2e-6 rad in the rotation,
+# including the rare activation that lands on the other side of a bfloat16
+# rounding boundary): held to 10x the observed error
+FWD_ROT_TOL = 2e-5
+# gradient: float32 sums against float64 ones, observed up to 7e-6 relative
+# L2 error per parameter tensor: held to about 10x that
+GRAD_REL_TOL = 1e-4
 
 
 @pytest.fixture(scope="module")
@@ -138,7 +138,7 @@ def test_gradient_matches_oracle(gpu):
         ref = np.linalg.norm(g[a:b])
         err = np.linalg.norm(gg[a:b] - g[a:b])
         _say(f"  {name}: |g| {ref:.4g}, relative error {err / max(ref, 1e-30):.3g}")
-        assert err <= GRAD_REL_TOL * ref + 1e-6, (name, err, ref)
+        assert err <= GRAD_REL_TOL * ref + 1e-9, (name, err, ref)
 
 
 def test_adam_step_and_determinism(gpu):

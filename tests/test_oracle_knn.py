@@ -126,6 +126,70 @@ def test_brute_key_is_float32_fma(oracle_mod):
         assert np.all(np.diff(d2[i]) >= 0)
 
 
+def _round_f32(x):
+    """Exact rounding of a rational to the nearest float32 (ties to even),
+    subnormals and overflow included, written out from the IEEE 754
+    definition on exact fractions."""
+    from fractions import Fraction
+    if x == 0:
+        return np.float32(0.0)
+    sign = -1 if x < 0 else 1
+    a = abs(Fraction(x))
+    e = a.numerator.bit_length() - a.denominator.bit_length()
+    while Fraction(2) ** e > a:
+        e -= 1
+    while Fraction(2) ** (e + 1) <= a:
+        e += 1
+    q = max(e, -126) - 23                     # the float32 quantum at a
+    m = a / Fraction(2) ** q
+    n = m.numerator // m.denominator
+    rem = m - n
+    if rem > Fraction(1, 2) or (rem == Fraction(1, 2) and n % 2 == 1):
+        n += 1
+    v = Fraction(n) * Fraction(2) ** q
+    if v > Fraction(int(np.finfo(np.float32).max)):
+        return np.float32(sign * np.inf)
+    return np.float32(sign * float(v))       # n has at most 24 bits: exact
+
+
+def _key_exact(r, q):
+    """The ranking key of the definition: float32 differences, then
+    fmaf(dz, dz, fmaf(dy, dy, dx * dx)), each operation rounded once."""
+    from fractions import Fraction
+    F = Fraction
+    dx, dy, dz = (_round_f32(F(float(r[a])) - F(float(q[a]))) for a in range(3))
+    p = _round_f32(F(float(dx)) * F(float(dx)))
+    s = _round_f32(F(float(dy)) * F(float(dy)) + F(float(p)))
+    return _round_f32(F(float(dz)) * F(float(dz)) + F(float(s)))
+
+
+def test_round_f32_against_numpy():
+    # the exact rounding agrees with numpy's float64 -> float32 cast where
+    # that cast is itself a single rounding (inputs exactly representable)
+    rng = rng_for(103)
+    x = rng.standard_normal(2000) * np.exp2(rng.integers(-140, 120, 2000))
+    for v in x:
+        assert _round_f32(float(v)) == np.float32(v) or (np.isinf(_round_f32(float(v))) and np.isinf(np.float32(v)))
+
+
+@pytest.mark.parametrize("scale", [1e-3, 1.0, 37.0, 4e3])
+def test_brute_key_bit_exact(oracle_mod, scale):
+    # every key the oracle returns equals the exactly rounded sequence of
+    # the definition, bit for bit (so ties, order and the k-th key are
+    # pinned to the last bit), at several coordinate magnitudes
+    rng = rng_for(104, int(scale * 1000))
+    ref = (uniform_cloud(rng, 32) * np.float32(scale)).astype(np.float32)
+    qry = (uniform_cloud(rng, 60, -1.3, 1.3) * np.float32(scale)).astype(np.float32)
+    # a few queries sharing coordinates with reference points (exact zeros)
+    qry[:4, :2] = ref[:4, :2]
+    idx, d2 = oracle_mod.knn(ref, qry, 32)
+    for i in range(qry.shape[0]):
+        keys = np.array([_key_exact(ref[j], qry[i]) for j in range(32)], np.float32)
+        order = sorted(range(32), key=lambda j: (keys[j], j))
+        assert idx[i].tolist() == order
+        assert np.array_equal(d2[i].view(np.uint32), keys[order].view(np.uint32))
+
+
 @pytest.mark.parametrize("case", ["uniform", "clustered", "duplicates", "lattice", "plane"])
 @pytest.mark.parametrize("k", [1, 10, 16, 32])
 def test_kdtree_bit_equal_to_brute(oracle_mod, case, k):

@@ -87,6 +87,52 @@ def test_rigid_fit_is_locally_optimal(oracle_mod):
         assert cost(d @ R) >= c0 - 1e-12
 
 
+def _near_line(rng, spread):
+    """50 points on a unit-direction line through a, each moved off it by
+    N(0, spread^2) per axis (float64, before any rounding)."""
+    s = np.sort(rng.uniform(-1.0, 1.0, 50))
+    d = np.array([0.6, -0.3, 0.74])
+    d /= np.linalg.norm(d)
+    return np.array([0.3, 1.1, 2.0]) + s[:, None] * d + rng.normal(size=(50, 3)) * spread, d
+
+
+def test_p2p_degeneracy_threshold_is_where_float32_data_stop_fixing_the_rotation(oracle_mod):
+    # The inputs are float32 points.  For a nearly collinear pair set the
+    # rotation about the line is fixed only by the off-line spread, so the
+    # float32 rounding of the inputs moves it by about 2^-24 / spread while
+    # Horn's gap/top is about spread^2.  Two float32 roundings of the same
+    # exact motion (the set moved along its own line by 3.3e-8 first) show
+    # it, with numpy's eigh (Horn's method, independent of the oracle):
+    # at gap/top ~ 1e-7 the rotation moves by more than the 1e-5 rad pose
+    # tolerance (undetermined by the data: the loop must stop, DEGENERATE);
+    # at gap/top ~ 1e-3 it is fixed well within it (the loop must step).
+    # A threshold of 1e-12 would accept the first set and apply a rotation
+    # that is rounding noise at the tolerance.
+    rng = rng_for(404)
+    for spread, undetermined in ((1e-4, True), (1e-2, False)):
+        exact, d = _near_line(rng, spread)
+        T = random_rigid(rng, 10.0, 0.2)
+        Rs = []
+        for shift in (0.0, 3.3e-8):
+            e = exact + d * shift
+            p = e.astype(np.float32).astype(np.float64)
+            q = (e @ T[:3, :3].T + T[:3, 3]).astype(np.float32).astype(np.float64)
+            R, lam, gap = _horn(p, q)
+            Rs.append(R)
+        moved = pose_err(np.block([[Rs[0], np.zeros((3, 1))], [np.zeros((1, 3)), 1.0]]),
+                         np.block([[Rs[1], np.zeros((3, 1))], [np.zeros((1, 3)), 1.0]]))[0]
+        src = exact.astype(np.float32)
+        tgt = (exact @ T[:3, :3].T + T[:3, 3]).astype(np.float32)
+        _, _, top, g = oracle_mod.rigid_fit(src.astype(np.float64), tgt.astype(np.float64))
+        r = oracle_mod.icp_p2p(src, tgt, T, d_max=1.0, max_iters=1)
+        if undetermined:
+            assert 1e-12 < g / top < 1e-6 and moved > 1e-5, (g / top, moved)
+            assert r["status"] == oracle_mod.ICP_DEGENERATE
+        else:
+            assert g / top > 1e-6 and moved < 1e-5, (g / top, moved)
+            assert r["status"] == oracle_mod.ICP_MAXITER and r["iterations"] == 1
+
+
 def test_rigid_fit_degenerate_when_collinear(oracle_mod):
     s = np.linspace(-1.0, 1.0, 20)[:, None]
     p = s * np.array([[1.0, 2.0, 0.5]])

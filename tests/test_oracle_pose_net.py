@@ -166,3 +166,55 @@ def test_learned_icp_keeps_or_falls_back(oracle_mod):
         assert (start == -1) == kept, start
         ea, et = pose_err(r["T"], T)
         assert ea < 1e-6 and et < 1e-6 and r["rms"] < 1e-5
+
+
+def test_straight_through_gradient_matches_autograd():
+    # The training gradient with the bfloat16 roundings in place: the forward
+    # rounds a1, a2, W2 and W3 to bfloat16, the backward takes each rounding
+    # as the identity.  torch's autograd (float64, CPU) computes the same
+    # thing independently: every rounding written as v + (round(v) - v)
+    # detached, the max-pool, ReLUs, head and quaternion loss written out.
+    import torch
+    params = _params(9)
+    pairs = [(sphere_plane(rng_for(810, j), 200), sphere_plane(rng_for(811, j), 180)) for j in range(2)]
+    labels = [random_rigid(rng_for(812, j), 40.0, 0.0) for j in range(2)]
+    weights = [1.0, 0.5]
+    L, g = pn.loss_and_grad(params, pairs, labels, weights, round_bf16=True)
+
+    def rnd(v):
+        # bfloat16 of the float32 value of v, held fixed by autograd
+        r = torch.from_numpy(pn.bf16(v.detach().numpy().astype(np.float32)))
+        return v + (r - v).detach()
+
+    T = {}
+    o = 0
+    for name, shp in pn.SHAPES:
+        n = int(np.prod(shp))
+        T[name] = torch.tensor(params[o:o + n].astype(np.float64).reshape(shp), requires_grad=True)
+        o += n
+    total = torch.zeros((), dtype=torch.float64)
+    for (src, tgt), lab, wgt in zip(pairs, labels, weights):
+        feats = []
+        for pts in (src, tgt):
+            x = torch.from_numpy(pn.normalise(pts)[0].astype(np.float64))
+            a1 = rnd(torch.relu(x @ T["W1"] + T["b1"]))
+            a2 = rnd(torch.relu(a1 @ rnd(T["W2"]) + T["b2"]))
+            a3 = torch.relu(a2 @ rnd(T["W3"]) + T["b3"])
+            feats.append(a3.max(dim=0).values)
+        h = torch.relu(torch.cat(feats) @ T["W4"] + T["b4"])
+        q = h @ T["W5"] + T["b5"]
+        w, xq, yq, zq = q / torch.linalg.norm(q)
+        R = torch.stack([torch.stack([w * w + xq * xq - yq * yq - zq * zq, 2 * (xq * yq - w * zq),
+                                      2 * (xq * zq + w * yq)]),
+                         torch.stack([2 * (xq * yq + w * zq), w * w - xq * xq + yq * yq - zq * zq,
+                                      2 * (yq * zq - w * xq)]),
+                         torch.stack([2 * (xq * zq - w * yq), 2 * (yq * zq + w * xq),
+                                      w * w - xq * xq - yq * yq + zq * zq])])
+        total = total + wgt * torch.sum((R - torch.from_numpy(np.asarray(lab)[:3, :3])) ** 2)
+    total.backward()
+    ga = np.concatenate([T[name].grad.numpy().ravel() for name, _ in pn.SHAPES])
+    assert abs(total.item() - L) <= 1e-12 * max(1.0, L)
+    assert np.linalg.norm(ga - g) <= 1e-10 * np.linalg.norm(ga), np.linalg.norm(ga - g) / np.linalg.norm(ga)
+    # and the roundings matter: the gradient without them differs
+    _, g0 = pn.loss_and_grad(params, pairs, labels, weights, round_bf16=False)
+    assert np.linalg.norm(g0 - g) > 1e-4 * np.linalg.norm(g)
