@@ -41,12 +41,16 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "ICP pairs/s + Mpt·iter/s at ≤1e-5 rad pose error; learned-init vs plain"
-WORKLOADS = {"sphere": 0, "room": 1, "street": 2, "batch": 3, "projective": 5, "learned": 4}
+WORKLOADS = {"sphere": 0, "room": 1, "street": 2, "batch": 3, "projective": 5, "learned": 4, "knn": 6, "normals": 7}
 HBM_PEAK_GBS = 8000.0
 # algorithmic bytes per source point per ICP iteration: source xyz (12),
 # matched target xyz + normal (24), cell lookup (4); the projective
 # association reads the pixel's point and normal directly (no cell lookup)
 ICP_BYTES_PER_POINT = 40
+# k-NN: the query's xyz read, k (index, key) pairs written; normals: xyz
+# read, normal and curvature written (neighbours come from the pyramid)
+KNN_BYTES_PER_QUERY = lambda k: 12 + 8 * k
+NORMALS_BYTES_PER_POINT = 28
 PROJ_BYTES_PER_POINT = 36
 PROJECTIVE = dict(name="room_views_vga", width=640, height=480, angle=3.0, t=0.03, k=16, d_max=0.2, iters=15)
 # matrix-core work of the learned initialiser's encoder per point: the
@@ -90,6 +94,8 @@ def parse():
                     help="single-pair and batch workloads: time eager launches instead of replays of a captured graph")
     ap.add_argument("--no-learned", action="store_true",
                     help="default run: skip the learned-initialiser comparison")
+    ap.add_argument("--cloud", choices=["room", "street"], default="room",
+                    help="knn and normals workloads: the cloud queried against itself")
     ap.add_argument("--no-street", action="store_true",
                     help="default run: skip the single-pair street line reported beside the batch")
     ap.add_argument("--copy-probe", action="store_true",
@@ -196,14 +202,21 @@ class HipEvents:
         return ms.value
 
 
-KERNEL_SOURCES = ("icp.hip", "search.h", "common.h")
+KERNEL_SOURCES = {"icp_accum": ("icp.hip", "search.h", "common.h"),
+                  "k_knn": ("knn.hip", "search.h", "common.h"),
+                  "k_normals": ("knn.hip", "search.h", "common.h")}
 
 
-def kernel_digest():
-    """Digest of the sources the ICP kernel is built from."""
+def kernel_tag_of(regex):
+    """Which kernel a rocprofv3 kernel regex names (for its source digest)."""
+    return "k_knn" if "knn" in regex else "k_normals" if "normals" in regex else "icp_accum"
+
+
+def kernel_digest(kernel_tag="icp_accum"):
+    """Digest of the sources a kernel is built from."""
     import hashlib
     h = hashlib.sha256()
-    for f in KERNEL_SOURCES:
+    for f in KERNEL_SOURCES[kernel_tag]:
         h.update(open(os.path.join(ROOT, "paper_1807_00399_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -219,7 +232,7 @@ def traffic_from_profiles(kernel_tag, workload):
         d = json.load(open(path))
     except Exception:
         return None
-    if d.get("kernel_digest") != kernel_digest():
+    if d.get("kernel_digest") != kernel_digest(kernel_tag if kernel_tag in KERNEL_SOURCES else "icp_accum"):
         return None
     return d.get("hbm_bytes_per_launch")
 
@@ -669,6 +682,88 @@ def bench_batch(args):
     return out
 
 
+def bench_search(args):
+    """Standalone k-NN (every point of a cloud against the cloud) or PCA
+    normals of a cloud: one step = the pyramid build + the search kernel
+    (knn_search / estimate_normals, one call)."""
+    import torch
+    from gen import make_workload
+    from paper_1807_00399_amd import pcgpu
+    dev = torch.device("cuda:0")
+    w = make_workload(WORKLOADS[args.cloud])
+    x = torch.from_numpy(w.target).to(dev)
+    n, k = w.n, w.k
+    knn = args.workload == "knn"
+    if knn:
+        idx = torch.empty((n, k), dtype=torch.int32, device=dev)
+        d2 = torch.empty((n, k), dtype=torch.float32, device=dev)
+        ws = torch.empty(pcgpu.lib.knn_search_workspace_size(n, n, k), dtype=torch.uint8, device=dev)
+        stream = torch.cuda.current_stream().cuda_stream
+
+        def step():
+            pcgpu._check(pcgpu.lib.knn_search(x.data_ptr(), n, x.data_ptr(), n, k, idx.data_ptr(), d2.data_ptr(),
+                                              ws.data_ptr(), ws.numel(), stream), "knn_search")
+    else:
+        ws = torch.empty(pcgpu.lib.estimate_normals_workspace_size(n, k), dtype=torch.uint8, device=dev)
+
+        def step():
+            pcgpu.estimate_normals(x, k, workspace=ws)
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    ev = HipEvents(1)
+    pcgpu.lib.pc_set_kernel_timer(ev.beg, ev.end, 1)
+    kern = []
+    for _ in range(max(3, min(args.steps, 10))):
+        step()
+        torch.cuda.synchronize()
+        assert pcgpu.lib.pc_kernel_timer_count() == 1
+        kern.append(ev.elapsed_ms(0))
+    pcgpu.lib.pc_set_kernel_timer(None, None, 0)
+    kern_s = float(np.median(kern)) * 1e-3
+    algo = (KNN_BYTES_PER_QUERY(k) if knn else NORMALS_BYTES_PER_POINT) * n
+    achieved = algo / kern_s / 1e9
+    name = "k_knn" if knn else "k_normals"
+    tag = f"{'knn' if knn else 'normals'}_{args.cloud}"
+    out = {
+        "metric": ("k-NN queries/s" if knn else "normals points/s") + " (exact, bit-equal to brute force)",
+        "value": n * args.steps / el, "unit": "queries/s" if knn else "points/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * el / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32 (normals: f64 covariance and eigensolver)", "data": "synthetic",
+        "config": {"workload": f"{w.name}: {'k-NN of every point against its cloud' if knn else 'PCA normals'}, "
+                               f"{n} points, k={k}; one step = pyramid build + {name}",
+                   "points": n, "k": k},
+        "search_kernel_ms": kern_s * 1e3,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profiles(name, args.cloud),
+                     "kernel": name, "avg_kernel_us": kern_s * 1e6, "algorithmic_bytes_per_launch": algo},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build(force=False)
+        t1 = time.perf_counter()
+        reps = 0
+        while True:
+            if knn:
+                oracle.knn(w.target, w.target, k, "kdtree")
+            else:
+                oracle.normals(w.target, k, (0.0, 0.0, 0.0), method="kdtree")
+            reps += 1
+            if time.perf_counter() - t1 >= args.cpu_seconds:
+                break
+        el1 = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": n * reps / el1, "unit": out["unit"], "cores": oracle.num_threads(),
+                               "cpu": cpu_model(), "kind": "oracle",
+                               "sample": f"{reps} whole cloud(s) through the oracle's kd-tree "
+                                         f"({'k-NN' if knn else 'normals'}), {el1:.1f} s wall"}
+    print(json.dumps(out), flush=True)
+
+
 def bench_single(args, workload, with_cpu=True):
     """One pair per step: target pyramid + normals + ICP in one call."""
     import torch
@@ -801,6 +896,9 @@ def main():
         return
     if args.workload == "learned":
         bench_learned(args)
+        return
+    if args.workload in ("knn", "normals"):
+        bench_search(args)
         return
     if args.workload != "batch":
         print(json.dumps(bench_single(args, args.workload)), flush=True)

@@ -463,7 +463,8 @@ const double *icp_history(void *workspace, size_t workspace_bytes,
 /* Registers caller-owned HIP events (created with timing enabled) that
    icp_point_to_plane and icp_point_to_plane_batched record on their stream
    immediately before and after the correspondence/accumulation kernel of
-   iteration i, for i < capacity.  Pass
+   iteration i, for i < capacity; knn_search and estimate_normals record
+   slot 0 around their search kernel (k_knn, k_normals).  Pass
    capacity 0 to stop.  pc_kernel_timer_count() returns how many pairs the
    last call recorded.  For measurement only; not thread-safe. */
 pc_status pc_set_kernel_timer(hipEvent_t *begin, hipEvent_t *end, int capacity);

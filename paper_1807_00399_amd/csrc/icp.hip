@@ -910,6 +910,20 @@ void icp_set_timer(hipEvent_t *b, hipEvent_t *e, int cap)
 
 int icp_timer_count() { return g_tcount; }
 
+// the search kernel of a k-NN or normals call takes slot 0
+void timer_search_begin(hipStream_t st)
+{
+    if (g_tcap > 0) (void)hipEventRecord(g_tbeg[0], st);
+}
+
+void timer_search_end(hipStream_t st)
+{
+    if (g_tcap > 0) {
+        (void)hipEventRecord(g_tend[0], st);
+        g_tcount = 1;
+    }
+}
+
 void icp_carve(Carver &c, int np, int64_t ns, int64_t nt, int64_t nblk, int64_t ngrp, int iters_max,
                IcpStore &s)
 {

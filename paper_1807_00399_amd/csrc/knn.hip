@@ -278,11 +278,13 @@ void launch_normals(const GridStore &g, const float *xyz, int k, const int32_t *
 hipError_t knn_run(const GridStore &g, const float *qry, int64_t nq, int k, int32_t *oi, float *od, hipStream_t s)
 {
     if (nq <= 0) return hipSuccess;
+    timer_search_begin(s);
     if (k <= 1) launch_knn<1>(g, qry, nq, k, oi, od, s);
     else if (k <= 4) launch_knn<4>(g, qry, nq, k, oi, od, s);
     else if (k <= 8) launch_knn<8>(g, qry, nq, k, oi, od, s);
     else if (k <= 16) launch_knn<16>(g, qry, nq, k, oi, od, s);
     else launch_knn<32>(g, qry, nq, k, oi, od, s);
+    timer_search_end(s);
     return hipGetLastError();
 }
 
@@ -291,10 +293,12 @@ hipError_t normals_run(const GridStore &g, const float *xyz, int k_max, const in
 {
     if (g.n <= 0) return hipSuccess;
     if (!(cap2 == INFINITY)) srt = nullptr;   // the gap needs plain k-NN
+    timer_search_begin(s);
     if (k_max <= 4) launch_normals<4>(g, xyz, k_max, kc, cap2, min_pts, vp, on, oc, srt, s);
     else if (k_max <= 8) launch_normals<8>(g, xyz, k_max, kc, cap2, min_pts, vp, on, oc, srt, s);
     else if (k_max <= 16) launch_normals<16>(g, xyz, k_max, kc, cap2, min_pts, vp, on, oc, srt, s);
     else launch_normals<32>(g, xyz, k_max, kc, cap2, min_pts, vp, on, oc, srt, s);
+    timer_search_end(s);
     return hipGetLastError();
 }
 

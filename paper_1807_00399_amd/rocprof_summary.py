@@ -68,8 +68,8 @@ def traffic(regex, fetch_csv, write_csv, copy_fetch_csv, copy_write_csv, copy_by
         "write_bytes_per_launch_median": statistics.median(w),
         "hbm_bytes_per_launch": statistics.mean(f) + statistics.mean(w),
     }
-    from bench import kernel_digest
-    res["kernel_digest"] = kernel_digest()
+    from bench import kernel_digest, kernel_tag_of
+    res["kernel_digest"] = kernel_digest(kernel_tag_of(regex))
     json.dump(res, open(out, "w"), indent=1)
 
 
@@ -94,8 +94,8 @@ def valu(regex, sq_csv, per_call, out, command):
                            "vmem_rd_per_wave": round(r["vmem_rd_per_wave"], 1),
                            "valu_issue_share_nominal": round(r["valu_issue_share_nominal"], 3)}
                           for r in rows[:int(per_call)]]}
-    from bench import kernel_digest
-    res["kernel_digest"] = kernel_digest()
+    from bench import kernel_digest, kernel_tag_of
+    res["kernel_digest"] = kernel_digest(kernel_tag_of(regex))
     json.dump(res, open(out, "w"), indent=1)
 
 
