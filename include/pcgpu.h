@@ -422,7 +422,8 @@ pc_status icp_learned_batched(int mode, const float *params, int n_pairs,
  * depend on the tuning.
  *   icp_block_threads  64, 128 or 256: source points per accumulate block
  *   icp_leaf           8, 16 or 32: nodes holding at most this many points
- *                      are scanned whole by the ICP correspondence search
+ *                      are scanned whole by the searches (ICP
+ *                      correspondences, k-NN, normals)
  *   node_budget        0.125 .. 1: the finest pyramid level of a cloud is
  *                      the finest one whose levels hold at most
  *                      node_budget * n nodes (smaller: coarser leaves); used

@@ -127,6 +127,7 @@ pc_status knn_search(const float *ref_xyz, int64_t n_ref, const float *qry_xyz, 
     GridStore g;
     grid_carve(c, n_ref, 1, g);
     if (!c.ok) return PC_EWORKSPACE;
+    g.leaf = g_tune.icp_leaf;
     if (grid_set_single_cloud(g, stream) != hipSuccess) return PC_EDEVICE;
     if (grid_build(g, ref_xyz, stream) != hipSuccess) return PC_EDEVICE;
     if (knn_run(g, qry_xyz, n_qry, k, out_idx, out_d2, stream) != hipSuccess) return PC_EDEVICE;
@@ -157,6 +158,7 @@ pc_status estimate_normals(const float *xyz, int64_t n, int k, const float viewp
     grid_carve(c, n, 1, g);
     if (!c.ok) return PC_EWORKSPACE;
     g.node_budget = g_tune.node_budget;
+    g.leaf = g_tune.icp_leaf;
     if (grid_set_single_cloud(g, stream) != hipSuccess) return PC_EDEVICE;
     if (grid_build(g, xyz, stream) != hipSuccess) return PC_EDEVICE;
     if (normals_run(g, xyz, k, nullptr, viewpoint, out_normals, out_curvature, stream) != hipSuccess)
@@ -193,6 +195,7 @@ pc_status estimate_normals_radius(const float *xyz, int64_t n, float radius, int
     grid_carve(c, n, 1, g);
     if (!c.ok) return PC_EWORKSPACE;
     g.node_budget = g_tune.node_budget;
+    g.leaf = g_tune.icp_leaf;
     if (grid_set_single_cloud(g, stream) != hipSuccess) return PC_EDEVICE;
     if (grid_build(g, xyz, stream) != hipSuccess) return PC_EDEVICE;
     const float r2 = radius * radius;
@@ -233,6 +236,7 @@ pc_status estimate_normals_batched(int n_clouds, const float *xyz, const int64_t
     int32_t *kc = carve_normals_batched(c, n_clouds, offsets, g);
     if (!c.ok) return PC_EWORKSPACE;
     g.node_budget = g_tune.node_budget;
+    g.leaf = g_tune.icp_leaf;
     if (!upload(g.off, offsets, sizeof(int64_t) * (n_clouds + 1), stream)) return PC_EDEVICE;
     if (!upload(kc, k, sizeof(int32_t) * n_clouds, stream)) return PC_EDEVICE;
     if (grid_build(g, xyz, stream) != hipSuccess) return PC_EDEVICE;
@@ -250,6 +254,7 @@ void tune(IcpStore &s)
     s.threads = g_tune.icp_block_threads;
     s.leaf = g_tune.icp_leaf;
     s.grid.node_budget = g_tune.node_budget;
+    s.grid.leaf = g_tune.icp_leaf;
     s.sort_src = g_tune.sort_queries != 0;
 }
 

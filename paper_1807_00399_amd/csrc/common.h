@@ -295,6 +295,7 @@ struct GridStore {
     int64_t max_nodes;
     int64_t hash_slots_max;
     float node_budget;        // nodes allowed per point when picking a cloud's finest level (<= 1)
+    int leaf;                 // k-NN / normals searches scan nodes of at most this many points whole (8, 16, 32)
     int nblk_sort, nblk_lvl;
     GridView view() const
     {

@@ -594,6 +594,7 @@ void grid_carve(Carver &c, int64_t n, int n_clouds, GridStore &g)
     // a cloud's region holds max(64, 2 x its nodes) slots
     g.hash_slots_max = 2 * g.max_nodes + 64 * (int64_t)nc;
     g.node_budget = 1.0f;
+    g.leaf = 16;
     g.params = c.take<GridParams>(nc);
     g.layout = c.take<GridLayout>(1);
     g.off = c.take<int64_t>(nc + 1);
@@ -621,6 +622,7 @@ void grid_carve_sort(Carver &c, int64_t n, int n_clouds, GridStore &g)
     g.n_clouds = nc;
     g.nblk_sort = (int)((nn + kSortTile - 1) / kSortTile);
     g.node_budget = 1.0f;
+    g.leaf = 16;
     g.params = c.take<GridParams>(nc);
     g.off = c.take<int64_t>(nc + 1);
     g.clev = c.take<int32_t>((size_t)nc * kLevels);

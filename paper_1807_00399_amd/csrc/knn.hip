@@ -25,7 +25,7 @@ namespace {
 // independently (street and batch normals ~8 % faster than 256 threads)
 constexpr int kQThreads = 64;
 
-template <int KT>
+template <int KT, int LEAF>
 __global__ void __launch_bounds__(kQThreads) k_knn(GridView g, const float *__restrict__ qry, int64_t nq, int k,
                                                  int32_t *__restrict__ out_idx, float *__restrict__ out_d2)
 {
@@ -36,7 +36,7 @@ __global__ void __launch_bounds__(kQThreads) k_knn(GridView g, const float *__re
     Query q{qry[3 * i], qry[3 * i + 1], qry[3 * i + 2]};
     TopK<KT> top;
     top.init(k);
-    search<TopK<KT>, 32>(g, P, q, top, k, stk + threadIdx.x, kQThreads);
+    search<TopK<KT>, LEAF>(g, P, q, top, k, stk + threadIdx.x, kQThreads);
 #pragma unroll
     for (int s = 0; s < KT; s++) {
         if (s >= KT - k) {
@@ -165,7 +165,7 @@ __device__ void finish_normal(double cxx, double cxy, double cxz, double cyy, do
 // squared distance to the nearest other point of the cloud (the second
 // neighbour's key less 2^-20 relative; 0 when k < 2): the target record of
 // the ICP correspondence search.
-template <int KT>
+template <int KT, int LEAF>
 __global__ void __launch_bounds__(kQThreads) k_normals(GridView g, int64_t n_all, const float *__restrict__ xyz, int k,
                                                      const int32_t *__restrict__ kc, float cap2, int min_pts,
                                                      float vx, float vy, float vz, float *__restrict__ out_n,
@@ -184,7 +184,7 @@ __global__ void __launch_bounds__(kQThreads) k_normals(GridView g, int64_t n_all
     Query q{p.x, p.y, p.z};
     TopK<KT> top;
     top.init(k, cap2);
-    search<TopK<KT>, 32>(g, P, q, top, k, stk + threadIdx.x, kQThreads);
+    search<TopK<KT>, LEAF>(g, P, q, top, k, stk + threadIdx.x, kQThreads);
     // the point itself (or an exact duplicate) is first, the nearest other
     // point second (selected with static indices: the list stays in registers)
     float gap = 0.f;
@@ -230,6 +230,7 @@ __global__ void __launch_bounds__(kQThreads) k_normals(GridView g, int64_t n_all
 // Radius neighbourhoods: every point of the cloud with key <= r2; the
 // covariance from the one-pass sums, C = S / m - mu mu^T with mu = s / m;
 // fewer than three points give normal 0.
+template <int LEAF>
 __global__ void __launch_bounds__(kQThreads) k_normals_radius(GridView g, int64_t n_all, float r2, float vx,
                                                             float vy, float vz, float *__restrict__ out_n,
                                                             float *__restrict__ out_c)
@@ -243,7 +244,7 @@ __global__ void __launch_bounds__(kQThreads) k_normals_radius(GridView g, int64_
     Query q{p.x, p.y, p.z};
     RadiusCov v;
     v.init(r2);
-    search<RadiusCov, 32>(g, P, q, v, 1, stk + threadIdx.x, kQThreads);
+    search<RadiusCov, LEAF>(g, P, q, v, 1, stk + threadIdx.x, kQThreads);
     double cxx = 0, cxy = 0, cxz = 0, cyy = 0, cyz = 0, czz = 0;
     if (v.m >= 3) {
         const double m = v.m, mx = v.sx / m, my = v.sy / m, mz = v.sz / m;
@@ -257,20 +258,40 @@ __global__ void __launch_bounds__(kQThreads) k_normals_radius(GridView g, int64_
     finish_normal(cxx, cxy, cxz, cyy, cyz, czz, p.x, p.y, p.z, vx, vy, vz, qi, out_n, out_c);
 }
 
+// Leaf size of the searches (nodes of at most LEAF points are scanned whole):
+// smaller leaves visit more nodes and scan fewer points.  Results do not
+// depend on it.
+template <int KT, int LEAF>
+void launch_knn_l(const GridStore &g, const float *qry, int64_t nq, int k, int32_t *oi, float *od, hipStream_t s)
+{
+    int blocks = (int)((nq + kQThreads - 1) / kQThreads);
+    k_knn<KT, LEAF><<<blocks, kQThreads, 0, s>>>(g.view(), qry, nq, k, oi, od);
+}
+
 template <int KT>
 void launch_knn(const GridStore &g, const float *qry, int64_t nq, int k, int32_t *oi, float *od, hipStream_t s)
 {
-    int blocks = (int)((nq + kQThreads - 1) / kQThreads);
-    k_knn<KT><<<blocks, kQThreads, 0, s>>>(g.view(), qry, nq, k, oi, od);
+    if (g.leaf <= 8) launch_knn_l<KT, 8>(g, qry, nq, k, oi, od, s);
+    else if (g.leaf <= 16) launch_knn_l<KT, 16>(g, qry, nq, k, oi, od, s);
+    else launch_knn_l<KT, 32>(g, qry, nq, k, oi, od, s);
+}
+
+template <int KT, int LEAF>
+void launch_normals_l(const GridStore &g, const float *xyz, int k, const int32_t *kc, float cap2, int min_pts,
+                      const float *vp, float *on, float *oc, float4 *srt, hipStream_t s)
+{
+    int blocks = (int)((g.n + kQThreads - 1) / kQThreads);
+    k_normals<KT, LEAF><<<blocks, kQThreads, 0, s>>>(g.view(), g.n, xyz, k, kc, cap2, min_pts, vp[0], vp[1], vp[2],
+                                                     on, oc, srt);
 }
 
 template <int KT>
 void launch_normals(const GridStore &g, const float *xyz, int k, const int32_t *kc, float cap2, int min_pts,
                     const float *vp, float *on, float *oc, float4 *srt, hipStream_t s)
 {
-    int blocks = (int)((g.n + kQThreads - 1) / kQThreads);
-    k_normals<KT><<<blocks, kQThreads, 0, s>>>(g.view(), g.n, xyz, k, kc, cap2, min_pts, vp[0], vp[1], vp[2], on,
-                                               oc, srt);
+    if (g.leaf <= 8) launch_normals_l<KT, 8>(g, xyz, k, kc, cap2, min_pts, vp, on, oc, srt, s);
+    else if (g.leaf <= 16) launch_normals_l<KT, 16>(g, xyz, k, kc, cap2, min_pts, vp, on, oc, srt, s);
+    else launch_normals_l<KT, 32>(g, xyz, k, kc, cap2, min_pts, vp, on, oc, srt, s);
 }
 
 }  // namespace
@@ -306,7 +327,10 @@ hipError_t normals_radius_run(const GridStore &g, float r2, const float *vp, flo
 {
     if (g.n <= 0) return hipSuccess;
     int blocks = (int)((g.n + kQThreads - 1) / kQThreads);
-    k_normals_radius<<<blocks, kQThreads, 0, s>>>(g.view(), g.n, r2, vp[0], vp[1], vp[2], on, oc);
+    if (g.leaf <= 8) k_normals_radius<8><<<blocks, kQThreads, 0, s>>>(g.view(), g.n, r2, vp[0], vp[1], vp[2], on, oc);
+    else if (g.leaf <= 16)
+        k_normals_radius<16><<<blocks, kQThreads, 0, s>>>(g.view(), g.n, r2, vp[0], vp[1], vp[2], on, oc);
+    else k_normals_radius<32><<<blocks, kQThreads, 0, s>>>(g.view(), g.n, r2, vp[0], vp[1], vp[2], on, oc);
     return hipGetLastError();
 }
 
