@@ -435,13 +435,23 @@ pc_status icp_learned_batched(int mode, const float *params, int n_pairs,
  *                      neighbouring cells; pays off when the input order is
  *                      not already spatially coherent.  Changes only the
  *                      order of the compensated sums.
- * Defaults: 128, 16, 1, 1.  pc_set_tuning returns PC_EINVAL for other values.
+ *   icp_persistent     0 or 1: point-to-plane ICP with nearest-neighbour
+ *                      correspondences (icp_point_to_plane*) runs its whole
+ *                      loop as one cooperative launch of co-resident
+ *                      workgroups with grid barriers between the phases
+ *                      (accumulate, merge, solve) instead of three launches
+ *                      per iteration; results are bit-identical.  The
+ *                      per-iteration kernel timer then records the whole
+ *                      loop in slot 0.
+ * Defaults: 128, 16, 1, 1, 0.  pc_set_tuning returns PC_EINVAL for other
+ * values.
  * ---------------------------------------------------------------------- */
 typedef struct {
     int32_t icp_block_threads;
     int32_t icp_leaf;
     float node_budget;
     int32_t sort_queries;
+    int32_t icp_persistent;
 } pc_tuning;
 
 pc_status pc_set_tuning(const pc_tuning *t);

@@ -27,7 +27,7 @@ bool valid_offsets(const int64_t *off, int m)
 }
 
 // process-wide tuning of the ICP kernels and the pyramid (pc_set_tuning)
-pc_tuning g_tune = {128, 16, 1.0f, 1};
+pc_tuning g_tune = {128, 16, 1.0f, 1, 0};
 
 // Small host arrays (offsets, per-pair parameters) reach the device as
 // kernel arguments, kUploadChunk bytes per launch, copied by value when the
@@ -256,6 +256,7 @@ void tune(IcpStore &s)
     s.grid.node_budget = g_tune.node_budget;
     s.grid.leaf = g_tune.icp_leaf;
     s.sort_src = g_tune.sort_queries != 0;
+    s.persistent = g_tune.icp_persistent != 0;
 }
 
 // the single-pair carve, shared by the size query, the call and the history
@@ -924,6 +925,7 @@ pc_status pc_set_tuning(const pc_tuning *t)
     if (l != 8 && l != 16 && l != 32) return PC_EINVAL;
     if (!(t->node_budget >= 0.125f && t->node_budget <= 1.0f)) return PC_EINVAL;
     if (t->sort_queries != 0 && t->sort_queries != 1) return PC_EINVAL;
+    if (t->icp_persistent != 0 && t->icp_persistent != 1) return PC_EINVAL;
     g_tune = *t;
     return PC_OK;
 }

@@ -28,6 +28,7 @@ struct IcpStore {
     float2 *gpart;      // per group of blocks: merged partial sums
     uint32_t *gcnt;     // per group of blocks: inlier counts
     double *hist;       // per pair and iteration: increment, inliers, sum r^2
+    int32_t *queue;     // persistent loop: tile counter per pass
     int hist_stride;    // doubles per pair in hist
     int np, nblk, ngrp, iters_max;
     int threads;        // accumulate block size (64, 128 or 256)
@@ -41,6 +42,7 @@ struct IcpStore {
     bool grid_built;    // the target pyramid is already built (by the caller, e.g. for its normals)
     bool nrm_ready;     // nrm already holds the sorted normals and gaps (written with the normals)
     bool sort_src;      // nearest association: visit the sources in Morton order (else input order)
+    bool persistent;    // point-to-plane with nearest association: the whole loop in one cooperative launch
 };
 
 enum { kAssocNearest = 0, kAssocProjective = 1 };

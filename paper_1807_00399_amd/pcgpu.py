@@ -40,10 +40,11 @@ PC_INIT_LEARNED, PC_INIT_MULTI_START, PC_INIT_LEARNED_ONLY = 0, 1, 2
 
 
 class Tuning(ctypes.Structure):
-    """pc_tuning: accumulate block size, ICP leaf size, pyramid node budget,
-    Morton-ordered ICP queries."""
+    """pc_tuning: accumulate block size, search leaf size, pyramid node
+    budget, Morton-ordered ICP queries, persistent ICP loop."""
     _fields_ = [("icp_block_threads", ctypes.c_int32), ("icp_leaf", ctypes.c_int32),
-                ("node_budget", ctypes.c_float), ("sort_queries", ctypes.c_int32)]
+                ("node_budget", ctypes.c_float), ("sort_queries", ctypes.c_int32),
+                ("icp_persistent", ctypes.c_int32)]
 
 
 class PcgpuError(RuntimeError):
@@ -550,8 +551,9 @@ def decode_stats_batched(stats: torch.Tensor) -> list:
     return [{name: r[name].item() for name, _ in STATS_DTYPE} for r in recs]
 
 
-def set_tuning(icp_block_threads: int = 128, icp_leaf: int = 16, node_budget: float = 1.0, sort_queries: int = 1):
-    t = Tuning(int(icp_block_threads), int(icp_leaf), float(node_budget), int(sort_queries))
+def set_tuning(icp_block_threads: int = 128, icp_leaf: int = 16, node_budget: float = 1.0, sort_queries: int = 1,
+               icp_persistent: int = 0):
+    t = Tuning(int(icp_block_threads), int(icp_leaf), float(node_budget), int(sort_queries), int(icp_persistent))
     _check(lib.pc_set_tuning(ctypes.byref(t)), "pc_set_tuning")
 
 
@@ -559,12 +561,12 @@ def get_tuning() -> dict:
     t = Tuning()
     lib.pc_get_tuning(ctypes.byref(t))
     return {"icp_block_threads": t.icp_block_threads, "icp_leaf": t.icp_leaf, "node_budget": t.node_budget,
-            "sort_queries": t.sort_queries}
+            "sort_queries": t.sort_queries, "icp_persistent": t.icp_persistent}
 
 
 def copy_probe(dst: torch.Tensor, src: torch.Tensor, stream=None):
-    _check(lib.pc_copy_probe(dst.data_ptr(), src.data_ptr(), src.numel() * src.element_size(), _stream(stream, locals())),
-           "pc_copy_probe")
+    _check(lib.pc_copy_probe(dst.data_ptr(), src.data_ptr(), src.numel() * src.element_size(),
+                             _stream(stream, locals())), "pc_copy_probe")
 
 
 # ---------------------------------------------------------------------------

@@ -12,8 +12,12 @@ def pc():
 
 def test_tuning_validation(pc):
     pc.set_tuning(64, 32, 0.5, 0)
-    assert pc.get_tuning() == {"icp_block_threads": 64, "icp_leaf": 32, "node_budget": 0.5, "sort_queries": 0}
-    for bad in ((96, 16, 1.0), (128, 12, 1.0), (128, 16, 1.5), (128, 16, 0.0), (128, 16, 1.0, 2)):
+    assert pc.get_tuning() == {"icp_block_threads": 64, "icp_leaf": 32, "node_budget": 0.5, "sort_queries": 0,
+                               "icp_persistent": 0}
+    pc.set_tuning(64, 32, 0.5, 0, 1)
+    assert pc.get_tuning()["icp_persistent"] == 1
+    for bad in ((96, 16, 1.0), (128, 12, 1.0), (128, 16, 1.5), (128, 16, 0.0), (128, 16, 1.0, 2),
+                (128, 16, 1.0, 1, 2)):
         with pytest.raises(pc.PcgpuError):
             pc.set_tuning(*bad)
     assert pc.get_tuning()["icp_block_threads"] == 64      # unchanged by rejected calls
@@ -28,16 +32,18 @@ def test_tune_picks_fastest_and_caches(pc, tmp_path):
 
     def step():
         t = pc.get_tuning()
-        # Morton-ordered queries save a little here
-        clock["t"] += cost[(t["icp_block_threads"], t["icp_leaf"], t["node_budget"])] - 0.25 * t["sort_queries"]
+        # Morton-ordered queries and the persistent loop save a little here
+        clock["t"] += (cost[(t["icp_block_threads"], t["icp_leaf"], t["node_budget"])] - 0.25 * t["sort_queries"]
+                       - 0.125 * t["icp_persistent"])
 
     cache = str(tmp_path / "tune.json")
     r = autotune.tune(step, "fake", 1 << 20, device_name="dev0", cache_file=cache, sync=lambda: None,
                       clock=lambda: clock["t"])
     assert not r["from_cache"]
-    assert r["tuning"] == {"icp_block_threads": 256, "icp_leaf": 8, "node_budget": 1.0, "sort_queries": 1}
+    assert r["tuning"] == {"icp_block_threads": 256, "icp_leaf": 8, "node_budget": 1.0, "sort_queries": 1,
+                           "icp_persistent": 1}
     assert pc.get_tuning() == r["tuning"]
-    assert len(r["timings"]) == len(autotune.CANDIDATES) + 1
+    assert len(r["timings"]) == len(autotune.CANDIDATES) + 2
     pc.set_tuning(128, 16, 1.0)
     # same device, tag and size bucket: served from the cache and applied
     r2 = autotune.tune(step, "fake", (1 << 20) + 5, device_name="dev0", cache_file=cache, sync=lambda: None,
@@ -57,5 +63,5 @@ def test_cache_entries_without_query_order_mean_input_order(pc, tmp_path):
     key = autotune.cache_key("dev0", "old", 1000)
     json.dump({key: {"tuning": {"icp_block_threads": 64, "icp_leaf": 16, "node_budget": 1.0}}}, open(cache, "w"))
     r = autotune.tune(lambda: None, "old", 1000, device_name="dev0", cache_file=cache)
-    assert r["from_cache"] and pc.get_tuning()["sort_queries"] == 0
+    assert r["from_cache"] and pc.get_tuning()["sort_queries"] == 0 and pc.get_tuning()["icp_persistent"] == 0
     pc.set_tuning(128, 16, 1.0)

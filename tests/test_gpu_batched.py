@@ -261,7 +261,8 @@ def test_batched_full_workload_fused_bench_tuning(gpu, oracle_mod):
     _say(f"full fused batch {b.name} n={b.n} tuned {tun}")
     nrm = torch.empty((b.target.shape[0], 3), dtype=torch.float32, device="cuda")
     try:
-        gpu.set_tuning(tun["icp_block_threads"], tun["icp_leaf"], tun["node_budget"], tun["sort_queries"])
+        gpu.set_tuning(tun["icp_block_threads"], tun["icp_leaf"], tun["node_budget"], tun["sort_queries"],
+                       tun.get("icp_persistent", 0))
         T, stats = gpu.icp_point_to_plane_with_normals_batched(_dev(b.source), off, _dev(b.target), off,
                                                                b.param("k").astype(np.int32), (0.0, 0.0, 0.0), None,
                                                                b.param("d_max").astype(np.float32),
@@ -314,7 +315,8 @@ def test_batched_full_workload_every_pair_vs_oracle(gpu):
     tun = hit["tuning"] if hit else gpu.get_tuning()
     _say(f"full fused batch {b.name} n={b.n} every pair vs oracle, tuning {tun}")
     try:
-        gpu.set_tuning(tun["icp_block_threads"], tun["icp_leaf"], tun["node_budget"], tun["sort_queries"])
+        gpu.set_tuning(tun["icp_block_threads"], tun["icp_leaf"], tun["node_budget"], tun["sort_queries"],
+                       tun.get("icp_persistent", 0))
         T, stats = gpu.icp_point_to_plane_with_normals_batched(_dev(b.source), off, _dev(b.target), off,
                                                                b.param("k").astype(np.int32), (0.0, 0.0, 0.0), None,
                                                                b.param("d_max").astype(np.float32),
@@ -382,3 +384,55 @@ def test_autotune_on_device(gpu, small_batch, tmp_path):
         assert not r["from_cache"] and gpu.get_tuning() == r["tuning"]
     finally:
         gpu.set_tuning(128, 16, 1.0)
+
+
+def test_persistent_loop_equals_lockstep(gpu, oracle_mod, small_batch):
+    # the whole ICP loop as one cooperative launch computes exactly what the
+    # three launches per iteration compute: same blocks, groups and pairs,
+    # same merge order, so poses and statistics are bit-identical
+    b = small_batch
+    off = b.offsets
+    kc, dm, it = b.param("k").astype(np.int32), b.param("d_max").astype(np.float32), b.param("iters").astype(np.int32)
+    src, tgt = _dev(b.source), _dev(b.target)
+    try:
+        for tb, leaf in ((64, 8), (128, 16), (256, 32)):
+            res = []
+            for pe in (0, 1):
+                gpu.set_tuning(tb, leaf, 1.0, 1, pe)
+                _say(f"persistent={pe} block {tb} leaf {leaf}")
+                T, st = gpu.icp_point_to_plane_with_normals_batched(src, off, tgt, off, kc, (0.0, 0.0, 0.0), None, dm,
+                                                                    it)
+                res.append((T.cpu().numpy(), st))
+            assert np.array_equal(res[0][0], res[1][0]), (tb, leaf)
+            assert res[0][1] == res[1][1]
+        # a single pair too, with an early stop from conv_tol
+        w = b.pairs[0]
+        nrm = oracle_mod.normals(w.target, w.k, (0, 0, 0))[0].astype(np.float32)
+        out = []
+        for pe in (0, 1):
+            gpu.set_tuning(128, 16, 1.0, 1, pe)
+            T, st = gpu.icp_point_to_plane(_dev(w.source), _dev(w.target), _dev(nrm), None, w.d_max, w.iters, 1e-9)
+            out.append((T.cpu().numpy(), st))
+        assert np.array_equal(out[0][0], out[1][0]) and out[0][1] == out[1][1]
+    finally:
+        gpu.set_tuning(128, 16, 1.0, 1, 0)
+
+
+def test_persistent_loop_full_batch_equals_lockstep(gpu):
+    # the benchmark's batch step with the persistent loop: bit-identical to
+    # the lockstep launches in the same launch shape
+    b = batch_workload(3)
+    off = b.offsets
+    kc, dm, it = b.param("k").astype(np.int32), b.param("d_max").astype(np.float32), b.param("iters").astype(np.int32)
+    src, tgt = _dev(b.source), _dev(b.target)
+    res = []
+    try:
+        for pe in (0, 1):
+            gpu.set_tuning(64, 8, 0.5, 1, pe)
+            _say(f"full batch persistent={pe}")
+            T, st = gpu.icp_point_to_plane_with_normals_batched(src, off, tgt, off, kc, (0.0, 0.0, 0.0), None, dm, it)
+            res.append((T.cpu().numpy(), st))
+    finally:
+        gpu.set_tuning(128, 16, 1.0, 1, 0)
+    assert np.array_equal(res[0][0], res[1][0])
+    assert res[0][1] == res[1][1]

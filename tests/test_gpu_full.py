@@ -154,7 +154,8 @@ def test_full_icp_with_normals_bench_tuning(gpu, oracle_mod, work):
     S, T = _dev(w.source), _dev(w.target)
     Td, sd = gpu.icp_point_to_plane_with_normals(S, T, w.k, (0.0, 0.0, 0.0), None, w.d_max, w.iters)
     try:
-        gpu.set_tuning(tun["icp_block_threads"], tun["icp_leaf"], tun["node_budget"], tun["sort_queries"])
+        gpu.set_tuning(tun["icp_block_threads"], tun["icp_leaf"], tun["node_budget"], tun["sort_queries"],
+                       tun.get("icp_persistent", 0))
         Tt, st = gpu.icp_point_to_plane_with_normals(S, T, w.k, (0.0, 0.0, 0.0), None, w.d_max, w.iters)
     finally:
         gpu.set_tuning(128, 16, 1.0, 1)

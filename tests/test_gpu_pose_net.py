@@ -300,7 +300,8 @@ def test_learned_full_workload_sampled(gpu, oracle_mod):
     try:
         if hit is not None:
             t = hit["tuning"]
-            gpu.set_tuning(t["icp_block_threads"], t["icp_leaf"], t["node_budget"], t["sort_queries"])
+            gpu.set_tuning(t["icp_block_threads"], t["icp_leaf"], t["node_budget"], t["sort_queries"],
+                           t.get("icp_persistent", 0))
         nrm, _ = gpu.estimate_normals_batched(tgt, off, cfg["k"], curvature=False)
         T, st, start = gpu.icp_learned_batched(gpu.PC_INIT_LEARNED, torch.from_numpy(params).cuda(), src, off, tgt,
                                                nrm, off, d, it, accept_rms=acc)

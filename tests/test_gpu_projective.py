@@ -92,7 +92,8 @@ def test_projective_bench_workload(gpu, oracle_mod):
     try:
         if hit is not None:
             t = hit["tuning"]
-            gpu.set_tuning(t["icp_block_threads"], t["icp_leaf"], t["node_budget"], t["sort_queries"])
+            gpu.set_tuning(t["icp_block_threads"], t["icp_leaf"], t["node_budget"], t["sort_queries"],
+                           t.get("icp_persistent", 0))
         nrm, _ = gpu.estimate_normals(_dev(tgt), c["k"], curvature=False)
         nrm = nrm.cpu().numpy()
         _parity(gpu, oracle_mod, src, tgt, nrm, c["width"], c["height"], K, c["d_max"], c["iters"])
