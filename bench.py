@@ -521,8 +521,68 @@ def learned_legs(steps, warmup, args=None):
             "pairs": m, "points_per_side": b.n, "legs": legs, "tuning": tuning,
             "learned_init_rotation_error_deg": {"median": float(np.median(e_init)),
                                                 "within_30": float(np.mean(e_init < 30))},
-            "predict_ms": pred_s * 1e3}
+            "predict_ms": pred_s * 1e3,
+            "encoder_forward_tflops": ENC_FLOPS_PER_POINT * 2 * b.n / pred_s / 1e12}
     return info, b, learned_T, pred_s
+
+
+# one training row of the encoder's backward (per cloud and channel): the
+# arg-max point's layer-1 and layer-2 recompute, the layer-1 gradient, and
+# the dW1|b1, dW2|b2 and dW3 products, 2 flops per multiply-add
+TRAIN_BWD_FLOPS_PER_ROW = 2 * (3 * 64 + 64 * 128 + 64 * 128 + 4 * 64 + 65 * 128 + 128)
+W2_GRAD_FLOPS_PER_ROW = 2 * 65 * 128
+
+
+def training_step_metrics(steps=10, warmup=2, n_pairs=64):
+    """pose_net_train_step (forward with arg-max, head and encoder backward,
+    Adam) on n_pairs pairs of 4,096 points, timed per phase by the library's
+    events: forward, backward, and the second-layer weight gradients on the
+    matrix cores."""
+    import torch
+    from gen import POSE_CONFIG, pose_pairs
+    from paper_1807_00399_amd import pcgpu
+    from paper_1807_00399_amd.train_pose_net import load_params
+    dev = torch.device("cuda:0")
+    b = pose_pairs(POSE_CONFIG["eval_config"], n_pairs)
+    off = b.offsets
+    src, tgt = torch.from_numpy(b.source).to(dev), torch.from_numpy(b.target).to(dev)
+    params = torch.from_numpy(load_params()).to(dev)
+    m_, v_ = torch.zeros_like(params), torch.zeros_like(params)
+    labels = np.stack([w.T_gt for w in b.pairs])
+    ws = torch.empty(pcgpu.lib.pose_net_workspace_size(n_pairs, off.ctypes.data, off.ctypes.data),
+                     dtype=torch.uint8, device=dev)
+    p0 = params.clone()
+
+    def step(i):
+        pcgpu.pose_net_train_step(params, m_, v_, i, 1e-6, src, off, tgt, off, labels, workspace=ws)
+
+    for i in range(warmup):
+        step(i + 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        step(warmup + i + 1)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / steps
+    ev = HipEvents(3)
+    pcgpu.lib.pc_set_kernel_timer(ev.beg, ev.end, 3)
+    ph = []
+    for i in range(3):
+        step(warmup + steps + i + 1)
+        torch.cuda.synchronize()
+        assert pcgpu.lib.pc_kernel_timer_count() == 3
+        ph.append([ev.elapsed_ms(k) for k in range(3)])
+    pcgpu.lib.pc_set_kernel_timer(None, None, 0)
+    params.copy_(p0)
+    fwd, bwd, w2 = (float(np.median([x[k] for x in ph])) * 1e-3 for k in range(3))
+    rows = 2 * n_pairs * 256
+    return {"pairs_per_step": n_pairs, "points_per_cloud": int(b.n // n_pairs), "steps_per_s": 1.0 / el,
+            "ms_per_step": el * 1e3, "forward_ms": fwd * 1e3, "backward_ms": bwd * 1e3,
+            "forward_tflops": ENC_FLOPS_PER_POINT * 2 * b.n / fwd / 1e12,
+            "backward_tflops": TRAIN_BWD_FLOPS_PER_ROW * rows / bwd / 1e12,
+            "w2_grad_us": w2 * 1e6, "w2_grad_tflops": W2_GRAD_FLOPS_PER_ROW * rows / w2 / 1e12,
+            "note": "backward flops: per (cloud, channel) row the arg-max point's recompute and the dW1, dW2, dW3 "
+                    "products; forward: the two matrix-core layers of every point of both clouds"}
 
 
 def bench_learned(args):
@@ -553,6 +613,7 @@ def bench_learned(args):
                      "kernel": "pose_net_predict (encoder forward, both clouds of every pair)",
                      "avg_call_us": pred_s * 1e6, "algorithmic_flops_per_call": float(flops)},
     }
+    out["training"] = training_step_metrics()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline_learned(b, learned_T, args.cpu_seconds)
     print(json.dumps(out), flush=True)
@@ -937,7 +998,9 @@ def main():
     if not args.no_learned:
         info = learned_legs(min(args.steps, 5), 1, args)[0]
         out["learned_vs_plain"] = {"workload": info["workload"], "legs": info["legs"],
-                                   "learned_init_rotation_error_deg": info["learned_init_rotation_error_deg"]}
+                                   "learned_init_rotation_error_deg": info["learned_init_rotation_error_deg"],
+                                   "encoder_forward_tflops": info["encoder_forward_tflops"],
+                                   "training": training_step_metrics()}
     print(json.dumps(out), flush=True)
 
 

@@ -67,6 +67,9 @@ int icp_timer_count();
 // events around the search kernel of knn_run / normals_run (slot 0)
 void timer_search_begin(hipStream_t st);
 void timer_search_end(hipStream_t st);
+// events of slot `slot` (ignored beyond the registered capacity)
+void timer_slot_begin(int slot, hipStream_t st);
+void timer_slot_end(int slot, hipStream_t st);
 
 hipError_t knn_run(const GridStore &g, const float *qry, int64_t nq, int k, int32_t *oi, float *od, hipStream_t s);
 // k_max: the largest k of any cloud; kc: per-cloud k (device), or null to

@@ -1042,19 +1042,22 @@ void icp_set_timer(hipEvent_t *b, hipEvent_t *e, int cap)
 
 int icp_timer_count() { return g_tcount; }
 
-// the search kernel of a k-NN or normals call takes slot 0
-void timer_search_begin(hipStream_t st)
+void timer_slot_begin(int slot, hipStream_t st)
 {
-    if (g_tcap > 0) (void)hipEventRecord(g_tbeg[0], st);
+    if (slot < g_tcap) (void)hipEventRecord(g_tbeg[slot], st);
 }
 
-void timer_search_end(hipStream_t st)
+void timer_slot_end(int slot, hipStream_t st)
 {
-    if (g_tcap > 0) {
-        (void)hipEventRecord(g_tend[0], st);
-        g_tcount = 1;
+    if (slot < g_tcap) {
+        (void)hipEventRecord(g_tend[slot], st);
+        if (g_tcount < slot + 1) g_tcount = slot + 1;
     }
 }
+
+// the search kernel of a k-NN or normals call takes slot 0
+void timer_search_begin(hipStream_t st) { timer_slot_begin(0, st); }
+void timer_search_end(hipStream_t st) { timer_slot_end(0, st); }
 
 void icp_carve(Carver &c, int np, int64_t ns, int64_t nt, int64_t nblk, int64_t ngrp, int iters_max,
                IcpStore &s)

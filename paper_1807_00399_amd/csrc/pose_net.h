@@ -35,6 +35,7 @@ struct PoseNetStore {
     float *scale;               // per cloud inverse RMS radius
     __bf16 *w2t, *w3t;          // bfloat16 copies of W2, W3, [n][k]
     __bf16 *w3p;                // W3 in the forward's K-slot order, [n][slot]
+    __bf16 *w2p;                // W2 in the forward's K-slot order, [n][slot]
     float *pmax;                // per tile x channel maxima
     int32_t *parg;              // ... and their point indices
     float *feat;                // per cloud features

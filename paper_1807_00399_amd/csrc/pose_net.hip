@@ -14,21 +14,23 @@
 // per-channel maximum over the cloud's points.  The 64 -> 128 and
 // 128 -> 256 layers are dense contractions over every point and run on the
 // bfloat16 matrix cores (v_mfma_f32_16x16x32_bf16, float32 accumulation),
-// with their inputs rounded to bfloat16; the first layer (3 inputs) and the
-// head are float32 vector code.
+// with their inputs rounded to bfloat16; the first layer (3 inputs and the
+// bias) runs on the float32 matrix cores (v_mfma_f32_16x16x4_f32); the head
+// is float32 vector code.
 //
 // Training: the loss of a pair is w_p |R(q) - R_label|_F^2.  The max-pool
 // routes each channel's gradient to one point, so the encoder's backward
 // recomputes one row per (cloud, channel) instead of keeping activations of
 // every point; the bfloat16 roundings pass gradients unchanged.  Weight
 // gradients are sums over those rows (or over pairs) formed in a fixed order
-// by chunked outer-product kernels and a second pass over the chunks: no
-// atomics, so a step is deterministic.  Adam updates the float32 master
+// by chunked outer-product kernels (layer 2 on the bfloat16 matrix cores)
+// and a second pass over the chunks: no atomics, so a step is deterministic.  Adam updates the float32 master
 // parameters.
 
 #include <math.h>
 
 #include "common.h"
+#include "icp.h"
 #include "pose_net.h"
 
 namespace pcg {
@@ -99,13 +101,18 @@ __device__ inline int w3_slot_channel(int kb, int s)
 }
 
 // bfloat16 copies of W2 and W3 with k contiguous per output column (w2t,
-// w3t: [n][k]), and W3 in the slot order of the forward (w3p: [n][slot])
+// w3t: [n][k]), and both in the slot order of the forward (w2p: [n][slot],
+// slot < 64; w3p: [n][slot], slot < 128)
 __global__ void k_weights_bf16(const float *__restrict__ params, __bf16 *__restrict__ w2t, __bf16 *__restrict__ w3t,
-                               __bf16 *__restrict__ w3p)
+                               __bf16 *__restrict__ w3p, __bf16 *__restrict__ w2p)
 {
     const float *W2 = params + kOffW2, *W3 = params + kOffW3;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < kC1 * kC2 + 2 * kC2 * kC3; i += gridDim.x * blockDim.x) {
-        if (i < kC1 * kC2) {
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 2 * kC1 * kC2 + 2 * kC2 * kC3;
+         i += gridDim.x * blockDim.x) {
+        if (i >= kC1 * kC2 + 2 * kC2 * kC3) {
+            int j = i - kC1 * kC2 - 2 * kC2 * kC3, n = j / kC1, sl = j % kC1;
+            w2p[j] = to_bf16(W2[w3_slot_channel(sl / 32, sl % 32) * kC2 + n]);
+        } else if (i < kC1 * kC2) {
             int n = i / kC1, k = i % kC1;
             w2t[i] = to_bf16(W2[k * kC2 + n]);
         } else if (i < kC1 * kC2 + kC2 * kC3) {
@@ -152,11 +159,11 @@ __global__ void __launch_bounds__(kEncThreads) k_enc_forward(const float *__rest
                                                            const double *__restrict__ cen,
                                                            const float *__restrict__ scale,
                                                            const float *__restrict__ params,
-                                                           const __bf16 *__restrict__ w2t,
+                                                           const __bf16 *__restrict__ w2p,
                                                            const __bf16 *__restrict__ w3p,
                                                            float *__restrict__ pmax, int32_t *__restrict__ parg)
 {
-    __shared__ __attribute__((aligned(16))) __bf16 sW2[kC2 * kP1];   // W2^T: [ch][k], k < 64
+    __shared__ __attribute__((aligned(16))) __bf16 sW2[kC2 * kP1];   // W2^T: [ch][slot], slot < 64
     __shared__ __attribute__((aligned(16))) __bf16 sW3[kC3 * kP2];   // W3: [n][slot], slot < 128
     __shared__ __attribute__((aligned(16))) float4 sW1[kC1];         // (w1x, w1y, w1z, b1) per channel
     __shared__ float sB2[kC2], sB3[kC3];
@@ -168,7 +175,7 @@ __global__ void __launch_bounds__(kEncThreads) k_enc_forward(const float *__rest
     const int lr = l & 15, g = l >> 4;
     for (int i = t; i < kC2 * (kC1 / 8); i += kEncThreads) {
         int n = i / (kC1 / 8), k8 = i % (kC1 / 8);
-        *reinterpret_cast<bf16x8 *>(&sW2[n * kP1 + 8 * k8]) = *reinterpret_cast<const bf16x8 *>(&w2t[n * kC1 + 8 * k8]);
+        *reinterpret_cast<bf16x8 *>(&sW2[n * kP1 + 8 * k8]) = *reinterpret_cast<const bf16x8 *>(&w2p[n * kC1 + 8 * k8]);
     }
     for (int i = t; i < kC3 * (kC2 / 8); i += kEncThreads) {
         int n = i / (kC2 / 8), k8 = i % (kC2 / 8);
@@ -219,26 +226,37 @@ __global__ void __launch_bounds__(kEncThreads) k_enc_forward(const float *__rest
         }
         const int64_t p0 = cr[2 * c] + (int64_t)(tile - toff[c]) * kT;
         const int64_t pend = cr[2 * c + 1];
-        // layer 1 into the B operand of layer 2: rows r0 + 16 m + lr,
-        // channels 32 kb + 8 g + j
+        // layer 1 on the float32 matrix cores (v_mfma_f32_16x16x4_f32: lane l
+        // supplies A[l % 16][g] and B[g][l % 16], receives C[4 g + i][l % 16]),
+        // transposed: C1^T[ch][row] = sum_k [W1; b1]^T[ch][k] [x y z 1]^T[k][row]
+        // per 16-channel tile tc1 and 16-row tile m.  The lane ends up with
+        // channels 16 tc1 + 4 g + i of row r0 + 16 m + lr; tiles (2 kb,
+        // 2 kb + 1) are then the B operand of layer 2 in slot order
+        // (w3_slot_channel), W2 being stored in that order.
         bf16x8 x1[4][2];
         {
             const float s = scale[c];
             const double cx = cen[3 * c], cy = cen[3 * c + 1], cz = cen[3 * c + 2];
+            float bop[4];
 #pragma unroll
             for (int m = 0; m < 4; m++) {
                 const bool ok = p0 + r0 + 16 * m + lr < pend;
                 const float x = ok ? (float)(px[m] - cx) * s : 0.f;
                 const float y = ok ? (float)(py[m] - cy) * s : 0.f;
                 const float z = ok ? (float)(pz[m] - cz) * s : 0.f;
+                bop[m] = g == 0 ? x : (g == 1 ? y : (g == 2 ? z : 1.f));
+            }
 #pragma unroll
-                for (int kb = 0; kb < 2; kb++)
+            for (int tc1 = 0; tc1 < kC1 / 16; tc1++) {
+                const float4 wv = sW1[16 * tc1 + lr];
+                const float aop = g == 0 ? wv.x : (g == 1 ? wv.y : (g == 2 ? wv.z : wv.w));
 #pragma unroll
-                    for (int j = 0; j < 8; j++) {
-                        const float4 wv = sW1[32 * kb + 8 * g + j];
-                        float a = __fmaf_rn(z, wv.z, __fmaf_rn(y, wv.y, __fmaf_rn(x, wv.x, wv.w)));
-                        x1[m][kb][j] = to_bf16(fmaxf(a, 0.f));
-                    }
+                for (int m = 0; m < 4; m++) {
+                    const f32x4 a = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bop[m], f32x4{0.f, 0.f, 0.f, 0.f}, 0,
+                                                                          0, 0);
+#pragma unroll
+                    for (int i = 0; i < 4; i++) x1[m][tc1 >> 1][4 * (tc1 & 1) + i] = to_bf16(fmaxf(a[i], 0.f));
+                }
             }
         }
         // layer 2 (transposed): per 16-channel tile, bias, ReLU, bfloat16,
@@ -625,6 +643,73 @@ __global__ void __launch_bounds__(256) k_outer_partial(const float *__restrict__
     }
 }
 
+// Second-layer weight gradients on the bfloat16 matrix cores: partial sums
+// of [dW2; db2][a][b] = sum over rows e of U2[a][e] V2[b][e] (a < 65: a1 and
+// the constant 1; b < 128: dz2), one chunk of kChunk rows per workgroup,
+// part[chunk][a * 128 + b] as k_outer_partial writes them.  U2 holds a1,
+// which the forward rounded to bfloat16, and ones: exact in bfloat16.  V2
+// (dz2) is float32, so it enters as two bfloat16 terms hi + lo (hi the
+// nearest bfloat16, lo that of the remainder; together within 2^-16 of
+// dz2), each product exact in float32, accumulated in float32 in a fixed
+// order (v_mfma_f32_16x16x32_bf16 over k-steps of 32 rows).  Wave w owns
+// output columns 32 w .. 32 w + 31 (two 16-column tiles) and all rows as
+// five 16-row tiles (rows 65..79 are zero).  Operand layout as in
+// k_enc_forward: lane l supplies A[l % 16][8 g + j] and B[8 g + j][l % 16]
+// (g = l / 16, j < 8) and receives C[4 g + i][l % 16].
+__global__ void __launch_bounds__(256) k_outer_w2_mfma(const float *__restrict__ U, const float *__restrict__ V,
+                                                     int64_t E, float *__restrict__ part)
+{
+    static_assert(kChunk % 32 == 0 && kC2 == 4 * 32 && kC1 == 64, "tile shapes");
+    const int w = threadIdx.x >> 6, l = __lane_id(), g = l >> 4, r = l & 15;
+    const int64_t e0 = (int64_t)blockIdx.x * kChunk;
+    f32x4 acc[5][2];
+#pragma unroll
+    for (int mt = 0; mt < 5; mt++)
+#pragma unroll
+        for (int nt = 0; nt < 2; nt++) acc[mt][nt] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int ks = 0; ks < kChunk; ks += 32) {
+        const int64_t eb = e0 + ks + 8 * g;        // this lane's 8 rows of the k-step
+        bf16x8 A[5];
+#pragma unroll
+        for (int mt = 0; mt < 5; mt++) {
+            const int a = 16 * mt + r;
+#pragma unroll
+            for (int j = 0; j < 8; j++) {
+                const bool in = eb + j < E;
+                const float u = a < kC1 ? (in ? U[(int64_t)a * E + eb + j] : 0.f) : (a == kC1 && in ? 1.f : 0.f);
+                A[mt][j] = to_bf16(u);
+            }
+        }
+#pragma unroll
+        for (int nt = 0; nt < 2; nt++) {
+            const int b = 32 * w + 16 * nt + r;
+            bf16x8 hi, lo;
+#pragma unroll
+            for (int j = 0; j < 8; j++) {
+                const float v = eb + j < E ? V[(int64_t)b * E + eb + j] : 0.f;
+                const __bf16 h = to_bf16(v);
+                hi[j] = h;
+                lo[j] = to_bf16(v - (float)h);
+            }
+#pragma unroll
+            for (int mt = 0; mt < 5; mt++) {
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt], hi, acc[mt][nt], 0, 0, 0);
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[mt], lo, acc[mt][nt], 0, 0, 0);
+            }
+        }
+    }
+    float *out = part + (int64_t)blockIdx.x * ((kC1 + 1) * kC2);
+#pragma unroll
+    for (int mt = 0; mt < 5; mt++)
+#pragma unroll
+        for (int nt = 0; nt < 2; nt++)
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const int a = 16 * mt + 4 * g + i, b = 32 * w + 16 * nt + r;
+                if (a <= kC1) out[a * kC2 + b] = acc[mt][nt][i];
+            }
+}
+
 // sum of the chunk partials, in chunk order
 __global__ void k_outer_reduce(const float *__restrict__ part, int nchunk, int nout, float *__restrict__ out)
 {
@@ -759,6 +844,7 @@ void pose_net_carve(Carver &c, int np, int ntile, bool train, PoseNetStore &s)
     s.w2t = c.take<__bf16>(kC1 * kC2);
     s.w3t = c.take<__bf16>(kC2 * kC3);
     s.w3p = c.take<__bf16>(kC2 * kC3);
+    s.w2p = c.take<__bf16>(kC1 * kC2);
     s.pmax = c.take<float>((size_t)nt1 * kC3);
     s.parg = c.take<int32_t>((size_t)nt1 * kC3);
     s.feat = c.take<float>((size_t)nc * kC3);
@@ -794,16 +880,16 @@ hipError_t forward_impl(PoseNetStore &s, const float *params, const float *xs, c
                         bool want_arg, hipStream_t st)
 {
     k_norm_stats<<<s.nc, 256, 0, st>>>(xs, xt, s.cr, s.nc, s.cen, s.scale);
-    k_weights_bf16<<<64, 256, 0, st>>>(params, s.w2t, s.w3t, s.w3p);
+    k_weights_bf16<<<64, 256, 0, st>>>(params, s.w2t, s.w3t, s.w3p, s.w2p);
     if (s.ntile > 0) {
         // one persistent workgroup per compute unit (LDS holds one), or fewer
         const int grid = s.ntile < 256 ? s.ntile : 256;
         if (want_arg)
             k_enc_forward<true><<<grid, kEncThreads, 0, st>>>(xs, xt, s.cr, s.toff, s.nc, s.ntile, s.cen, s.scale,
-                                                              params, s.w2t, s.w3p, s.pmax, s.parg);
+                                                              params, s.w2p, s.w3p, s.pmax, s.parg);
         else
             k_enc_forward<false><<<grid, kEncThreads, 0, st>>>(xs, xt, s.cr, s.toff, s.nc, s.ntile, s.cen, s.scale,
-                                                               params, s.w2t, s.w3p, s.pmax, s.parg);
+                                                               params, s.w2p, s.w3p, s.pmax, s.parg);
     }
     k_enc_pool<<<s.nc, kC3, 0, st>>>(s.pmax, s.parg, s.toff, s.nc, s.feat, s.arg);
     k_head_forward<<<s.np, kH, 0, st>>>(s.feat, s.cen, params, s.np, s.z4, s.q, out_T ? out_T : s.T);
@@ -822,9 +908,14 @@ hipError_t pose_net_train(PoseNetStore &s, float *params, float *adam_m, float *
                           const float *xs, const float *xt, const double *label_T, const float *pair_w,
                           float *out_loss, hipStream_t st)
 {
+    // timer slots (pc_set_kernel_timer): 0 forward, 1 backward, 2 the
+    // second-layer weight gradients on the matrix cores
+    timer_slot_begin(0, st);
     hipError_t e = forward_impl(s, params, xs, xt, nullptr, true, st);
+    timer_slot_end(0, st);
     if (e != hipSuccess) return e;
     const int64_t E = (int64_t)s.nc * kC3;
+    timer_slot_begin(1, st);
     k_head_backward<<<s.np, kH, 0, st>>>(params, s.np, s.z4, s.q, label_T, pair_w, out_loss ? out_loss : s.loss,
                                         s.dq, s.dz, s.df);
     k_head_grads<<<512, 256, 0, st>>>(s.feat, s.z4, s.dq, s.dz, s.np, s.grad);
@@ -833,9 +924,12 @@ hipError_t pose_net_train(PoseNetStore &s, float *params, float *adam_m, float *
     k_w3_grads<<<128, 256, 0, st>>>(s.A2, s.G3, s.nc, s.grad);
     k_outer_partial<4, kC1><<<s.nchunk, 256, 0, st>>>(s.U1, s.V1, E, s.part);
     k_outer_reduce<<<1, 256, 0, st>>>(s.part, s.nchunk, 4 * kC1, s.grad + kOffW1);
-    k_outer_partial<kC1 + 1, kC2><<<s.nchunk, 256, 0, st>>>(s.U2, s.V2, E, s.part);
+    timer_slot_begin(2, st);
+    k_outer_w2_mfma<<<s.nchunk, 256, 0, st>>>(s.U2, s.V2, E, s.part);
+    timer_slot_end(2, st);
     k_outer_reduce<<<(((kC1 + 1) * kC2) + 255) / 256, 256, 0, st>>>(s.part, s.nchunk, (kC1 + 1) * kC2,
                                                                       s.grad + kOffW2);
+    timer_slot_end(1, st);
     if (lr > 0.f) k_adam<<<256, 256, 0, st>>>(params, adam_m, adam_v, s.grad, pair_w, s.np, step, lr);
     return hipGetLastError();
 }
