@@ -26,8 +26,21 @@ import statistics
 import sys
 
 
+def _demangle(name: str) -> str:
+    """Itanium-mangled kernel names (some ROCm versions report them so) in
+    readable form, through c++filt when it is installed."""
+    if not name.startswith("_Z"):
+        return name
+    import subprocess
+    try:
+        r = subprocess.run(["c++filt", name], capture_output=True, text=True, timeout=10)
+        return r.stdout.strip() or name
+    except (OSError, subprocess.SubprocessError):
+        return name
+
+
 def _short(name: str) -> str:
-    name = name.replace("(anonymous namespace)::", "").replace("void ", "")
+    name = _demangle(name).replace("(anonymous namespace)::", "").replace("void ", "")
     return name.split("(")[0]
 
 
