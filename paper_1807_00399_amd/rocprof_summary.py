@@ -34,9 +34,27 @@ def _demangle(name: str) -> str:
     import subprocess
     try:
         r = subprocess.run(["c++filt", name], capture_output=True, text=True, timeout=10)
-        return r.stdout.strip() or name
+        out = r.stdout.strip()
+        if out and out != name:
+            return out
     except (OSError, subprocess.SubprocessError):
+        pass
+    # c++filt without support for some argument types: the nested name's
+    # identifiers (<length><name> ... up to E, or I for template arguments)
+    if not name.startswith("_ZN"):
         return name
+    ids, pos = [], 3
+    while pos < len(name) and name[pos].isdigit():
+        k = pos
+        while name[k].isdigit():
+            k += 1
+        n = int(name[pos:k])
+        ids.append(name[k:k + n])
+        pos = k + n
+    ids = [i for i in ids if not i.startswith("_GLOBAL__N")]
+    if not ids:
+        return name
+    return "::".join(ids) + ("<...>" if name[pos:pos + 1] == "I" else "") + "("
 
 
 def _short(name: str) -> str:
