@@ -33,9 +33,10 @@ struct PoseNetStore {
     int32_t *toff;              // tile offsets (nc + 1)
     double *cen;                // per cloud centroid
     float *scale;               // per cloud inverse RMS radius
-    __bf16 *w2t, *w3t;          // bfloat16 copies of W2, W3, [n][k]
+    __bf16 *w3t;                // bfloat16 copy of W3, [n][k]
     __bf16 *w3p;                // W3 in the forward's K-slot order, [n][slot]
     __bf16 *w2p;                // W2 in the forward's K-slot order, [n][slot]
+    __bf16 *w2q;                // W2 by rows, columns in that slot order, [j][slot]
     float *pmax;                // per tile x channel maxima
     int32_t *parg;              // ... and their point indices
     float *feat;                // per cloud features

@@ -100,27 +100,28 @@ __device__ inline int w3_slot_channel(int kb, int s)
     return 32 * kb + (j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4));
 }
 
-// bfloat16 copies of W2 and W3 with k contiguous per output column (w2t,
-// w3t: [n][k]), and both in the slot order of the forward (w2p: [n][slot],
-// slot < 64; w3p: [n][slot], slot < 128)
-__global__ void k_weights_bf16(const float *__restrict__ params, __bf16 *__restrict__ w2t, __bf16 *__restrict__ w3t,
-                               __bf16 *__restrict__ w3p, __bf16 *__restrict__ w2p)
+// bfloat16 copies of the weights the matrix cores read: W3 with k
+// contiguous per output column (w3t: [n][k]); W2 and W3 in the slot order of
+// the forward (w2p: [n][slot], slot < 64; w3p: [n][slot], slot < 128); W2 by
+// rows with its columns in that slot order (w2q: [j][slot], slot < 128)
+__global__ void k_weights_bf16(const float *__restrict__ params, __bf16 *__restrict__ w3t, __bf16 *__restrict__ w3p,
+                               __bf16 *__restrict__ w2p, __bf16 *__restrict__ w2q)
 {
     const float *W2 = params + kOffW2, *W3 = params + kOffW3;
-    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 2 * kC1 * kC2 + 2 * kC2 * kC3;
-         i += gridDim.x * blockDim.x) {
-        if (i >= kC1 * kC2 + 2 * kC2 * kC3) {
-            int j = i - kC1 * kC2 - 2 * kC2 * kC3, n = j / kC1, sl = j % kC1;
-            w2p[j] = to_bf16(W2[w3_slot_channel(sl / 32, sl % 32) * kC2 + n]);
-        } else if (i < kC1 * kC2) {
-            int n = i / kC1, k = i % kC1;
-            w2t[i] = to_bf16(W2[k * kC2 + n]);
-        } else if (i < kC1 * kC2 + kC2 * kC3) {
-            int j = i - kC1 * kC2, n = j / kC2, k = j % kC2;
-            w3t[j] = to_bf16(W3[k * kC3 + n]);
+    constexpr int n3 = kC2 * kC3, n2 = kC1 * kC2;
+    for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < 2 * n3 + 2 * n2; i += gridDim.x * blockDim.x) {
+        if (i < n3) {
+            const int n = i / kC2, k = i % kC2;
+            w3t[i] = to_bf16(W3[k * kC3 + n]);
+        } else if (i < 2 * n3) {
+            const int q = i - n3, n = q / kC2, sl = q % kC2;
+            w3p[q] = to_bf16(W3[w3_slot_channel(sl / 32, sl % 32) * kC3 + n]);
+        } else if (i < 2 * n3 + n2) {
+            const int q = i - 2 * n3, n = q / kC1, sl = q % kC1;
+            w2p[q] = to_bf16(W2[w3_slot_channel(sl / 32, sl % 32) * kC2 + n]);
         } else {
-            int j = i - kC1 * kC2 - kC2 * kC3, n = j / kC2, sl = j % kC2;
-            w3p[j] = to_bf16(W3[w3_slot_channel(sl / 32, sl % 32) * kC3 + n]);
+            const int q = i - 2 * n3 - n2, jr = q / kC2, sl = q % kC2;
+            w2q[q] = to_bf16(W2[jr * kC2 + w3_slot_channel(sl / 32, sl % 32)]);
         }
     }
 }
@@ -524,6 +525,7 @@ __global__ void k_head_grads(const float *__restrict__ feat, const float *__rest
         float a = 0.f;
         if (e < nW4) {
             int i = e / kH, j = e % kH;
+#pragma unroll 16
             for (int p = 0; p < np; p++)
                 a = __fmaf_rn(feat[(int64_t)(2 * p + i / kC3) * kC3 + (i % kC3)], dz[(int64_t)p * kH + j], a);
             grad[kOffW4 + e] = a;
@@ -552,61 +554,111 @@ __global__ void k_head_grads(const float *__restrict__ feat, const float *__rest
 //   A2 (128): a2                     G3 (1): dz3 at channel ch
 // so that dW1|b1 = U1 V1^T, dW2|b2 = U2 V2^T and dW3[k][ch] = sum over
 // clouds of A2[k] G3.  Rows without gradient are all zero.
-__global__ void __launch_bounds__(kC3) k_enc_backward(const float *__restrict__ xs, const float *__restrict__ xt,
-                                                    const int64_t *__restrict__ cr, int nc,
-                                                    const double *__restrict__ cen, const float *__restrict__ scale,
-                                                    const float *__restrict__ params,
-                                                    const __bf16 *__restrict__ w2t, const __bf16 *__restrict__ w3t,
-                                                    const float *__restrict__ feat, const int32_t *__restrict__ arg,
-                                                    const float *__restrict__ df, float *__restrict__ U1,
-                                                    float *__restrict__ V1, float *__restrict__ U2,
-                                                    float *__restrict__ V2, float *__restrict__ A2,
-                                                    float *__restrict__ G3)
+//
+// On the matrix cores, 16 rows per wave (4 waves, 64 rows per workgroup; E
+// is a multiple of 64).  Row e = 16 w + lr of the block (lr =
+// l % 16) is held by the four lane groups g = l / 16, each with a quarter
+// of every channel range, as in the forward's transposed layers:
+//   layer 1 (v_mfma_f32_16x16x4_f32) and layer 2 (v_mfma_f32_16x16x32_bf16,
+//     W2 in slot order) recompute a1 and a2 exactly as the forward does;
+//   dz2[k] = g W3[k][ch] where a2 > 0 (W3 rounded to bfloat16);
+//   d1^T = W2 dz2^T on the bfloat16 matrix cores: A = W2 by rows with its
+//     columns in slot order (w2q), B = dz2 of this lane's channels, which are
+//     that slot order, as hi + lo bfloat16 terms (within 2^-16 of dz2).
+__global__ void __launch_bounds__(256) k_enc_backward_mfma(const float *__restrict__ xs, const float *__restrict__ xt,
+                                                         const int64_t *__restrict__ cr, int nc,
+                                                         const double *__restrict__ cen,
+                                                         const float *__restrict__ scale,
+                                                         const float *__restrict__ params,
+                                                         const __bf16 *__restrict__ w2p, const __bf16 *__restrict__ w2q,
+                                                         const __bf16 *__restrict__ w3t, const float *__restrict__ feat,
+                                                         const int32_t *__restrict__ arg, const float *__restrict__ df,
+                                                         float *__restrict__ U1, float *__restrict__ V1,
+                                                         float *__restrict__ U2, float *__restrict__ V2,
+                                                         float *__restrict__ A2, float *__restrict__ G3)
 {
-    const int c = blockIdx.x, ch = threadIdx.x;
-    if (c >= nc) return;
+    const int w = threadIdx.x >> 6, l = __lane_id(), g = l >> 4, lr = l & 15;
     const int64_t E = (int64_t)nc * kC3;
-    const int64_t e = (int64_t)c * kC3 + ch;
+    const int64_t e = (int64_t)blockIdx.x * 64 + 16 * w + lr;
+    const int c = (int)(e / kC3), ch = (int)(e % kC3);
     const int32_t r = arg[e];
-    const float g = (r >= 0 && feat[e] > 0.f) ? df[e] : 0.f;
-    G3[e] = g;
-    if (g == 0.f) {
-        for (int d = 0; d < 4; d++) U1[d * E + e] = 0.f;
-        for (int j = 0; j < kC1; j++) V1[j * E + e] = 0.f;
-        for (int j = 0; j <= kC1; j++) U2[j * E + e] = 0.f;
-        for (int k = 0; k < kC2; k++) V2[k * E + e] = A2[k * E + e] = 0.f;
-        return;
-    }
-    const float *X = cloud_xyz(xs, xt, c);
-    float x, y, z;
-    norm_point(X, cr[2 * c] + r, cen, scale[c], c, x, y, z);
+    const float gv = (r >= 0 && feat[e] > 0.f) ? df[e] : 0.f;
+    const bool live = gv != 0.f;
+    float x = 0.f, y = 0.f, z = 0.f;
+    if (live) norm_point(cloud_xyz(xs, xt, c), cr[2 * c] + r, cen, scale[c], c, x, y, z);
     const float *W1 = params + kOffW1, *b1 = params + kOffB1, *b2 = params + kOffB2;
-    float a1[kC1], d1[kC1];
-    for (int j = 0; j < kC1; j++) {
-        float a = __fmaf_rn(z, W1[2 * kC1 + j], __fmaf_rn(y, W1[kC1 + j], __fmaf_rn(x, W1[j], b1[j])));
-        a1[j] = (float)to_bf16(fmaxf(a, 0.f));
-        d1[j] = 0.f;
+    // layer 1: lane holds channels 16 t + 4 g + i of its row (t < 4)
+    const float bop = g == 0 ? x : (g == 1 ? y : (g == 2 ? z : 1.f));
+    float a1v[4][4];
+    bf16x8 x1[2];
+#pragma unroll
+    for (int t = 0; t < kC1 / 16; t++) {
+        const int chl = 16 * t + lr;
+        const float aop = g < 3 ? W1[g * kC1 + chl] : b1[chl];
+        const f32x4 a = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bop, f32x4{0.f, 0.f, 0.f, 0.f}, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const __bf16 h = to_bf16(fmaxf(a[i], 0.f));
+            x1[t >> 1][4 * (t & 1) + i] = h;
+            a1v[t][i] = (float)h;
+        }
     }
-    const __bf16 *w3c = w3t + (int64_t)ch * kC2;          // W3[k][ch], k contiguous
-    for (int k = 0; k < kC2; k++) {
-        const __bf16 *w2c = w2t + (int64_t)k * kC1;       // W2[j][k], j contiguous
-        float a = 0.f;
-        for (int j = 0; j < kC1; j++) a = __fmaf_rn(a1[j], (float)w2c[j], a);
-        const float a2 = (float)to_bf16(fmaxf(a + b2[k], 0.f));
-        const float dz2 = a2 > 0.f ? g * (float)w3c[k] : 0.f;
-        A2[k * E + e] = a2;
-        V2[k * E + e] = dz2;
-        for (int j = 0; j < kC1; j++) d1[j] = __fmaf_rn((float)w2c[j], dz2, d1[j]);
+    // layer 2: lane holds channels 16 t + 4 g + i (t < 8); then dz2 there
+    float dz2[8][4];
+#pragma unroll
+    for (int t = 0; t < kC2 / 16; t++) {
+        f32x4 acc = {b2[16 * t + 4 * g], b2[16 * t + 4 * g + 1], b2[16 * t + 4 * g + 2], b2[16 * t + 4 * g + 3]};
+#pragma unroll
+        for (int kb = 0; kb < 2; kb++) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&w2p[(16 * t + lr) * kC1 + 32 * kb + 8 * g]);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, x1[kb], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const int k = 16 * t + 4 * g + i;
+            const float a2 = (float)to_bf16(fmaxf(acc[i], 0.f));
+            const float d = a2 > 0.f ? gv * (float)w3t[(int64_t)ch * kC2 + k] : 0.f;
+            dz2[t][i] = d;
+            A2[k * E + e] = live ? a2 : 0.f;
+            V2[k * E + e] = d;
+        }
     }
-    U1[0 * E + e] = x;
-    U1[1 * E + e] = y;
-    U1[2 * E + e] = z;
-    U1[3 * E + e] = 1.f;
-    for (int j = 0; j < kC1; j++) {
-        V1[j * E + e] = a1[j] > 0.f ? d1[j] : 0.f;
-        U2[j * E + e] = a1[j];
+    // d1^T[j][row] = sum_k W2[j][k] dz2[k]: k-blocks kb of 32 channels are the
+    // lane's tiles (2 kb, 2 kb + 1), i.e. the slot order of w2q
+    bf16x8 bh[4], bl[4];
+#pragma unroll
+    for (int kb = 0; kb < 4; kb++)
+#pragma unroll
+        for (int jj = 0; jj < 8; jj++) {
+            const float v = dz2[2 * kb + (jj >> 2)][jj & 3];
+            const __bf16 h = to_bf16(v);
+            bh[kb][jj] = h;
+            bl[kb][jj] = to_bf16(v - (float)h);
+        }
+#pragma unroll
+    for (int t = 0; t < kC1 / 16; t++) {
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kb = 0; kb < 4; kb++) {
+            const bf16x8 a = *reinterpret_cast<const bf16x8 *>(&w2q[(16 * t + lr) * kC2 + 32 * kb + 8 * g]);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bh[kb], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bl[kb], acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const int j = 16 * t + 4 * g + i;
+            V1[j * E + e] = a1v[t][i] > 0.f ? acc[i] : 0.f;
+            U2[j * E + e] = live ? a1v[t][i] : 0.f;
+        }
     }
-    U2[kC1 * E + e] = 1.f;
+    if (g == 0) {
+        U1[0 * E + e] = x;
+        U1[1 * E + e] = y;
+        U1[2 * E + e] = z;
+        U1[3 * E + e] = live ? 1.f : 0.f;
+        U2[kC1 * E + e] = live ? 1.f : 0.f;
+        G3[e] = gv;
+    }
 }
 
 // Partial sums of out[a][b] = sum over rows e of U[a][e] V[b][e], one chunk
@@ -715,6 +767,8 @@ __global__ void k_outer_reduce(const float *__restrict__ part, int nchunk, int n
 {
     for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nout; i += gridDim.x * blockDim.x) {
         float a = 0.f;
+        // unrolled so the loads go out ahead of the (ordered) additions
+#pragma unroll 16
         for (int ch = 0; ch < nchunk; ch++) a += part[(int64_t)ch * nout + i];
         out[i] = a;
     }
@@ -729,6 +783,7 @@ __global__ void k_w3_grads(const float *__restrict__ A2, const float *__restrict
         float a = 0.f;
         if (i < kC2 * kC3) {
             const int k = i / kC3, ch = i % kC3;
+#pragma unroll 16
             for (int c = 0; c < nc; c++)
                 a = __fmaf_rn(A2[k * E + (int64_t)c * kC3 + ch], G3[(int64_t)c * kC3 + ch], a);
             grad[kOffW3 + i] = a;
@@ -841,10 +896,10 @@ void pose_net_carve(Carver &c, int np, int ntile, bool train, PoseNetStore &s)
     s.toff = c.take<int32_t>(nc + 1);
     s.cen = c.take<double>((size_t)nc * 3);
     s.scale = c.take<float>(nc);
-    s.w2t = c.take<__bf16>(kC1 * kC2);
     s.w3t = c.take<__bf16>(kC2 * kC3);
     s.w3p = c.take<__bf16>(kC2 * kC3);
     s.w2p = c.take<__bf16>(kC1 * kC2);
+    s.w2q = c.take<__bf16>(kC1 * kC2);
     s.pmax = c.take<float>((size_t)nt1 * kC3);
     s.parg = c.take<int32_t>((size_t)nt1 * kC3);
     s.feat = c.take<float>((size_t)nc * kC3);
@@ -880,7 +935,7 @@ hipError_t forward_impl(PoseNetStore &s, const float *params, const float *xs, c
                         bool want_arg, hipStream_t st)
 {
     k_norm_stats<<<s.nc, 256, 0, st>>>(xs, xt, s.cr, s.nc, s.cen, s.scale);
-    k_weights_bf16<<<64, 256, 0, st>>>(params, s.w2t, s.w3t, s.w3p, s.w2p);
+    k_weights_bf16<<<64, 256, 0, st>>>(params, s.w3t, s.w3p, s.w2p, s.w2q);
     if (s.ntile > 0) {
         // one persistent workgroup per compute unit (LDS holds one), or fewer
         const int grid = s.ntile < 256 ? s.ntile : 256;
@@ -919,8 +974,9 @@ hipError_t pose_net_train(PoseNetStore &s, float *params, float *adam_m, float *
     k_head_backward<<<s.np, kH, 0, st>>>(params, s.np, s.z4, s.q, label_T, pair_w, out_loss ? out_loss : s.loss,
                                         s.dq, s.dz, s.df);
     k_head_grads<<<512, 256, 0, st>>>(s.feat, s.z4, s.dq, s.dz, s.np, s.grad);
-    k_enc_backward<<<s.nc, kC3, 0, st>>>(xs, xt, s.cr, s.nc, s.cen, s.scale, params, s.w2t, s.w3t, s.feat, s.arg,
-                                         s.df, s.U1, s.V1, s.U2, s.V2, s.A2, s.G3);
+    k_enc_backward_mfma<<<(int)(E / 64), 256, 0, st>>>(xs, xt, s.cr, s.nc, s.cen, s.scale, params, s.w2p, s.w2q,
+                                                       s.w3t, s.feat, s.arg, s.df, s.U1, s.V1, s.U2, s.V2, s.A2,
+                                                       s.G3);
     k_w3_grads<<<128, 256, 0, st>>>(s.A2, s.G3, s.nc, s.grad);
     k_outer_partial<4, kC1><<<s.nchunk, 256, 0, st>>>(s.U1, s.V1, E, s.part);
     k_outer_reduce<<<1, 256, 0, st>>>(s.part, s.nchunk, 4 * kC1, s.grad + kOffW1);
