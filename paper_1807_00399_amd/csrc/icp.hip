@@ -808,6 +808,7 @@ __global__ void __launch_bounds__(kFinThreads) k_icp_finalize(const float2 *__re
     const int a = threadIdx.x >> 5, j = threadIdx.x & 31;
     if (a < kAcc) {
         CSum c{0.f, 0.f};
+#pragma unroll 4
         for (int b = g0 + j; b < g1; b += 32) {
             float2 v = gpart[(int64_t)b * kAcc + a];
             c = csum_merge(c, CSum{v.x, v.y});
