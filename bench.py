@@ -65,15 +65,8 @@ def autotune_step(args, step, tag, n_points):
     """Sets the tuning for this workload (cached choice, or timed now)."""
     from paper_1807_00399_amd import autotune, pcgpu
     if args.no_autotune:
-        if args.persistent:
-            t = pcgpu.get_tuning()
-            pcgpu.set_tuning(t["icp_block_threads"], t["icp_leaf"], t["node_budget"], t["sort_queries"], 1)
         return {"tuning": pcgpu.get_tuning(), "source": "default"}
     r = autotune.tune(step, tag, n_points, cache_file=TUNING_CACHE, use_cache=not args.retune)
-    if args.persistent:
-        t = pcgpu.get_tuning()
-        pcgpu.set_tuning(t["icp_block_threads"], t["icp_leaf"], t["node_budget"], t["sort_queries"], 1)
-        return {"tuning": pcgpu.get_tuning(), "source": "forced persistent loop"}
     if not r["from_cache"]:
         # record the timings where a GPU run keeps its outputs
         out = os.path.join(ROOT, "gpurun_out")
@@ -101,8 +94,6 @@ def parse():
                     help="single-pair and batch workloads: time eager launches instead of replays of a captured graph")
     ap.add_argument("--no-learned", action="store_true",
                     help="default run: skip the learned-initialiser comparison")
-    ap.add_argument("--persistent", action="store_true",
-                    help="ICP workloads: run the ICP loop as one persistent cooperative launch (after tuning)")
     ap.add_argument("--cloud", choices=["room", "street"], default="room",
                     help="knn and normals workloads: the cloud queried against itself")
     ap.add_argument("--no-street", action="store_true",
@@ -691,12 +682,7 @@ def bench_batch(args):
     # source points processed by launch i: pairs still iterating
     ran = np.array([r["iterations_run"] for r in st])
     sizes = np.diff(off)
-    persistent = bool(pcgpu.get_tuning()["icp_persistent"])
-    if persistent:
-        # one launch runs every pass: each pair's iterations and the statistics pass
-        active = np.array([int((sizes * (ran + 1)).sum())])
-    else:
-        active = np.array([int(sizes[ran > i].sum()) for i in range(len(kern))])
+    active = np.array([int(sizes[ran > i].sum()) for i in range(len(kern))])
     achieved = ICP_BYTES_PER_POINT * active.sum() / kern.sum() / 1e9
     pts_iter = int((sizes * ran).sum())
 
@@ -740,8 +726,8 @@ def bench_batch(args):
                                                                         return_counts=True))},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": None if persistent else traffic_from_profiles("icp_accum", "batch"),
-                     "kernel": "k_icp_persistent" if persistent else "k_icp_accum",
+                     "traffic": traffic_from_profiles("icp_accum", "batch"),
+                     "kernel": "k_icp_accum",
                      "avg_kernel_us": float(kern.mean()) * 1e6,
                      "algorithmic_bytes_per_launch": float(ICP_BYTES_PER_POINT * active.mean())},
     }
@@ -911,20 +897,13 @@ def bench_single(args, workload, with_cpu=True):
         kern_ms += [ev.elapsed_ms(i) for i in range(cnt)]
         loop_ms.append(ev.span_ms(0, cnt - 1))
     pcgpu.lib.pc_set_kernel_timer(None, None, 0)
-    persistent = bool(pcgpu.get_tuning()["icp_persistent"])
     loop_s = float(np.median(loop_ms)) * 1e-3
-    if persistent:
-        # one launch runs every pass (iterations + the statistics pass)
-        avg_kernel_s = float(np.median(kern_ms)) * 1e-3
-        algo_bytes = ICP_BYTES_PER_POINT * w.n * (w.iters + 1)
-        kernel_name, by_iter = "k_icp_persistent", None
-    else:
-        avg_kernel_s = float(np.mean(kern_ms)) * 1e-3
-        algo_bytes = ICP_BYTES_PER_POINT * w.n
-        kernel_name = "k_icp_accum"
-        by_iter = [round(float(x) * 1e3, 1) for x in np.median(np.array(kern_ms).reshape(-1, w.iters), axis=0)]
+    avg_kernel_s = float(np.mean(kern_ms)) * 1e-3
+    algo_bytes = ICP_BYTES_PER_POINT * w.n
+    kernel_name = "k_icp_accum"
+    by_iter = [round(float(x) * 1e3, 1) for x in np.median(np.array(kern_ms).reshape(-1, w.iters), axis=0)]
     achieved = algo_bytes / avg_kernel_s / 1e9
-    traffic = None if persistent else traffic_from_profiles("icp_accum", workload)
+    traffic = traffic_from_profiles("icp_accum", workload)
 
     out = {
         "metric": METRIC,
@@ -952,7 +931,7 @@ def bench_single(args, workload, with_cpu=True):
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": kernel_name, "avg_kernel_us": avg_kernel_s * 1e6,
                      "algorithmic_bytes_per_launch": algo_bytes,
-                     "valu_issue_share": None if persistent else valu_from_profiles(workload)},
+                     "valu_issue_share": valu_from_profiles(workload)},
     }
     g = single_golden(w)
     out["pose_vs_oracle"] = None if g is None else pose_check(

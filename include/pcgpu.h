@@ -435,14 +435,12 @@ pc_status icp_learned_batched(int mode, const float *params, int n_pairs,
  *                      neighbouring cells; pays off when the input order is
  *                      not already spatially coherent.  Changes only the
  *                      order of the compensated sums.
- *   icp_persistent     0 or 1: point-to-plane ICP with nearest-neighbour
- *                      correspondences (icp_point_to_plane*) runs its whole
- *                      loop as one cooperative launch of co-resident
- *                      workgroups with grid barriers between the phases
- *                      (accumulate, merge, solve) instead of three launches
- *                      per iteration; results are bit-identical.  The
- *                      per-iteration kernel timer then records the whole
- *                      loop in slot 0.
+ *   icp_persistent     must be 0.  Reserved for running the whole
+ *                      point-to-plane loop as one cooperative launch of
+ *                      co-resident workgroups with grid barriers between
+ *                      its phases; that form is switched off (a run of it
+ *                      stopped making progress and the cause is not
+ *                      established), so pc_set_tuning rejects 1.
  * Defaults: 128, 16, 1, 1, 0.  pc_set_tuning returns PC_EINVAL for other
  * values.
  * ---------------------------------------------------------------------- */

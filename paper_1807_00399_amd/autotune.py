@@ -4,12 +4,10 @@ The paper chose its implementation variants by benchmarking the
 alternatives (Section 2, "Performance"); this module does the same at run
 time for the knobs of the GPU path (pc_tuning: accumulate block size, the
 leaf size of the searches, the node budget that sets the pyramid's finest
-level, whether the ICP queries run in Morton order, and whether the ICP loop
-runs as one persistent cooperative launch).  The launch-shape candidates are
-timed in input order with the lockstep loop; the winner is then timed once
-more with Morton-ordered queries, and the better of those once more as a
-persistent launch.  Every candidate computes the same correspondences, so
-the choice only affects speed.
+level, and whether the ICP queries run in Morton order).  The launch-shape
+candidates are timed in input order; the winner is then timed once more
+with Morton-ordered queries.  Every candidate computes the same
+correspondences, so the choice only affects speed.
 
     from paper_1807_00399_amd import autotune
     best = autotune.tune(step, tag="uneven_pairs", n_points=b.n)
@@ -98,14 +96,14 @@ def tune(step, tag: str, n_points: int, device_name: str | None = None, candidat
         hit = load_cache(cache_file).get(key)
         if hit and "tuning" in hit:
             t = hit["tuning"]
-            # entries from before the query-order and persistent knobs were
-            # timed in input order with the lockstep loop
-            pcgpu.set_tuning(t["icp_block_threads"], t["icp_leaf"], t["node_budget"], t.get("sort_queries", 0),
-                             t.get("icp_persistent", 0))
+            # entries from before the query-order knob were timed in input
+            # order; the persistent loop is switched off, so its flag is not
+            # applied
+            pcgpu.set_tuning(t["icp_block_threads"], t["icp_leaf"], t["node_budget"], t.get("sort_queries", 0))
             return {**hit, "tuning": pcgpu.get_tuning(), "from_cache": True}
 
-    def timed(b, l, nb, sq, pe=0):
-        pcgpu.set_tuning(b, l, nb, sq, pe)
+    def timed(b, l, nb, sq):
+        pcgpu.set_tuning(b, l, nb, sq)
         step()                      # warm-up (the workspace does not depend on the tuning)
         sync()
         best = math.inf
@@ -114,14 +112,12 @@ def tune(step, tag: str, n_points: int, device_name: str | None = None, candidat
             step()
             sync()
             best = min(best, clock() - t0)
-        return {"icp_block_threads": b, "icp_leaf": l, "node_budget": nb, "sort_queries": sq, "icp_persistent": pe,
+        return {"icp_block_threads": b, "icp_leaf": l, "node_budget": nb, "sort_queries": sq, "icp_persistent": 0,
                 "seconds": best}
 
     timings = [timed(b, l, nb, 0) for b, l, nb in candidates]
     win = min(timings, key=lambda r: r["seconds"])
     timings.append(timed(win["icp_block_threads"], win["icp_leaf"], win["node_budget"], 1))
-    win = min(timings, key=lambda r: r["seconds"])
-    timings.append(timed(win["icp_block_threads"], win["icp_leaf"], win["node_budget"], win["sort_queries"], 1))
     win = min(timings, key=lambda r: r["seconds"])
     tuning = {"icp_block_threads": win["icp_block_threads"], "icp_leaf": win["icp_leaf"],
               "node_budget": win["node_budget"], "sort_queries": win["sort_queries"],

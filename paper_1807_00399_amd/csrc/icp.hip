@@ -148,6 +148,15 @@ struct Near64 {
     }
 };
 
+// p[i] by a load the compiler cannot merge with an earlier load of it, so
+// that neither the first value nor what was computed from it is kept in
+// registers until this point
+__device__ inline float4 reload(const float4 *p, int64_t i)
+{
+    asm volatile("" : "+s"(p));
+    return p[i];
+}
+
 // float32 (hi, lo) split of the float64 pose used by the transform below
 __device__ inline void split_pose(IcpState *st)
 {
@@ -233,7 +242,7 @@ constexpr int kGapThreads = 256;
 __global__ void __launch_bounds__(kGapThreads) k_nrm_gap(GridView g, int64_t n_all, const float *__restrict__ tgt_n,
                                                         float4 *__restrict__ nrm)
 {
-    __shared__ uint32_t stk[kStack * kGapThreads];
+    __shared__ __align__(8) uint32_t stk[SearchStack::words * kGapThreads];
     const int64_t s = xcd_block(blockIdx.x, gridDim.x) * (int64_t)kGapThreads + threadIdx.x;
     if (s >= n_all) return;
     const GridParams P = g.params[key_cloud(g.keys[s])];
@@ -242,7 +251,7 @@ __global__ void __launch_bounds__(kGapThreads) k_nrm_gap(GridView g, int64_t n_a
     TopK<2> top;
     top.init(2);
     Query q{p.x, p.y, p.z};
-    search<TopK<2>, 16>(g, P, q, top, 2, stk + threadIdx.x, kGapThreads);
+    search<TopK<2>, 16>(g, P, q, top, 2, lane_stack<SearchStack>(stk, kGapThreads));
     // the point itself (or an exact duplicate) is first; the second key is
     // the squared distance to the nearest other point, rounded to float32
     // (relative error below 2^-21)
@@ -355,7 +364,7 @@ __device__ inline void plane_values(float hx, float lx, float hy, float ly, floa
 //       |p' - q|^2, zeros; c = the target cloud's cube centre.
 // One accumulate block (block lblk of the pair that owns it): the body of
 // k_icp_accum and of the accumulate phase of k_icp_persistent.  stk: the
-// block's LDS stack (kStackNear * NT entries), reused for the reduction.
+// block's LDS stack (NearStack::words * NT words), reused for the reduction.
 template <int NT, int LEAF, int METRIC>
 __device__ inline void accum_block(const GridView &g, const float4 *__restrict__ srcp,
                                    const int64_t *__restrict__ soff, const int32_t *__restrict__ boff, int np,
@@ -387,6 +396,9 @@ __device__ inline void accum_block(const GridView &g, const float4 *__restrict__
         df_row(Rh, Rl, px, py, pz, hx, lx);
         df_row(Rh + 4, Rl + 4, px, py, pz, hy, ly);
         df_row(Rh + 8, Rl + 8, px, py, pz, hz, lz);
+        // the search needs q alone; the source point and the double-float
+        // p' are loaded and computed again after it (registers held across
+        // the search cost occupancy, which the search's latency needs)
         Query q{hx + lx, hy + ly, hz + lz};
         // q is p' rounded to float32 (plus ~2^-44 relative): per axis it is
         // within half an ulp, bounded here with slack, of the float64 p'
@@ -418,7 +430,7 @@ __device__ inline void accum_block(const GridView &g, const float4 *__restrict__
             }
         }
         if (!done) {
-            if (!searched) search<NearBand, LEAF, kStackNear>(g, P, q, v, 1, stk + threadIdx.x, NT);
+            if (!searched) search<NearBand, LEAF>(g, P, q, v, 1, lane_stack<NearStack>(stk, NT));
             if (v.best_pos >= 0) {
                 float b = v.best_key();
                 float e = v.err(b);
@@ -429,6 +441,10 @@ __device__ inline void accum_block(const GridView &g, const float4 *__restrict__
                     j = v.best_pos;
                 } else if (!sure_out) {
                     const double *T = st->T;
+                    const float4 sp2 = reload(srcp, i);
+                    px = sp2.x;
+                    py = sp2.y;
+                    pz = sp2.z;
                     Near64 w;
                     w.px = T[0] * (double)px + T[1] * (double)py + T[2] * (double)pz + T[3];
                     w.py = T[4] * (double)px + T[5] * (double)py + T[6] * (double)pz + T[7];
@@ -438,13 +454,19 @@ __device__ inline void accum_block(const GridView &g, const float4 *__restrict__
                     w.best_orig = 0xffffffffu;
                     w.best_pos = -1;
                     w.r2 = b + 2.f * e;
-                    cover<Near64, LEAF, kStackNear>(g, P, q, w, stk + threadIdx.x, NT, 0u, 0u);
+                    cover<Near64, LEAF>(g, P, q, w, lane_stack<NearStack>(stk, NT), 0u, 0u);
                     j = w.best_pos;
                 }
             }
             const int2 pn = v.best_pos >= 0 ? make_int2(v.best_pos, (int32_t)v.best_node) : make_int2(-1, -1);
             if (pn.x != pv.x || pn.y != pv.y) prev[i] = pn;
         }
+    }
+    if (j >= 0) {
+        const float4 sp = reload(srcp, i);
+        df_row(Rh, Rl, sp.x, sp.y, sp.z, hx, lx);
+        df_row(Rh + 4, Rl + 4, sp.x, sp.y, sp.z, hy, ly);
+        df_row(Rh + 8, Rl + 8, sp.x, sp.y, sp.z, hz, lz);
     }
     // This lane's values of the sums (zero when it is not an inlier).
     float val[kAcc];
@@ -514,8 +536,8 @@ k_icp_accum(GridView g, const float4 *__restrict__ srcp, const int64_t *__restri
             float2 *__restrict__ part, uint32_t *__restrict__ pcnt, int nblk, float w_point, float w_plane)
 {
     // the DFS stack and, after the search, the reduction buffer share LDS
-    static_assert((kAcc / 2) * (NT + 1) <= kStackNear * NT, "reduction buffer must fit in the stack");
-    __shared__ uint32_t stk[kStackNear * NT];
+    static_assert((kAcc / 2) * (NT + 1) <= NearStack::words * NT, "reduction buffer must fit in the stack");
+    __shared__ __align__(8) uint32_t stk[NearStack::words * NT];
     accum_block<NT, LEAF, METRIC>(g, srcp, soff, boff, np, nrm, prev, state, dmaxv, final_pass, part, pcnt, w_point,
                                   w_plane, xcd_block(blockIdx.x, nblk), stk);
 }
@@ -848,8 +870,8 @@ k_icp_persistent(GridView g, const float4 *__restrict__ srcp, const int64_t *__r
                  pc_icp_stats *out_stats, double *__restrict__ hist, int hist_stride,
                  const GridParams *__restrict__ params, int32_t *__restrict__ queue)
 {
-    static_assert((kAcc / 2) * (NT + 1) <= kStackNear * NT, "reduction buffer must fit in the stack");
-    __shared__ uint32_t stk[kStackNear * NT];
+    static_assert((kAcc / 2) * (NT + 1) <= NearStack::words * NT, "reduction buffer must fit in the stack");
+    __shared__ __align__(8) uint32_t stk[NearStack::words * NT];
     __shared__ int next;
     cg::grid_group grid = cg::this_grid();
     const int G = (int)gridDim.x;

@@ -29,14 +29,14 @@ template <int KT, int LEAF>
 __global__ void __launch_bounds__(kQThreads) k_knn(GridView g, const float *__restrict__ qry, int64_t nq, int k,
                                                  int32_t *__restrict__ out_idx, float *__restrict__ out_d2)
 {
-    __shared__ uint32_t stk[kStack * kQThreads];
+    __shared__ __align__(8) uint32_t stk[SearchStack::words * kQThreads];
     const GridParams P = g.params[0];   // the reference cloud
     int64_t i = xcd_block(blockIdx.x, gridDim.x) * (int64_t)kQThreads + threadIdx.x;
     if (i >= nq) return;
     Query q{qry[3 * i], qry[3 * i + 1], qry[3 * i + 2]};
     TopK<KT> top;
     top.init(k);
-    search<TopK<KT>, LEAF>(g, P, q, top, k, stk + threadIdx.x, kQThreads);
+    search<TopK<KT>, LEAF>(g, P, q, top, k, lane_stack<SearchStack>(stk, kQThreads));
 #pragma unroll
     for (int s = 0; s < KT; s++) {
         if (s >= KT - k) {
@@ -169,9 +169,10 @@ template <int KT, int LEAF>
 __global__ void __launch_bounds__(kQThreads) k_normals(GridView g, int64_t n_all, const float *__restrict__ xyz, int k,
                                                      const int32_t *__restrict__ kc, float cap2, int min_pts,
                                                      float vx, float vy, float vz, float *__restrict__ out_n,
-                                                     float *__restrict__ out_c, float4 *__restrict__ srt)
+                                                     float *__restrict__ out_c, float4 *__restrict__ srt, int k_lo,
+                                                     int k_hi)
 {
-    __shared__ uint32_t stk[kStack * kQThreads];
+    __shared__ __align__(8) uint32_t stk[SearchStack::words * kQThreads];
     int64_t s = xcd_block(blockIdx.x, gridDim.x) * (int64_t)kQThreads + threadIdx.x;
     // queries are the points in sorted order, so neighbouring lanes search
     // neighbouring cells
@@ -179,12 +180,13 @@ __global__ void __launch_bounds__(kQThreads) k_normals(GridView g, int64_t n_all
     const int cl = key_cloud(g.keys[s]);
     const GridParams P = g.params[cl];
     if (kc) k = kc[cl];
+    if (k <= k_lo || k > k_hi) return;   // another launch serves this cloud's k
     float4 p = g.pts[s];
     uint32_t qi = __float_as_uint(p.w);
     Query q{p.x, p.y, p.z};
     TopK<KT> top;
     top.init(k, cap2);
-    search<TopK<KT>, LEAF>(g, P, q, top, k, stk + threadIdx.x, kQThreads);
+    search<TopK<KT>, LEAF>(g, P, q, top, k, lane_stack<SearchStack>(stk, kQThreads));
     // the point itself (or an exact duplicate) is first, the nearest other
     // point second (selected with static indices: the list stays in registers)
     float gap = 0.f;
@@ -235,7 +237,7 @@ __global__ void __launch_bounds__(kQThreads) k_normals_radius(GridView g, int64_
                                                             float vy, float vz, float *__restrict__ out_n,
                                                             float *__restrict__ out_c)
 {
-    __shared__ uint32_t stk[kStack * kQThreads];
+    __shared__ __align__(8) uint32_t stk[SearchStack::words * kQThreads];
     int64_t s = xcd_block(blockIdx.x, gridDim.x) * (int64_t)kQThreads + threadIdx.x;
     if (s >= n_all) return;
     const GridParams P = g.params[key_cloud(g.keys[s])];
@@ -244,7 +246,7 @@ __global__ void __launch_bounds__(kQThreads) k_normals_radius(GridView g, int64_
     Query q{p.x, p.y, p.z};
     RadiusCov v;
     v.init(r2);
-    search<RadiusCov, LEAF>(g, P, q, v, 1, stk + threadIdx.x, kQThreads);
+    search<RadiusCov, LEAF>(g, P, q, v, 1, lane_stack<SearchStack>(stk, kQThreads));
     double cxx = 0, cxy = 0, cxz = 0, cyy = 0, cyz = 0, czz = 0;
     if (v.m >= 3) {
         const double m = v.m, mx = v.sx / m, my = v.sy / m, mz = v.sz / m;
@@ -278,20 +280,30 @@ void launch_knn(const GridStore &g, const float *qry, int64_t nq, int k, int32_t
 
 template <int KT, int LEAF>
 void launch_normals_l(const GridStore &g, const float *xyz, int k, const int32_t *kc, float cap2, int min_pts,
-                      const float *vp, float *on, float *oc, float4 *srt, hipStream_t s)
+                      const float *vp, float *on, float *oc, float4 *srt, int k_lo, int k_hi, hipStream_t s)
 {
     int blocks = (int)((g.n + kQThreads - 1) / kQThreads);
     k_normals<KT, LEAF><<<blocks, kQThreads, 0, s>>>(g.view(), g.n, xyz, k, kc, cap2, min_pts, vp[0], vp[1], vp[2],
-                                                     on, oc, srt);
+                                                     on, oc, srt, k_lo, k_hi);
 }
 
+// the points of clouds whose k lies in (k_lo, k_hi] (KT >= k_hi)
 template <int KT>
 void launch_normals(const GridStore &g, const float *xyz, int k, const int32_t *kc, float cap2, int min_pts,
-                    const float *vp, float *on, float *oc, float4 *srt, hipStream_t s)
+                    const float *vp, float *on, float *oc, float4 *srt, int k_lo, int k_hi, hipStream_t s)
 {
-    if (g.leaf <= 8) launch_normals_l<KT, 8>(g, xyz, k, kc, cap2, min_pts, vp, on, oc, srt, s);
-    else if (g.leaf <= 16) launch_normals_l<KT, 16>(g, xyz, k, kc, cap2, min_pts, vp, on, oc, srt, s);
-    else launch_normals_l<KT, 32>(g, xyz, k, kc, cap2, min_pts, vp, on, oc, srt, s);
+    if (g.leaf <= 8) launch_normals_l<KT, 8>(g, xyz, k, kc, cap2, min_pts, vp, on, oc, srt, k_lo, k_hi, s);
+    else if (g.leaf <= 16) launch_normals_l<KT, 16>(g, xyz, k, kc, cap2, min_pts, vp, on, oc, srt, k_lo, k_hi, s);
+    else launch_normals_l<KT, 32>(g, xyz, k, kc, cap2, min_pts, vp, on, oc, srt, k_lo, k_hi, s);
+}
+
+// list sizes the kernels are built for: the smallest one holding k
+constexpr int kListSizes[] = {4, 8, 10, 16, 32};
+int list_size(int k)
+{
+    for (int t : kListSizes)
+        if (k <= t) return t;
+    return 32;
 }
 
 }  // namespace
@@ -303,6 +315,7 @@ hipError_t knn_run(const GridStore &g, const float *qry, int64_t nq, int k, int3
     if (k <= 1) launch_knn<1>(g, qry, nq, k, oi, od, s);
     else if (k <= 4) launch_knn<4>(g, qry, nq, k, oi, od, s);
     else if (k <= 8) launch_knn<8>(g, qry, nq, k, oi, od, s);
+    else if (k <= 10) launch_knn<10>(g, qry, nq, k, oi, od, s);
     else if (k <= 16) launch_knn<16>(g, qry, nq, k, oi, od, s);
     else launch_knn<32>(g, qry, nq, k, oi, od, s);
     timer_search_end(s);
@@ -310,15 +323,29 @@ hipError_t knn_run(const GridStore &g, const float *qry, int64_t nq, int k, int3
 }
 
 hipError_t normals_run(const GridStore &g, const float *xyz, int k_max, const int32_t *kc, const float *vp,
-                       float *on, float *oc, hipStream_t s, float cap2, int min_pts, float4 *srt)
+                       float *on, float *oc, hipStream_t s, float cap2, int min_pts, float4 *srt, int k_min)
 {
     if (g.n <= 0) return hipSuccess;
     if (!(cap2 == INFINITY)) srt = nullptr;   // the gap needs plain k-NN
+    // one launch per list size the clouds' k values need (a batch mixing
+    // k = 10 and k = 16 clouds runs each with its own list), each serving
+    // the clouds whose k falls in its range
+    const int lo_size = list_size(kc && k_min > 0 ? k_min : k_max), hi_size = list_size(k_max);
     timer_search_begin(s);
-    if (k_max <= 4) launch_normals<4>(g, xyz, k_max, kc, cap2, min_pts, vp, on, oc, srt, s);
-    else if (k_max <= 8) launch_normals<8>(g, xyz, k_max, kc, cap2, min_pts, vp, on, oc, srt, s);
-    else if (k_max <= 16) launch_normals<16>(g, xyz, k_max, kc, cap2, min_pts, vp, on, oc, srt, s);
-    else launch_normals<32>(g, xyz, k_max, kc, cap2, min_pts, vp, on, oc, srt, s);
+    int prev = 0;
+    for (int t : kListSizes) {
+        if (t < lo_size || t > hi_size) {
+            if (t < lo_size) prev = t;
+            continue;
+        }
+        const int k_lo = t == lo_size ? 0 : prev, k_hi = t == hi_size ? PCGPU_KMAX : t;
+        if (t == 4) launch_normals<4>(g, xyz, k_max, kc, cap2, min_pts, vp, on, oc, srt, k_lo, k_hi, s);
+        else if (t == 8) launch_normals<8>(g, xyz, k_max, kc, cap2, min_pts, vp, on, oc, srt, k_lo, k_hi, s);
+        else if (t == 10) launch_normals<10>(g, xyz, k_max, kc, cap2, min_pts, vp, on, oc, srt, k_lo, k_hi, s);
+        else if (t == 16) launch_normals<16>(g, xyz, k_max, kc, cap2, min_pts, vp, on, oc, srt, k_lo, k_hi, s);
+        else launch_normals<32>(g, xyz, k_max, kc, cap2, min_pts, vp, on, oc, srt, k_lo, k_hi, s);
+        prev = t;
+    }
     timer_search_end(s);
     return hipGetLastError();
 }

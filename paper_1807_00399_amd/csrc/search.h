@@ -28,9 +28,66 @@
 
 namespace pcg {
 
-constexpr int kStack = 32;              // default per-lane DFS stack entries (LDS, 4 bytes each)
+constexpr int kStack = 32;              // default per-lane DFS stack entries
 constexpr int kStackNear = 24;          // nearest-neighbour searches of ICP: shallower stacks, higher occupancy
+// Whether stack entries carry their push-time distance (below).  Off for
+// both searches: a pop beyond the bound then still loads its node, but the
+// 8-byte entries double the stack's LDS, and the waves lost to that cost
+// more than the loads saved (ICP loops 20-30 % slower, k-NN and normals
+// 15-30 % slower).
+constexpr bool kSearchDist = false;     // k-NN and normals
+constexpr bool kNearDist = false;       // ICP correspondences
 constexpr int kVisitBudget = 1 << 20;   // node pops per DFS; only a corrupted tree reaches it
+
+// One lane's DFS stack in LDS: a column of CAP entries `stride` apart (the
+// lanes of a block interleave, so a wave's accesses are conflict-free).
+// With DIST, an entry also holds a lower bound of the squared distance from
+// the query to the node's points, taken when it was pushed (the node's box
+// distance for a child, the cell's for a cover cell), so a pop whose node
+// lies beyond the bound tightened since is dropped without loading the node.
+template <int CAP, bool DIST>
+struct Stack;
+
+template <int CAP>
+struct Stack<CAP, false> {
+    static constexpr int cap = CAP;
+    static constexpr int words = CAP;   // 4-byte LDS words per lane
+    uint32_t *p;
+    int stride;
+    __device__ void put(int sp, uint32_t id, float) const { p[sp * stride] = id; }
+    __device__ uint32_t get(int sp, float &d) const
+    {
+        d = 0.f;
+        return p[sp * stride];
+    }
+};
+
+template <int CAP>
+struct Stack<CAP, true> {
+    static constexpr int cap = CAP;
+    static constexpr int words = 2 * CAP;
+    uint2 *p;
+    int stride;
+    __device__ void put(int sp, uint32_t id, float d) const { p[sp * stride] = make_uint2(id, __float_as_uint(d)); }
+    __device__ uint32_t get(int sp, float &d) const
+    {
+        const uint2 e = p[sp * stride];
+        d = __uint_as_float(e.y);
+        return e.x;
+    }
+};
+
+// the stacks of the k-NN / normals searches and of the ICP correspondence
+// search; `base` is the block's LDS array (S::words * threads words, 8-byte
+// aligned), lane t's column starts at entry t
+template <class S>
+__device__ inline S lane_stack(uint32_t *base, int threads)
+{
+    if constexpr (S::words == S::cap) return S{base + threadIdx.x, threads};
+    else return S{reinterpret_cast<uint2 *>(base) + threadIdx.x, threads};
+}
+using SearchStack = Stack<kStack, kSearchDist>;
+using NearStack = Stack<kStackNear, kNearDist>;
 
 __device__ inline uint64_t enc_cand(float key, float w) { return ((uint64_t)__float_as_uint(key) << 32) | __float_as_uint(w); }
 
@@ -149,61 +206,53 @@ __device__ inline int32_t probe_from(const GridView &g, const GridParams &P, uin
     return -1;
 }
 
-// ascending sort of 8 (distance, cell) pairs: Batcher's odd-even merge network
-__device__ inline void cmp_swap(float *d, uint32_t *id, int i, int j)
+// ascending sort of 8 words: Batcher's odd-even merge network
+__device__ inline void cmp_swap(uint32_t *k, int i, int j)
 {
-    bool sw = d[j] < d[i];
-    float td = sw ? d[j] : d[i];
-    uint32_t ti = sw ? id[j] : id[i];
-    d[j] = sw ? d[i] : d[j];
-    id[j] = sw ? id[i] : id[j];
-    d[i] = td;
-    id[i] = ti;
+    const uint32_t a = k[i], b = k[j];
+    k[i] = a < b ? a : b;
+    k[j] = a < b ? b : a;
 }
-__device__ inline void sort8(float *d, uint32_t *id)
+__device__ inline void sort8u(uint32_t *k)
 {
-    cmp_swap(d, id, 0, 1); cmp_swap(d, id, 2, 3); cmp_swap(d, id, 4, 5); cmp_swap(d, id, 6, 7);
-    cmp_swap(d, id, 0, 2); cmp_swap(d, id, 1, 3); cmp_swap(d, id, 4, 6); cmp_swap(d, id, 5, 7);
-    cmp_swap(d, id, 1, 2); cmp_swap(d, id, 5, 6);
-    cmp_swap(d, id, 0, 4); cmp_swap(d, id, 1, 5); cmp_swap(d, id, 2, 6); cmp_swap(d, id, 3, 7);
-    cmp_swap(d, id, 2, 4); cmp_swap(d, id, 3, 5);
-    cmp_swap(d, id, 1, 2); cmp_swap(d, id, 3, 4); cmp_swap(d, id, 5, 6);
+    cmp_swap(k, 0, 1); cmp_swap(k, 2, 3); cmp_swap(k, 4, 5); cmp_swap(k, 6, 7);
+    cmp_swap(k, 0, 2); cmp_swap(k, 1, 3); cmp_swap(k, 4, 6); cmp_swap(k, 5, 7);
+    cmp_swap(k, 1, 2); cmp_swap(k, 5, 6);
+    cmp_swap(k, 0, 4); cmp_swap(k, 1, 5); cmp_swap(k, 2, 6); cmp_swap(k, 3, 7);
+    cmp_swap(k, 2, 4); cmp_swap(k, 3, 5);
+    cmp_swap(k, 1, 2); cmp_swap(k, 3, 4); cmp_swap(k, 5, 6);
 }
 
-// Depth-first search from the nodes already on the stack.
-// stk: this lane's stack column (stride `stride` entries, STK of them); a
+// Depth-first search from the nodes already on the stack (sp entries); a
 // node whose children would overflow the stack is scanned as a leaf.
-template <class V, int LEAF, int STK = kStack>
-__device__ inline void dfs(const GridView &g, const GridParams &P, const Query &q, V &v, uint32_t *stk, int stride,
-                           int sp, uint32_t xs, uint32_t xe)
+template <class V, int LEAF, class S>
+__device__ inline void dfs(const GridView &g, const GridParams &P, const Query &q, V &v, const S &stk, int sp,
+                           uint32_t xs, uint32_t xe)
 {
     for (int visits = 0; sp > 0 && visits < kVisitBudget; visits++) {
         --sp;
-        uint32_t m = stk[sp * stride];
+        float dpush;
+        uint32_t m = stk.get(sp, dpush);
+        float b2 = v.bound2();
+        if (dpush > b2) continue;   // beyond the bound: the node is not loaded
         Node nd = g.node[m];
         const NodeHdr &h = nd.h;
-        float b2 = v.bound2();
         if (node_mindist2(nd, q.x, q.y, q.z) > b2) continue;
         if (h.start >= xs && h.start + h.count <= xe) continue;      // already searched
         uint32_t nc = node_nchild(h);
-        bool leaf = (h.count <= (uint32_t)LEAF) || node_level(h) == P.lmin || sp + (int)nc > STK;
+        bool leaf = (h.count <= (uint32_t)LEAF) || node_level(h) == P.lmin || sp + (int)nc > S::cap;
         if (leaf) {
             scan_range(g.pts, h.start, h.start + h.count, xs, xe, q, v, m);
             continue;
         }
         // all children boxes in one round trip
+        const uint32_t fc = h.first_child;
         float d[8];
-        uint32_t id[8];
 #pragma unroll
         for (int c = 0; c < 8; c++) {
-            // padding slots sort last and are never pushed, even when the
-            // bound is still infinite
-            d[c] = INFINITY;
-            id[c] = 0xffffffffu;
-            if (c < (int)nc) {
-                d[c] = node_box_mindist2(g.node, h.first_child + c, q.x, q.y, q.z);
-                id[c] = h.first_child + c;
-            }
+            // padding slots are never pushed, even when the bound is still
+            // infinite
+            d[c] = c < (int)nc ? node_box_mindist2(g.node, fc + c, q.x, q.y, q.z) : NAN;
         }
         // nearest child last (searched next), the others in index order
         // (cheaper than sorting all eight, and as fast to tighten the bound)
@@ -217,13 +266,13 @@ __device__ inline void dfs(const GridView &g, const GridParams &P, const Query &
         }
 #pragma unroll
         for (int c = 0; c < 8; c++) {
-            if (c != best && id[c] != 0xffffffffu && d[c] <= b2) {
-                stk[sp * stride] = id[c];
+            if (c != best && d[c] <= b2) {   // false for padding (NaN)
+                stk.put(sp, fc + c, d[c]);
                 ++sp;
             }
         }
-        if (id[best] != 0xffffffffu && bd <= b2) {
-            stk[sp * stride] = id[best];
+        if (bd <= b2) {
+            stk.put(sp, fc + best, bd);
             ++sp;
         }
     }
@@ -249,9 +298,9 @@ __device__ inline int cover_level(const GridParams &P, float b2)
 // is decided from their boxes before any memory access; their hash probes
 // go out four at a time, which keeps the live registers (and so the
 // occupancy of the kernels that search) lower than eight probes in flight.
-template <class V, int LEAF, int STK = kStack>
-__device__ inline void cover(const GridView &g, const GridParams &P, const Query &q, V &v, uint32_t *stk,
-                             int stride, uint32_t xs, uint32_t xe)
+template <class V, int LEAF, class S>
+__device__ inline void cover(const GridView &g, const GridParams &P, const Query &q, V &v, const S &stk, uint32_t xs,
+                             uint32_t xe)
 {
     const float inv = P.inv_h0;
     float b2 = v.bound2();
@@ -267,61 +316,59 @@ __device__ inline void cover(const GridView &g, const GridParams &P, const Query
     const HSlot *hs = g.hash + P.hash_base;
     if (hx - lx <= 1 && hy - ly <= 1 && hz - lz <= 1) {
         // up to 8 cells (bit 0: x + 1, bit 1: y + 1, bit 2: z + 1); only
-        // those meeting the ball are probed, nearest first, four hash probes
-        // in flight at a time (cells sorted by distance, so a second round is
-        // needed only when more than four meet the ball).  The keys of the
-        // upper neighbours are derived from the lower corner's key.
-        float d[8];
+        // those meeting the ball are probed.  Sort words: the cell's
+        // distance bits with the cell number in the low 3 bits (distances
+        // are non-negative, so their bits order as integers; the 3 bits
+        // dropped only reorder near-ties), cells outside the ball last.
+        uint32_t sk[8];
 #pragma unroll
         for (int c = 0; c < 8; c++) {
             uint32_t cx = lx + (c & 1), cy = ly + ((c >> 1) & 1), cz = lz + (c >> 2);
             bool ok = cx <= hx && cy <= hy && cz <= hz;
             float dc = ok ? cell_mindist2(P, q.x, q.y, q.z, cx, cy, cz, l) : INFINITY;
-            d[c] = dc <= b2 ? dc : INFINITY;
+            sk[c] = dc <= b2 ? ((__float_as_uint(dc) & ~7u) | (uint32_t)c) : 0xffffffffu;
         }
-        uint32_t id[8];
-#pragma unroll
-        for (int c = 0; c < 8; c++) id[c] = c;
-        sort8(d, id);
+        sort8u(sk);
+        // keys of the upper neighbours derived from the lower corner's key
         const uint64_t m0 = morton3(lx, ly, lz);
         const uint64_t mx = hx > lx ? morton_inc<0>(m0) : m0;
         const uint64_t ymask = 0x249249249249ull << 1;
         const uint64_t yd = hy > ly ? morton_inc<1>(m0) & ymask : m0 & ymask;
         const uint64_t zmask = 0x249249249249ull << 2;
         const uint64_t zd = hz > lz ? morton_inc<2>(m0) & zmask : m0 & zmask;
-        int32_t node[8];
+        // hash probes four at a time: the farther four first (a round only
+        // when one of them meets the ball), pushed before the nearer four so
+        // the nearest cell is searched first
 #pragma unroll
-        for (int h = 0; h < 8; h += 4) {
-            if (!(d[h] < INFINITY || d[h + 1] < INFINITY || d[h + 2] < INFINITY || d[h + 3] < INFINITY)) {
-#pragma unroll
-                for (int u = 0; u < 4; u++) node[h + u] = -1;
-                continue;
-            }
+        for (int h = 4; h >= 0; h -= 4) {
+            if (sk[h] == 0xffffffffu) continue;   // sorted: none of the four meets the ball
             uint64_t key[4];
             uint32_t slot[4];
             uint64_t hk[4];
+            int32_t node[4];
 #pragma unroll
             for (int u = 0; u < 4; u++) {
-                const uint32_t c = id[h + u];
+                const uint32_t c = sk[h + u] & 7u;
+                const bool in = sk[h + u] != 0xffffffffu;
                 const uint64_t xm = (c & 1) ? mx : m0;
                 const uint64_t mk = (xm & ~(ymask | zmask)) | (((c >> 1) & 1) ? yd : (m0 & ymask)) |
                                     ((c >> 2) ? zd : (m0 & zmask));
                 key[u] = hash_key(l, mk);
                 slot[u] = hash_slot(key[u], P.hash_cap);
-                HSlot e = d[h + u] < INFINITY ? hs[slot[u]] : HSlot{kEmptyKey, 0u, 0u};
+                HSlot e = in ? hs[slot[u]] : HSlot{kEmptyKey, 0u, 0u};
                 hk[u] = e.key;
-                node[h + u] = (e.key == key[u]) ? (int32_t)e.val : -1;
+                node[u] = (e.key == key[u]) ? (int32_t)e.val : -1;
             }
 #pragma unroll
             for (int u = 0; u < 4; u++)
-                if (d[h + u] < INFINITY && hk[u] != key[u] && hk[u] != kEmptyKey)
-                    node[h + u] = probe_from(g, P, key[u], slot[u]);
-        }
+                if (sk[h + u] != 0xffffffffu && hk[u] != key[u] && hk[u] != kEmptyKey)
+                    node[u] = probe_from(g, P, key[u], slot[u]);
 #pragma unroll
-        for (int c = 7; c >= 0; c--) {
-            if (node[c] >= 0) {
-                stk[sp * stride] = (uint32_t)node[c];
-                ++sp;
+            for (int u = 3; u >= 0; u--) {
+                if (node[u] >= 0) {
+                    stk.put(sp, (uint32_t)node[u], __uint_as_float(sk[h + u] & ~7u));
+                    ++sp;
+                }
             }
         }
     } else {
@@ -332,8 +379,8 @@ __device__ inline void cover(const GridView &g, const GridParams &P, const Query
                     int32_t m = find_cell(g, P, l, cx, cy, cz);
                     float dc = cell_mindist2(P, q.x, q.y, q.z, cx, cy, cz, l);
                     if (m < 0 || dc > b2) continue;
-                    if (sp < STK) {
-                        stk[sp * stride] = (uint32_t)m;
+                    if (sp < S::cap) {
+                        stk.put(sp, (uint32_t)m, dc);
                         ++sp;
                     } else {
                         NodeHdr h = g.node[m].h;
@@ -341,7 +388,7 @@ __device__ inline void cover(const GridView &g, const GridParams &P, const Query
                     }
                 }
     }
-    dfs<V, LEAF, STK>(g, P, q, v, stk, stride, sp, xs, xe);
+    dfs<V, LEAF>(g, P, q, v, stk, sp, xs, xe);
 }
 
 // smallest cell (level lmin and up) around q holding >= need points, or -1;
@@ -407,9 +454,8 @@ __device__ inline bool search_in_node(const GridView &g, const GridParams &P, co
 // Full search.  `need` = number of points the seed cell must hold (k, or 1
 // for the nearest neighbour).  When the visitor already has a finite radius
 // (a warm start) the seed phase is skipped.
-template <class V, int LEAF, int STK = kStack>
-__device__ inline void search(const GridView &g, const GridParams &P, const Query &q, V &v, int need,
-                              uint32_t *stk, int stride)
+template <class V, int LEAF, class S>
+__device__ inline void search(const GridView &g, const GridParams &P, const Query &q, V &v, int need, const S &stk)
 {
     uint32_t xs = 0, xe = 0;
     // with a finite cap no larger than a few finest cells, the cover alone is
@@ -419,13 +465,13 @@ __device__ inline void search(const GridView &g, const GridParams &P, const Quer
     if (!v.have() && !direct) {
         int32_t seed = seed_cell(g, P, q, need);
         if (seed < 0) return;   // fewer than `need` points in the cloud
-        stk[0] = (uint32_t)seed;
-        dfs<V, LEAF, STK>(g, P, q, v, stk, stride, 1, 0u, 0u);
+        stk.put(0, (uint32_t)seed, 0.f);
+        dfs<V, LEAF>(g, P, q, v, stk, 1, 0u, 0u);
         NodeHdr hs = g.node[seed].h;
         xs = hs.start;
         xe = hs.start + hs.count;
     }
-    cover<V, LEAF, STK>(g, P, q, v, stk, stride, xs, xe);
+    cover<V, LEAF>(g, P, q, v, stk, xs, xe);
 }
 
 }  // namespace pcg

