@@ -219,12 +219,11 @@ pc_status estimate_normals_batched(int n_clouds, const float *xyz, const int64_t
 {
     if (n_clouds < 1 || !valid_offsets(offsets, n_clouds) || !k || !viewpoint) return PC_EINVAL;
     const int64_t n = offsets[n_clouds];
-    int k_max = 1, k_min = PCGPU_KMAX;
+    int k_max = 1;
     for (int c = 0; c < n_clouds; c++) {
         int64_t nc = offsets[c + 1] - offsets[c];
         if (k[c] < 1 || k[c] > PCGPU_KMAX || (nc > 0 && k[c] > nc)) return PC_EINVAL;
         k_max = k[c] > k_max ? k[c] : k_max;
-        k_min = k[c] < k_min ? k[c] : k_min;
     }
     if (!isfinite(viewpoint[0]) || !isfinite(viewpoint[1]) || !isfinite(viewpoint[2])) return PC_EINVAL;
     if (n == 0) return PC_OK;
@@ -241,8 +240,7 @@ pc_status estimate_normals_batched(int n_clouds, const float *xyz, const int64_t
     if (!upload(g.off, offsets, sizeof(int64_t) * (n_clouds + 1), stream)) return PC_EDEVICE;
     if (!upload(kc, k, sizeof(int32_t) * n_clouds, stream)) return PC_EDEVICE;
     if (grid_build(g, xyz, stream) != hipSuccess) return PC_EDEVICE;
-    if (normals_run(g, xyz, k_max, kc, viewpoint, out_normals, out_curvature, stream, INFINITY, 0, nullptr, k_min) !=
-        hipSuccess)
+    if (normals_run(g, xyz, k_max, kc, viewpoint, out_normals, out_curvature, stream) != hipSuccess)
         return PC_EDEVICE;
     return PC_OK;
 }
@@ -570,14 +568,13 @@ pc_status icp_point_to_plane_with_normals_batched(int n_pairs, const float *src_
 {
     if (n_pairs < 1 || !valid_offsets(src_off, n_pairs) || !valid_offsets(tgt_off, n_pairs)) return PC_EINVAL;
     if (!max_corr_dist || !max_iters || !k || !viewpoint) return PC_EINVAL;
-    int iters_max = 0, k_max = 1, k_min = PCGPU_KMAX;
+    int iters_max = 0, k_max = 1;
     for (int p = 0; p < n_pairs; p++) {
         if (max_iters[p] < 0 || !(max_corr_dist[p] > 0.f) || !isfinite(max_corr_dist[p])) return PC_EINVAL;
         iters_max = max_iters[p] > iters_max ? max_iters[p] : iters_max;
         const int64_t nc = tgt_off[p + 1] - tgt_off[p];
         if (k[p] < 1 || k[p] > PCGPU_KMAX || (nc > 0 && k[p] > nc)) return PC_EINVAL;
         k_max = k[p] > k_max ? k[p] : k_max;
-        k_min = k[p] < k_min ? k[p] : k_min;
     }
     if (!isfinite(viewpoint[0]) || !isfinite(viewpoint[1]) || !isfinite(viewpoint[2])) return PC_EINVAL;
     if (!(conv_tol >= 0.0) || !isfinite(conv_tol)) return PC_EINVAL;
@@ -608,8 +605,7 @@ pc_status icp_point_to_plane_with_normals_batched(int n_pairs, const float *src_
     // one pyramid over the targets serves their normals and the correspondences
     if (grid_build(s.grid, tgt_xyz, stream) != hipSuccess) return PC_EDEVICE;
     if (nt > 0 &&
-        normals_run(s.grid, tgt_xyz, k_max, kc, viewpoint, nb, nullptr, stream, INFINITY, 0, s.nrm, k_min) !=
-            hipSuccess)
+        normals_run(s.grid, tgt_xyz, k_max, kc, viewpoint, nb, nullptr, stream, INFINITY, 0, s.nrm) != hipSuccess)
         return PC_EDEVICE;
     s.grid_built = true;
     s.nrm_ready = true;

@@ -77,11 +77,9 @@ hipError_t knn_run(const GridStore &g, const float *qry, int64_t nq, int k, int3
 // fewer than min_pts neighbours giving normal 0
 // srt (optional, plain k-NN only): the normals in sorted order with the
 // nearest-other-point gap in w, as the ICP correspondence search reads them
-// k_min: the smallest k of any cloud (0: k_max), which sets the list sizes
-// launched for a batch of mixed k
 hipError_t normals_run(const GridStore &g, const float *xyz, int k_max, const int32_t *kc, const float *vp,
                        float *on, float *oc, hipStream_t s, float cap2 = INFINITY, int min_pts = 0,
-                       float4 *srt = nullptr, int k_min = 0);
+                       float4 *srt = nullptr);
 // radius neighbourhoods: every point with key <= r2
 hipError_t normals_radius_run(const GridStore &g, float r2, const float *vp, float *on, float *oc, hipStream_t s);
 
