@@ -34,9 +34,10 @@ __global__ void __launch_bounds__(kQThreads) k_knn(GridView g, const float *__re
     int64_t i = xcd_block(blockIdx.x, gridDim.x) * (int64_t)kQThreads + threadIdx.x;
     if (i >= nq) return;
     Query q{qry[3 * i], qry[3 * i + 1], qry[3 * i + 2]};
+    const int32_t seed = search_seed(g, P, q, k, INFINITY);   // before the list is set up
     TopK<KT> top;
     top.init(k);
-    search<TopK<KT>, LEAF>(g, P, q, top, k, lane_stack<SearchStack>(stk, kQThreads));
+    search_from<TopK<KT>, LEAF>(g, P, q, top, seed, lane_stack<SearchStack>(stk, kQThreads));
 #pragma unroll
     for (int s = 0; s < KT; s++) {
         if (s >= KT - k) {
@@ -182,9 +183,10 @@ __global__ void __launch_bounds__(kQThreads) k_normals(GridView g, int64_t n_all
     float4 p = g.pts[s];
     uint32_t qi = __float_as_uint(p.w);
     Query q{p.x, p.y, p.z};
+    const int32_t seed = search_seed(g, P, q, k, cap2);   // before the list is set up
     TopK<KT> top;
     top.init(k, cap2);
-    search<TopK<KT>, LEAF>(g, P, q, top, k, lane_stack<SearchStack>(stk, kQThreads));
+    search_from<TopK<KT>, LEAF>(g, P, q, top, seed, lane_stack<SearchStack>(stk, kQThreads));
     // the point itself (or an exact duplicate) is first, the nearest other
     // point second (selected with static indices: the list stays in registers)
     float gap = 0.f;

@@ -451,20 +451,31 @@ __device__ inline bool search_in_node(const GridView &g, const GridParams &P, co
     return true;
 }
 
-// Full search.  `need` = number of points the seed cell must hold (k, or 1
-// for the nearest neighbour).  When the visitor already has a finite radius
-// (a warm start) the seed phase is skipped.
-template <class V, int LEAF, class S>
-__device__ inline void search(const GridView &g, const GridParams &P, const Query &q, V &v, int need, const S &stk)
+constexpr int32_t kSeedNone = -2;   // search_seed: no seed, the cap alone is covered
+
+// First step of a search by a visitor that holds no candidate yet and whose
+// radius is cap2 (`need` = number of points the seed cell must hold: k, or 1
+// for the nearest neighbour): the smallest cell around q holding `need`
+// points, searched first so the cover starts from a small radius; kSeedNone
+// when a finite cap no larger than a few finest cells is cheap to cover
+// alone; -1 when the cloud holds fewer than `need` points.  Callers with a
+// large visitor (a k-NN list) take it before setting the visitor up, so the
+// list's registers are not held across these hash probes.
+__device__ inline int32_t search_seed(const GridView &g, const GridParams &P, const Query &q, int need, float cap2)
 {
+    if (cap2 < INFINITY && cover_level(P, cap2) <= P.lmin + 2) return kSeedNone;
+    return seed_cell(g, P, q, need);
+}
+
+// The rest of a search from the result of search_seed: the seed cell
+// depth-first, then the cover of the remaining ball without that cell.
+template <class V, int LEAF, class S>
+__device__ inline void search_from(const GridView &g, const GridParams &P, const Query &q, V &v, int32_t seed,
+                                   const S &stk)
+{
+    if (seed == -1) return;   // fewer than `need` points in the cloud
     uint32_t xs = 0, xe = 0;
-    // with a finite cap no larger than a few finest cells, the cover alone is
-    // cheap; otherwise a seed cell first gives a small radius
-    float cap2 = v.bound2();
-    bool direct = cap2 < INFINITY && cover_level(P, cap2) <= P.lmin + 2;
-    if (!v.have() && !direct) {
-        int32_t seed = seed_cell(g, P, q, need);
-        if (seed < 0) return;   // fewer than `need` points in the cloud
+    if (seed >= 0) {
         stk.put(0, (uint32_t)seed, 0.f);
         dfs<V, LEAF>(g, P, q, v, stk, 1, 0u, 0u);
         NodeHdr hs = g.node[seed].h;
@@ -472,6 +483,17 @@ __device__ inline void search(const GridView &g, const GridParams &P, const Quer
         xe = hs.start + hs.count;
     }
     cover<V, LEAF>(g, P, q, v, stk, xs, xe);
+}
+
+// Full search.  When the visitor already has a candidate (a warm start) the
+// seed phase is skipped and the cover starts from its radius.
+template <class V, int LEAF, class S>
+__device__ inline void search(const GridView &g, const GridParams &P, const Query &q, V &v, int need, const S &stk)
+{
+    // one inlined cover (two copies of it grew the ICP kernel's code, and it
+    // ran slower)
+    const int32_t seed = v.have() ? kSeedNone : search_seed(g, P, q, need, v.bound2());
+    search_from<V, LEAF>(g, P, q, v, seed, stk);
 }
 
 }  // namespace pcg
