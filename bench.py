@@ -771,6 +771,8 @@ def bench_search(args):
 
         def step():
             pcgpu.estimate_normals(x, k, workspace=ws)
+    # leaf size and pyramid depth of the search, as for the ICP workloads
+    tuning = autotune_step(args, step, f"{args.workload}_{w.name}", n)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -802,6 +804,7 @@ def bench_search(args):
                                f"{n} points, k={k}; one step = pyramid build + {name}",
                    "points": n, "k": k},
         "search_kernel_ms": kern_s * 1e3,
+        "tuning": tuning,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_from_profiles(name, args.cloud),
                      "kernel": name, "avg_kernel_us": kern_s * 1e6, "algorithmic_bytes_per_launch": algo},
