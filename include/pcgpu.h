@@ -53,6 +53,13 @@ enum {
 };
 
 enum { PCGPU_KMAX = 32 };   /* largest k for knn_search / estimate_normals */
+/* Most clouds (pairs) in one batched call: the batch's search structure
+ * sorts points by (cloud, Morton key) in 64-bit keys with 16 bits for the
+ * cloud.  Batched calls and their workspace-size queries reject more (the
+ * size queries return 0); icp_learned_batched replicates up to every pair
+ * 8 times for its multi-start fallback, so it takes at most
+ * PCGPU_MAX_CLOUDS / 8 pairs. */
+enum { PCGPU_MAX_CLOUDS = 65536 };
 
 /* Human-readable name of a status code (static string). */
 const char *pc_status_string(pc_status s);

@@ -17,10 +17,12 @@ constexpr int64_t kMaxPoints = (int64_t)1 << 31;
 
 bool aligned(const void *p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
-// host offsets of m items: off[0] = 0, non-decreasing, total below kMaxPoints
-bool valid_offsets(const int64_t *off, int m)
+// host offsets of m items (1 <= m <= max_m; batches of clouds are limited by
+// the cloud bits of the sort keys): off[0] = 0, non-decreasing, total below
+// kMaxPoints
+bool valid_offsets(const int64_t *off, int m, int max_m = PCGPU_MAX_CLOUDS)
 {
-    if (!off || m < 1 || off[0] != 0) return false;
+    if (!off || m < 1 || m > max_m || off[0] != 0) return false;
     for (int i = 0; i < m; i++)
         if (off[i + 1] < off[i]) return false;
     return off[m] < kMaxPoints;
@@ -644,7 +646,9 @@ bool pose_layout(int n_pairs, const int64_t *src_off, const int64_t *tgt_off, st
 bool pose_args_ok(int n_pairs, const float *src_xyz, const int64_t *src_off, const float *tgt_xyz,
                   const int64_t *tgt_off)
 {
-    if (n_pairs < 1 || n_pairs > (1 << 24) || !valid_offsets(src_off, n_pairs) || !valid_offsets(tgt_off, n_pairs))
+    // the encoder alone has no search structure, so no cloud limit of its own
+    if (n_pairs < 1 || n_pairs > (1 << 24) || !valid_offsets(src_off, n_pairs, 1 << 24) ||
+        !valid_offsets(tgt_off, n_pairs, 1 << 24))
         return false;
     if ((src_off[n_pairs] > 0 && !src_xyz) || (tgt_off[n_pairs] > 0 && !tgt_xyz)) return false;
     return aligned(src_xyz, 4) && aligned(tgt_xyz, 4);
@@ -737,7 +741,9 @@ size_t pose_net_workspace_size(int n_pairs, const int64_t *src_off, const int64_
     std::vector<int64_t> cr;
     std::vector<int32_t> toff;
     int ntile = 0;
-    if (n_pairs < 1 || !valid_offsets(src_off, n_pairs) || !valid_offsets(tgt_off, n_pairs)) return 0;
+    if (n_pairs < 1 || n_pairs > (1 << 24) || !valid_offsets(src_off, n_pairs, 1 << 24) ||
+        !valid_offsets(tgt_off, n_pairs, 1 << 24))
+        return 0;
     if (!pose_layout(n_pairs, src_off, tgt_off, cr, toff, ntile)) return 0;
     return pose_store_bytes(n_pairs, ntile, true);
 }
@@ -793,6 +799,7 @@ size_t icp_learned_batched_workspace_size(int n_pairs, const int64_t *src_off, c
         return 0;
     if ((int64_t)kStarts * src_off[n_pairs] >= kMaxPoints || (int64_t)kStarts * tgt_off[n_pairs] >= kMaxPoints)
         return 0;
+    if ((int64_t)kStarts * n_pairs > PCGPU_MAX_CLOUDS) return 0;   // the replicated multi-start batch
     if (!pose_layout(n_pairs, src_off, tgt_off, cr, toff, ntile)) return 0;
     Carver c(nullptr, ~(size_t)0 >> 1);
     LearnedLayout L;

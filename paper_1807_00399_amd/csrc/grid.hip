@@ -664,8 +664,11 @@ hipError_t grid_sort_points(GridStore &g, const float *xyz, hipStream_t s)
     k_params<<<blocks_for(nc, T), T, 0, s>>>(g.bbox, g.off, nc, g.params);
     if (n > 0) {
         k_keys<<<blocks_for(n, T), T, 0, s>>>(xyz, g.off, nc, g.params, g.keys);
-        // a single cloud needs the 48 Morton bits only; a batch also sorts by cloud
-        const int passes = nc > 1 ? 8 : 6;
+        // a single cloud needs the 48 Morton bits only; a batch also sorts by
+        // the cloud index above them, one more pass per byte it needs
+        int cloud_bits = 0;
+        while (cloud_bits < 16 && (1 << cloud_bits) < nc) cloud_bits++;
+        const int passes = (kCloudShift + cloud_bits + kRadixBits - 1) / kRadixBits;
         uint64_t *ka = g.keys, *kb = g.keys_alt;
         uint32_t *ia = nullptr, *ib2 = g.idx_alt;
         for (int p = 0; p < passes; p++) {
@@ -674,11 +677,18 @@ hipError_t grid_sort_points(GridStore &g, const float *xyz, hipStream_t s)
             k_radix_colscan<<<kRadix / 4, 256, 0, s>>>(g.radix_hist, g.nblk_sort, g.radix_tot);
             k_radix_scatter<<<g.nblk_sort, kSortThreads, 0, s>>>(ka, ia, n, shift, g.radix_hist, g.radix_tot,
                                                                  kb, ib2);
-            // ping-pong; with an even number of passes the result lands in keys/idx
+            // ping-pong between the two buffers
             uint64_t *tk = ka; ka = kb; kb = tk;
             if (p == 0) { ia = g.idx_alt; ib2 = g.idx; }
             else { uint32_t *ti = ia; ia = ib2; ib2 = ti; }
         }
+        // the sorted keys and indices are in (ka, ia): after an odd number of
+        // passes that is the alternate pair, which then takes the primary
+        // role (the alternates are used by the sort alone)
+        g.keys = ka;
+        g.keys_alt = kb;
+        g.idx = ia;
+        g.idx_alt = ib2;
         k_gather_pts<<<blocks_for(n, T), T, 0, s>>>(xyz, g.idx, n, g.pts);
     }
     return hipGetLastError();

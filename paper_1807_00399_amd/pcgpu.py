@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libpcgpu.so")
 PC_OK, PC_EINVAL, PC_EWORKSPACE, PC_EDEVICE = 0, 1, 2, 3
 PC_ICP_CONVERGED, PC_ICP_MAXITER, PC_ICP_DEGENERATE, PC_ICP_NO_INLIERS = 0, 1, 2, 3
 KMAX = 32
+MAX_CLOUDS = 65536          # PCGPU_MAX_CLOUDS: clouds (pairs) per batched call
 
 # every symbol the header declares
 EXPORTS = (

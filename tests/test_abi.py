@@ -345,3 +345,26 @@ def test_batched_icp_with_normals_rejects_bad_arguments(pc):
     assert call(m=0) == pc.PC_EINVAL
     assert call(out=None) == pc.PC_EINVAL
     assert call(tol=float("inf")) == pc.PC_EINVAL
+
+
+def test_batched_calls_limit_the_cloud_count(pc):
+    # the batch's sort keys hold the cloud index in 16 bits above the 48-bit
+    # Morton key: more clouds per call are rejected, not silently mis-sorted
+    L = pc.lib
+    assert pc.MAX_CLOUDS == 65536
+    for m in (pc.MAX_CLOUDS, pc.MAX_CLOUDS + 1):
+        off = _i64(list(range(m + 1)))                  # one point per cloud
+        ok = m <= pc.MAX_CLOUDS
+        assert (L.estimate_normals_batched_workspace_size(m, off) > 0) == ok
+        assert (L.icp_point_to_plane_batched_workspace_size(m, off, off, 5) > 0) == ok
+        vp = (ctypes.c_float * 3)(0, 0, 0)
+        k = _i32([1] * m)
+        if not ok:
+            assert L.estimate_normals_batched(m, FAKE, off, k, vp, FAKE, None, FAKE, 1 << 40, None) == pc.PC_EINVAL
+    # the learned registration replicates each pair 8 times for its fallback
+    for m in (pc.MAX_CLOUDS // 8, pc.MAX_CLOUDS // 8 + 1):
+        off = _i64(list(range(m + 1)))
+        assert (L.icp_learned_batched_workspace_size(m, off, off, 5) > 0) == (m <= pc.MAX_CLOUDS // 8)
+    # the encoder alone is not limited by it
+    off = _i64(list(range(pc.MAX_CLOUDS + 2)))
+    assert L.pose_net_workspace_size(pc.MAX_CLOUDS + 1, off, off) > 0
