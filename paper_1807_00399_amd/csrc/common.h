@@ -27,7 +27,6 @@ constexpr uint32_t kMaxCoord = (1u << kBits) - 1u;
 constexpr uint64_t kEmptyKey = ~0ull;     // empty hash slot
 
 constexpr int kCloudShift = 48;           // cloud index position in sort keys
-static_assert(PCGPU_MAX_CLOUDS <= (1 << (64 - kCloudShift)), "cloud indices must fit above the Morton key");
 
 struct GridParams {        // one per cloud, written on the device by the grid builder
     float ox, oy, oz;      // origin (cube corner)

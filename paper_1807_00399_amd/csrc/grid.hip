@@ -149,6 +149,9 @@ __global__ void k_keys(const float *__restrict__ xyz, const int64_t *__restrict_
     keys[i] = ((uint64_t)c << kCloudShift) | morton3(cx, cy, cz);
 }
 
+// the cloud index of every key fits above its Morton bits
+static_assert(PCGPU_MAX_CLOUDS <= (1 << (64 - kCloudShift)), "cloud indices must fit above the Morton key");
+
 // ---------------------------------------------------------------- radix sort
 // hist[d * nblk + b] = number of keys with digit d in tile b
 __global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint64_t *__restrict__ keys, int64_t n,
