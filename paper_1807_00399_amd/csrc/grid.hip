@@ -193,66 +193,100 @@ __global__ void __launch_bounds__(256) k_radix_colscan(uint32_t *__restrict__ hi
     if (lane == 0) tot[d] = carry;
 }
 
-// Stable scatter of one radix pass.  Each block walks its tile in rounds of
-// 256 consecutive keys; the rank of a key among equal digits is its lane rank
-// inside the wave (from eight ballots) plus the counts of earlier waves and
-// earlier rounds, so the original order of equal digits is kept.
+// exclusive prefix sum of one value per thread of a 256-thread block (all
+// threads call it); ws: 4 words of LDS
+__device__ inline uint32_t block_excl_scan256(uint32_t v, uint32_t *ws)
+{
+    uint32_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        uint32_t y = __shfl_up(x, off);
+        if (__lane_id() >= off) x += y;
+    }
+    const int w = threadIdx.x >> 6;
+    if (__lane_id() == 63) ws[w] = x;
+    __syncthreads();
+    uint32_t before = 0;
+    for (int x2 = 0; x2 < w; x2++) before += ws[x2];
+    __syncthreads();   // ws may be reused after the call
+    return before + x - v;
+}
+
+// Stable scatter of one radix pass.  A block ranks its tile of kSortTile
+// keys in rounds of 256 (the rank of a key among equal digits is its lane
+// rank inside the wave, from eight ballots, plus the counts of earlier waves
+// and earlier rounds, so the original order of equal digits is kept), places
+// them in LDS in digit order, and then writes each digit's run to its place
+// in the output with consecutive lanes on consecutive addresses: the writes
+// coalesce (placed straight from its round, a key landed next to about one
+// other key of its digit).
 __global__ void __launch_bounds__(kSortThreads) k_radix_scatter(
     const uint64_t *__restrict__ kin, const uint32_t *__restrict__ iin, int64_t n, int shift,
     const uint32_t *__restrict__ hist, const uint32_t *__restrict__ tot, uint64_t *__restrict__ kout,
     uint32_t *__restrict__ iout)
 {
+    static_assert(kSortThreads == kRadix, "one thread per digit");
     constexpr int W = kSortThreads / 64;
-    __shared__ uint32_t running[kRadix];
-    __shared__ uint32_t wcnt[W][kRadix];
-    __shared__ uint32_t wsum[W];
-    int t = threadIdx.x, w = t >> 6;
-    // digit base = exclusive scan of the digit totals (256 values, in LDS)
+    __shared__ uint64_t skey[kSortTile];
+    __shared__ uint32_t sidx[kSortTile];
+    __shared__ uint32_t running[kRadix];   // next tile-local position of each digit
+    __shared__ int64_t delta[kRadix];      // output position minus tile-local position, per digit
+    __shared__ uint16_t wcnt[W][kRadix];
+    __shared__ uint32_t ws[W];
+    const int t = threadIdx.x, w = t >> 6, nblk = gridDim.x, b = blockIdx.x;
+    const int64_t base = (int64_t)b * kSortTile;
     {
-        uint32_t v = tot[t], x = v;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            uint32_t y = __shfl_up(x, off);
-            if (__lane_id() >= off) x += y;
-        }
-        if (__lane_id() == 63) wsum[w] = x;
-        __syncthreads();
-        uint32_t before = 0;
-        for (int x2 = 0; x2 < w; x2++) before += wsum[x2];
-        running[t] = before + x - v + hist[(int64_t)t * gridDim.x + blockIdx.x];
+        // digit t: this tile's count (offsets of consecutive tiles within the
+        // digit differ by it), its start inside the tile, and its place in
+        // the output (digit base + this tile's offset within the digit)
+        const uint32_t off_b = hist[(int64_t)t * nblk + b];
+        const uint32_t next = b + 1 < nblk ? hist[(int64_t)t * nblk + b + 1] : tot[t];
+        const uint32_t local = block_excl_scan256(next - off_b, ws);
+        const uint32_t dbase = block_excl_scan256(tot[t], ws);
+        running[t] = local;
+        delta[t] = (int64_t)dbase + off_b - local;
     }
     for (int x = 0; x < W; x++) wcnt[x][t] = 0;
     __syncthreads();
-    int64_t base = (int64_t)blockIdx.x * kSortTile;
-    uint64_t lt = lanemask_lt();
+    const uint64_t lt = lanemask_lt();
     for (int r = 0; r < kSortItems; r++) {
-        int64_t e = base + r * kSortThreads + t;
-        bool valid = e < n;
-        uint64_t key = valid ? kin[e] : 0ull;
-        uint32_t id = valid ? (iin ? iin[e] : (uint32_t)e) : 0u;
-        uint32_t d = (uint32_t)(key >> shift) & (kRadix - 1);
+        const int64_t e = base + r * kSortThreads + t;
+        const bool valid = e < n;
+        const uint64_t key = valid ? kin[e] : 0ull;
+        const uint32_t id = valid ? (iin ? iin[e] : (uint32_t)e) : 0u;
+        const uint32_t d = (uint32_t)(key >> shift) & (kRadix - 1);
         uint64_t m = __ballot(valid);
-        for (int b = 0; b < kRadixBits; b++) {
-            uint64_t bb = __ballot((d >> b) & 1u);
-            m &= ((d >> b) & 1u) ? bb : ~bb;
+        for (int bit = 0; bit < kRadixBits; bit++) {
+            const uint64_t bb = __ballot((d >> bit) & 1u);
+            m &= ((d >> bit) & 1u) ? bb : ~bb;
         }
-        uint32_t wrank = __popcll(m & lt);
-        if (valid && wrank == 0) wcnt[w][d] = __popcll(m);
+        const uint32_t wrank = __popcll(m & lt);
+        if (valid && wrank == 0) wcnt[w][d] = (uint16_t)__popcll(m);
         __syncthreads();
         if (valid) {
             uint32_t pos = running[d] + wrank;
             for (int x = 0; x < w; x++) pos += wcnt[x][d];
-            kout[pos] = key;
-            iout[pos] = id;
+            skey[pos] = key;
+            sidx[pos] = id;
         }
         __syncthreads();
-        uint32_t tot = 0;
+        uint32_t cnt = 0;
         for (int x = 0; x < W; x++) {
-            tot += wcnt[x][t];
+            cnt += wcnt[x][t];
             wcnt[x][t] = 0;
         }
-        running[t] += tot;
+        running[t] += cnt;
         __syncthreads();
+    }
+    // the tile in digit order: runs of equal digits go to consecutive
+    // output positions
+    const int64_t rem = n - base;
+    const int tile_n = rem < kSortTile ? (int)rem : kSortTile;
+    for (int x = t; x < tile_n; x += kSortThreads) {
+        const uint64_t key = skey[x];
+        const int64_t pos = delta[(uint32_t)(key >> shift) & (kRadix - 1)] + x;
+        kout[pos] = key;
+        iout[pos] = sidx[x];
     }
 }
 
