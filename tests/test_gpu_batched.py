@@ -445,3 +445,23 @@ def test_persistent_loop_full_batch_equals_lockstep(gpu):
         gpu.set_tuning(128, 16, 1.0, 1, 0)
     assert np.array_equal(res[0][0], res[1][0])
     assert res[0][1] == res[1][1]
+
+
+@pytest.mark.parametrize("n_clouds", [1, 2, 300])
+def test_batched_normals_sort_passes(gpu, n_clouds):
+    # the batch's radix sort runs one pass per byte of the (cloud, Morton
+    # key): 6 passes for one cloud, 7 for up to 256 clouds, 8 for 300; an
+    # odd count leaves the sorted keys in the alternate buffers.  Each cloud
+    # of the batch must still get exactly the single call's normals.
+    rng = rng_for(90, n_clouds)
+    sizes = rng.integers(16, 48, size=n_clouds)
+    clouds = [sphere_plane(rng, int(m)) for m in sizes]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    k = np.full(n_clouds, 8, np.int32)
+    _say(f"sort passes: {n_clouds} clouds, {off[-1]} points")
+    bn, bc = gpu.estimate_normals_batched(_dev(np.vstack(clouds)), off, k)
+    bn, bc = bn.cpu().numpy(), bc.cpu().numpy()
+    for j, c in enumerate(clouds):
+        sn, sc = gpu.estimate_normals(_dev(c), 8)
+        assert np.array_equal(bn[off[j]:off[j + 1]], sn.cpu().numpy()), f"cloud {j}"
+        assert np.array_equal(bc[off[j]:off[j + 1]], sc.cpu().numpy()), f"cloud {j}"
