@@ -170,27 +170,47 @@ __global__ void __launch_bounds__(kSortThreads) k_radix_hist(const uint64_t *__r
     hist[(int64_t)t * gridDim.x + blockIdx.x] = cnt[t];
 }
 
-// Per-digit exclusive scan over tiles (one wave per digit, 64 tiles per
-// step): hist[d * nblk + b] becomes the offset of tile b within digit d;
-// tot[d] receives the digit's total.
+// Exclusive scan, in place, of the n values a[0], a[stride], ... by one
+// wave, 64 values per step; the loads of kAhead steps go out together (the
+// running total is the only dependence between steps).  Returns the total.
+template <class T>
+__device__ inline T wave_excl_scan(T *a, int64_t stride, int n)
+{
+    constexpr int kAhead = 8;
+    const int lane = __lane_id();
+    T carry = 0;
+    for (int b0 = 0; b0 < n; b0 += 64 * kAhead) {
+        T v[kAhead];
+#pragma unroll
+        for (int u = 0; u < kAhead; u++) {
+            const int b = b0 + 64 * u + lane;
+            v[u] = b < n ? a[(int64_t)b * stride] : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < kAhead; u++) {
+            const int b = b0 + 64 * u + lane;
+            T x = v[u];
+#pragma unroll
+            for (int off = 1; off < 64; off <<= 1) {
+                T y = __shfl_up(x, off);
+                if (lane >= off) x += y;
+            }
+            if (b < n) a[(int64_t)b * stride] = carry + x - v[u];
+            carry += __shfl(x, 63);
+        }
+    }
+    return carry;
+}
+
+// Per-digit exclusive scan over tiles (one wave per digit):
+// hist[d * nblk + b] becomes the offset of tile b within digit d; tot[d]
+// receives the digit's total.
 __global__ void __launch_bounds__(256) k_radix_colscan(uint32_t *__restrict__ hist, int nblk,
                                                      uint32_t *__restrict__ tot)
 {
-    const int d = blockIdx.x * 4 + (threadIdx.x >> 6), lane = __lane_id();
-    uint32_t carry = 0;
-    for (int b0 = 0; b0 < nblk; b0 += 64) {
-        int b = b0 + lane;
-        uint32_t v = (b < nblk) ? hist[(int64_t)d * nblk + b] : 0u;
-        uint32_t x = v;
-#pragma unroll
-        for (int off = 1; off < 64; off <<= 1) {
-            uint32_t y = __shfl_up(x, off);
-            if (lane >= off) x += y;
-        }
-        if (b < nblk) hist[(int64_t)d * nblk + b] = carry + x - v;
-        carry += __shfl(x, 63);
-    }
-    if (lane == 0) tot[d] = carry;
+    const int d = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const uint32_t total = wave_excl_scan(hist + (int64_t)d * nblk, 1, nblk);
+    if (__lane_id() == 0) tot[d] = total;
 }
 
 // exclusive prefix sum of one value per thread of a 256-thread block (all
@@ -457,21 +477,8 @@ __global__ void __launch_bounds__(kLvlThreads) k_level_count(const uint32_t *__r
 // exclusive scan over tiles, one wave per level
 __global__ void __launch_bounds__(1024) k_level_scan(int32_t *__restrict__ lb, int nblk)
 {
-    int w = threadIdx.x >> 6, lane = __lane_id();
-    for (int l = w; l < kLevels; l += 16) {
-        int32_t carry = 0;
-        for (int b0 = 0; b0 < nblk; b0 += 64) {
-            int b = b0 + lane;
-            int32_t v = (b < nblk) ? lb[(int64_t)b * kLevels + l] : 0;
-            int32_t x = v;
-            for (int off = 1; off < 64; off <<= 1) {
-                int32_t y = __shfl_up(x, off);
-                if (lane >= off) x += y;
-            }
-            if (b < nblk) lb[(int64_t)b * kLevels + l] = carry + x - v;
-            carry += __shfl(x, 63);
-        }
-    }
+    const int w = threadIdx.x >> 6;
+    for (int l = w; l < kLevels; l += 16) wave_excl_scan(lb + l, kLevels, nblk);
 }
 
 // writes node starts, levels and first children
