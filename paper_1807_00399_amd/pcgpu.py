@@ -42,7 +42,8 @@ PC_INIT_LEARNED, PC_INIT_MULTI_START, PC_INIT_LEARNED_ONLY = 0, 1, 2
 
 class Tuning(ctypes.Structure):
     """pc_tuning: accumulate block size, search leaf size, pyramid node
-    budget, Morton-ordered ICP queries, persistent ICP loop."""
+    budget, Morton-ordered ICP queries, and the reserved persistent-loop
+    flag (must be 0)."""
     _fields_ = [("icp_block_threads", ctypes.c_int32), ("icp_leaf", ctypes.c_int32),
                 ("node_budget", ctypes.c_float), ("sort_queries", ctypes.c_int32),
                 ("icp_persistent", ctypes.c_int32)]
