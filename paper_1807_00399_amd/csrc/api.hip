@@ -269,13 +269,14 @@ void carve_single(Carver &c, int64_t n_src, int64_t n_tgt, int max_iters, IcpSto
     tune(s);
     s.nblk = (int)icp_blocks(n_src, s.threads);
     s.ngrp = (int)icp_groups(s.nblk);
+    s.max_pair_groups = s.ngrp;
 }
 
 // the batched carve: blocks and groups per pair from the host offsets
 void carve_batched(Carver &c, int n_pairs, const int64_t *src_off, const int64_t *tgt_off, int iters_max,
                    IcpStore &s, std::vector<int32_t> *boff, std::vector<int32_t> *goff)
 {
-    int64_t cap_b = 0, cap_g = 0, nblk = 0, ngrp = 0;
+    int64_t cap_b = 0, cap_g = 0, nblk = 0, ngrp = 0, max_g = 0;
     const int threads = g_tune.icp_block_threads;
     if (boff) boff->assign(1, 0);
     if (goff) goff->assign(1, 0);
@@ -286,6 +287,7 @@ void carve_batched(Carver &c, int n_pairs, const int64_t *src_off, const int64_t
         int64_t b = icp_blocks(ns, threads);
         nblk += b;
         ngrp += icp_groups(b);
+        max_g = icp_groups(b) > max_g ? icp_groups(b) : max_g;
         if (boff) boff->push_back((int32_t)nblk);
         if (goff) goff->push_back((int32_t)ngrp);
     }
@@ -293,6 +295,7 @@ void carve_batched(Carver &c, int n_pairs, const int64_t *src_off, const int64_t
     tune(s);
     s.nblk = (int)nblk;
     s.ngrp = (int)ngrp;
+    s.max_pair_groups = (int)max_g;
 }
 
 }  // namespace

@@ -31,6 +31,7 @@ struct IcpStore {
     int32_t *queue;     // persistent loop: tile counter per pass
     int hist_stride;    // doubles per pair in hist
     int np, nblk, ngrp, iters_max;
+    int max_pair_groups;  // most reduction groups of any pair (small: the solve kernel merges them)
     int threads;        // accumulate block size (64, 128 or 256)
     int leaf;           // largest node scanned as a leaf by the search (8, 16 or 32)
     int metric;         // 0 point-to-plane, 1 point-to-point (closed form), 2 combined

@@ -810,6 +810,10 @@ __device__ inline void finalize_pair(const float2 *__restrict__ gpart, const uin
     __syncthreads();   // red is reused by the next pair of this block
 }
 
+// With fuse (pairs of at most kFuseGroups groups), the group partials are
+// formed here from the block partials, exactly as k_icp_reduce forms them
+// (the same loads, merge tree and order), and the reduce launch is skipped.
+constexpr int kFuseGroups = 4;
 __global__ void __launch_bounds__(kFinThreads) k_icp_finalize(const float2 *__restrict__ gpart,
                                                             const uint32_t *__restrict__ gcnt,
                                                             const int32_t *__restrict__ goff,
@@ -817,7 +821,10 @@ __global__ void __launch_bounds__(kFinThreads) k_icp_finalize(const float2 *__re
                                                             int final_pass, double conv_tol,
                                                             double *__restrict__ out_T, pc_icp_stats *out_stats,
                                                             double *__restrict__ hist, int hist_stride, int metric,
-                                                            const GridParams *__restrict__ params)
+                                                            const GridParams *__restrict__ params, int fuse,
+                                                            const float2 *__restrict__ part,
+                                                            const uint32_t *__restrict__ pcnt,
+                                                            const int32_t *__restrict__ boff)
 {
     // the merge of finalize_pair with one thread per (sum, lane), and the
     // other waves leave before the solve
@@ -830,16 +837,50 @@ __global__ void __launch_bounds__(kFinThreads) k_icp_finalize(const float2 *__re
     const int a = threadIdx.x >> 5, j = threadIdx.x & 31;
     if (a < kAcc) {
         CSum c{0.f, 0.f};
+        if (fuse) {
+            // group b's partial (lane 0 of its 32-lane merge, as
+            // k_icp_reduce stores it), taken by lane (b - g0) mod 32
+            const int bend = boff[pr + 1];
+            for (int b = g0; b < g1; b++) {
+                const int b0 = boff[pr] + (b - g0) * kGroup;
+                const int gsz = (bend - b0) < kGroup ? (bend - b0) : kGroup;
+                CSum x{0.f, 0.f};
+                if (j < gsz) {
+                    float2 v = part[(int64_t)(b0 + j) * kAcc + a];
+                    x = CSum{v.x, v.y};
+                }
+                if (j + 32 < gsz) {
+                    float2 v = part[(int64_t)(b0 + j + 32) * kAcc + a];
+                    x = csum_merge(x, CSum{v.x, v.y});
+                }
+                x = merge32(x);
+                const int l0 = __lane_id() & 32;   // lane 0 of this 32-lane half
+                x = CSum{__shfl(x.hi, l0), __shfl(x.lo, l0)};
+                if (((b - g0) & 31) == j) c = csum_merge(c, x);
+            }
+        } else {
 #pragma unroll 4
-        for (int b = g0 + j; b < g1; b += 32) {
-            float2 v = gpart[(int64_t)b * kAcc + a];
-            c = csum_merge(c, CSum{v.x, v.y});
+            for (int b = g0 + j; b < g1; b += 32) {
+                float2 v = gpart[(int64_t)b * kAcc + a];
+                c = csum_merge(c, CSum{v.x, v.y});
+            }
         }
         c = merge32(c);
         if (j == 0) red[a] = make_float2(c.hi, c.lo);
     } else if (a == kAcc) {
         uint32_t c = 0;
-        for (int b = g0 + j; b < g1; b += 32) c += gcnt[b];
+        if (fuse) {
+            const int bend = boff[pr + 1];
+            for (int b = g0; b < g1; b++) {
+                const int b0 = boff[pr] + (b - g0) * kGroup;
+                const int gsz = (bend - b0) < kGroup ? (bend - b0) : kGroup;
+                uint32_t x = (j < gsz ? pcnt[b0 + j] : 0u) + (j + 32 < gsz ? pcnt[b0 + j + 32] : 0u);
+                x = sum32(x);
+                if (((b - g0) & 31) == j) c += x;
+            }
+        } else {
+            for (int b = g0 + j; b < g1; b += 32) c += gcnt[b];
+        }
         c = sum32(c);
         if (j == 0) redc = c;
     }
@@ -1104,6 +1145,7 @@ void icp_carve(Carver &c, int np, int64_t ns, int64_t nt, int64_t nblk, int64_t 
     s.nrm_ready = false;
     s.sort_src = true;
     s.persistent = false;
+    s.max_pair_groups = 1 << 30;   // unknown: no fused merge
     s.iters_max = iters_max > 0 ? iters_max : 0;
     s.nrm = c.take<float4>(nt1);
     s.prev = c.take<int2>(ns1);
@@ -1278,6 +1320,8 @@ hipError_t icp_run(IcpStore &s, const float *src, int64_t ns, const float *tgt, 
         }
         return e != hipSuccess ? e : hipGetLastError();
     }
+    // small pairs: the solve kernel merges the block partials itself
+    const bool fuse = s.max_pair_groups <= kFuseGroups;
     for (int pass = 0; pass <= s.iters_max; pass++) {
         const int fin = pass == s.iters_max;   // the last pass gives the statistics
         const bool timed = !fin && pass < g_tcap;
@@ -1288,10 +1332,13 @@ hipError_t icp_run(IcpStore &s, const float *src, int64_t ns, const float *tgt, 
                 (void)hipEventRecord(g_tend[pass], st);
                 g_tcount = pass + 1;
             }
-            k_icp_reduce<<<s.ngrp, 1024, 0, st>>>(s.part, s.pcnt, s.boff, s.goff, np, s.st, fin, s.gpart, s.gcnt);
+            if (!fuse)
+                k_icp_reduce<<<s.ngrp, 1024, 0, st>>>(s.part, s.pcnt, s.boff, s.goff, np, s.st, fin, s.gpart,
+                                                      s.gcnt);
         }
         k_icp_finalize<<<np, kFinThreads, 0, st>>>(s.gpart, s.gcnt, s.goff, s.st, s.maxit, fin, conv_tol, out_T,
-                                                   out_stats, s.hist, s.hist_stride, s.metric, s.grid.params);
+                                                   out_stats, s.hist, s.hist_stride, s.metric, s.grid.params,
+                                                   fuse ? 1 : 0, s.part, s.pcnt, s.boff);
     }
     return hipGetLastError();
 }
