@@ -480,7 +480,8 @@ const double *icp_history(void *workspace, size_t workspace_bytes,
    icp_point_to_plane and icp_point_to_plane_batched record on their stream
    immediately before and after the correspondence/accumulation kernel of
    iteration i, for i < capacity; knn_search and estimate_normals record
-   slot 0 around their search kernel (k_knn, k_normals); pose_net_train_step
+   slot 0 around their search kernel (k_knn, k_normals); pose_net_predict
+   records slot 0 around the encoder kernel; pose_net_train_step
    records slot 0 around the forward, 1 around the backward and 2 around
    the second-layer weight-gradient kernel.  Pass
    capacity 0 to stop.  pc_kernel_timer_count() returns how many pairs the

@@ -762,7 +762,8 @@ pc_status pose_net_predict(const float *params, int n_pairs, const float *src_xy
     PoseNetStore s;
     pc_status r = pose_setup(c, n_pairs, src_off, tgt_off, false, s, stream);
     if (r != PC_OK) return r;
-    return pose_net_forward(s, params, src_xyz, tgt_xyz, out_T, stream) == hipSuccess ? PC_OK : PC_EDEVICE;
+    // kernel timer slot 0: the encoder kernel
+    return pose_net_forward(s, params, src_xyz, tgt_xyz, out_T, stream, 0) == hipSuccess ? PC_OK : PC_EDEVICE;
 }
 
 pc_status pose_net_train_step(float *params, float *adam_m, float *adam_v, int step, float lr, int n_pairs,

@@ -54,8 +54,9 @@ void pose_net_carve(Carver &c, int np, int ntile, bool train, PoseNetStore &s);
 // centroids and scales only (cr and toff must be on the device)
 hipError_t pose_net_stats(PoseNetStore &s, const float *xs, const float *xt, hipStream_t st);
 // forward: initial pose per pair into out_T (n_pairs x 16), or into s.T
+// enc_slot >= 0: kernel timer slot recorded around the encoder kernel
 hipError_t pose_net_forward(PoseNetStore &s, const float *params, const float *xs, const float *xt, double *out_T,
-                            hipStream_t st);
+                            hipStream_t st, int enc_slot = -1);
 // forward + weighted loss + backward (gradient into s.grad) + Adam step when lr > 0
 hipError_t pose_net_train(PoseNetStore &s, float *params, float *adam_m, float *adam_v, int step, float lr,
                           const float *xs, const float *xt, const double *label_T, const float *pair_w,

@@ -39,6 +39,11 @@ namespace {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kT = 512;          // points per encoder tile
 constexpr int kEncWaves = 8;     // waves per encoder workgroup; wave w owns rows 64w .. 64w + 63
@@ -48,6 +53,29 @@ constexpr int kP2 = kC2 + 8;
 constexpr int kChunk = 128;      // rows per outer-product chunk
 
 __device__ inline __bf16 to_bf16(float x) { return (__bf16)x; }
+
+// ReLU of two float32 values rounded to bfloat16 and packed in one word (a
+// packed conversion, then a packed signed 16-bit maximum with zero: a
+// negative value, sign bit set, -0 included, becomes +0).  Rounding to
+// nearest keeps the sign, so rounding first and clamping afterwards gives
+// what clamping first would, at one instruction per two values for the
+// clamp, where a float maximum in IEEE mode takes two per value (one quiets
+// the operand).
+__device__ inline uint32_t relu_pk_bf16(float a, float b)
+{
+    const bf16x2 h = __builtin_convertvector((f32x2){a, b}, bf16x2);
+    const s16x2 r = __builtin_elementwise_max(__builtin_bit_cast(s16x2, h), (s16x2){0, 0});
+    return __builtin_bit_cast(uint32_t, r);
+}
+
+// the four words of one accumulator tile's ReLU'd bfloat16 values
+__device__ inline u32x2 relu_tile(f32x4 a) { return u32x2{relu_pk_bf16(a[0], a[1]), relu_pk_bf16(a[2], a[3])}; }
+
+// two tiles' halves into one eight-value operand (lo in slots 0-3)
+__device__ inline bf16x8 join_bf16x8(u32x2 lo, u32x2 hi)
+{
+    return __builtin_bit_cast(bf16x8, u32x4{lo[0], lo[1], hi[0], hi[1]});
+}
 
 // rows of cloud c: [cr[2c], cr[2c + 1]) of the source buffer (even c) or
 // the target buffer (odd c)
@@ -64,6 +92,9 @@ __global__ void k_norm_stats(const float *__restrict__ xs, const float *__restri
     const float *X = cloud_xyz(xs, xt, c);
     const int64_t a = cr[2 * c], b = cr[2 * c + 1];
     double s[3] = {0.0, 0.0, 0.0};
+    // unrolled so that several points' loads are in flight; each thread's
+    // sums still take its points in ascending order
+#pragma unroll 8
     for (int64_t i = a + threadIdx.x; i < b; i += blockDim.x)
         for (int k = 0; k < 3; k++) s[k] += X[3 * i + k];
     for (int o = 32; o > 0; o >>= 1)
@@ -76,6 +107,7 @@ __global__ void k_norm_stats(const float *__restrict__ xs, const float *__restri
     double m[3];
     for (int k = 0; k < 3; k++) m[k] = n > 0 ? (red[0][k] + red[1][k] + red[2][k] + red[3][k]) / n : 0.0;
     double r2 = 0.0;
+#pragma unroll 8
     for (int64_t i = a + threadIdx.x; i < b; i += blockDim.x)
         for (int k = 0; k < 3; k++) {
             double d = X[3 * i + k] - m[k];
@@ -136,10 +168,14 @@ __device__ inline void norm_point(const float *X, int64_t i, const double *cen, 
 }
 
 // Encoder forward.  Persistent workgroups (kEncWaves waves) load the
-// bfloat16 weights into LDS once and then take tiles of kT points of one
-// cloud each; per tile and channel they write the tile's maximum activation
-// and, with ARG (training), the lowest point index reaching it (without it,
-// the tile's first point stands in).
+// bfloat16 weights into LDS once and then take a contiguous run of tiles of
+// kT points (a tile holds points of one cloud).  Each lane keeps its
+// running per-channel maximum over the tiles of one cloud in its own LDS
+// slot, so tiles need no barrier; at a cloud's last tile in the run the
+// slots are combined and the maximum activation per channel is written,
+// with ARG (training) the lowest point index reaching it (without it, a
+// point of the cloud stands in); the run's other tiles of that cloud are
+// marked empty for the pool.
 //
 // Matrix-core operands of v_mfma_f32_16x16x32_bf16 (wave of 64 lanes, g =
 // l / 16): lane l supplies A[l % 16][8 g + j] and B[8 g + j][l % 16] for
@@ -213,20 +249,27 @@ __global__ void __launch_bounds__(kEncThreads) k_enc_forward(const float *__rest
             pz[m] = ok ? X[3 * i + 2] : 0.f;
         }
     };
-    int tile = blockIdx.x;
-    int c = tile < ntile ? cloud_of(tile) : 0;
+    // a contiguous run of tiles per workgroup; the tiles of one cloud within
+    // it form a segment, whose maxima are combined once, at its last tile
+    const int per = (ntile + (int)gridDim.x - 1) / (int)gridDim.x;
+    const int t0 = blockIdx.x * per, t1 = min(ntile, t0 + per);
+    int tile = t0;
+    int c = tile < t1 ? cloud_of(tile) : 0;
     float px[4], py[4], pz[4];
-    if (tile < ntile) load_rows(tile, c, px, py, pz);
-    for (; tile < ntile; tile += gridDim.x) {
-        const int tn = tile + gridDim.x;
+    if (tile < t1) load_rows(tile, c, px, py, pz);
+    for (; tile < t1; tile++) {
+        const int tn = tile + 1;
         int cn = c;
         float nx[4], ny[4], nz[4];
-        if (tn < ntile) {
-            cn = cloud_of(tn);
+        if (tn < t1) {
+            while (cn + 1 < nc && toff[cn + 1] <= tn) cn++;
             load_rows(tn, cn, nx, ny, nz);
         }
+        const bool fresh = tile == t0 || toff[c] == tile;     // first tile of the segment
+        const bool flush = tn == t1 || cn != c;               // last tile of the segment
         const int64_t p0 = cr[2 * c] + (int64_t)(tile - toff[c]) * kT;
         const int64_t pend = cr[2 * c + 1];
+        const int32_t pc0 = (int32_t)(p0 - cr[2 * c]);       // the tile's first point within its cloud
         // layer 1 on the float32 matrix cores (v_mfma_f32_16x16x4_f32: lane l
         // supplies A[l % 16][g] and B[g][l % 16], receives C[4 g + i][l % 16]),
         // transposed: C1^T[ch][row] = sum_k [W1; b1]^T[ch][k] [x y z 1]^T[k][row]
@@ -248,21 +291,22 @@ __global__ void __launch_bounds__(kEncThreads) k_enc_forward(const float *__rest
                 bop[m] = g == 0 ? x : (g == 1 ? y : (g == 2 ? z : 1.f));
             }
 #pragma unroll
-            for (int tc1 = 0; tc1 < kC1 / 16; tc1++) {
-                const float4 wv = sW1[16 * tc1 + lr];
-                const float aop = g == 0 ? wv.x : (g == 1 ? wv.y : (g == 2 ? wv.z : wv.w));
+            for (int kb = 0; kb < kC1 / 32; kb++) {
+                const float aop0 = reinterpret_cast<const float *>(sW1)[4 * (32 * kb + lr) + g];
+                const float aop1 = reinterpret_cast<const float *>(sW1)[4 * (32 * kb + 16 + lr) + g];
 #pragma unroll
                 for (int m = 0; m < 4; m++) {
-                    const f32x4 a = __builtin_amdgcn_mfma_f32_16x16x4f32(aop, bop[m], f32x4{0.f, 0.f, 0.f, 0.f}, 0,
-                                                                          0, 0);
-#pragma unroll
-                    for (int i = 0; i < 4; i++) x1[m][tc1 >> 1][4 * (tc1 & 1) + i] = to_bf16(fmaxf(a[i], 0.f));
+                    const f32x4 zero = {0.f, 0.f, 0.f, 0.f};
+                    const f32x4 a0 = __builtin_amdgcn_mfma_f32_16x16x4f32(aop0, bop[m], zero, 0, 0, 0);
+                    const f32x4 a1 = __builtin_amdgcn_mfma_f32_16x16x4f32(aop1, bop[m], zero, 0, 0, 0);
+                    x1[m][kb] = join_bf16x8(relu_tile(a0), relu_tile(a1));
                 }
             }
         }
         // layer 2 (transposed): per 16-channel tile, bias, ReLU, bfloat16,
         // stored straight into the layer-3 A operands (tiles 2 kb, 2 kb + 1)
         bf16x8 x2[4][4];
+        u32x2 half[4];     // the even tile's rounded outputs, until the odd one completes the operand
 #pragma unroll
         for (int tc = 0; tc < kC2 / 16; tc++) {
             f32x4 acc[4];
@@ -277,10 +321,11 @@ __global__ void __launch_bounds__(kEncThreads) k_enc_forward(const float *__rest
                 for (int m = 0; m < 4; m++) acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, x1[m][kb], acc[m], 0, 0, 0);
             }
 #pragma unroll
-            for (int m = 0; m < 4; m++)
-#pragma unroll
-                for (int i = 0; i < 4; i++)
-                    x2[m][tc >> 1][4 * (tc & 1) + i] = to_bf16(fmaxf(acc[m][i], 0.f));
+            for (int m = 0; m < 4; m++) {
+                const u32x2 h = relu_tile(acc[m]);
+                if (tc & 1) x2[m][tc >> 1] = join_bf16x8(half[m], h);
+                else half[m] = h;
+            }
         }
         // layer 3 and, per channel, the maximum over this lane's 16 rows
         // (ascending, first maximum kept; rows past the cloud's end, only in
@@ -311,9 +356,14 @@ __global__ void __launch_bounds__(kEncThreads) k_enc_forward(const float *__rest
                         for (int i = 0; i < 4; i++)
                             if (acc[m][i] > best) { best = acc[m][i]; barg = r0 + 16 * m + 4 * g + i; }
                 } else {
+                    // NaN-propagating maximum: the matrix cores' finite
+                    // outputs need no quieting, and three operands go to
+                    // one instruction
 #pragma unroll
                     for (int m = 0; m < 4; m++)
-                        best = fmaxf(fmaxf(best, fmaxf(acc[m][0], acc[m][1])), fmaxf(acc[m][2], acc[m][3]));
+                        best = __builtin_elementwise_maximum(
+                            __builtin_elementwise_maximum(best, __builtin_elementwise_maximum(acc[m][0], acc[m][1])),
+                            __builtin_elementwise_maximum(acc[m][2], acc[m][3]));
                     barg = r0 + 4 * g;
                 }
             } else {
@@ -325,9 +375,21 @@ __global__ void __launch_bounds__(kEncThreads) k_enc_forward(const float *__rest
                         if (p0 + row < pend && acc[m][i] > best) { best = acc[m][i]; barg = row; }
                     }
             }
-            sMax[4 * w + g][col] = best + sB3[col];
-            sArg[4 * w + g][col] = barg;
+            // this lane's running maximum over the segment's tiles, in its
+            // own LDS slot (no other lane touches it until the combine);
+            // ties keep the earlier tile, whose rows are lower
+            const float v = best + sB3[col];
+            const int32_t a = barg == 0x7fffffff ? barg : pc0 + (ARG ? barg : 0);
+            if (fresh || v > sMax[4 * w + g][col]) {
+                sMax[4 * w + g][col] = v;
+                sArg[4 * w + g][col] = a;
+            }
         }
+        if (!flush) {
+            // the segment's result goes to its last tile; the pool skips
+            // the others
+            if (t < kC3) parg[(int64_t)tile * kC3 + t] = -1;
+        } else {
         __syncthreads();
         // across lanes and waves, ties to the lower row: each column's 32
         // partials in two halves of 16, one per thread
@@ -352,11 +414,11 @@ __global__ void __launch_bounds__(kEncThreads) k_enc_forward(const float *__rest
                 const int32_t a = sFinArg[col];
                 if (v > best || (v == best && a < barg)) { best = v; barg = a; }
                 pmax[(int64_t)tile * kC3 + col] = fmaxf(best, 0.f);
-                parg[(int64_t)tile * kC3 + col] =
-                    barg == 0x7fffffff ? -1 : (int32_t)(p0 - cr[2 * c]) + (ARG ? barg : 0);
+                parg[(int64_t)tile * kC3 + col] = barg == 0x7fffffff ? -1 : barg;
             }
         }
         __syncthreads();
+        }
 #pragma unroll
         for (int m = 0; m < 4; m++) {
             px[m] = nx[m];
@@ -411,32 +473,68 @@ __device__ inline void pose_about_centroids(const double R[9], const double *cs,
 
 // Head per pair (clouds 2p = source, 2p + 1 = target): h = ReLU(W4^T f + b4),
 // q = W5^T h + b5, R = rotation of q / |q|, T0 = [R, c_tgt - R c_src].
+// A workgroup takes kHeadPairs pairs, so each W4 element it loads feeds
+// that many independent sums; every sum runs over its inputs in ascending
+// order, one fused multiply-add at a time.
+constexpr int kHeadPairs = 4;
+
 __global__ void __launch_bounds__(kH) k_head_forward(const float *__restrict__ feat, const double *__restrict__ cen,
                                                    const float *__restrict__ params, int np,
                                                    float *__restrict__ zbuf, float *__restrict__ qbuf,
                                                    double *__restrict__ out_T)
 {
-    __shared__ float f[2 * kC3];
-    __shared__ float h[kH];
-    const int p = blockIdx.x, j = threadIdx.x;
-    if (p >= np) return;
-    f[j] = feat[(int64_t)(2 * p) * kC3 + j];
-    f[kC3 + j] = feat[(int64_t)(2 * p + 1) * kC3 + j];
+    __shared__ float f[kHeadPairs][2 * kC3];
+    __shared__ float h[kHeadPairs][kH];
+    __shared__ double qs[kHeadPairs][4];
+    const int p0 = blockIdx.x * kHeadPairs, j = threadIdx.x;
+    const int npb = min(kHeadPairs, np - p0);     // pairs of this workgroup
+    if (npb <= 0) return;
+    for (int e = 0; e < kHeadPairs; e++) {
+        const int p = p0 + (e < npb ? e : 0);       // a missing pair repeats the first; nothing of it is written
+        f[e][j] = feat[(int64_t)(2 * p) * kC3 + j];
+        f[e][kC3 + j] = feat[(int64_t)(2 * p + 1) * kC3 + j];
+    }
     __syncthreads();
     const float *W4 = params + kOffW4, *b4 = params + kOffB4, *W5 = params + kOffW5, *b5 = params + kOffB5;
-    float a = b4[j];
-    for (int i = 0; i < 2 * kC3; i++) a = __fmaf_rn(f[i], W4[i * kH + j], a);
-    h[j] = fmaxf(a, 0.f);
-    zbuf[(int64_t)p * kH + j] = a;
-    __syncthreads();
-    if (j == 0) {
-        double q[4];
-        for (int o = 0; o < 4; o++) {
-            float s = b5[o];
-            for (int i = 0; i < kH; i++) s = __fmaf_rn(h[i], W5[i * 4 + o], s);
-            q[o] = s;
-            qbuf[(int64_t)p * 4 + o] = s;
+    float a[kHeadPairs];
+#pragma unroll
+    for (int e = 0; e < kHeadPairs; e++) a[e] = b4[j];
+    // W4 in batches of kB rows: the next batch's loads are in flight while
+    // the current one is summed
+    constexpr int kB = 32;
+    float wc[kB], wn[kB];
+#pragma unroll
+    for (int u = 0; u < kB; u++) wc[u] = W4[u * kH + j];
+    for (int i0 = 0; i0 < 2 * kC3; i0 += kB) {
+        if (i0 + kB < 2 * kC3) {
+#pragma unroll
+            for (int u = 0; u < kB; u++) wn[u] = W4[(i0 + kB + u) * kH + j];
         }
+#pragma unroll
+        for (int u = 0; u < kB; u++)
+#pragma unroll
+            for (int e = 0; e < kHeadPairs; e++) a[e] = __fmaf_rn(f[e][i0 + u], wc[u], a[e]);
+#pragma unroll
+        for (int u = 0; u < kB; u++) wc[u] = wn[u];
+    }
+#pragma unroll
+    for (int e = 0; e < kHeadPairs; e++) {
+        h[e][j] = fmaxf(a[e], 0.f);
+        if (e < npb) zbuf[(int64_t)(p0 + e) * kH + j] = a[e];
+    }
+    __syncthreads();
+    if (j < 4 * kHeadPairs) {     // one thread per (pair, quaternion component)
+        const int e = j >> 2, o = j & 3;
+        float s = b5[o];
+#pragma unroll 16
+        for (int i = 0; i < kH; i++) s = __fmaf_rn(h[e][i], W5[i * 4 + o], s);
+        qs[e][o] = s;
+        if (e < npb) qbuf[(int64_t)(p0 + e) * 4 + o] = s;
+    }
+    __syncthreads();
+    if (j < npb) {
+        const int p = p0 + j;
+        double q[4] = {qs[j][0], qs[j][1], qs[j][2], qs[j][3]};
         double nq = sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
         if (!(nq > 0.0)) { q[0] = 1.0; q[1] = q[2] = q[3] = 0.0; nq = 1.0; }
         double R[9];
@@ -931,32 +1029,36 @@ hipError_t pose_net_stats(PoseNetStore &s, const float *xs, const float *xt, hip
 
 namespace {
 
+// enc_slot >= 0: the kernel timer slot recorded around the encoder kernel
 hipError_t forward_impl(PoseNetStore &s, const float *params, const float *xs, const float *xt, double *out_T,
-                        bool want_arg, hipStream_t st)
+                        bool want_arg, int enc_slot, hipStream_t st)
 {
     k_norm_stats<<<s.nc, 256, 0, st>>>(xs, xt, s.cr, s.nc, s.cen, s.scale);
     k_weights_bf16<<<64, 256, 0, st>>>(params, s.w3t, s.w3p, s.w2p, s.w2q);
     if (s.ntile > 0) {
         // one persistent workgroup per compute unit (LDS holds one), or fewer
         const int grid = s.ntile < 256 ? s.ntile : 256;
+        if (enc_slot >= 0) timer_slot_begin(enc_slot, st);
         if (want_arg)
             k_enc_forward<true><<<grid, kEncThreads, 0, st>>>(xs, xt, s.cr, s.toff, s.nc, s.ntile, s.cen, s.scale,
                                                               params, s.w2p, s.w3p, s.pmax, s.parg);
         else
             k_enc_forward<false><<<grid, kEncThreads, 0, st>>>(xs, xt, s.cr, s.toff, s.nc, s.ntile, s.cen, s.scale,
                                                                params, s.w2p, s.w3p, s.pmax, s.parg);
+        if (enc_slot >= 0) timer_slot_end(enc_slot, st);
     }
     k_enc_pool<<<s.nc, kC3, 0, st>>>(s.pmax, s.parg, s.toff, s.nc, s.feat, s.arg);
-    k_head_forward<<<s.np, kH, 0, st>>>(s.feat, s.cen, params, s.np, s.z4, s.q, out_T ? out_T : s.T);
+    k_head_forward<<<(s.np + kHeadPairs - 1) / kHeadPairs, kH, 0, st>>>(s.feat, s.cen, params, s.np, s.z4, s.q,
+                                                                        out_T ? out_T : s.T);
     return hipGetLastError();
 }
 
 }  // namespace
 
 hipError_t pose_net_forward(PoseNetStore &s, const float *params, const float *xs, const float *xt, double *out_T,
-                            hipStream_t st)
+                            hipStream_t st, int enc_slot)
 {
-    return forward_impl(s, params, xs, xt, out_T, false, st);
+    return forward_impl(s, params, xs, xt, out_T, false, enc_slot, st);
 }
 
 hipError_t pose_net_train(PoseNetStore &s, float *params, float *adam_m, float *adam_v, int step, float lr,
@@ -966,7 +1068,7 @@ hipError_t pose_net_train(PoseNetStore &s, float *params, float *adam_m, float *
     // timer slots (pc_set_kernel_timer): 0 forward, 1 backward, 2 the
     // second-layer weight gradients on the matrix cores
     timer_slot_begin(0, st);
-    hipError_t e = forward_impl(s, params, xs, xt, nullptr, true, st);
+    hipError_t e = forward_impl(s, params, xs, xt, nullptr, true, -1, st);
     timer_slot_end(0, st);
     if (e != hipSuccess) return e;
     const int64_t E = (int64_t)s.nc * kC3;
