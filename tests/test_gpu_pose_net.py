@@ -17,10 +17,18 @@ pytestmark = pytest.mark.gpu
 
 # forward: both sides round the same activations and weights to bfloat16,
 # but the GPU accumulates in float32 where the oracle uses float64 (relative
-# error ~1e-6 in the features; observed up to 2e-6 rad in the rotation,
-# including the rare activation that lands on the other side of a bfloat16
-# rounding boundary): held to 10x the observed error
+# error ~1e-6 in the features; observed up to 2e-6 rad in the rotation on
+# the pairs of test_forward_matches_oracle): held to 10x the observed error
 FWD_ROT_TOL = 2e-5
+# an activation whose pre-activation lies within the float32 error of a
+# bfloat16 rounding midpoint is rounded one way by the GPU and the other by
+# the oracle; where that point carries a channel's maximum, the feature moves
+# by a fraction of one bfloat16 step.  On 160 pairs of 1 to 2,600 points
+# (test_encoder_tile_runs_match_single_pair_calls) 89-91 % of the poses
+# agree within FWD_ROT_TOL and the rest within 1e-4 to 2e-4 rad: the bulk is
+# held to FWD_ROT_TOL and every pair to 10x the worst such case
+FLIP_ROT_TOL = 2e-3
+FLIP_SHARE_MIN = 0.85
 # gradient: float32 sums against float64 ones, observed up to 7e-6 relative
 # L2 error per parameter tensor: held to about 10x that
 GRAD_REL_TOL = 1e-4
@@ -142,6 +150,87 @@ def test_gradient_matches_oracle(gpu):
         err = np.linalg.norm(gg[a:b] - g[a:b])
         _say(f"  {name}: |g| {ref:.4g}, relative error {err / max(ref, 1e-30):.3g}")
         assert err <= GRAD_REL_TOL * ref + 1e-9, (name, err, ref)
+
+
+def _tile_run_case():
+    # 160 pairs of 1 to 2,600 points: about 1,000 encoder tiles of 512
+    # points, so each of the 256 workgroups takes a run of several tiles,
+    # and clouds of up to 6 tiles straddle the runs' boundaries
+    rng = np.random.default_rng(21)
+    return _uneven(rng.integers(1, 2600, 160).tolist(), 600)
+
+
+def test_encoder_tile_runs_match_single_pair_calls(gpu):
+    # each pose of the batched call equals the pose of the same pair
+    # predicted alone (one tile per workgroup there): the maxima are exact,
+    # so how tiles are grouped into runs cannot change a bit; two empty
+    # sources and two empty targets sit inside runs; every other pair
+    # against the oracle (FLIP_ROT_TOL)
+    pairs = _tile_run_case()
+    params = _params(5)
+    srcs = [w.source.astype(np.float32) for w in pairs]
+    tgts = [w.target.astype(np.float32) for w in pairs]
+    for j in (7, 90):
+        srcs[j] = srcs[j][:0]
+    for j in (8, 91):
+        tgts[j] = tgts[j][:0]
+    so = np.concatenate([[0], np.cumsum([len(a) for a in srcs])]).astype(np.int64)
+    to = np.concatenate([[0], np.cumsum([len(a) for a in tgts])]).astype(np.int64)
+    tiles = sum(-(-len(a) // 512) for a in srcs + tgts)
+    _say(f"tile runs: pairs={len(pairs)} points={so[-1] + to[-1]} tiles={tiles}")
+    assert tiles > 3 * 256
+    P = _dev(params)
+    T = gpu.pose_net_predict(P, _dev(np.vstack(srcs)), so, _dev(np.vstack(tgts)), to).cpu().numpy()
+    for j in range(len(pairs)):
+        Tj = gpu.pose_net_predict(P, _dev(srcs[j].reshape(-1, 3)), np.array([0, len(srcs[j])], np.int64),
+                                  _dev(tgts[j].reshape(-1, 3)), np.array([0, len(tgts[j])], np.int64)).cpu().numpy()
+        assert np.array_equal(T[j], Tj[0]), (j, len(srcs[j]), len(tgts[j]))
+    errs = []
+    for j, w in enumerate(pairs):
+        if len(srcs[j]) and len(tgts[j]):
+            To = pn.predict(params, w.source, w.target)
+            errs.append(rot_angle(T[j][:3, :3], To[:3, :3]))
+    errs = np.array(errs)
+    share = float(np.mean(errs < FWD_ROT_TOL))
+    _say(f"  against the oracle: {share:.3f} of {errs.size} pairs within {FWD_ROT_TOL}, worst {errs.max():.3g} rad")
+    assert share >= FLIP_SHARE_MIN and errs.max() < FLIP_ROT_TOL, (share, errs.max())
+
+
+def test_gradient_over_tile_runs_matches_single_pair_calls(gpu):
+    # the training forward's arg-max over runs of several tiles per
+    # workgroup (the case above): each pair's loss equals that of the pair
+    # trained alone, bit for bit, and the batch's gradient equals the sum of
+    # the single-pair gradients up to float32 summation order (a maximum
+    # routed to a wrong point would move it by orders of magnitude more).
+    # The single-pair path is the one test_gradient_matches_oracle checks
+    # against the oracle.  Against the oracle directly this batch's first-
+    # layer gradient differs by 1.6e-3 (one pair of 2,501 points by 12 %):
+    # there a bfloat16 rounding decision or a near-tie moves a channel's
+    # arg-max point, and the oracle's own gradient jumps the same way when
+    # its inputs move by 1e-7 to 3e-6 relative (0.3 to 4 % for that pair;
+    # for another, the GPU's 0.47 % exactly), so the oracle is not a
+    # tighter reference than this at these sizes.
+    import torch
+    pairs = _tile_run_case()
+    params = _dev(_params(6))
+    labels = np.stack([random_rigid(rng_for(43, j), 60, 0.1) for j in range(len(pairs))])
+    src, tgt, off = _pack(pairs)
+    loss, grad = gpu.pose_net_train_step(params, None, None, 1, 0.0, _dev(src), off, _dev(tgt), off, labels,
+                                         want_grad=True)
+    loss, grad = loss.cpu().numpy(), grad.cpu().numpy().astype(np.float64)
+    gsum = np.zeros_like(grad)
+    for j, w in enumerate(pairs):
+        o = np.array([0, w.n], np.int64)
+        lj, gj = gpu.pose_net_train_step(params, None, None, 1, 0.0, _dev(w.source.astype(np.float32)), o,
+                                         _dev(w.target.astype(np.float32)), o, labels[j:j + 1], want_grad=True)
+        assert lj.cpu().numpy()[0] == loss[j], j
+        gsum += gj.cpu().numpy()
+    offs = np.cumsum([0] + [int(np.prod(s)) for _, s in pn.SHAPES])
+    for (name, _), a, b in zip(pn.SHAPES, offs[:-1], offs[1:]):
+        ref = np.linalg.norm(gsum[a:b])
+        err = np.linalg.norm(grad[a:b] - gsum[a:b])
+        _say(f"  {name}: |g| {ref:.4g}, batched against summed single-pair: relative {err / max(ref, 1e-30):.3g}")
+        assert err <= 1e-5 * ref + 1e-9, (name, err, ref)
 
 
 def test_adam_step_and_determinism(gpu):
