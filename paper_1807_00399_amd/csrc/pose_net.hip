@@ -612,32 +612,50 @@ __global__ void __launch_bounds__(kH) k_head_backward(const float *__restrict__ 
     }
 }
 
-// Head weight gradients, one thread per weight, summed over pairs in order:
-// W4 and b4 from [features, 1] x dz4, W5 and b5 from [h, 1] x dq.
-__global__ void k_head_grads(const float *__restrict__ feat, const float *__restrict__ zbuf,
-                             const float *__restrict__ dq, const float *__restrict__ dz, int np,
-                             float *__restrict__ grad)
+// Head weight gradients, summed over pairs in order: W4 from features x
+// dz4 (a workgroup per kGradRows rows of W4, a thread per column, each dz4
+// value loaded once for those rows; the features are uniform over the
+// workgroup), then b4, W5 from [h, 1] x dq and b5, one thread per weight.
+constexpr int kGradRows = 8;
+constexpr int kGradW4Blocks = 2 * kC3 / kGradRows;
+
+__global__ void __launch_bounds__(kH) k_head_grads(const float *__restrict__ feat, const float *__restrict__ zbuf,
+                                                 const float *__restrict__ dq, const float *__restrict__ dz, int np,
+                                                 float *__restrict__ grad)
 {
-    const int nW4 = 2 * kC3 * kH, nW5 = kH * 4;
-    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nW4 + kH + nW5 + 4; e += gridDim.x * blockDim.x) {
+    const int nW5 = kH * 4;
+    if ((int)blockIdx.x < kGradW4Blocks) {
+        const int i0 = blockIdx.x * kGradRows, j = threadIdx.x;
+        const int side = i0 / kC3, c0 = i0 % kC3;     // the rows' cloud (source or target) and channels
+        float a[kGradRows];
+#pragma unroll
+        for (int r = 0; r < kGradRows; r++) a[r] = 0.f;
+#pragma unroll 8
+        for (int p = 0; p < np; p++) {
+            const float d = dz[(int64_t)p * kH + j];
+            const float *f = feat + (int64_t)(2 * p + side) * kC3 + c0;
+#pragma unroll
+            for (int r = 0; r < kGradRows; r++) a[r] = __fmaf_rn(f[r], d, a[r]);
+        }
+#pragma unroll
+        for (int r = 0; r < kGradRows; r++) grad[kOffW4 + (int64_t)(i0 + r) * kH + j] = a[r];
+        return;
+    }
+    const int nrest = kH + nW5 + 4;
+    for (int e = (blockIdx.x - kGradW4Blocks) * blockDim.x + threadIdx.x; e < nrest;
+         e += (gridDim.x - kGradW4Blocks) * blockDim.x) {
         float a = 0.f;
-        if (e < nW4) {
-            int i = e / kH, j = e % kH;
-#pragma unroll 16
-            for (int p = 0; p < np; p++)
-                a = __fmaf_rn(feat[(int64_t)(2 * p + i / kC3) * kC3 + (i % kC3)], dz[(int64_t)p * kH + j], a);
-            grad[kOffW4 + e] = a;
-        } else if (e < nW4 + kH) {
-            int j = e - nW4;
-            for (int p = 0; p < np; p++) a += dz[(int64_t)p * kH + j];
-            grad[kOffB4 + j] = a;
-        } else if (e < nW4 + kH + nW5) {
-            int k = e - nW4 - kH, i = k / 4, o = k % 4;
+        if (e < kH) {
+            const int jj = e;
+            for (int p = 0; p < np; p++) a += dz[(int64_t)p * kH + jj];
+            grad[kOffB4 + jj] = a;
+        } else if (e < kH + nW5) {
+            int k = e - kH, i = k / 4, o = k % 4;
             for (int p = 0; p < np; p++)
                 a = __fmaf_rn(fmaxf(zbuf[(int64_t)p * kH + i], 0.f), dq[(int64_t)p * 4 + o], a);
             grad[kOffW5 + k] = a;
         } else {
-            int o = e - nW4 - kH - nW5;
+            int o = e - kH - nW5;
             for (int p = 0; p < np; p++) a += dq[(int64_t)p * 4 + o];
             grad[kOffB5 + o] = a;
         }
@@ -1075,7 +1093,8 @@ hipError_t pose_net_train(PoseNetStore &s, float *params, float *adam_m, float *
     timer_slot_begin(1, st);
     k_head_backward<<<s.np, kH, 0, st>>>(params, s.np, s.z4, s.q, label_T, pair_w, out_loss ? out_loss : s.loss,
                                         s.dq, s.dz, s.df);
-    k_head_grads<<<512, 256, 0, st>>>(s.feat, s.z4, s.dq, s.dz, s.np, s.grad);
+    k_head_grads<<<kGradW4Blocks + (kH + kH * 4 + 4 + kH - 1) / kH, kH, 0, st>>>(s.feat, s.z4, s.dq, s.dz, s.np,
+                                                                              s.grad);
     k_enc_backward_mfma<<<(int)(E / 64), 256, 0, st>>>(xs, xt, s.cr, s.nc, s.cen, s.scale, params, s.w2p, s.w2q,
                                                        s.w3t, s.feat, s.arg, s.df, s.U1, s.V1, s.U2, s.V2, s.A2,
                                                        s.G3);
