@@ -204,10 +204,14 @@ __global__ void __launch_bounds__(kEncThreads) k_enc_forward(const float *__rest
     __shared__ __attribute__((aligned(16))) __bf16 sW3[kC3 * kP2];   // W3: [n][slot], slot < 128
     __shared__ __attribute__((aligned(16))) float4 sW1[kC1];         // (w1x, w1y, w1z, b1) per channel
     __shared__ float sB2[kC2], sB3[kC3];
-    __shared__ float sMax[4 * kEncWaves][kC3 + 1];   // per wave and lane group g (padded rows)
-    __shared__ int32_t sArg[4 * kEncWaves][kC3 + 1];
+    // running maxima per wave and lane group g; rows kC3 + 16 apart, so
+    // the four groups of a wave (16 consecutive columns each) fall on
+    // disjoint halves of the 32 banks, two groups per half
+    constexpr int kRow = kC3 + 16;
+    __shared__ float sMax[4 * kEncWaves][kRow];
+    __shared__ int32_t sArg[ARG ? 4 * kEncWaves : 1][kRow];    // arg-max rows only for training
     __shared__ float sFinMax[kC3];                   // upper half of the combine
-    __shared__ int32_t sFinArg[kC3];
+    __shared__ int32_t sFinArg[ARG ? kC3 : 1];
     const int t = threadIdx.x, w = t >> 6, l = __lane_id();
     const int lr = l & 15, g = l >> 4;
     for (int i = t; i < kC2 * (kC1 / 8); i += kEncThreads) {
@@ -382,7 +386,7 @@ __global__ void __launch_bounds__(kEncThreads) k_enc_forward(const float *__rest
             const int32_t a = barg == 0x7fffffff ? barg : pc0 + (ARG ? barg : 0);
             if (fresh || v > sMax[4 * w + g][col]) {
                 sMax[4 * w + g][col] = v;
-                sArg[4 * w + g][col] = a;
+                if (ARG) sArg[4 * w + g][col] = a;
             }
         }
         if (!flush) {
@@ -401,18 +405,29 @@ __global__ void __launch_bounds__(kEncThreads) k_enc_forward(const float *__rest
 #pragma unroll
             for (int x = 0; x < 2 * kEncWaves; x++) {
                 const float v = sMax[2 * kEncWaves * h + x][col];
-                const int32_t a = sArg[2 * kEncWaves * h + x][col];
-                if (v > best || (v == best && a < barg)) { best = v; barg = a; }
+                if (ARG) {
+                    const int32_t a = sArg[2 * kEncWaves * h + x][col];
+                    if (v > best || (v == best && a < barg)) { best = v; barg = a; }
+                } else if (v > best) {
+                    best = v;
+                }
             }
             if (h == 1) {
                 sFinMax[col] = best;
-                sFinArg[col] = barg;
+                if (ARG) sFinArg[col] = barg;
             }
             __syncthreads();
             if (h == 0) {
                 const float v = sFinMax[col];
-                const int32_t a = sFinArg[col];
-                if (v > best || (v == best && a < barg)) { best = v; barg = a; }
+                if (ARG) {
+                    const int32_t a = sFinArg[col];
+                    if (v > best || (v == best && a < barg)) { best = v; barg = a; }
+                } else {
+                    if (v > best) best = v;
+                    // every tile has points, so every column a finite maximum;
+                    // without training the index is not used, 0 marks it valid
+                    barg = best == -INFINITY ? 0x7fffffff : 0;
+                }
                 pmax[(int64_t)tile * kC3 + col] = fmaxf(best, 0.f);
                 parg[(int64_t)tile * kC3 + col] = barg == 0x7fffffff ? -1 : barg;
             }
