@@ -338,18 +338,29 @@ __global__ void __launch_bounds__(kEncThreads) k_enc_forward(const float *__rest
         // and its arg-max matters only where it is positive, where it is the
         // arg-max of the pre-activation.
         const bool all_valid = p0 + r0 + 63 < pend;     // uniform over the wave
+        // the next column tile's weight fragments are read from LDS while
+        // the current one's products run
+        bf16x8 bw[4];
+#pragma unroll
+        for (int kb = 0; kb < 4; kb++) bw[kb] = *reinterpret_cast<const bf16x8 *>(&sW3[lr * kP2 + 32 * kb + 8 * g]);
 #pragma unroll 2
         for (int n3 = 0; n3 < kC3 / 16; n3++) {
             const int col = 16 * n3 + lr;
+            bf16x8 bn[4];
+            const int n3n = n3 + 1 < kC3 / 16 ? n3 + 1 : n3;
+#pragma unroll
+            for (int kb = 0; kb < 4; kb++)
+                bn[kb] = *reinterpret_cast<const bf16x8 *>(&sW3[(16 * n3n + lr) * kP2 + 32 * kb + 8 * g]);
             f32x4 acc[4];
 #pragma unroll
             for (int m = 0; m < 4; m++) acc[m] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int kb = 0; kb < 4; kb++) {
-                const bf16x8 bw = *reinterpret_cast<const bf16x8 *>(&sW3[(16 * n3 + lr) * kP2 + 32 * kb + 8 * g]);
+            for (int kb = 0; kb < 4; kb++)
 #pragma unroll
-                for (int m = 0; m < 4; m++) acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x2[m][kb], bw, acc[m], 0, 0, 0);
-            }
+                for (int m = 0; m < 4; m++)
+                    acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(x2[m][kb], bw[kb], acc[m], 0, 0, 0);
+#pragma unroll
+            for (int kb = 0; kb < 4; kb++) bw[kb] = bn[kb];
             float best = -INFINITY;
             int32_t barg = 0x7fffffff;
             if (all_valid) {
