@@ -346,6 +346,12 @@ __global__ void __launch_bounds__(kEncThreads) k_enc_forward(const float *__rest
 #pragma unroll 2
         for (int n3 = 0; n3 < kC3 / 16; n3++) {
             const int col = 16 * n3 + lr;
+            // without training the slot holds the unbiased running maximum
+            // (the bias is added at the combine: rounding is monotone, so
+            // the maximum of the biased values is the biased maximum); it is
+            // read here, ahead of the products, so the wait for it does not
+            // also wait for the weight fragments read below
+            const float old = ARG ? 0.f : sMax[4 * w + g][col];
             bf16x8 bn[4];
             const int n3n = n3 + 1 < kC3 / 16 ? n3 + 1 : n3;
 #pragma unroll
@@ -393,11 +399,15 @@ __global__ void __launch_bounds__(kEncThreads) k_enc_forward(const float *__rest
             // this lane's running maximum over the segment's tiles, in its
             // own LDS slot (no other lane touches it until the combine);
             // ties keep the earlier tile, whose rows are lower
-            const float v = best + sB3[col];
-            const int32_t a = barg == 0x7fffffff ? barg : pc0 + (ARG ? barg : 0);
-            if (fresh || v > sMax[4 * w + g][col]) {
-                sMax[4 * w + g][col] = v;
-                if (ARG) sArg[4 * w + g][col] = a;
+            if (ARG) {
+                const float v = best + sB3[col];
+                const int32_t a = barg == 0x7fffffff ? barg : pc0 + barg;
+                if (fresh || v > sMax[4 * w + g][col]) {
+                    sMax[4 * w + g][col] = v;
+                    sArg[4 * w + g][col] = a;
+                }
+            } else {
+                sMax[4 * w + g][col] = fresh ? best : __builtin_elementwise_maximum(old, best);
             }
         }
         if (!flush) {
@@ -438,6 +448,7 @@ __global__ void __launch_bounds__(kEncThreads) k_enc_forward(const float *__rest
                     // every tile has points, so every column a finite maximum;
                     // without training the index is not used, 0 marks it valid
                     barg = best == -INFINITY ? 0x7fffffff : 0;
+                    best += sB3[col];
                 }
                 pmax[(int64_t)tile * kC3 + col] = fmaxf(best, 0.f);
                 parg[(int64_t)tile * kC3 + col] = barg == 0x7fffffff ? -1 : barg;
