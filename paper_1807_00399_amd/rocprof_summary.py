@@ -54,7 +54,20 @@ def _demangle(name: str) -> str:
     ids = [i for i in ids if not i.startswith("_GLOBAL__N")]
     if not ids:
         return name
-    return "::".join(ids) + ("<...>" if name[pos:pos + 1] == "I" else "") + "("
+    targs = ""
+    if name[pos:pos + 1] == "I":
+        # template arguments that are literals (L<type><value>E, as in
+        # ILb1E or ILi64ELi8E) are spelled out; anything else stays "..."
+        m = re.match(r"I((?:L[bijl]n?\d+E)+)E", name[pos:])
+        if m:
+            vals = []
+            for t, v in re.findall(r"L([bijl])(n?\d+)E", m.group(1)):
+                v = v.replace("n", "-")
+                vals.append(("true" if v == "1" else "false") if t == "b" else v)
+            targs = "<" + ", ".join(vals) + ">"
+        else:
+            targs = "<...>"
+    return "::".join(ids) + targs + "("
 
 
 def _short(name: str) -> str:
