@@ -370,21 +370,22 @@ __global__ void __launch_bounds__(kEncThreads) k_enc_forward(const float *__rest
             float best = -INFINITY;
             int32_t barg = 0x7fffffff;
             if (all_valid) {
+                // NaN-propagating maximum: the matrix cores' finite outputs
+                // need no quieting, and three operands go to one instruction
+#pragma unroll
+                for (int m = 0; m < 4; m++)
+                    best = __builtin_elementwise_maximum(
+                        __builtin_elementwise_maximum(best, __builtin_elementwise_maximum(acc[m][0], acc[m][1])),
+                        __builtin_elementwise_maximum(acc[m][2], acc[m][3]));
                 if (ARG) {
+                    // the lowest of this lane's rows reaching it (rows in
+                    // descending order, each equal one overwriting)
 #pragma unroll
-                    for (int m = 0; m < 4; m++)
+                    for (int m = 3; m >= 0; m--)
 #pragma unroll
-                        for (int i = 0; i < 4; i++)
-                            if (acc[m][i] > best) { best = acc[m][i]; barg = r0 + 16 * m + 4 * g + i; }
+                        for (int i = 3; i >= 0; i--)
+                            barg = acc[m][i] == best ? r0 + 16 * m + 4 * g + i : barg;
                 } else {
-                    // NaN-propagating maximum: the matrix cores' finite
-                    // outputs need no quieting, and three operands go to
-                    // one instruction
-#pragma unroll
-                    for (int m = 0; m < 4; m++)
-                        best = __builtin_elementwise_maximum(
-                            __builtin_elementwise_maximum(best, __builtin_elementwise_maximum(acc[m][0], acc[m][1])),
-                            __builtin_elementwise_maximum(acc[m][2], acc[m][3]));
                     barg = r0 + 4 * g;
                 }
             } else {
