@@ -665,6 +665,17 @@ size_t pose_store_bytes(int n_pairs, int ntile, bool train)
     return c.used();
 }
 
+// the pairs' offsets to the device (half the bytes of the per-cloud rows
+// and tile offsets, so fewer upload launches), expanded there into both
+pc_status pose_upload_layout(int n_pairs, const int64_t *src_off, const int64_t *tgt_off, PoseNetStore &s,
+                             hipStream_t stream)
+{
+    std::vector<int64_t> offs(src_off, src_off + n_pairs + 1);
+    offs.insert(offs.end(), tgt_off, tgt_off + n_pairs + 1);
+    if (!upload(s.offs, offs.data(), sizeof(int64_t) * offs.size(), stream)) return PC_EDEVICE;
+    return pose_net_layout(s, stream) == hipSuccess ? PC_OK : PC_EDEVICE;
+}
+
 // carve the pose store at the front of the workspace and upload its layout
 pc_status pose_setup(Carver &c, int n_pairs, const int64_t *src_off, const int64_t *tgt_off, bool train,
                      PoseNetStore &s, hipStream_t stream)
@@ -675,10 +686,7 @@ pc_status pose_setup(Carver &c, int n_pairs, const int64_t *src_off, const int64
     if (!pose_layout(n_pairs, src_off, tgt_off, cr, toff, ntile)) return PC_EINVAL;
     pose_net_carve(c, n_pairs, ntile, train, s);
     if (!c.ok) return PC_EWORKSPACE;
-    if (!upload(s.cr, cr.data(), sizeof(int64_t) * cr.size(), stream) ||
-        !upload(s.toff, toff.data(), sizeof(int32_t) * toff.size(), stream))
-        return PC_EDEVICE;
-    return PC_OK;
+    return pose_upload_layout(n_pairs, src_off, tgt_off, s, stream);
 }
 
 // replicated offsets of every pair kStarts times (pair-major)
@@ -836,9 +844,7 @@ pc_status icp_learned_batched(int mode, const float *params, int n_pairs, const 
     int ntile = 0;
     if (!pose_layout(n_pairs, src_off, tgt_off, cr, toff, ntile)) return PC_EINVAL;
     if (!learned_carve(c, n_pairs, src_off, tgt_off, max_iters, ntile, L)) return PC_EWORKSPACE;
-    if (!upload(L.pose.cr, cr.data(), sizeof(int64_t) * cr.size(), stream) ||
-        !upload(L.pose.toff, toff.data(), sizeof(int32_t) * toff.size(), stream))
-        return PC_EDEVICE;
+    if (pose_upload_layout(n_pairs, src_off, tgt_off, L.pose, stream) != PC_OK) return PC_EDEVICE;
     std::vector<float> dmax(kStarts * (size_t)n_pairs, max_corr_dist);
     std::vector<int32_t> maxit(kStarts * (size_t)n_pairs, max_iters);
     if (out_start && fill_i32(out_start, n_pairs, -1, stream) != hipSuccess) return PC_EDEVICE;

@@ -29,6 +29,7 @@ struct PoseNetStore {
     int np, nc;                 // pairs and clouds (cloud 2p: source p, 2p + 1: target p)
     int ntile;                  // encoder tiles
     int nchunk;                 // outer-product chunks (training)
+    int64_t *offs;              // the pairs' row offsets as uploaded: source (np + 1), then target (np + 1)
     int64_t *cr;                // per cloud: first and end row in its buffer (2 nc)
     int32_t *toff;              // tile offsets (nc + 1)
     double *cen;                // per cloud centroid
@@ -51,6 +52,8 @@ struct PoseNetStore {
 int pose_net_tiles(int64_t n_cloud);
 // carve for np pairs and ntile encoder tiles; train adds the backward buffers
 void pose_net_carve(Carver &c, int np, int ntile, bool train, PoseNetStore &s);
+// cr and toff from the offsets in s.offs (on the device)
+hipError_t pose_net_layout(PoseNetStore &s, hipStream_t st);
 // centroids and scales only (cr and toff must be on the device)
 hipError_t pose_net_stats(PoseNetStore &s, const float *xs, const float *xt, hipStream_t st);
 // forward: initial pose per pair into out_T (n_pairs x 16), or into s.T

@@ -467,6 +467,47 @@ __global__ void __launch_bounds__(kEncThreads) k_enc_forward(const float *__rest
     }
 }
 
+// The cloud layout from the pairs' row offsets (off: the source offsets
+// 0..np, then the target offsets 0..np): rows [cr[2c], cr[2c + 1]) of cloud
+// c (2p: source p, 2p + 1: target p), and toff, the exclusive prefix sum of
+// the clouds' tile counts (toff[nc] = all tiles).  One workgroup, in chunks
+// of 1024 clouds; integer sums, so the result is exact.
+__global__ void __launch_bounds__(1024) k_pose_layout(const int64_t *__restrict__ off, int np,
+                                                    int64_t *__restrict__ cr, int32_t *__restrict__ toff)
+{
+    __shared__ int32_t wsum[16];
+    const int nc = 2 * np, t = threadIdx.x, w = t >> 6, l = __lane_id();
+    int32_t carry = 0;     // tiles before this chunk (the same in every thread)
+    for (int base = 0; base < nc; base += 1024) {
+        const int c = base + t;
+        int32_t v = 0;
+        if (c < nc) {
+            const int64_t *o = (c & 1) ? off + (np + 1) : off;
+            const int64_t a = o[c >> 1], b = o[(c >> 1) + 1];
+            cr[2 * (int64_t)c] = a;
+            cr[2 * (int64_t)c + 1] = b;
+            v = (int32_t)((b - a + kT - 1) / kT);
+        }
+        int32_t x = v;     // inclusive scan within the wave
+        for (int d = 1; d < 64; d <<= 1) {
+            const int32_t y = __shfl_up(x, d);
+            if (l >= d) x += y;
+        }
+        if (l == 63) wsum[w] = x;
+        __syncthreads();
+        int32_t before = 0, total = 0;
+        for (int k = 0; k < 16; k++) {
+            const int32_t ws = wsum[k];
+            before += k < w ? ws : 0;
+            total += ws;
+        }
+        if (c < nc) toff[c] = carry + before + x - v;
+        carry += total;
+        __syncthreads();   // wsum is rewritten by the next chunk
+    }
+    if (t == 0) toff[nc] = carry;
+}
+
 // per cloud: maximum over its tiles (ties: the lower point index)
 __global__ void k_enc_pool(const float *__restrict__ pmax, const int32_t *__restrict__ parg,
                            const int32_t *__restrict__ toff, int nc, float *__restrict__ feat,
@@ -1046,6 +1087,7 @@ void pose_net_carve(Carver &c, int np, int ntile, bool train, PoseNetStore &s)
     s.np = np1;
     s.nc = nc;
     s.ntile = ntile;
+    s.offs = c.take<int64_t>((size_t)2 * (np1 + 1));
     s.cr = c.take<int64_t>((size_t)2 * nc);
     s.toff = c.take<int32_t>(nc + 1);
     s.cen = c.take<double>((size_t)nc * 3);
@@ -1075,6 +1117,12 @@ void pose_net_carve(Carver &c, int np, int ntile, bool train, PoseNetStore &s)
     s.A2 = c.take<float>((size_t)kC2 * E);
     s.G3 = c.take<float>((size_t)E);
     s.part = c.take<float>((size_t)s.nchunk * (kC1 + 1) * kC2);
+}
+
+hipError_t pose_net_layout(PoseNetStore &s, hipStream_t st)
+{
+    k_pose_layout<<<1, 1024, 0, st>>>(s.offs, s.np, s.cr, s.toff);
+    return hipGetLastError();
 }
 
 hipError_t pose_net_stats(PoseNetStore &s, const float *xs, const float *xt, hipStream_t st)
