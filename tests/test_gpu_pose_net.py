@@ -196,6 +196,25 @@ def test_encoder_tile_runs_match_single_pair_calls(gpu):
     assert share >= FLIP_SHARE_MIN and errs.max() < FLIP_ROT_TOL, (share, errs.max())
 
 
+def test_layout_over_many_clouds_matches_single_pair_calls(gpu):
+    # 700 pairs (1,400 clouds): the device-side layout (rows and tile
+    # offsets from the uploaded pair offsets) takes its prefix sum in two
+    # chunks of 1,024 clouds; sampled poses, and the last pair's, against
+    # the same pairs predicted alone, bit for bit
+    rng = np.random.default_rng(23)
+    pairs = _uneven(rng.integers(1, 300, 700).tolist(), 900)
+    params = _dev(_params(7))
+    src, tgt, off = _pack(pairs)
+    _say(f"many clouds: pairs={len(pairs)} points={off[-1]}")
+    T = gpu.pose_net_predict(params, _dev(src), off, _dev(tgt), off).cpu().numpy()
+    for j in list(range(0, 700, 37)) + [510, 511, 512, 513, 699]:
+        w = pairs[j]
+        o = np.array([0, w.n], np.int64)
+        Tj = gpu.pose_net_predict(params, _dev(w.source.astype(np.float32)), o, _dev(w.target.astype(np.float32)),
+                                  o).cpu().numpy()
+        assert np.array_equal(T[j], Tj[0]), (j, w.n)
+
+
 def test_gradient_over_tile_runs_matches_single_pair_calls(gpu):
     # the training forward's arg-max over runs of several tiles per
     # workgroup (the case above): each pair's loss equals that of the pair
