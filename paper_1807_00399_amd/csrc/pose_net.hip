@@ -565,16 +565,18 @@ __global__ void __launch_bounds__(kH) k_head_forward(const float *__restrict__ f
     __shared__ float f[kHeadPairs][2 * kC3];
     __shared__ float h[kHeadPairs][kH];
     __shared__ double qs[kHeadPairs][4];
+    __shared__ float sW5[kH * 4];     // W5 staged while h is formed: the q sums then read LDS, not memory
     const int p0 = blockIdx.x * kHeadPairs, j = threadIdx.x;
     const int npb = min(kHeadPairs, np - p0);     // pairs of this workgroup
     if (npb <= 0) return;
+    const float *W4 = params + kOffW4, *b4 = params + kOffB4, *W5 = params + kOffW5, *b5 = params + kOffB5;
     for (int e = 0; e < kHeadPairs; e++) {
         const int p = p0 + (e < npb ? e : 0);       // a missing pair repeats the first; nothing of it is written
         f[e][j] = feat[(int64_t)(2 * p) * kC3 + j];
         f[e][kC3 + j] = feat[(int64_t)(2 * p + 1) * kC3 + j];
     }
+    for (int x = j; x < kH * 4; x += kH) sW5[x] = W5[x];
     __syncthreads();
-    const float *W4 = params + kOffW4, *b4 = params + kOffB4, *W5 = params + kOffW5, *b5 = params + kOffB5;
     float a[kHeadPairs];
 #pragma unroll
     for (int e = 0; e < kHeadPairs; e++) a[e] = b4[j];
@@ -606,7 +608,7 @@ __global__ void __launch_bounds__(kH) k_head_forward(const float *__restrict__ f
         const int e = j >> 2, o = j & 3;
         float s = b5[o];
 #pragma unroll 16
-        for (int i = 0; i < kH; i++) s = __fmaf_rn(h[e][i], W5[i * 4 + o], s);
+        for (int i = 0; i < kH; i++) s = __fmaf_rn(h[e][i], sW5[i * 4 + o], s);
         qs[e][o] = s;
         if (e < npb) qbuf[(int64_t)(p0 + e) * 4 + o] = s;
     }
